@@ -1,0 +1,430 @@
+"""Plain FP64 CPU oracle for the phase-space hot path of MadSpace (arXiv:2602.06895).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no code
+with the HIP library (``paper_2602_06895_amd``) and never imports it.
+
+The per-event chain (VEGAS lookup, s-hat and invariant sampling, PDF
+convolution, 2->2 t-channel blocks, (phi, theta) decays, beam boost, Jacobian
+product, unphysical cut, integrand and local channel weight) lives in
+``oracle.c``.  This module compiles a process description into the oracle's
+own node-tree form, and implements in numpy the host-level pieces: VEGAS grid
+refinement, per-channel statistics and the unweighting efficiency.
+
+Parity status of each function is listed in the docstrings; everything here is
+pinned by the ``-m "not gpu"`` tests against closed forms, invariants and
+brute force, except where a docstring says "parity unpinned".
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+LEAF, CLUSTER, TNODE = 0, 1, 2
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into liboracle.so with gcc (plain -O2, no fast-math,
+    no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-Wall", "-Wno-unused-function", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_LIB)
+        dp, ip = C.POINTER(C.c_double), C.POINTER(C.c_int32)
+        L.orc_map.restype = C.c_int
+        L.orc_kallen.restype = C.c_double
+        L.orc_kallen.argtypes = [C.c_double] * 3
+        L.orc_map_nu.restype = C.c_double
+        L.orc_map_nu.argtypes = [C.c_double] * 5 + [dp]
+        L.orc_map_bw.restype = C.c_double
+        L.orc_map_bw.argtypes = [C.c_double] * 5 + [dp]
+        L.orc_two_body_decay.restype = C.c_double
+        L.orc_two_body_decay.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                         C.c_double, dp, dp]
+        L.orc_two_to_two.restype = C.c_double
+        L.orc_two_to_two.argtypes = [dp, dp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                     C.c_double, C.c_double, dp, dp, dp]
+        L.orc_t_inv_min_max.restype = None
+        L.orc_t_inv_min_max.argtypes = [dp, dp, C.c_double, C.c_double, dp, dp]
+        L.orc_r_to_x1x2.restype = C.c_double
+        L.orc_r_to_x1x2.argtypes = [C.c_double, C.c_double, C.c_double, dp, dp]
+        L.orc_vegas_map.restype = C.c_double
+        L.orc_vegas_map.argtypes = [C.c_double, dp, C.c_int32, dp]
+        L.orc_boost.restype = None
+        L.orc_boost.argtypes = [dp, C.c_double, dp, dp]
+        _lib = L
+    return _lib
+
+
+class _Channel(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("root", C.c_int32), ("n_sorder", C.c_int32),
+                ("n_dec", C.c_int32),
+                ("kind", C.c_void_p), ("particle", C.c_void_p), ("parent", C.c_void_p),
+                ("child_start", C.c_void_p), ("child_count", C.c_void_p), ("children", C.c_void_p),
+                ("mass", C.c_void_p), ("width", C.c_void_p), ("nu", C.c_void_p),
+                ("t_order", C.c_char_p), ("s_order", C.c_void_p), ("dec_order", C.c_void_p)]
+
+
+class _Process(C.Structure):
+    _fields_ = [("hadronic", C.c_int32), ("n_final", C.c_int32), ("s_lab", C.c_double),
+                ("shat_min", C.c_double), ("nu", C.c_double), ("reg_a", C.c_double),
+                ("mass", C.c_void_p),
+                ("pdf", C.c_int32), ("pdf_a", C.c_double), ("pdf_b", C.c_double),
+                ("pt_min", C.c_double), ("ang", C.c_int32), ("n_prop", C.c_int32),
+                ("prop_t", C.c_void_p), ("prop_set", C.c_void_p), ("prop_bw", C.c_void_p),
+                ("prop_m", C.c_void_p), ("prop_w", C.c_void_p), ("prop_mu", C.c_void_p),
+                ("n_chan", C.c_int32), ("alpha_mu", C.c_double), ("ch_start", C.c_void_p),
+                ("chp_t", C.c_void_p), ("chp_set", C.c_void_p), ("chp_m", C.c_void_p),
+                ("chp_w", C.c_void_p)]
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p) if a.size else None
+
+
+class ChannelTree:
+    """One channel as a node tree (the oracle's own channel compiler).
+
+    Node 0 is the root: the effective t-node with the spine legs as children
+    (t-channel topologies), or the cluster decaying at s-hat (pure s-channel)."""
+
+    def __init__(self, chan: dict, masses, nu: float):
+        self.kind, self.particle, self.parent, self.children = [], [], [], []
+        self.mass, self.width, self.nu, self.order = [], [], [], []
+
+        def add(leg, parent):
+            idx = len(self.kind)
+            self.parent.append(parent)
+            self.children.append([])
+            if isinstance(leg, (int, np.integer)):
+                lab = int(leg)
+                if not 1 <= lab <= len(masses):
+                    raise ValueError(f"particle label {lab} out of range")
+                self.kind.append(LEAF)
+                self.particle.append(lab - 1)
+                self.mass.append(float(masses[lab - 1]))
+                self.width.append(0.0)
+                self.nu.append(nu)
+                self.order.append(None)
+            else:
+                kids = leg["d"]
+                if len(kids) != 2:
+                    raise ValueError("a cluster decays into exactly two children")
+                self.kind.append(CLUSTER)
+                self.particle.append(-1)
+                self.mass.append(float(leg.get("m", 0.0)))
+                self.width.append(float(leg.get("w", 0.0)))
+                self.nu.append(float(leg.get("nu", nu)))
+                self.order.append(leg.get("order"))
+                for kid in kids:
+                    self.children[idx].append(add(kid, idx))
+            return idx
+
+        if "t_chain" in chan:
+            legs = chan["t_chain"]
+            if len(legs) < 2:
+                raise ValueError("a t-channel spine needs at least two legs")
+            self.kind.append(TNODE)
+            self.particle.append(-1)
+            self.parent.append(-1)
+            self.children.append([])
+            self.mass.append(0.0)
+            self.width.append(0.0)
+            self.nu.append(nu)
+            self.order.append(None)
+            for leg in legs:
+                self.children[0].append(add(leg, 0))
+            self.t_order = chan.get("t_order", "")
+            kappa = len(legs) - 1
+            if len(self.t_order) != kappa - 1 or any(c not in "AB" for c in self.t_order):
+                raise ValueError("t_order needs kappa-1 letters from {A, B}")
+        else:
+            add(chan["s"], -1)
+            if self.kind[0] != CLUSTER:
+                raise ValueError("a pure s-channel root must be a cluster")
+            self.t_order = ""
+        leaves = sorted(self.particle[j] for j in range(len(self.kind)) if self.kind[j] == LEAF)
+        if leaves != list(range(len(masses))):
+            raise ValueError("every final-state particle must appear exactly once")
+        clusters = [j for j in range(len(self.kind)) if self.kind[j] == CLUSTER and j != 0]
+        # sampling order: explicit "order" keys first, then depth-first order
+        self.s_order = sorted(clusters, key=lambda j: (self.order[j] is None,
+                                                       self.order[j] if self.order[j] is not None else 0, j))
+        self.dec_order = [j for j in range(len(self.kind)) if self.kind[j] == CLUSTER]
+        self.kappa = len(self.children[0]) - 1 if self.kind[0] == TNODE else 0
+
+    def particles(self, j):
+        if self.kind[j] == LEAF:
+            return [self.particle[j]]
+        out = []
+        for c in self.children[j]:
+            out += self.particles(c)
+        return out
+
+    def dims(self, hadronic: bool) -> int:
+        d = len(self.s_order) + max(self.kappa - 1, 0) + 2 * self.kappa + 2 * len(self.dec_order)
+        return d + (2 if hadronic else 0)
+
+    def propagators(self):
+        """(t_type, particle set, mass, width) of every internal line."""
+        out = []
+        if self.kind[0] == TNODE:
+            acc = []
+            for leg in self.children[0][:-1]:
+                acc = acc + self.particles(leg)
+                out.append((1, _mask(acc), 0.0, 0.0))
+        for j in range(len(self.kind)):
+            if self.kind[j] == CLUSTER:
+                out.append((0, _mask(self.particles(j)), self.mass[j], self.width[j]))
+        return out
+
+    def struct(self):
+        n = len(self.kind)
+        starts, counts, flat = [], [], []
+        for j in range(n):
+            starts.append(len(flat))
+            counts.append(len(self.children[j]))
+            flat += self.children[j]
+        self._keep = dict(
+            kind=np.array(self.kind, np.int32), particle=np.array(self.particle, np.int32),
+            parent=np.array(self.parent, np.int32), child_start=np.array(starts, np.int32),
+            child_count=np.array(counts, np.int32), children=np.array(flat + [0], np.int32),
+            mass=np.array(self.mass, np.float64), width=np.array(self.width, np.float64),
+            nu=np.array(self.nu, np.float64), s_order=np.array(self.s_order + [0], np.int32),
+            dec_order=np.array(self.dec_order + [0], np.int32),
+            t_order=self.t_order.encode() + b"\0")
+        k = self._keep
+        return _Channel(n, 0, len(self.s_order), len(self.dec_order),
+                        _ptr(k["kind"]), _ptr(k["particle"]), _ptr(k["parent"]),
+                        _ptr(k["child_start"]), _ptr(k["child_count"]), _ptr(k["children"]),
+                        _ptr(k["mass"]), _ptr(k["width"]), _ptr(k["nu"]), k["t_order"],
+                        _ptr(k["s_order"]), _ptr(k["dec_order"]))
+
+
+def _mask(parts):
+    m = 0
+    for p in parts:
+        m |= 1 << p
+    return m
+
+
+class Process:
+    """A process description compiled for the oracle."""
+
+    def __init__(self, desc: dict):
+        self.desc = desc
+        self.masses = [float(m) for m in desc["masses"]]
+        self.n = len(self.masses)
+        self.hadronic = desc.get("beams", "hadronic") == "hadronic"
+        self.s_lab = float(desc["sqrt_s"]) ** 2
+        self.nu = float(desc.get("nu", 0.8))
+        self.reg_a = float(desc.get("regulator", 1e-3))
+        self.nbins = int(desc.get("vegas_bins", 64))
+        self.channels = [ChannelTree(c, self.masses, self.nu) for c in desc["channels"]]
+        self.dims = [c.dims(self.hadronic) for c in self.channels]
+        ig = desc.get("integrand", {})
+        pdf = ig.get("pdf")
+        props = ig.get("props", [])
+        self._k = dict(
+            mass=np.array(self.masses, np.float64),
+            prop_t=np.array([1 if p.get("t") else 0 for p in props] + [0], np.int32),
+            prop_set=np.array([_mask([q - 1 for q in p["particles"]]) for p in props] + [0], np.uint32),
+            prop_bw=np.array([1 if p.get("bw") else 0 for p in props] + [0], np.int32),
+            prop_m=np.array([float(p.get("m", 0.0)) for p in props] + [0], np.float64),
+            prop_w=np.array([float(p.get("w", 0.0)) for p in props] + [0], np.float64),
+            prop_mu=np.array([float(p.get("mu", 0.0)) for p in props] + [0], np.float64),
+        )
+        chp, start = [], [0]
+        for c in self.channels:
+            chp += c.propagators()
+            start.append(len(chp))
+        self._k.update(
+            ch_start=np.array(start, np.int32),
+            chp_t=np.array([q[0] for q in chp] + [0], np.int32),
+            chp_set=np.array([q[1] for q in chp] + [0], np.uint32),
+            chp_m=np.array([q[2] for q in chp] + [0], np.float64),
+            chp_w=np.array([q[3] for q in chp] + [0], np.float64))
+        k = self._k
+        n_chan = len(self.channels) if "alpha_mu" in desc else 1
+        self._proc = _Process(
+            1 if self.hadronic else 0, self.n, self.s_lab, float(desc.get("shat_min", 0.0)),
+            self.nu, self.reg_a, _ptr(k["mass"]),
+            1 if pdf else 0, float(pdf[0]) if pdf else 0.0, float(pdf[1]) if pdf else 0.0,
+            float(ig.get("pt_min", 0.0)), int(ig["ang"]) - 1 if "ang" in ig else -1, len(props),
+            _ptr(k["prop_t"]), _ptr(k["prop_set"]), _ptr(k["prop_bw"]), _ptr(k["prop_m"]),
+            _ptr(k["prop_w"]), _ptr(k["prop_mu"]), n_chan, float(desc.get("alpha_mu", 0.0)),
+            _ptr(k["ch_start"]), _ptr(k["chp_t"]), _ptr(k["chp_set"]), _ptr(k["chp_m"]),
+            _ptr(k["chp_w"]))
+        self._chs = [c.struct() for c in self.channels]
+
+    def uniform_grid(self, chan: int) -> np.ndarray:
+        nb = self.nbins
+        e = np.arange(nb + 1, dtype=np.float64) / nb
+        return np.tile(e, (self.dims[chan], 1))
+
+    def map(self, chan: int, y: np.ndarray, grid: np.ndarray | None = None,
+            nthreads: int = 0, want_inv: bool = False) -> dict:
+        """Run the per-event chain on uniforms y [dims][n] through the VEGAS grid
+        [dims][nb+1] (None: no VEGAS step).  Returns p [4][n+2][N] (lab frame,
+        incoming a, b first), x1x2 [2][N], jac, w, alpha, f (and inv when asked)."""
+        d = self.dims[chan]
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        if y.ndim != 2 or y.shape[0] != d:
+            raise ValueError(f"y must be [{d}][n]")
+        n = y.shape[1]
+        np_ = self.n + 2
+        out = dict(p=np.empty((4, np_, n)), x1x2=np.empty((2, n)), jac=np.empty(n),
+                   w=np.empty(n), alpha=np.empty(n), f=np.empty(n))
+        if want_inv:
+            out["inv"] = np.empty((len(self.channels[chan].kind), n))
+            out["tabs"] = np.empty((self.channels[chan].kappa, n))
+        g = None
+        if grid is not None:
+            g = np.ascontiguousarray(grid, dtype=np.float64)
+            if g.shape != (d, self.nbins + 1):
+                raise ValueError("grid shape mismatch")
+        nt = nthreads if nthreads > 0 else (os.cpu_count() or 1)
+        dp = lambda a: a.ctypes.data_as(C.c_void_p) if a is not None else None
+        rc = lib().orc_map(C.byref(self._proc), C.byref(self._chs[chan]), C.c_int32(chan),
+                           C.c_int32(d), C.c_int64(n), dp(y), dp(g), C.c_int32(self.nbins),
+                           dp(out["p"]), dp(out["x1x2"]), dp(out["jac"]), dp(out["w"]),
+                           dp(out["alpha"]), dp(out["f"]), dp(out.get("inv")),
+                           dp(out.get("tabs")), C.c_int32(nt))
+        if rc != 0:
+            raise ValueError("oracle rejected the sizes")
+        return out
+
+
+# ---------------------------------------------------------------------------
+# VEGAS (Lepage 1978; "VEGAS enhanced" 2021), cited by the paper for its
+# adaptive grids; the paper gives no formulas, the classic algorithm is used.
+# ---------------------------------------------------------------------------
+
+def vegas_histogram(y: np.ndarray, w: np.ndarray, nbins: int) -> np.ndarray:
+    """d[k][i] = sum of w^2 over events whose uniform y_k lies in bin i."""
+    y = np.asarray(y, np.float64)
+    w2 = np.asarray(w, np.float64) ** 2
+    out = np.zeros((y.shape[0], nbins))
+    for k in range(y.shape[0]):
+        b = np.minimum(np.floor(y[k] * nbins).astype(np.int64), nbins - 1)
+        out[k] = np.bincount(b, weights=w2, minlength=nbins)
+    return out
+
+
+def vegas_refine(edges: np.ndarray, d: np.ndarray, alpha: float) -> np.ndarray:
+    """One grid refinement per dimension: smooth the accumulated d_i with
+    weights (1,6,1)/8 ((7,1)/8 at the ends), normalise, damp with
+    omega_i = ((1 - d_i)/ln(1/d_i))^alpha, then move the edges so that every
+    new bin holds the same share of sum(omega), linearly inside old bins."""
+    edges = np.array(edges, np.float64, copy=True)
+    d = np.asarray(d, np.float64)
+    nb = d.shape[1]
+    for k in range(edges.shape[0]):
+        dk = d[k]
+        if dk.sum() <= 0.0:
+            continue
+        sm = np.empty(nb)
+        if nb == 1:
+            sm[0] = dk[0]
+        else:
+            sm[0] = (7.0 * dk[0] + dk[1]) / 8.0
+            sm[-1] = (dk[-2] + 7.0 * dk[-1]) / 8.0
+            for i in range(1, nb - 1):
+                sm[i] = (dk[i - 1] + 6.0 * dk[i] + dk[i + 1]) / 8.0
+        sm = sm / sm.sum()
+        om = np.empty(nb)
+        for i in range(nb):
+            if sm[i] <= 0.0:
+                om[i] = 0.0
+            elif sm[i] >= 1.0:
+                om[i] = 1.0
+            else:
+                om[i] = ((1.0 - sm[i]) / math.log(1.0 / sm[i])) ** alpha
+        total = om.sum()
+        if total <= 0.0:
+            continue
+        share = total / nb
+        old = edges[k].copy()
+        new = np.empty(nb + 1)
+        new[0], new[nb] = 0.0, 1.0
+        i, acc = 0, 0.0  # acc: omega collected from old bins before bin i
+        for j in range(1, nb):
+            target = j * share
+            while i < nb - 1 and acc + om[i] < target:
+                acc += om[i]
+                i += 1
+            frac = (target - acc) / om[i] if om[i] > 0.0 else 0.0
+            frac = min(max(frac, 0.0), 1.0)
+            new[j] = old[i] + (old[i + 1] - old[i]) * frac
+        edges[k] = new
+    return edges
+
+
+# ---------------------------------------------------------------------------
+# Statistics and unweighting
+# ---------------------------------------------------------------------------
+
+def channel_stats(w: np.ndarray) -> np.ndarray:
+    """[sum w, sum w^2, n, n with w == 0, max w] of one channel's weights."""
+    w = np.asarray(w, np.float64)
+    return np.array([w.sum(), (w * w).sum(), float(w.size), float((w == 0.0).sum()),
+                     w.max() if w.size else 0.0])
+
+
+def integral(stats: np.ndarray):
+    """Multichannel estimate I = sum_c <w>_c and its error, stats [C][5]."""
+    tot, var = 0.0, 0.0
+    for s1, s2, n, _, _ in stats:
+        if n <= 0:
+            continue
+        mean = s1 / n
+        tot += mean
+        if n > 1:
+            var += max(s2 / n - mean * mean, 0.0) / (n - 1)
+    return tot, math.sqrt(var)
+
+
+def unweighting_efficiency(w: np.ndarray, overweight: float = 1e-3):
+    """Smallest W with sum_i max(0, w_i - W) <= overweight * sum_i w_i; returns
+    (mean(w)/W, W).  Computed exactly from the sorted weights: between two
+    consecutive sorted weights the overweight sum is linear in W."""
+    w = np.sort(np.asarray(w, np.float64))[::-1]
+    n = w.size
+    if n == 0:
+        return 0.0, 0.0
+    total = w.sum()
+    if total <= 0.0:
+        return 0.0, 0.0
+    target = overweight * total
+    csum = np.cumsum(w)
+    # with the k largest weights at or above W, excess(W) = csum[k-1] - k W on
+    # [w[k], w[k-1]]; the first interval whose lower end reaches the target
+    # holds the crossing
+    k = np.arange(1, n + 1, dtype=np.float64)
+    lo = np.append(w[1:], 0.0)
+    ex_lo = csum - k * lo
+    kk = int(np.argmax(ex_lo >= target))
+    W = (csum[kk] - target) / (kk + 1)
+    W = max(W, 0.0)
+    return (total / n) / W if W > 0 else 0.0, W

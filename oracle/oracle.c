@@ -1,0 +1,638 @@
+/*
+ * Plain FP64 CPU oracle for the phase-space hot path of MadSpace
+ * (Heimel, Mattelaer, Winterhalder, arXiv:2602.06895).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests/, __graft_entry__.smoke() and the
+ * cpu_baseline leg of bench.py may load or call this library.  It shares no
+ * code with the HIP library: different sources, headers and channel compiler.
+ *
+ * Every function follows the paper's definitions step by step, in FP64,
+ * without blocking, fusion or reordering; events are independent and are
+ * distributed over OpenMP threads with a static schedule.
+ *
+ * Conventions: metric (+,-,-,-), p = (E, px, py, pz), GeV.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#define ORC_MAX_NODES 64
+#define ORC_MAX_FINAL 16
+#define ORC_MAX_DIMS 64
+#define ORC_MAX_PROPS 64
+
+enum { ORC_LEAF = 0, ORC_CLUSTER = 1, ORC_TNODE = 2 };
+
+/* One channel = one diagram topology.  The root node is sampled first: its
+ * invariant is s-hat.  For a t-channel topology the root is the effective
+ * t-node whose children are the legs along the spine from a to b (section
+ * "s-channel integration order": the t-channel part is one node with
+ * kappa+1 children); for a pure s-channel topology it is the cluster that
+ * decays at s-hat. */
+typedef struct {
+    int32_t n_nodes, root, n_sorder, n_dec;
+    const int32_t* kind;        /* [n_nodes] */
+    const int32_t* particle;    /* leaf: final-state index 0..n-1 */
+    const int32_t* parent;      /* -1 for the root */
+    const int32_t* child_start; /* index into children[] */
+    const int32_t* child_count;
+    const int32_t* children;
+    const double* mass;         /* leaf mass, or propagator mass of a cluster */
+    const double* width;        /* propagator width (clusters) */
+    const double* nu;           /* power-law exponent per cluster (or default) */
+    const char* t_order;        /* kappa-1 letters 'A'/'B' */
+    const int32_t* s_order;     /* clusters other than the root, sampling order */
+    const int32_t* dec_order;   /* clusters decayed with (phi,theta), parents first */
+} orc_channel;
+
+typedef struct {
+    int32_t hadronic;   /* 1: PDF convolution with s-hat sampling; 0: fixed sqrt(s) */
+    int32_t n_final;
+    double s_lab;
+    double shat_min;
+    double nu;          /* default power-law exponent */
+    double reg_a;       /* auxiliary negative mass parameter m^2 = -a */
+    const double* mass; /* [n_final] */
+    /* integrand */
+    int32_t pdf;
+    double pdf_a, pdf_b;
+    double pt_min;      /* <= 0: no cut */
+    int32_t ang;        /* -1, or particle index k: f *= 1 + cos^2(theta_k) */
+    int32_t n_prop;
+    const int32_t* prop_t;    /* 1: q = p_a - sum p_k;  0: q = sum p_k */
+    const uint32_t* prop_set; /* bit k -> final-state particle k */
+    const int32_t* prop_bw;   /* 1: 1/((q^2-M^2)^2 + M^2 G^2);  0: 1/(|q^2| + mu^2) */
+    const double* prop_m;
+    const double* prop_w;
+    const double* prop_mu;
+    /* channel weights alpha_c(x): every channel's propagator list */
+    int32_t n_chan;
+    double alpha_mu;
+    const int32_t* ch_start;  /* [n_chan + 1] into chp_* */
+    const int32_t* chp_t;
+    const uint32_t* chp_set;
+    const double* chp_m;
+    const double* chp_w;
+} orc_process;
+
+/* ------------------------------------------------------------------------ */
+/* Elementary pieces                                                         */
+/* ------------------------------------------------------------------------ */
+
+static const double ORC_PI = 3.14159265358979323846;
+
+/* Kallen function lambda(x, y, z) = (x - y - z)^2 - 4 y z (section 2.2.3). */
+double orc_kallen(double x, double y, double z)
+{
+    double d = x - y - z;
+    return d * d - 4.0 * y * z;
+}
+
+static double mdot(const double a[4], const double b[4])
+{
+    return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+}
+
+/* Power-law invariant mapping G_nu with its Jacobian 1/g (equations
+ * prop_stable_nu, prop_stable_nu1 for nu = 1, prop_flat for nu = 0). */
+double orc_map_nu(double r, double m2, double nu, double xmin, double xmax, double* jac)
+{
+    if (nu == 0.0) {
+        *jac = xmax - xmin;
+        return xmin + (xmax - xmin) * r;
+    }
+    if (nu == 1.0) {
+        double lmax = log(xmax - m2), lmin = log(xmin - m2);
+        double x = exp(r * lmax + (1.0 - r) * lmin) + m2;
+        *jac = (x - m2) * (lmax - lmin);
+        return x;
+    }
+    double e = 1.0 - nu;
+    double A = pow(xmax - m2, e), B = pow(xmin - m2, e);
+    double x = pow(r * A + (1.0 - r) * B, 1.0 / e) + m2;
+    *jac = (A - B) * pow(x - m2, nu) / e;
+    return x;
+}
+
+/* Breit-Wigner mapping G_BW with its Jacobian 1/g (equation prop_massive). */
+double orc_map_bw(double r, double m, double w, double xmin, double xmax, double* jac)
+{
+    double m2 = m * m, mw = m * w;
+    double u1 = atan((xmin - m2) / mw), u2 = atan((xmax - m2) / mw);
+    double x = mw * tan(u1 + (u2 - u1) * r) + m2;
+    *jac = (u2 - u1) * ((x - m2) * (x - m2) + mw * mw) / mw;
+    return x;
+}
+
+/* Invariant of a propagator with mass m and width w: Breit-Wigner for w > 0,
+ * otherwise G_nu; a massless structure gets the auxiliary m^2 = -a. */
+static double map_invariant(double r, double m, double w, double nu, double reg_a,
+                            double xmin, double xmax, double* jac)
+{
+    if (w > 0.0)
+        return orc_map_bw(r, m, w, xmin, xmax, jac);
+    double m2 = (m == 0.0) ? -reg_a : m * m;
+    return orc_map_nu(r, m2, nu, xmin, xmax, jac);
+}
+
+/* Pure boost of k from the rest frame of P (mass m) to the frame in which P
+ * has the given momentum. */
+void orc_boost(const double P[4], double m, const double k[4], double out[4])
+{
+    double pk = P[1] * k[1] + P[2] * k[2] + P[3] * k[3];
+    double e = (P[0] * k[0] + pk) / m;
+    double c = (pk / (P[0] + m) + k[0]) / m;
+    out[0] = e;
+    out[1] = k[1] + c * P[1];
+    out[2] = k[2] + c * P[2];
+    out[3] = k[3] + c * P[3];
+}
+
+/* Rotation R(phi, theta) = R_z(phi) R_y(theta) (section 2.2.6) applied to v,
+ * with the angles given by their cosines and sines. */
+static void rotate(double cphi, double sphi, double cth, double sth, const double v[3], double out[3])
+{
+    double x = v[0] * cth + v[2] * sth;
+    double y = v[1];
+    double z = -v[0] * sth + v[2] * cth;
+    out[0] = x * cphi - y * sphi;
+    out[1] = x * sphi + y * cphi;
+    out[2] = z;
+}
+
+/* Two-particle phase space in (phi, theta) (section 2.2.3, eq. ps2_phi_theta):
+ * P of mass^2 m0sq decays into masses m1, m2; angles sampled uniformly in the
+ * rest frame of P with fixed axes, then boosted back.  Returns the Jacobian
+ * sqrt(lambda)/(8 m0^2) * 2pi * 2. */
+double orc_two_body_decay(const double P[4], double m0sq, double m1, double m2,
+                          double r_phi, double r_theta, double p1[4], double p2[4])
+{
+    double m0 = sqrt(m0sq);
+    double m1s = m1 * m1, m2s = m2 * m2;
+    double lam = orc_kallen(m0sq, m1s, m2s);
+    double e1 = (m0sq + (m1s - m2s)) / (2.0 * m0);
+    double e2 = (m0sq - (m1s - m2s)) / (2.0 * m0);
+    double q = sqrt(lam) / (2.0 * m0);
+    double phi = 2.0 * ORC_PI * r_phi;
+    double cth = 2.0 * r_theta - 1.0;
+    double sth = sqrt((1.0 - cth) * (1.0 + cth));
+    double k1[4] = {e1, q * sth * cos(phi), q * sth * sin(phi), q * cth};
+    double k2[4] = {e2, -k1[1], -k1[2], -k1[3]};
+    orc_boost(P, m0, k1, p1);
+    orc_boost(P, m0, k2, p2);
+    return sqrt(lam) / (8.0 * m0sq) * (2.0 * ORC_PI) * 2.0;
+}
+
+/* -t range of a 2->2 block from eq. t_invariant_theta at cos(theta) = +1, -1
+ * (the t_inv_min_max operation). */
+void orc_t_inv_min_max(const double pA[4], const double pB[4], double m1, double m2,
+                       double* abst_min, double* abst_max)
+{
+    double P[4] = {pA[0] + pB[0], pA[1] + pB[1], pA[2] + pB[2], pA[3] + pB[3]};
+    double m0sq = mdot(P, P), ma2 = mdot(pA, pA), mb2 = mdot(pB, pB);
+    double m1s = m1 * m1, m2s = m2 * m2;
+    double C = (m0sq + (m1s - m2s)) * (m0sq + (ma2 - mb2));
+    double R = sqrt(orc_kallen(m0sq, m1s, m2s) * orc_kallen(m0sq, ma2, mb2));
+    double t_at_plus = m1s + ma2 - (C - R) / (2.0 * m0sq);
+    double t_at_minus = m1s + ma2 - (C + R) / (2.0 * m0sq);
+    *abst_min = fmax(0.0, -t_at_plus);
+    *abst_max = -t_at_minus;
+}
+
+/* Two-particle phase space in (phi, t) (section 2.2.4, eqs. t_invariant_theta,
+ * 2_to_2_mapping, ps2_phi_t).  |t| = G_nu(r_t; 0, |t|_min, |t|_max) with the
+ * auxiliary mass of a massless t-propagator; theta is measured from the
+ * direction of p_A in the rest frame of P = p_A + p_B, phi around it.
+ * Returns J_t * 2pi / (4 sqrt(lambda(m0^2, ma^2, mb^2))); *abst receives |t|. */
+double orc_two_to_two(const double pA[4], const double pB[4], double m1, double m2,
+                      double r_phi, double r_t, double nu, double reg_a,
+                      double p1[4], double p2[4], double* abst_out)
+{
+    double P[4] = {pA[0] + pB[0], pA[1] + pB[1], pA[2] + pB[2], pA[3] + pB[3]};
+    double m0sq = mdot(P, P), ma2 = mdot(pA, pA), mb2 = mdot(pB, pB);
+    double m0 = sqrt(m0sq);
+    double m1s = m1 * m1, m2s = m2 * m2;
+    double lam12 = orc_kallen(m0sq, m1s, m2s), lamab = orc_kallen(m0sq, ma2, mb2);
+    double C = (m0sq + (m1s - m2s)) * (m0sq + (ma2 - mb2));
+    double R = sqrt(lam12 * lamab);
+    double tmin_abs, tmax_abs;
+    orc_t_inv_min_max(pA, pB, m1, m2, &tmin_abs, &tmax_abs);
+    double jt;
+    double abst = orc_map_nu(r_t, -reg_a, nu, tmin_abs, tmax_abs, &jt);
+    /* invert eq. t_invariant_theta for cos(theta) */
+    double cth = (C - 2.0 * m0sq * (m1s + ma2 + abst)) / R;
+    if (cth > 1.0) cth = 1.0;
+    if (cth < -1.0) cth = -1.0;
+    double sth = sqrt((1.0 - cth) * (1.0 + cth));
+    double phi = 2.0 * ORC_PI * r_phi;
+    double q = sqrt(lam12) / (2.0 * m0);
+    double e1 = (m0sq + (m1s - m2s)) / (2.0 * m0);
+    double e2 = (m0sq - (m1s - m2s)) / (2.0 * m0);
+    double v1[3] = {q * sth * cos(phi), q * sth * sin(phi), q * cth};
+    /* direction of p_A in the rest frame of P */
+    double Pbar[4] = {P[0], -P[1], -P[2], -P[3]};
+    double pAr[4];
+    orc_boost(Pbar, m0, pA, pAr);
+    double len = sqrt(pAr[1] * pAr[1] + pAr[2] * pAr[2] + pAr[3] * pAr[3]);
+    double nx = pAr[1] / len, ny = pAr[2] / len, nz = pAr[3] / len;
+    double st = sqrt(nx * nx + ny * ny);
+    double cp = 1.0, sp = 0.0;
+    if (st > 0.0) {
+        cp = nx / st;
+        sp = ny / st;
+    }
+    double w1[3];
+    rotate(cp, sp, nz, st, v1, w1);
+    double k1[4] = {e1, w1[0], w1[1], w1[2]};
+    double k2[4] = {e2, -w1[0], -w1[1], -w1[2]};
+    orc_boost(P, m0, k1, p1);
+    orc_boost(P, m0, k2, p2);
+    if (abst_out) *abst_out = abst;
+    return jt * (2.0 * ORC_PI) / (4.0 * sqrt(lamab));
+}
+
+/* PDF convolution (section 2.2.2, eqs. pdf_conv, pdf_sampling): x1 = tau^r,
+ * x2 = tau^(1-r), Jacobian -log(tau)/s_lab (the r_to_x1x2 operation). */
+double orc_r_to_x1x2(double r, double shat, double s_lab, double* x1, double* x2)
+{
+    double tau = shat / s_lab;
+    *x1 = pow(tau, r);
+    *x2 = pow(tau, 1.0 - r);
+    return -log(tau) / s_lab;
+}
+
+/* VEGAS map of one uniform y through a grid with nb bins (edges e_0..e_nb):
+ * bin i = floor(y nb), linear inside the bin, Jacobian nb (e_{i+1} - e_i). */
+double orc_vegas_map(double y, const double* edges, int32_t nb, double* jac)
+{
+    double t = y * nb;
+    int32_t i = (int32_t)floor(t);
+    if (i > nb - 1) i = nb - 1;
+    if (i < 0) i = 0;
+    double wdt = edges[i + 1] - edges[i];
+    *jac = nb * wdt;
+    return edges[i] + wdt * (t - i);
+}
+
+/* ------------------------------------------------------------------------ */
+/* s-channel integration order bounds (section 2.2.7)                        */
+/* ------------------------------------------------------------------------ */
+
+static double node_m_min(const orc_channel* ch, int32_t j, const int32_t* sampled, const double* s)
+{
+    if (ch->kind[j] == ORC_LEAF) return ch->mass[j];
+    if (sampled[j]) return sqrt(s[j]);
+    double sum = 0.0;
+    for (int32_t c = 0; c < ch->child_count[j]; ++c)
+        sum += node_m_min(ch, ch->children[ch->child_start[j] + c], sampled, s);
+    return sum;
+}
+
+/* Walk from node i towards the root until a sampled node r is met and
+ * subtract the minimal masses of everything that branches off the path
+ * (children of r included, children of i excluded). */
+static double node_m_max(const orc_channel* ch, int32_t i, const int32_t* sampled, const double* s)
+{
+    double sub = 0.0;
+    int32_t v = i;
+    while (!sampled[v]) {
+        int32_t par = ch->parent[v];
+        for (int32_t c = 0; c < ch->child_count[par]; ++c) {
+            int32_t sib = ch->children[ch->child_start[par] + c];
+            if (sib != v) sub += node_m_min(ch, sib, sampled, s);
+        }
+        v = par;
+    }
+    return sqrt(s[v]) - sub;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One event                                                                 */
+/* ------------------------------------------------------------------------ */
+
+static double pdf_toy(const orc_process* pr, double x)
+{
+    return pow(x, pr->pdf_a) * pow(1.0 - x, pr->pdf_b);
+}
+
+static double prop_q2(int32_t t_type, uint32_t set, const double pa[4], double mom[][4], int32_t n)
+{
+    double q[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int32_t k = 0; k < n; ++k)
+        if (set & (1u << k))
+            for (int c = 0; c < 4; ++c) q[c] += mom[k][c];
+    if (t_type)
+        for (int c = 0; c < 4; ++c) q[c] = pa[c] - q[c];
+    return mdot(q, q);
+}
+
+typedef struct {
+    double p[ORC_MAX_FINAL + 2][4]; /* lab frame: a, b, 1..n */
+    double x1, x2, jac, w, alpha, f;
+    double inv[ORC_MAX_NODES];      /* sampled invariants per node (0 if none) */
+    double tabs[ORC_MAX_FINAL];     /* |t| sampled by each 2->2 block, in order */
+} orc_event;
+
+/* The whole per-event chain for channel `chan` of process `pr`, given the
+ * uniforms y[d] (before VEGAS) and the channel's VEGAS grid (NULL: none). */
+static void event(const orc_process* pr, const orc_channel* ch, int32_t chan,
+                  const double* y, int32_t dims, const double* grid, int32_t nb, orc_event* ev)
+{
+    const int32_t n = pr->n_final;
+    double r[ORC_MAX_DIMS];
+    double jv = 1.0;
+    for (int32_t k = 0; k < dims; ++k) {
+        if (grid) {
+            double jk;
+            r[k] = orc_vegas_map(y[k], grid + (size_t)k * (nb + 1), nb, &jk);
+            jv *= jk;
+        } else {
+            r[k] = y[k];
+        }
+    }
+
+    double s[ORC_MAX_NODES];
+    int32_t sampled[ORC_MAX_NODES];
+    double mom[ORC_MAX_NODES][4];
+    for (int32_t j = 0; j < ch->n_nodes; ++j) {
+        s[j] = 0.0;
+        sampled[j] = 0;
+        ev->inv[j] = 0.0;
+    }
+    double factors[4 * ORC_MAX_FINAL + 8];
+    int32_t nf = 0;
+    factors[nf++] = pow(2.0 * ORC_PI, 4.0 - 3.0 * n); /* (2pi)^(4-3n), section 2.2 */
+
+    int32_t k = 0; /* dimension cursor */
+    const int32_t root = ch->root;
+
+    /* (1) s-hat: power-law map (or Breit-Wigner for a resonant pure-s root)
+     *     on [shat_min, s_lab]; fixed for lepton beams. */
+    double shat;
+    if (pr->hadronic) {
+        double m = 0.0, w = 0.0, nu = pr->nu;
+        if (ch->kind[root] == ORC_CLUSTER) {
+            m = ch->mass[root];
+            w = ch->width[root];
+            nu = ch->nu[root];
+        }
+        double lo = pr->shat_min;
+        double msum = 0.0;
+        for (int32_t i = 0; i < n; ++i) msum += pr->mass[i];
+        if (msum * msum > lo) lo = msum * msum;
+        double js;
+        shat = map_invariant(r[k++], m, w, nu, pr->reg_a, lo, pr->s_lab, &js);
+        factors[nf++] = js;
+    } else {
+        shat = pr->s_lab;
+    }
+    s[root] = shat;
+    sampled[root] = 1;
+    ev->inv[root] = shat;
+
+    /* (2) time-like invariants of the decay clusters in the channel's order,
+     *     bounds from the minimal/maximal mass recursion (section 2.2.7). */
+    for (int32_t q = 0; q < ch->n_sorder; ++q) {
+        int32_t i = ch->s_order[q];
+        double mmin = 0.0;
+        for (int32_t c = 0; c < ch->child_count[i]; ++c)
+            mmin += node_m_min(ch, ch->children[ch->child_start[i] + c], sampled, s);
+        double mmax = node_m_max(ch, i, sampled, s);
+        double ji;
+        s[i] = map_invariant(r[k++], ch->mass[i], ch->width[i], ch->nu[i], pr->reg_a,
+                             mmin * mmin, mmax * mmax, &ji);
+        sampled[i] = 1;
+        ev->inv[i] = s[i];
+        factors[nf++] = ji;
+    }
+
+    /* (3) t-channel: generation order sigma from the A/B choices, then the
+     *     kappa-1 time-like invariants s_1..s_{kappa-1} (section 2.2.8). */
+    int32_t kappa = 0;
+    int32_t sigma[ORC_MAX_FINAL + 1];
+    int32_t from_a[ORC_MAX_FINAL + 1];
+    double st[ORC_MAX_FINAL + 1]; /* s_0 .. s_{kappa-1} */
+    if (ch->kind[root] == ORC_TNODE) {
+        kappa = ch->child_count[root] - 1;
+        const int32_t* legs = ch->children + ch->child_start[root];
+        int32_t lo = 0, hi = kappa;
+        for (int32_t i = 1; i < kappa; ++i) {
+            if (ch->t_order[i - 1] == 'A') {
+                sigma[i] = legs[lo++];
+                from_a[i] = 1;
+            } else {
+                sigma[i] = legs[hi--];
+                from_a[i] = 0;
+            }
+        }
+        sigma[kappa] = legs[lo];
+        sigma[kappa + 1] = legs[hi];
+        st[0] = shat;
+        for (int32_t i = 1; i < kappa; ++i) {
+            double msum = 0.0;
+            for (int32_t j = i + 1; j <= kappa + 1; ++j) msum += node_m_min(ch, sigma[j], sampled, s);
+            double mi = node_m_min(ch, sigma[i], sampled, s);
+            double smin = msum * msum;
+            double dm = sqrt(st[i - 1]) - mi;
+            double ji;
+            st[i] = map_invariant(r[k++], 0.0, 0.0, pr->nu, pr->reg_a, smin, dm * dm, &ji);
+            factors[nf++] = ji;
+        }
+    }
+
+    /* (4) momentum fractions */
+    double x1 = 1.0, x2 = 1.0;
+    if (pr->hadronic) {
+        double jx = orc_r_to_x1x2(r[k++], shat, pr->s_lab, &x1, &x2);
+        factors[nf++] = jx;
+    }
+
+    /* (5) incoming momenta in the partonic centre-of-mass frame (com_p_in) */
+    double rs = sqrt(shat);
+    double pa[4] = {0.5 * rs, 0.0, 0.0, 0.5 * rs};
+    double pb[4] = {0.5 * rs, 0.0, 0.0, -0.5 * rs};
+
+    /* (6) chain of 2->2 blocks with the corrected leg update: peeling the leg
+     *     next to A replaces p_A by p_A - p1, next to B replaces p_B by p_B - p2. */
+    if (ch->kind[root] == ORC_TNODE) {
+        double pA[4], pB[4];
+        memcpy(pA, pa, sizeof pA);
+        memcpy(pB, pb, sizeof pB);
+        for (int32_t i = 1; i <= kappa; ++i) {
+            double m1, m2;
+            if (i == kappa) {
+                m1 = node_m_min(ch, sigma[kappa], sampled, s);
+                m2 = node_m_min(ch, sigma[kappa + 1], sampled, s);
+            } else if (from_a[i]) {
+                m1 = node_m_min(ch, sigma[i], sampled, s);
+                m2 = sqrt(st[i]);
+            } else {
+                m1 = sqrt(st[i]);
+                m2 = node_m_min(ch, sigma[i], sampled, s);
+            }
+            double r_phi = r[k++], r_t = r[k++];
+            double p1[4], p2[4];
+            double jb = orc_two_to_two(pA, pB, m1, m2, r_phi, r_t, pr->nu, pr->reg_a, p1, p2,
+                                       &ev->tabs[i - 1]);
+            factors[nf++] = jb;
+            if (i == kappa) {
+                memcpy(mom[sigma[kappa]], p1, sizeof p1);
+                memcpy(mom[sigma[kappa + 1]], p2, sizeof p2);
+            } else if (from_a[i]) {
+                memcpy(mom[sigma[i]], p1, sizeof p1);
+                for (int c = 0; c < 4; ++c) pA[c] -= p1[c];
+            } else {
+                memcpy(mom[sigma[i]], p2, sizeof p2);
+                for (int c = 0; c < 4; ++c) pB[c] -= p2[c];
+            }
+        }
+    } else {
+        mom[root][0] = rs;
+        mom[root][1] = mom[root][2] = mom[root][3] = 0.0;
+    }
+
+    /* (7) (phi, theta) decays of the clusters, parents before children */
+    for (int32_t q = 0; q < ch->n_dec; ++q) {
+        int32_t c = ch->dec_order[q];
+        int32_t c0 = ch->children[ch->child_start[c]], c1 = ch->children[ch->child_start[c] + 1];
+        double m1 = node_m_min(ch, c0, sampled, s), m2 = node_m_min(ch, c1, sampled, s);
+        double r_phi = r[k++], r_theta = r[k++];
+        double jd = orc_two_body_decay(mom[c], s[c], m1, m2, r_phi, r_theta, mom[c0], mom[c1]);
+        factors[nf++] = jd;
+    }
+    factors[nf++] = 1.0; /* channel constant */
+    factors[nf++] = jv;  /* VEGAS Jacobian */
+
+    /* final-state momenta in the partonic frame, by particle label */
+    double pf[ORC_MAX_FINAL][4];
+    for (int32_t j = 0; j < ch->n_nodes; ++j)
+        if (ch->kind[j] == ORC_LEAF) memcpy(pf[ch->particle[j]], mom[j], sizeof pf[0]);
+
+    /* (8) boost_beam: longitudinal boost to the lab frame */
+    double g = 1.0, gb = 0.0;
+    if (pr->hadronic) {
+        double sq = sqrt(x1 * x2);
+        g = (x1 + x2) / (2.0 * sq);
+        gb = (x1 - x2) / (2.0 * sq);
+    }
+    double (*out)[4] = ev->p;
+    const double* src[ORC_MAX_FINAL + 2];
+    src[0] = pa;
+    src[1] = pb;
+    for (int32_t i = 0; i < n; ++i) src[i + 2] = pf[i];
+    for (int32_t i = 0; i < n + 2; ++i) {
+        out[i][0] = g * src[i][0] + gb * src[i][3];
+        out[i][1] = src[i][1];
+        out[i][2] = src[i][2];
+        out[i][3] = gb * src[i][0] + g * src[i][3];
+    }
+
+    /* (9) reduce_product of all Jacobian factors, left to right */
+    double jac = 1.0;
+    for (int32_t i = 0; i < nf; ++i) jac *= factors[i];
+
+    /* (10) cut_unphysical: non-finite values, momentum fractions outside
+     *      (0, 1], negative energies or a non-positive Jacobian -> weight 0 */
+    int ok = isfinite(jac) && jac > 0.0;
+    for (int32_t i = 0; i < n + 2 && ok; ++i)
+        for (int c = 0; c < 4; ++c)
+            if (!isfinite(out[i][c])) ok = 0;
+    for (int32_t i = 0; i < n + 2 && ok; ++i)
+        if (out[i][0] < 0.0) ok = 0;
+    if (pr->hadronic && ok)
+        if (!(isfinite(x1) && isfinite(x2) && x1 > 0.0 && x1 <= 1.0 && x2 > 0.0 && x2 <= 1.0)) ok = 0;
+    if (!ok) jac = 0.0;
+
+    /* (11) integrand f and local channel weight alpha_c(x) (SDE multichannel,
+     *      eq. multi-channel-mg) from invariants of the partonic-frame momenta */
+    double f = 0.0, alpha = 0.0;
+    if (ok) {
+        f = 1.0;
+        if (pr->pdf) f *= pdf_toy(pr, x1) * pdf_toy(pr, x2);
+        if (pr->pt_min > 0.0)
+            for (int32_t i = 0; i < n; ++i)
+                if (!(pf[i][1] * pf[i][1] + pf[i][2] * pf[i][2] > pr->pt_min * pr->pt_min)) f = 0.0;
+        if (pr->ang >= 0) {
+            const double* p = pf[pr->ang];
+            double c = p[3] / sqrt(p[1] * p[1] + p[2] * p[2] + p[3] * p[3]);
+            f *= 1.0 + c * c;
+        }
+        for (int32_t u = 0; u < pr->n_prop; ++u) {
+            double q2 = prop_q2(pr->prop_t[u], pr->prop_set[u], pa, pf, n);
+            if (pr->prop_bw[u]) {
+                double m2 = pr->prop_m[u] * pr->prop_m[u], mw = pr->prop_m[u] * pr->prop_w[u];
+                f *= 1.0 / ((q2 - m2) * (q2 - m2) + mw * mw);
+            } else {
+                f *= 1.0 / (fabs(q2) + pr->prop_mu[u] * pr->prop_mu[u]);
+            }
+        }
+        if (pr->n_chan <= 1) {
+            alpha = 1.0;
+        } else {
+            double den = 0.0, mine = 0.0;
+            for (int32_t c = 0; c < pr->n_chan; ++c) {
+                double P = 1.0;
+                for (int32_t u = pr->ch_start[c]; u < pr->ch_start[c + 1]; ++u) {
+                    double q2 = prop_q2(pr->chp_t[u], pr->chp_set[u], pa, pf, n);
+                    double m = pr->chp_m[u];
+                    if (m > 0.0) {
+                        double mw = m * pr->chp_w[u];
+                        P *= 1.0 / ((q2 - m * m) * (q2 - m * m) + mw * mw);
+                    } else {
+                        double d = fabs(q2) + pr->alpha_mu * pr->alpha_mu;
+                        P *= 1.0 / (d * d);
+                    }
+                }
+                den += P;
+                if (c == chan) mine = P;
+            }
+            alpha = mine / den;
+        }
+    }
+    ev->x1 = x1;
+    ev->x2 = x2;
+    ev->jac = jac;
+    ev->f = f;
+    ev->alpha = alpha;
+    ev->w = alpha * f * jac;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Batched entry point                                                       */
+/* ------------------------------------------------------------------------ */
+
+/* Map n events of one channel.  y: [dims][n] uniforms before VEGAS; grid:
+ * [dims][nb+1] edges or NULL.  Outputs (any may be NULL): p [4][n_final+2][n],
+ * x1x2 [2][n], jac [n], w [n], alpha [n], f [n], inv [n_nodes][n],
+ * tabs [kappa][n] (|t| of each 2->2 block).
+ * Returns 0, or -1 on invalid sizes. */
+int orc_map(const orc_process* pr, const orc_channel* ch, int32_t chan, int32_t dims, int64_t n,
+            const double* y, const double* grid, int32_t nb, double* p, double* x1x2, double* jac,
+            double* w, double* alpha, double* f, double* inv, double* tabs, int32_t nthreads)
+{
+    if (dims > ORC_MAX_DIMS || pr->n_final > ORC_MAX_FINAL || ch->n_nodes > ORC_MAX_NODES) return -1;
+    const int32_t np = pr->n_final + 2;
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t e = 0; e < n; ++e) {
+        double ye[ORC_MAX_DIMS];
+        for (int32_t k = 0; k < dims; ++k) ye[k] = y[(size_t)k * n + e];
+        orc_event ev;
+        event(pr, ch, chan, ye, dims, grid, nb, &ev);
+        if (p)
+            for (int32_t i = 0; i < np; ++i)
+                for (int c = 0; c < 4; ++c) p[((size_t)c * np + i) * n + e] = ev.p[i][c];
+        if (x1x2) {
+            x1x2[e] = ev.x1;
+            x1x2[n + e] = ev.x2;
+        }
+        if (jac) jac[e] = ev.jac;
+        if (w) w[e] = ev.w;
+        if (alpha) alpha[e] = ev.alpha;
+        if (f) f[e] = ev.f;
+        if (inv)
+            for (int32_t j = 0; j < ch->n_nodes; ++j) inv[(size_t)j * n + e] = ev.inv[j];
+        if (tabs && ch->kind[ch->root] == ORC_TNODE)
+            for (int32_t j = 0; j < ch->child_count[ch->root] - 1; ++j) tabs[(size_t)j * n + e] = ev.tabs[j];
+    }
+    return 0;
+}

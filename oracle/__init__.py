@@ -26,32 +26,39 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# Two builds of the same source: the reference (SSE2 doubles, no FMA
+# contraction) and an x87 build whose intermediates carry extra precision.
+# The second only serves as an independent rounding of the same formulas:
+# the spread between them estimates each event's FP64 forward error.
+_VARIANTS = {
+    "ref": ("liboracle.so", ["-ffp-contract=off"]),
+    "x87": ("liboracle_x87.so", ["-ffp-contract=off", "-mfpmath=387"]),
+}
 
 LEAF, CLUSTER, TNODE = 0, 1, 2
 
 
 def build(force: bool = False) -> str:
-    """Compile oracle.c into liboracle.so with gcc (plain -O2, no fast-math,
-    no FMA contraction, OpenMP)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-               "-Wall", "-Wno-unused-function", _SRC, "-o", tmp, "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+    """Compile oracle.c with gcc (plain -O2, no fast-math, OpenMP)."""
+    for name, (so, flags) in _VARIANTS.items():
+        out = os.path.join(_HERE, so)
+        if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+            tmp = out + ".tmp%d" % os.getpid()
+            cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-Wall",
+                   "-Wno-unused-function"] + flags + [_SRC, "-o", tmp, "-lm"]
+            subprocess.run(cmd, check=True)
+            os.replace(tmp, out)
+    return os.path.join(_HERE, _VARIANTS["ref"][0])
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
+def lib(variant: str = "ref"):
+    if variant not in _libs:
         build()
-        L = C.CDLL(_LIB)
-        dp, ip = C.POINTER(C.c_double), C.POINTER(C.c_int32)
+        L = C.CDLL(os.path.join(_HERE, _VARIANTS[variant][0]))
+        dp = C.POINTER(C.c_double)
         L.orc_map.restype = C.c_int
         L.orc_kallen.restype = C.c_double
         L.orc_kallen.argtypes = [C.c_double] * 3
@@ -63,18 +70,17 @@ def lib():
         L.orc_two_body_decay.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_double,
                                          C.c_double, dp, dp]
         L.orc_two_to_two.restype = C.c_double
-        L.orc_two_to_two.argtypes = [dp, dp, C.c_double, C.c_double, C.c_double, C.c_double,
-                                     C.c_double, C.c_double, dp, dp, dp]
-        L.orc_t_inv_min_max.restype = None
-        L.orc_t_inv_min_max.argtypes = [dp, dp, C.c_double, C.c_double, dp, dp]
+        L.orc_two_to_two.argtypes = [dp, dp] + [C.c_double] * 9 + [dp, dp, dp]
+        L.orc_t_range.restype = None
+        L.orc_t_range.argtypes = [C.c_double] * 5 + [dp, dp]
         L.orc_r_to_x1x2.restype = C.c_double
         L.orc_r_to_x1x2.argtypes = [C.c_double, C.c_double, C.c_double, dp, dp]
         L.orc_vegas_map.restype = C.c_double
         L.orc_vegas_map.argtypes = [C.c_double, dp, C.c_int32, dp]
         L.orc_boost.restype = None
         L.orc_boost.argtypes = [dp, C.c_double, dp, dp]
-        _lib = L
-    return _lib
+        _libs[variant] = L
+    return _libs[variant]
 
 
 class _Channel(C.Structure):
@@ -284,7 +290,7 @@ class Process:
         return np.tile(e, (self.dims[chan], 1))
 
     def map(self, chan: int, y: np.ndarray, grid: np.ndarray | None = None,
-            nthreads: int = 0, want_inv: bool = False) -> dict:
+            nthreads: int = 0, want_inv: bool = False, variant: str = "ref") -> dict:
         """Run the per-event chain on uniforms y [dims][n] through the VEGAS grid
         [dims][nb+1] (None: no VEGAS step).  Returns p [4][n+2][N] (lab frame,
         incoming a, b first), x1x2 [2][N], jac, w, alpha, f (and inv when asked)."""
@@ -306,13 +312,35 @@ class Process:
                 raise ValueError("grid shape mismatch")
         nt = nthreads if nthreads > 0 else (os.cpu_count() or 1)
         dp = lambda a: a.ctypes.data_as(C.c_void_p) if a is not None else None
-        rc = lib().orc_map(C.byref(self._proc), C.byref(self._chs[chan]), C.c_int32(chan),
+        rc = lib(variant).orc_map(C.byref(self._proc), C.byref(self._chs[chan]), C.c_int32(chan),
                            C.c_int32(d), C.c_int64(n), dp(y), dp(g), C.c_int32(self.nbins),
                            dp(out["p"]), dp(out["x1x2"]), dp(out["jac"]), dp(out["w"]),
                            dp(out["alpha"]), dp(out["f"]), dp(out.get("inv")),
                            dp(out.get("tabs")), C.c_int32(nt))
         if rc != 0:
             raise ValueError("oracle rejected the sizes")
+        return out
+
+    def forward_error(self, chan: int, y: np.ndarray, grid: np.ndarray | None = None,
+                      ref: dict | None = None) -> dict:
+        """Per-event estimate of the FP64 forward error of the reference
+        evaluation: the largest deviation from it among (a) the x87 build and
+        (b, c) the reference build on inputs moved by one ulp up and down.
+        Returns relative deviations of w and jac, and momentum deviations in
+        units of the event's largest energy."""
+        ref = ref if ref is not None else self.map(chan, y, grid)
+        y = np.asarray(y, np.float64)
+        alts = [self.map(chan, y, grid, variant="x87"),
+                self.map(chan, np.nextafter(y, 1.0), grid),
+                self.map(chan, np.nextafter(y, 0.0), grid)]
+        emax = np.abs(ref["p"][0]).max(axis=0)
+        out = {}
+        for key in ("w", "jac"):
+            a = ref[key]
+            den = np.where(a != 0.0, np.abs(a), 1.0)
+            out[key] = np.max([np.abs(o[key] - a) / den for o in alts], axis=0)
+        out["p"] = np.max([np.abs(o["p"] - ref["p"]).max(axis=(0, 1)) / np.where(emax > 0, emax, 1.0)
+                           for o in alts], axis=0)
         return out
 
 

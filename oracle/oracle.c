@@ -183,40 +183,52 @@ double orc_two_body_decay(const double P[4], double m0sq, double m1, double m2,
     return sqrt(lam) / (8.0 * m0sq) * (2.0 * ORC_PI) * 2.0;
 }
 
-/* -t range of a 2->2 block from eq. t_invariant_theta at cos(theta) = +1, -1
- * (the t_inv_min_max operation). */
-void orc_t_inv_min_max(const double pA[4], const double pB[4], double m1, double m2,
-                       double* abst_min, double* abst_max)
+/* -t range of a 2->2 block (the t_inv_min_max operation): eq. t_invariant_theta
+ * at cos(theta) = +1 and -1, for invariants m0^2 = (p_A + p_B)^2, ma^2 = p_A^2,
+ * mb^2 = p_B^2 and outgoing masses m1, m2.  The root of smaller magnitude
+ * (cos(theta) = +1), whose two terms cancel, is taken from the product of the
+ * roots,
+ *   t+ t- = (m1^2 - ma^2)(m2^2 - mb^2)
+ *         + (ma^2 - mb^2 - m1^2 + m2^2)(ma^2 m2^2 - m1^2 mb^2) / m0^2,
+ * which is exact algebra on the same two roots; it keeps |t|_min accurate
+ * when it is far below the rounding noise of the other root (it is exactly 0
+ * for massless external legs). */
+void orc_t_range(double m0sq, double ma2, double mb2, double m1, double m2,
+                 double* abst_min, double* abst_max)
 {
-    double P[4] = {pA[0] + pB[0], pA[1] + pB[1], pA[2] + pB[2], pA[3] + pB[3]};
-    double m0sq = mdot(P, P), ma2 = mdot(pA, pA), mb2 = mdot(pB, pB);
     double m1s = m1 * m1, m2s = m2 * m2;
     double C = (m0sq + (m1s - m2s)) * (m0sq + (ma2 - mb2));
     double R = sqrt(orc_kallen(m0sq, m1s, m2s) * orc_kallen(m0sq, ma2, mb2));
-    double t_at_plus = m1s + ma2 - (C - R) / (2.0 * m0sq);
-    double t_at_minus = m1s + ma2 - (C + R) / (2.0 * m0sq);
-    *abst_min = fmax(0.0, -t_at_plus);
-    *abst_max = -t_at_minus;
+    double prod = (m1s - ma2) * (m2s - mb2) + (ma2 - mb2 - m1s + m2s) * (ma2 * m2s - m1s * mb2) / m0sq;
+    /* t at cos(theta) = -1 is the root of larger magnitude: evaluate it
+     * directly, the other one from the product */
+    double t_minus = m1s + ma2 - (C + R) / (2.0 * m0sq);
+    double t_plus = (t_minus != 0.0) ? prod / t_minus : 0.0;
+    *abst_min = fmax(0.0, -t_plus);
+    *abst_max = -t_minus;
 }
 
 /* Two-particle phase space in (phi, t) (section 2.2.4, eqs. t_invariant_theta,
- * 2_to_2_mapping, ps2_phi_t).  |t| = G_nu(r_t; 0, |t|_min, |t|_max) with the
- * auxiliary mass of a massless t-propagator; theta is measured from the
- * direction of p_A in the rest frame of P = p_A + p_B, phi around it.
+ * 2_to_2_mapping, ps2_phi_t).  p_A, p_B fix the frame; their invariants
+ * m0sq = (p_A + p_B)^2, ma2 = p_A^2, mb2 = p_B^2 are the values already
+ * sampled upstream (s-hat or a time-like invariant, and the |t| of earlier
+ * blocks), which the momenta satisfy up to rounding.
+ * |t| = G_nu(r_t; 0, |t|_min, |t|_max) with the auxiliary mass of a massless
+ * t-propagator; theta is measured from the direction of p_A in the rest
+ * frame of P = p_A + p_B, phi around it.
  * Returns J_t * 2pi / (4 sqrt(lambda(m0^2, ma^2, mb^2))); *abst receives |t|. */
-double orc_two_to_two(const double pA[4], const double pB[4], double m1, double m2,
-                      double r_phi, double r_t, double nu, double reg_a,
+double orc_two_to_two(const double pA[4], const double pB[4], double m0sq, double ma2, double mb2,
+                      double m1, double m2, double r_phi, double r_t, double nu, double reg_a,
                       double p1[4], double p2[4], double* abst_out)
 {
     double P[4] = {pA[0] + pB[0], pA[1] + pB[1], pA[2] + pB[2], pA[3] + pB[3]};
-    double m0sq = mdot(P, P), ma2 = mdot(pA, pA), mb2 = mdot(pB, pB);
     double m0 = sqrt(m0sq);
     double m1s = m1 * m1, m2s = m2 * m2;
     double lam12 = orc_kallen(m0sq, m1s, m2s), lamab = orc_kallen(m0sq, ma2, mb2);
     double C = (m0sq + (m1s - m2s)) * (m0sq + (ma2 - mb2));
     double R = sqrt(lam12 * lamab);
     double tmin_abs, tmax_abs;
-    orc_t_inv_min_max(pA, pB, m1, m2, &tmin_abs, &tmax_abs);
+    orc_t_range(m0sq, ma2, mb2, m1, m2, &tmin_abs, &tmax_abs);
     double jt;
     double abst = orc_map_nu(r_t, -reg_a, nu, tmin_abs, tmax_abs, &jt);
     /* invert eq. t_invariant_theta for cos(theta) */
@@ -458,6 +470,7 @@ static void event(const orc_process* pr, const orc_channel* ch, int32_t chan,
         double pA[4], pB[4];
         memcpy(pA, pa, sizeof pA);
         memcpy(pB, pb, sizeof pB);
+        double ma2 = 0.0, mb2 = 0.0; /* p_A^2, p_B^2: 0, then the t of the block that updated them */
         for (int32_t i = 1; i <= kappa; ++i) {
             double m1, m2;
             if (i == kappa) {
@@ -472,8 +485,8 @@ static void event(const orc_process* pr, const orc_channel* ch, int32_t chan,
             }
             double r_phi = r[k++], r_t = r[k++];
             double p1[4], p2[4];
-            double jb = orc_two_to_two(pA, pB, m1, m2, r_phi, r_t, pr->nu, pr->reg_a, p1, p2,
-                                       &ev->tabs[i - 1]);
+            double jb = orc_two_to_two(pA, pB, st[i - 1], ma2, mb2, m1, m2, r_phi, r_t, pr->nu,
+                                       pr->reg_a, p1, p2, &ev->tabs[i - 1]);
             factors[nf++] = jb;
             if (i == kappa) {
                 memcpy(mom[sigma[kappa]], p1, sizeof p1);
@@ -481,9 +494,11 @@ static void event(const orc_process* pr, const orc_channel* ch, int32_t chan,
             } else if (from_a[i]) {
                 memcpy(mom[sigma[i]], p1, sizeof p1);
                 for (int c = 0; c < 4; ++c) pA[c] -= p1[c];
+                ma2 = -ev->tabs[i - 1];
             } else {
                 memcpy(mom[sigma[i]], p2, sizeof p2);
                 for (int c = 0; c < 4; ++c) pB[c] -= p2[c];
+                mb2 = -ev->tabs[i - 1];
             }
         }
     } else {

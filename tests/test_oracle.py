@@ -151,12 +151,13 @@ def test_two_to_two_block_invariants(kind):
     L = oracle.lib()
     rng = np.random.default_rng(1)
     pA, pB, m1, m2 = _block_inputs(kind, rng)
-    tlo, thi = C.c_double(), C.c_double()
-    L.orc_t_inv_min_max(_arr(pA), _arr(pB), m1, m2, C.byref(tlo), C.byref(thi))
     P = [pA[c] + pB[c] for c in range(4)]
+    inv = (_minkowski(P), _minkowski(pA), _minkowski(pB))
+    tlo, thi = C.c_double(), C.c_double()
+    L.orc_t_range(*inv, m1, m2, C.byref(tlo), C.byref(thi))
     for _ in range(50):
         p1, p2, at = _arr([0] * 4), _arr([0] * 4), C.c_double()
-        L.orc_two_to_two(_arr(pA), _arr(pB), m1, m2, rng.random(), rng.random(), 0.8, 1e-3,
+        L.orc_two_to_two(_arr(pA), _arr(pB), *inv, m1, m2, rng.random(), rng.random(), 0.8, 1e-3,
                          p1, p2, C.byref(at))
         E = max(abs(x) for x in P)
         q = [pA[c] - p1[c] for c in range(4)]
@@ -190,13 +191,14 @@ def test_two_to_two_jacobian_integrates_to_two_body_volume(kind):
     pA, pB, m1, m2 = _block_inputs(kind, np.random.default_rng(2))
     P = [pA[c] + pB[c] for c in range(4)]
     s = _minkowski(P)
+    inv = (s, _minkowski(pA), _minkowski(pB))
     lam = (s - m1 ** 2 - m2 ** 2) ** 2 - 4 * m1 ** 2 * m2 ** 2
     expect = math.pi * math.sqrt(lam) / (2 * s)
     r, wq = _gl(200)
     for nu in (0.0, 0.3):
         tot = 0.0
         for ri, wi in zip(r, wq):
-            j = L.orc_two_to_two(_arr(pA), _arr(pB), m1, m2, 0.37, ri, nu, 1e-3,
+            j = L.orc_two_to_two(_arr(pA), _arr(pB), *inv, m1, m2, 0.37, ri, nu, 1e-3,
                                  _arr([0] * 4), _arr([0] * 4), None)
             tot += wi * j
             if nu == 0.0 and kind == "com":
@@ -451,7 +453,8 @@ def test_paper_compute_graph_example():
         h = math.sqrt(shat) / 2
         pa, pb = _arr([h, 0, 0, h]), _arr([h, 0, 0, -h])
         p26, p27 = _arr([0] * 4), _arr([0] * 4)
-        j29 = L.orc_two_to_two(pa, pb, math.sqrt(s), 0.0, r[3], r[4], g["nu"], a, p26, p27, None)
+        j29 = L.orc_two_to_two(pa, pb, shat, 0.0, 0.0, math.sqrt(s), 0.0, r[3], r[4], g["nu"], a,
+                               p26, p27, None)
         j33 = L.orc_two_body_decay(p26, s, 0.0, 0.0, r[5], r[6], _arr([0] * 4), _arr([0] * 4))
         expect = g["reduce_product_constant"] * j12 * j15 * j19 * j29 * j33 * 1.0
         if out["jac"][e] > 0:
@@ -630,3 +633,19 @@ def test_philox_uniforms_addressing_and_range():
     hist = np.bincount((big * 64).astype(int), minlength=64)
     chi2 = ((hist - big.size / 64) ** 2 / (big.size / 64)).sum()
     assert chi2 < 120  # 63 dof
+
+
+@pytest.mark.parametrize("cfg,bound", [("c1", 1e-14), ("c2", 1e-7), ("c3", 1e-8)])
+def test_fp64_forward_error_stays_bounded(cfg, bound):
+    """Two roundings of the same formulas (SSE2 and x87 builds, plus one-ulp
+    input moves) agree closely: the t-range roots come from the product of
+    roots and the blocks use the sampled invariants, so no event loses more
+    than a few digits.  (Evaluated naively from momenta, some pure t-channel
+    events disagreed at the 1e-1 level.)"""
+    P = oracle.Process(W.CONFIG_NAMES[cfg]())
+    for c in range(len(P.channels)):
+        y = W.philox_uniforms(2, 0, 0, 50000, P.dims[c])
+        fe = P.forward_error(c, y, P.uniform_grid(c))
+        assert fe["w"].max() < bound
+        assert fe["p"].max() < 1e-4
+        assert np.median(fe["w"]) < 1e-11

@@ -26,13 +26,16 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-# Two builds of the same source: the reference (SSE2 doubles, no FMA
-# contraction) and an x87 build whose intermediates carry extra precision.
-# The second only serves as an independent rounding of the same formulas:
-# the spread between them estimates each event's FP64 forward error.
+# Builds of the same source: the reference (SSE2 doubles, no FMA
+# contraction); an x87 build whose intermediates carry extra precision; and
+# two builds in which every transcendental and square-root result is moved by
+# one ulp up / down.  The others only serve as re-roundings of the same
+# formulas: their spread estimates each event's FP64 forward error.
 _VARIANTS = {
     "ref": ("liboracle.so", ["-ffp-contract=off"]),
     "x87": ("liboracle_x87.so", ["-ffp-contract=off", "-mfpmath=387"]),
+    "up": ("liboracle_up.so", ["-ffp-contract=off", "-DORC_LIBM_NUDGE=1"]),
+    "down": ("liboracle_down.so", ["-ffp-contract=off", "-DORC_LIBM_NUDGE=-1"]),
 }
 
 LEAF, CLUSTER, TNODE = 0, 1, 2
@@ -324,13 +327,16 @@ class Process:
     def forward_error(self, chan: int, y: np.ndarray, grid: np.ndarray | None = None,
                       ref: dict | None = None) -> dict:
         """Per-event estimate of the FP64 forward error of the reference
-        evaluation: the largest deviation from it among (a) the x87 build and
-        (b, c) the reference build on inputs moved by one ulp up and down.
+        evaluation: the largest deviation from it among the x87 build, the
+        builds with every libm result moved one ulp up / down, and the
+        reference build on inputs moved by one ulp up / down.
         Returns relative deviations of w and jac, and momentum deviations in
         units of the event's largest energy."""
         ref = ref if ref is not None else self.map(chan, y, grid)
         y = np.asarray(y, np.float64)
         alts = [self.map(chan, y, grid, variant="x87"),
+                self.map(chan, y, grid, variant="up"),
+                self.map(chan, y, grid, variant="down"),
                 self.map(chan, np.nextafter(y, 1.0), grid),
                 self.map(chan, np.nextafter(y, 0.0), grid)]
         emax = np.abs(ref["p"][0]).max(axis=0)
@@ -341,6 +347,9 @@ class Process:
             out[key] = np.max([np.abs(o[key] - a) / den for o in alts], axis=0)
         out["p"] = np.max([np.abs(o["p"] - ref["p"]).max(axis=(0, 1)) / np.where(emax > 0, emax, 1.0)
                            for o in alts], axis=0)
+        # events that some rounding variant keeps while the reference cuts them
+        # (or the reverse): a cut decided within rounding
+        out["cut_ambiguous"] = np.any([(o["w"] == 0.0) != (ref["w"] == 0.0) for o in alts], axis=0)
         return out
 
 

@@ -16,6 +16,26 @@
 #include <stdint.h>
 #include <string.h>
 
+/* Perturbation builds (forward-error estimation only, never the reference):
+ * with ORC_LIBM_NUDGE = +1 or -1 every inexact transcendental result is
+ * moved by one ulp up or down, standing in for a different math library or
+ * evaluation order.  Square roots (correctly rounded everywhere) and the exact
+ * results 0 and +-1 are left alone. */
+#ifdef ORC_LIBM_NUDGE
+static double orc_nudge(double v)
+{
+    if (v == 0.0 || v == 1.0 || v == -1.0 || !isfinite(v)) return v;
+    return nextafter(v, ORC_LIBM_NUDGE > 0 ? INFINITY : -INFINITY);
+}
+#define pow(a, b) orc_nudge(pow(a, b))
+#define exp(a) orc_nudge(exp(a))
+#define log(a) orc_nudge(log(a))
+#define atan(a) orc_nudge(atan(a))
+#define tan(a) orc_nudge(tan(a))
+#define sin(a) orc_nudge(sin(a))
+#define cos(a) orc_nudge(cos(a))
+#endif
+
 #define ORC_MAX_NODES 64
 #define ORC_MAX_FINAL 16
 #define ORC_MAX_DIMS 64
@@ -522,6 +542,15 @@ static void event(const orc_process* pr, const orc_channel* ch, int32_t chan,
     double pf[ORC_MAX_FINAL][4];
     for (int32_t j = 0; j < ch->n_nodes; ++j)
         if (ch->kind[j] == ORC_LEAF) memcpy(pf[ch->particle[j]], mom[j], sizeof pf[0]);
+#ifdef ORC_LIBM_NUDGE
+    /* perturbation builds: move every component by one ulp, alternating in
+     * direction, so that quantities recomputed from the momenta see a
+     * rounding-size change of the momenta themselves */
+    for (int32_t i = 0; i < n; ++i)
+        for (int c = 0; c < 4; ++c)
+            if (pf[i][c] != 0.0)
+                pf[i][c] = nextafter(pf[i][c], ((i + c + (ORC_LIBM_NUDGE > 0)) & 1) ? INFINITY : -INFINITY);
+#endif
 
     /* (8) boost_beam: longitudinal boost to the lab frame */
     double g = 1.0, gb = 0.0;

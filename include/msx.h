@@ -1,0 +1,186 @@
+/*
+ * msx.h -- C ABI of the MI355X (gfx950) phase-space sampling library.
+ *
+ * The library turns batches of uniform random numbers into collider-event
+ * momenta and importance weights, following the phase-space generator of
+ * Heimel, Mattelaer and Winterhalder, "MadSpace -- Event Generation for the
+ * Era of GPUs and ML" (arXiv:2602.06895):
+ *
+ *   VEGAS grid lookup -> multichannel selection -> chain of phase-space
+ *   mappings (section 2.2) -> Jacobian product -> integrand x channel weight.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns an msx_status and never throws or aborts.
+ *    Argument and shape errors return MSX_ERR_ARG synchronously, before any
+ *    work is enqueued; msx_last_error() then holds a message.
+ *  - Event buffers are DEVICE pointers owned by the caller (the paper's
+ *    zero-copy tensor sharing, section 3.2.7); the context owns its channel
+ *    tables, VEGAS grids, statistics and scratch, and msx_destroy frees them.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
+ *    the call returns without waiting, except where a function says it
+ *    synchronises.  A context is not thread-safe; use one per host thread.
+ *  - Layout is structure-of-arrays with the event index fastest:
+ *      y     [d][n]               uniforms in (0,1), before VEGAS
+ *      p     [4][np][n]           (E, px, py, pz) of np = n_final + 2 momenta:
+ *                                 incoming a, b first, then final-state
+ *                                 particles by label; lab frame
+ *      x1x2  [2][n]               momentum fractions (hadronic beams only)
+ *      jac / w / alpha [n]        double
+ *      chan  [n]                  int32 channel index (msx_sample)
+ *  - Per-event physics failures are not errors: such events get weight 0
+ *    (the paper's technical cut, operation cut_unphysical).
+ *
+ * Process description (msx_create_channels): a JSON object, or an object
+ * {"processes": [...]} holding several, each with
+ *   "sqrt_s"      collider energy in GeV
+ *   "beams"       "hadronic" (s-hat sampled, PDF convolution, section 2.2.2)
+ *                 or "fixed" (s-hat = sqrt_s^2, no x1/x2)
+ *   "shat_min"    lower bound of s-hat in GeV^2 (hadronic)
+ *   "masses"      outgoing masses; particles are labelled 1..n
+ *   "nu"          default power-law exponent (section 2.2.1), "regulator" a
+ *                 (auxiliary mass^2 -a used for massless structures)
+ *   "vegas_bins"  bins per VEGAS dimension
+ *   "integrand"   toy integrand: "pdf": [a, b] for x^a (1-x)^b on both
+ *                 momentum fractions; "pt_min"; "ang": k for 1 + cos^2 of
+ *                 particle k (fixed beams); "props": list of
+ *                 {"t": bool, "particles": [...], "bw": bool, "m", "w", "mu"}
+ *                 factors 1/(|q^2| + mu^2) or 1/((q^2 - m^2)^2 + m^2 w^2)
+ *                 with q = p_a - sum p_k (t) or sum p_k (s)
+ *   "alpha_mu"    present: local multichannel weights alpha_c(x) from the
+ *                 channels' propagator denominators (section 2.1.1); absent:
+ *                 alpha = 1
+ *   "channels"    diagram topologies:
+ *                   {"t_chain": [leg...], "t_order": "AB.."}  legs along the
+ *                   t-channel spine from incoming a to b, and for each of the
+ *                   first kappa-1 generation steps whether the next leg is
+ *                   peeled from the A or the B side (section 2.2.8);
+ *                   {"s": cluster}  pure s-channel.
+ *                 A leg is a particle label or a cluster
+ *                 {"d": [child, child], "m", "w", "nu", "order"}.
+ * Random-number dimensions of a channel, in order: s-hat (hadronic), the
+ * cluster invariants in sampling order, the kappa-1 t-channel invariants,
+ * x1 (hadronic), (r_phi, r_t) per 2->2 block, (r_phi, r_theta) per decay in
+ * depth-first order -- the order of the paper's compute-graph example
+ * (section 3.2.1).
+ */
+#ifndef MSX_H
+#define MSX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MSX_OK = 0,
+    MSX_ERR_ARG = 1,         /* invalid argument, size or description */
+    MSX_ERR_DEVICE = 2,      /* a HIP runtime call failed */
+    MSX_ERR_OOM = 3,         /* device allocation failed */
+    MSX_ERR_UNSUPPORTED = 4, /* valid request beyond this build's limits */
+    MSX_ERR_STATE = 5        /* call not valid in the context's state */
+} msx_status;
+
+typedef struct msx_ctx msx_ctx;
+
+enum { MSX_FP64 = 0 };
+
+/* Metadata keys for msx_get_meta (integer keys, in the spirit of the UMAMI
+ * interface of section 3.3). `index` selects a channel where noted. */
+enum {
+    MSX_META_N_CHANNELS = 0,   /* number of channels (all processes) */
+    MSX_META_DIMS = 1,         /* random dimensions of channel `index` */
+    MSX_META_N_MOMENTA = 2,    /* np = n_final + 2 of channel `index` */
+    MSX_META_HADRONIC = 3,     /* 1 if channel `index` has x1/x2 */
+    MSX_META_VEGAS_BINS = 4,   /* bins per dimension of channel `index` */
+    MSX_META_MAX_MOMENTA = 5,  /* largest np over all channels */
+    MSX_META_PROCESS = 6,      /* process index of channel `index` */
+    MSX_META_DEVICE = 7        /* HIP device ordinal of the context */
+};
+
+/* Text of the last error on this context (or of the last failed create when
+ * ctx is NULL).  Owned by the library; valid until the next call. */
+const char* msx_last_error(const msx_ctx* ctx);
+
+/* Parse the process description, compile every channel into its device
+ * table (section 2.2: recursive decomposition, s- and t-channel orders),
+ * upload tables and uniform VEGAS grids to device `device`.  `precision`
+ * must be MSX_FP64.  On success *out owns all device state. */
+msx_status msx_create_channels(const char* process_json, int32_t precision, int32_t device,
+                               msx_ctx** out);
+
+/* Free every device and host resource of ctx (NULL is allowed). */
+msx_status msx_destroy(msx_ctx* ctx);
+
+msx_status msx_get_meta(const msx_ctx* ctx, int32_t key, int32_t index, int64_t* value);
+
+/* Uniforms of the library's counter-based generator: Philox4x64-10 (Salmon
+ * et al., SC'11) with key (seed, stream_id) and counter (e, k/4, 0, 0);
+ * y[k][i] for event id e = e0 + i is ((word_{k mod 4} >> 11) + 0.5) 2^-53.
+ * msx_sample draws exactly these numbers for event id = counter_offset +
+ * output position.  y: device [d][n]; 1 <= d <= 64. */
+msx_status msx_uniform(msx_ctx* ctx, uint64_t seed, uint64_t stream_id, uint64_t e0, int64_t n,
+                       int32_t d, double* y, void* stream);
+
+/* Forward map of one channel (the parity entry point): y [d][n] uniforms are
+ * pushed through the channel's current VEGAS grid and mapping chain.
+ * Outputs p [4][np][n] (required), x1x2 [2][n] (required for hadronic
+ * beams, must be NULL otherwise), jac [n] (required; 0 for unphysical
+ * events), w [n] (optional: also evaluate alpha_c * f * jac, as msx_weight
+ * would).  n = 0 is a no-op. */
+msx_status msx_map(msx_ctx* ctx, int32_t channel, int64_t n, const double* y, double* p,
+                   double* x1x2, double* jac, double* w, void* stream);
+
+/* Event weight w = alpha_c(x) f(x) jac from momenta p [4][np][n] (lab frame,
+ * as written by msx_map), x1x2 (hadronic) and jac; alpha [n] optional. */
+msx_status msx_weight(msx_ctx* ctx, int32_t channel, int64_t n, const double* p,
+                      const double* x1x2, const double* jac, double* w, double* alpha,
+                      void* stream);
+
+/* Fused production path, all channels in one launch: for channel c,
+ * counts[c] events (host array of n_channels entries) are generated at
+ * output positions [off_c, off_c + counts[c]) with off_c = sum of earlier
+ * counts: Philox uniforms -> VEGAS -> mapping chain -> weight.  Outputs:
+ * p [4][npmax][N] (rows beyond a channel's np untouched), x1x2 [2][N] (or
+ * NULL when no channel is hadronic), w [N], chan [N] (optional), with
+ * N = sum counts.  Per-channel statistics are added to the context's
+ * accumulators (msx_stats).  Results do not depend on launch shapes. */
+msx_status msx_sample(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id,
+                      uint64_t counter_offset, double* p, double* x1x2, double* w, int32_t* chan,
+                      void* stream);
+
+/* Copy the accumulated per-channel statistics to host out [n_channels][5]:
+ * (sum w, sum w^2, n, n with w == 0, max w).  Synchronises `stream`. */
+msx_status msx_stats(msx_ctx* ctx, double* out, void* stream);
+msx_status msx_reset_stats(msx_ctx* ctx, void* stream);
+
+/* Add sum w^2 per VEGAS bin of channel `channel` from uniforms y [d][n] and
+ * weights w [n] into the context's histogram (deterministic order). */
+msx_status msx_vegas_accumulate(msx_ctx* ctx, int32_t channel, int64_t n, const double* y,
+                                const double* w, void* stream);
+
+/* Refine every channel's grid from its accumulated histogram (smoothing,
+ * damping exponent `alpha` > 0, equal-share redistribution; VEGAS as cited
+ * by the paper for its adaptive grids), then clear the histograms.  Channels
+ * with an empty histogram keep their grid. */
+msx_status msx_vegas_update(msx_ctx* ctx, double alpha, void* stream);
+
+/* Host copies of a channel's grid edges [d][bins+1] (checkpoint/resume and
+ * tests).  Both synchronise. set_grid validates monotone edges from 0 to 1. */
+msx_status msx_get_grid(msx_ctx* ctx, int32_t channel, double* edges);
+msx_status msx_set_grid(msx_ctx* ctx, int32_t channel, const double* edges);
+
+/* Unweighting efficiency of weights w [n] >= 0 (device): the smallest W with
+ * sum max(0, w_i - W) <= overweight * sum w_i, and eff = mean(w) / W -- the
+ * on-the-fly maximum weight with an overweight allowance of section 3.4.1.
+ * Results on host; synchronises `stream`. */
+msx_status msx_unweight_eff(msx_ctx* ctx, const double* w, int64_t n, double overweight,
+                            double* eff, double* w_max, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSX_H */

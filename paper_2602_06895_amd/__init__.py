@@ -1,0 +1,263 @@
+"""Python binding of the MI355X phase-space library (libmsx.so, C ABI in
+include/msx.h).
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+libmsx.so.  torch supplies device buffers and the current HIP stream.  There
+is no CPU fallback: without the built library or a GPU every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmsx.so")
+
+FP64 = 0
+META_N_CHANNELS, META_DIMS, META_N_MOMENTA, META_HADRONIC = 0, 1, 2, 3
+META_VEGAS_BINS, META_MAX_MOMENTA, META_PROCESS, META_DEVICE = 4, 5, 6, 7
+STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_DEVICE", 3: "ERR_OOM", 4: "ERR_UNSUPPORTED", 5: "ERR_STATE"}
+
+EXPORTS = ["msx_last_error", "msx_create_channels", "msx_destroy", "msx_get_meta", "msx_uniform", "msx_map",
+           "msx_weight", "msx_sample", "msx_stats", "msx_reset_stats", "msx_vegas_accumulate",
+           "msx_vegas_update", "msx_get_grid", "msx_set_grid", "msx_unweight_eff"]
+
+
+class MsxError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libmsx.so and declare the C signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build()")
+    L = C.CDLL(path)
+    vp, i32, i64, u64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
+    sigs = {
+        "msx_last_error": ([vp], C.c_char_p),
+        "msx_create_channels": ([C.c_char_p, i32, i32, C.POINTER(vp)], C.c_int),
+        "msx_destroy": ([vp], C.c_int),
+        "msx_get_meta": ([vp, i32, i32, C.POINTER(i64)], C.c_int),
+        "msx_uniform": ([vp, u64, u64, u64, i64, i32, vp, vp], C.c_int),
+        "msx_map": ([vp, i32, i64, vp, vp, vp, vp, vp, vp], C.c_int),
+        "msx_weight": ([vp, i32, i64, vp, vp, vp, vp, vp, vp], C.c_int),
+        "msx_sample": ([vp, vp, u64, u64, u64, vp, vp, vp, vp, vp], C.c_int),
+        "msx_stats": ([vp, vp, vp], C.c_int),
+        "msx_reset_stats": ([vp, vp], C.c_int),
+        "msx_vegas_accumulate": ([vp, i32, i64, vp, vp, vp], C.c_int),
+        "msx_vegas_update": ([vp, dbl, vp], C.c_int),
+        "msx_get_grid": ([vp, i32, vp], C.c_int),
+        "msx_set_grid": ([vp, i32, vp], C.c_int),
+        "msx_unweight_eff": ([vp, vp, i64, dbl, C.POINTER(dbl), C.POINTER(dbl), vp], C.c_int),
+    }
+    for name, (args, res) in sigs.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _ptr(t):
+    """Device (or host numpy) pointer of a tensor/array, None for None."""
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+class Context:
+    """One msx context: compiled channels, VEGAS grids and statistics on one GPU.
+
+    `desc` is a process description (dict or JSON string, see include/msx.h)."""
+
+    def __init__(self, desc, device: int = 0, precision: int = FP64):
+        import torch
+
+        self.torch = torch
+        self.L = load_library()
+        text = desc if isinstance(desc, str) else json.dumps(desc)
+        h = C.c_void_p()
+        st = self.L.msx_create_channels(text.encode(), precision, device, C.byref(h))
+        if st != 0:
+            raise MsxError(st, self.L.msx_last_error(None).decode())
+        self.h = h
+        self.device = torch.device("cuda", device)
+        self.n_channels = self._meta(META_N_CHANNELS, 0)
+        self.max_momenta = self._meta(META_MAX_MOMENTA, 0)
+        self.dims = [self._meta(META_DIMS, c) for c in range(self.n_channels)]
+        self.n_momenta = [self._meta(META_N_MOMENTA, c) for c in range(self.n_channels)]
+        self.hadronic = [bool(self._meta(META_HADRONIC, c)) for c in range(self.n_channels)]
+        self.nbins = [self._meta(META_VEGAS_BINS, c) for c in range(self.n_channels)]
+
+    # -- plumbing ------------------------------------------------------------
+    def _check(self, st):
+        if st != 0:
+            raise MsxError(st, self.L.msx_last_error(self.h).decode())
+
+    def _meta(self, key, index):
+        v = C.c_int64()
+        self._check(self.L.msx_get_meta(self.h, key, index, C.byref(v)))
+        return v.value
+
+    def _stream(self):
+        return self.torch.cuda.current_stream(self.device).cuda_stream
+
+    def _empty(self, *shape, dtype=None):
+        return self.torch.empty(shape, dtype=dtype or self.torch.float64, device=self.device)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.msx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- API -----------------------------------------------------------------
+    def uniform(self, seed: int, stream_id: int, e0: int, n: int, d: int):
+        y = self._empty(d, n)
+        self._check(self.L.msx_uniform(self.h, seed, stream_id, e0, n, d, _ptr(y), self._stream()))
+        return y
+
+    def _check_y(self, channel: int, y):
+        if not (0 <= channel < self.n_channels):
+            return
+        if y.dim() != 2 or y.shape[0] != self.dims[channel] or y.dtype != self.torch.float64 or y.device != self.device:
+            raise ValueError(f"y must be a float64 [{self.dims[channel]}][n] tensor on {self.device}")
+
+    def map(self, channel: int, y, weight: bool = False):
+        self._check_y(channel, y)
+        n = y.shape[1]
+        np_ = self.n_momenta[channel]
+        out = {"p": self._empty(4, np_, n), "jac": self._empty(n)}
+        out["x1x2"] = self._empty(2, n) if self.hadronic[channel] else None
+        out["w"] = self._empty(n) if weight else None
+        y = y.contiguous()
+        self._check(self.L.msx_map(self.h, channel, n, _ptr(y), _ptr(out["p"]), _ptr(out["x1x2"]),
+                                   _ptr(out["jac"]), _ptr(out["w"]), self._stream()))
+        return out
+
+    def weight(self, channel: int, p, x1x2, jac, alpha: bool = False):
+        n = jac.shape[0]
+        if 0 <= channel < self.n_channels and tuple(p.shape) != (4, self.n_momenta[channel], n):
+            raise ValueError(f"p must be [4][{self.n_momenta[channel]}][{n}]")
+        w = self._empty(n)
+        a = self._empty(n) if alpha else None
+        self._check(self.L.msx_weight(self.h, channel, n, _ptr(p), _ptr(x1x2), _ptr(jac), _ptr(w), _ptr(a),
+                                      self._stream()))
+        return (w, a) if alpha else w
+
+    def sample(self, counts, seed: int, stream_id: int = 0, counter_offset: int = 0, out: dict | None = None,
+               want_chan: bool = True):
+        counts = np.ascontiguousarray(counts, dtype=np.int64)
+        if counts.shape != (self.n_channels,):
+            raise ValueError(f"counts must have {self.n_channels} entries")
+        N = int(counts.sum())
+        if out is not None and (out["p"].shape[1] != self.max_momenta or out["p"].shape[2] < N or out["w"].shape[0] < N):
+            raise ValueError("output buffers are too small")
+        if out is None:
+            out = {"p": self._empty(4, self.max_momenta, N), "w": self._empty(N),
+                   "x1x2": self._empty(2, N) if any(self.hadronic) else None,
+                   "chan": self._empty(N, dtype=self.torch.int32) if want_chan else None}
+        self._check(self.L.msx_sample(self.h, counts.ctypes.data, seed, stream_id, counter_offset,
+                                      _ptr(out["p"]), _ptr(out["x1x2"]), _ptr(out["w"]), _ptr(out.get("chan")),
+                                      self._stream()))
+        return out
+
+    def stats(self) -> np.ndarray:
+        out = np.zeros((self.n_channels, 5))
+        self._check(self.L.msx_stats(self.h, out.ctypes.data, self._stream()))
+        return out
+
+    def reset_stats(self):
+        self._check(self.L.msx_reset_stats(self.h, self._stream()))
+
+    def vegas_accumulate(self, channel: int, y, w):
+        self._check_y(channel, y)
+        if w.dim() != 1 or w.shape[0] != y.shape[1] or w.dtype != self.torch.float64:
+            raise ValueError("w must be float64 [n] matching y")
+        self._check(self.L.msx_vegas_accumulate(self.h, channel, w.shape[0], _ptr(y.contiguous()),
+                                                _ptr(w.contiguous()), self._stream()))
+
+    def vegas_update(self, alpha: float = 0.5):
+        self._check(self.L.msx_vegas_update(self.h, alpha, self._stream()))
+
+    def get_grid(self, channel: int) -> np.ndarray:
+        out = np.zeros((self.dims[channel], self.nbins[channel] + 1))
+        self._check(self.L.msx_get_grid(self.h, channel, out.ctypes.data))
+        return out
+
+    def set_grid(self, channel: int, edges):
+        e = np.ascontiguousarray(edges, dtype=np.float64)
+        if e.shape != (self.dims[channel], self.nbins[channel] + 1):
+            raise ValueError("grid shape mismatch")
+        self._check(self.L.msx_set_grid(self.h, channel, e.ctypes.data))
+
+    def unweight_eff(self, w, overweight: float = 1e-3):
+        if w.dtype != self.torch.float64 or w.device != self.device:
+            raise ValueError("w must be a float64 tensor on the context's device")
+        eff, wmax = C.c_double(), C.c_double()
+        self._check(self.L.msx_unweight_eff(self.h, _ptr(w.contiguous()), w.shape[0], overweight, C.byref(eff),
+                                            C.byref(wmax), self._stream()))
+        return eff.value, wmax.value
+
+
+def adapt_vegas(ctx: Context, n_per_channel: int, iterations: int, alpha: float = 0.5, seed: int = 1,
+                stream_id: int = 1):
+    """VEGAS adaptation phase (grids optimised, then frozen): each iteration
+    samples n_per_channel events per channel with the fused path, regenerates
+    the same uniforms (same event ids) for the histograms of sum w^2 per bin,
+    and refines every grid.  Returns the statistics [C][5] of the last
+    iteration.  Leaves the context's statistics reset."""
+    import torch
+
+    C_ = ctx.n_channels
+    counts = np.full(C_, n_per_channel, dtype=np.int64)
+    out = None
+    last = None
+    for it in range(iterations):
+        off = it * C_ * n_per_channel
+        ctx.reset_stats()
+        out = ctx.sample(counts, seed=seed, stream_id=stream_id, counter_offset=off, out=out, want_chan=False)
+        for c in range(C_):
+            lo = c * n_per_channel
+            y = ctx.uniform(seed, stream_id, off + lo, n_per_channel, ctx.dims[c])
+            ctx.vegas_accumulate(c, y, out["w"][lo:lo + n_per_channel])
+        last = ctx.stats()
+        ctx.vegas_update(alpha)
+    torch.cuda.synchronize(ctx.device)
+    ctx.reset_stats()
+    return last
+
+
+def neyman_counts(stats: np.ndarray, total: int, floor_frac: float = 0.01) -> np.ndarray:
+    """Events per channel proportional to each channel's weight standard
+    deviation (minimum variance of sum_c <w>_c), with a floor of
+    floor_frac * total per channel."""
+    n = stats[:, 2]
+    mean = stats[:, 0] / np.maximum(n, 1)
+    var = np.maximum(stats[:, 1] / np.maximum(n, 1) - mean ** 2, 0.0)
+    sd = np.sqrt(var)
+    C = len(sd)
+    floor = int(floor_frac * total)
+    rest = total - floor * C
+    share = sd / sd.sum() if sd.sum() > 0 else np.full(C, 1.0 / C)
+    counts = floor + np.floor(share * rest).astype(np.int64)
+    counts[np.argmax(share)] += total - counts.sum()
+    return counts.astype(np.int64)

@@ -1,0 +1,469 @@
+// C ABI of the phase-space library (declared in include/msx.h).
+#include "../../include/msx.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "compiler.h"
+#include "json.h"
+#include "launch.h"
+#include "tables.h"
+
+using namespace msx;
+
+struct msx_ctx {
+    int device = 0;
+    int cu_count = 256;
+    Compiled comp;
+    std::string err;
+    // device tables
+    ChannelTab* d_chans = nullptr;
+    ProcessTab* d_procs = nullptr;
+    double* d_grids = nullptr;      // all channels' edges, [dims][nb+1] each
+    double* d_hist = nullptr;       // all channels' sum w^2 per bin, [dims][nb] each
+    double* d_stats = nullptr;      // [C][5]
+    int64_t* d_grid_off = nullptr;  // per channel offset into d_grids
+    int32_t* d_chan_nb = nullptr;   // per channel bins
+    int32_t* d_row_nb = nullptr;    // per (channel, dim) row: bins, grid offset, hist offset
+    int64_t* d_row_grid = nullptr;
+    int64_t* d_row_hist = nullptr;
+    std::vector<int64_t> grid_off, hist_off;
+    int64_t grid_total = 0, hist_total = 0;
+    int n_rows = 0;
+    int max_np = 0;
+    // scratch, grown on demand
+    double* d_tile = nullptr;
+    int64_t tile_cap = 0;
+    double* d_vpart = nullptr;
+    int64_t vpart_cap = 0;
+    double* d_unw = nullptr;  // 2 * 4096 buckets + 2 * 1024 partials + 2
+    size_t lds_max = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+msx_status fail(msx_ctx* ctx, msx_status st, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    else g_err = msg;
+    return st;
+}
+
+msx_status dev_fail(msx_ctx* ctx, hipError_t e, const char* what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(ctx, e == hipErrorOutOfMemory ? MSX_ERR_OOM : MSX_ERR_DEVICE, m);
+}
+
+#define MSX_HIP(ctx, call, what)                          \
+    do {                                                  \
+        hipError_t _e = (call);                           \
+        if (_e != hipSuccess) return dev_fail(ctx, _e, what); \
+    } while (0)
+
+template <class T>
+hipError_t dmalloc(T** p, size_t count) {
+    return hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
+}
+
+void free_all(msx_ctx* c) {
+    void* ptrs[] = {c->d_chans, c->d_procs, c->d_grids, c->d_hist, c->d_stats, c->d_grid_off, c->d_chan_nb,
+                    c->d_row_nb, c->d_row_grid, c->d_row_hist, c->d_tile, c->d_vpart, c->d_unw};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+bool bad_ctx(const msx_ctx* ctx) { return ctx == nullptr; }
+
+msx_status set_device(msx_ctx* ctx) {
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return dev_fail(ctx, e, "hipSetDevice");
+    return MSX_OK;
+}
+
+msx_status check_channel(msx_ctx* ctx, int32_t channel) {
+    if (channel < 0 || channel >= (int32_t)ctx->comp.chans.size())
+        return fail(ctx, MSX_ERR_ARG, "channel index out of range");
+    return MSX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* msx_last_error(const msx_ctx* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+msx_status msx_create_channels(const char* process_json, int32_t precision, int32_t device, msx_ctx** out) {
+    if (!out) return fail(nullptr, MSX_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!process_json) return fail(nullptr, MSX_ERR_ARG, "process_json is NULL");
+    if (precision != MSX_FP64) return fail(nullptr, MSX_ERR_UNSUPPORTED, "only MSX_FP64 is supported");
+    JValue root;
+    std::string err;
+    if (!parse_json(process_json, root, err)) return fail(nullptr, MSX_ERR_ARG, "JSON: " + err);
+    msx_ctx* c = new msx_ctx();
+    if (!compile_processes(root, c->comp, err)) {
+        delete c;
+        return fail(nullptr, MSX_ERR_ARG, "process description: " + err);
+    }
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || device < 0 || device >= ndev) {
+        delete c;
+        return fail(nullptr, MSX_ERR_DEVICE, "no such HIP device");
+    }
+    c->device = device;
+    if ((e = hipSetDevice(device)) != hipSuccess) {
+        delete c;
+        return fail(nullptr, MSX_ERR_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        c->cu_count = cus;
+    const int C = (int)c->comp.chans.size();
+    std::vector<double> grids, hist_init;
+    std::vector<int32_t> chan_nb(C), row_nb;
+    std::vector<int64_t> row_grid, row_hist;
+    for (int ch = 0; ch < C; ++ch) {
+        const ChannelMeta& m = c->comp.meta[ch];
+        c->grid_off.push_back((int64_t)grids.size());
+        c->hist_off.push_back(c->hist_total);
+        chan_nb[ch] = m.nbins;
+        for (int k = 0; k < m.dims; ++k) {
+            row_nb.push_back(m.nbins);
+            row_grid.push_back((int64_t)grids.size());
+            row_hist.push_back(c->hist_total + (int64_t)k * m.nbins);
+            for (int i = 0; i <= m.nbins; ++i) grids.push_back((double)i / m.nbins);
+        }
+        c->hist_total += (int64_t)m.dims * m.nbins;
+        c->max_np = std::max(c->max_np, m.n_momenta);
+        c->lds_max = std::max(c->lds_max, sizeof(double) * (size_t)m.dims * (m.nbins + 1));
+    }
+    c->grid_total = (int64_t)grids.size();
+    c->n_rows = (int)row_nb.size();
+    auto up = [&](void* dst, const void* src, size_t bytes) { return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice); };
+    if ((e = dmalloc(&c->d_chans, C)) != hipSuccess || (e = dmalloc(&c->d_procs, c->comp.procs.size())) != hipSuccess ||
+        (e = dmalloc(&c->d_grids, grids.size())) != hipSuccess || (e = dmalloc(&c->d_hist, c->hist_total)) != hipSuccess ||
+        (e = dmalloc(&c->d_stats, 5 * C)) != hipSuccess || (e = dmalloc(&c->d_grid_off, C)) != hipSuccess ||
+        (e = dmalloc(&c->d_chan_nb, C)) != hipSuccess || (e = dmalloc(&c->d_row_nb, row_nb.size())) != hipSuccess ||
+        (e = dmalloc(&c->d_row_grid, row_grid.size())) != hipSuccess ||
+        (e = dmalloc(&c->d_row_hist, row_hist.size())) != hipSuccess ||
+        (e = dmalloc(&c->d_unw, 2 * 4096 + 2 * 1024 + 2)) != hipSuccess ||
+        (e = up(c->d_chans, c->comp.chans.data(), sizeof(ChannelTab) * C)) != hipSuccess ||
+        (e = up(c->d_procs, c->comp.procs.data(), sizeof(ProcessTab) * c->comp.procs.size())) != hipSuccess ||
+        (e = up(c->d_grids, grids.data(), sizeof(double) * grids.size())) != hipSuccess ||
+        (e = up(c->d_grid_off, c->grid_off.data(), sizeof(int64_t) * C)) != hipSuccess ||
+        (e = up(c->d_chan_nb, chan_nb.data(), sizeof(int32_t) * C)) != hipSuccess ||
+        (e = up(c->d_row_nb, row_nb.data(), sizeof(int32_t) * row_nb.size())) != hipSuccess ||
+        (e = up(c->d_row_grid, row_grid.data(), sizeof(int64_t) * row_grid.size())) != hipSuccess ||
+        (e = up(c->d_row_hist, row_hist.data(), sizeof(int64_t) * row_hist.size())) != hipSuccess ||
+        (e = hipMemset(c->d_hist, 0, sizeof(double) * std::max<int64_t>(c->hist_total, 1))) != hipSuccess ||
+        (e = hipMemset(c->d_stats, 0, sizeof(double) * 5 * C)) != hipSuccess) {
+        std::string m = std::string("device setup: ") + hipGetErrorString(e);
+        msx_status st = e == hipErrorOutOfMemory ? MSX_ERR_OOM : MSX_ERR_DEVICE;
+        free_all(c);
+        delete c;
+        return fail(nullptr, st, m);
+    }
+    *out = c;
+    return MSX_OK;
+}
+
+msx_status msx_destroy(msx_ctx* ctx) {
+    if (!ctx) return MSX_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    free_all(ctx);
+    delete ctx;
+    return MSX_OK;
+}
+
+msx_status msx_get_meta(const msx_ctx* ctx, int32_t key, int32_t index, int64_t* value) {
+    msx_ctx* c = const_cast<msx_ctx*>(ctx);
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (!value) return fail(c, MSX_ERR_ARG, "value is NULL");
+    const int C = (int)ctx->comp.chans.size();
+    auto chan = [&](int64_t v) -> msx_status {
+        if (index < 0 || index >= C) return fail(c, MSX_ERR_ARG, "channel index out of range");
+        *value = v;
+        return MSX_OK;
+    };
+    switch (key) {
+        case MSX_META_N_CHANNELS: *value = C; return MSX_OK;
+        case MSX_META_MAX_MOMENTA: *value = ctx->max_np; return MSX_OK;
+        case MSX_META_DEVICE: *value = ctx->device; return MSX_OK;
+        case MSX_META_DIMS: return chan(index >= 0 && index < C ? ctx->comp.meta[index].dims : 0);
+        case MSX_META_N_MOMENTA: return chan(index >= 0 && index < C ? ctx->comp.meta[index].n_momenta : 0);
+        case MSX_META_HADRONIC: return chan(index >= 0 && index < C ? ctx->comp.meta[index].hadronic : 0);
+        case MSX_META_VEGAS_BINS: return chan(index >= 0 && index < C ? ctx->comp.meta[index].nbins : 0);
+        case MSX_META_PROCESS: return chan(index >= 0 && index < C ? ctx->comp.meta[index].process : 0);
+        default: return fail(c, MSX_ERR_ARG, "unknown metadata key");
+    }
+}
+
+msx_status msx_uniform(msx_ctx* ctx, uint64_t seed, uint64_t stream_id, uint64_t e0, int64_t n, int32_t d, double* y,
+                       void* stream) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (n < 0 || d < 1 || d > 64) return fail(ctx, MSX_ERR_ARG, "need n >= 0 and 1 <= d <= 64");
+    if (n > 0 && !y) return fail(ctx, MSX_ERR_ARG, "y is NULL");
+    if (n > 0 && e0 > UINT64_MAX - (uint64_t)n) return fail(ctx, MSX_ERR_ARG, "event ids overflow the counter");
+    if (msx_status st = set_device(ctx)) return st;
+    MSX_HIP(ctx, launch_uniform(seed, stream_id, e0, n, d, y, (hipStream_t)stream), "uniform launch");
+    return MSX_OK;
+}
+
+msx_status msx_map(msx_ctx* ctx, int32_t channel, int64_t n, const double* y, double* p, double* x1x2, double* jac,
+                   double* w, void* stream) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (msx_status st = check_channel(ctx, channel)) return st;
+    if (n < 0) return fail(ctx, MSX_ERR_ARG, "n < 0");
+    const ChannelMeta& m = ctx->comp.meta[channel];
+    if (n > 0 && (!y || !p || !jac)) return fail(ctx, MSX_ERR_ARG, "y, p and jac are required");
+    if (m.hadronic && n > 0 && !x1x2) return fail(ctx, MSX_ERR_ARG, "x1x2 is required for hadronic beams");
+    if (!m.hadronic && x1x2) return fail(ctx, MSX_ERR_ARG, "x1x2 must be NULL for fixed beams");
+    if (n == 0) return MSX_OK;
+    if (msx_status st = set_device(ctx)) return st;
+    const ChannelTab& t = ctx->comp.chans[channel];
+    const ProcessTab& pt = ctx->comp.procs[m.process];
+    MSX_HIP(ctx,
+            launch_map(ctx->d_chans + channel, ctx->d_procs + m.process, ctx->d_grids + ctx->grid_off[channel], m.nbins,
+                       m.dims, t.n_slots, pt.s_lab, m.n_momenta, n, y, p, x1x2, jac, w, ctx->cu_count,
+                       (hipStream_t)stream),
+            "map launch");
+    return MSX_OK;
+}
+
+msx_status msx_weight(msx_ctx* ctx, int32_t channel, int64_t n, const double* p, const double* x1x2,
+                      const double* jac, double* w, double* alpha, void* stream) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (msx_status st = check_channel(ctx, channel)) return st;
+    if (n < 0) return fail(ctx, MSX_ERR_ARG, "n < 0");
+    const ChannelMeta& m = ctx->comp.meta[channel];
+    if (n > 0 && (!p || !jac || !w)) return fail(ctx, MSX_ERR_ARG, "p, jac and w are required");
+    if (m.hadronic && n > 0 && !x1x2) return fail(ctx, MSX_ERR_ARG, "x1x2 is required for hadronic beams");
+    if (n == 0) return MSX_OK;
+    if (msx_status st = set_device(ctx)) return st;
+    MSX_HIP(ctx,
+            launch_weight(ctx->d_chans + channel, ctx->d_procs + m.process, m.n_momenta, n, p, x1x2, jac, w, alpha,
+                          (hipStream_t)stream),
+            "weight launch");
+    return MSX_OK;
+}
+
+msx_status msx_sample(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id, uint64_t counter_offset,
+                      double* p, double* x1x2, double* w, int32_t* chan, void* stream) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (!counts) return fail(ctx, MSX_ERR_ARG, "counts is NULL");
+    const int C = (int)ctx->comp.chans.size();
+    SampleCall call;
+    std::memset(&call, 0, sizeof call);
+    call.n_chan = C;
+    const int T = sample_tile_size();
+    int64_t N = 0, tiles = 0;
+    bool any_hadronic = false;
+    int max_slots = 0;
+    for (int c = 0; c < C; ++c) {
+        if (counts[c] < 0) return fail(ctx, MSX_ERR_ARG, "negative event count");
+        call.ev_start[c] = N;
+        call.tile_start[c] = tiles;
+        if (counts[c] > INT64_MAX / 4 - N) return fail(ctx, MSX_ERR_ARG, "event count overflow");
+        N += counts[c];
+        tiles += (counts[c] + T - 1) / T;
+        if (counts[c] > 0) {
+            any_hadronic = any_hadronic || ctx->comp.meta[c].hadronic;
+            max_slots = std::max(max_slots, ctx->comp.chans[c].n_slots);
+        }
+    }
+    call.ev_start[C] = N;
+    call.tile_start[C] = tiles;
+    call.n_tiles = tiles;
+    if (N == 0) return MSX_OK;
+    if (counter_offset > UINT64_MAX - (uint64_t)N) return fail(ctx, MSX_ERR_ARG, "event ids overflow the counter");
+    if (!p || !w) return fail(ctx, MSX_ERR_ARG, "p and w are required");
+    if (any_hadronic && !x1x2) return fail(ctx, MSX_ERR_ARG, "x1x2 is required when a sampled channel is hadronic");
+    if (msx_status st = set_device(ctx)) return st;
+    if (tiles > ctx->tile_cap) {
+        if (ctx->d_tile) MSX_HIP(ctx, hipFree(ctx->d_tile), "hipFree");
+        ctx->d_tile = nullptr;
+        ctx->tile_cap = 0;
+        MSX_HIP(ctx, dmalloc(&ctx->d_tile, 4 * tiles), "tile scratch");
+        ctx->tile_cap = tiles;
+    }
+    int grid = ctx->cu_count * 8;
+    MSX_HIP(ctx,
+            launch_sample(ctx->d_chans, ctx->d_procs, ctx->d_grids, ctx->d_grid_off, ctx->d_chan_nb, call, max_slots,
+                          ctx->lds_max, seed, stream_id, counter_offset, ctx->max_np, N, p, x1x2, w, chan, ctx->d_tile,
+                          ctx->d_stats, grid, (hipStream_t)stream),
+            "sample launch");
+    return MSX_OK;
+}
+
+msx_status msx_stats(msx_ctx* ctx, double* out, void* stream) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (!out) return fail(ctx, MSX_ERR_ARG, "out is NULL");
+    if (msx_status st = set_device(ctx)) return st;
+    const int C = (int)ctx->comp.chans.size();
+    MSX_HIP(ctx, hipMemcpyAsync(out, ctx->d_stats, sizeof(double) * 5 * C, hipMemcpyDeviceToHost, (hipStream_t)stream),
+            "stats copy");
+    MSX_HIP(ctx, hipStreamSynchronize((hipStream_t)stream), "stats sync");
+    return MSX_OK;
+}
+
+msx_status msx_reset_stats(msx_ctx* ctx, void* stream) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (msx_status st = set_device(ctx)) return st;
+    const int C = (int)ctx->comp.chans.size();
+    MSX_HIP(ctx, hipMemsetAsync(ctx->d_stats, 0, sizeof(double) * 5 * C, (hipStream_t)stream), "stats reset");
+    return MSX_OK;
+}
+
+msx_status msx_vegas_accumulate(msx_ctx* ctx, int32_t channel, int64_t n, const double* y, const double* w,
+                                void* stream) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (msx_status st = check_channel(ctx, channel)) return st;
+    if (n < 0) return fail(ctx, MSX_ERR_ARG, "n < 0");
+    if (n == 0) return MSX_OK;
+    if (!y || !w) return fail(ctx, MSX_ERR_ARG, "y and w are required");
+    if (msx_status st = set_device(ctx)) return st;
+    const ChannelMeta& m = ctx->comp.meta[channel];
+    const int64_t chunk_min = 4096;
+    int64_t nchunk = std::min<int64_t>(1024, (n + chunk_min - 1) / chunk_min);
+    int64_t chunk = (n + nchunk - 1) / nchunk;
+    int64_t need = nchunk * m.dims * m.nbins;
+    if (need > ctx->vpart_cap) {
+        if (ctx->d_vpart) MSX_HIP(ctx, hipFree(ctx->d_vpart), "hipFree");
+        ctx->d_vpart = nullptr;
+        ctx->vpart_cap = 0;
+        MSX_HIP(ctx, dmalloc(&ctx->d_vpart, need), "histogram scratch");
+        ctx->vpart_cap = need;
+    }
+    MSX_HIP(ctx,
+            launch_vegas_accumulate(n, m.dims, m.nbins, y, w, ctx->d_vpart, nchunk, chunk,
+                                    ctx->d_hist + ctx->hist_off[channel], (hipStream_t)stream),
+            "histogram launch");
+    return MSX_OK;
+}
+
+msx_status msx_vegas_update(msx_ctx* ctx, double alpha, void* stream) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(ctx, MSX_ERR_ARG, "alpha must be finite and > 0");
+    if (msx_status st = set_device(ctx)) return st;
+    MSX_HIP(ctx,
+            launch_vegas_refine(ctx->n_rows, ctx->d_row_nb, ctx->d_row_grid, ctx->d_row_hist, alpha, ctx->d_grids,
+                                ctx->d_hist, (hipStream_t)stream),
+            "refine launch");
+    return MSX_OK;
+}
+
+msx_status msx_get_grid(msx_ctx* ctx, int32_t channel, double* edges) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (msx_status st = check_channel(ctx, channel)) return st;
+    if (!edges) return fail(ctx, MSX_ERR_ARG, "edges is NULL");
+    if (msx_status st = set_device(ctx)) return st;
+    const ChannelMeta& m = ctx->comp.meta[channel];
+    MSX_HIP(ctx, hipDeviceSynchronize(), "sync");
+    MSX_HIP(ctx,
+            hipMemcpy(edges, ctx->d_grids + ctx->grid_off[channel], sizeof(double) * m.dims * (m.nbins + 1),
+                      hipMemcpyDeviceToHost),
+            "grid copy");
+    return MSX_OK;
+}
+
+msx_status msx_set_grid(msx_ctx* ctx, int32_t channel, const double* edges) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (msx_status st = check_channel(ctx, channel)) return st;
+    if (!edges) return fail(ctx, MSX_ERR_ARG, "edges is NULL");
+    const ChannelMeta& m = ctx->comp.meta[channel];
+    for (int k = 0; k < m.dims; ++k) {
+        const double* e = edges + (size_t)k * (m.nbins + 1);
+        if (e[0] != 0.0 || e[m.nbins] != 1.0) return fail(ctx, MSX_ERR_ARG, "grid edges must run from 0 to 1");
+        for (int i = 0; i < m.nbins; ++i)
+            if (!(e[i + 1] > e[i])) return fail(ctx, MSX_ERR_ARG, "grid edges must increase strictly");
+    }
+    if (msx_status st = set_device(ctx)) return st;
+    MSX_HIP(ctx, hipDeviceSynchronize(), "sync");
+    MSX_HIP(ctx,
+            hipMemcpy(ctx->d_grids + ctx->grid_off[channel], edges, sizeof(double) * m.dims * (m.nbins + 1),
+                      hipMemcpyHostToDevice),
+            "grid copy");
+    return MSX_OK;
+}
+
+msx_status msx_unweight_eff(msx_ctx* ctx, const double* w, int64_t n, double overweight, double* eff, double* w_max,
+                            void* stream) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (n <= 0 || !w) return fail(ctx, MSX_ERR_ARG, "need n > 0 weights");
+    if (!eff || !w_max) return fail(ctx, MSX_ERR_ARG, "eff and w_max are required");
+    if (!(overweight > 0.0 && overweight < 1.0)) return fail(ctx, MSX_ERR_ARG, "overweight must be in (0, 1)");
+    if (msx_status st = set_device(ctx)) return st;
+    hipStream_t s = (hipStream_t)stream;
+    double* counts = ctx->d_unw;
+    double* sums = ctx->d_unw + 4096;
+    double* part = ctx->d_unw + 2 * 4096;
+    double* tot = part + 2 * 1024;
+    const int nblk = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    MSX_HIP(ctx, launch_sum_max(n, w, tot, part, nblk, s), "sum launch");
+    double hs[2];
+    MSX_HIP(ctx, hipMemcpyAsync(hs, tot, sizeof hs, hipMemcpyDeviceToHost, s), "copy");
+    MSX_HIP(ctx, hipStreamSynchronize(s), "sync");
+    const double total = hs[0];
+    if (!(total > 0.0) || !std::isfinite(total)) return fail(ctx, MSX_ERR_ARG, "weights must be finite with a positive sum");
+    const double target = overweight * total;
+    // Refine over the 63 value bits of non-negative doubles: buckets of 12
+    // bits (the last pass 3); S_up/N_up collect weights in buckets above the
+    // crossing bucket of earlier passes.
+    const int shifts[6] = {51, 39, 27, 15, 3, 0};
+    const int widths[6] = {12, 12, 12, 12, 12, 3};
+    double S_up = 0.0, N_up = 0.0;
+    uint64_t prefix = 0;
+    std::vector<double> hc(4096), hsum(4096);
+    for (int pass = 0; pass < 6; ++pass) {
+        const int nbk = 1 << widths[pass];
+        MSX_HIP(ctx, hipMemsetAsync(counts, 0, sizeof(double) * 2 * 4096, s), "memset");
+        MSX_HIP(ctx, launch_unw_pass(n, w, shifts[pass], widths[pass], prefix, pass == 0, counts, sums, ctx->cu_count, s),
+                "histogram launch");
+        MSX_HIP(ctx, hipMemcpyAsync(hc.data(), counts, sizeof(double) * nbk, hipMemcpyDeviceToHost, s), "copy");
+        MSX_HIP(ctx, hipMemcpyAsync(hsum.data(), sums, sizeof(double) * nbk, hipMemcpyDeviceToHost, s), "copy");
+        MSX_HIP(ctx, hipStreamSynchronize(s), "sync");
+        // excess at the lower edge L_b of bucket b: every weight in buckets >= b
+        // lies at or above L_b
+        double S = S_up, N = N_up;
+        int found = -1;
+        double S_above_b = S_up, N_above_b = N_up;
+        for (int b = nbk - 1; b >= 0; --b) {
+            S_above_b = S;
+            N_above_b = N;
+            S += hsum[b];
+            N += hc[b];
+            uint64_t lb_bits = (((prefix << widths[pass]) | (uint64_t)b) << shifts[pass]);
+            double lb;
+            std::memcpy(&lb, &lb_bits, sizeof lb);
+            if (S - lb * N >= target) {
+                found = b;
+                break;
+            }
+        }
+        if (found < 0) {  // only possible for the zero bucket: W lies below every positive weight
+            found = 0;
+        }
+        S_up = S_above_b;
+        N_up = N_above_b;
+        prefix = (prefix << widths[pass]) | (uint64_t)found;
+    }
+    // the crossing bucket is now the single value v; for W in [v, next) the
+    // weights above W are exactly those counted in S_up / N_up
+    double v;
+    std::memcpy(&v, &prefix, sizeof v);
+    double W = N_up > 0.0 ? (S_up - target) / N_up : v;
+    if (W < v) W = v;
+    *w_max = W;
+    *eff = W > 0.0 ? (total / (double)n) / W : 0.0;
+    return MSX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,453 @@
+// Per-event phase-space chain on gfx950: one thread per event, every lane of
+// a wave in the same channel.  Channel tables are read with scalar loads;
+// the per-event momentum slots and invariants live in small private arrays
+// indexed only by wave-uniform values, which the compiler keeps in VGPRs
+// (indexed with s_set_gpr_idx) instead of scratch.
+//
+// Steps follow section 2.2 of arXiv:2602.06895: s-hat (eqs. prop_stable_nu /
+// prop_massive), time-like invariants with s-/t-channel bounds, the PDF
+// convolution (eq. pdf_sampling), the chain of (phi, t) 2->2 blocks (eqs.
+// t_invariant_theta, 2_to_2_mapping, ps2_phi_t), (phi, theta) decays (eq.
+// ps2_phi_theta), the beam boost, the Jacobian product and the unphysical
+// cut; then the integrand and the local channel weight (eq.
+// multi-channel-mg).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tables.h"
+
+namespace msx {
+
+constexpr double kPiD = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter-based generator.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x64_10(uint64_t& c0, uint64_t& c1, uint64_t& c2, uint64_t& c3,
+                                              uint64_t k0, uint64_t k1) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+}
+
+// 53 random bits -> (0, 1), never 0 or 1.
+__device__ __forceinline__ double to_unit(uint64_t w) {
+    return ((double)(w >> 11) + 0.5) * 0x1.0p-53;
+}
+
+// ---------------------------------------------------------------------------
+// Small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double kallen(double x, double y, double z) {
+    double d = x - y - z;
+    return d * d - 4.0 * y * z;
+}
+
+__device__ __forceinline__ double ipow(double b, int n) {
+    double b2 = b * b;
+    switch (n) {
+        case 2: return b2;
+        case 3: return b2 * b;
+        case 4: return b2 * b2;
+        case 5: return b2 * b2 * b;
+        case 6: return b2 * b2 * b2;
+        case 7: return b2 * b2 * b2 * b;
+        default: return (b2 * b2) * (b2 * b2);
+    }
+}
+
+// Power-law core: b = r A + (1 - r) B, x - m^2 = b^(1/e), and
+// J = (A - B) (x - m^2)^nu / e with (x - m^2)^nu = (x - m^2) / b.
+__device__ __forceinline__ double pow_core(const MapParams& p, double A, double B, double r, double& jac) {
+    double b = r * A + (1.0 - r) * B;
+    double xm = p.int_pow ? ipow(b, p.int_pow) : pow(b, p.inv_e);
+    jac = (A - B) * (xm / b) * p.inv_e;
+    return xm + p.m2;
+}
+
+// G_nu / G_BW with bounds known only per event.
+__device__ __forceinline__ double map_dyn(const MapParams& p, double r, double xmin, double xmax, double& jac) {
+    const int kind = p.kind;
+    if (kind == MAP_POW) {
+        double A = pow(xmax - p.m2, p.e), B = pow(xmin - p.m2, p.e);
+        return pow_core(p, A, B, r, jac);
+    }
+    if (kind == MAP_BW) {
+        double u1 = atan((xmin - p.m2) / p.mw), u2 = atan((xmax - p.m2) / p.mw);
+        double d = p.mw * tan(u1 + (u2 - u1) * r);
+        jac = (u2 - u1) * (d * d + p.mw * p.mw) / p.mw;
+        return d + p.m2;
+    }
+    if (kind == MAP_LOG) {
+        double lmax = log(xmax - p.m2), lmin = log(xmin - p.m2);
+        double xm = exp(r * lmax + (1.0 - r) * lmin);
+        jac = xm * (lmax - lmin);
+        return xm + p.m2;
+    }
+    jac = xmax - xmin;
+    return xmin + (xmax - xmin) * r;
+}
+
+// G_nu / G_BW with precomputed static constants (s-hat).
+__device__ __forceinline__ double map_static(const InvSpec& iv, double r, double& jac) {
+    const MapParams& p = iv.map;
+    const int kind = p.kind;
+    if (kind == MAP_POW) return pow_core(p, iv.A, iv.B, r, jac);
+    if (kind == MAP_BW) {
+        double u2 = iv.A, u1 = iv.B;
+        double d = p.mw * tan(u1 + (u2 - u1) * r);
+        jac = (u2 - u1) * (d * d + p.mw * p.mw) / p.mw;
+        return d + p.m2;
+    }
+    if (kind == MAP_LOG) {
+        double lmax = iv.A, lmin = iv.B;
+        double xm = exp(r * lmax + (1.0 - r) * lmin);
+        jac = xm * (lmax - lmin);
+        return xm + p.m2;
+    }
+    jac = iv.xmax - iv.xmin;
+    return iv.xmin + (iv.xmax - iv.xmin) * r;
+}
+
+// Pure boost of k from the rest frame of P (mass m) into the frame of P.
+__device__ __forceinline__ void boost_by(double Pe, double Px, double Py, double Pz, double m, double& ke,
+                                         double& kx, double& ky, double& kz) {
+    double pk = Px * kx + Py * ky + Pz * kz;
+    double inv_m = 1.0 / m;
+    double e = (Pe * ke + pk) * inv_m;
+    double c = (pk / (Pe + m) + ke) * inv_m;
+    ke = e;
+    kx += c * Px;
+    ky += c * Py;
+    kz += c * Pz;
+}
+
+// ---------------------------------------------------------------------------
+// Per-event state.  NS: momentum slots; the uniforms are held in two
+// 16-entry arrays (dims <= 32).  All arrays are indexed by uniform values.
+// ---------------------------------------------------------------------------
+struct ChainOut {
+    double shat, x1, x2, logtau, jac;
+    bool ok;
+};
+
+template <int NS>
+struct Slots {
+    double E[NS], X[NS], Y[NS], Z[NS];
+};
+
+#define MSX_U(k) ((k) < 16 ? U0[(k)] : U1[(k)-16])
+
+template <int NS>
+__device__ __forceinline__ void set_slot(double (&E)[NS], double (&X)[NS], double (&Y)[NS], double (&Z)[NS],
+                                         int s, double e, double x, double y, double z) {
+    if (s >= 0) {
+        E[s] = e;
+        X[s] = x;
+        Y[s] = y;
+        Z[s] = z;
+    }
+}
+
+__device__ __forceinline__ double src_mass(const MassSrc& ms, const double (&SQ)[kMaxInv]) {
+    return ms.inv >= 0 ? SQ[ms.inv] : ms.m;
+}
+
+__device__ __forceinline__ double masked_sum(uint32_t mask, const double (&SQ)[kMaxInv]) {
+    double s = 0.0;
+    while (mask) {
+        int b = __builtin_ctz(mask);
+        s += SQ[b];
+        mask &= mask - 1;
+    }
+    return s;
+}
+
+// The mapping chain.  U0/U1: VEGAS-mapped random numbers in dimension order.
+// Leaves the final-state momenta in the partonic frame in the slots.
+template <int NS>
+__device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, double s_lab,
+                                          const double (&U0)[16], const double (&U1)[16], double (&E)[NS],
+                                          double (&X)[NS], double (&Y)[NS], double (&Z)[NS],
+                                          double (&S)[kMaxInv], double (&SQ)[kMaxInv], ChainOut& o) {
+    int k = 0;
+    double jac = ct->jac_const;
+    const int hadronic = ct->hadronic;
+
+    // (1) s-hat
+    double shat;
+    if (hadronic) {
+        double j;
+        shat = map_static(ct->inv[0], MSX_U(k), j);
+        ++k;
+        jac *= j;
+    } else {
+        shat = s_lab;
+    }
+    S[0] = shat;
+    SQ[0] = sqrt(shat);
+
+    // (2) time-like invariants: bounds as linear forms in sqrt(s_j)
+    const int n_inv = ct->n_inv;
+    for (int i = 1; i < n_inv; ++i) {
+        const InvSpec& iv = ct->inv[i];
+        double mmin = iv.min_const + masked_sum(iv.min_mask, SQ);
+        double mmax = SQ[iv.parent] - iv.max_const - masked_sum(iv.max_mask, SQ);
+        double j;
+        double s = map_dyn(iv.map, MSX_U(k), mmin * mmin, mmax * mmax, j);
+        ++k;
+        jac *= j;
+        S[i] = s;
+        SQ[i] = sqrt(s);
+    }
+
+    // (3) momentum fractions x1 = tau^r, x2 = tau^(1-r), J = -log(tau)/s_lab
+    double x1 = 1.0, x2 = 1.0, L = 0.0;
+    if (hadronic) {
+        double r = MSX_U(k);
+        ++k;
+        L = log(shat / s_lab);
+        x1 = exp(r * L);
+        x2 = exp((1.0 - r) * L);
+        jac *= -L / s_lab;
+    }
+
+    // (4) 2->2 blocks along the t-channel spine.  The block invariants are
+    // the sampled ones: (p_A + p_B)^2 = s of the remaining cluster, p_A^2 and
+    // p_B^2 = 0 or the t of the block that last updated the leg.
+    const double h = 0.5 * SQ[0];
+    double Ae = h, Ax = 0.0, Ay = 0.0, Az = h;   // p_A
+    double Be = h, Bx = 0.0, By = 0.0, Bz = -h;  // p_B
+    double ma2 = 0.0, mb2 = 0.0;
+    const int n_blocks = ct->n_blocks;
+    for (int bi = 0; bi < n_blocks; ++bi) {
+        const BlockSpec& bs = ct->blk[bi];
+        double m1 = src_mass(bs.m1, SQ), m2 = src_mass(bs.m2, SQ);
+        double r_phi = MSX_U(k), r_t = MSX_U(k + 1);
+        k += 2;
+        double Pe = Ae + Be, Px = Ax + Bx, Py = Ay + By, Pz = Az + Bz;
+        double m0sq = S[bs.m0_inv];
+        double m0 = SQ[bs.m0_inv];
+        double m1s = m1 * m1, m2s = m2 * m2;
+        double lam12 = kallen(m0sq, m1s, m2s), lamab = kallen(m0sq, ma2, mb2);
+        double C = (m0sq + (m1s - m2s)) * (m0sq + (ma2 - mb2));
+        double R = sqrt(lam12 * lamab);
+        double inv2 = 1.0 / (2.0 * m0sq);
+        // t at cos(theta) = -1 directly; the root at +1 from the product of
+        // roots t+ t- = (m1^2-ma^2)(m2^2-mb^2) + (ma^2-mb^2-m1^2+m2^2)(ma^2 m2^2-m1^2 mb^2)/m0^2
+        double t_minus = m1s + ma2 - (C + R) * inv2;
+        double prod = (m1s - ma2) * (m2s - mb2) + (ma2 - mb2 - m1s + m2s) * (ma2 * m2s - m1s * mb2) / m0sq;
+        double t_plus = (t_minus != 0.0) ? prod / t_minus : 0.0;
+        double tmin = fmax(0.0, -t_plus);
+        double tmax = -t_minus;
+        double jt;
+        double abst = map_dyn(bs.tmap, r_t, tmin, tmax, jt);
+        double cth = (C - 2.0 * m0sq * (m1s + ma2 + abst)) / R;
+        cth = fmin(1.0, fmax(-1.0, cth));
+        double sth = sqrt((1.0 - cth) * (1.0 + cth));
+        double sphi, cphi;
+        sincospi(2.0 * r_phi, &sphi, &cphi);
+        double inv_2m0 = 1.0 / (2.0 * m0);
+        double q = sqrt(lam12) * inv_2m0;
+        double e1 = (m0sq + (m1s - m2s)) * inv_2m0;
+        double e2 = (m0sq - (m1s - m2s)) * inv_2m0;
+        double vx = q * sth * cphi, vy = q * sth * sphi, vz = q * cth;
+        double k1e = e1, k1x, k1y, k1z, k2e = e2, k2x, k2y, k2z;
+        if (bs.com) {
+            // P at rest, p_A along +z: no rotation, no boost
+            k1x = vx;
+            k1y = vy;
+            k1z = vz;
+        } else {
+            // direction of p_A in the rest frame of P, then R(phi_A, theta_A)
+            double ae = Ae, ax = Ax, ay = Ay, az = Az;
+            boost_by(Pe, -Px, -Py, -Pz, m0, ae, ax, ay, az);
+            double inv_len = 1.0 / sqrt(ax * ax + ay * ay + az * az);
+            double nx = ax * inv_len, ny = ay * inv_len, nz = az * inv_len;
+            double st = sqrt(nx * nx + ny * ny);
+            double cp = 1.0, sp = 0.0;
+            if (st > 0.0) {
+                cp = nx / st;
+                sp = ny / st;
+            }
+            double rx = vx * nz + vz * st;
+            double ry = vy;
+            double rz = -vx * st + vz * nz;
+            k1x = rx * cp - ry * sp;
+            k1y = rx * sp + ry * cp;
+            k1z = rz;
+        }
+        k2x = -k1x;
+        k2y = -k1y;
+        k2z = -k1z;
+        if (!bs.com) {
+            boost_by(Pe, Px, Py, Pz, m0, k1e, k1x, k1y, k1z);
+            boost_by(Pe, Px, Py, Pz, m0, k2e, k2x, k2y, k2z);
+        }
+        jac *= jt * (2.0 * kPiD) / (4.0 * sqrt(lamab));
+        const int side = bs.side;
+        if (side == 0) {
+            set_slot(E, X, Y, Z, bs.slot1, k1e, k1x, k1y, k1z);
+            Ae -= k1e;
+            Ax -= k1x;
+            Ay -= k1y;
+            Az -= k1z;
+            ma2 = -abst;
+        } else if (side == 1) {
+            set_slot(E, X, Y, Z, bs.slot2, k2e, k2x, k2y, k2z);
+            Be -= k2e;
+            Bx -= k2x;
+            By -= k2y;
+            Bz -= k2z;
+            mb2 = -abst;
+        } else {
+            set_slot(E, X, Y, Z, bs.slot1, k1e, k1x, k1y, k1z);
+            set_slot(E, X, Y, Z, bs.slot2, k2e, k2x, k2y, k2z);
+        }
+    }
+
+    // (5) (phi, theta) decays, parents before children
+    const int n_dec = ct->n_decays;
+    for (int di = 0; di < n_dec; ++di) {
+        const DecaySpec& ds = ct->dec[di];
+        double m0sq = S[ds.parent_inv];
+        double m0 = SQ[ds.parent_inv];
+        double m1 = src_mass(ds.m1, SQ), m2 = src_mass(ds.m2, SQ);
+        double r_phi = MSX_U(k), r_th = MSX_U(k + 1);
+        k += 2;
+        double m1s = m1 * m1, m2s = m2 * m2;
+        double lam = kallen(m0sq, m1s, m2s);
+        double inv_2m0 = 1.0 / (2.0 * m0);
+        double e1 = (m0sq + (m1s - m2s)) * inv_2m0;
+        double e2 = (m0sq - (m1s - m2s)) * inv_2m0;
+        double sl = sqrt(lam);
+        double q = sl * inv_2m0;
+        double cth = 2.0 * r_th - 1.0;
+        double sth = sqrt((1.0 - cth) * (1.0 + cth));
+        double sphi, cphi;
+        sincospi(2.0 * r_phi, &sphi, &cphi);
+        double k1e = e1, k1x = q * sth * cphi, k1y = q * sth * sphi, k1z = q * cth;
+        double k2e = e2, k2x = -k1x, k2y = -k1y, k2z = -k1z;
+        const int ps = ds.parent_slot;
+        if (ps >= 0) {
+            double Pe = E[ps], Px = X[ps], Py = Y[ps], Pz = Z[ps];
+            boost_by(Pe, Px, Py, Pz, m0, k1e, k1x, k1y, k1z);
+            boost_by(Pe, Px, Py, Pz, m0, k2e, k2x, k2y, k2z);
+        }
+        set_slot(E, X, Y, Z, ds.slot1, k1e, k1x, k1y, k1z);
+        set_slot(E, X, Y, Z, ds.slot2, k2e, k2x, k2y, k2z);
+        jac *= sl / (8.0 * m0sq) * (4.0 * kPiD);
+    }
+
+    o.shat = shat;
+    o.x1 = x1;
+    o.x2 = x2;
+    o.logtau = L;
+    o.jac = jac;
+}
+
+// ---------------------------------------------------------------------------
+// Integrand and local channel weight, from momenta supplied by an accessor
+// get(k, c) for final-state particle k (0-based) and component c, plus p_a.
+// ---------------------------------------------------------------------------
+template <class Get>
+__device__ __forceinline__ double inv_q2(const ProcessTab* __restrict__ pt, int u, double pae, double pax, double pay,
+                                         double paz, Get get) {
+    double qe = 0.0, qx = 0.0, qy = 0.0, qz = 0.0;
+    uint32_t set = pt->uniq_set[u];
+    while (set) {
+        int b = __builtin_ctz(set);
+        set &= set - 1;
+        qe += get(b, 0);
+        qx += get(b, 1);
+        qy += get(b, 2);
+        qz += get(b, 3);
+    }
+    if (pt->uniq_t[u]) {
+        qe = pae - qe;
+        qx = pax - qx;
+        qy = pay - qy;
+        qz = paz - qz;
+    }
+    return qe * qe - qx * qx - qy * qy - qz * qz;
+}
+
+// Returns alpha * f; *alpha_out receives alpha.  `logtau` = log(x1 x2).
+template <class Get>
+__device__ __forceinline__ double integrand_alpha(const ProcessTab* __restrict__ pt, int chan_in_proc, double x1,
+                                                  double x2, double logtau, double pae, double pax, double pay,
+                                                  double paz, Get get, double& alpha_out) {
+    double f = 1.0;
+    const int n = pt->n_final;
+    if (pt->pdf) {
+        // x1^a x2^a = tau^a
+        f = exp(pt->pdf_a * logtau) * pow(1.0 - x1, pt->pdf_b) * pow(1.0 - x2, pt->pdf_b);
+    }
+    if (pt->pt_min2 > 0.0) {
+        for (int i = 0; i < n; ++i) {
+            double px = get(i, 1), py = get(i, 2);
+            if (!(px * px + py * py > pt->pt_min2)) f = 0.0;
+        }
+    }
+    if (pt->ang >= 0) {
+        double px = get(pt->ang, 1), py = get(pt->ang, 2), pz = get(pt->ang, 3);
+        double c = pz / sqrt(px * px + py * py + pz * pz);
+        f *= 1.0 + c * c;
+    }
+    double qv[kMaxUniq];
+    const int nu = pt->n_uniq;
+    for (int u = 0; u < nu; ++u) qv[u] = inv_q2(pt, u, pae, pax, pay, paz, get);
+    const int nf = pt->n_fprop;
+    for (int i = 0; i < nf; ++i) {
+        double q2 = qv[pt->f_uniq[i]];
+        if (pt->f_bw[i]) {
+            double d = q2 - pt->f_m2[i];
+            f *= 1.0 / (d * d + pt->f_mw[i] * pt->f_mw[i]);
+        } else {
+            f *= 1.0 / (fabs(q2) + pt->f_mu2[i]);
+        }
+    }
+    double alpha = 1.0;
+    const int nc = pt->n_chan;
+    if (nc > 1) {
+        double den = 0.0, mine = 0.0;
+        for (int c = 0; c < nc; ++c) {
+            double P = 1.0;
+            uint32_t m = pt->chan_mask[c];
+            while (m) {
+                int u = __builtin_ctz(m);
+                m &= m - 1;
+                double q2 = qv[u];
+                if (pt->uniq_massive[u]) {
+                    double d = q2 - pt->uniq_m2[u];
+                    P *= 1.0 / (d * d + pt->uniq_mw[u] * pt->uniq_mw[u]);
+                } else {
+                    double d = fabs(q2) + pt->alpha_mu2;
+                    P *= 1.0 / (d * d);
+                }
+            }
+            den += P;
+            if (c == chan_in_proc) mine = P;
+        }
+        alpha = mine / den;
+    }
+    alpha_out = alpha;
+    return alpha * f;
+}
+
+}  // namespace msx

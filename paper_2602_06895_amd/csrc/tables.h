@@ -1,0 +1,146 @@
+// Device-resident channel and process tables.
+//
+// The host channel compiler turns each diagram topology into one ChannelTab:
+// the time-like invariants with their bounds written as linear forms over the
+// square roots of earlier invariants (the min/max mass recursion of the
+// s-channel integration order, and the t-channel bounds, resolved once at
+// construction), the chain of 2->2 blocks, the (phi, theta) decays and the
+// momentum slot of every particle.  Every lane of a wave runs the same
+// channel, so kernels read these tables with scalar loads and index the
+// per-event register file with wave-uniform slot numbers.
+#pragma once
+
+#include <stdint.h>
+
+namespace msx {
+
+constexpr int kMaxFinal = 8;        // final-state particles per process
+constexpr int kMaxInv = 8;          // s-hat plus time-like invariants per channel
+constexpr int kMaxSlots = 16;       // momentum slots per event
+constexpr int kMaxDims = 32;        // random dimensions per channel
+constexpr int kMaxUniq = 16;        // distinct propagator invariants per process
+constexpr int kMaxChanPerProc = 32; // channels per process (local weights)
+constexpr int kMaxFactors = 8;      // integrand propagator factors
+constexpr int kMaxChannels = 64;    // channels per context
+constexpr int kMaxProcesses = 8;
+constexpr int kMaxBins = 128;       // VEGAS bins per dimension
+
+enum MapKind : int32_t {
+    MAP_FIXED = 0,  // value fixed (lepton beams: s-hat = s)
+    MAP_FLAT = 1,   // nu = 0
+    MAP_POW = 2,    // power law, nu != 0, 1
+    MAP_LOG = 3,    // nu = 1
+    MAP_BW = 4      // Breit-Wigner
+};
+
+// Parameters of one G_nu / G_BW mapping.
+struct MapParams {
+    int32_t kind;
+    int32_t int_pow;  // MAP_POW: 1/(1-nu) when it is a small integer, else 0
+    double m2;        // pole: m^2, or -a for a massless structure; BW: m^2
+    double mw;        // BW: m * Gamma
+    double e;         // MAP_POW: 1 - nu
+    double inv_e;     // MAP_POW: 1 / (1 - nu)
+};
+
+// Source of a mass: sqrt of invariant `inv` when inv >= 0, else the constant.
+struct MassSrc {
+    int32_t inv;
+    int32_t pad;
+    double m;
+};
+
+// One time-like invariant.  Index 0 is s-hat with static bounds.  Others:
+//   m_min = min_const + sum_{j in min_mask} sqrt(s_j)
+//   m_max = sqrt(s_parent) - max_const - sum_{j in max_mask} sqrt(s_j)
+struct InvSpec {
+    MapParams map;
+    int32_t parent;
+    uint32_t min_mask;
+    uint32_t max_mask;
+    int32_t pad;
+    double min_const, max_const;
+    // static bounds (s-hat): precomputed A = (xmax - m2)^e, B = (xmin - m2)^e
+    // (MAP_POW), logs (MAP_LOG) or arctangents u2, u1 (MAP_BW)
+    double xmin, xmax, A, B;
+};
+
+// One 2->2 block of the t-channel chain (section 2.2.4).
+struct BlockSpec {
+    MassSrc m1, m2;
+    MapParams tmap;  // |t| mapping: G_nu with the massless auxiliary pole
+    int32_t side;    // 0: leg next to A (slot1 <- p1, p_A -= p1); 1: next to B
+                     // (slot2 <- p2, p_B -= p2); 2: last block (both stored)
+    int32_t slot1, slot2;
+    int32_t com;     // p_A, p_B are the incoming partons in their CM frame
+    int32_t m0_inv;  // (p_A + p_B)^2 = s[m0_inv] (s-hat or the previous t-channel invariant)
+    int32_t pad;
+};
+
+// One (phi, theta) two-body decay (section 2.2.3).
+struct DecaySpec {
+    int32_t parent_slot;  // -1: parent at rest in the partonic frame
+    int32_t parent_inv;   // m0^2 = s[parent_inv]
+    MassSrc m1, m2;
+    int32_t slot1, slot2;
+};
+
+struct ChannelTab {
+    int32_t process;
+    int32_t dims;
+    int32_t n_final;
+    int32_t n_inv;       // including s-hat
+    int32_t n_blocks;
+    int32_t n_decays;
+    int32_t hadronic;
+    int32_t alpha_index; // position of this channel within its process
+    int32_t n_slots;
+    int32_t pad;
+    double jac_const;    // (2 pi)^(4 - 3 n) times the channel constant
+    InvSpec inv[kMaxInv];
+    BlockSpec blk[kMaxFinal];
+    DecaySpec dec[kMaxFinal];
+    int32_t final_slot[kMaxFinal];
+};
+
+// Integrand and local channel weights of one process.
+struct ProcessTab {
+    int32_t n_final;
+    int32_t hadronic;
+    int32_t n_chan;      // channels entering alpha (1: alpha = 1)
+    int32_t n_uniq;      // distinct invariants q^2 needed
+    int32_t n_fprop;     // integrand propagator factors
+    int32_t pdf;         // toy PDF on both momentum fractions
+    int32_t ang;         // -1, or particle index for 1 + cos^2 theta
+    int32_t pad;
+    double s_lab;
+    double pdf_a, pdf_b;
+    double pt_min2;      // <= 0: no cut
+    double alpha_mu2;
+    // distinct invariants: q = p_a - sum (t) or sum (s) over a particle set
+    int32_t uniq_t[kMaxUniq];
+    uint32_t uniq_set[kMaxUniq];
+    // form of each invariant in alpha: massive -> 1/((q^2-m^2)^2 + m^2 w^2),
+    // massless -> 1/(|q^2| + mu^2)^2
+    int32_t uniq_massive[kMaxUniq];
+    double uniq_m2[kMaxUniq];
+    double uniq_mw[kMaxUniq];
+    uint32_t chan_mask[kMaxChanPerProc];  // invariants of each channel
+    // integrand factors
+    int32_t f_uniq[kMaxFactors];
+    int32_t f_bw[kMaxFactors];
+    double f_m2[kMaxFactors];
+    double f_mw[kMaxFactors];
+    double f_mu2[kMaxFactors];
+};
+
+// Per-call description of a multichannel launch (passed by value).
+struct SampleCall {
+    int32_t n_chan;
+    int32_t pad;
+    int64_t n_tiles;
+    int64_t tile_start[kMaxChannels + 1];  // first tile of each channel
+    int64_t ev_start[kMaxChannels + 1];    // first output position
+};
+
+}  // namespace msx

@@ -63,6 +63,7 @@ def lib(variant: str = "ref"):
         L = C.CDLL(os.path.join(_HERE, _VARIANTS[variant][0]))
         dp = C.POINTER(C.c_double)
         L.orc_map.restype = C.c_int
+        L.orc_weight.restype = C.c_int
         L.orc_kallen.restype = C.c_double
         L.orc_kallen.argtypes = [C.c_double] * 3
         L.orc_map_nu.restype = C.c_double
@@ -323,6 +324,37 @@ class Process:
         if rc != 0:
             raise ValueError("oracle rejected the sizes")
         return out
+
+    def weight(self, chan: int, p: np.ndarray, x1x2: np.ndarray | None, jac: np.ndarray,
+               nthreads: int = 0, variant: str = "ref") -> dict:
+        """w = alpha_c f jac from lab-frame momenta p [4][n+2][N], x1x2 [2][N]
+        and jac [N]; returns w and alpha."""
+        p = np.ascontiguousarray(p, dtype=np.float64)
+        jac = np.ascontiguousarray(jac, dtype=np.float64)
+        n = jac.size
+        if p.shape != (4, self.n + 2, n):
+            raise ValueError("p shape mismatch")
+        x = None if x1x2 is None else np.ascontiguousarray(x1x2, dtype=np.float64)
+        if self.hadronic and (x is None or x.shape != (2, n)):
+            raise ValueError("x1x2 [2][n] required")
+        w, a = np.empty(n), np.empty(n)
+        nt = nthreads if nthreads > 0 else (os.cpu_count() or 1)
+        dp = lambda arr: arr.ctypes.data_as(C.c_void_p) if arr is not None else None
+        rc = lib(variant).orc_weight(C.byref(self._proc), C.c_int32(chan), C.c_int64(n), dp(p), dp(x),
+                                     dp(jac), dp(w), dp(a), C.c_int32(nt))
+        if rc != 0:
+            raise ValueError("oracle rejected the sizes")
+        return {"w": w, "alpha": a}
+
+    def weight_forward_error(self, chan: int, p, x1x2, jac, ref: dict | None = None) -> dict:
+        """Forward-error estimate of weight(): largest deviation from the
+        reference among the x87 and the one-ulp perturbation builds."""
+        ref = ref if ref is not None else self.weight(chan, p, x1x2, jac)
+        a = ref["w"]
+        den = np.where(a != 0.0, np.abs(a), 1.0)
+        alts = [self.weight(chan, p, x1x2, jac, variant=v) for v in ("x87", "up", "down")]
+        return {"w": np.max([np.abs(o["w"] - a) / den for o in alts], axis=0),
+                "cut_ambiguous": np.any([(o["w"] == 0.0) != (a == 0.0) for o in alts], axis=0)}
 
     def forward_error(self, chan: int, y: np.ndarray, grid: np.ndarray | None = None,
                       ref: dict | None = None) -> dict:

@@ -17,10 +17,10 @@
 #include <string.h>
 
 /* Perturbation builds (forward-error estimation only, never the reference):
- * with ORC_LIBM_NUDGE = +1 or -1 every inexact transcendental result is
- * moved by one ulp up or down, standing in for a different math library or
- * evaluation order.  Square roots (correctly rounded everywhere) and the exact
- * results 0 and +-1 are left alone. */
+ * with ORC_LIBM_NUDGE = +1 or -1 every transcendental and square-root result
+ * is moved by one ulp up or down, standing in for a different math library or
+ * a different rounding of its argument.  The exact results 0 and +-1 are left
+ * alone (every library returns them exactly). */
 #ifdef ORC_LIBM_NUDGE
 static double orc_nudge(double v)
 {
@@ -30,6 +30,7 @@ static double orc_nudge(double v)
 #define pow(a, b) orc_nudge(pow(a, b))
 #define exp(a) orc_nudge(exp(a))
 #define log(a) orc_nudge(log(a))
+#define sqrt(a) orc_nudge(sqrt(a))
 #define atan(a) orc_nudge(atan(a))
 #define tan(a) orc_nudge(tan(a))
 #define sin(a) orc_nudge(sin(a))
@@ -358,6 +359,59 @@ static double prop_q2(int32_t t_type, uint32_t set, const double pa[4], double m
     return mdot(q, q);
 }
 
+/* Integrand f (BASELINE toy: PDFs, pT cut, 1 + cos^2, propagator factors) and
+ * the local channel weight alpha_c(x) = P_c / sum_c' P_c' (eq.
+ * multi-channel-mg, weights from propagator denominators) of final-state
+ * momenta pf[n] and incoming p_a. */
+static double integrand(const orc_process* pr, int32_t chan, double pf[][4], const double pa[4],
+                        double x1, double x2, double* alpha_out)
+{
+    const int32_t n = pr->n_final;
+    double f = 1.0, alpha;
+    if (pr->pdf) f *= pdf_toy(pr, x1) * pdf_toy(pr, x2);
+    if (pr->pt_min > 0.0)
+        for (int32_t i = 0; i < n; ++i)
+            if (!(pf[i][1] * pf[i][1] + pf[i][2] * pf[i][2] > pr->pt_min * pr->pt_min)) f = 0.0;
+    if (pr->ang >= 0) {
+        const double* p = pf[pr->ang];
+        double c = p[3] / sqrt(p[1] * p[1] + p[2] * p[2] + p[3] * p[3]);
+        f *= 1.0 + c * c;
+    }
+    for (int32_t u = 0; u < pr->n_prop; ++u) {
+        double q2 = prop_q2(pr->prop_t[u], pr->prop_set[u], pa, pf, n);
+        if (pr->prop_bw[u]) {
+            double m2 = pr->prop_m[u] * pr->prop_m[u], mw = pr->prop_m[u] * pr->prop_w[u];
+            f *= 1.0 / ((q2 - m2) * (q2 - m2) + mw * mw);
+        } else {
+            f *= 1.0 / (fabs(q2) + pr->prop_mu[u] * pr->prop_mu[u]);
+        }
+    }
+    if (pr->n_chan <= 1) {
+        alpha = 1.0;
+    } else {
+        double den = 0.0, mine = 0.0;
+        for (int32_t c = 0; c < pr->n_chan; ++c) {
+            double P = 1.0;
+            for (int32_t u = pr->ch_start[c]; u < pr->ch_start[c + 1]; ++u) {
+                double q2 = prop_q2(pr->chp_t[u], pr->chp_set[u], pa, pf, n);
+                double m = pr->chp_m[u];
+                if (m > 0.0) {
+                    double mw = m * pr->chp_w[u];
+                    P *= 1.0 / ((q2 - m * m) * (q2 - m * m) + mw * mw);
+                } else {
+                    double d = fabs(q2) + pr->alpha_mu * pr->alpha_mu;
+                    P *= 1.0 / (d * d);
+                }
+            }
+            den += P;
+            if (c == chan) mine = P;
+        }
+        alpha = mine / den;
+    }
+    *alpha_out = alpha;
+    return f;
+}
+
 typedef struct {
     double p[ORC_MAX_FINAL + 2][4]; /* lab frame: a, b, 1..n */
     double x1, x2, jac, w, alpha, f;
@@ -590,49 +644,7 @@ static void event(const orc_process* pr, const orc_channel* ch, int32_t chan,
     /* (11) integrand f and local channel weight alpha_c(x) (SDE multichannel,
      *      eq. multi-channel-mg) from invariants of the partonic-frame momenta */
     double f = 0.0, alpha = 0.0;
-    if (ok) {
-        f = 1.0;
-        if (pr->pdf) f *= pdf_toy(pr, x1) * pdf_toy(pr, x2);
-        if (pr->pt_min > 0.0)
-            for (int32_t i = 0; i < n; ++i)
-                if (!(pf[i][1] * pf[i][1] + pf[i][2] * pf[i][2] > pr->pt_min * pr->pt_min)) f = 0.0;
-        if (pr->ang >= 0) {
-            const double* p = pf[pr->ang];
-            double c = p[3] / sqrt(p[1] * p[1] + p[2] * p[2] + p[3] * p[3]);
-            f *= 1.0 + c * c;
-        }
-        for (int32_t u = 0; u < pr->n_prop; ++u) {
-            double q2 = prop_q2(pr->prop_t[u], pr->prop_set[u], pa, pf, n);
-            if (pr->prop_bw[u]) {
-                double m2 = pr->prop_m[u] * pr->prop_m[u], mw = pr->prop_m[u] * pr->prop_w[u];
-                f *= 1.0 / ((q2 - m2) * (q2 - m2) + mw * mw);
-            } else {
-                f *= 1.0 / (fabs(q2) + pr->prop_mu[u] * pr->prop_mu[u]);
-            }
-        }
-        if (pr->n_chan <= 1) {
-            alpha = 1.0;
-        } else {
-            double den = 0.0, mine = 0.0;
-            for (int32_t c = 0; c < pr->n_chan; ++c) {
-                double P = 1.0;
-                for (int32_t u = pr->ch_start[c]; u < pr->ch_start[c + 1]; ++u) {
-                    double q2 = prop_q2(pr->chp_t[u], pr->chp_set[u], pa, pf, n);
-                    double m = pr->chp_m[u];
-                    if (m > 0.0) {
-                        double mw = m * pr->chp_w[u];
-                        P *= 1.0 / ((q2 - m * m) * (q2 - m * m) + mw * mw);
-                    } else {
-                        double d = fabs(q2) + pr->alpha_mu * pr->alpha_mu;
-                        P *= 1.0 / (d * d);
-                    }
-                }
-                den += P;
-                if (c == chan) mine = P;
-            }
-            alpha = mine / den;
-        }
-    }
+    if (ok) f = integrand(pr, chan, pf, pa, x1, x2, &alpha);
     ev->x1 = x1;
     ev->x2 = x2;
     ev->jac = jac;
@@ -677,6 +689,39 @@ int orc_map(const orc_process* pr, const orc_channel* ch, int32_t chan, int32_t 
             for (int32_t j = 0; j < ch->n_nodes; ++j) inv[(size_t)j * n + e] = ev.inv[j];
         if (tabs && ch->kind[ch->root] == ORC_TNODE)
             for (int32_t j = 0; j < ch->child_count[ch->root] - 1; ++j) tabs[(size_t)j * n + e] = ev.tabs[j];
+    }
+    return 0;
+}
+
+/* Weight of given events: w = alpha_c f jac from lab-frame momenta p
+ * [4][n_final+2][n] (incoming a, b first), x1x2 [2][n] (hadronic) and jac [n]
+ * (events with jac = 0 get w = 0).  alpha [n] may be NULL. */
+int orc_weight(const orc_process* pr, int32_t chan, int64_t n, const double* p, const double* x1x2,
+               const double* jac, double* w, double* alpha, int32_t nthreads)
+{
+    if (pr->n_final > ORC_MAX_FINAL) return -1;
+    const int32_t np = pr->n_final + 2;
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t e = 0; e < n; ++e) {
+        double pf[ORC_MAX_FINAL][4], pa[4];
+        for (int c = 0; c < 4; ++c) {
+            pa[c] = p[((size_t)c * np + 0) * n + e];
+            for (int32_t i = 0; i < pr->n_final; ++i) pf[i][c] = p[((size_t)c * np + i + 2) * n + e];
+        }
+#ifdef ORC_LIBM_NUDGE
+        for (int32_t i = 0; i < pr->n_final; ++i)
+            for (int c = 0; c < 4; ++c)
+                if (pf[i][c] != 0.0)
+                    pf[i][c] = nextafter(pf[i][c], ((i + c + (ORC_LIBM_NUDGE > 0)) & 1) ? INFINITY : -INFINITY);
+#endif
+        double x1 = 1.0, x2 = 1.0, a = 0.0, f = 0.0;
+        if (pr->hadronic) {
+            x1 = x1x2[e];
+            x2 = x1x2[n + e];
+        }
+        if (jac[e] != 0.0) f = integrand(pr, chan, pf, pa, x1, x2, &a);
+        w[e] = a * f * jac[e];
+        if (alpha) alpha[e] = a;
     }
     return 0;
 }

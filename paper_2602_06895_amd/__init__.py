@@ -135,9 +135,12 @@ class Context:
         self._check(self.L.msx_uniform(self.h, seed, stream_id, e0, n, d, _ptr(y), self._stream()))
         return y
 
-    def _check_y(self, channel: int, y):
+    def _check_channel(self, channel: int):
         if not (0 <= channel < self.n_channels):
-            return
+            raise MsxError(1, f"channel index {channel} out of range")
+
+    def _check_y(self, channel: int, y):
+        self._check_channel(channel)
         if y.dim() != 2 or y.shape[0] != self.dims[channel] or y.dtype != self.torch.float64 or y.device != self.device:
             raise ValueError(f"y must be a float64 [{self.dims[channel]}][n] tensor on {self.device}")
 
@@ -155,7 +158,8 @@ class Context:
 
     def weight(self, channel: int, p, x1x2, jac, alpha: bool = False):
         n = jac.shape[0]
-        if 0 <= channel < self.n_channels and tuple(p.shape) != (4, self.n_momenta[channel], n):
+        self._check_channel(channel)
+        if tuple(p.shape) != (4, self.n_momenta[channel], n):
             raise ValueError(f"p must be [4][{self.n_momenta[channel]}][{n}]")
         w = self._empty(n)
         a = self._empty(n) if alpha else None
@@ -168,6 +172,8 @@ class Context:
         counts = np.ascontiguousarray(counts, dtype=np.int64)
         if counts.shape != (self.n_channels,):
             raise ValueError(f"counts must have {self.n_channels} entries")
+        if (counts < 0).any():
+            raise MsxError(1, "negative event count")
         N = int(counts.sum())
         if out is not None and (out["p"].shape[1] != self.max_momenta or out["p"].shape[2] < N or out["w"].shape[0] < N):
             raise ValueError("output buffers are too small")

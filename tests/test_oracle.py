@@ -635,8 +635,8 @@ def test_philox_uniforms_addressing_and_range():
     assert chi2 < 120  # 63 dof
 
 
-@pytest.mark.parametrize("cfg,bound", [("c1", 1e-14), ("c2", 1e-7), ("c3", 1e-8)])
-def test_fp64_forward_error_stays_bounded(cfg, bound):
+@pytest.mark.parametrize("cfg,bound,median", [("c1", 1e-14, 1e-15), ("c2", 1e-7, 1e-11), ("c3", 1e-8, 1e-10)])
+def test_fp64_forward_error_stays_bounded(cfg, bound, median):
     """Two roundings of the same formulas (SSE2 and x87 builds, plus one-ulp
     input moves) agree closely: the t-range roots come from the product of
     roots and the blocks use the sampled invariants, so no event loses more
@@ -648,4 +648,4 @@ def test_fp64_forward_error_stays_bounded(cfg, bound):
         fe = P.forward_error(c, y, P.uniform_grid(c))
         assert fe["w"].max() < bound
         assert fe["p"].max() < 1e-4
-        assert np.median(fe["w"]) < 1e-11
+        assert np.median(fe["w"]) < median

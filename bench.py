@@ -56,6 +56,95 @@ def cpu_baseline(desc, grids, counts, seed, min_seconds=10.0):
                       f"GPU's proportions, frozen grids), {elapsed:.1f} s on {threads} threads"}
 
 
+KERNEL_SOURCES = ["paper_2602_06895_amd/csrc/kernels.hip", "paper_2602_06895_amd/csrc/chain.h",
+                  "paper_2602_06895_amd/csrc/tables.h"]
+PROFILE = os.path.join(ROOT, "profiles", "k_sample_pp4j_1e7.txt")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic():
+    """HBM bytes per launch from the committed counter summary, or None when the
+    kernel sources changed since the counters were taken."""
+    if not os.path.exists(PROFILE):
+        return None
+    vals = {}
+    for line in open(PROFILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def summarize(d: str, events: int):
+    """Summary of the rocprofv3 runs under d (rocpd databases written by the
+    commands printed below) for the k_sample dispatches of `events` events."""
+    import glob
+    import sqlite3
+
+    def db(sub):
+        f = glob.glob(os.path.join(d, sub, "*_results.db"))
+        return sqlite3.connect(f[0]) if f else None
+
+    out = []
+    tr = db("trace")
+    rows = list(tr.execute("select duration, grid_x, workgroup_x, vgpr_count, accum_vgpr_count, sgpr_count, "
+                           "scratch_size, lds_size from kernels where name like '%k_sample%' order by start"))
+    # the timed launches are the large ones (adaptation launches are 8e5 events)
+    big = max(r[0] for r in rows)
+    timed = [r for r in rows if r[0] > 0.5 * big]
+    dur = np.array([r[0] for r in timed]) / 1e3
+    r0 = timed[0]
+    out.append(f"kernel: k_sample (fused multichannel sample), {len(timed)} timed dispatches of {events} events")
+    out.append(f"duration_us: avg {dur.mean():.1f} min {dur.min():.1f} max {dur.max():.1f}")
+    out.append(f"launch: grid {r0[1]} work-items, workgroup {r0[2]}, vgpr {r0[3]}, agpr {r0[4]}, sgpr {r0[5]}, "
+               f"scratch {r0[6]} B/lane, lds {r0[7]} B")
+    others = list(tr.execute("select name, count(*), avg(duration) from kernels group by name order by sum(duration) desc"))
+    for name, cnt, avg in others[:8]:
+        short = name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
+        out.append(f"  kernel {short}: {cnt} dispatches, avg {avg / 1e3:.1f} us")
+
+    def counter(sub, like, name):
+        c = db(sub)
+        if c is None:
+            return None
+        v = [r[0] for r in c.execute("select value from counters_collection where kernel_name like ? and "
+                                     "counter_name = ? order by dispatch_id", (like, name))]
+        return v
+
+    fetch = counter("fetch", "%k_sample%", "FETCH_SIZE")
+    write = counter("write", "%k_sample%", "WRITE_SIZE")
+    cf = counter("cfetch", "%copyBuffer%", "FETCH_SIZE")
+    cw = counter("cwrite", "%copyBuffer%", "WRITE_SIZE")
+    if fetch and write and cf and cw:
+        copy_kib = 2 ** 30 / 1024
+        sf, sw = copy_kib / np.median(cf), copy_kib / np.median(cw)
+        f_big = max(fetch)
+        w_big = max(write)
+        hbm = f_big * 1024 * sf + w_big * 1024 * sw
+        out.append(f"copy calibration (1 GiB device copy): FETCH_SIZE {np.median(cf):.0f} KiB -> read scale {sf:.3f}; "
+                   f"WRITE_SIZE {np.median(cw):.0f} KiB -> write scale {sw:.3f}")
+        out.append(f"counters per timed dispatch: FETCH_SIZE {f_big:.1f} KiB, WRITE_SIZE {w_big:.1f} KiB")
+        out.append(f"hbm_bytes_per_launch: {hbm:.6e}")
+        out.append(f"hbm_bytes_per_event: {hbm / events:.1f}")
+    out.append(f"algorithmic_bytes_per_event: {BYTES_PER_EVENT}")
+    out.append(f"kernel_source_sha256: {kernel_source_hash()}")
+    print("\n".join(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,7 +152,23 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--events", type=int, default=N_EVENTS)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run device-to-device copies of 1 GiB (scale for HBM byte counters)")
+    ap.add_argument("--summarize", metavar="DIR", help="summarise rocprofv3 output under DIR and exit")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args.summarize, args.events)
+        return
+    if args.copy_calibration:
+        import torch
+
+        src = torch.ones(2 ** 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8, "copies": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is "
               "design-only in this build", file=sys.stderr)
@@ -146,7 +251,7 @@ def main():
         "unweighting_eff": eff,
         "passing_events_per_s": N * pass_frac / (ms_per_step / 1e3),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(),
                      "kernel": "k_sample (fused multichannel sample)",
                      "bytes_per_event": BYTES_PER_EVENT, "avg_launch_ms": avg_launch_s * 1e3},
     }

@@ -232,7 +232,8 @@ msx_status msx_map(msx_ctx* ctx, int32_t channel, int64_t n, const double* y, do
     const ProcessTab& pt = ctx->comp.procs[m.process];
     MSX_HIP(ctx,
             launch_map(ctx->d_chans + channel, ctx->d_procs + m.process, ctx->d_grids + ctx->grid_off[channel], m.nbins,
-                       m.dims, t.n_slots, pt.s_lab, m.n_momenta, n, y, p, x1x2, jac, w, ctx->cu_count,
+                       m.dims, t.n_slots, t.n_inv, t.kinds, pt.s_lab, m.n_momenta, n, y, p, x1x2, jac, w,
+                       ctx->cu_count,
                        (hipStream_t)stream),
             "map launch");
     return MSX_OK;
@@ -266,7 +267,7 @@ msx_status msx_sample(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64
     const int T = sample_tile_size();
     int64_t N = 0, tiles = 0;
     bool any_hadronic = false;
-    int max_slots = 0;
+    int max_slots = 0, max_inv = 0, kinds = 0;
     for (int c = 0; c < C; ++c) {
         if (counts[c] < 0) return fail(ctx, MSX_ERR_ARG, "negative event count");
         call.ev_start[c] = N;
@@ -277,6 +278,8 @@ msx_status msx_sample(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64
         if (counts[c] > 0) {
             any_hadronic = any_hadronic || ctx->comp.meta[c].hadronic;
             max_slots = std::max(max_slots, ctx->comp.chans[c].n_slots);
+            max_inv = std::max(max_inv, ctx->comp.chans[c].n_inv);
+            kinds |= ctx->comp.chans[c].kinds;
         }
     }
     call.ev_start[C] = N;
@@ -297,7 +300,7 @@ msx_status msx_sample(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64
     int grid = ctx->cu_count * 8;
     MSX_HIP(ctx,
             launch_sample(ctx->d_chans, ctx->d_procs, ctx->d_grids, ctx->d_grid_off, ctx->d_chan_nb, call, max_slots,
-                          ctx->lds_max, seed, stream_id, counter_offset, ctx->max_np, N, p, x1x2, w, chan, ctx->d_tile,
+                          max_inv, kinds, ctx->lds_max, seed, stream_id, counter_offset, ctx->max_np, N, p, x1x2, w, chan, ctx->d_tile,
                           ctx->d_stats, grid, (hipStream_t)stream),
             "sample launch");
     return MSX_OK;

@@ -61,6 +61,7 @@ __device__ __forceinline__ double kallen(double x, double y, double z) {
 __device__ __forceinline__ double ipow(double b, int n) {
     double b2 = b * b;
     switch (n) {
+        case 1: return b;
         case 2: return b2;
         case 3: return b2 * b;
         case 4: return b2 * b2;
@@ -71,29 +72,81 @@ __device__ __forceinline__ double ipow(double b, int n) {
     }
 }
 
+// Map kinds compiled into a kernel (a launch picks the smallest set covering
+// its channels; paths not compiled in cost no registers).
+enum : int {
+    KIND_POW_INT = 1,  // power law with 1/(1 - nu) an integer (k-th roots)
+    KIND_POW = 2,      // general power law (pow)
+    KIND_LOG = 4,      // nu = 1
+    KIND_FLAT = 8,     // nu = 0
+    KIND_BW = 16,      // Breit-Wigner
+    KINDS_ALL = 31
+};
+
+// x^(1/k) for x >= 0 and integer k in 2..8: an FP32 estimate refined by two
+// Newton steps on y^k = x in FP64 (error ~1 ulp, a third of the cost of
+// pow).  The exponent is split off first so any double is in range.
+__device__ __forceinline__ double kth_root(double x, int k) {
+    if (!(x > 0.0)) return x == 0.0 ? 0.0 : __builtin_nan("");
+    int ex;
+    double f = frexp(x, &ex);  // x = f 2^ex, f in [0.5, 1)
+    int q = ex >= 0 ? ex / k : -((-ex + k - 1) / k);
+    int rem = ex - q * k;      // 0 <= rem < k
+    double g = ldexp(f, rem);  // in [0.5, 2^k)
+    float yf = exp2f(log2f((float)g) / (float)k);
+    double y = (double)yf;
+    const double inv_k = 1.0 / k;
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        double yk1 = ipow(y, k - 1);
+        y = ((double)(k - 1) * y + g / yk1) * inv_k;
+    }
+    return ldexp(y, q);
+}
+
+// (x - m2)^e for the power-law maps: a k-th root when e = 1/k.
+template <int KINDS>
+__device__ __forceinline__ double pow_e(const MapParams& p, double x) {
+    if (!(KINDS & KIND_POW)) return kth_root(x, p.int_pow);
+    return p.int_pow ? kth_root(x, p.int_pow) : pow(x, p.e);
+}
+
+// b^n for an integer n >= 1 (square and multiply).
+__device__ __forceinline__ double ipow_any(double b, int n) {
+    double r = 1.0;
+    while (n) {
+        if (n & 1) r *= b;
+        b *= b;
+        n >>= 1;
+    }
+    return r;
+}
+
 // Power-law core: b = r A + (1 - r) B, x - m^2 = b^(1/e), and
 // J = (A - B) (x - m^2)^nu / e with (x - m^2)^nu = (x - m^2) / b.
+template <int KINDS>
 __device__ __forceinline__ double pow_core(const MapParams& p, double A, double B, double r, double& jac) {
     double b = r * A + (1.0 - r) * B;
-    double xm = p.int_pow ? ipow(b, p.int_pow) : pow(b, p.inv_e);
+    double xm = (!(KINDS & KIND_POW) || p.int_pow) ? ipow(b, p.int_pow) : pow(b, p.inv_e);
     jac = (A - B) * (xm / b) * p.inv_e;
     return xm + p.m2;
 }
 
 // G_nu / G_BW with bounds known only per event.
+template <int KINDS>
 __device__ __forceinline__ double map_dyn(const MapParams& p, double r, double xmin, double xmax, double& jac) {
     const int kind = p.kind;
-    if (kind == MAP_POW) {
-        double A = pow(xmax - p.m2, p.e), B = pow(xmin - p.m2, p.e);
-        return pow_core(p, A, B, r, jac);
+    if ((KINDS & (KIND_POW | KIND_POW_INT)) && kind == MAP_POW) {
+        double A = pow_e<KINDS>(p, xmax - p.m2), B = pow_e<KINDS>(p, xmin - p.m2);
+        return pow_core<KINDS>(p, A, B, r, jac);
     }
-    if (kind == MAP_BW) {
+    if ((KINDS & KIND_BW) && kind == MAP_BW) {
         double u1 = atan((xmin - p.m2) / p.mw), u2 = atan((xmax - p.m2) / p.mw);
         double d = p.mw * tan(u1 + (u2 - u1) * r);
         jac = (u2 - u1) * (d * d + p.mw * p.mw) / p.mw;
         return d + p.m2;
     }
-    if (kind == MAP_LOG) {
+    if ((KINDS & KIND_LOG) && kind == MAP_LOG) {
         double lmax = log(xmax - p.m2), lmin = log(xmin - p.m2);
         double xm = exp(r * lmax + (1.0 - r) * lmin);
         jac = xm * (lmax - lmin);
@@ -104,17 +157,18 @@ __device__ __forceinline__ double map_dyn(const MapParams& p, double r, double x
 }
 
 // G_nu / G_BW with precomputed static constants (s-hat).
+template <int KINDS>
 __device__ __forceinline__ double map_static(const InvSpec& iv, double r, double& jac) {
     const MapParams& p = iv.map;
     const int kind = p.kind;
-    if (kind == MAP_POW) return pow_core(p, iv.A, iv.B, r, jac);
-    if (kind == MAP_BW) {
+    if ((KINDS & (KIND_POW | KIND_POW_INT)) && kind == MAP_POW) return pow_core<KINDS>(p, iv.A, iv.B, r, jac);
+    if ((KINDS & KIND_BW) && kind == MAP_BW) {
         double u2 = iv.A, u1 = iv.B;
         double d = p.mw * tan(u1 + (u2 - u1) * r);
         jac = (u2 - u1) * (d * d + p.mw * p.mw) / p.mw;
         return d + p.m2;
     }
-    if (kind == MAP_LOG) {
+    if ((KINDS & KIND_LOG) && kind == MAP_LOG) {
         double lmax = iv.A, lmin = iv.B;
         double xm = exp(r * lmax + (1.0 - r) * lmin);
         jac = xm * (lmax - lmin);
@@ -146,29 +200,20 @@ struct ChainOut {
     bool ok;
 };
 
+// Register index of a slot code (codes >= 0 count from the bottom of the
+// slot file, codes < 0 from the top).
 template <int NS>
-struct Slots {
-    double E[NS], X[NS], Y[NS], Z[NS];
-};
-
-#define MSX_U(k) ((k) < 16 ? U0[(k)] : U1[(k)-16])
-
-template <int NS>
-__device__ __forceinline__ void set_slot(double (&E)[NS], double (&X)[NS], double (&Y)[NS], double (&Z)[NS],
-                                         int s, double e, double x, double y, double z) {
-    if (s >= 0) {
-        E[s] = e;
-        X[s] = x;
-        Y[s] = y;
-        Z[s] = z;
-    }
+__device__ __forceinline__ int slot_index(int code) {
+    return code >= 0 ? code : NS + code;
 }
 
-__device__ __forceinline__ double src_mass(const MassSrc& ms, const double (&SQ)[kMaxInv]) {
+template <int NI>
+__device__ __forceinline__ double src_mass(const MassSrc& ms, const double (&SQ)[NI]) {
     return ms.inv >= 0 ? SQ[ms.inv] : ms.m;
 }
 
-__device__ __forceinline__ double masked_sum(uint32_t mask, const double (&SQ)[kMaxInv]) {
+template <int NI>
+__device__ __forceinline__ double masked_sum(uint32_t mask, const double (&SQ)[NI]) {
     double s = 0.0;
     while (mask) {
         int b = __builtin_ctz(mask);
@@ -178,14 +223,13 @@ __device__ __forceinline__ double masked_sum(uint32_t mask, const double (&SQ)[k
     return s;
 }
 
-// The mapping chain.  U0/U1: VEGAS-mapped random numbers in dimension order.
-// Leaves the final-state momenta in the partonic frame in the slots.
-template <int NS>
-__device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, double s_lab,
-                                          const double (&U0)[16], const double (&U1)[16], double (&E)[NS],
-                                          double (&X)[NS], double (&Y)[NS], double (&Z)[NS],
-                                          double (&S)[kMaxInv], double (&SQ)[kMaxInv], ChainOut& o) {
-    int k = 0;
+// The mapping chain.  next() returns the VEGAS-mapped random number of the
+// next dimension (dimensions are consumed in order).  Leaves the final-state
+// momenta in the partonic frame in the slots.
+template <int NS, int NI, int KINDS, class Next>
+__device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, double s_lab, Next& next,
+                                          double (&E)[NS], double (&X)[NS], double (&Y)[NS], double (&Z)[NS],
+                                          double (&S)[NI], double (&SQ)[NI], ChainOut& o) {
     double jac = ct->jac_const;
     const int hadronic = ct->hadronic;
 
@@ -193,8 +237,7 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
     double shat;
     if (hadronic) {
         double j;
-        shat = map_static(ct->inv[0], MSX_U(k), j);
-        ++k;
+        shat = map_static<KINDS>(ct->inv[0], next(), j);
         jac *= j;
     } else {
         shat = s_lab;
@@ -209,8 +252,7 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
         double mmin = iv.min_const + masked_sum(iv.min_mask, SQ);
         double mmax = SQ[iv.parent] - iv.max_const - masked_sum(iv.max_mask, SQ);
         double j;
-        double s = map_dyn(iv.map, MSX_U(k), mmin * mmin, mmax * mmax, j);
-        ++k;
+        double s = map_dyn<KINDS>(iv.map, next(), mmin * mmin, mmax * mmax, j);
         jac *= j;
         S[i] = s;
         SQ[i] = sqrt(s);
@@ -219,8 +261,7 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
     // (3) momentum fractions x1 = tau^r, x2 = tau^(1-r), J = -log(tau)/s_lab
     double x1 = 1.0, x2 = 1.0, L = 0.0;
     if (hadronic) {
-        double r = MSX_U(k);
-        ++k;
+        double r = next();
         L = log(shat / s_lab);
         x1 = exp(r * L);
         x2 = exp((1.0 - r) * L);
@@ -234,12 +275,17 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
     double Ae = h, Ax = 0.0, Ay = 0.0, Az = h;   // p_A
     double Be = h, Bx = 0.0, By = 0.0, Bz = -h;  // p_B
     double ma2 = 0.0, mb2 = 0.0;
+    // Both loops are unrolled so that every slot store has a constant index
+    // (block b -> slots 2b, 2b+1; decay d -> NS-2-2d, NS-1-2d): a store with a
+    // run-time index would turn the slot file into selects.
     const int n_blocks = ct->n_blocks;
-    for (int bi = 0; bi < n_blocks; ++bi) {
+#pragma unroll
+    for (int bi = 0; bi < NS / 2; ++bi) {
+        if (bi >= n_blocks) break;
         const BlockSpec& bs = ct->blk[bi];
         double m1 = src_mass(bs.m1, SQ), m2 = src_mass(bs.m2, SQ);
-        double r_phi = MSX_U(k), r_t = MSX_U(k + 1);
-        k += 2;
+        double r_phi = next();
+        double r_t = next();
         double Pe = Ae + Be, Px = Ax + Bx, Py = Ay + By, Pz = Az + Bz;
         double m0sq = S[bs.m0_inv];
         double m0 = SQ[bs.m0_inv];
@@ -256,7 +302,7 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
         double tmin = fmax(0.0, -t_plus);
         double tmax = -t_minus;
         double jt;
-        double abst = map_dyn(bs.tmap, r_t, tmin, tmax, jt);
+        double abst = map_dyn<KINDS>(bs.tmap, r_t, tmin, tmax, jt);
         double cth = (C - 2.0 * m0sq * (m1s + ma2 + abst)) / R;
         cth = fmin(1.0, fmax(-1.0, cth));
         double sth = sqrt((1.0 - cth) * (1.0 + cth));
@@ -300,36 +346,41 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
             boost_by(Pe, Px, Py, Pz, m0, k2e, k2x, k2y, k2z);
         }
         jac *= jt * (2.0 * kPiD) / (4.0 * sqrt(lamab));
+        // store both outputs and update the legs with uniform 0/1 factors:
+        // leg next to A -> p_A -= p1, next to B -> p_B -= p2, last block -> neither
+        E[2 * bi] = k1e;
+        X[2 * bi] = k1x;
+        Y[2 * bi] = k1y;
+        Z[2 * bi] = k1z;
+        E[2 * bi + 1] = k2e;
+        X[2 * bi + 1] = k2x;
+        Y[2 * bi + 1] = k2y;
+        Z[2 * bi + 1] = k2z;
         const int side = bs.side;
-        if (side == 0) {
-            set_slot(E, X, Y, Z, bs.slot1, k1e, k1x, k1y, k1z);
-            Ae -= k1e;
-            Ax -= k1x;
-            Ay -= k1y;
-            Az -= k1z;
-            ma2 = -abst;
-        } else if (side == 1) {
-            set_slot(E, X, Y, Z, bs.slot2, k2e, k2x, k2y, k2z);
-            Be -= k2e;
-            Bx -= k2x;
-            By -= k2y;
-            Bz -= k2z;
-            mb2 = -abst;
-        } else {
-            set_slot(E, X, Y, Z, bs.slot1, k1e, k1x, k1y, k1z);
-            set_slot(E, X, Y, Z, bs.slot2, k2e, k2x, k2y, k2z);
-        }
+        const double fa = side == 0 ? 1.0 : 0.0, fb = side == 1 ? 1.0 : 0.0;
+        Ae -= fa * k1e;
+        Ax -= fa * k1x;
+        Ay -= fa * k1y;
+        Az -= fa * k1z;
+        Be -= fb * k2e;
+        Bx -= fb * k2x;
+        By -= fb * k2y;
+        Bz -= fb * k2z;
+        ma2 = side == 0 ? -abst : ma2;
+        mb2 = side == 1 ? -abst : mb2;
     }
 
     // (5) (phi, theta) decays, parents before children
     const int n_dec = ct->n_decays;
-    for (int di = 0; di < n_dec; ++di) {
+#pragma unroll
+    for (int di = 0; di < NS / 2; ++di) {
+        if (di >= n_dec) break;
         const DecaySpec& ds = ct->dec[di];
         double m0sq = S[ds.parent_inv];
         double m0 = SQ[ds.parent_inv];
         double m1 = src_mass(ds.m1, SQ), m2 = src_mass(ds.m2, SQ);
-        double r_phi = MSX_U(k), r_th = MSX_U(k + 1);
-        k += 2;
+        double r_phi = next();
+        double r_th = next();
         double m1s = m1 * m1, m2s = m2 * m2;
         double lam = kallen(m0sq, m1s, m2s);
         double inv_2m0 = 1.0 / (2.0 * m0);
@@ -343,14 +394,20 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
         sincospi(2.0 * r_phi, &sphi, &cphi);
         double k1e = e1, k1x = q * sth * cphi, k1y = q * sth * sphi, k1z = q * cth;
         double k2e = e2, k2x = -k1x, k2y = -k1y, k2z = -k1z;
-        const int ps = ds.parent_slot;
-        if (ps >= 0) {
+        if (!ds.parent_rest) {
+            const int ps = slot_index<NS>(ds.parent_slot);
             double Pe = E[ps], Px = X[ps], Py = Y[ps], Pz = Z[ps];
             boost_by(Pe, Px, Py, Pz, m0, k1e, k1x, k1y, k1z);
             boost_by(Pe, Px, Py, Pz, m0, k2e, k2x, k2y, k2z);
         }
-        set_slot(E, X, Y, Z, ds.slot1, k1e, k1x, k1y, k1z);
-        set_slot(E, X, Y, Z, ds.slot2, k2e, k2x, k2y, k2z);
+        E[NS - 2 - 2 * di] = k1e;
+        X[NS - 2 - 2 * di] = k1x;
+        Y[NS - 2 - 2 * di] = k1y;
+        Z[NS - 2 - 2 * di] = k1z;
+        E[NS - 1 - 2 * di] = k2e;
+        X[NS - 1 - 2 * di] = k2x;
+        Y[NS - 1 - 2 * di] = k2y;
+        Z[NS - 1 - 2 * di] = k2z;
         jac *= sl / (8.0 * m0sq) * (4.0 * kPiD);
     }
 
@@ -395,8 +452,17 @@ __device__ __forceinline__ double integrand_alpha(const ProcessTab* __restrict__
     double f = 1.0;
     const int n = pt->n_final;
     if (pt->pdf) {
-        // x1^a x2^a = tau^a
-        f = exp(pt->pdf_a * logtau) * pow(1.0 - x1, pt->pdf_b) * pow(1.0 - x2, pt->pdf_b);
+        // x1^a x2^a = tau^a; integer b by multiplication
+        double u1 = 1.0 - x1, u2 = 1.0 - x2;
+        double b1, b2;
+        if (pt->pdf_b_int > 0) {
+            b1 = ipow_any(u1, pt->pdf_b_int);
+            b2 = ipow_any(u2, pt->pdf_b_int);
+        } else {
+            b1 = pow(u1, pt->pdf_b);
+            b2 = pow(u2, pt->pdf_b);
+        }
+        f = exp(pt->pdf_a * logtau) * b1 * b2;
     }
     if (pt->pt_min2 > 0.0) {
         for (int i = 0; i < n; ++i) {

@@ -14,6 +14,7 @@ namespace {
 constexpr double kPi = 3.14159265358979323846;
 
 enum { N_LEAF = 0, N_CLUSTER = 1, N_TNODE = 2 };
+constexpr int kNoSlot = 1 << 20;
 
 struct Node {
     int kind = N_LEAF;
@@ -23,7 +24,7 @@ struct Node {
     double m = 0.0, w = 0.0, nu = 0.0;
     bool has_order = false;
     double order = 0.0;
-    int slot = -1;
+    int slot = kNoSlot;
     int inv = -1;  // invariant index once scheduled
 };
 
@@ -223,13 +224,8 @@ bool compile_channel(Ctx& cx, const JValue& cj, const std::vector<double>& masse
             if (c != 1) return cx.fail("every final-state particle must appear exactly once");
     }
 
-    // ---- slots: finals 0..n-1, then non-root clusters in node order
-    int nslot = n;
-    for (size_t j = 0; j < nodes.size(); ++j) {
-        if (nodes[j].kind == N_LEAF) nodes[j].slot = nodes[j].particle;
-        else if (nodes[j].kind == N_CLUSTER && j != 0) nodes[j].slot = nslot++;
-    }
-    if (nslot > kMaxSlots) return cx.fail("too many momentum slots");
+    // ---- slots: assigned with the operations below (block b: codes 2b, 2b+1;
+    // decay d: codes -2-2d, -1-2d, i.e. from the top of the slot file)
 
     // ---- invariants: 0 = s-hat (root), then clusters in sampling order
     std::vector<int> s_order;
@@ -247,7 +243,7 @@ bool compile_channel(Ctx& cx, const JValue& cj, const std::vector<double>& masse
 
     t.n_final = n;
     t.hadronic = hadronic ? 1 : 0;
-    t.n_slots = nslot;
+    t.n_slots = 2 * (n - 1);
     t.jac_const = std::pow(2.0 * kPi, 4.0 - 3.0 * n);
 
     // s-hat
@@ -359,20 +355,18 @@ bool compile_channel(Ctx& cx, const JValue& cj, const std::vector<double>& masse
                 bs.side = 2;
                 bs.m1 = mass_src(nodes[sigma[kappa]]);
                 bs.m2 = mass_src(nodes[sigma[kappa + 1]]);
-                bs.slot1 = nodes[sigma[kappa]].slot;
-                bs.slot2 = nodes[sigma[kappa + 1]].slot;
+                nodes[sigma[kappa]].slot = 2 * (i - 1);
+                nodes[sigma[kappa + 1]].slot = 2 * (i - 1) + 1;
             } else if (from_a[i]) {
                 bs.side = 0;
                 bs.m1 = mass_src(nodes[sigma[i]]);
                 bs.m2 = rem;
-                bs.slot1 = nodes[sigma[i]].slot;
-                bs.slot2 = -1;
+                nodes[sigma[i]].slot = 2 * (i - 1);
             } else {
                 bs.side = 1;
                 bs.m1 = rem;
                 bs.m2 = mass_src(nodes[sigma[i]]);
-                bs.slot1 = -1;
-                bs.slot2 = nodes[sigma[i]].slot;
+                nodes[sigma[i]].slot = 2 * (i - 1) + 1;
             }
         }
     }
@@ -384,18 +378,39 @@ bool compile_channel(Ctx& cx, const JValue& cj, const std::vector<double>& masse
     for (size_t j = 0; j < nodes.size(); ++j) {
         if (nodes[j].kind != N_CLUSTER) continue;
         if (nd >= kMaxFinal) return cx.fail("too many decays");
-        DecaySpec& ds = t.dec[nd++];
-        ds.parent_slot = (j == 0) ? -1 : nodes[j].slot;
+        DecaySpec& ds = t.dec[nd];
+        ds.parent_rest = (j == 0) ? 1 : 0;
+        ds.parent_slot = (j == 0) ? 0 : nodes[j].slot;
         ds.parent_inv = nodes[j].inv;
-        const Node& k0 = nodes[nodes[j].kids[0]];
-        const Node& k1 = nodes[nodes[j].kids[1]];
+        Node& k0 = nodes[nodes[j].kids[0]];
+        Node& k1 = nodes[nodes[j].kids[1]];
         ds.m1 = mass_src(k0);
         ds.m2 = mass_src(k1);
-        ds.slot1 = k0.slot;
-        ds.slot2 = k1.slot;
+        k0.slot = -2 - 2 * nd;
+        k1.slot = -1 - 2 * nd;
+        ++nd;
     }
     t.n_decays = nd;
-    for (int k = 0; k < n; ++k) t.final_slot[k] = k;
+    if (t.n_blocks + t.n_decays != n - 1) return cx.fail("internal: operation count");
+    for (size_t j = 0; j < nodes.size(); ++j) {
+        if (nodes[j].kind != N_LEAF) continue;
+        if (nodes[j].slot == kNoSlot) return cx.fail("internal: particle without a slot");
+        t.final_slot[nodes[j].particle] = nodes[j].slot;
+    }
+    // map kinds used (bit values as in the kernels: 1 integer-root power law,
+    // 2 general power law, 4 log, 8 flat, 16 Breit-Wigner)
+    auto kind_bit = [](const MapParams& p) -> int32_t {
+        switch (p.kind) {
+            case MAP_POW: return p.int_pow ? 1 : 2;
+            case MAP_LOG: return 4;
+            case MAP_FLAT: return 8;
+            case MAP_BW: return 16;
+            default: return 0;
+        }
+    };
+    t.kinds = 0;
+    for (int i = 0; i < t.n_inv; ++i) t.kinds |= kind_bit(t.inv[i].map);
+    for (int i = 0; i < t.n_blocks; ++i) t.kinds |= kind_bit(t.blk[i].tmap);
     t.dims = (hadronic ? 2 : 0) + (int)s_order.size() + std::max(kappa - 1, 0) + 2 * kappa + 2 * nd;
     if (t.dims > kMaxDims) return cx.fail("too many random dimensions");
 
@@ -479,6 +494,7 @@ bool compile_process(Ctx& cx, const JValue& pj, Compiled& out) {
             pt.pdf = 1;
             pt.pdf_a = pdf->arr[0].num;
             pt.pdf_b = pdf->arr[1].num;
+            if (pt.pdf_b == std::floor(pt.pdf_b) && pt.pdf_b >= 1.0 && pt.pdf_b <= 16.0) pt.pdf_b_int = (int32_t)pt.pdf_b;
         }
         double ptmin = num_or(*ig, "pt_min", 0.0);
         pt.pt_min2 = ptmin > 0.0 ? ptmin * ptmin : 0.0;

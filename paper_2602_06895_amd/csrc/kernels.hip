@@ -26,11 +26,6 @@ __device__ __forceinline__ double vegas_map(double y, const double* __restrict__
     return e0 + wd * (t - i);
 }
 
-__device__ __forceinline__ void set_u(double (&U0)[16], double (&U1)[16], int k, double v) {
-    if (k < 16) U0[k] = v;
-    else U1[k - 16] = v;
-}
-
 // Deterministic wave-level reductions (fixed butterfly order).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -70,7 +65,7 @@ __device__ __forceinline__ double finish_event(const ChannelTab* __restrict__ ct
             py = 0.0;
             pz = i == 0 ? h : -h;
         } else {
-            int s = ct->final_slot[i - 2];
+            int s = slot_index<NS>(ct->final_slot[i - 2]);
             pe = E[s];
             px = X[s];
             py = Y[s];
@@ -102,7 +97,7 @@ __device__ __forceinline__ double finish_event(const ChannelTab* __restrict__ ct
     if (want_w && ok) {
         double alpha;
         auto get = [&](int k, int c) -> double {
-            int s = ct->final_slot[k];
+            int s = slot_index<NS>(ct->final_slot[k]);
             return c == 0 ? E[s] : (c == 1 ? X[s] : (c == 2 ? Y[s] : Z[s]));
         };
         double af = integrand_alpha(pt, ct->alpha_index, o.x1, o.x2, o.logtau, h, 0.0, 0.0, h, get, alpha);
@@ -132,7 +127,7 @@ __global__ __launch_bounds__(kBlock) void k_uniform(uint64_t seed, uint64_t sid,
     }
 }
 
-template <int NS>
+template <int NS, int NI, int KINDS>
 __global__ __launch_bounds__(kBlock) void k_map(const ChannelTab* __restrict__ ct, const ProcessTab* __restrict__ pt,
                                                 const double* __restrict__ grid, int nb, double s_lab, int np,
                                                 int64_t n, const double* __restrict__ y, double* __restrict__ p,
@@ -144,15 +139,16 @@ __global__ __launch_bounds__(kBlock) void k_map(const ChannelTab* __restrict__ c
     __syncthreads();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
-        double U0[16], U1[16];
+        int k = 0;
         double jv = 1.0;
-        for (int k = 0; k < dims; ++k) {
+        auto next = [&]() -> double {
             double r = vegas_map(y[(int64_t)k * n + e], lg + k * (nb + 1), nb, jv);
-            set_u(U0, U1, k, r);
-        }
-        double E[NS], X[NS], Y[NS], Z[NS], S[kMaxInv], SQ[kMaxInv];
+            ++k;
+            return r;
+        };
+        double E[NS], X[NS], Y[NS], Z[NS], S[NI], SQ[NI];
         ChainOut o;
-        run_chain<NS>(ct, s_lab, U0, U1, E, X, Y, Z, S, SQ, o);
+        run_chain<NS, NI, KINDS>(ct, s_lab, next, E, X, Y, Z, S, SQ, o);
         double wv = finish_event<NS>(ct, pt, o, jv, E, X, Y, Z, np, n, e, p, x1x2, jac, w != nullptr);
         if (w) w[e] = wv;
     }
@@ -187,7 +183,7 @@ __global__ __launch_bounds__(kBlock) void k_weight(const ChannelTab* __restrict_
 // channels; block b takes tiles b, b + gridDim, ... (static, so per-tile
 // statistics are reproducible).  Each tile writes (sum w, sum w^2, n(w == 0),
 // max w) to tile_stats.
-template <int NS>
+template <int NS, int NI, int KINDS>
 __global__ __launch_bounds__(kBlock) void k_sample(const ChannelTab* __restrict__ cts, const ProcessTab* __restrict__ pts,
                                                    const double* __restrict__ grids, const int64_t* __restrict__ grid_off,
                                                    const int32_t* __restrict__ chan_nb, SampleCall call, uint64_t seed,
@@ -220,21 +216,26 @@ __global__ __launch_bounds__(kBlock) void k_sample(const ChannelTab* __restrict_
         double wv = 0.0;
         if (active) {
             const uint64_t e = ctr_off + (uint64_t)pos;
-            double U0[16], U1[16];
+            // uniforms on demand, four per Philox block (dimensions are consumed in order)
+            double ub[4];
+            int k = 0;
             double jv = 1.0;
-            for (int gi = 0; gi < (dims + 3) / 4; ++gi) {
-                uint64_t c0 = e, c1 = (uint64_t)gi, c2 = 0, c3 = 0;
-                philox4x64_10(c0, c1, c2, c3, seed, sid);
-                const uint64_t wd[4] = {c0, c1, c2, c3};
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    int k = 4 * gi + j;
-                    if (k < dims) set_u(U0, U1, k, vegas_map(to_unit(wd[j]), lg + k * (nb + 1), nb, jv));
+            auto next = [&]() -> double {
+                if ((k & 3) == 0) {
+                    uint64_t c0 = e, c1 = (uint64_t)(k >> 2), c2 = 0, c3 = 0;
+                    philox4x64_10(c0, c1, c2, c3, seed, sid);
+                    ub[0] = to_unit(c0);
+                    ub[1] = to_unit(c1);
+                    ub[2] = to_unit(c2);
+                    ub[3] = to_unit(c3);
                 }
-            }
-            double E[NS], X[NS], Y[NS], Z[NS], S[kMaxInv], SQ[kMaxInv];
+                double r = vegas_map(ub[k & 3], lg + k * (nb + 1), nb, jv);
+                ++k;
+                return r;
+            };
+            double E[NS], X[NS], Y[NS], Z[NS], S[NI], SQ[NI];
             ChainOut o;
-            run_chain<NS>(ct, s_lab, U0, U1, E, X, Y, Z, S, SQ, o);
+            run_chain<NS, NI, KINDS>(ct, s_lab, next, E, X, Y, Z, S, SQ, o);
             wv = finish_event<NS>(ct, pt, o, jv, E, X, Y, Z, np, N, pos, p, x1x2, nullptr, true);
             w[pos] = wv;
             if (chan_out) chan_out[pos] = c;
@@ -395,6 +396,42 @@ __global__ void k_vegas_refine(int n_rows, const int32_t* __restrict__ row_nb, c
     for (int i = 0; i < nb; ++i) d[i] = 0.0;
 }
 
+// Register-file class of a launch: momentum slots (2 per operation) and
+// invariants per event.
+int reg_class(int slots, int inv) {
+    if (slots <= 6 && inv <= 4) return 0;
+    if (slots <= 10 && inv <= 8) return 1;
+    return 2;
+}
+
+// Map-kind class of a launch: 0 integer-root power laws only, 1 plus
+// Breit-Wigner, 2 everything.
+int kind_class(int kinds) {
+    if ((kinds & ~KIND_POW_INT) == 0) return 0;
+    if ((kinds & ~(KIND_POW_INT | KIND_BW)) == 0) return 1;
+    return 2;
+}
+
+// One launch per (register class, kind class) instantiation.
+#define MSX_DISPATCH(RC, KC, LAUNCH)                                       \
+    do {                                                                   \
+        constexpr int K0 = KIND_POW_INT, K1 = KIND_POW_INT | KIND_BW, K2 = KINDS_ALL; \
+        const int rc_ = (RC), kc_ = (KC);                                  \
+        if (rc_ == 0) {                                                    \
+            if (kc_ == 0) LAUNCH(6, 4, K0);                                \
+            else if (kc_ == 1) LAUNCH(6, 4, K1);                           \
+            else LAUNCH(6, 4, K2);                                         \
+        } else if (rc_ == 1) {                                             \
+            if (kc_ == 0) LAUNCH(10, 8, K0);                               \
+            else if (kc_ == 1) LAUNCH(10, 8, K1);                          \
+            else LAUNCH(10, 8, K2);                                        \
+        } else {                                                           \
+            if (kc_ == 0) LAUNCH(14, 8, K0);                               \
+            else if (kc_ == 1) LAUNCH(14, 8, K1);                          \
+            else LAUNCH(14, 8, K2);                                        \
+        }                                                                  \
+    } while (0)
+
 int grid_for(int64_t n, int cap) {
     int64_t g = (n + kBlock - 1) / kBlock;
     if (g > cap) g = cap;
@@ -415,15 +452,14 @@ hipError_t launch_uniform(uint64_t seed, uint64_t sid, uint64_t e0, int64_t n, i
 }
 
 hipError_t launch_map(const ChannelTab* ct, const ProcessTab* pt, const double* grid, int nb, int dims, int n_slots,
-                      double s_lab, int np, int64_t n, const double* y, double* p, double* x1x2, double* jac,
-                      double* w, int cu_count, hipStream_t s) {
+                      int n_inv, int kinds, double s_lab, int np, int64_t n, const double* y, double* p,
+                      double* x1x2, double* jac, double* w, int cu_count, hipStream_t s) {
     if (n == 0) return hipSuccess;
     size_t lds = sizeof(double) * (size_t)dims * (nb + 1);
     int g = grid_for(n, cu_count * 8);
-    if (n_slots <= 8)
-        k_map<8><<<g, kBlock, lds, s>>>(ct, pt, grid, nb, s_lab, np, n, y, p, x1x2, jac, w);
-    else
-        k_map<16><<<g, kBlock, lds, s>>>(ct, pt, grid, nb, s_lab, np, n, y, p, x1x2, jac, w);
+#define MSX_MAP(NS, NI, K) k_map<NS, NI, K><<<g, kBlock, lds, s>>>(ct, pt, grid, nb, s_lab, np, n, y, p, x1x2, jac, w)
+    MSX_DISPATCH(reg_class(n_slots, n_inv), kind_class(kinds), MSX_MAP);
+#undef MSX_MAP
     return hipGetLastError();
 }
 
@@ -436,17 +472,17 @@ hipError_t launch_weight(const ChannelTab* ct, const ProcessTab* pt, int np, int
 }
 
 hipError_t launch_sample(const ChannelTab* cts, const ProcessTab* pts, const double* grids, const int64_t* grid_off,
-                         const int32_t* chan_nb, const SampleCall& call, int max_slots, size_t lds_bytes,
+                         const int32_t* chan_nb, const SampleCall& call, int max_slots, int max_inv, int kinds,
+                         size_t lds_bytes,
                          uint64_t seed, uint64_t sid, uint64_t ctr_off, int np, int64_t N, double* p, double* x1x2,
                          double* w, int32_t* chan, double* tile_stats, double* stats, int grid, hipStream_t s) {
     if (call.n_tiles == 0) return hipSuccess;
     int g = (int)std::min<int64_t>(call.n_tiles, grid);
-    if (max_slots <= 8)
-        k_sample<8><<<g, kBlock, lds_bytes, s>>>(cts, pts, grids, grid_off, chan_nb, call, seed, sid, ctr_off, 0.0, np,
-                                                 N, p, x1x2, w, chan, tile_stats);
-    else
-        k_sample<16><<<g, kBlock, lds_bytes, s>>>(cts, pts, grids, grid_off, chan_nb, call, seed, sid, ctr_off, 0.0, np,
-                                                  N, p, x1x2, w, chan, tile_stats);
+#define MSX_SAMPLE(NS, NI, K)                                                                                \
+    k_sample<NS, NI, K><<<g, kBlock, lds_bytes, s>>>(cts, pts, grids, grid_off, chan_nb, call, seed, sid, ctr_off, \
+                                                     0.0, np, N, p, x1x2, w, chan, tile_stats)
+    MSX_DISPATCH(reg_class(max_slots, max_inv), kind_class(kinds), MSX_SAMPLE);
+#undef MSX_SAMPLE
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     k_stats_final<<<call.n_chan, kBlock, 0, s>>>(call, tile_stats, stats);

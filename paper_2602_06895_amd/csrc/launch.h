@@ -11,14 +11,15 @@ namespace msx {
 hipError_t launch_uniform(uint64_t seed, uint64_t sid, uint64_t e0, int64_t n, int d, double* y, hipStream_t s);
 
 hipError_t launch_map(const ChannelTab* ct, const ProcessTab* pt, const double* grid, int nb, int dims, int n_slots,
-                      double s_lab, int np, int64_t n, const double* y, double* p, double* x1x2, double* jac,
-                      double* w, int cu_count, hipStream_t s);
+                      int n_inv, int kinds, double s_lab, int np, int64_t n, const double* y, double* p,
+                      double* x1x2, double* jac, double* w, int cu_count, hipStream_t s);
 
 hipError_t launch_weight(const ChannelTab* ct, const ProcessTab* pt, int np, int64_t n, const double* p,
                          const double* x1x2, const double* jac, double* w, double* alpha, hipStream_t s);
 
 hipError_t launch_sample(const ChannelTab* cts, const ProcessTab* pts, const double* grids, const int64_t* grid_off,
-                         const int32_t* chan_nb, const SampleCall& call, int max_slots, size_t lds_bytes,
+                         const int32_t* chan_nb, const SampleCall& call, int max_slots, int max_inv, int kinds,
+                         size_t lds_bytes,
                          uint64_t seed, uint64_t sid, uint64_t ctr_off, int np, int64_t N, double* p, double* x1x2,
                          double* w, int32_t* chan, double* tile_stats, double* stats, int grid, hipStream_t s);
 

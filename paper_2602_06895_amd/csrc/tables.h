@@ -8,6 +8,12 @@
 // momentum slot of every particle.  Every lane of a wave runs the same
 // channel, so kernels read these tables with scalar loads and index the
 // per-event register file with wave-uniform slot numbers.
+//
+// Slots are tied to the operation that writes them, so every write has an
+// index known at compile time: 2->2 block b writes slots 2b, 2b + 1 from the
+// bottom; decay d writes slots NS - 2 - 2d, NS - 1 - 2d from the top of an
+// NS-slot file.  A slot code c >= 0 names bottom slot c, c < 0 names top
+// slot NS + c, so the tables do not depend on the kernel's NS.
 #pragma once
 
 #include <stdint.h>
@@ -16,7 +22,7 @@ namespace msx {
 
 constexpr int kMaxFinal = 8;        // final-state particles per process
 constexpr int kMaxInv = 8;          // s-hat plus time-like invariants per channel
-constexpr int kMaxSlots = 16;       // momentum slots per event
+constexpr int kMaxSlots = 2 * (kMaxFinal - 1);  // momentum slots per event
 constexpr int kMaxDims = 32;        // random dimensions per channel
 constexpr int kMaxUniq = 16;        // distinct propagator invariants per process
 constexpr int kMaxChanPerProc = 32; // channels per process (local weights)
@@ -69,20 +75,19 @@ struct InvSpec {
 struct BlockSpec {
     MassSrc m1, m2;
     MapParams tmap;  // |t| mapping: G_nu with the massless auxiliary pole
-    int32_t side;    // 0: leg next to A (slot1 <- p1, p_A -= p1); 1: next to B
-                     // (slot2 <- p2, p_B -= p2); 2: last block (both stored)
-    int32_t slot1, slot2;
+    int32_t side;    // 0: p1 is a leg next to A (p_A -= p1); 1: p2 is a leg next
+                     // to B (p_B -= p2); 2: last block (both outputs are legs)
     int32_t com;     // p_A, p_B are the incoming partons in their CM frame
     int32_t m0_inv;  // (p_A + p_B)^2 = s[m0_inv] (s-hat or the previous t-channel invariant)
-    int32_t pad;
 };
 
 // One (phi, theta) two-body decay (section 2.2.3).
 struct DecaySpec {
-    int32_t parent_slot;  // -1: parent at rest in the partonic frame
+    int32_t parent_rest;  // 1: parent at rest in the partonic frame (no boost)
+    int32_t parent_slot;  // slot code of the parent momentum otherwise
     int32_t parent_inv;   // m0^2 = s[parent_inv]
+    int32_t pad;
     MassSrc m1, m2;
-    int32_t slot1, slot2;
 };
 
 struct ChannelTab {
@@ -94,13 +99,13 @@ struct ChannelTab {
     int32_t n_decays;
     int32_t hadronic;
     int32_t alpha_index; // position of this channel within its process
-    int32_t n_slots;
-    int32_t pad;
+    int32_t n_slots;     // 2 (n_blocks + n_decays) = 2 (n_final - 1)
+    int32_t kinds;       // map kinds used (bitmask, see chain.h)
     double jac_const;    // (2 pi)^(4 - 3 n) times the channel constant
     InvSpec inv[kMaxInv];
     BlockSpec blk[kMaxFinal];
     DecaySpec dec[kMaxFinal];
-    int32_t final_slot[kMaxFinal];
+    int32_t final_slot[kMaxFinal];  // slot code of each final-state particle
 };
 
 // Integrand and local channel weights of one process.
@@ -112,7 +117,7 @@ struct ProcessTab {
     int32_t n_fprop;     // integrand propagator factors
     int32_t pdf;         // toy PDF on both momentum fractions
     int32_t ang;         // -1, or particle index for 1 + cos^2 theta
-    int32_t pad;
+    int32_t pdf_b_int;   // pdf_b when it is an integer 1..16, else 0
     double s_lab;
     double pdf_a, pdf_b;
     double pt_min2;      // <= 0: no cut

@@ -56,8 +56,9 @@ def cpu_baseline(desc, grids, counts, seed, min_seconds=10.0):
                       f"GPU's proportions, frozen grids), {elapsed:.1f} s on {threads} threads"}
 
 
-KERNEL_SOURCES = ["paper_2602_06895_amd/csrc/kernels.hip", "paper_2602_06895_amd/csrc/chain.h",
-                  "paper_2602_06895_amd/csrc/tables.h"]
+# sources of the fused sample kernel (a change invalidates the committed counter figures)
+KERNEL_SOURCES = ["paper_2602_06895_amd/csrc/" + f for f in
+                  ("chain_kernels.h", "chain.h", "device_util.h", "tables.h", "chain_f64_s.hip")]
 PROFILE = os.path.join(ROOT, "profiles", "k_sample_pp4j_1e7.txt")
 
 

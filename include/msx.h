@@ -85,7 +85,18 @@ typedef enum {
 
 typedef struct msx_ctx msx_ctx;
 
-enum { MSX_FP64 = 0 };
+/* Arithmetic of the mapping chain (msx_create_channels `precision`).
+ *  MSX_FP64:  every step in FP64.
+ *  MSX_MIXED: the well-conditioned transcendentals of the chain -- the power
+ *             laws of the G_nu maps (eq. prop_stable_nu), exp/log of the
+ *             luminosity map (eq. pdf_sampling) and of the log maps, the
+ *             azimuth/polar sines and cosines of the 2->2 blocks and decays,
+ *             the toy-PDF powers -- in FP32.  Kallen functions, x - m^2, the
+ *             t range, the s-channel mass bounds, square roots of invariants,
+ *             the Breit-Wigner map (eq. prop_massive), every boost and the
+ *             Jacobian product stay FP64.  Output layout and types are the
+ *             same as for MSX_FP64. */
+enum { MSX_FP64 = 0, MSX_MIXED = 1 };
 
 /* Metadata keys for msx_get_meta (integer keys, in the spirit of the UMAMI
  * interface of section 3.3). `index` selects a channel where noted. */
@@ -97,7 +108,10 @@ enum {
     MSX_META_VEGAS_BINS = 4,   /* bins per dimension of channel `index` */
     MSX_META_MAX_MOMENTA = 5,  /* largest np over all channels */
     MSX_META_PROCESS = 6,      /* process index of channel `index` */
-    MSX_META_DEVICE = 7        /* HIP device ordinal of the context */
+    MSX_META_DEVICE = 7,       /* HIP device ordinal of the context */
+    MSX_META_PRECISION = 8,    /* MSX_FP64 or MSX_MIXED */
+    MSX_META_EVENTS_PER_THREAD = 9, /* sample launch shape: events per thread per tile */
+    MSX_META_GRID = 10         /* sample launch shape: workgroups of the persistent grid */
 };
 
 /* Text of the last error on this context (or of the last failed create when
@@ -107,7 +121,8 @@ const char* msx_last_error(const msx_ctx* ctx);
 /* Parse the process description, compile every channel into its device
  * table (section 2.2: recursive decomposition, s- and t-channel orders),
  * upload tables and uniform VEGAS grids to device `device`.  `precision`
- * must be MSX_FP64.  On success *out owns all device state. */
+ * is MSX_FP64 or MSX_MIXED (else MSX_ERR_ARG).  On success *out owns all
+ * device state. */
 msx_status msx_create_channels(const char* process_json, int32_t precision, int32_t device,
                                msx_ctx** out);
 
@@ -150,6 +165,49 @@ msx_status msx_weight(msx_ctx* ctx, int32_t channel, int64_t n, const double* p,
 msx_status msx_sample(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id,
                       uint64_t counter_offset, double* p, double* x1x2, double* w, int32_t* chan,
                       void* stream);
+
+/* msx_sample with its parameters in device memory, for launches captured in
+ * a HIP graph and replayed with new values: counts [n_channels] (int64) and
+ * counter_offset (one uint64) are read by the device when the launch runs.
+ * Outputs have room for `capacity` events: p [4][max_np][capacity], x1x2
+ * [2][capacity] (required if any channel is hadronic), w, chan [capacity];
+ * events fill positions 0 .. sum(counts) - 1.  If a count is negative or the
+ * total exceeds capacity, nothing is sampled and *status (device int32,
+ * optional) is set to 1, else 0.  The channel lookup and register class cover
+ * all channels of the context.  Statistics accumulate as for msx_sample.  The
+ * first call allocates scratch sized for `capacity`; capture it only after a
+ * call of the same capacity (msx_sample_graph_create does this itself). */
+msx_status msx_sample_device(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id,
+                             const uint64_t* counter_offset, int64_t capacity, double* p, double* x1x2,
+                             double* w, int32_t* chan, int32_t* status, void* stream);
+
+/* A captured, instantiated HIP graph of one msx_sample_device launch (the
+ * persistent fused kernel of all channels plus its statistics pass).  Launch
+ * it any number of times after writing new counts / counter offset to the
+ * device buffers it was created with; those buffers and the context must
+ * outlive the graph.  The graph owns its call table and tile scratch; it
+ * adds to the context's statistics, so launches that overlap with other
+ * sample calls of the same context race on them. */
+typedef struct msx_graph msx_graph;
+msx_status msx_sample_graph_create(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id,
+                                   const uint64_t* counter_offset, int64_t capacity, double* p,
+                                   double* x1x2, double* w, int32_t* chan, int32_t* status,
+                                   msx_graph** out);
+msx_status msx_graph_launch(msx_graph* graph, void* stream);
+msx_status msx_graph_destroy(msx_graph* graph);
+
+/* Launch shape of the fused sample kernel: events per thread per tile (1..64)
+ * and workgroups of the persistent grid (0: 8 per compute unit).  Per-event
+ * results are independent of the shape; per-channel statistics are summed in
+ * a shape-dependent order. */
+msx_status msx_set_launch(msx_ctx* ctx, int32_t events_per_thread, int32_t grid);
+
+/* Time msx_sample on `counts` (host) for each candidate launch shape
+ * (events per thread 1, 2, 4; 2, 4, 8, 16 workgroups per compute unit),
+ * `reps` timed launches each, and keep the fastest (msx_set_launch).  Uses
+ * its own output scratch; the context's statistics are left unchanged.
+ * Synchronises the device.  *best_ms (optional) gets the time per launch. */
+msx_status msx_autotune(msx_ctx* ctx, const int64_t* counts, uint64_t seed, int32_t reps, double* best_ms);
 
 /* Copy the accumulated per-channel statistics to host out [n_channels][5]:
  * (sum w, sum w^2, n, n with w == 0, max w).  Synchronises `stream`. */

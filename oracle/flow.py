@@ -239,24 +239,6 @@ class Flow:
         return float(L.detach()), g.detach()
 
 
-def init_params(dims: int, layers: int, bins: int, hidden: int, gen) -> torch.Tensor:
-    """Starting point of training: hidden layers uniform in +-1/sqrt(fan_in),
-    the last layer zero (so the flow starts as the identity).  `gen` is a
-    numpy Generator (an input, drawn by the caller)."""
-    f = Flow(dims, layers, bins, hidden)
-    out = []
-    for layer in range(layers):
-        for i, s in enumerate(f.shapes):
-            n = math.prod(s)
-            if i >= 6:
-                out.append(torch.zeros(n, dtype=DT))
-            else:
-                fan_in = s[1] if len(s) == 2 else f.shapes[i - 1][1]
-                lim = 1.0 / math.sqrt(fan_in)
-                out.append(torch.as_tensor(gen.uniform(-lim, lim, n), dtype=DT))
-    return torch.cat(out)
-
-
 class Adam:
     """Adam with bias correction (Kingma and Ba 2015)."""
 

@@ -16,14 +16,20 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmsx.so")
 
-FP64 = 0
+FP64, MIXED = 0, 1
 META_N_CHANNELS, META_DIMS, META_N_MOMENTA, META_HADRONIC = 0, 1, 2, 3
-META_VEGAS_BINS, META_MAX_MOMENTA, META_PROCESS, META_DEVICE = 4, 5, 6, 7
+META_VEGAS_BINS, META_MAX_MOMENTA, META_PROCESS, META_DEVICE, META_PRECISION = 4, 5, 6, 7, 8
+META_EVENTS_PER_THREAD, META_GRID = 9, 10
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_DEVICE", 3: "ERR_OOM", 4: "ERR_UNSUPPORTED", 5: "ERR_STATE"}
 
 EXPORTS = ["msx_last_error", "msx_create_channels", "msx_destroy", "msx_get_meta", "msx_uniform", "msx_map",
            "msx_weight", "msx_sample", "msx_stats", "msx_reset_stats", "msx_vegas_accumulate",
-           "msx_vegas_update", "msx_get_grid", "msx_set_grid", "msx_unweight_eff"]
+           "msx_vegas_update", "msx_get_grid", "msx_set_grid", "msx_unweight_eff",
+           "msx_flow_last_error", "msx_flow_create", "msx_flow_destroy", "msx_flow_param_count",
+           "msx_flow_set_params", "msx_flow_get_params", "msx_flow_forward", "msx_flow_inverse",
+           "msx_flow_gradient", "msx_flow_train_step", "msx_flow_sample", "msx_sample_device",
+           "msx_sample_graph_create", "msx_graph_launch", "msx_graph_destroy", "msx_set_launch", "msx_autotune"]
+FLOW_BF16, FLOW_FP32 = 0, 1
 
 
 class MsxError(RuntimeError):
@@ -60,6 +66,23 @@ def load_library(path: str = LIB_PATH):
         "msx_get_grid": ([vp, i32, vp], C.c_int),
         "msx_set_grid": ([vp, i32, vp], C.c_int),
         "msx_unweight_eff": ([vp, vp, i64, dbl, C.POINTER(dbl), C.POINTER(dbl), vp], C.c_int),
+        "msx_sample_device": ([vp, vp, u64, u64, vp, i64, vp, vp, vp, vp, vp, vp], C.c_int),
+        "msx_sample_graph_create": ([vp, vp, u64, u64, vp, i64, vp, vp, vp, vp, vp, C.POINTER(vp)], C.c_int),
+        "msx_graph_launch": ([vp, vp], C.c_int),
+        "msx_graph_destroy": ([vp], C.c_int),
+        "msx_set_launch": ([vp, i32, i32], C.c_int),
+        "msx_autotune": ([vp, vp, u64, i32, C.POINTER(dbl)], C.c_int),
+        "msx_flow_last_error": ([vp], C.c_char_p),
+        "msx_flow_create": ([i32, i32, i32, i32, i32, i32, C.POINTER(vp)], C.c_int),
+        "msx_flow_destroy": ([vp], C.c_int),
+        "msx_flow_param_count": ([vp, C.POINTER(i64)], C.c_int),
+        "msx_flow_set_params": ([vp, vp, i64], C.c_int),
+        "msx_flow_get_params": ([vp, vp, i64], C.c_int),
+        "msx_flow_forward": ([vp, i64, vp, vp, vp, vp], C.c_int),
+        "msx_flow_inverse": ([vp, i64, vp, vp, vp, vp], C.c_int),
+        "msx_flow_gradient": ([vp, i64, vp, vp, vp, vp, vp, vp], C.c_int),
+        "msx_flow_train_step": ([vp, i64, vp, vp, vp, C.c_float, vp, vp], C.c_int),
+        "msx_flow_sample": ([vp, vp, i32, i64, u64, u64, u64, vp, vp, vp, vp, vp, vp, vp], C.c_int),
     }
     for name, (args, res) in sigs.items():
         f = getattr(L, name)
@@ -101,6 +124,7 @@ class Context:
         self.n_momenta = [self._meta(META_N_MOMENTA, c) for c in range(self.n_channels)]
         self.hadronic = [bool(self._meta(META_HADRONIC, c)) for c in range(self.n_channels)]
         self.nbins = [self._meta(META_VEGAS_BINS, c) for c in range(self.n_channels)]
+        self.precision = self._meta(META_PRECISION, 0)
 
     # -- plumbing ------------------------------------------------------------
     def _check(self, st):
@@ -186,6 +210,40 @@ class Context:
                                       self._stream()))
         return out
 
+    def sample_device(self, counts, seed: int, stream_id: int, counter_offset, out: dict, status=None):
+        """msx_sample_device: counts (int64 [C]) and counter_offset (uint64 [1],
+        stored as int64) are device tensors; out holds buffers of one capacity."""
+        cap = out["w"].shape[0]
+        self._check(self.L.msx_sample_device(self.h, _ptr(counts), seed, stream_id, _ptr(counter_offset), cap,
+                                             _ptr(out["p"]), _ptr(out.get("x1x2")), _ptr(out["w"]),
+                                             _ptr(out.get("chan")), _ptr(status), self._stream()))
+
+    def sample_graph(self, counts, seed: int, stream_id: int, counter_offset, out: dict, status=None):
+        """Capture msx_sample_device into a HIP graph; returns a SampleGraph."""
+        cap = out["w"].shape[0]
+        g = C.c_void_p()
+        self._check(self.L.msx_sample_graph_create(self.h, _ptr(counts), seed, stream_id, _ptr(counter_offset), cap,
+                                                   _ptr(out["p"]), _ptr(out.get("x1x2")), _ptr(out["w"]),
+                                                   _ptr(out.get("chan")), _ptr(status), C.byref(g)))
+        return SampleGraph(self, g, (counts, counter_offset, out, status))
+
+    def sample_buffers(self, capacity: int, want_chan: bool = True) -> dict:
+        return {"p": self._empty(4, self.max_momenta, capacity), "w": self._empty(capacity),
+                "x1x2": self._empty(2, capacity) if any(self.hadronic) else None,
+                "chan": self._empty(capacity, dtype=self.torch.int32) if want_chan else None}
+
+    def set_launch(self, events_per_thread: int, grid: int = 0):
+        self._check(self.L.msx_set_launch(self.h, events_per_thread, grid))
+
+    def launch_shape(self):
+        return self._meta(META_EVENTS_PER_THREAD, 0), self._meta(META_GRID, 0)
+
+    def autotune(self, counts, seed: int = 1, reps: int = 3) -> float:
+        c = np.ascontiguousarray(counts, dtype=np.int64)
+        ms = C.c_double()
+        self._check(self.L.msx_autotune(self.h, c.ctypes.data, seed, reps, C.byref(ms)))
+        return ms.value
+
     def stats(self) -> np.ndarray:
         out = np.zeros((self.n_channels, 5))
         self._check(self.L.msx_stats(self.h, out.ctypes.data, self._stream()))
@@ -222,6 +280,138 @@ class Context:
         self._check(self.L.msx_unweight_eff(self.h, _ptr(w.contiguous()), w.shape[0], overweight, C.byref(eff),
                                             C.byref(wmax), self._stream()))
         return eff.value, wmax.value
+
+
+class SampleGraph:
+    """An instantiated HIP graph of one device-count sample launch; keeps the
+    buffers it was captured with alive."""
+
+    def __init__(self, ctx: Context, handle, buffers):
+        self.ctx, self.h, self._buffers = ctx, handle, buffers
+
+    def launch(self):
+        self.ctx._check(self.ctx.L.msx_graph_launch(self.h, self.ctx._stream()))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.L.msx_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Flow:
+    """Rational-quadratic spline coupling flow on one GPU (include/msx_flow.h).
+
+    Event arrays are float32 [d][n] CUDA tensors; parameters are a flat float32
+    vector in the layout the header documents."""
+
+    def __init__(self, dims: int, layers: int = 8, bins: int = 16, hidden: int = 128, mlp: int = FLOW_BF16,
+                 device: int = 0):
+        import torch
+
+        self.torch = torch
+        self.L = load_library()
+        h = C.c_void_p()
+        st = self.L.msx_flow_create(dims, layers, bins, hidden, mlp, device, C.byref(h))
+        if st != 0:
+            raise MsxError(st, self.L.msx_flow_last_error(None).decode())
+        self.h = h
+        self.dims, self.layers, self.bins, self.hidden, self.mlp = dims, layers, bins, hidden, mlp
+        self.device = torch.device("cuda", device)
+        n = C.c_int64()
+        self._check(self.L.msx_flow_param_count(self.h, C.byref(n)))
+        self.n_params = n.value
+
+    def _check(self, st):
+        if st != 0:
+            raise MsxError(st, self.L.msx_flow_last_error(self.h).decode())
+
+    def _stream(self):
+        return self.torch.cuda.current_stream(self.device).cuda_stream
+
+    def _events(self, t, name):
+        if t.dim() != 2 or t.shape[0] != self.dims or t.dtype != self.torch.float32 or t.device != self.device:
+            raise ValueError(f"{name} must be a float32 [{self.dims}][n] tensor on {self.device}")
+        return t.contiguous()
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.msx_flow_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.shape != (self.n_params,):
+            raise ValueError(f"expected {self.n_params} parameters")
+        self._check(self.L.msx_flow_set_params(self.h, p.ctypes.data, p.shape[0]))
+
+    def get_params(self) -> np.ndarray:
+        p = np.empty(self.n_params, dtype=np.float32)
+        self._check(self.L.msx_flow_get_params(self.h, p.ctypes.data, p.shape[0]))
+        return p
+
+    def forward(self, u):
+        u = self._events(u, "u")
+        n = u.shape[1]
+        y = self.torch.empty_like(u)
+        ld = self.torch.empty(n, dtype=self.torch.float32, device=self.device)
+        self._check(self.L.msx_flow_forward(self.h, n, _ptr(u), _ptr(y), _ptr(ld), self._stream()))
+        return y, ld
+
+    def inverse(self, y):
+        y = self._events(y, "y")
+        n = y.shape[1]
+        u = self.torch.empty_like(y)
+        lq = self.torch.empty(n, dtype=self.torch.float32, device=self.device)
+        self._check(self.L.msx_flow_inverse(self.h, n, _ptr(y), _ptr(u), _ptr(lq), self._stream()))
+        return u, lq
+
+    def _batch(self, y, wfj, logq_old):
+        y = self._events(y, "y")
+        n = y.shape[1]
+        if wfj.shape != (n,) or wfj.dtype != self.torch.float64 or logq_old.shape != (n,) or \
+                logq_old.dtype != self.torch.float32:
+            raise ValueError("wfj must be float64 [n] and logq_old float32 [n]")
+        return y, wfj.contiguous(), logq_old.contiguous(), n
+
+    def gradient(self, y, wfj, logq_old):
+        y, wfj, lqo, n = self._batch(y, wfj, logq_old)
+        g = self.torch.empty(self.n_params, dtype=self.torch.float32, device=self.device)
+        loss = self.torch.empty(1, dtype=self.torch.float64, device=self.device)
+        self._check(self.L.msx_flow_gradient(self.h, n, _ptr(y), _ptr(wfj), _ptr(lqo), _ptr(g), _ptr(loss),
+                                             self._stream()))
+        return g, loss
+
+    def train_step(self, y, wfj, logq_old, lr: float = 1e-3):
+        y, wfj, lqo, n = self._batch(y, wfj, logq_old)
+        loss = self.torch.empty(1, dtype=self.torch.float64, device=self.device)
+        self._check(self.L.msx_flow_train_step(self.h, n, _ptr(y), _ptr(wfj), _ptr(lqo), lr, _ptr(loss),
+                                               self._stream()))
+        return loss
+
+    def sample(self, ctx: "Context", channel: int, n: int, seed: int, stream_id: int = 0, counter_offset: int = 0):
+        ctx._check_channel(channel)
+        t = self.torch
+        np_ = ctx.n_momenta[channel]
+        out = {"y": t.empty(self.dims, n, dtype=t.float32, device=self.device),
+               "logq": t.empty(n, dtype=t.float32, device=self.device),
+               "p": ctx._empty(4, np_, n), "x1x2": ctx._empty(2, n) if ctx.hadronic[channel] else None,
+               "wfj": ctx._empty(n), "w": ctx._empty(n)}
+        self._check(self.L.msx_flow_sample(self.h, ctx.h, channel, n, seed, stream_id, counter_offset,
+                                           _ptr(out["y"]), _ptr(out["logq"]), _ptr(out["p"]), _ptr(out["x1x2"]),
+                                           _ptr(out["wfj"]), _ptr(out["w"]), self._stream()))
+        return out
 
 
 def adapt_vegas(ctx: Context, n_per_channel: int, iterations: int, alpha: float = 0.5, seed: int = 1,

@@ -19,6 +19,7 @@ using namespace msx;
 struct msx_ctx {
     int device = 0;
     int cu_count = 256;
+    int mixed = 0;  // MSX_MIXED: FP32 transcendentals in the mapping chain
     Compiled comp;
     std::string err;
     // device tables
@@ -43,6 +44,24 @@ struct msx_ctx {
     int64_t vpart_cap = 0;
     double* d_unw = nullptr;  // 2 * 4096 buckets + 2 * 1024 partials + 2
     size_t lds_max = 0;
+    SampleCall* d_call = nullptr;  // call table of the last sample launch
+    // launch shape of the fused sample kernel (events per thread per tile,
+    // workgroups of the persistent grid; 0 = 8 per compute unit)
+    int ept = 1;
+    int grid = 0;
+    // register / kind class covering every channel (device-count launches)
+    int all_slots = 0, all_inv = 0, all_kinds = 0;
+    bool any_hadronic = false;
+};
+
+struct msx_graph {
+    int device = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    // the graph's own call table and tile scratch (the context's may be
+    // reallocated by later calls)
+    SampleCall* d_call = nullptr;
+    double* d_tile = nullptr;
 };
 
 namespace {
@@ -73,7 +92,7 @@ hipError_t dmalloc(T** p, size_t count) {
 
 void free_all(msx_ctx* c) {
     void* ptrs[] = {c->d_chans, c->d_procs, c->d_grids, c->d_hist, c->d_stats, c->d_grid_off, c->d_chan_nb,
-                    c->d_row_nb, c->d_row_grid, c->d_row_hist, c->d_tile, c->d_vpart, c->d_unw};
+                    c->d_row_nb, c->d_row_grid, c->d_row_hist, c->d_tile, c->d_vpart, c->d_unw, c->d_call};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -83,6 +102,43 @@ bool bad_ctx(const msx_ctx* ctx) { return ctx == nullptr; }
 msx_status set_device(msx_ctx* ctx) {
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return dev_fail(ctx, e, "hipSetDevice");
+    return MSX_OK;
+}
+
+msx_status ensure_tiles(msx_ctx* ctx, int64_t tiles) {
+    if (tiles <= ctx->tile_cap) return MSX_OK;
+    if (ctx->d_tile) MSX_HIP(ctx, hipFree(ctx->d_tile), "hipFree");
+    ctx->d_tile = nullptr;
+    ctx->tile_cap = 0;
+    MSX_HIP(ctx, dmalloc(&ctx->d_tile, 4 * tiles), "tile scratch");
+    ctx->tile_cap = tiles;
+    return MSX_OK;
+}
+
+int sample_grid(const msx_ctx* ctx) { return ctx->grid > 0 ? ctx->grid : ctx->cu_count * 8; }
+
+// Device-count sample: plan kernel, then the fused launch with the register
+// class of all channels.  Enqueues only (safe to capture).
+int64_t device_max_tiles(const msx_ctx* ctx, int64_t capacity) {
+    const int64_t T = (int64_t)sample_block() * ctx->ept;
+    return (capacity + T - 1) / T + (int64_t)ctx->comp.chans.size();
+}
+
+// Device-count sample: plan kernel, then the fused launch with the register
+// class of all channels.  Enqueues only (safe to capture).  d_tile must hold
+// 4 * device_max_tiles(capacity) doubles.
+msx_status sample_device(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id,
+                         const uint64_t* counter_offset, int64_t capacity, double* p, double* x1x2, double* w,
+                         int32_t* chan, int32_t* status, SampleCall* d_call, double* d_tile, hipStream_t s) {
+    const int C = (int)ctx->comp.chans.size();
+    const int64_t max_tiles = device_max_tiles(ctx, capacity);
+    MSX_HIP(ctx, launch_plan(counts, C, capacity, ctx->ept, d_call, status, s), "sample plan");
+    const int grid = (int)std::min<int64_t>(max_tiles, sample_grid(ctx));
+    MSX_HIP(ctx,
+            launch_sample(ctx->d_chans, ctx->d_procs, ctx->d_grids, ctx->d_grid_off, ctx->d_chan_nb, d_call, C,
+                          ctx->all_slots, ctx->all_inv, ctx->all_kinds, ctx->mixed, ctx->lds_max, seed, stream_id,
+                          counter_offset, 0, ctx->max_np, capacity, p, x1x2, w, chan, d_tile, ctx->d_stats, grid, s),
+            "sample launch");
     return MSX_OK;
 }
 
@@ -102,11 +158,13 @@ msx_status msx_create_channels(const char* process_json, int32_t precision, int3
     if (!out) return fail(nullptr, MSX_ERR_ARG, "out is NULL");
     *out = nullptr;
     if (!process_json) return fail(nullptr, MSX_ERR_ARG, "process_json is NULL");
-    if (precision != MSX_FP64) return fail(nullptr, MSX_ERR_UNSUPPORTED, "only MSX_FP64 is supported");
+    if (precision != MSX_FP64 && precision != MSX_MIXED)
+        return fail(nullptr, MSX_ERR_ARG, "precision must be MSX_FP64 or MSX_MIXED");
     JValue root;
     std::string err;
     if (!parse_json(process_json, root, err)) return fail(nullptr, MSX_ERR_ARG, "JSON: " + err);
     msx_ctx* c = new msx_ctx();
+    c->mixed = precision == MSX_MIXED ? 1 : 0;
     if (!compile_processes(root, c->comp, err)) {
         delete c;
         return fail(nullptr, MSX_ERR_ARG, "process description: " + err);
@@ -143,6 +201,10 @@ msx_status msx_create_channels(const char* process_json, int32_t precision, int3
         c->hist_total += (int64_t)m.dims * m.nbins;
         c->max_np = std::max(c->max_np, m.n_momenta);
         c->lds_max = std::max(c->lds_max, sizeof(double) * (size_t)m.dims * (m.nbins + 1));
+        c->all_slots = std::max(c->all_slots, c->comp.chans[ch].n_slots);
+        c->all_inv = std::max(c->all_inv, c->comp.chans[ch].n_inv);
+        c->all_kinds |= c->comp.chans[ch].kinds;
+        c->any_hadronic = c->any_hadronic || m.hadronic;
     }
     c->grid_total = (int64_t)grids.size();
     c->n_rows = (int)row_nb.size();
@@ -153,7 +215,7 @@ msx_status msx_create_channels(const char* process_json, int32_t precision, int3
         (e = dmalloc(&c->d_chan_nb, C)) != hipSuccess || (e = dmalloc(&c->d_row_nb, row_nb.size())) != hipSuccess ||
         (e = dmalloc(&c->d_row_grid, row_grid.size())) != hipSuccess ||
         (e = dmalloc(&c->d_row_hist, row_hist.size())) != hipSuccess ||
-        (e = dmalloc(&c->d_unw, 2 * 4096 + 2 * 1024 + 2)) != hipSuccess ||
+        (e = dmalloc(&c->d_unw, 2 * 4096 + 2 * 1024 + 2)) != hipSuccess || (e = dmalloc(&c->d_call, 1)) != hipSuccess ||
         (e = up(c->d_chans, c->comp.chans.data(), sizeof(ChannelTab) * C)) != hipSuccess ||
         (e = up(c->d_procs, c->comp.procs.data(), sizeof(ProcessTab) * c->comp.procs.size())) != hipSuccess ||
         (e = up(c->d_grids, grids.data(), sizeof(double) * grids.size())) != hipSuccess ||
@@ -197,6 +259,9 @@ msx_status msx_get_meta(const msx_ctx* ctx, int32_t key, int32_t index, int64_t*
         case MSX_META_N_CHANNELS: *value = C; return MSX_OK;
         case MSX_META_MAX_MOMENTA: *value = ctx->max_np; return MSX_OK;
         case MSX_META_DEVICE: *value = ctx->device; return MSX_OK;
+        case MSX_META_PRECISION: *value = ctx->mixed ? MSX_MIXED : MSX_FP64; return MSX_OK;
+        case MSX_META_EVENTS_PER_THREAD: *value = ctx->ept; return MSX_OK;
+        case MSX_META_GRID: *value = sample_grid(ctx); return MSX_OK;
         case MSX_META_DIMS: return chan(index >= 0 && index < C ? ctx->comp.meta[index].dims : 0);
         case MSX_META_N_MOMENTA: return chan(index >= 0 && index < C ? ctx->comp.meta[index].n_momenta : 0);
         case MSX_META_HADRONIC: return chan(index >= 0 && index < C ? ctx->comp.meta[index].hadronic : 0);
@@ -232,7 +297,7 @@ msx_status msx_map(msx_ctx* ctx, int32_t channel, int64_t n, const double* y, do
     const ProcessTab& pt = ctx->comp.procs[m.process];
     MSX_HIP(ctx,
             launch_map(ctx->d_chans + channel, ctx->d_procs + m.process, ctx->d_grids + ctx->grid_off[channel], m.nbins,
-                       m.dims, t.n_slots, t.n_inv, t.kinds, pt.s_lab, m.n_momenta, n, y, p, x1x2, jac, w,
+                       m.dims, t.n_slots, t.n_inv, t.kinds, ctx->mixed, pt.s_lab, m.n_momenta, n, y, p, x1x2, jac, w,
                        ctx->cu_count,
                        (hipStream_t)stream),
             "map launch");
@@ -250,7 +315,7 @@ msx_status msx_weight(msx_ctx* ctx, int32_t channel, int64_t n, const double* p,
     if (n == 0) return MSX_OK;
     if (msx_status st = set_device(ctx)) return st;
     MSX_HIP(ctx,
-            launch_weight(ctx->d_chans + channel, ctx->d_procs + m.process, m.n_momenta, n, p, x1x2, jac, w, alpha,
+            launch_weight(ctx->d_chans + channel, ctx->d_procs + m.process, ctx->mixed, m.n_momenta, n, p, x1x2, jac, w, alpha,
                           (hipStream_t)stream),
             "weight launch");
     return MSX_OK;
@@ -264,7 +329,8 @@ msx_status msx_sample(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64
     SampleCall call;
     std::memset(&call, 0, sizeof call);
     call.n_chan = C;
-    const int T = sample_tile_size();
+    call.ept = ctx->ept;
+    const int64_t T = (int64_t)sample_block() * ctx->ept;
     int64_t N = 0, tiles = 0;
     bool any_hadronic = false;
     int max_slots = 0, max_inv = 0, kinds = 0;
@@ -290,19 +356,188 @@ msx_status msx_sample(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64
     if (!p || !w) return fail(ctx, MSX_ERR_ARG, "p and w are required");
     if (any_hadronic && !x1x2) return fail(ctx, MSX_ERR_ARG, "x1x2 is required when a sampled channel is hadronic");
     if (msx_status st = set_device(ctx)) return st;
-    if (tiles > ctx->tile_cap) {
-        if (ctx->d_tile) MSX_HIP(ctx, hipFree(ctx->d_tile), "hipFree");
-        ctx->d_tile = nullptr;
-        ctx->tile_cap = 0;
-        MSX_HIP(ctx, dmalloc(&ctx->d_tile, 4 * tiles), "tile scratch");
-        ctx->tile_cap = tiles;
-    }
-    int grid = ctx->cu_count * 8;
+    if (msx_status st = ensure_tiles(ctx, tiles)) return st;
+    hipStream_t s = (hipStream_t)stream;
+    MSX_HIP(ctx, launch_set_call(call, ctx->d_call, s), "sample call table");
+    const int grid = (int)std::min<int64_t>(tiles, sample_grid(ctx));
     MSX_HIP(ctx,
-            launch_sample(ctx->d_chans, ctx->d_procs, ctx->d_grids, ctx->d_grid_off, ctx->d_chan_nb, call, max_slots,
-                          max_inv, kinds, ctx->lds_max, seed, stream_id, counter_offset, ctx->max_np, N, p, x1x2, w, chan, ctx->d_tile,
-                          ctx->d_stats, grid, (hipStream_t)stream),
+            launch_sample(ctx->d_chans, ctx->d_procs, ctx->d_grids, ctx->d_grid_off, ctx->d_chan_nb, ctx->d_call, C,
+                          max_slots, max_inv, kinds, ctx->mixed, ctx->lds_max, seed, stream_id, nullptr,
+                          counter_offset, ctx->max_np, N, p, x1x2, w, chan, ctx->d_tile, ctx->d_stats, grid, s),
             "sample launch");
+    return MSX_OK;
+}
+
+msx_status msx_sample_device(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id,
+                             const uint64_t* counter_offset, int64_t capacity, double* p, double* x1x2, double* w,
+                             int32_t* chan, int32_t* status, void* stream) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (!counts || !counter_offset) return fail(ctx, MSX_ERR_ARG, "counts and counter_offset are required");
+    if (capacity <= 0) return fail(ctx, MSX_ERR_ARG, "capacity must be positive");
+    if (!p || !w) return fail(ctx, MSX_ERR_ARG, "p and w are required");
+    if (ctx->any_hadronic && !x1x2) return fail(ctx, MSX_ERR_ARG, "x1x2 is required (the context has hadronic channels)");
+    if (msx_status st = set_device(ctx)) return st;
+    if (msx_status st = ensure_tiles(ctx, device_max_tiles(ctx, capacity))) return st;
+    return sample_device(ctx, counts, seed, stream_id, counter_offset, capacity, p, x1x2, w, chan, status,
+                         ctx->d_call, ctx->d_tile, (hipStream_t)stream);
+}
+
+msx_status msx_sample_graph_create(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id,
+                                   const uint64_t* counter_offset, int64_t capacity, double* p, double* x1x2,
+                                   double* w, int32_t* chan, int32_t* status, msx_graph** out) {
+    if (!out) return fail(ctx, MSX_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (!counts || !counter_offset) return fail(ctx, MSX_ERR_ARG, "counts and counter_offset are required");
+    if (capacity <= 0) return fail(ctx, MSX_ERR_ARG, "capacity must be positive");
+    if (!p || !w) return fail(ctx, MSX_ERR_ARG, "p and w are required");
+    if (ctx->any_hadronic && !x1x2) return fail(ctx, MSX_ERR_ARG, "x1x2 is required (the context has hadronic channels)");
+    if (msx_status st = set_device(ctx)) return st;
+    // everything the launches need is allocated before the capture
+    msx_graph* g = new msx_graph();
+    g->device = ctx->device;
+    auto drop = [&](msx_graph* q) {
+        if (q->exec) (void)hipGraphExecDestroy(q->exec);
+        if (q->graph) (void)hipGraphDestroy(q->graph);
+        if (q->d_call) (void)hipFree(q->d_call);
+        if (q->d_tile) (void)hipFree(q->d_tile);
+        delete q;
+    };
+    hipError_t e = dmalloc(&g->d_call, 1);
+    if (e == hipSuccess) e = dmalloc(&g->d_tile, (size_t)4 * device_max_tiles(ctx, capacity));
+    if (e != hipSuccess) {
+        drop(g);
+        return dev_fail(ctx, e, "graph scratch");
+    }
+    hipStream_t s = nullptr;
+    if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) {
+        drop(g);
+        return dev_fail(ctx, e, "capture stream");
+    }
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    msx_status st = MSX_OK;
+    if (e == hipSuccess) {
+        st = sample_device(ctx, counts, seed, stream_id, counter_offset, capacity, p, x1x2, w, chan, status, g->d_call,
+                           g->d_tile, s);
+        hipError_t e2 = hipStreamEndCapture(s, &g->graph);
+        if (st == MSX_OK && e2 != hipSuccess) e = e2;
+    }
+    if (e == hipSuccess && st == MSX_OK) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(s);
+    if (e != hipSuccess || st != MSX_OK) {
+        drop(g);
+        return st != MSX_OK ? st : dev_fail(ctx, e, "graph capture");
+    }
+    *out = g;
+    return MSX_OK;
+}
+
+msx_status msx_graph_launch(msx_graph* g, void* stream) {
+    if (!g) return fail(nullptr, MSX_ERR_ARG, "graph is NULL");
+    hipError_t e = hipSetDevice(g->device);
+    if (e == hipSuccess) e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(nullptr, e, "graph launch");
+    return MSX_OK;
+}
+
+msx_status msx_graph_destroy(msx_graph* g) {
+    if (!g) return MSX_OK;
+    (void)hipSetDevice(g->device);
+    (void)hipDeviceSynchronize();
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->d_call) (void)hipFree(g->d_call);
+    if (g->d_tile) (void)hipFree(g->d_tile);
+    delete g;
+    return MSX_OK;
+}
+
+msx_status msx_set_launch(msx_ctx* ctx, int32_t events_per_thread, int32_t grid) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (events_per_thread < 1 || events_per_thread > 64) return fail(ctx, MSX_ERR_ARG, "events_per_thread must be 1..64");
+    if (grid < 0 || grid > (1 << 20)) return fail(ctx, MSX_ERR_ARG, "grid must be 0..2^20");
+    ctx->ept = events_per_thread;
+    ctx->grid = grid;
+    return MSX_OK;
+}
+
+msx_status msx_autotune(msx_ctx* ctx, const int64_t* counts, uint64_t seed, int32_t reps, double* best_ms) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (!counts) return fail(ctx, MSX_ERR_ARG, "counts is NULL");
+    if (reps < 1 || reps > 1000) return fail(ctx, MSX_ERR_ARG, "reps must be 1..1000");
+    const int C = (int)ctx->comp.chans.size();
+    int64_t N = 0;
+    for (int c = 0; c < C; ++c) {
+        if (counts[c] < 0 || counts[c] > INT64_MAX / 4 - N) return fail(ctx, MSX_ERR_ARG, "bad event count");
+        N += counts[c];
+    }
+    if (N == 0) return fail(ctx, MSX_ERR_ARG, "no events to time");
+    if (msx_status st = set_device(ctx)) return st;
+    // scratch outputs for the trial launches
+    double *p = nullptr, *x1x2 = nullptr, *w = nullptr, *stats_save = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        if (p) (void)hipFree(p);
+        if (x1x2) (void)hipFree(x1x2);
+        if (w) (void)hipFree(w);
+        if (stats_save) (void)hipFree(stats_save);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (s) (void)hipStreamDestroy(s);
+    };
+    hipError_t e;
+    if ((e = dmalloc(&p, (size_t)4 * ctx->max_np * N)) != hipSuccess || (e = dmalloc(&x1x2, (size_t)2 * N)) != hipSuccess ||
+        (e = dmalloc(&w, (size_t)N)) != hipSuccess || (e = dmalloc(&stats_save, (size_t)5 * C)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess ||
+        (e = hipMemcpy(stats_save, ctx->d_stats, sizeof(double) * 5 * C, hipMemcpyDeviceToDevice)) != hipSuccess) {
+        cleanup();
+        return dev_fail(ctx, e, "autotune setup");
+    }
+    const int ept_c[] = {1, 2, 4};
+    const int mult_c[] = {2, 4, 8, 16};
+    double best = 1e300;
+    int best_ept = 1, best_grid = 0;
+    const int save_ept = ctx->ept, save_grid = ctx->grid;
+    msx_status st = MSX_OK;
+    for (int ept : ept_c) {
+        for (int mult : mult_c) {
+            ctx->ept = ept;
+            ctx->grid = ctx->cu_count * mult;
+            // one untimed launch, then reps timed ones
+            st = msx_sample(ctx, counts, seed, 0, 0, p, x1x2, w, nullptr, s);
+            for (int r = 0; st == MSX_OK && r < reps; ++r) {
+                if (r == 0) (void)hipEventRecord(e0, s);
+                st = msx_sample(ctx, counts, seed, 0, 0, p, x1x2, w, nullptr, s);
+            }
+            if (st != MSX_OK) break;
+            (void)hipEventRecord(e1, s);
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            const double per = ms / reps;
+            if (per < best) {
+                best = per;
+                best_ept = ept;
+                best_grid = ctx->grid;
+            }
+        }
+        if (st != MSX_OK || e != hipSuccess) break;
+    }
+    ctx->ept = save_ept;
+    ctx->grid = save_grid;
+    if (st == MSX_OK && e == hipSuccess) {
+        // the trial launches accumulated statistics: restore them
+        e = hipMemcpy(ctx->d_stats, stats_save, sizeof(double) * 5 * C, hipMemcpyDeviceToDevice);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+    }
+    cleanup();
+    if (st != MSX_OK) return st;
+    if (e != hipSuccess) return dev_fail(ctx, e, "autotune");
+    ctx->ept = best_ept;
+    ctx->grid = best_grid;
+    if (best_ms) *best_ms = best;
     return MSX_OK;
 }
 

@@ -83,11 +83,44 @@ enum : int {
     KINDS_ALL = 31
 };
 
+// Precision of the well-conditioned transcendentals (power laws, exp, log,
+// angles).  MIX = false: FP64 throughout.  MIX = true: these are evaluated in
+// FP32 on the FP64 argument rounded to float and widened back; everything
+// whose rounding is amplified -- differences near threshold (Kallen
+// functions, x - m^2, the t range, the s-channel mass bounds), square roots of
+// invariants, the Breit-Wigner arctangent / tangent (ill-conditioned off
+// resonance), the boosts and the Jacobian product -- stays FP64.
+template <bool MIX>
+__device__ __forceinline__ double t_exp(double x) {
+    return MIX ? (double)expf((float)x) : exp(x);
+}
+template <bool MIX>
+__device__ __forceinline__ double t_log(double x) {
+    return MIX ? (double)logf((float)x) : log(x);
+}
+template <bool MIX>
+__device__ __forceinline__ double t_pow(double x, double e) {
+    return MIX ? (double)powf((float)x, (float)e) : pow(x, e);
+}
+template <bool MIX>
+__device__ __forceinline__ void t_sincospi(double x, double* s, double* c) {
+    if (MIX) {
+        float sf, cf;
+        sincospif((float)x, &sf, &cf);
+        *s = sf;
+        *c = cf;
+    } else {
+        sincospi(x, s, c);
+    }
+}
+
 // x^(1/k) for x >= 0 and integer k in 2..8: an FP32 estimate refined by two
 // Newton steps on y^k = x in FP64 (error ~1 ulp, a third of the cost of
 // pow).  The exponent is split off first so any double is in range.
+template <bool MIX>
 __device__ __forceinline__ double kth_root(double x, int k) {
     if (!(x > 0.0)) return x == 0.0 ? 0.0 : __builtin_nan("");
+    if (MIX) return (double)exp2f(log2f((float)x) / (float)k);
     int ex;
     double f = frexp(x, &ex);  // x = f 2^ex, f in [0.5, 1)
     int q = ex >= 0 ? ex / k : -((-ex + k - 1) / k);
@@ -105,10 +138,10 @@ __device__ __forceinline__ double kth_root(double x, int k) {
 }
 
 // (x - m2)^e for the power-law maps: a k-th root when e = 1/k.
-template <int KINDS>
+template <int KINDS, bool MIX>
 __device__ __forceinline__ double pow_e(const MapParams& p, double x) {
-    if (!(KINDS & KIND_POW)) return kth_root(x, p.int_pow);
-    return p.int_pow ? kth_root(x, p.int_pow) : pow(x, p.e);
+    if (!(KINDS & KIND_POW)) return kth_root<MIX>(x, p.int_pow);
+    return p.int_pow ? kth_root<MIX>(x, p.int_pow) : t_pow<MIX>(x, p.e);
 }
 
 // b^n for an integer n >= 1 (square and multiply).
@@ -124,21 +157,21 @@ __device__ __forceinline__ double ipow_any(double b, int n) {
 
 // Power-law core: b = r A + (1 - r) B, x - m^2 = b^(1/e), and
 // J = (A - B) (x - m^2)^nu / e with (x - m^2)^nu = (x - m^2) / b.
-template <int KINDS>
+template <int KINDS, bool MIX>
 __device__ __forceinline__ double pow_core(const MapParams& p, double A, double B, double r, double& jac) {
     double b = r * A + (1.0 - r) * B;
-    double xm = (!(KINDS & KIND_POW) || p.int_pow) ? ipow(b, p.int_pow) : pow(b, p.inv_e);
+    double xm = (!(KINDS & KIND_POW) || p.int_pow) ? ipow(b, p.int_pow) : t_pow<MIX>(b, p.inv_e);
     jac = (A - B) * (xm / b) * p.inv_e;
     return xm + p.m2;
 }
 
 // G_nu / G_BW with bounds known only per event.
-template <int KINDS>
+template <int KINDS, bool MIX>
 __device__ __forceinline__ double map_dyn(const MapParams& p, double r, double xmin, double xmax, double& jac) {
     const int kind = p.kind;
     if ((KINDS & (KIND_POW | KIND_POW_INT)) && kind == MAP_POW) {
-        double A = pow_e<KINDS>(p, xmax - p.m2), B = pow_e<KINDS>(p, xmin - p.m2);
-        return pow_core<KINDS>(p, A, B, r, jac);
+        double A = pow_e<KINDS, MIX>(p, xmax - p.m2), B = pow_e<KINDS, MIX>(p, xmin - p.m2);
+        return pow_core<KINDS, MIX>(p, A, B, r, jac);
     }
     if ((KINDS & KIND_BW) && kind == MAP_BW) {
         double u1 = atan((xmin - p.m2) / p.mw), u2 = atan((xmax - p.m2) / p.mw);
@@ -147,8 +180,8 @@ __device__ __forceinline__ double map_dyn(const MapParams& p, double r, double x
         return d + p.m2;
     }
     if ((KINDS & KIND_LOG) && kind == MAP_LOG) {
-        double lmax = log(xmax - p.m2), lmin = log(xmin - p.m2);
-        double xm = exp(r * lmax + (1.0 - r) * lmin);
+        double lmax = t_log<MIX>(xmax - p.m2), lmin = t_log<MIX>(xmin - p.m2);
+        double xm = t_exp<MIX>(r * lmax + (1.0 - r) * lmin);
         jac = xm * (lmax - lmin);
         return xm + p.m2;
     }
@@ -157,11 +190,11 @@ __device__ __forceinline__ double map_dyn(const MapParams& p, double r, double x
 }
 
 // G_nu / G_BW with precomputed static constants (s-hat).
-template <int KINDS>
+template <int KINDS, bool MIX>
 __device__ __forceinline__ double map_static(const InvSpec& iv, double r, double& jac) {
     const MapParams& p = iv.map;
     const int kind = p.kind;
-    if ((KINDS & (KIND_POW | KIND_POW_INT)) && kind == MAP_POW) return pow_core<KINDS>(p, iv.A, iv.B, r, jac);
+    if ((KINDS & (KIND_POW | KIND_POW_INT)) && kind == MAP_POW) return pow_core<KINDS, MIX>(p, iv.A, iv.B, r, jac);
     if ((KINDS & KIND_BW) && kind == MAP_BW) {
         double u2 = iv.A, u1 = iv.B;
         double d = p.mw * tan(u1 + (u2 - u1) * r);
@@ -170,7 +203,7 @@ __device__ __forceinline__ double map_static(const InvSpec& iv, double r, double
     }
     if ((KINDS & KIND_LOG) && kind == MAP_LOG) {
         double lmax = iv.A, lmin = iv.B;
-        double xm = exp(r * lmax + (1.0 - r) * lmin);
+        double xm = t_exp<MIX>(r * lmax + (1.0 - r) * lmin);
         jac = xm * (lmax - lmin);
         return xm + p.m2;
     }
@@ -226,7 +259,7 @@ __device__ __forceinline__ double masked_sum(uint32_t mask, const double (&SQ)[N
 // The mapping chain.  next() returns the VEGAS-mapped random number of the
 // next dimension (dimensions are consumed in order).  Leaves the final-state
 // momenta in the partonic frame in the slots.
-template <int NS, int NI, int KINDS, class Next>
+template <int NS, int NI, int KINDS, bool MIX, class Next>
 __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, double s_lab, Next& next,
                                           double (&E)[NS], double (&X)[NS], double (&Y)[NS], double (&Z)[NS],
                                           double (&S)[NI], double (&SQ)[NI], ChainOut& o) {
@@ -237,7 +270,7 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
     double shat;
     if (hadronic) {
         double j;
-        shat = map_static<KINDS>(ct->inv[0], next(), j);
+        shat = map_static<KINDS, MIX>(ct->inv[0], next(), j);
         jac *= j;
     } else {
         shat = s_lab;
@@ -252,7 +285,7 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
         double mmin = iv.min_const + masked_sum(iv.min_mask, SQ);
         double mmax = SQ[iv.parent] - iv.max_const - masked_sum(iv.max_mask, SQ);
         double j;
-        double s = map_dyn<KINDS>(iv.map, next(), mmin * mmin, mmax * mmax, j);
+        double s = map_dyn<KINDS, MIX>(iv.map, next(), mmin * mmin, mmax * mmax, j);
         jac *= j;
         S[i] = s;
         SQ[i] = sqrt(s);
@@ -262,9 +295,9 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
     double x1 = 1.0, x2 = 1.0, L = 0.0;
     if (hadronic) {
         double r = next();
-        L = log(shat / s_lab);
-        x1 = exp(r * L);
-        x2 = exp((1.0 - r) * L);
+        L = t_log<MIX>(shat / s_lab);
+        x1 = t_exp<MIX>(r * L);
+        x2 = t_exp<MIX>((1.0 - r) * L);
         jac *= -L / s_lab;
     }
 
@@ -302,12 +335,12 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
         double tmin = fmax(0.0, -t_plus);
         double tmax = -t_minus;
         double jt;
-        double abst = map_dyn<KINDS>(bs.tmap, r_t, tmin, tmax, jt);
+        double abst = map_dyn<KINDS, MIX>(bs.tmap, r_t, tmin, tmax, jt);
         double cth = (C - 2.0 * m0sq * (m1s + ma2 + abst)) / R;
         cth = fmin(1.0, fmax(-1.0, cth));
         double sth = sqrt((1.0 - cth) * (1.0 + cth));
         double sphi, cphi;
-        sincospi(2.0 * r_phi, &sphi, &cphi);
+        t_sincospi<MIX>(2.0 * r_phi, &sphi, &cphi);
         double inv_2m0 = 1.0 / (2.0 * m0);
         double q = sqrt(lam12) * inv_2m0;
         double e1 = (m0sq + (m1s - m2s)) * inv_2m0;
@@ -391,7 +424,7 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
         double cth = 2.0 * r_th - 1.0;
         double sth = sqrt((1.0 - cth) * (1.0 + cth));
         double sphi, cphi;
-        sincospi(2.0 * r_phi, &sphi, &cphi);
+        t_sincospi<MIX>(2.0 * r_phi, &sphi, &cphi);
         double k1e = e1, k1x = q * sth * cphi, k1y = q * sth * sphi, k1z = q * cth;
         double k2e = e2, k2x = -k1x, k2y = -k1y, k2z = -k1z;
         if (!ds.parent_rest) {
@@ -445,7 +478,7 @@ __device__ __forceinline__ double inv_q2(const ProcessTab* __restrict__ pt, int 
 }
 
 // Returns alpha * f; *alpha_out receives alpha.  `logtau` = log(x1 x2).
-template <class Get>
+template <bool MIX, class Get>
 __device__ __forceinline__ double integrand_alpha(const ProcessTab* __restrict__ pt, int chan_in_proc, double x1,
                                                   double x2, double logtau, double pae, double pax, double pay,
                                                   double paz, Get get, double& alpha_out) {
@@ -459,10 +492,10 @@ __device__ __forceinline__ double integrand_alpha(const ProcessTab* __restrict__
             b1 = ipow_any(u1, pt->pdf_b_int);
             b2 = ipow_any(u2, pt->pdf_b_int);
         } else {
-            b1 = pow(u1, pt->pdf_b);
-            b2 = pow(u2, pt->pdf_b);
+            b1 = t_pow<MIX>(u1, pt->pdf_b);
+            b2 = t_pow<MIX>(u2, pt->pdf_b);
         }
-        f = exp(pt->pdf_a * logtau) * b1 * b2;
+        f = t_exp<MIX>(pt->pdf_a * logtau) * b1 * b2;
     }
     if (pt->pt_min2 > 0.0) {
         for (int i = 0; i < n; ++i) {

@@ -1,0 +1,6 @@
+// Mapping-chain kernels: 6 momentum slots, 4 invariants, FP64.
+#include "chain_kernels.h"
+
+namespace msx {
+MSX_INSTANTIATE_CHAIN(6, 4, false)
+}  // namespace msx

@@ -1,0 +1,233 @@
+// The mapping-chain kernels (single-channel map and fused multichannel
+// sample) as templates over the register class (NS momentum slots, NI
+// invariants), the compiled map kinds and the precision.  Each instantiation
+// unit includes this header and instantiates launch_chain_class for one
+// (NS, NI, precision); the units compile in parallel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "chain.h"
+#include "device_util.h"
+#include "launch.h"
+
+namespace msx {
+
+// Beam boost, unphysical cut, integrand x channel weight and the stores of one
+// event whose partonic-frame momenta sit in the slots.
+template <int NS, bool MIX>
+__device__ __forceinline__ double finish_event(const ChannelTab* __restrict__ ct, const ProcessTab* __restrict__ pt,
+                                               const ChainOut& o, double jv, double (&E)[NS], double (&X)[NS],
+                                               double (&Y)[NS], double (&Z)[NS], int np, int64_t n, int64_t e,
+                                               double* __restrict__ p, double* __restrict__ x1x2,
+                                               double* __restrict__ jac_out, bool want_w) {
+    const int nf = ct->n_final;
+    const int hadronic = ct->hadronic;
+    double g = 1.0, gb = 0.0;
+    if (hadronic) {
+        double inv = 1.0 / (2.0 * sqrt(o.x1 * o.x2));
+        g = (o.x1 + o.x2) * inv;
+        gb = (o.x1 - o.x2) * inv;
+    }
+    const double h = 0.5 * sqrt(o.shat);
+    bool ok = true;
+    // incoming partons, then final-state particles by label
+    for (int i = 0; i < nf + 2; ++i) {
+        double pe, px, py, pz;
+        if (i < 2) {
+            pe = h;
+            px = 0.0;
+            py = 0.0;
+            pz = i == 0 ? h : -h;
+        } else {
+            int s = slot_index<NS>(ct->final_slot[i - 2]);
+            pe = E[s];
+            px = X[s];
+            py = Y[s];
+            pz = Z[s];
+        }
+        double le = pe, lz = pz;
+        if (hadronic) {
+            le = g * pe + gb * pz;
+            lz = gb * pe + g * pz;
+        }
+        ok = ok && isfinite(le) && isfinite(px) && isfinite(py) && isfinite(lz) && le >= 0.0;
+        p[((int64_t)0 * np + i) * n + e] = le;
+        p[((int64_t)1 * np + i) * n + e] = px;
+        p[((int64_t)2 * np + i) * n + e] = py;
+        p[((int64_t)3 * np + i) * n + e] = lz;
+    }
+    double jac = o.jac * jv;
+    ok = ok && isfinite(jac) && jac > 0.0;
+    if (hadronic) {
+        ok = ok && o.x1 > 0.0 && o.x1 <= 1.0 && o.x2 > 0.0 && o.x2 <= 1.0;
+        if (x1x2) {
+            x1x2[e] = o.x1;
+            x1x2[n + e] = o.x2;
+        }
+    }
+    if (!ok) jac = 0.0;
+    if (jac_out) jac_out[e] = jac;
+    double w = 0.0;
+    if (want_w && ok) {
+        double alpha;
+        auto get = [&](int k, int c) -> double {
+            int s = slot_index<NS>(ct->final_slot[k]);
+            return c == 0 ? E[s] : (c == 1 ? X[s] : (c == 2 ? Y[s] : Z[s]));
+        };
+        double af = integrand_alpha<MIX>(pt, ct->alpha_index, o.x1, o.x2, o.logtau, h, 0.0, 0.0, h, get, alpha);
+        w = af * jac;
+    }
+    return w;
+}
+
+template <int NS, int NI, int KINDS, bool MIX>
+__global__ __launch_bounds__(kBlock) void k_map(const ChannelTab* __restrict__ ct, const ProcessTab* __restrict__ pt,
+                                                const double* __restrict__ grid, int nb, double s_lab, int np,
+                                                int64_t n, const double* __restrict__ y, double* __restrict__ p,
+                                                double* __restrict__ x1x2, double* __restrict__ jac,
+                                                double* __restrict__ w) {
+    extern __shared__ double lg[];
+    const int dims = ct->dims;
+    for (int i = threadIdx.x; i < dims * (nb + 1); i += blockDim.x) lg[i] = grid[i];
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        int k = 0;
+        double jv = 1.0;
+        auto next = [&]() -> double {
+            double r = vegas_map(y[(int64_t)k * n + e], lg + k * (nb + 1), nb, jv);
+            ++k;
+            return r;
+        };
+        double E[NS], X[NS], Y[NS], Z[NS], S[NI], SQ[NI];
+        ChainOut o;
+        run_chain<NS, NI, KINDS, MIX>(ct, s_lab, next, E, X, Y, Z, S, SQ, o);
+        double wv = finish_event<NS, MIX>(ct, pt, o, jv, E, X, Y, Z, np, n, e, p, x1x2, jac, w != nullptr);
+        if (w) w[e] = wv;
+    }
+}
+
+// All channels in one persistent launch.  The call table (per-channel tile
+// and event ranges, events per thread) is read from device memory, so a
+// captured graph can be replayed with new counts.  A tile is kBlock * ept
+// events of one channel; block b takes tiles b, b + gridDim, ... (static, so
+// per-tile statistics are reproducible for a given launch shape).  Each tile
+// writes (sum w, sum w^2, n(w == 0), max w) to tile_stats.  Per-event results
+// do not depend on the launch shape: the uniforms are keyed by event id.
+template <int NS, int NI, int KINDS, bool MIX>
+__global__ __launch_bounds__(kBlock) void k_sample(const ChannelTab* __restrict__ cts, const ProcessTab* __restrict__ pts,
+                                                   const double* __restrict__ grids, const int64_t* __restrict__ grid_off,
+                                                   const int32_t* __restrict__ chan_nb,
+                                                   const SampleCall* __restrict__ call, uint64_t seed, uint64_t sid,
+                                                   const uint64_t* __restrict__ ctr_dev, uint64_t ctr_off, int np,
+                                                   int64_t ld, double* __restrict__ p, double* __restrict__ x1x2,
+                                                   double* __restrict__ w, int32_t* __restrict__ chan_out,
+                                                   double* __restrict__ tile_stats) {
+    extern __shared__ double lg[];
+    __shared__ double red[4][kWaves];
+    int cur = -1;
+    int nb = 0, dims = 0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t n_tiles = call->n_tiles;
+    const int n_chan = call->n_chan;
+    const int ept = call->ept;
+    const uint64_t ctr0 = ctr_dev ? *ctr_dev : ctr_off;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        int c = 0;
+        while (c + 1 < n_chan && call->tile_start[c + 1] <= tile) ++c;
+        const ChannelTab* ct = cts + c;
+        if (c != cur) {
+            __syncthreads();
+            nb = chan_nb[c];
+            dims = ct->dims;
+            const double* g = grids + grid_off[c];
+            for (int i = threadIdx.x; i < dims * (nb + 1); i += blockDim.x) lg[i] = g[i];
+            __syncthreads();
+            cur = c;
+        }
+        const ProcessTab* pt = pts + ct->process;
+        const double s_lab = pt->s_lab;
+        const int64_t base = call->ev_start[c] + (tile - call->tile_start[c]) * (int64_t)kBlock * ept;
+        const int64_t end = call->ev_start[c + 1];
+        double a1 = 0.0, a2 = 0.0, az = 0.0, am = 0.0;
+        for (int sub = 0; sub < ept; ++sub) {
+            const int64_t pos = base + (int64_t)sub * kBlock + threadIdx.x;
+            if (pos >= end) break;
+            const uint64_t e = ctr0 + (uint64_t)pos;
+            // uniforms on demand, four per Philox block (dimensions are consumed in order)
+            double ub[4];
+            int k = 0;
+            double jv = 1.0;
+            auto next = [&]() -> double {
+                if ((k & 3) == 0) {
+                    uint64_t c0 = e, c1 = (uint64_t)(k >> 2), c2 = 0, c3 = 0;
+                    philox4x64_10(c0, c1, c2, c3, seed, sid);
+                    ub[0] = to_unit(c0);
+                    ub[1] = to_unit(c1);
+                    ub[2] = to_unit(c2);
+                    ub[3] = to_unit(c3);
+                }
+                double r = vegas_map(ub[k & 3], lg + k * (nb + 1), nb, jv);
+                ++k;
+                return r;
+            };
+            double E[NS], X[NS], Y[NS], Z[NS], S[NI], SQ[NI];
+            ChainOut o;
+            run_chain<NS, NI, KINDS, MIX>(ct, s_lab, next, E, X, Y, Z, S, SQ, o);
+            const double wv = finish_event<NS, MIX>(ct, pt, o, jv, E, X, Y, Z, np, ld, pos, p, x1x2, nullptr, true);
+            w[pos] = wv;
+            if (chan_out) chan_out[pos] = c;
+            a1 += wv;
+            a2 += wv * wv;
+            az += wv == 0.0 ? 1.0 : 0.0;
+            am = fmax(am, wv);
+        }
+        double s1 = wave_sum(a1), s2 = wave_sum(a2);
+        double nz = wave_sum(az);
+        double mx = wave_max(am);
+        if (lane == 0) {
+            red[0][wave] = s1;
+            red[1][wave] = s2;
+            red[2][wave] = nz;
+            red[3][wave] = mx;
+        }
+        __syncthreads();
+        if (threadIdx.x < 4) {
+            int q = threadIdx.x;
+            double acc = red[q][0];
+            for (int v = 1; v < kWaves; ++v) acc = (q == 3) ? fmax(acc, red[q][v]) : acc + red[q][v];
+            tile_stats[tile * 4 + q] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+// Launch of one register class: kind class `kc` picks the compiled map kinds
+// (0: integer-root power laws, 1: plus Breit-Wigner, 2: all; the mixed
+// kernels exist for classes 1 and 2 only).
+template <int NS, int NI, bool MIX>
+hipError_t launch_chain_class(int kc, const ChainLaunch& a) {
+    constexpr int K0 = KIND_POW_INT, K1 = KIND_POW_INT | KIND_BW, K2 = KINDS_ALL;
+    auto go = [&](auto kt) {
+        constexpr int K = decltype(kt)::value;
+        if (a.sample)
+            k_sample<NS, NI, K, MIX><<<a.grid, kBlock, a.lds, a.stream>>>(
+                a.cts, a.pts, a.grids, a.grid_off, a.chan_nb, a.call, a.seed, a.sid, a.ctr_dev, a.ctr_off, a.np, a.n,
+                a.p, a.x1x2, a.w, a.chan, a.tile_stats);
+        else
+            k_map<NS, NI, K, MIX><<<a.grid, kBlock, a.lds, a.stream>>>(a.cts, a.pts, a.grids, a.nb, a.s_lab, a.np, a.n,
+                                                                         a.y, a.p, a.x1x2, a.jac, a.w);
+    };
+    if (!MIX && kc == 0) go(std::integral_constant<int, K0>{});
+    else if (kc <= 1) go(std::integral_constant<int, K1>{});
+    else go(std::integral_constant<int, K2>{});
+    return hipGetLastError();
+}
+
+#define MSX_INSTANTIATE_CHAIN(NS, NI, MIX) \
+    template hipError_t launch_chain_class<NS, NI, MIX>(int kc, const ChainLaunch& a);
+
+}  // namespace msx

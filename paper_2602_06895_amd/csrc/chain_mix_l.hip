@@ -1,0 +1,6 @@
+// Mapping-chain kernels: 14 momentum slots, 8 invariants, mixed precision.
+#include "chain_kernels.h"
+
+namespace msx {
+MSX_INSTANTIATE_CHAIN(14, 8, true)
+}  // namespace msx

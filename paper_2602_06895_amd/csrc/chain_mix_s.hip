@@ -1,0 +1,6 @@
+// Mapping-chain kernels: 6 momentum slots, 4 invariants, mixed precision.
+#include "chain_kernels.h"
+
+namespace msx {
+MSX_INSTANTIATE_CHAIN(6, 4, true)
+}  // namespace msx

@@ -1,0 +1,674 @@
+// Kernels of the rational-quadratic spline coupling flow on gfx950: the MLP
+// conditioner as GEMMs on the matrix cores (BF16 operands with FP32
+// accumulation, or FP32 operands), the spline forward / inverse / reverse-mode
+// passes in FP32 (one thread per event), the variance loss and Adam.
+//
+// The spline is the monotone rational-quadratic transformation of Durkan et
+// al. (2019) that the paper uses for its neural importance sampler (section
+// 2.3, adaptive sampling); its single-bin case is the RQF of the FastRambo
+// mapping (section 2.2.9).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "chain.h"
+#include "device_util.h"
+#include "flow_launch.h"
+
+namespace msx {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// GEMM on the matrix cores: 64 x 64 output tile per 256-thread workgroup,
+// 32-deep K steps through LDS; wave w owns the 32 x 32 quarter (w / 2, w % 2)
+// as 2 x 2 tiles of 16 x 16.
+//   BF16: v_mfma_f32_16x16x32_bf16, lane l holds A[l % 16][8 (l / 16) + 0..7]
+//         and B[8 (l / 16) + 0..7][l % 16];
+//   FP32: v_mfma_f32_16x16x4_f32,  lane l holds A[l % 16][l / 16], B[l / 16][l % 16];
+//   both: lane l receives D[4 (l / 16) + 0..3][l % 16].
+// ---------------------------------------------------------------------------
+constexpr int BM = 64, BN = 64, BK = 32, GT = 256;
+
+template <class T>
+struct Lds;
+template <>
+struct Lds<__bf16> {
+    static constexpr int LDK = BK + 8;  // 80-byte rows keep 16-byte operand reads aligned
+};
+template <>
+struct Lds<float> {
+    static constexpr int LDK = BK + 1;  // odd stride: column reads spread over the banks
+};
+
+template <class T>
+__device__ __forceinline__ T to_t(float v) {
+    return (T)v;
+}
+
+// One 64 x 32 tile of P (rows r0.., k k0..) into S[r][k]; zero outside
+// rows < R and k < kend.  8 elements per thread, walking the unit stride.
+template <class T>
+__device__ __forceinline__ void load_tile(const T* __restrict__ P, int64_t s_r, int64_t s_k, int R, int r0, int k0,
+                                          int kend, T (*S)[Lds<T>::LDK], int tid) {
+    if (s_r == 1 && s_k != 1) {
+        const int kk = tid >> 3, rb = (tid & 7) * 8;
+        const int k = k0 + kk;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int r = r0 + rb + i;
+            T v = to_t<T>(0.0f);
+            if (r < R && k < kend) v = P[(int64_t)r + (int64_t)k * s_k];
+            S[rb + i][kk] = v;
+        }
+    } else {
+        const int rr = tid >> 2, kb = (tid & 3) * 8;
+        const int r = r0 + rr;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = k0 + kb + i;
+            T v = to_t<T>(0.0f);
+            if (r < R && k < kend) v = P[(int64_t)r * s_r + (int64_t)k * s_k];
+            S[rr][kb + i] = v;
+        }
+    }
+}
+
+__device__ __forceinline__ void mma(const __bf16 (*As)[Lds<__bf16>::LDK], const __bf16 (*Bs)[Lds<__bf16>::LDK], int wm,
+                                    int wn, int lane, floatx4 (&acc)[2][2]) {
+    bf16x8 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) a[i] = *(const bf16x8*)&As[wm + i * 16 + (lane & 15)][8 * (lane >> 4)];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) b[j] = *(const bf16x8*)&Bs[wn + j * 16 + (lane & 15)][8 * (lane >> 4)];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+}
+
+__device__ __forceinline__ void mma(const float (*As)[Lds<float>::LDK], const float (*Bs)[Lds<float>::LDK], int wm,
+                                    int wn, int lane, floatx4 (&acc)[2][2]) {
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+        float a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = As[wm + i * 16 + (lane & 15)][4 * ks + (lane >> 4)];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = Bs[wn + j * 16 + (lane & 15)][4 * ks + (lane >> 4)];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(GT) void k_gemm(GemmArgs g, int kchunk) {
+    constexpr int LDK = Lds<T>::LDK;
+    __shared__ __attribute__((aligned(16))) T As[BM][LDK];
+    __shared__ __attribute__((aligned(16))) T Bs[BN][LDK];
+    const T* __restrict__ A = (const T*)g.A;
+    const T* __restrict__ B = (const T*)g.B;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const int kbeg = blockIdx.z * kchunk;
+    const int kend = min(g.K, kbeg + kchunk);
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+        load_tile<T>(A, g.a_m, g.a_k, g.M, m0, k0, kend, As, tid);
+        load_tile<T>(B, g.b_n, g.b_k, g.N, n0, k0, kend, Bs, tid);
+        __syncthreads();
+        mma(As, Bs, wm, wn, lane, acc);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = m0 + wm + i * 16 + 4 * (lane >> 4) + e;
+                const int c = n0 + wn + j * 16 + (lane & 15);
+                if (r >= g.M || c >= g.N) continue;
+                const float v = acc[i][j][e];
+                switch (g.epi) {
+                    case EPI_PARTIAL:
+                        ((float*)g.out)[((int64_t)blockIdx.z * g.M + r) * g.N + c] = v;
+                        break;
+                    case EPI_BIAS_RELU:
+                        ((T*)g.out)[(int64_t)r * g.ldc + c] = to_t<T>(fmaxf(v + g.bias[c], 0.0f));
+                        break;
+                    case EPI_BIAS_F32:
+                        ((float*)g.out)[(int64_t)r * g.ldc + c] = v + g.bias[c];
+                        break;
+                    case EPI_RELU_MASK: {
+                        const float h = (float)((const T*)g.mask)[(int64_t)r * g.ldm + c];
+                        ((T*)g.out)[(int64_t)r * g.ldc + c] = to_t<T>(h > 0.0f ? v : 0.0f);
+                        break;
+                    }
+                    default:
+                        ((float*)g.out)[(int64_t)r * g.ldc + c] = v;
+                        break;
+                }
+            }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_partials(const float* __restrict__ part, int splits, int M, int N,
+                                                         float* __restrict__ out, int64_t ldo) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t MN = (int64_t)M * N;
+    if (i >= MN) return;
+    float s = 0.0f;
+    for (int z = 0; z < splits; ++z) s += part[z * MN + i];
+    const int64_t r = i / N, c = i % N;
+    out[r * ldo + c] = s;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_colsum(const T* __restrict__ X, int64_t R, int N, int64_t ldx, int64_t chunk,
+                                                float* __restrict__ part) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    const int64_t r0 = (int64_t)blockIdx.y * chunk, r1 = min(R, r0 + chunk);
+    float s = 0.0f;
+    for (int64_t r = r0; r < r1; ++r) s += (float)X[r * ldx + c];
+    part[(int64_t)blockIdx.y * N + c] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Layer plumbing
+// ---------------------------------------------------------------------------
+struct Idx {
+    int32_t v[kFlowMaxHalf];
+};
+
+template <class T>
+__global__ __launch_bounds__(256) void k_gather(const float* __restrict__ z, int64_t n, int nc, Idx cond,
+                                                T* __restrict__ x0) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    for (int i = 0; i < nc; ++i) x0[b * nc + i] = to_t<T>(z[(int64_t)cond.v[i] * n + b]);
+}
+
+__global__ __launch_bounds__(256) void k_scatter_add(float* __restrict__ adj, const float* __restrict__ dx0, int64_t n,
+                                                     int nc, Idx cond) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    for (int i = 0; i < nc; ++i) adj[(int64_t)cond.v[i] * n + b] += dx0[b * nc + i];
+}
+
+// ---------------------------------------------------------------------------
+// Spline: bin of a value from the 3K + 1 unconstrained parameters.
+// Widths / heights: kMin + (1 - K kMin) softmax; knot slopes: kMin +
+// softplus(theta + s0) with s0 = log(e^(1 - kMin) - 1) (theta = 0 -> slope 1);
+// knots are cumulative sums with the last one exactly 1.
+// ---------------------------------------------------------------------------
+constexpr float kMinW = 1e-3f, kMinH = 1e-3f, kMinD = 1e-3f;
+
+__device__ __forceinline__ float softplus_f(float x) {
+    return x > 20.0f ? x : log1pf(expf(x));
+}
+__device__ __forceinline__ float sigmoid_f(float x) {
+    return 1.0f / (1.0f + expf(-x));
+}
+__device__ __forceinline__ float slope_shift() {
+    return logf(expm1f(1.0f - kMinD));
+}
+
+struct Bin {
+    int k;
+    float x0, w, y0, h, d0, d1;
+    float pw, ph;  // softmax mass of the widths / heights below bin k
+};
+
+// BY_Y: locate v among the y knots (inverse) instead of the x knots.
+template <bool BY_Y>
+__device__ __forceinline__ Bin spline_bin(const float* __restrict__ th, int K, float v, float& mw, float& sw,
+                                          float& mh, float& sh) {
+    mw = -INFINITY;
+    mh = -INFINITY;
+    for (int i = 0; i < K; ++i) {
+        mw = fmaxf(mw, th[i]);
+        mh = fmaxf(mh, th[K + i]);
+    }
+    sw = 0.0f;
+    sh = 0.0f;
+    for (int i = 0; i < K; ++i) {
+        sw += expf(th[i] - mw);
+        sh += expf(th[K + i] - mh);
+    }
+    const float cw = (1.0f - K * kMinW) / sw, ch = (1.0f - K * kMinH) / sh;
+    Bin b{};
+    float cx = 0.0f, cy = 0.0f, pw = 0.0f, ph = 0.0f;
+    for (int i = 0; i < K; ++i) {
+        const float ew = expf(th[i] - mw), eh = expf(th[K + i] - mh);
+        const float xl = cx, yl = cy;
+        cx = (i == K - 1) ? 1.0f : cx + (kMinW + cw * ew);
+        cy = (i == K - 1) ? 1.0f : cy + (kMinH + ch * eh);
+        const bool take = (i == 0) || (v >= (BY_Y ? yl : xl));
+        if (take) {
+            b.k = i;
+            b.x0 = xl;
+            b.w = cx - xl;
+            b.y0 = yl;
+            b.h = cy - yl;
+            b.pw = pw;
+            b.ph = ph;
+        }
+        pw += ew / sw;
+        ph += eh / sh;
+    }
+    const float s0 = slope_shift();
+    b.d0 = kMinD + softplus_f(th[2 * K + b.k] + s0);
+    b.d1 = kMinD + softplus_f(th[2 * K + b.k + 1] + s0);
+    return b;
+}
+
+__device__ __forceinline__ float spline_slope(const Bin& b, float xi) {
+    const float s = b.h / b.w;
+    const float om = xi * (1.0f - xi);
+    const float den = s + (b.d1 + b.d0 - 2.0f * s) * om;
+    return s * s * (b.d1 * xi * xi + 2.0f * s * om + b.d0 * (1.0f - xi) * (1.0f - xi)) / (den * den);
+}
+
+template <bool INV>
+__global__ __launch_bounds__(256) void k_spline(float* __restrict__ z, int64_t n, const float* __restrict__ theta,
+                                                int64_t ldt, int nh, Idx trans, int K, float* __restrict__ logdet) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    float ld = 0.0f;
+    for (int j = 0; j < nh; ++j) {
+        const float* th = theta + e * ldt + (int64_t)j * (3 * K + 1);
+        float* zp = z + (int64_t)trans.v[j] * n + e;
+        const float v = *zp;
+        float mw, sw, mh, sh;
+        const Bin b = spline_bin<INV>(th, K, v, mw, sw, mh, sh);
+        const float s = b.h / b.w;
+        const float kap = b.d1 + b.d0 - 2.0f * s;
+        float xi, out;
+        if (!INV) {
+            xi = (v - b.x0) / b.w;
+            const float om = xi * (1.0f - xi);
+            out = b.y0 + b.h * (s * xi * xi + b.d0 * om) / (s + kap * om);
+        } else {
+            const float dy = v - b.y0;
+            const float qa = b.h * (s - b.d0) + dy * kap;
+            const float qb = b.h * b.d0 - dy * kap;
+            const float qc = -s * dy;
+            const float disc = fmaxf(qb * qb - 4.0f * qa * qc, 0.0f);
+            xi = 2.0f * qc / (-qb - sqrtf(disc));
+            out = b.x0 + xi * b.w;
+        }
+        const float g = spline_slope(b, xi);
+        ld += INV ? -logf(g) : logf(g);
+        *zp = out;
+    }
+    logdet[e] += ld;
+}
+
+// Forward-mode dual numbers with 7 tangents: (y, x0, w, y0, h, d0, d1).
+struct D7 {
+    float v;
+    float g[7];
+};
+__device__ __forceinline__ D7 dconst(float v) {
+    D7 r;
+    r.v = v;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) r.g[i] = 0.0f;
+    return r;
+}
+__device__ __forceinline__ D7 dvar(float v, int i) {
+    D7 r = dconst(v);
+    r.g[i] = 1.0f;
+    return r;
+}
+__device__ __forceinline__ D7 operator+(const D7& a, const D7& b) {
+    D7 r;
+    r.v = a.v + b.v;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) r.g[i] = a.g[i] + b.g[i];
+    return r;
+}
+__device__ __forceinline__ D7 operator-(const D7& a, const D7& b) {
+    D7 r;
+    r.v = a.v - b.v;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) r.g[i] = a.g[i] - b.g[i];
+    return r;
+}
+__device__ __forceinline__ D7 operator*(const D7& a, const D7& b) {
+    D7 r;
+    r.v = a.v * b.v;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) r.g[i] = a.g[i] * b.v + a.v * b.g[i];
+    return r;
+}
+__device__ __forceinline__ D7 operator*(float a, const D7& b) {
+    D7 r;
+    r.v = a * b.v;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) r.g[i] = a * b.g[i];
+    return r;
+}
+__device__ __forceinline__ D7 operator/(const D7& a, const D7& b) {
+    D7 r;
+    const float ib = 1.0f / b.v;
+    r.v = a.v * ib;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) r.g[i] = (a.g[i] - r.v * b.g[i]) * ib;
+    return r;
+}
+__device__ __forceinline__ D7 dsqrt(const D7& a) {
+    D7 r;
+    r.v = sqrtf(a.v);
+    const float c = 0.5f / r.v;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) r.g[i] = a.g[i] * c;
+    return r;
+}
+__device__ __forceinline__ D7 dlog(const D7& a) {
+    D7 r;
+    r.v = logf(a.v);
+    const float c = 1.0f / a.v;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) r.g[i] = a.g[i] * c;
+    return r;
+}
+
+// Reverse mode through the inverse spline of one layer (see flow_launch.h).
+template <class T>
+__global__ __launch_bounds__(256) void k_spline_backward(const float* __restrict__ y, float* __restrict__ adj,
+                                                         int64_t n, const float* __restrict__ theta, int64_t ldt,
+                                                         int nh, Idx trans, int K, const float* __restrict__ G,
+                                                         T* __restrict__ dtheta) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const float ge = G[e];
+    const int P = 3 * K + 1;
+    for (int j = 0; j < nh; ++j) {
+        const float* th = theta + e * ldt + (int64_t)j * P;
+        T* dth = dtheta + e * ldt + (int64_t)j * P;
+        const int64_t zi = (int64_t)trans.v[j] * n + e;
+        const float v = y[zi];
+        float mw, sw, mh, sh;
+        const Bin bn = spline_bin<true>(th, K, v, mw, sw, mh, sh);
+        // x = S^-1(y) and ld = log (S^-1)'(y) = -log S'(x) as duals
+        const D7 Y = dvar(v, 0), X0 = dvar(bn.x0, 1), W = dvar(bn.w, 2), Y0 = dvar(bn.y0, 3), H = dvar(bn.h, 4),
+                 Dd0 = dvar(bn.d0, 5), Dd1 = dvar(bn.d1, 6);
+        const D7 s = H / W;
+        const D7 dy = Y - Y0;
+        const D7 kap = Dd1 + Dd0 - 2.0f * s;
+        const D7 qa = H * (s - Dd0) + dy * kap;
+        const D7 qb = H * Dd0 - dy * kap;
+        const D7 qc = dconst(0.0f) - s * dy;
+        D7 disc = qb * qb - 4.0f * (qa * qc);
+        disc.v = fmaxf(disc.v, 1e-30f);
+        const D7 xi = (2.0f * qc) / (dconst(0.0f) - qb - dsqrt(disc));
+        const D7 X = X0 + xi * W;
+        const D7 om = xi * (dconst(1.0f) - xi);
+        const D7 den = s + kap * om;
+        const D7 omx = dconst(1.0f) - xi;
+        const D7 num = s * s * (Dd1 * xi * xi + 2.0f * (s * om) + Dd0 * omx * omx);
+        const D7 ld = 2.0f * dlog(den) - dlog(num);
+        const float ax = adj[zi];
+        float gp[7];
+#pragma unroll
+        for (int i = 0; i < 7; ++i) gp[i] = ax * X.g[i] + ge * ld.g[i];
+        adj[zi] = gp[0];
+        // to the unconstrained parameters: softmax of widths / heights, softplus of slopes
+        const float Cw = 1.0f - K * kMinW, Ch = 1.0f - K * kMinH;
+        const float sumw = gp[1] * bn.pw + gp[2] * (expf(th[bn.k] - mw) / sw);
+        const float sumh = gp[3] * bn.ph + gp[4] * (expf(th[K + bn.k] - mh) / sh);
+        for (int i = 0; i < K; ++i) {
+            const float pwi = expf(th[i] - mw) / sw, phi = expf(th[K + i] - mh) / sh;
+            const float dwi = (i < bn.k ? gp[1] : 0.0f) + (i == bn.k ? gp[2] : 0.0f);
+            const float dhi = (i < bn.k ? gp[3] : 0.0f) + (i == bn.k ? gp[4] : 0.0f);
+            dth[i] = to_t<T>(Cw * pwi * (dwi - sumw));
+            dth[K + i] = to_t<T>(Ch * phi * (dhi - sumh));
+        }
+        const float s0 = slope_shift();
+        for (int i = 0; i <= K; ++i) {
+            const float dd = (i == bn.k ? gp[5] : 0.0f) + (i == bn.k + 1 ? gp[6] : 0.0f);
+            dth[2 * K + i] = to_t<T>(dd * sigmoid_f(th[2 * K + i] + s0));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Loss, optimiser, conversions
+// ---------------------------------------------------------------------------
+constexpr int kLossBlocks = 1024;
+
+__global__ __launch_bounds__(256) void k_flow_loss(int64_t n, const double* __restrict__ wfj,
+                                                   const float* __restrict__ logq, const float* __restrict__ lqo,
+                                                   float* __restrict__ G, double* __restrict__ part) {
+    __shared__ double red[4];
+    double acc = 0.0;
+    const double inv_n = 1.0 / (double)n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const double f = wfj[e];
+        const double t = f * f * exp(-(double)logq[e] - (double)lqo[e]);
+        acc += t;
+        G[e] = (float)(-t * inv_n);
+    }
+    const double s = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+__global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ part, int nb, double inv_n,
+                                                    double* __restrict__ loss) {
+    __shared__ double red[4];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) a += part[i];
+    const double s = wave_sum(a);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) loss[0] = (((red[0] + red[1]) + red[2]) + red[3]) * inv_n;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_adam(int64_t P, float* __restrict__ p, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v, float b1, float b2,
+                                              float lr_t, float eps_t, T* __restrict__ pt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float q = p[i] - lr_t * mi / (sqrtf(vi) + eps_t);
+    p[i] = q;
+    pt[i] = to_t<T>(q);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_cast(int64_t P, const float* __restrict__ p, T* __restrict__ pt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P) pt[i] = to_t<T>(p[i]);
+}
+
+__global__ __launch_bounds__(256) void k_uniform_f32(uint64_t seed, uint64_t sid, uint64_t e0, int64_t n, int d,
+                                                     float* __restrict__ u) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t e = e0 + (uint64_t)i;
+    for (int g = 0; g < (d + 3) / 4; ++g) {
+        uint64_t c0 = e, c1 = (uint64_t)g, c2 = 0, c3 = 0;
+        philox4x64_10(c0, c1, c2, c3, seed, sid);
+        const uint64_t wv[4] = {c0, c1, c2, c3};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 4 * g + j;
+            if (k < d) u[(int64_t)k * n + i] = ((float)(wv[j] >> 40) + 0.5f) * 0x1.0p-24f;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_widen(int64_t count, const float* __restrict__ y, double* __restrict__ yd) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    // keep the mapped point inside the open unit cube
+    yd[i] = (double)fminf(fmaxf(y[i], 0x1.0p-26f), 1.0f - 0x1.0p-24f);
+}
+
+__global__ __launch_bounds__(256) void k_flow_weight(int64_t n, const double* __restrict__ wfj,
+                                                     const float* __restrict__ logdet, double* __restrict__ w,
+                                                     float* __restrict__ logq) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float ld = logdet[i];
+    w[i] = wfj[i] * exp((double)ld);
+    if (logq) logq[i] = -ld;
+}
+
+unsigned blocks(int64_t n) {
+    return (unsigned)std::max<int64_t>(1, (n + 255) / 256);
+}
+
+Idx make_idx(const int32_t* h, int count) {
+    Idx r{};
+    for (int i = 0; i < count && i < kFlowMaxHalf; ++i) r.v[i] = h[i];
+    return r;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
+    if (g.M <= 0 || g.N <= 0) return hipSuccess;
+    const int splits = std::max(1, g.splits);
+    int kchunk = (g.K + splits - 1) / splits;
+    kchunk = ((kchunk + BK - 1) / BK) * BK;
+    dim3 grid((unsigned)((g.M + BM - 1) / BM), (unsigned)((g.N + BN - 1) / BN), (unsigned)splits);
+    if (g.type == FT_BF16)
+        k_gemm<__bf16><<<grid, GT, 0, s>>>(g, kchunk);
+    else
+        k_gemm<float><<<grid, GT, 0, s>>>(g, kchunk);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const float* part, int splits, int M, int N, float* out, int64_t ldo,
+                                  hipStream_t s) {
+    const int64_t MN = (int64_t)M * N;
+    if (MN == 0) return hipSuccess;
+    k_reduce_partials<<<blocks(MN), 256, 0, s>>>(part, splits, M, N, out, ldo);
+    return hipGetLastError();
+}
+
+hipError_t launch_colsum(int type, const void* X, int64_t R, int N, int64_t ldx, float* part, int nchunk, float* out,
+                         hipStream_t s) {
+    const int64_t chunk = (R + nchunk - 1) / nchunk;
+    dim3 grid((unsigned)((N + 255) / 256), (unsigned)nchunk);
+    if (type == FT_BF16)
+        k_colsum<__bf16><<<grid, 256, 0, s>>>((const __bf16*)X, R, N, ldx, chunk, part);
+    else
+        k_colsum<float><<<grid, 256, 0, s>>>((const float*)X, R, N, ldx, chunk, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce_partials(part, nchunk, 1, N, out, N, s);
+}
+
+hipError_t launch_gather(int type, const float* z, int64_t n, int n_cond, const int32_t* cond_host, void* x0,
+                         hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    Idx c = make_idx(cond_host, n_cond);
+    if (type == FT_BF16)
+        k_gather<__bf16><<<blocks(n), 256, 0, s>>>(z, n, n_cond, c, (__bf16*)x0);
+    else
+        k_gather<float><<<blocks(n), 256, 0, s>>>(z, n, n_cond, c, (float*)x0);
+    return hipGetLastError();
+}
+
+hipError_t launch_spline(bool inverse, float* z, int64_t n, const float* theta, int64_t ldt, int n_half,
+                         const int32_t* trans_host, int K, float* logdet, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    Idx t = make_idx(trans_host, n_half);
+    if (inverse)
+        k_spline<true><<<blocks(n), 256, 0, s>>>(z, n, theta, ldt, n_half, t, K, logdet);
+    else
+        k_spline<false><<<blocks(n), 256, 0, s>>>(z, n, theta, ldt, n_half, t, K, logdet);
+    return hipGetLastError();
+}
+
+hipError_t launch_spline_backward(int type, const float* y, float* adj, int64_t n, const float* theta, int64_t ldt,
+                                  int n_half, const int32_t* trans_host, int K, const float* G, void* dtheta,
+                                  hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    Idx t = make_idx(trans_host, n_half);
+    if (type == FT_BF16)
+        k_spline_backward<__bf16><<<blocks(n), 256, 0, s>>>(y, adj, n, theta, ldt, n_half, t, K, G, (__bf16*)dtheta);
+    else
+        k_spline_backward<float><<<blocks(n), 256, 0, s>>>(y, adj, n, theta, ldt, n_half, t, K, G, (float*)dtheta);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_add(float* adj, const float* dx0, int64_t n, int n_cond, const int32_t* cond_host,
+                              hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    k_scatter_add<<<blocks(n), 256, 0, s>>>(adj, dx0, n, n_cond, make_idx(cond_host, n_cond));
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_loss(int64_t n, const double* wfj, const float* logq, const float* logq_old, float* G,
+                            double* part, double* loss, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    k_flow_loss<<<kLossBlocks, 256, 0, s>>>(n, wfj, logq, logq_old, G, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_loss_final<<<1, 256, 0, s>>>(part, kLossBlocks, 1.0 / (double)n, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(int64_t P, float* params, const float* grad, float* m, float* v, float b1, float b2,
+                       float lr_t, float eps_t, int type, void* params_t, hipStream_t s) {
+    if (type == FT_BF16)
+        k_adam<__bf16><<<blocks(P), 256, 0, s>>>(P, params, grad, m, v, b1, b2, lr_t, eps_t, (__bf16*)params_t);
+    else
+        k_adam<float><<<blocks(P), 256, 0, s>>>(P, params, grad, m, v, b1, b2, lr_t, eps_t, (float*)params_t);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast(int64_t P, const float* params, int type, void* params_t, hipStream_t s) {
+    if (type == FT_BF16)
+        k_cast<__bf16><<<blocks(P), 256, 0, s>>>(P, params, (__bf16*)params_t);
+    else
+        k_cast<float><<<blocks(P), 256, 0, s>>>(P, params, (float*)params_t);
+    return hipGetLastError();
+}
+
+hipError_t launch_uniform_f32(uint64_t seed, uint64_t sid, uint64_t e0, int64_t n, int d, float* u, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    k_uniform_f32<<<blocks(n), 256, 0, s>>>(seed, sid, e0, n, d, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_widen(int64_t count, const float* y, double* y_d, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    k_widen<<<blocks(count), 256, 0, s>>>(count, y, y_d);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_weight(int64_t n, const double* wfj, const float* logdet, double* w, float* logq,
+                              hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    k_flow_weight<<<blocks(n), 256, 0, s>>>(n, wfj, logdet, w, logq);
+    return hipGetLastError();
+}
+
+}  // namespace msx

@@ -5,106 +5,12 @@
 #include <cmath>
 
 #include "chain.h"
+#include "device_util.h"
 #include "launch.h"
 
 namespace msx {
 
 namespace {
-
-constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / 64;
-
-// VEGAS map of one uniform through a grid row in LDS: bin i = floor(y nb),
-// linear inside the bin, Jacobian nb (e_{i+1} - e_i).
-__device__ __forceinline__ double vegas_map(double y, const double* __restrict__ g, int nb, double& jv) {
-    double t = y * nb;
-    int i = (int)t;
-    i = i < 0 ? 0 : (i > nb - 1 ? nb - 1 : i);
-    double e0 = g[i], e1 = g[i + 1];
-    double wd = e1 - e0;
-    jv *= nb * wd;
-    return e0 + wd * (t - i);
-}
-
-// Deterministic wave-level reductions (fixed butterfly order).
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-// Beam boost, unphysical cut, integrand x channel weight and the stores of one
-// event whose partonic-frame momenta sit in the slots.
-template <int NS>
-__device__ __forceinline__ double finish_event(const ChannelTab* __restrict__ ct, const ProcessTab* __restrict__ pt,
-                                               const ChainOut& o, double jv, double (&E)[NS], double (&X)[NS],
-                                               double (&Y)[NS], double (&Z)[NS], int np, int64_t n, int64_t e,
-                                               double* __restrict__ p, double* __restrict__ x1x2,
-                                               double* __restrict__ jac_out, bool want_w) {
-    const int nf = ct->n_final;
-    const int hadronic = ct->hadronic;
-    double g = 1.0, gb = 0.0;
-    if (hadronic) {
-        double inv = 1.0 / (2.0 * sqrt(o.x1 * o.x2));
-        g = (o.x1 + o.x2) * inv;
-        gb = (o.x1 - o.x2) * inv;
-    }
-    const double h = 0.5 * sqrt(o.shat);
-    bool ok = true;
-    // incoming partons, then final-state particles by label
-    for (int i = 0; i < nf + 2; ++i) {
-        double pe, px, py, pz;
-        if (i < 2) {
-            pe = h;
-            px = 0.0;
-            py = 0.0;
-            pz = i == 0 ? h : -h;
-        } else {
-            int s = slot_index<NS>(ct->final_slot[i - 2]);
-            pe = E[s];
-            px = X[s];
-            py = Y[s];
-            pz = Z[s];
-        }
-        double le = pe, lz = pz;
-        if (hadronic) {
-            le = g * pe + gb * pz;
-            lz = gb * pe + g * pz;
-        }
-        ok = ok && isfinite(le) && isfinite(px) && isfinite(py) && isfinite(lz) && le >= 0.0;
-        p[((int64_t)0 * np + i) * n + e] = le;
-        p[((int64_t)1 * np + i) * n + e] = px;
-        p[((int64_t)2 * np + i) * n + e] = py;
-        p[((int64_t)3 * np + i) * n + e] = lz;
-    }
-    double jac = o.jac * jv;
-    ok = ok && isfinite(jac) && jac > 0.0;
-    if (hadronic) {
-        ok = ok && o.x1 > 0.0 && o.x1 <= 1.0 && o.x2 > 0.0 && o.x2 <= 1.0;
-        if (x1x2) {
-            x1x2[e] = o.x1;
-            x1x2[n + e] = o.x2;
-        }
-    }
-    if (!ok) jac = 0.0;
-    if (jac_out) jac_out[e] = jac;
-    double w = 0.0;
-    if (want_w && ok) {
-        double alpha;
-        auto get = [&](int k, int c) -> double {
-            int s = slot_index<NS>(ct->final_slot[k]);
-            return c == 0 ? E[s] : (c == 1 ? X[s] : (c == 2 ? Y[s] : Z[s]));
-        };
-        double af = integrand_alpha(pt, ct->alpha_index, o.x1, o.x2, o.logtau, h, 0.0, 0.0, h, get, alpha);
-        w = af * jac;
-    }
-    return w;
-}
 
 // ---------------------------------------------------------------------------
 // Kernels
@@ -127,33 +33,7 @@ __global__ __launch_bounds__(kBlock) void k_uniform(uint64_t seed, uint64_t sid,
     }
 }
 
-template <int NS, int NI, int KINDS>
-__global__ __launch_bounds__(kBlock) void k_map(const ChannelTab* __restrict__ ct, const ProcessTab* __restrict__ pt,
-                                                const double* __restrict__ grid, int nb, double s_lab, int np,
-                                                int64_t n, const double* __restrict__ y, double* __restrict__ p,
-                                                double* __restrict__ x1x2, double* __restrict__ jac,
-                                                double* __restrict__ w) {
-    extern __shared__ double lg[];
-    const int dims = ct->dims;
-    for (int i = threadIdx.x; i < dims * (nb + 1); i += blockDim.x) lg[i] = grid[i];
-    __syncthreads();
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
-        int k = 0;
-        double jv = 1.0;
-        auto next = [&]() -> double {
-            double r = vegas_map(y[(int64_t)k * n + e], lg + k * (nb + 1), nb, jv);
-            ++k;
-            return r;
-        };
-        double E[NS], X[NS], Y[NS], Z[NS], S[NI], SQ[NI];
-        ChainOut o;
-        run_chain<NS, NI, KINDS>(ct, s_lab, next, E, X, Y, Z, S, SQ, o);
-        double wv = finish_event<NS>(ct, pt, o, jv, E, X, Y, Z, np, n, e, p, x1x2, jac, w != nullptr);
-        if (w) w[e] = wv;
-    }
-}
-
+template <bool MIX>
 __global__ __launch_bounds__(kBlock) void k_weight(const ChannelTab* __restrict__ ct, const ProcessTab* __restrict__ pt,
                                                    int np, int64_t n, const double* __restrict__ p,
                                                    const double* __restrict__ x1x2, const double* __restrict__ jac,
@@ -167,106 +47,27 @@ __global__ __launch_bounds__(kBlock) void k_weight(const ChannelTab* __restrict_
         if (ct->hadronic) {
             x1 = x1x2[e];
             x2 = x1x2[n + e];
-            L = log(x1 * x2);
+            L = t_log<MIX>(x1 * x2);
         }
         auto get = [&](int k, int c) -> double { return p[((int64_t)c * np + k + 2) * n + e]; };
         double pae = p[((int64_t)0 * np) * n + e], pax = p[((int64_t)1 * np) * n + e];
         double pay = p[((int64_t)2 * np) * n + e], paz = p[((int64_t)3 * np) * n + e];
-        double af = integrand_alpha(pt, ct->alpha_index, x1, x2, L, pae, pax, pay, paz, get, av);
+        double af = integrand_alpha<MIX>(pt, ct->alpha_index, x1, x2, L, pae, pax, pay, paz, get, av);
         wv = af * j;
     }
     w[e] = wv;
     if (alpha) alpha[e] = av;
 }
 
-// All channels in one persistent launch.  Tiles of kBlock events never mix
-// channels; block b takes tiles b, b + gridDim, ... (static, so per-tile
-// statistics are reproducible).  Each tile writes (sum w, sum w^2, n(w == 0),
-// max w) to tile_stats.
-template <int NS, int NI, int KINDS>
-__global__ __launch_bounds__(kBlock) void k_sample(const ChannelTab* __restrict__ cts, const ProcessTab* __restrict__ pts,
-                                                   const double* __restrict__ grids, const int64_t* __restrict__ grid_off,
-                                                   const int32_t* __restrict__ chan_nb, SampleCall call, uint64_t seed,
-                                                   uint64_t sid, uint64_t ctr_off, double s_lab_unused, int np,
-                                                   int64_t N, double* __restrict__ p, double* __restrict__ x1x2,
-                                                   double* __restrict__ w, int32_t* __restrict__ chan_out,
-                                                   double* __restrict__ tile_stats) {
-    extern __shared__ double lg[];
-    __shared__ double red[4][kWaves];
-    int cur = -1;
-    int nb = 0, dims = 0;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int64_t tile = blockIdx.x; tile < call.n_tiles; tile += gridDim.x) {
-        int c = 0;
-        while (c + 1 < call.n_chan && call.tile_start[c + 1] <= tile) ++c;
-        const ChannelTab* ct = cts + c;
-        if (c != cur) {
-            __syncthreads();
-            nb = chan_nb[c];
-            dims = ct->dims;
-            const double* g = grids + grid_off[c];
-            for (int i = threadIdx.x; i < dims * (nb + 1); i += blockDim.x) lg[i] = g[i];
-            __syncthreads();
-            cur = c;
-        }
-        const ProcessTab* pt = pts + ct->process;
-        const double s_lab = pt->s_lab;
-        const int64_t pos = call.ev_start[c] + (tile - call.tile_start[c]) * kBlock + threadIdx.x;
-        const bool active = pos < call.ev_start[c + 1];
-        double wv = 0.0;
-        if (active) {
-            const uint64_t e = ctr_off + (uint64_t)pos;
-            // uniforms on demand, four per Philox block (dimensions are consumed in order)
-            double ub[4];
-            int k = 0;
-            double jv = 1.0;
-            auto next = [&]() -> double {
-                if ((k & 3) == 0) {
-                    uint64_t c0 = e, c1 = (uint64_t)(k >> 2), c2 = 0, c3 = 0;
-                    philox4x64_10(c0, c1, c2, c3, seed, sid);
-                    ub[0] = to_unit(c0);
-                    ub[1] = to_unit(c1);
-                    ub[2] = to_unit(c2);
-                    ub[3] = to_unit(c3);
-                }
-                double r = vegas_map(ub[k & 3], lg + k * (nb + 1), nb, jv);
-                ++k;
-                return r;
-            };
-            double E[NS], X[NS], Y[NS], Z[NS], S[NI], SQ[NI];
-            ChainOut o;
-            run_chain<NS, NI, KINDS>(ct, s_lab, next, E, X, Y, Z, S, SQ, o);
-            wv = finish_event<NS>(ct, pt, o, jv, E, X, Y, Z, np, N, pos, p, x1x2, nullptr, true);
-            w[pos] = wv;
-            if (chan_out) chan_out[pos] = c;
-        }
-        double s1 = wave_sum(wv), s2 = wave_sum(wv * wv);
-        double nz = wave_sum((active && wv == 0.0) ? 1.0 : 0.0);
-        double mx = wave_max(active ? wv : 0.0);
-        if (lane == 0) {
-            red[0][wave] = s1;
-            red[1][wave] = s2;
-            red[2][wave] = nz;
-            red[3][wave] = mx;
-        }
-        __syncthreads();
-        if (threadIdx.x < 4) {
-            int q = threadIdx.x;
-            double acc = red[q][0];
-            for (int v = 1; v < kWaves; ++v) acc = (q == 3) ? fmax(acc, red[q][v]) : acc + red[q][v];
-            tile_stats[tile * 4 + q] = acc;
-        }
-        __syncthreads();
-    }
-}
-
 // Reduce the tiles of each channel in order and add to the accumulators
 // stats[c] = (sum w, sum w^2, n, n(w == 0), max w).
-__global__ __launch_bounds__(kBlock) void k_stats_final(SampleCall call, const double* __restrict__ tile_stats,
+__global__ __launch_bounds__(kBlock) void k_stats_final(const SampleCall* __restrict__ call,
+                                                        const double* __restrict__ tile_stats,
                                                         double* __restrict__ stats) {
     const int c = blockIdx.x;
     __shared__ double red[4][kWaves];
-    const int64_t t0 = call.tile_start[c], t1 = call.tile_start[c + 1];
+    if (c >= call->n_chan) return;
+    const int64_t t0 = call->tile_start[c], t1 = call->tile_start[c + 1];
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
         a[0] += tile_stats[t * 4 + 0];
@@ -294,10 +95,47 @@ __global__ __launch_bounds__(kBlock) void k_stats_final(SampleCall call, const d
         double* st = stats + 5 * c;
         st[0] += s0;
         st[1] += s1;
-        st[2] += (double)(call.ev_start[c + 1] - call.ev_start[c]);
+        st[2] += (double)(call->ev_start[c + 1] - call->ev_start[c]);
         st[3] += s2;
         st[4] = fmax(st[4], mx);
     }
+}
+
+__global__ void k_set_call(SampleCall call, SampleCall* __restrict__ dev) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dev = call;
+}
+
+// Call table from device-resident counts (one thread: at most kMaxChannels).
+__global__ void k_plan(const int64_t* __restrict__ counts, int n_chan, int64_t capacity, int ept,
+                       SampleCall* __restrict__ dev, int32_t* __restrict__ status) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int64_t T = (int64_t)kBlock * ept;
+    int64_t N = 0, tiles = 0;
+    int bad = 0;
+    dev->n_chan = n_chan;
+    dev->ept = ept;
+    for (int c = 0; c < n_chan; ++c) {
+        const int64_t k = counts[c];
+        dev->ev_start[c] = N;
+        dev->tile_start[c] = tiles;
+        if (k < 0 || k > capacity - N) {
+            bad = 1;
+        } else {
+            N += k;
+            tiles += (k + T - 1) / T;
+        }
+    }
+    dev->ev_start[n_chan] = N;
+    dev->tile_start[n_chan] = tiles;
+    dev->n_tiles = bad ? 0 : tiles;
+    if (bad) {
+        // no events: empty ranges everywhere
+        for (int c = 0; c <= n_chan; ++c) {
+            dev->ev_start[c] = 0;
+            dev->tile_start[c] = 0;
+        }
+    }
+    if (status) *status = bad;
 }
 
 // VEGAS histogram, pass 1: block (chunk, k) accumulates sum w^2 per bin of
@@ -412,30 +250,22 @@ int kind_class(int kinds) {
     return 2;
 }
 
-// One launch per (register class, kind class) instantiation.
-#define MSX_DISPATCH(RC, KC, LAUNCH)                                       \
-    do {                                                                   \
-        constexpr int K0 = KIND_POW_INT, K1 = KIND_POW_INT | KIND_BW, K2 = KINDS_ALL; \
-        const int rc_ = (RC), kc_ = (KC);                                  \
-        if (rc_ == 0) {                                                    \
-            if (kc_ == 0) LAUNCH(6, 4, K0);                                \
-            else if (kc_ == 1) LAUNCH(6, 4, K1);                           \
-            else LAUNCH(6, 4, K2);                                         \
-        } else if (rc_ == 1) {                                             \
-            if (kc_ == 0) LAUNCH(10, 8, K0);                               \
-            else if (kc_ == 1) LAUNCH(10, 8, K1);                          \
-            else LAUNCH(10, 8, K2);                                        \
-        } else {                                                           \
-            if (kc_ == 0) LAUNCH(14, 8, K0);                               \
-            else if (kc_ == 1) LAUNCH(14, 8, K1);                          \
-            else LAUNCH(14, 8, K2);                                        \
-        }                                                                  \
-    } while (0)
-
 int grid_for(int64_t n, int cap) {
     int64_t g = (n + kBlock - 1) / kBlock;
     if (g > cap) g = cap;
     return (int)std::max<int64_t>(g, 1);
+}
+
+// Register class -> the instantiation unit compiled for it.
+hipError_t launch_chain(int rc, int kc, int mixed, const ChainLaunch& a) {
+    if (mixed) {
+        if (rc == 0) return launch_chain_class<6, 4, true>(kc, a);
+        if (rc == 1) return launch_chain_class<10, 8, true>(kc, a);
+        return launch_chain_class<14, 8, true>(kc, a);
+    }
+    if (rc == 0) return launch_chain_class<6, 4, false>(kc, a);
+    if (rc == 1) return launch_chain_class<10, 8, false>(kc, a);
+    return launch_chain_class<14, 8, false>(kc, a);
 }
 
 }  // namespace
@@ -452,44 +282,85 @@ hipError_t launch_uniform(uint64_t seed, uint64_t sid, uint64_t e0, int64_t n, i
 }
 
 hipError_t launch_map(const ChannelTab* ct, const ProcessTab* pt, const double* grid, int nb, int dims, int n_slots,
-                      int n_inv, int kinds, double s_lab, int np, int64_t n, const double* y, double* p,
+                      int n_inv, int kinds, int mixed, double s_lab, int np, int64_t n, const double* y, double* p,
                       double* x1x2, double* jac, double* w, int cu_count, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    size_t lds = sizeof(double) * (size_t)dims * (nb + 1);
-    int g = grid_for(n, cu_count * 8);
-#define MSX_MAP(NS, NI, K) k_map<NS, NI, K><<<g, kBlock, lds, s>>>(ct, pt, grid, nb, s_lab, np, n, y, p, x1x2, jac, w)
-    MSX_DISPATCH(reg_class(n_slots, n_inv), kind_class(kinds), MSX_MAP);
-#undef MSX_MAP
-    return hipGetLastError();
+    ChainLaunch a{};
+    a.sample = false;
+    a.lds = sizeof(double) * (size_t)dims * (nb + 1);
+    a.grid = grid_for(n, cu_count * 8);
+    a.stream = s;
+    a.cts = ct;
+    a.pts = pt;
+    a.grids = grid;
+    a.nb = nb;
+    a.s_lab = s_lab;
+    a.np = np;
+    a.n = n;
+    a.y = y;
+    a.p = p;
+    a.x1x2 = x1x2;
+    a.jac = jac;
+    a.w = w;
+    return launch_chain(reg_class(n_slots, n_inv), kind_class(kinds), mixed, a);
 }
 
-hipError_t launch_weight(const ChannelTab* ct, const ProcessTab* pt, int np, int64_t n, const double* p,
+hipError_t launch_weight(const ChannelTab* ct, const ProcessTab* pt, int mixed, int np, int64_t n, const double* p,
                          const double* x1x2, const double* jac, double* w, double* alpha, hipStream_t s) {
     if (n == 0) return hipSuccess;
     int64_t g = (n + kBlock - 1) / kBlock;
-    k_weight<<<dim3((unsigned)g), dim3(kBlock), 0, s>>>(ct, pt, np, n, p, x1x2, jac, w, alpha);
+    if (mixed)
+        k_weight<true><<<dim3((unsigned)g), dim3(kBlock), 0, s>>>(ct, pt, np, n, p, x1x2, jac, w, alpha);
+    else
+        k_weight<false><<<dim3((unsigned)g), dim3(kBlock), 0, s>>>(ct, pt, np, n, p, x1x2, jac, w, alpha);
     return hipGetLastError();
 }
 
 hipError_t launch_sample(const ChannelTab* cts, const ProcessTab* pts, const double* grids, const int64_t* grid_off,
-                         const int32_t* chan_nb, const SampleCall& call, int max_slots, int max_inv, int kinds,
-                         size_t lds_bytes,
-                         uint64_t seed, uint64_t sid, uint64_t ctr_off, int np, int64_t N, double* p, double* x1x2,
-                         double* w, int32_t* chan, double* tile_stats, double* stats, int grid, hipStream_t s) {
-    if (call.n_tiles == 0) return hipSuccess;
-    int g = (int)std::min<int64_t>(call.n_tiles, grid);
-#define MSX_SAMPLE(NS, NI, K)                                                                                \
-    k_sample<NS, NI, K><<<g, kBlock, lds_bytes, s>>>(cts, pts, grids, grid_off, chan_nb, call, seed, sid, ctr_off, \
-                                                     0.0, np, N, p, x1x2, w, chan, tile_stats)
-    MSX_DISPATCH(reg_class(max_slots, max_inv), kind_class(kinds), MSX_SAMPLE);
-#undef MSX_SAMPLE
-    hipError_t err = hipGetLastError();
+                         const int32_t* chan_nb, const SampleCall* call, int n_chan, int max_slots, int max_inv,
+                         int kinds, int mixed, size_t lds_bytes, uint64_t seed, uint64_t sid, const uint64_t* ctr_dev,
+                         uint64_t ctr_off, int np, int64_t ld, double* p, double* x1x2, double* w, int32_t* chan,
+                         double* tile_stats, double* stats, int grid, hipStream_t s) {
+    ChainLaunch a{};
+    a.sample = true;
+    a.lds = lds_bytes;
+    a.grid = std::max(grid, 1);
+    a.stream = s;
+    a.cts = cts;
+    a.pts = pts;
+    a.grids = grids;
+    a.grid_off = grid_off;
+    a.chan_nb = chan_nb;
+    a.call = call;
+    a.seed = seed;
+    a.sid = sid;
+    a.ctr_dev = ctr_dev;
+    a.ctr_off = ctr_off;
+    a.np = np;
+    a.n = ld;
+    a.p = p;
+    a.x1x2 = x1x2;
+    a.w = w;
+    a.chan = chan;
+    a.tile_stats = tile_stats;
+    hipError_t err = launch_chain(reg_class(max_slots, max_inv), kind_class(kinds), mixed, a);
     if (err != hipSuccess) return err;
-    k_stats_final<<<call.n_chan, kBlock, 0, s>>>(call, tile_stats, stats);
+    k_stats_final<<<n_chan, kBlock, 0, s>>>(call, tile_stats, stats);
     return hipGetLastError();
 }
 
-int sample_tile_size() { return kBlock; }
+hipError_t launch_set_call(const SampleCall& host, SampleCall* dev, hipStream_t s) {
+    k_set_call<<<1, 64, 0, s>>>(host, dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan(const int64_t* counts, int n_chan, int64_t capacity, int ept, SampleCall* dev,
+                       int32_t* status, hipStream_t s) {
+    k_plan<<<1, 64, 0, s>>>(counts, n_chan, capacity, ept, dev, status);
+    return hipGetLastError();
+}
+
+int sample_block() { return kBlock; }
 
 hipError_t launch_vegas_accumulate(int64_t n, int dims, int nb, const double* y, const double* w, double* part,
                                    int64_t nchunk, int64_t chunk, double* hist, hipStream_t s) {

@@ -8,22 +8,69 @@
 
 namespace msx {
 
+// Arguments of one mapping-chain launch (single-channel map or fused sample).
+struct ChainLaunch {
+    bool sample;
+    size_t lds;
+    int grid;
+    hipStream_t stream;
+    const ChannelTab* cts;
+    const ProcessTab* pts;
+    const double* grids;
+    // map
+    int nb;
+    double s_lab;
+    const double* y;
+    double* jac;
+    // sample
+    const int64_t* grid_off;
+    const int32_t* chan_nb;
+    const SampleCall* call;  // device memory
+    uint64_t seed, sid, ctr_off;
+    const uint64_t* ctr_dev;  // device counter offset (overrides ctr_off) or NULL
+    int32_t* chan;
+    double* tile_stats;
+    // both
+    int np;
+    int64_t n;  // map: events; sample: row stride of the outputs
+    double* p;
+    double* x1x2;
+    double* w;
+};
+
+// One register class (NS slots, NI invariants) at one precision; defined in
+// the chain_*.hip instantiation units.
+template <int NS, int NI, bool MIX>
+hipError_t launch_chain_class(int kind_class, const ChainLaunch& a);
+
 hipError_t launch_uniform(uint64_t seed, uint64_t sid, uint64_t e0, int64_t n, int d, double* y, hipStream_t s);
 
 hipError_t launch_map(const ChannelTab* ct, const ProcessTab* pt, const double* grid, int nb, int dims, int n_slots,
-                      int n_inv, int kinds, double s_lab, int np, int64_t n, const double* y, double* p,
+                      int n_inv, int kinds, int mixed, double s_lab, int np, int64_t n, const double* y, double* p,
                       double* x1x2, double* jac, double* w, int cu_count, hipStream_t s);
 
-hipError_t launch_weight(const ChannelTab* ct, const ProcessTab* pt, int np, int64_t n, const double* p,
+hipError_t launch_weight(const ChannelTab* ct, const ProcessTab* pt, int mixed, int np, int64_t n, const double* p,
                          const double* x1x2, const double* jac, double* w, double* alpha, hipStream_t s);
 
+// Fused multichannel sample.  `call` is the device copy of the call table;
+// `max_tiles` bounds its n_tiles (for the per-channel statistics pass);
+// `ld` is the row stride of the outputs (>= the events of the call).
 hipError_t launch_sample(const ChannelTab* cts, const ProcessTab* pts, const double* grids, const int64_t* grid_off,
-                         const int32_t* chan_nb, const SampleCall& call, int max_slots, int max_inv, int kinds,
-                         size_t lds_bytes,
-                         uint64_t seed, uint64_t sid, uint64_t ctr_off, int np, int64_t N, double* p, double* x1x2,
-                         double* w, int32_t* chan, double* tile_stats, double* stats, int grid, hipStream_t s);
+                         const int32_t* chan_nb, const SampleCall* call, int n_chan, int max_slots, int max_inv,
+                         int kinds, int mixed, size_t lds_bytes, uint64_t seed, uint64_t sid, const uint64_t* ctr_dev,
+                         uint64_t ctr_off, int np, int64_t ld, double* p, double* x1x2, double* w, int32_t* chan,
+                         double* tile_stats, double* stats, int grid, hipStream_t s);
 
-int sample_tile_size();
+// Device copy of a host-built call table (stream ordered).
+hipError_t launch_set_call(const SampleCall& host, SampleCall* dev, hipStream_t s);
+
+// Call table from device-resident counts: prefix sums over n_chan channels,
+// tiles of kBlock * ept events.  If a count is negative or the total exceeds
+// `capacity`, n_tiles = 0 and *status = 1 (else 0).
+hipError_t launch_plan(const int64_t* counts, int n_chan, int64_t capacity, int ept, SampleCall* dev,
+                       int32_t* status, hipStream_t s);
+
+int sample_block();  // threads per workgroup of the sample kernel
 
 hipError_t launch_vegas_accumulate(int64_t n, int dims, int nb, const double* y, const double* w, double* part,
                                    int64_t nchunk, int64_t chunk, double* hist, hipStream_t s);

@@ -142,7 +142,7 @@ struct ProcessTab {
 // Per-call description of a multichannel launch (passed by value).
 struct SampleCall {
     int32_t n_chan;
-    int32_t pad;
+    int32_t ept;                           // events per thread per tile
     int64_t n_tiles;
     int64_t tile_start[kMaxChannels + 1];  // first tile of each channel
     int64_t ev_start[kMaxChannels + 1];    // first output position

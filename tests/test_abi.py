@@ -25,8 +25,12 @@ def L():
 
 
 def declared_symbols():
-    text = open(os.path.join(ROOT, "include", "msx.h")).read()
-    return sorted(set(re.findall(r"\b(msx_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            names |= set(re.findall(r"\b(msx_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_binding_exports():
@@ -69,7 +73,7 @@ def test_null_and_precision_errors(L):
     st, _ = _create(L, None)
     assert st == 1
     st, _ = _create(L, json.dumps(W.c1_ee_mumu()), precision=7)
-    assert st == 4
+    assert st == 1 and "precision" in L.msx_last_error(None).decode()
     assert L.msx_create_channels(b"{}", 0, 0, None) == 1
 
 

@@ -10,6 +10,7 @@ import pytest
 import torch
 
 from oracle import flow as F
+import workloads as W
 
 DT = torch.float64
 
@@ -123,7 +124,7 @@ def test_parameter_count_matches_the_shape():
 
 def test_flow_identity_init_round_trip_and_logdet():
     gen = np.random.default_rng(5)
-    p0 = F.init_params(8, 4, 6, 16, gen)
+    p0 = torch.as_tensor(W.flow_params(5, 8, 4, 6, 16), dtype=DT)
     f = F.Flow(8, 4, 6, 16, params=p0)
     u = torch.rand(300, 8, dtype=DT, generator=torch.Generator().manual_seed(6))
     y, ld = f.forward(u)
@@ -201,7 +202,7 @@ def test_bf16_rounding():
 
 def test_bf16_mlp_differs_by_bf16_rounding_only():
     gen = np.random.default_rng(11)
-    p = F.init_params(16, 2, 16, 128, gen) + 0.01 * torch.as_tensor(gen.standard_normal(F.Flow(16, 2).n_params))
+    p = torch.as_tensor(W.flow_params(11, 16, 2, 16, 128, last_scale=0.01), dtype=DT)
     a = F.Flow(16, 2, 16, 128, params=p)
     b = F.Flow(16, 2, 16, 128, params=p, bf16_mlp=True)
     cond = torch.as_tensor(gen.uniform(0, 1, (100, 8)))

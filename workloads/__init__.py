@@ -194,6 +194,26 @@ def c4_multichannel(seed: int = 4, n_channels: int = 24, lo: float = 1e3, hi: fl
     return members, counts
 
 
+def c4_context(seed: int = 4, n_channels: int = 24, lo: float = 1e3, hi: float = 1e6):
+    """The multichannel batch as one context: consecutive runs of the
+    c4_multichannel members become processes (a C1 process with one channel,
+    a C2 process with the C2 channels that follow it), so every channel keeps
+    the local weights of its own process.  Returns (description, counts)."""
+    members, counts = c4_multichannel(seed, n_channels, lo, hi)
+    procs = []
+    c2 = _c2_channels()
+    for cfg, ch in members:
+        if cfg == "c1":
+            procs.append(c1_ee_mumu())
+        else:
+            if not procs or procs[-1]["name"] != "pp4j":
+                d = c2_pp4j()
+                d["channels"] = []
+                procs.append(d)
+            procs[-1]["channels"].append(c2[ch])
+    return {"processes": procs}, counts
+
+
 def counts_powerlaw(n: int, seed: int, lo: float, hi: float, exponent: float = -1.5) -> np.ndarray:
     """Event counts with density ~ n^exponent on [lo, hi] by inverse-CDF sampling
     of seeded Philox uniforms (one per channel)."""
@@ -245,3 +265,45 @@ def philox_uniforms(seed: int, stream: int, e0: int, n: int, d: int) -> np.ndarr
                 break
             out[k] = ((raw[:, j] >> np.uint64(11)).astype(np.float64) + 0.5) * _TWO_M53
     return out
+
+
+def philox_uniforms_f32(seed: int, stream: int, e0: int, n: int, d: int) -> np.ndarray:
+    """24-bit uniforms in (0, 1) as float32, layout [d][n]: the top 24 bits of
+    the same Philox words, (k + 0.5) 2^-24."""
+    out = np.empty((d, n), dtype=np.float32)
+    for g in range((d + 3) // 4):
+        raw = philox_raw(seed, stream, e0, n, g)
+        for j in range(4):
+            k = 4 * g + j
+            if k >= d:
+                break
+            out[k] = ((raw[:, j] >> np.uint64(40)).astype(np.float64) + 0.5) * 2.0 ** -24
+    return out
+
+
+def flow_shapes(dims: int, bins: int, hidden: int):
+    """Per-layer parameter blocks of the coupling flow, in storage order:
+    W1 [hidden][d/2], b1, W2 [hidden][hidden], b2, W3, b3,
+    W4 [(d/2)(3 bins + 1)][hidden], b4."""
+    nh = dims // 2
+    no = nh * (3 * bins + 1)
+    return [(hidden, nh), (hidden,), (hidden, hidden), (hidden,), (hidden, hidden), (hidden,), (no, hidden), (no,)]
+
+
+def flow_params(seed: int, dims: int, layers: int, bins: int, hidden: int, last_scale: float = 0.0) -> np.ndarray:
+    """Flat float32 starting parameters: hidden layers uniform in
+    +-1/sqrt(fan_in); the last layer N(0, last_scale^2) (zero: the flow starts
+    as the identity)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(layers):
+        shapes = flow_shapes(dims, bins, hidden)
+        for i, s in enumerate(shapes):
+            n = int(np.prod(s))
+            if i >= 6:
+                out.append(rng.standard_normal(n) * last_scale if last_scale else np.zeros(n))
+            else:
+                fan_in = s[1] if len(s) == 2 else shapes[i - 1][1]
+                lim = 1.0 / np.sqrt(fan_in)
+                out.append(rng.uniform(-lim, lim, n))
+    return np.concatenate(out).astype(np.float32)

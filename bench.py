@@ -90,6 +90,124 @@ def profiled_traffic():
         return None
 
 
+def _timed(fn, reps):
+    """Average milliseconds of fn() over reps launches (HIP events on the
+    current stream, after one untimed call)."""
+    import torch
+
+    fn()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def mixed_report(n=10_000_000, reps=5):
+    """pp -> t tbar -> 6 (16 dims, Breit-Wigner t and W): FP64 and mixed
+    precision sample throughput on the same events, and the per-quantity error
+    of the mixed results against the FP64 ones."""
+    import workloads as W
+    from paper_2602_06895_amd import MIXED, Context, adapt_vegas
+    from paper_2602_06895_amd.report import precision_error
+
+    c64 = Context(W.c3_ttbar6())
+    cmx = Context(W.c3_ttbar6(), precision=MIXED)
+    adapt_vegas(c64, n_per_channel=100_000, iterations=5, seed=2, stream_id=1)
+    cmx.set_grid(0, c64.get_grid(0))
+    counts = np.array([n])
+    o64 = c64.sample(counts, seed=77, stream_id=0)
+    omx = cmx.sample(counts, seed=77, stream_id=0)
+    t64 = _timed(lambda: c64.sample(counts, seed=77, stream_id=0, out=o64), reps)
+    tmx = _timed(lambda: cmx.sample(counts, seed=77, stream_id=0, out=omx), reps)
+    err = precision_error(omx["p"], omx["w"], o64["p"], o64["w"], c64.max_momenta)
+    c64.close()
+    cmx.close()
+    return {"workload": f"pp->ttbar->6 13 TeV, BW t/W, 16 dims, {n} events per launch",
+            "fp64_events_per_s": n / (t64 / 1e3), "mixed_events_per_s": n / (tmx / 1e3), "speedup": t64 / tmx,
+            "mixed_error_vs_fp64": err}
+
+
+def flow_report(train_steps=400, batch=65536, n_eval=1_000_000, lr=1e-3):
+    """Learned sampler on the pp -> t tbar -> 6 integrand: VEGAS adapted and
+    frozen, then an 8-layer rational-quadratic coupling flow (16 bins, MLP
+    3 x 128, BF16 matrix cores) trained on weights the sampler generates;
+    unweighting efficiency and relative error of the same number of events
+    with and without the flow.  The flow is kept only if its weight variance
+    is below VEGAS's."""
+    import torch
+
+    import workloads as W
+    from paper_2602_06895_amd import FLOW_BF16, Context, Flow, adapt_vegas
+
+    ctx = Context(W.c3_ttbar6())
+    adapt_vegas(ctx, n_per_channel=100_000, iterations=10, seed=3, stream_id=1)
+    ov = ctx.sample(np.array([n_eval]), seed=9, stream_id=4)
+    wv = ov["w"]
+    eff_v, _ = ctx.unweight_eff(wv, 1e-3)
+    rel_v = float(wv.std() / wv.mean()) / math.sqrt(n_eval)
+    flow = Flow(16, 8, 16, 128, mlp=FLOW_BF16)
+    flow.set_params(W.flow_params(31, 16, 8, 16, 128))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = []
+    for s in range(train_steps):
+        o = flow.sample(ctx, 0, batch, seed=10, stream_id=5, counter_offset=s * batch)
+        losses.append(flow.train_step(o["y"], o["wfj"], o["logq"], lr))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    of = flow.sample(ctx, 0, n_eval, seed=11, stream_id=6)
+    wf = of["w"]
+    eff_f, _ = ctx.unweight_eff(wf, 1e-3)
+    rel_f = float(wf.std() / wf.mean()) / math.sqrt(n_eval)
+    # matrix-core throughput of the conditioner: one forward pass of 2^20 events
+    nf = 1 << 20
+    u = torch.rand(16, nf, device="cuda", dtype=torch.float32) * 0.999 + 5e-4
+    ms = _timed(lambda: flow.forward(u), 3)
+    flops = 2.0 * 8 * (8 * 128 + 2 * 128 * 128 + 128 * 392) * nf
+    use_flow = rel_f < rel_v
+    res = {"workload": f"pp->ttbar->6 integrand, VEGAS 10x1e5 then flow {train_steps} x {batch} BF16",
+           "vegas": {"unweighting_eff": eff_v, "rel_error": rel_v, "integral": float(wv.mean())},
+           "flow": {"unweighting_eff": eff_f, "rel_error": rel_f, "integral": float(wf.mean())},
+           "events": n_eval, "eff_ratio_flow_over_vegas": eff_f / eff_v,
+           "rel_error_ratio_vegas_over_flow": rel_v / rel_f, "sampler_kept": "flow" if use_flow else "vegas",
+           "train_seconds": train_s, "loss_first": float(losses[0].cpu()[0]), "loss_last": float(losses[-1].cpu()[0]),
+           "mlp_forward": {"events": nf, "ms": ms, "tflops": flops / (ms / 1e3) / 1e12, "peak_tflops": 2500.0,
+                           "frac": flops / (ms / 1e3) / 1e12 / 2500.0}}
+    flow.close()
+    ctx.close()
+    return res
+
+
+def graph_report(reps=10):
+    """24-channel batch (C1 and C2 topologies, power-law counts) as one
+    persistent launch replayed from a HIP graph, after the autotuner."""
+    import torch
+
+    import workloads as W
+    from paper_2602_06895_amd import Context
+
+    desc, counts = W.c4_context()
+    ctx = Context(desc)
+    N = int(counts.sum())
+    eager_ms = _timed(lambda: ctx.sample(counts, seed=4, stream_id=8), reps)
+    best = ctx.autotune(counts, seed=4, reps=3)
+    ept, grid = ctx.launch_shape()
+    buf = ctx.sample_buffers(N, want_chan=True)
+    dc = torch.from_numpy(counts.astype(np.int64)).cuda()
+    off = torch.zeros(1, dtype=torch.int64, device="cuda")
+    g = ctx.sample_graph(dc, 4, 8, off, buf)
+    graph_ms = _timed(g.launch, reps)
+    g.close()
+    ctx.close()
+    return {"workload": f"24 channels (6 processes), {N} events, counts power-law 1e3..1e6",
+            "eager_ms": eager_ms, "graph_ms": graph_ms, "graph_events_per_s": N / (graph_ms / 1e3),
+            "autotuned": {"events_per_thread": ept, "grid": grid, "ms": best}}
+
+
 def summarize(d: str, events: int):
     """Summary of the rocprofv3 runs under d (rocpd databases written by the
     commands printed below) for the k_sample dispatches of `events` events."""
@@ -146,6 +264,27 @@ def summarize(d: str, events: int):
     print("\n".join(out))
 
 
+def summarize_flow(d: str):
+    """Per-kernel summary of a rocprofv3 kernel trace of `bench.py --flow-only`
+    under d/flow (the coupling-flow kernels; GEMMs split by launch grid)."""
+    import glob
+    import sqlite3
+
+    f = glob.glob(os.path.join(d, "flow", "*_results.db"))
+    c = sqlite3.connect(f[0])
+    out = ["flow kernels (name: dispatches, avg us, total ms)"]
+    for name, cnt, avg, tot in c.execute("select name, count(*), avg(duration), sum(duration) from kernels "
+                                         "group by name order by sum(duration) desc"):
+        short = name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
+        out.append(f"  {short[:60]}: {cnt}, {avg / 1e3:.1f}, {tot / 1e6:.2f}")
+    out.append("k_gemm by grid (x work-items, y, z: dispatches, avg us, vgpr, agpr)")
+    for gx, gy, gz, cnt, avg, vg, ag in c.execute(
+            "select grid_x, grid_y, grid_z, count(*), avg(duration), max(vgpr_count), max(accum_vgpr_count) "
+            "from kernels where name like '%k_gemm%' group by grid_x, grid_y, grid_z order by sum(duration) desc"):
+        out.append(f"  {gx} x {gy} x {gz}: {cnt}, {avg / 1e3:.1f}, {vg}, {ag}")
+    print("\n".join(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,12 +292,23 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--events", type=int, default=N_EVENTS)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the mixed-precision, flow and graph reports")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run device-to-device copies of 1 GiB (scale for HBM byte counters)")
     ap.add_argument("--summarize", metavar="DIR", help="summarise rocprofv3 output under DIR and exit")
+    ap.add_argument("--summarize-flow", metavar="DIR", help="summarise a flow kernel trace under DIR/flow and exit")
+    ap.add_argument("--flow-only", action="store_true", help="only the learned-sampler report")
+    ap.add_argument("--flow-steps", type=int, default=400, help="training steps of the learned sampler")
     args = ap.parse_args()
     if args.summarize:
         summarize(args.summarize, args.events)
+        return
+    if args.summarize_flow:
+        summarize_flow(args.summarize_flow)
+        return
+    if args.flow_only:
+        print(json.dumps({"flow_vs_vegas": flow_report(train_steps=args.flow_steps)}))
         return
     if args.copy_calibration:
         import torch
@@ -256,9 +406,17 @@ def main():
                      "kernel": "k_sample (fused multichannel sample)",
                      "bytes_per_event": BYTES_PER_EVENT, "avg_launch_ms": avg_launch_s * 1e3},
     }
+    ctx.close()
+    del out
+    if not args.no_extras:
+        torch.cuda.empty_cache()
+        result["mixed_precision"] = mixed_report()
+        torch.cuda.empty_cache()
+        result["flow_vs_vegas"] = flow_report(train_steps=args.flow_steps)
+        torch.cuda.empty_cache()
+        result["multichannel_graph"] = graph_report()
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(desc, grids, counts, seed=1)
-    ctx.close()
     print(json.dumps(result))
 
 

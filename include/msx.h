@@ -88,14 +88,15 @@ typedef struct msx_ctx msx_ctx;
 /* Arithmetic of the mapping chain (msx_create_channels `precision`).
  *  MSX_FP64:  every step in FP64.
  *  MSX_MIXED: the well-conditioned transcendentals of the chain -- the power
- *             laws of the G_nu maps (eq. prop_stable_nu), exp/log of the
- *             luminosity map (eq. pdf_sampling) and of the log maps, the
- *             azimuth/polar sines and cosines of the 2->2 blocks and decays,
- *             the toy-PDF powers -- in FP32.  Kallen functions, x - m^2, the
- *             t range, the s-channel mass bounds, square roots of invariants,
- *             the Breit-Wigner map (eq. prop_massive), every boost and the
- *             Jacobian product stay FP64.  Output layout and types are the
- *             same as for MSX_FP64. */
+ *             laws of the G_nu maps (eq. prop_stable_nu; their endpoint
+ *             difference through log1p / expm1 of the FP64 range ratio), the
+ *             exp/log of the log maps, the azimuth sines and cosines of the
+ *             2->2 blocks and decays, the toy-PDF powers -- in FP32.  Kallen
+ *             functions, x - m^2, the t range, the s-channel mass bounds,
+ *             square roots of invariants, the momentum fractions x1, x2 (eq.
+ *             pdf_sampling; the PDFs take 1 - x), the Breit-Wigner map (eq.
+ *             prop_massive), every boost and the Jacobian product stay FP64.
+ *             Output layout and types are the same as for MSX_FP64. */
 enum { MSX_FP64 = 0, MSX_MIXED = 1 };
 
 /* Metadata keys for msx_get_meta (integer keys, in the spirit of the UMAMI

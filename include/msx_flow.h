@@ -81,8 +81,10 @@ msx_status msx_flow_inverse(msx_flow* flow, int64_t n, const float* y, float* u,
 msx_status msx_flow_gradient(msx_flow* flow, int64_t n, const float* y, const double* wfj, const float* logq_old,
                              float* grad, double* loss, void* stream);
 
-/* msx_flow_gradient followed by one Adam step (beta 0.9, 0.999, eps 1e-8,
- * learning rate lr) on the flow's parameters. */
+/* One Adam step (beta 0.9, 0.999, eps 1e-8, learning rate lr) on the
+ * gradient of log L (the direction of msx_flow_gradient's, divided by L: free
+ * of the integrand's units, so eps does not interact with the weight scale).
+ * loss[0] (device, optional) receives L. */
 msx_status msx_flow_train_step(msx_flow* flow, int64_t n, const float* y, const double* wfj, const float* logq_old,
                                float lr, double* loss, void* stream);
 

@@ -87,9 +87,11 @@ enum : int {
 // angles).  MIX = false: FP64 throughout.  MIX = true: these are evaluated in
 // FP32 on the FP64 argument rounded to float and widened back; everything
 // whose rounding is amplified -- differences near threshold (Kallen
-// functions, x - m^2, the t range, the s-channel mass bounds), square roots of
-// invariants, the Breit-Wigner arctangent / tangent (ill-conditioned off
-// resonance), the boosts and the Jacobian product -- stays FP64.
+// functions, x - m^2, the t range, the s-channel mass bounds, the difference
+// of the power-law endpoints), square roots of invariants, the momentum
+// fractions x1, x2 (the PDFs take 1 - x), the Breit-Wigner arctangent /
+// tangent (ill-conditioned off resonance), the boosts and the Jacobian
+// product -- stays FP64.
 template <bool MIX>
 __device__ __forceinline__ double t_exp(double x) {
     return MIX ? (double)expf((float)x) : exp(x);
@@ -114,34 +116,34 @@ __device__ __forceinline__ void t_sincospi(double x, double* s, double* c) {
     }
 }
 
-// x^(1/k) for x >= 0 and integer k in 2..8: an FP32 estimate refined by two
-// Newton steps on y^k = x in FP64 (error ~1 ulp, a third of the cost of
-// pow).  The exponent is split off first so any double is in range.
+// x^(1/k) for x >= 0 and integer k in 2..8 (inv_k = 1/k): an FP32 estimate
+// of z = x^(-1/k) refined by two Newton steps on z^k x = 1, which need no
+// division (z += z (1 - x z^k) / k), then x^(1/k) = x z^(k-1) (error a few
+// ulp).  Outside the FP32 range the exponent is split off first.
 template <bool MIX>
-__device__ __forceinline__ double kth_root(double x, int k) {
+__device__ __forceinline__ double kth_root(double x, int k, double inv_k) {
     if (!(x > 0.0)) return x == 0.0 ? 0.0 : __builtin_nan("");
-    if (MIX) return (double)exp2f(log2f((float)x) / (float)k);
-    int ex;
-    double f = frexp(x, &ex);  // x = f 2^ex, f in [0.5, 1)
-    int q = ex >= 0 ? ex / k : -((-ex + k - 1) / k);
-    int rem = ex - q * k;      // 0 <= rem < k
-    double g = ldexp(f, rem);  // in [0.5, 2^k)
-    float yf = exp2f(log2f((float)g) / (float)k);
-    double y = (double)yf;
-    const double inv_k = 1.0 / k;
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        double yk1 = ipow(y, k - 1);
-        y = ((double)(k - 1) * y + g / yk1) * inv_k;
+    if (MIX) return (double)exp2f(log2f((float)x) * (float)inv_k);
+    int q = 0;
+    double g = x;
+    if (!(x > 1e-30 && x < 1e30)) {
+        int ex;
+        const double f = frexp(x, &ex);  // x = f 2^ex, f in [0.5, 1)
+        q = ex >= 0 ? ex / k : -((-ex + k - 1) / k);
+        g = ldexp(f, ex - q * k);  // in [0.5, 2^k)
     }
-    return ldexp(y, q);
+    double z = (double)exp2f(-log2f((float)g) * (float)inv_k);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) z = fma(z * inv_k, fma(-g, ipow(z, k), 1.0), z);
+    const double y = g * ipow(z, k - 1);
+    return q ? ldexp(y, q) : y;
 }
 
 // (x - m2)^e for the power-law maps: a k-th root when e = 1/k.
 template <int KINDS, bool MIX>
 __device__ __forceinline__ double pow_e(const MapParams& p, double x) {
-    if (!(KINDS & KIND_POW)) return kth_root<MIX>(x, p.int_pow);
-    return p.int_pow ? kth_root<MIX>(x, p.int_pow) : t_pow<MIX>(x, p.e);
+    if (!(KINDS & KIND_POW)) return kth_root<MIX>(x, p.int_pow, p.e);
+    return p.int_pow ? kth_root<MIX>(x, p.int_pow, p.e) : t_pow<MIX>(x, p.e);
 }
 
 // b^n for an integer n >= 1 (square and multiply).
@@ -170,6 +172,18 @@ template <int KINDS, bool MIX>
 __device__ __forceinline__ double map_dyn(const MapParams& p, double r, double xmin, double xmax, double& jac) {
     const int kind = p.kind;
     if ((KINDS & (KIND_POW | KIND_POW_INT)) && kind == MAP_POW) {
+        if (MIX) {
+            // A - B = B ((X / Y)^e - 1) = B expm1(e log1p((xmax - xmin) / Y)) with
+            // Y = xmin - m2: no cancellation of two FP32 powers near threshold
+            const double Y = xmin - p.m2;
+            const double B = pow_e<KINDS, true>(p, Y);
+            const float lr = log1pf((float)((xmax - xmin) / Y));
+            const double AmB = B * (double)expm1f((float)p.e * lr);
+            const double b = B + r * AmB;
+            const double xm = (!(KINDS & KIND_POW) || p.int_pow) ? ipow(b, p.int_pow) : t_pow<true>(b, p.inv_e);
+            jac = AmB * (xm / b) * p.inv_e;
+            return xm + p.m2;
+        }
         double A = pow_e<KINDS, MIX>(p, xmax - p.m2), B = pow_e<KINDS, MIX>(p, xmin - p.m2);
         return pow_core<KINDS, MIX>(p, A, B, r, jac);
     }
@@ -211,13 +225,14 @@ __device__ __forceinline__ double map_static(const InvSpec& iv, double r, double
     return iv.xmin + (iv.xmax - iv.xmin) * r;
 }
 
-// Pure boost of k from the rest frame of P (mass m) into the frame of P.
-__device__ __forceinline__ void boost_by(double Pe, double Px, double Py, double Pz, double m, double& ke,
-                                         double& kx, double& ky, double& kz) {
+// Pure boost of k from the rest frame of P (mass m) into the frame of P,
+// with inv_m = 1/m and inv_em = 1/(E_P + m) supplied (shared by the boosts of
+// one operation).
+__device__ __forceinline__ void boost_by(double Pe, double Px, double Py, double Pz, double inv_m, double inv_em,
+                                         double& ke, double& kx, double& ky, double& kz) {
     double pk = Px * kx + Py * ky + Pz * kz;
-    double inv_m = 1.0 / m;
     double e = (Pe * ke + pk) * inv_m;
-    double c = (pk / (Pe + m) + ke) * inv_m;
+    double c = (pk * inv_em + ke) * inv_m;
     ke = e;
     kx += c * Px;
     ky += c * Py;
@@ -295,9 +310,10 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
     double x1 = 1.0, x2 = 1.0, L = 0.0;
     if (hadronic) {
         double r = next();
-        L = t_log<MIX>(shat / s_lab);
-        x1 = t_exp<MIX>(r * L);
-        x2 = t_exp<MIX>((1.0 - r) * L);
+        // FP64 in both precisions: the PDFs take 1 - x, which cancels for x -> 1
+        L = log(shat / s_lab);
+        x1 = exp(r * L);
+        x2 = exp((1.0 - r) * L);
         jac *= -L / s_lab;
     }
 
@@ -347,6 +363,7 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
         double e2 = (m0sq - (m1s - m2s)) * inv_2m0;
         double vx = q * sth * cphi, vy = q * sth * sphi, vz = q * cth;
         double k1e = e1, k1x, k1y, k1z, k2e = e2, k2x, k2y, k2z;
+        double inv_m0 = 0.0, inv_em = 0.0;
         if (bs.com) {
             // P at rest, p_A along +z: no rotation, no boost
             k1x = vx;
@@ -354,15 +371,18 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
             k1z = vz;
         } else {
             // direction of p_A in the rest frame of P, then R(phi_A, theta_A)
+            inv_m0 = 1.0 / m0;
+            inv_em = 1.0 / (Pe + m0);
             double ae = Ae, ax = Ax, ay = Ay, az = Az;
-            boost_by(Pe, -Px, -Py, -Pz, m0, ae, ax, ay, az);
+            boost_by(Pe, -Px, -Py, -Pz, inv_m0, inv_em, ae, ax, ay, az);
             double inv_len = 1.0 / sqrt(ax * ax + ay * ay + az * az);
             double nx = ax * inv_len, ny = ay * inv_len, nz = az * inv_len;
             double st = sqrt(nx * nx + ny * ny);
             double cp = 1.0, sp = 0.0;
             if (st > 0.0) {
-                cp = nx / st;
-                sp = ny / st;
+                const double ist = 1.0 / st;
+                cp = nx * ist;
+                sp = ny * ist;
             }
             double rx = vx * nz + vz * st;
             double ry = vy;
@@ -375,8 +395,8 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
         k2y = -k1y;
         k2z = -k1z;
         if (!bs.com) {
-            boost_by(Pe, Px, Py, Pz, m0, k1e, k1x, k1y, k1z);
-            boost_by(Pe, Px, Py, Pz, m0, k2e, k2x, k2y, k2z);
+            boost_by(Pe, Px, Py, Pz, inv_m0, inv_em, k1e, k1x, k1y, k1z);
+            boost_by(Pe, Px, Py, Pz, inv_m0, inv_em, k2e, k2x, k2y, k2z);
         }
         jac *= jt * (2.0 * kPiD) / (4.0 * sqrt(lamab));
         // store both outputs and update the legs with uniform 0/1 factors:
@@ -430,8 +450,9 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
         if (!ds.parent_rest) {
             const int ps = slot_index<NS>(ds.parent_slot);
             double Pe = E[ps], Px = X[ps], Py = Y[ps], Pz = Z[ps];
-            boost_by(Pe, Px, Py, Pz, m0, k1e, k1x, k1y, k1z);
-            boost_by(Pe, Px, Py, Pz, m0, k2e, k2x, k2y, k2z);
+            const double inv_m = 1.0 / m0, inv_em = 1.0 / (Pe + m0);
+            boost_by(Pe, Px, Py, Pz, inv_m, inv_em, k1e, k1x, k1y, k1z);
+            boost_by(Pe, Px, Py, Pz, inv_m, inv_em, k2e, k2x, k2y, k2z);
         }
         E[NS - 2 - 2 * di] = k1e;
         X[NS - 2 - 2 * di] = k1x;
@@ -511,22 +532,25 @@ __device__ __forceinline__ double integrand_alpha(const ProcessTab* __restrict__
     double qv[kMaxUniq];
     const int nu = pt->n_uniq;
     for (int u = 0; u < nu; ++u) qv[u] = inv_q2(pt, u, pae, pax, pay, paz, get);
+    // propagator factors: one reciprocal of the product of the denominators
     const int nf = pt->n_fprop;
+    double fden = 1.0;
     for (int i = 0; i < nf; ++i) {
         double q2 = qv[pt->f_uniq[i]];
         if (pt->f_bw[i]) {
             double d = q2 - pt->f_m2[i];
-            f *= 1.0 / (d * d + pt->f_mw[i] * pt->f_mw[i]);
+            fden *= d * d + pt->f_mw[i] * pt->f_mw[i];
         } else {
-            f *= 1.0 / (fabs(q2) + pt->f_mu2[i]);
+            fden *= fabs(q2) + pt->f_mu2[i];
         }
     }
+    if (nf > 0) f /= fden;
     double alpha = 1.0;
     const int nc = pt->n_chan;
     if (nc > 1) {
         double den = 0.0, mine = 0.0;
         for (int c = 0; c < nc; ++c) {
-            double P = 1.0;
+            double D = 1.0;
             uint32_t m = pt->chan_mask[c];
             while (m) {
                 int u = __builtin_ctz(m);
@@ -534,12 +558,13 @@ __device__ __forceinline__ double integrand_alpha(const ProcessTab* __restrict__
                 double q2 = qv[u];
                 if (pt->uniq_massive[u]) {
                     double d = q2 - pt->uniq_m2[u];
-                    P *= 1.0 / (d * d + pt->uniq_mw[u] * pt->uniq_mw[u]);
+                    D *= d * d + pt->uniq_mw[u] * pt->uniq_mw[u];
                 } else {
                     double d = fabs(q2) + pt->alpha_mu2;
-                    P *= 1.0 / (d * d);
+                    D *= d * d;
                 }
             }
+            const double P = 1.0 / D;
             den += P;
             if (c == chan_in_proc) mine = P;
         }

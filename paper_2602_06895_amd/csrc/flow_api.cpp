@@ -231,11 +231,12 @@ msx_status inverse_saving(msx_flow* f, int64_t n, const float* y, hipStream_t s)
 }
 
 msx_status gradient(msx_flow* f, int64_t n, const float* y, const double* wfj, const float* logq_old, float* grad,
-                    double* loss, hipStream_t s) {
+                    double* loss, bool log_loss, hipStream_t s) {
     if (msx_status st = ensure_work(f, n)) return st;
     if (!f->lpart) FHIP(f, fmalloc(&f->lpart, sizeof(double) * 1025), "flow loss partials");
     if (msx_status st = inverse_saving(f, n, y, s)) return st;
-    FHIP(f, launch_flow_loss(n, wfj, f->logq, logq_old, f->G, f->lpart, loss ? loss : f->lpart + 1024, s), "flow loss");
+    FHIP(f, launch_flow_loss(n, wfj, f->logq, logq_old, f->G, f->lpart, loss ? loss : f->lpart + 1024, log_loss, s),
+         "flow loss");
     const size_t zs = (size_t)f->d * n;
     FHIP(f, hipMemsetAsync(f->adj, 0, sizeof(float) * zs, s), "flow clear");
     const int H = f->H, nh = f->nh, no = f->n_out;
@@ -446,7 +447,7 @@ msx_status msx_flow_gradient(msx_flow* f, int64_t n, const float* y, const doubl
     if (n == 0) return ffail(f, MSX_ERR_ARG, "empty batch");
     if (!y || !wfj || !logq_old || !grad) return ffail(f, MSX_ERR_ARG, "y, wfj, logq_old and grad are required");
     FHIP(f, hipSetDevice(f->device), "hipSetDevice");
-    return gradient(f, n, y, wfj, logq_old, grad, loss, (hipStream_t)stream);
+    return gradient(f, n, y, wfj, logq_old, grad, loss, false, (hipStream_t)stream);
 }
 
 msx_status msx_flow_train_step(msx_flow* f, int64_t n, const float* y, const double* wfj, const float* logq_old,
@@ -458,7 +459,7 @@ msx_status msx_flow_train_step(msx_flow* f, int64_t n, const float* y, const dou
     if (!(lr > 0.0f) || !std::isfinite(lr)) return ffail(f, MSX_ERR_ARG, "lr must be positive");
     hipStream_t s = (hipStream_t)stream;
     FHIP(f, hipSetDevice(f->device), "hipSetDevice");
-    if (msx_status st = gradient(f, n, y, wfj, logq_old, f->grad, loss, s)) return st;
+    if (msx_status st = gradient(f, n, y, wfj, logq_old, f->grad, loss, true, s)) return st;
     const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
     f->adam_t += 1;
     const double c1 = 1.0 - std::pow(b1, (double)f->adam_t), c2 = 1.0 - std::pow(b2, (double)f->adam_t);

@@ -24,21 +24,21 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
-// GEMM on the matrix cores: 64 x 64 output tile per 256-thread workgroup,
-// 32-deep K steps through LDS; wave w owns the 32 x 32 quarter (w / 2, w % 2)
-// as 2 x 2 tiles of 16 x 16.
+// GEMM on the matrix cores: 64 x 128 output tile per 256-thread workgroup,
+// 64-deep K steps through LDS; wave w owns rows 32 (w / 2).., columns
+// 64 (w % 2).. as 2 x 4 tiles of 16 x 16.
 //   BF16: v_mfma_f32_16x16x32_bf16, lane l holds A[l % 16][8 (l / 16) + 0..7]
 //         and B[8 (l / 16) + 0..7][l % 16];
 //   FP32: v_mfma_f32_16x16x4_f32,  lane l holds A[l % 16][l / 16], B[l / 16][l % 16];
 //   both: lane l receives D[4 (l / 16) + 0..3][l % 16].
 // ---------------------------------------------------------------------------
-constexpr int BM = 64, BN = 64, BK = 32, GT = 256;
+constexpr int BM = 64, BN = 128, BK = 64, GT = 256;
 
 template <class T>
 struct Lds;
 template <>
 struct Lds<__bf16> {
-    static constexpr int LDK = BK + 8;  // 80-byte rows keep 16-byte operand reads aligned
+    static constexpr int LDK = BK + 8;  // 144-byte rows keep 16-byte operand reads aligned
 };
 template <>
 struct Lds<float> {
@@ -50,60 +50,94 @@ __device__ __forceinline__ T to_t(float v) {
     return (T)v;
 }
 
-// One 64 x 32 tile of P (rows r0.., k k0..) into S[r][k]; zero outside
-// rows < R and k < kend.  8 elements per thread, walking the unit stride.
+// Eight consecutive elements from global memory: one or two 16-byte loads
+// when the run is in bounds and aligned, element by element otherwise.
 template <class T>
+__device__ __forceinline__ void load8(const T* __restrict__ src, int valid, T (&v)[8]) {
+    if (valid == 8 && (((uintptr_t)src) & 15) == 0) {
+        constexpr int W = (int)(8 * sizeof(T) / 16);  // 16-byte words: 1 (BF16) or 2 (FP32)
+        uint4 q[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) q[i] = ((const uint4*)src)[i];
+        __builtin_memcpy(v, q, sizeof v);
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = i < valid ? src[i] : to_t<T>(0.0f);
+}
+
+// One ROWS x BK tile of P (rows r0.., k k0..) into S[r][k]; zero outside
+// rows < R and k < kend.  Runs of 8 elements along the unit stride.
+template <class T, int ROWS>
 __device__ __forceinline__ void load_tile(const T* __restrict__ P, int64_t s_r, int64_t s_k, int R, int r0, int k0,
                                           int kend, T (*S)[Lds<T>::LDK], int tid) {
+    constexpr int RUNS = ROWS * BK / 8 / GT;
+    T v[8];
     if (s_r == 1 && s_k != 1) {
-        const int kk = tid >> 3, rb = (tid & 7) * 8;
-        const int k = k0 + kk;
+        // runs of 8 consecutive rows at one k
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int r = r0 + rb + i;
-            T v = to_t<T>(0.0f);
-            if (r < R && k < kend) v = P[(int64_t)r + (int64_t)k * s_k];
-            S[rb + i][kk] = v;
+        for (int t = 0; t < RUNS; ++t) {
+            const int q = tid + GT * t;
+            const int kk = q / (ROWS / 8), rb = (q % (ROWS / 8)) * 8;
+            const int k = k0 + kk;
+            const int valid = k < kend ? max(0, min(8, R - (r0 + rb))) : 0;
+            load8<T>(P + (int64_t)(r0 + rb) + (int64_t)k * s_k, valid, v);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) S[rb + i][kk] = v[i];
         }
     } else {
-        const int rr = tid >> 2, kb = (tid & 3) * 8;
-        const int r = r0 + rr;
+        // runs of 8 consecutive k of one row
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int k = k0 + kb + i;
-            T v = to_t<T>(0.0f);
-            if (r < R && k < kend) v = P[(int64_t)r * s_r + (int64_t)k * s_k];
-            S[rr][kb + i] = v;
+        for (int t = 0; t < RUNS; ++t) {
+            const int q = tid + GT * t;
+            const int rr = q / (BK / 8), kb = (q % (BK / 8)) * 8;
+            const int r = r0 + rr;
+            if (s_k == 1) {
+                const int valid = r < R ? max(0, min(8, kend - (k0 + kb))) : 0;
+                load8<T>(P + (int64_t)r * s_r + (k0 + kb), valid, v);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int k = k0 + kb + i;
+                    v[i] = (r < R && k < kend) ? P[(int64_t)r * s_r + (int64_t)k * s_k] : to_t<T>(0.0f);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) S[rr][kb + i] = v[i];
         }
     }
 }
 
 __device__ __forceinline__ void mma(const __bf16 (*As)[Lds<__bf16>::LDK], const __bf16 (*Bs)[Lds<__bf16>::LDK], int wm,
-                                    int wn, int lane, floatx4 (&acc)[2][2]) {
-    bf16x8 a[2], b[2];
+                                    int wn, int lane, floatx4 (&acc)[2][4]) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) a[i] = *(const bf16x8*)&As[wm + i * 16 + (lane & 15)][8 * (lane >> 4)];
+    for (int ks = 0; ks < BK / 32; ++ks) {
+        bf16x8 a[2], b[4];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) b[j] = *(const bf16x8*)&Bs[wn + j * 16 + (lane & 15)][8 * (lane >> 4)];
+        for (int i = 0; i < 2; ++i) a[i] = *(const bf16x8*)&As[wm + i * 16 + (lane & 15)][32 * ks + 8 * (lane >> 4)];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-}
-
-__device__ __forceinline__ void mma(const float (*As)[Lds<float>::LDK], const float (*Bs)[Lds<float>::LDK], int wm,
-                                    int wn, int lane, floatx4 (&acc)[2][2]) {
-#pragma unroll
-    for (int ks = 0; ks < BK / 4; ++ks) {
-        float a[2], b[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = As[wm + i * 16 + (lane & 15)][4 * ks + (lane >> 4)];
-#pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = Bs[wn + j * 16 + (lane & 15)][4 * ks + (lane >> 4)];
+        for (int j = 0; j < 4; ++j) b[j] = *(const bf16x8*)&Bs[wn + j * 16 + (lane & 15)][32 * ks + 8 * (lane >> 4)];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+}
+
+__device__ __forceinline__ void mma(const float (*As)[Lds<float>::LDK], const float (*Bs)[Lds<float>::LDK], int wm,
+                                    int wn, int lane, floatx4 (&acc)[2][4]) {
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+        float a[2], b[4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = As[wm + i * 16 + (lane & 15)][4 * ks + (lane >> 4)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = Bs[wn + j * 16 + (lane & 15)][4 * ks + (lane >> 4)];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
 }
 
@@ -118,15 +152,15 @@ __global__ __launch_bounds__(GT) void k_gemm(GemmArgs g, int kchunk) {
     const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
     const int kbeg = blockIdx.z * kchunk;
     const int kend = min(g.K, kbeg + kchunk);
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    floatx4 acc[2][2];
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 64;
+    floatx4 acc[2][4];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
     for (int k0 = kbeg; k0 < kend; k0 += BK) {
-        load_tile<T>(A, g.a_m, g.a_k, g.M, m0, k0, kend, As, tid);
-        load_tile<T>(B, g.b_n, g.b_k, g.N, n0, k0, kend, Bs, tid);
+        load_tile<T, BM>(A, g.a_m, g.a_k, g.M, m0, k0, kend, As, tid);
+        load_tile<T, BN>(B, g.b_n, g.b_k, g.N, n0, k0, kend, Bs, tid);
         __syncthreads();
         mma(As, Bs, wm, wn, lane, acc);
         __syncthreads();
@@ -134,7 +168,7 @@ __global__ __launch_bounds__(GT) void k_gemm(GemmArgs g, int kchunk) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int r = m0 + wm + i * 16 + 4 * (lane >> 4) + e;
@@ -281,39 +315,63 @@ __device__ __forceinline__ float spline_slope(const Bin& b, float xi) {
     return s * s * (b.d1 * xi * xi + 2.0f * s * om + b.d0 * (1.0f - xi) * (1.0f - xi)) / (den * den);
 }
 
+// The spline kernels take one wave of kSplineT events per workgroup and walk
+// the transformed coordinates; for each, the events' 3K + 1 parameters (a
+// strided slab of theta) are staged through LDS with coalesced loads (odd row
+// length: conflict-free reads).
+constexpr int kSplineT = 64;
+
+__device__ __forceinline__ void load_slab(const float* __restrict__ theta, int64_t ldt, int64_t e0, int rows, int j,
+                                          int P, float* __restrict__ slab) {
+    const int total = rows * P;
+    for (int i = threadIdx.x; i < total; i += kSplineT) {
+        const int r = i / P, c = i - r * P;
+        slab[i] = theta[(e0 + r) * ldt + (int64_t)j * P + c];
+    }
+}
+
 template <bool INV>
-__global__ __launch_bounds__(256) void k_spline(float* __restrict__ z, int64_t n, const float* __restrict__ theta,
-                                                int64_t ldt, int nh, Idx trans, int K, float* __restrict__ logdet) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
+__global__ __launch_bounds__(kSplineT) void k_spline(float* __restrict__ z, int64_t n, const float* __restrict__ theta,
+                                                     int64_t ldt, int nh, Idx trans, int K, float* __restrict__ logdet) {
+    extern __shared__ float slab[];
+    const int64_t e0 = (int64_t)blockIdx.x * kSplineT;
+    const int rows = (int)min<int64_t>(kSplineT, n - e0);
+    const int P = 3 * K + 1;
+    const int64_t e = e0 + threadIdx.x;
+    const bool active = threadIdx.x < rows;
     float ld = 0.0f;
     for (int j = 0; j < nh; ++j) {
-        const float* th = theta + e * ldt + (int64_t)j * (3 * K + 1);
-        float* zp = z + (int64_t)trans.v[j] * n + e;
-        const float v = *zp;
-        float mw, sw, mh, sh;
-        const Bin b = spline_bin<INV>(th, K, v, mw, sw, mh, sh);
-        const float s = b.h / b.w;
-        const float kap = b.d1 + b.d0 - 2.0f * s;
-        float xi, out;
-        if (!INV) {
-            xi = (v - b.x0) / b.w;
-            const float om = xi * (1.0f - xi);
-            out = b.y0 + b.h * (s * xi * xi + b.d0 * om) / (s + kap * om);
-        } else {
-            const float dy = v - b.y0;
-            const float qa = b.h * (s - b.d0) + dy * kap;
-            const float qb = b.h * b.d0 - dy * kap;
-            const float qc = -s * dy;
-            const float disc = fmaxf(qb * qb - 4.0f * qa * qc, 0.0f);
-            xi = 2.0f * qc / (-qb - sqrtf(disc));
-            out = b.x0 + xi * b.w;
+        load_slab(theta, ldt, e0, rows, j, P, slab);
+        __syncthreads();
+        if (active) {
+            const float* th = slab + threadIdx.x * P;
+            float* zp = z + (int64_t)trans.v[j] * n + e;
+            const float v = *zp;
+            float mw, sw, mh, sh;
+            const Bin b = spline_bin<INV>(th, K, v, mw, sw, mh, sh);
+            const float s = b.h / b.w;
+            const float kap = b.d1 + b.d0 - 2.0f * s;
+            float xi, out;
+            if (!INV) {
+                xi = (v - b.x0) / b.w;
+                const float om = xi * (1.0f - xi);
+                out = b.y0 + b.h * (s * xi * xi + b.d0 * om) / (s + kap * om);
+            } else {
+                const float dy = v - b.y0;
+                const float qa = b.h * (s - b.d0) + dy * kap;
+                const float qb = b.h * b.d0 - dy * kap;
+                const float qc = -s * dy;
+                const float disc = fmaxf(qb * qb - 4.0f * qa * qc, 0.0f);
+                xi = 2.0f * qc / (-qb - sqrtf(disc));
+                out = b.x0 + xi * b.w;
+            }
+            const float g = spline_slope(b, xi);
+            ld += INV ? -logf(g) : logf(g);
+            *zp = out;
         }
-        const float g = spline_slope(b, xi);
-        ld += INV ? -logf(g) : logf(g);
-        *zp = out;
+        __syncthreads();
     }
-    logdet[e] += ld;
+    if (active) logdet[e] += ld;
 }
 
 // Forward-mode dual numbers with 7 tangents: (y, x0, w, y0, h, d0, d1).
@@ -387,61 +445,78 @@ __device__ __forceinline__ D7 dlog(const D7& a) {
 }
 
 // Reverse mode through the inverse spline of one layer (see flow_launch.h).
+// The parameter slab comes in through LDS and the parameter gradients go out
+// through a second LDS slab with coalesced stores.
 template <class T>
-__global__ __launch_bounds__(256) void k_spline_backward(const float* __restrict__ y, float* __restrict__ adj,
-                                                         int64_t n, const float* __restrict__ theta, int64_t ldt,
-                                                         int nh, Idx trans, int K, const float* __restrict__ G,
-                                                         T* __restrict__ dtheta) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
-    const float ge = G[e];
+__global__ __launch_bounds__(kSplineT) void k_spline_backward(const float* __restrict__ y, float* __restrict__ adj,
+                                                              int64_t n, const float* __restrict__ theta, int64_t ldt,
+                                                              int nh, Idx trans, int K, const float* __restrict__ G,
+                                                              T* __restrict__ dtheta) {
+    extern __shared__ float slab[];
     const int P = 3 * K + 1;
+    float* dslab = slab + kSplineT * P;
+    const int64_t e0 = (int64_t)blockIdx.x * kSplineT;
+    const int rows = (int)min<int64_t>(kSplineT, n - e0);
+    const int64_t e = e0 + threadIdx.x;
+    const bool active = threadIdx.x < rows;
+    const float ge = active ? G[e] : 0.0f;
     for (int j = 0; j < nh; ++j) {
-        const float* th = theta + e * ldt + (int64_t)j * P;
-        T* dth = dtheta + e * ldt + (int64_t)j * P;
-        const int64_t zi = (int64_t)trans.v[j] * n + e;
-        const float v = y[zi];
-        float mw, sw, mh, sh;
-        const Bin bn = spline_bin<true>(th, K, v, mw, sw, mh, sh);
-        // x = S^-1(y) and ld = log (S^-1)'(y) = -log S'(x) as duals
-        const D7 Y = dvar(v, 0), X0 = dvar(bn.x0, 1), W = dvar(bn.w, 2), Y0 = dvar(bn.y0, 3), H = dvar(bn.h, 4),
-                 Dd0 = dvar(bn.d0, 5), Dd1 = dvar(bn.d1, 6);
-        const D7 s = H / W;
-        const D7 dy = Y - Y0;
-        const D7 kap = Dd1 + Dd0 - 2.0f * s;
-        const D7 qa = H * (s - Dd0) + dy * kap;
-        const D7 qb = H * Dd0 - dy * kap;
-        const D7 qc = dconst(0.0f) - s * dy;
-        D7 disc = qb * qb - 4.0f * (qa * qc);
-        disc.v = fmaxf(disc.v, 1e-30f);
-        const D7 xi = (2.0f * qc) / (dconst(0.0f) - qb - dsqrt(disc));
-        const D7 X = X0 + xi * W;
-        const D7 om = xi * (dconst(1.0f) - xi);
-        const D7 den = s + kap * om;
-        const D7 omx = dconst(1.0f) - xi;
-        const D7 num = s * s * (Dd1 * xi * xi + 2.0f * (s * om) + Dd0 * omx * omx);
-        const D7 ld = 2.0f * dlog(den) - dlog(num);
-        const float ax = adj[zi];
-        float gp[7];
+        load_slab(theta, ldt, e0, rows, j, P, slab);
+        __syncthreads();
+        if (active) {
+            const float* th = slab + threadIdx.x * P;
+            float* dth = dslab + threadIdx.x * P;
+            const int64_t zi = (int64_t)trans.v[j] * n + e;
+            const float v = y[zi];
+            float mw, sw, mh, sh;
+            const Bin bn = spline_bin<true>(th, K, v, mw, sw, mh, sh);
+            // x = S^-1(y) and ld = log (S^-1)'(y) = -log S'(x) as duals
+            const D7 Y = dvar(v, 0), X0 = dvar(bn.x0, 1), W = dvar(bn.w, 2), Y0 = dvar(bn.y0, 3), H = dvar(bn.h, 4),
+                     Dd0 = dvar(bn.d0, 5), Dd1 = dvar(bn.d1, 6);
+            const D7 s = H / W;
+            const D7 dy = Y - Y0;
+            const D7 kap = Dd1 + Dd0 - 2.0f * s;
+            const D7 qa = H * (s - Dd0) + dy * kap;
+            const D7 qb = H * Dd0 - dy * kap;
+            const D7 qc = dconst(0.0f) - s * dy;
+            D7 disc = qb * qb - 4.0f * (qa * qc);
+            disc.v = fmaxf(disc.v, 1e-30f);
+            const D7 xi = (2.0f * qc) / (dconst(0.0f) - qb - dsqrt(disc));
+            const D7 X = X0 + xi * W;
+            const D7 om = xi * (dconst(1.0f) - xi);
+            const D7 den = s + kap * om;
+            const D7 omx = dconst(1.0f) - xi;
+            const D7 num = s * s * (Dd1 * xi * xi + 2.0f * (s * om) + Dd0 * omx * omx);
+            const D7 ld = 2.0f * dlog(den) - dlog(num);
+            const float ax = adj[zi];
+            float gp[7];
 #pragma unroll
-        for (int i = 0; i < 7; ++i) gp[i] = ax * X.g[i] + ge * ld.g[i];
-        adj[zi] = gp[0];
-        // to the unconstrained parameters: softmax of widths / heights, softplus of slopes
-        const float Cw = 1.0f - K * kMinW, Ch = 1.0f - K * kMinH;
-        const float sumw = gp[1] * bn.pw + gp[2] * (expf(th[bn.k] - mw) / sw);
-        const float sumh = gp[3] * bn.ph + gp[4] * (expf(th[K + bn.k] - mh) / sh);
-        for (int i = 0; i < K; ++i) {
-            const float pwi = expf(th[i] - mw) / sw, phi = expf(th[K + i] - mh) / sh;
-            const float dwi = (i < bn.k ? gp[1] : 0.0f) + (i == bn.k ? gp[2] : 0.0f);
-            const float dhi = (i < bn.k ? gp[3] : 0.0f) + (i == bn.k ? gp[4] : 0.0f);
-            dth[i] = to_t<T>(Cw * pwi * (dwi - sumw));
-            dth[K + i] = to_t<T>(Ch * phi * (dhi - sumh));
+            for (int i = 0; i < 7; ++i) gp[i] = ax * X.g[i] + ge * ld.g[i];
+            adj[zi] = gp[0];
+            // to the unconstrained parameters: softmax of widths / heights, softplus of slopes
+            const float Cw = 1.0f - K * kMinW, Ch = 1.0f - K * kMinH;
+            const float sumw = gp[1] * bn.pw + gp[2] * (expf(th[bn.k] - mw) / sw);
+            const float sumh = gp[3] * bn.ph + gp[4] * (expf(th[K + bn.k] - mh) / sh);
+            for (int i = 0; i < K; ++i) {
+                const float pwi = expf(th[i] - mw) / sw, phi = expf(th[K + i] - mh) / sh;
+                const float dwi = (i < bn.k ? gp[1] : 0.0f) + (i == bn.k ? gp[2] : 0.0f);
+                const float dhi = (i < bn.k ? gp[3] : 0.0f) + (i == bn.k ? gp[4] : 0.0f);
+                dth[i] = Cw * pwi * (dwi - sumw);
+                dth[K + i] = Ch * phi * (dhi - sumh);
+            }
+            const float s0 = slope_shift();
+            for (int i = 0; i <= K; ++i) {
+                const float dd = (i == bn.k ? gp[5] : 0.0f) + (i == bn.k + 1 ? gp[6] : 0.0f);
+                dth[2 * K + i] = dd * sigmoid_f(th[2 * K + i] + s0);
+            }
         }
-        const float s0 = slope_shift();
-        for (int i = 0; i <= K; ++i) {
-            const float dd = (i == bn.k ? gp[5] : 0.0f) + (i == bn.k + 1 ? gp[6] : 0.0f);
-            dth[2 * K + i] = to_t<T>(dd * sigmoid_f(th[2 * K + i] + s0));
+        __syncthreads();
+        const int total = rows * P;
+        for (int i = threadIdx.x; i < total; i += kSplineT) {
+            const int r = i / P, c = i - r * P;
+            dtheta[(e0 + r) * ldt + (int64_t)j * P + c] = to_t<T>(dslab[i]);
         }
+        __syncthreads();
     }
 }
 
@@ -477,6 +552,13 @@ __global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ p
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) loss[0] = (((red[0] + red[1]) + red[2]) + red[3]) * inv_n;
+}
+
+// G[e] /= loss: the gradient of log L instead of L
+__global__ __launch_bounds__(256) void k_scale_by_loss(int64_t n, const double* __restrict__ loss,
+                                                       float* __restrict__ G) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) G[i] = (float)((double)G[i] / loss[0]);
 }
 
 template <class T>
@@ -599,10 +681,12 @@ hipError_t launch_spline(bool inverse, float* z, int64_t n, const float* theta, 
                          const int32_t* trans_host, int K, float* logdet, hipStream_t s) {
     if (n == 0) return hipSuccess;
     Idx t = make_idx(trans_host, n_half);
+    const unsigned nb = (unsigned)((n + kSplineT - 1) / kSplineT);
+    const size_t lds = sizeof(float) * kSplineT * (3 * K + 1);
     if (inverse)
-        k_spline<true><<<blocks(n), 256, 0, s>>>(z, n, theta, ldt, n_half, t, K, logdet);
+        k_spline<true><<<nb, kSplineT, lds, s>>>(z, n, theta, ldt, n_half, t, K, logdet);
     else
-        k_spline<false><<<blocks(n), 256, 0, s>>>(z, n, theta, ldt, n_half, t, K, logdet);
+        k_spline<false><<<nb, kSplineT, lds, s>>>(z, n, theta, ldt, n_half, t, K, logdet);
     return hipGetLastError();
 }
 
@@ -611,10 +695,12 @@ hipError_t launch_spline_backward(int type, const float* y, float* adj, int64_t 
                                   hipStream_t s) {
     if (n == 0) return hipSuccess;
     Idx t = make_idx(trans_host, n_half);
+    const unsigned nb = (unsigned)((n + kSplineT - 1) / kSplineT);
+    const size_t lds = 2 * sizeof(float) * kSplineT * (3 * K + 1);
     if (type == FT_BF16)
-        k_spline_backward<__bf16><<<blocks(n), 256, 0, s>>>(y, adj, n, theta, ldt, n_half, t, K, G, (__bf16*)dtheta);
+        k_spline_backward<__bf16><<<nb, kSplineT, lds, s>>>(y, adj, n, theta, ldt, n_half, t, K, G, (__bf16*)dtheta);
     else
-        k_spline_backward<float><<<blocks(n), 256, 0, s>>>(y, adj, n, theta, ldt, n_half, t, K, G, (float*)dtheta);
+        k_spline_backward<float><<<nb, kSplineT, lds, s>>>(y, adj, n, theta, ldt, n_half, t, K, G, (float*)dtheta);
     return hipGetLastError();
 }
 
@@ -626,12 +712,15 @@ hipError_t launch_scatter_add(float* adj, const float* dx0, int64_t n, int n_con
 }
 
 hipError_t launch_flow_loss(int64_t n, const double* wfj, const float* logq, const float* logq_old, float* G,
-                            double* part, double* loss, hipStream_t s) {
+                            double* part, double* loss, bool log_loss, hipStream_t s) {
     if (n == 0) return hipSuccess;
     k_flow_loss<<<kLossBlocks, 256, 0, s>>>(n, wfj, logq, logq_old, G, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_loss_final<<<1, 256, 0, s>>>(part, kLossBlocks, 1.0 / (double)n, loss);
+    e = hipGetLastError();
+    if (e != hipSuccess || !log_loss) return e;
+    k_scale_by_loss<<<blocks(n), 256, 0, s>>>(n, loss, G);
     return hipGetLastError();
 }
 

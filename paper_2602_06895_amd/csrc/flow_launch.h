@@ -75,9 +75,9 @@ hipError_t launch_scatter_add(float* adj, const float* dx0, int64_t n, int n_con
 
 // G[b] = -F_b exp(-logq_b - logq_old_b) / n with F_b = wfj_b^2, and the loss
 // sum_b F_b exp(...) / n into loss[0] (deterministic two-pass sum; `part`
-// holds 1024 doubles).
+// holds 1024 doubles).  log_loss: G is then divided by the loss (dlogL/dlogq).
 hipError_t launch_flow_loss(int64_t n, const double* wfj, const float* logq, const float* logq_old, float* G,
-                            double* part, double* loss, hipStream_t s);
+                            double* part, double* loss, bool log_loss, hipStream_t s);
 
 // Adam step on P parameters (bias corrections folded into lr_t, eps_t by the
 // caller), then the operand copy of the parameters in `type`.

@@ -93,7 +93,8 @@ def test_gradient_matches_oracle(torch, mlp):
     torch.cuda.synchronize()
     orc = _oracle(params, bf16=(mlp == 0))
     yy = _t.from_numpy(y.cpu().numpy().T.astype(np.float64))
-    lr, gr = orc.loss_and_grad(yy, _t.from_numpy(wfj.cpu().numpy()), _t.from_numpy(lqo.cpu().numpy().astype(np.float64)))
+    fj = _t.from_numpy(wfj.cpu().numpy())
+    lr, gr = orc.loss_and_grad(yy, fj * fj, _t.from_numpy(lqo.cpu().numpy().astype(np.float64)))
     gg = g.cpu().numpy().astype(np.float64)
     grn = gr.numpy()
     rel = np.linalg.norm(gg - grn) / np.linalg.norm(grn)
@@ -113,11 +114,12 @@ def test_adam_first_step(torch):
     u = _u(n, seed=7)
     y, ld = f.forward(torch.from_numpy(u).cuda())
     wfj = torch.from_numpy(np.random.default_rng(8).uniform(0.5, 2.0, n)).cuda()
-    g, _ = f.gradient(y, wfj, -ld)
+    g, loss = f.gradient(y, wfj, -ld)
     f.train_step(y, wfj, -ld, lr=1e-3)
     torch.cuda.synchronize()
     p1 = f.get_params().astype(np.float64)
-    gg = g.cpu().numpy().astype(np.float64)
+    # the step descends log L: gradient g / L
+    gg = g.cpu().numpy().astype(np.float64) / float(loss.cpu()[0])
     exp = params.astype(np.float64) - 1e-3 * gg / (np.abs(gg) + 1e-8)
     # the step is lr sign(g) wherever |g| >> eps; FP32 parameters (ulp 6e-8)
     assert np.abs(p1 - exp).max() < 1e-6

@@ -14,7 +14,7 @@ def _quantiles(x, qs):
     return [float(xs[min(n - 1, int(q * (n - 1) + 0.5))]) for q in qs]
 
 
-def precision_error(p, w, p_ref, w_ref, np_):
+def precision_error(p, w, p_ref, w_ref, np_, jac=None, jac_ref=None):
     """Compare (p, w) with the FP64 (p_ref, w_ref) of the same events.
 
     p, p_ref: [4][np][n] momenta; w, w_ref: [n] weights.  Returns a dict:
@@ -23,7 +23,8 @@ def precision_error(p, w, p_ref, w_ref, np_):
       weight_{median,p99,max}: |dw| / |w_ref| over events kept by both;
       cut_flips: events kept by exactly one side;
       integral_shift_sigma: (sum w - sum w_ref) / n over the Monte Carlo
-        standard error of the reference mean.
+        standard error of the reference mean;
+      jac_{median,p99,max} (when jac, jac_ref are given): |dJ| / |J_ref|.
     """
     import torch
 
@@ -41,7 +42,13 @@ def precision_error(p, w, p_ref, w_ref, np_):
     mean_ref = w_ref.double().mean()
     sigma = float(w_ref.double().std() / n ** 0.5) if n > 1 else 0.0
     shift = float((w.double().mean() - mean_ref))
+    out = {}
+    if jac is not None and jac_ref is not None:
+        kept = (jac != 0) & (jac_ref != 0)
+        mj = _quantiles(((jac - jac_ref).abs() / jac_ref.abs())[kept], [0.5, 0.99, 1.0])
+        out = {"jac_median": mj[0], "jac_p99": mj[1], "jac_max": mj[2]}
     return {
+        **out,
         "momenta_median": mp[0], "momenta_p99": mp[1], "momenta_max": mp[2],
         "weight_median": mw[0], "weight_p99": mw[1], "weight_max": mw[2],
         "cut_flips": flips, "events": n,

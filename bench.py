@@ -299,6 +299,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--events", type=int, default=N_EVENTS)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-autotune", action="store_true", help="default launch shape instead of the autotuned one")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed-precision, flow and graph reports")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -343,6 +344,9 @@ def main():
     st = adapt_vegas(ctx, n_per_channel=100_000, iterations=8, alpha=0.5, seed=1, stream_id=1)
     counts = neyman_counts(st, args.events)
     grids = [ctx.get_grid(c) for c in range(ctx.n_channels)]
+    # launch shape of the fused kernel for these counts (untimed setup)
+    if not args.no_autotune:
+        ctx.autotune(counts, seed=1, reps=2)
     N = int(counts.sum())
     out = {"p": torch.empty((4, ctx.max_momenta, N), dtype=torch.float64, device="cuda"),
            "w": torch.empty(N, dtype=torch.float64, device="cuda"),
@@ -402,7 +406,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "pp->4j 13 TeV, 8 channels (t/mixed/s), VEGAS 64 bins x 10 dims frozen, "
                                f"{N} events per step, FP64", "events_per_step": N, "channels": int(ctx.n_channels),
-                   "sampler": "vegas"},
+                   "sampler": "vegas", "launch": {"events_per_thread": ctx.launch_shape()[0],
+                                                  "workgroups": ctx.launch_shape()[1]}},
         "integral": I,
         "rel_error_per_step": rel_err_step,
         "pass_cut_fraction": pass_frac,

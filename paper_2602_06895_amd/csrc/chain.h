@@ -476,18 +476,22 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
 // Integrand and local channel weight, from momenta supplied by an accessor
 // get(k, c) for final-state particle k (0-based) and component c, plus p_a.
 // ---------------------------------------------------------------------------
-template <class Get>
+// Loops over final-state particles run over a compile-time bound NF with a
+// wave-uniform guard, so get(k, c) is always called with a constant k (the
+// momenta stay in statically indexed registers).
+template <int NF, class Get>
 __device__ __forceinline__ double inv_q2(const ProcessTab* __restrict__ pt, int u, double pae, double pax, double pay,
                                          double paz, Get get) {
     double qe = 0.0, qx = 0.0, qy = 0.0, qz = 0.0;
-    uint32_t set = pt->uniq_set[u];
-    while (set) {
-        int b = __builtin_ctz(set);
-        set &= set - 1;
-        qe += get(b, 0);
-        qx += get(b, 1);
-        qy += get(b, 2);
-        qz += get(b, 3);
+    const uint32_t set = pt->uniq_set[u];
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+        if (set & (1u << k)) {
+            qe += get(k, 0);
+            qx += get(k, 1);
+            qy += get(k, 2);
+            qz += get(k, 3);
+        }
     }
     if (pt->uniq_t[u]) {
         qe = pae - qe;
@@ -499,7 +503,8 @@ __device__ __forceinline__ double inv_q2(const ProcessTab* __restrict__ pt, int 
 }
 
 // Returns alpha * f; *alpha_out receives alpha.  `logtau` = log(x1 x2).
-template <bool MIX, class Get>
+// NF bounds the number of final-state particles of the process.
+template <bool MIX, int NF, class Get>
 __device__ __forceinline__ double integrand_alpha(const ProcessTab* __restrict__ pt, int chan_in_proc, double x1,
                                                   double x2, double logtau, double pae, double pax, double pay,
                                                   double paz, Get get, double& alpha_out) {
@@ -519,19 +524,27 @@ __device__ __forceinline__ double integrand_alpha(const ProcessTab* __restrict__
         f = t_exp<MIX>(pt->pdf_a * logtau) * b1 * b2;
     }
     if (pt->pt_min2 > 0.0) {
-        for (int i = 0; i < n; ++i) {
-            double px = get(i, 1), py = get(i, 2);
-            if (!(px * px + py * py > pt->pt_min2)) f = 0.0;
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+            if (i < n) {
+                double px = get(i, 1), py = get(i, 2);
+                if (!(px * px + py * py > pt->pt_min2)) f = 0.0;
+            }
         }
     }
     if (pt->ang >= 0) {
-        double px = get(pt->ang, 1), py = get(pt->ang, 2), pz = get(pt->ang, 3);
-        double c = pz / sqrt(px * px + py * py + pz * pz);
-        f *= 1.0 + c * c;
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+            if (i == pt->ang) {
+                double px = get(i, 1), py = get(i, 2), pz = get(i, 3);
+                double c = pz / sqrt(px * px + py * py + pz * pz);
+                f *= 1.0 + c * c;
+            }
+        }
     }
     double qv[kMaxUniq];
     const int nu = pt->n_uniq;
-    for (int u = 0; u < nu; ++u) qv[u] = inv_q2(pt, u, pae, pax, pay, paz, get);
+    for (int u = 0; u < nu; ++u) qv[u] = inv_q2<NF>(pt, u, pae, pax, pay, paz, get);
     // propagator factors: one reciprocal of the product of the denominators
     const int nf = pt->n_fprop;
     double fden = 1.0;

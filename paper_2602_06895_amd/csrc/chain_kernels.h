@@ -16,15 +16,31 @@
 namespace msx {
 
 // Beam boost, unphysical cut, integrand x channel weight and the stores of one
-// event whose partonic-frame momenta sit in the slots.
+// event whose partonic-frame momenta sit in the slots.  The final-state
+// momenta are first gathered by label into statically indexed arrays (NF =
+// the most final-state particles an NS-slot channel has), so the stores and
+// the integrand index registers with constants.
 template <int NS, bool MIX>
 __device__ __forceinline__ double finish_event(const ChannelTab* __restrict__ ct, const ProcessTab* __restrict__ pt,
                                                const ChainOut& o, double jv, double (&E)[NS], double (&X)[NS],
                                                double (&Y)[NS], double (&Z)[NS], int np, int64_t n, int64_t e,
                                                double* __restrict__ p, double* __restrict__ x1x2,
                                                double* __restrict__ jac_out, bool want_w) {
+    constexpr int NF = NS / 2 + 1;
     const int nf = ct->n_final;
     const int hadronic = ct->hadronic;
+    double FE[NF], FX[NF], FY[NF], FZ[NF];
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+        FE[k] = FX[k] = FY[k] = FZ[k] = 0.0;
+        if (k < nf) {
+            const int s = slot_index<NS>(ct->final_slot[k]);
+            FE[k] = E[s];
+            FX[k] = X[s];
+            FY[k] = Y[s];
+            FZ[k] = Z[s];
+        }
+    }
     double g = 1.0, gb = 0.0;
     if (hadronic) {
         double inv = 1.0 / (2.0 * sqrt(o.x1 * o.x2));
@@ -33,21 +49,7 @@ __device__ __forceinline__ double finish_event(const ChannelTab* __restrict__ ct
     }
     const double h = 0.5 * sqrt(o.shat);
     bool ok = true;
-    // incoming partons, then final-state particles by label
-    for (int i = 0; i < nf + 2; ++i) {
-        double pe, px, py, pz;
-        if (i < 2) {
-            pe = h;
-            px = 0.0;
-            py = 0.0;
-            pz = i == 0 ? h : -h;
-        } else {
-            int s = slot_index<NS>(ct->final_slot[i - 2]);
-            pe = E[s];
-            px = X[s];
-            py = Y[s];
-            pz = Z[s];
-        }
+    auto store = [&](int i, double pe, double px, double py, double pz) {
         double le = pe, lz = pz;
         if (hadronic) {
             le = g * pe + gb * pz;
@@ -58,7 +60,13 @@ __device__ __forceinline__ double finish_event(const ChannelTab* __restrict__ ct
         p[((int64_t)1 * np + i) * n + e] = px;
         p[((int64_t)2 * np + i) * n + e] = py;
         p[((int64_t)3 * np + i) * n + e] = lz;
-    }
+    };
+    // incoming partons, then final-state particles by label
+    store(0, h, 0.0, 0.0, h);
+    store(1, h, 0.0, 0.0, -h);
+#pragma unroll
+    for (int k = 0; k < NF; ++k)
+        if (k < nf) store(k + 2, FE[k], FX[k], FY[k], FZ[k]);
     double jac = o.jac * jv;
     ok = ok && isfinite(jac) && jac > 0.0;
     if (hadronic) {
@@ -74,10 +82,9 @@ __device__ __forceinline__ double finish_event(const ChannelTab* __restrict__ ct
     if (want_w && ok) {
         double alpha;
         auto get = [&](int k, int c) -> double {
-            int s = slot_index<NS>(ct->final_slot[k]);
-            return c == 0 ? E[s] : (c == 1 ? X[s] : (c == 2 ? Y[s] : Z[s]));
+            return c == 0 ? FE[k] : (c == 1 ? FX[k] : (c == 2 ? FY[k] : FZ[k]));
         };
-        double af = integrand_alpha<MIX>(pt, ct->alpha_index, o.x1, o.x2, o.logtau, h, 0.0, 0.0, h, get, alpha);
+        double af = integrand_alpha<MIX, NF>(pt, ct->alpha_index, o.x1, o.x2, o.logtau, h, 0.0, 0.0, h, get, alpha);
         w = af * jac;
     }
     return w;

@@ -472,6 +472,13 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
     o.jac = jac;
 }
 
+// Invariant store in private registers (the weight entry point).
+struct RegQ {
+    double v[kMaxUniq];
+    __device__ __forceinline__ void set(int u, double x) { v[u] = x; }
+    __device__ __forceinline__ double get(int u) const { return v[u]; }
+};
+
 // ---------------------------------------------------------------------------
 // Integrand and local channel weight, from momenta supplied by an accessor
 // get(k, c) for final-state particle k (0-based) and component c, plus p_a.
@@ -503,11 +510,13 @@ __device__ __forceinline__ double inv_q2(const ProcessTab* __restrict__ pt, int 
 }
 
 // Returns alpha * f; *alpha_out receives alpha.  `logtau` = log(x1 x2).
-// NF bounds the number of final-state particles of the process.
-template <bool MIX, int NF, class Get>
+// NF bounds the number of final-state particles of the process.  q is the
+// per-event store of the invariants' channel-weight denominators, indexed by
+// invariant (q.set(u, v), q.get(u)): an LDS column in the sampling kernels.
+template <bool MIX, int NF, class Get, class Q>
 __device__ __forceinline__ double integrand_alpha(const ProcessTab* __restrict__ pt, int chan_in_proc, double x1,
                                                   double x2, double logtau, double pae, double pax, double pay,
-                                                  double paz, Get get, double& alpha_out) {
+                                                  double paz, Get get, Q& q, double& alpha_out) {
     double f = 1.0;
     const int n = pt->n_final;
     if (pt->pdf) {
@@ -542,40 +551,45 @@ __device__ __forceinline__ double integrand_alpha(const ProcessTab* __restrict__
             }
         }
     }
-    double qv[kMaxUniq];
+    // each distinct invariant once: its integrand factor (product of the
+    // denominators, one reciprocal) and its channel-weight denominator
     const int nu = pt->n_uniq;
-    for (int u = 0; u < nu; ++u) qv[u] = inv_q2<NF>(pt, u, pae, pax, pay, paz, get);
-    // propagator factors: one reciprocal of the product of the denominators
-    const int nf = pt->n_fprop;
+    const int nc = pt->n_chan;
     double fden = 1.0;
-    for (int i = 0; i < nf; ++i) {
-        double q2 = qv[pt->f_uniq[i]];
-        if (pt->f_bw[i]) {
-            double d = q2 - pt->f_m2[i];
-            fden *= d * d + pt->f_mw[i] * pt->f_mw[i];
-        } else {
-            fden *= fabs(q2) + pt->f_mu2[i];
+    for (int u = 0; u < nu; ++u) {
+        const double q2 = inv_q2<NF>(pt, u, pae, pax, pay, paz, get);
+        const int fi = pt->uniq_f[u];
+        if (fi >= 0) {
+            if (pt->f_bw[fi]) {
+                const double d = q2 - pt->f_m2[fi];
+                fden *= d * d + pt->f_mw[fi] * pt->f_mw[fi];
+            } else {
+                fden *= fabs(q2) + pt->f_mu2[fi];
+            }
+        }
+        if (nc > 1) {
+            double dd;
+            if (pt->uniq_massive[u] > 0) {
+                const double d = q2 - pt->uniq_m2[u];
+                dd = d * d + pt->uniq_mw[u] * pt->uniq_mw[u];
+            } else {
+                const double d = fabs(q2) + pt->alpha_mu2;
+                dd = d * d;
+            }
+            q.set(u, dd);
         }
     }
-    if (nf > 0) f /= fden;
+    if (pt->n_fprop > 0) f /= fden;
     double alpha = 1.0;
-    const int nc = pt->n_chan;
     if (nc > 1) {
         double den = 0.0, mine = 0.0;
         for (int c = 0; c < nc; ++c) {
             double D = 1.0;
             uint32_t m = pt->chan_mask[c];
             while (m) {
-                int u = __builtin_ctz(m);
+                const int u = __builtin_ctz(m);
                 m &= m - 1;
-                double q2 = qv[u];
-                if (pt->uniq_massive[u]) {
-                    double d = q2 - pt->uniq_m2[u];
-                    D *= d * d + pt->uniq_mw[u] * pt->uniq_mw[u];
-                } else {
-                    double d = fabs(q2) + pt->alpha_mu2;
-                    D *= d * d;
-                }
+                D *= q.get(u);
             }
             const double P = 1.0 / D;
             den += P;

@@ -15,6 +15,16 @@
 
 namespace msx {
 
+// Per-thread column of the invariant store in LDS: kMaxUniq doubles with
+// stride kBlock (conflict-free across a wave).  It occupies the first
+// kQBytes of the kernels' dynamic LDS; the VEGAS grid follows.
+constexpr size_t kQBytes = sizeof(double) * kMaxUniq * kBlock;
+struct LdsQ {
+    double* b;
+    __device__ __forceinline__ void set(int u, double x) { b[u * kBlock] = x; }
+    __device__ __forceinline__ double get(int u) const { return b[u * kBlock]; }
+};
+
 // Beam boost, unphysical cut, integrand x channel weight and the stores of one
 // event whose partonic-frame momenta sit in the slots.  The final-state
 // momenta are first gathered by label into statically indexed arrays (NF =
@@ -25,7 +35,7 @@ __device__ __forceinline__ double finish_event(const ChannelTab* __restrict__ ct
                                                const ChainOut& o, double jv, double (&E)[NS], double (&X)[NS],
                                                double (&Y)[NS], double (&Z)[NS], int np, int64_t n, int64_t e,
                                                double* __restrict__ p, double* __restrict__ x1x2,
-                                               double* __restrict__ jac_out, bool want_w) {
+                                               double* __restrict__ jac_out, bool want_w, LdsQ q) {
     constexpr int NF = NS / 2 + 1;
     const int nf = ct->n_final;
     const int hadronic = ct->hadronic;
@@ -84,7 +94,7 @@ __device__ __forceinline__ double finish_event(const ChannelTab* __restrict__ ct
         auto get = [&](int k, int c) -> double {
             return c == 0 ? FE[k] : (c == 1 ? FX[k] : (c == 2 ? FY[k] : FZ[k]));
         };
-        double af = integrand_alpha<MIX, NF>(pt, ct->alpha_index, o.x1, o.x2, o.logtau, h, 0.0, 0.0, h, get, alpha);
+        double af = integrand_alpha<MIX, NF>(pt, ct->alpha_index, o.x1, o.x2, o.logtau, h, 0.0, 0.0, h, get, q, alpha);
         w = af * jac;
     }
     return w;
@@ -96,7 +106,9 @@ __global__ __launch_bounds__(kBlock) void k_map(const ChannelTab* __restrict__ c
                                                 int64_t n, const double* __restrict__ y, double* __restrict__ p,
                                                 double* __restrict__ x1x2, double* __restrict__ jac,
                                                 double* __restrict__ w) {
-    extern __shared__ double lg[];
+    extern __shared__ double lds[];
+    double* lg = lds + kMaxUniq * kBlock;
+    const LdsQ q{lds + threadIdx.x};
     const int dims = ct->dims;
     for (int i = threadIdx.x; i < dims * (nb + 1); i += blockDim.x) lg[i] = grid[i];
     __syncthreads();
@@ -112,7 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_map(const ChannelTab* __restrict__ c
         double E[NS], X[NS], Y[NS], Z[NS], S[NI], SQ[NI];
         ChainOut o;
         run_chain<NS, NI, KINDS, MIX>(ct, s_lab, next, E, X, Y, Z, S, SQ, o);
-        double wv = finish_event<NS, MIX>(ct, pt, o, jv, E, X, Y, Z, np, n, e, p, x1x2, jac, w != nullptr);
+        double wv = finish_event<NS, MIX>(ct, pt, o, jv, E, X, Y, Z, np, n, e, p, x1x2, jac, w != nullptr, q);
         if (w) w[e] = wv;
     }
 }
@@ -133,7 +145,9 @@ __global__ __launch_bounds__(kBlock) void k_sample(const ChannelTab* __restrict_
                                                    int64_t ld, double* __restrict__ p, double* __restrict__ x1x2,
                                                    double* __restrict__ w, int32_t* __restrict__ chan_out,
                                                    double* __restrict__ tile_stats) {
-    extern __shared__ double lg[];
+    extern __shared__ double lds[];
+    double* lg = lds + kMaxUniq * kBlock;
+    const LdsQ q{lds + threadIdx.x};
     __shared__ double red[4][kWaves];
     int cur = -1;
     int nb = 0, dims = 0;
@@ -184,7 +198,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(const ChannelTab* __restrict_
             double E[NS], X[NS], Y[NS], Z[NS], S[NI], SQ[NI];
             ChainOut o;
             run_chain<NS, NI, KINDS, MIX>(ct, s_lab, next, E, X, Y, Z, S, SQ, o);
-            const double wv = finish_event<NS, MIX>(ct, pt, o, jv, E, X, Y, Z, np, ld, pos, p, x1x2, nullptr, true);
+            const double wv = finish_event<NS, MIX>(ct, pt, o, jv, E, X, Y, Z, np, ld, pos, p, x1x2, nullptr, true, q);
             w[pos] = wv;
             if (chan_out) chan_out[pos] = c;
             a1 += wv;
@@ -220,12 +234,19 @@ hipError_t launch_chain_class(int kc, const ChainLaunch& a) {
     constexpr int K0 = KIND_POW_INT, K1 = KIND_POW_INT | KIND_BW, K2 = KINDS_ALL;
     auto go = [&](auto kt) {
         constexpr int K = decltype(kt)::value;
+        const size_t lds = a.lds + kQBytes;
+        if (lds > 65536) {
+            // beyond the default 64 KiB per workgroup (gfx950 has 160 KiB per CU)
+            const void* fn = a.sample ? (const void*)k_sample<NS, NI, K, MIX> : (const void*)k_map<NS, NI, K, MIX>;
+            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return;
+        }
         if (a.sample)
-            k_sample<NS, NI, K, MIX><<<a.grid, kBlock, a.lds, a.stream>>>(
+            k_sample<NS, NI, K, MIX><<<a.grid, kBlock, lds, a.stream>>>(
                 a.cts, a.pts, a.grids, a.grid_off, a.chan_nb, a.call, a.seed, a.sid, a.ctr_dev, a.ctr_off, a.np, a.n,
                 a.p, a.x1x2, a.w, a.chan, a.tile_stats);
         else
-            k_map<NS, NI, K, MIX><<<a.grid, kBlock, a.lds, a.stream>>>(a.cts, a.pts, a.grids, a.nb, a.s_lab, a.np, a.n,
+            k_map<NS, NI, K, MIX><<<a.grid, kBlock, lds, a.stream>>>(a.cts, a.pts, a.grids, a.nb, a.s_lab, a.np, a.n,
                                                                          a.y, a.p, a.x1x2, a.jac, a.w);
     };
     if (!MIX && kc == 0) go(std::integral_constant<int, K0>{});

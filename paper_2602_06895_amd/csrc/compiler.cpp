@@ -444,6 +444,7 @@ int find_or_add_uniq(ProcessTab& pt, int tt, uint32_t set) {
     pt.uniq_t[u] = tt;
     pt.uniq_set[u] = set;
     pt.uniq_massive[u] = -1;  // alpha form not yet assigned
+    pt.uniq_f[u] = -1;
     return u;
 }
 
@@ -521,8 +522,10 @@ bool compile_process(Ctx& cx, const JValue& pj, Compiled& out) {
                 int is_bw = (bw && bw->kind == JValue::BOOL && bw->b) ? 1 : 0;
                 int u = find_or_add_uniq(pt, is_t, set);
                 if (u < 0) return cx.fail("too many distinct invariants");
+                if (pt.uniq_f[u] >= 0) return cx.fail("two integrand factors on the same invariant");
                 int f = pt.n_fprop++;
                 pt.f_uniq[f] = u;
+                pt.uniq_f[u] = f;
                 pt.f_bw[f] = is_bw;
                 double m = num_or(pr, "m", 0.0), w = num_or(pr, "w", 0.0), mu = num_or(pr, "mu", 0.0);
                 pt.f_m2[f] = m * m;

@@ -52,7 +52,8 @@ __global__ __launch_bounds__(kBlock) void k_weight(const ChannelTab* __restrict_
         auto get = [&](int k, int c) -> double { return p[((int64_t)c * np + k + 2) * n + e]; };
         double pae = p[((int64_t)0 * np) * n + e], pax = p[((int64_t)1 * np) * n + e];
         double pay = p[((int64_t)2 * np) * n + e], paz = p[((int64_t)3 * np) * n + e];
-        double af = integrand_alpha<MIX, kMaxFinal>(pt, ct->alpha_index, x1, x2, L, pae, pax, pay, paz, get, av);
+        RegQ q;
+        double af = integrand_alpha<MIX, kMaxFinal>(pt, ct->alpha_index, x1, x2, L, pae, pax, pay, paz, get, q, av);
         wv = af * j;
     }
     w[e] = wv;

@@ -131,6 +131,7 @@ struct ProcessTab {
     double uniq_m2[kMaxUniq];
     double uniq_mw[kMaxUniq];
     uint32_t chan_mask[kMaxChanPerProc];  // invariants of each channel
+    int32_t uniq_f[kMaxUniq];             // integrand factor on each invariant, -1: none
     // integrand factors
     int32_t f_uniq[kMaxFactors];
     int32_t f_bw[kMaxFactors];

@@ -175,11 +175,15 @@ def flow_report(train_steps=400, batch=65536, n_eval=1_000_000, lr=1e-3, workloa
     nh = d // 2
     no = nh * 49
     flops = 2.0 * 8 * (nh * 128 + 2 * 128 * 128 + 128 * no) * nf
-    # HBM bytes per event and layer of the unfused forward pass: gather (z
-    # read, BF16 input written and read), hidden activations written and read
-    # (3 x 128 BF16), spline parameters written and read (FP32), the
-    # transformed coordinates read and written
-    bytes_layer = (nh * 4 + 2 * nh * 2) + 2 * 3 * 128 * 2 + 2 * no * 4 + 2 * nh * 4
+    # HBM bytes per event and layer of the fused forward pass (BF16, hidden
+    # 128, 16 bins, aligned layer blocks): z read (d floats), the transformed
+    # coordinates written, the log-determinant read and written; weights come
+    # from L2.  The unfused pass (other shapes) also moves the activations and
+    # the spline parameters.
+    per_layer = 128 * nh + 128 + 2 * (128 * 128 + 128) + no * 128 + no
+    fused = per_layer % 8 == 0
+    bytes_layer = d * 4 + nh * 4 + 8 if fused else \
+        (nh * 4 + 2 * nh * 2) + 2 * 3 * 128 * 2 + 2 * no * 4 + 2 * nh * 4
     hbm_gbs = 8 * bytes_layer * nf / (ms / 1e3) / 1e9
     use_flow = rel_f < rel_v
     name = "pp->ttbar->6 integrand" if workload == "c3" else f"pp->4j channel {channel}"
@@ -191,6 +195,7 @@ def flow_report(train_steps=400, batch=65536, n_eval=1_000_000, lr=1e-3, workloa
            "train_seconds": train_s, "loss_first": float(losses[0].cpu()[0]), "loss_last": float(losses[-1].cpu()[0]),
            "flow_forward_2e20": {"ms": ms, "mlp_tflops": flops / (ms / 1e3) / 1e12, "peak_tflops": 2500.0,
                                  "frac": flops / (ms / 1e3) / 1e12 / 2500.0,
+                                 "fused_layers": fused, "bound": "mfma" if fused else "hbm",
                                  "algorithmic_bytes_per_event": 8 * bytes_layer, "hbm_gbs": hbm_gbs,
                                  "hbm_frac": hbm_gbs / HBM_PEAK_GBS}}
     flow.close()

@@ -411,10 +411,22 @@ msx_status msx_flow_forward(msx_flow* f, int64_t n, const float* u, float* y, fl
     if (!u || !y || !logdet) return ffail(f, MSX_ERR_ARG, "u, y and logdet are required");
     hipStream_t s = (hipStream_t)stream;
     FHIP(f, hipSetDevice(f->device), "hipSetDevice");
-    if (msx_status st = ensure_work(f, n)) return st;
+    // whole layers in one kernel where the shape allows it (BF16, hidden 128,
+    // <= 16 bins, 16-byte aligned layer blocks); no work buffers then
+    const bool fused = f->type == FT_BF16 && f->H == kFusedHidden && f->K <= kFusedMaxBins && f->per_layer % 8 == 0;
+    if (!fused)
+        if (msx_status st = ensure_work(f, n)) return st;
     if (y != u) FHIP(f, hipMemcpyAsync(y, u, sizeof(float) * (size_t)f->d * n, hipMemcpyDeviceToDevice, s), "flow copy");
     FHIP(f, hipMemsetAsync(logdet, 0, sizeof(float) * n, s), "flow clear");
     for (int l = 0; l < f->L; ++l) {
+        if (fused) {
+            const int64_t base = l * f->per_layer;
+            FHIP(f,
+                 launch_flow_layer_fwd(y, n, tptr(f, f->params_t, base), f->params + base, f->off, f->nh,
+                                       f->trans[l].data(), f->cond[l].data(), f->K, logdet, s),
+                 "flow layer");
+            continue;
+        }
         if (msx_status st = run_mlp(f, l, y, n, f->x0, f->h, f->theta, s)) return st;
         FHIP(f, launch_spline(false, y, n, f->theta, f->n_out, f->nh, f->trans[l].data(), f->K, logdet, s),
              "flow spline");

@@ -617,6 +617,170 @@ __global__ __launch_bounds__(256) void k_flow_weight(int64_t n, const double* __
     if (logq) logq[i] = -ld;
 }
 
+// ---------------------------------------------------------------------------
+// Fused forward coupling layer (BF16 conditioner of hidden width 128).  Each
+// wave takes 64 events.  Their conditioning coordinates are gathered straight
+// into MFMA operand fragments; the hidden layers run on the matrix cores with
+// the weight fragments read from L2 (about 2 KB per event and layer) and the
+// activations passed through a per-wave LDS tile, which also turns the MFMA
+// output layout (4 rows of one column per lane) into the operand layout (8 k
+// of one row per lane).  The last layer produces the 3K + 1 spline
+// parameters of one transformed coordinate at a time into LDS, where each of
+// the 64 lanes evaluates the spline of its own event.  Per event only z and
+// the log-determinant touch HBM.
+// ---------------------------------------------------------------------------
+constexpr int kFH = 128;                 // hidden width of the fused path
+constexpr int kFW = 2;                   // waves per workgroup
+constexpr int kFRow = kFH + 8;           // LDS row of an activation tile (bf16)
+constexpr int kFStage = 64 * kFRow;      // bf16 elements per wave (>= 64 x 49 floats)
+
+struct FusedW {
+    const __bf16* w1;  // [128][nh]
+    const __bf16* w2;  // [128][128]
+    const __bf16* w3;  // [128][128]
+    const __bf16* w4;  // [n_out][128]
+    const float* b1;
+    const float* b2;
+    const float* b3;
+    const float* b4;
+};
+
+// acc (16 events x 16 columns per tile t) + bias, ReLU, BF16 -> activation tile
+__device__ __forceinline__ void hidden_epilogue(const floatx4 (&acc)[4], const float* __restrict__ b, int c, int lane,
+                                                __bf16* __restrict__ st) {
+    const int r16 = lane & 15, kq = lane >> 4;
+    const float bias = b[16 * c + r16];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            st[(16 * t + 4 * kq + e) * kFRow + 16 * c + r16] = (__bf16)fmaxf(acc[t][e] + bias, 0.0f);
+}
+
+// 128 -> 128 layer from the activation tile in LDS back into it
+__device__ __forceinline__ void hidden_layer(const __bf16* __restrict__ Wl, const float* __restrict__ bl, int lane,
+                                             __bf16* __restrict__ st) {
+    const int r16 = lane & 15, kq = lane >> 4;
+    bf16x8 a[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) a[t][s4] = *(const bf16x8*)&st[(16 * t + r16) * kFRow + 32 * s4 + 8 * kq];
+    __syncthreads();  // the tile is overwritten below
+#pragma unroll 1
+    for (int c = 0; c < kFH / 16; ++c) {
+        bf16x8 b[4];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) b[s4] = *(const bf16x8*)&Wl[(16 * c + r16) * kFH + 32 * s4 + 8 * kq];
+        floatx4 acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            acc[t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t][s4], b[s4], acc[t], 0, 0, 0);
+        }
+        hidden_epilogue(acc, bl, c, lane, st);
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(64 * kFW) void k_flow_layer_fwd(float* __restrict__ z, int64_t n, FusedW fw, int nh,
+                                                             Idx trans, Idx cond, int K, float* __restrict__ logdet) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char fsm[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r16 = lane & 15, kq = lane >> 4;
+    __bf16* st = (__bf16*)fsm + (size_t)wave * kFStage;
+    float* th = (float*)st;
+    const int64_t e0 = ((int64_t)blockIdx.x * kFW + wave) * 64;
+    const int P = 3 * K + 1;
+    const int n_out = nh * P;
+
+    // layer 1: A fragments = BF16 conditioning coordinates (k = 8 kq + i < nh)
+    bf16x8 a1[4];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int k = 8 * kq + i;
+        const int ci = kq == 0 ? cond.v[i] : (kq == 1 ? cond.v[8 + i] : (kq == 2 ? cond.v[16 + i] : cond.v[24 + i]));
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int64_t e = e0 + 16 * t + r16;
+            a1[t][i] = (__bf16)((k < nh && e < n) ? z[(int64_t)ci * n + e] : 0.0f);
+        }
+    }
+#pragma unroll 1
+    for (int c = 0; c < kFH / 16; ++c) {
+        bf16x8 b;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = 8 * kq + i;
+            b[i] = k < nh ? fw.w1[(16 * c + r16) * nh + k] : (__bf16)0.0f;
+        }
+        floatx4 acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[t], b, floatx4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
+        hidden_epilogue(acc, fw.b1, c, lane, st);
+    }
+    __syncthreads();
+    hidden_layer(fw.w2, fw.b2, lane, st);
+    hidden_layer(fw.w3, fw.b3, lane, st);
+
+    // last layer, one transformed coordinate at a time, then its spline
+    bf16x8 a3[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) a3[t][s4] = *(const bf16x8*)&st[(16 * t + r16) * kFRow + 32 * s4 + 8 * kq];
+    __syncthreads();
+    const int64_t e = e0 + lane;
+    const bool active = e < n;
+    float ld = 0.0f;
+    for (int j = 0; j < nh; ++j) {
+#pragma unroll 1
+        for (int c = 0; c < (P + 15) / 16; ++c) {
+            const int q = 16 * c + r16;          // parameter within the coordinate
+            const int row = j * P + q;           // row of W4 / column of theta
+            const bool ok = q < P && row < n_out;
+            bf16x8 b[4];
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                if (ok) {
+                    b[s4] = *(const bf16x8*)&fw.w4[(int64_t)row * kFH + 32 * s4 + 8 * kq];
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) b[s4][i] = (__bf16)0.0f;
+                }
+            }
+            const float bias = ok ? fw.b4[row] : 0.0f;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                floatx4 acc = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3[t][s4], b[s4], acc, 0, 0, 0);
+                if (ok) {
+#pragma unroll
+                    for (int x = 0; x < 4; ++x) th[(16 * t + 4 * kq + x) * P + q] = acc[x] + bias;
+                }
+            }
+        }
+        __syncthreads();
+        if (active) {
+            float* zp = z + (int64_t)trans.v[j] * n + e;
+            const float v = *zp;
+            float mw, sw, mh, sh;
+            const Bin bn = spline_bin<false>(th + lane * P, K, v, mw, sw, mh, sh);
+            const float sl = bn.h / bn.w;
+            const float kap = bn.d1 + bn.d0 - 2.0f * sl;
+            const float xi = (v - bn.x0) / bn.w;
+            const float om = xi * (1.0f - xi);
+            *zp = bn.y0 + bn.h * (sl * xi * xi + bn.d0 * om) / (sl + kap * om);
+            ld += logf(spline_slope(bn, xi));
+        }
+        __syncthreads();
+    }
+    if (active) logdet[e] += ld;
+}
+
 unsigned blocks(int64_t n) {
     return (unsigned)std::max<int64_t>(1, (n + 255) / 256);
 }
@@ -642,6 +806,27 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
         k_gemm<__bf16><<<grid, GT, 0, s>>>(g, kchunk);
     else
         k_gemm<float><<<grid, GT, 0, s>>>(g, kchunk);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_layer_fwd(float* z, int64_t n, const void* params_t, const float* params, const int64_t* off,
+                                 int nh, const int32_t* trans_host, const int32_t* cond_host, int K, float* logdet,
+                                 hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    FusedW fw;
+    const __bf16* W = (const __bf16*)params_t;
+    fw.w1 = W + off[0];
+    fw.b1 = params + off[1];
+    fw.w2 = W + off[2];
+    fw.b2 = params + off[3];
+    fw.w3 = W + off[4];
+    fw.b3 = params + off[5];
+    fw.w4 = W + off[6];
+    fw.b4 = params + off[7];
+    const unsigned nb = (unsigned)((n + 64 * kFW - 1) / (64 * kFW));
+    const size_t lds = sizeof(__bf16) * kFStage * kFW;
+    k_flow_layer_fwd<<<nb, 64 * kFW, lds, s>>>(z, n, fw, nh, make_idx(trans_host, nh), make_idx(cond_host, nh), K,
+                                              logdet);
     return hipGetLastError();
 }
 

@@ -41,6 +41,16 @@ struct GemmArgs {
 };
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t s);
 
+// One whole forward coupling layer in one kernel (BF16 operands, hidden width
+// 128, up to 16 bins): conditioner on the matrix cores and spline, z updated
+// in place, logdet accumulated.  params_t / params: the layer's weights in
+// BF16 / biases in FP32 at the offsets off[0..7] (W1 b1 W2 b2 W3 b3 W4 b4).
+hipError_t launch_flow_layer_fwd(float* z, int64_t n, const void* params_t, const float* params, const int64_t* off,
+                                 int nh, const int32_t* trans_host, const int32_t* cond_host, int K, float* logdet,
+                                 hipStream_t s);
+constexpr int kFusedHidden = 128;
+constexpr int kFusedMaxBins = 16;
+
 // out[m][n] = sum_z part[z][m][n] in z order (out has leading dimension ldo).
 hipError_t launch_reduce_partials(const float* part, int splits, int M, int N, float* out, int64_t ldo,
                                   hipStream_t s);

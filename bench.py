@@ -229,9 +229,10 @@ def graph_report(reps=10):
             "autotuned": {"events_per_thread": ept, "grid": grid, "ms": best}}
 
 
-def summarize(d: str, events: int):
+def summarize(d: str, events: int, steps: int = 10):
     """Summary of the rocprofv3 runs under d (rocpd databases written by the
-    commands printed below) for the k_sample dispatches of `events` events."""
+    commands printed below) for the last `steps` k_sample dispatches of
+    `events` events (the timed steps of the traced run)."""
     import glob
     import sqlite3
 
@@ -243,9 +244,10 @@ def summarize(d: str, events: int):
     tr = db("trace")
     rows = list(tr.execute("select duration, grid_x, workgroup_x, vgpr_count, accum_vgpr_count, sgpr_count, "
                            "scratch_size, lds_size from kernels where name like '%k_sample%' order by start"))
-    # the timed launches are the large ones (adaptation launches are 8e5 events)
+    # the timed launches are the last `steps` large ones (adaptation launches
+    # carry 8e5 events; the autotuner's trial launches come before the timed ones)
     big = max(r[0] for r in rows)
-    timed = [r for r in rows if r[0] > 0.5 * big]
+    timed = [r for r in rows if r[0] > 0.5 * big][-steps:]
     dur = np.array([r[0] for r in timed]) / 1e3
     r0 = timed[0]
     out.append(f"kernel: k_sample (fused multichannel sample), {len(timed)} timed dispatches of {events} events")

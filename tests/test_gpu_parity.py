@@ -339,8 +339,12 @@ def test_full_size_c2_sample_spot_check(ctxs, torch):
     are recomputed by the oracle."""
     ctx, orc = ctxs["c2"]
     counts = np.full(8, 1_250_000, dtype=np.int64)
+    # the shape bench.py runs: autotuned for these counts
+    ctx.autotune(counts, seed=1, reps=1)
     out = ctx.sample(counts, seed=1, stream_id=0)
     torch.cuda.synchronize()
+    ctx.set_launch(1, 0)
+    ctx.reset_stats()
     rng = np.random.default_rng(4)
     w = out["w"]
     for _ in range(6):
@@ -353,3 +357,25 @@ def test_full_size_c2_sample_spot_check(ctxs, torch):
         seg = {"w": _np(w[pos:pos + 3000]), "p": _np(out["p"][:, :, pos:pos + 3000]),
                "x1x2": _np(out["x1x2"][:, pos:pos + 3000])}
         compare(seg, ref, fe, hadronic=True, label=f"full-size ch{c}@{start}")
+
+
+def test_full_size_c3_sample_spot_check(ctxs, torch):
+    """pp -> t tbar -> 6 at its full size (1e8 events in one fused launch, 16
+    dims, Breit-Wigner maps): windows of events at random positions, the
+    first and the last events, recomputed by the oracle."""
+    ctx, orc = ctxs["c3"]
+    N = 100_000_000
+    out = ctx.sample(np.array([N]), seed=3, stream_id=0, want_chan=False)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(6)
+    starts = [0, N - 2000] + [int(rng.integers(0, N - 2000)) for _ in range(4)]
+    for start in starts:
+        y = W.philox_uniforms(3, 0, start, 2000, ctx.dims[0])
+        ref = orc.map(0, y, orc.uniform_grid(0))
+        fe = orc.forward_error(0, y, orc.uniform_grid(0), ref=ref)
+        seg = {"w": _np(out["w"][start:start + 2000]), "p": _np(out["p"][:, :, start:start + 2000]),
+               "x1x2": _np(out["x1x2"][:, start:start + 2000])}
+        compare(seg, ref, fe, hadronic=True, label=f"c3 full-size @{start}")
+    del out
+    torch.cuda.empty_cache()
+    ctx.reset_stats()

@@ -25,6 +25,17 @@ constexpr double kPiD = 3.14159265358979323846;
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter-based generator.
 // ---------------------------------------------------------------------------
+// Full 64 x 64 -> 128-bit product from four 32 x 32 -> 64 partial products
+// (each a v_mad_u64_u32 with the carry folded in), shared by both halves.
+__device__ __forceinline__ void mul128(uint64_t a, uint64_t b, uint64_t& hi, uint64_t& lo) {
+    const uint64_t a0 = (uint32_t)a, a1 = a >> 32, b0 = (uint32_t)b, b1 = b >> 32;
+    const uint64_t p00 = a0 * b0;
+    const uint64_t mid = a0 * b1 + (p00 >> 32);           // < 2^64
+    const uint64_t mid2 = a1 * b0 + (uint32_t)mid;        // < 2^64
+    hi = a1 * b1 + (mid >> 32) + (mid2 >> 32);
+    lo = (mid2 << 32) | (uint32_t)p00;
+}
+
 __device__ __forceinline__ void philox4x64_10(uint64_t& c0, uint64_t& c1, uint64_t& c2, uint64_t& c3,
                                               uint64_t k0, uint64_t k1) {
     const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
@@ -35,8 +46,9 @@ __device__ __forceinline__ void philox4x64_10(uint64_t& c0, uint64_t& c1, uint64
             k0 += W0;
             k1 += W1;
         }
-        uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
-        uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        uint64_t hi0, lo0, hi1, lo1;
+        mul128(M0, c0, hi0, lo0);
+        mul128(M1, c2, hi1, lo1);
         uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
         c1 = lo1;

@@ -176,14 +176,10 @@ def flow_report(train_steps=400, batch=65536, n_eval=1_000_000, lr=1e-3, workloa
     no = nh * 49
     flops = 2.0 * 8 * (nh * 128 + 2 * 128 * 128 + 128 * no) * nf
     # HBM bytes per event and layer of the fused forward pass (BF16, hidden
-    # 128, 16 bins, aligned layer blocks): z read (d floats), the transformed
-    # coordinates written, the log-determinant read and written; weights come
-    # from L2.  The unfused pass (other shapes) also moves the activations and
-    # the spline parameters.
-    per_layer = 128 * nh + 128 + 2 * (128 * 128 + 128) + no * 128 + no
-    fused = per_layer % 8 == 0
-    bytes_layer = d * 4 + nh * 4 + 8 if fused else \
-        (nh * 4 + 2 * nh * 2) + 2 * 3 * 128 * 2 + 2 * no * 4 + 2 * nh * 4
+    # 128, 16 bins): z read (d floats), the transformed coordinates written,
+    # the log-determinant read and written; weights come from L2
+    fused = True
+    bytes_layer = d * 4 + nh * 4 + 8
     hbm_gbs = 8 * bytes_layer * nf / (ms / 1e3) / 1e9
     use_flow = rel_f < rel_v
     name = "pp->ttbar->6 integrand" if workload == "c3" else f"pp->4j channel {channel}"

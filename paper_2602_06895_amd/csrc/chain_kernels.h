@@ -227,8 +227,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(const ChannelTab* __restrict_
 }
 
 // Launch of one register class: kind class `kc` picks the compiled map kinds
-// (0: integer-root power laws, 1: plus Breit-Wigner, 2: all; the mixed
-// kernels exist for classes 1 and 2 only).
+// (0: integer-root power laws, 1: plus Breit-Wigner, 2: all).
 template <int NS, int NI, bool MIX>
 hipError_t launch_chain_class(int kc, const ChainLaunch& a) {
     constexpr int K0 = KIND_POW_INT, K1 = KIND_POW_INT | KIND_BW, K2 = KINDS_ALL;
@@ -249,7 +248,7 @@ hipError_t launch_chain_class(int kc, const ChainLaunch& a) {
             k_map<NS, NI, K, MIX><<<a.grid, kBlock, lds, a.stream>>>(a.cts, a.pts, a.grids, a.nb, a.s_lab, a.np, a.n,
                                                                          a.y, a.p, a.x1x2, a.jac, a.w);
     };
-    if (!MIX && kc == 0) go(std::integral_constant<int, K0>{});
+    if (kc == 0) go(std::integral_constant<int, K0>{});
     else if (kc <= 1) go(std::integral_constant<int, K1>{});
     else go(std::integral_constant<int, K2>{});
     return hipGetLastError();

@@ -20,10 +20,11 @@ struct msx_flow {
     int d = 0, L = 0, K = 0, H = 0, type = FT_BF16;
     int nh = 0, n_out = 0;
     int64_t per_layer = 0, P = 0;
+    int64_t per_layer_t = 0;   // layer block of the operand copy (multiple of 8 elements)
     int64_t off[8] = {};  // W1 b1 W2 b2 W3 b3 W4 b4 within a layer
     std::vector<std::vector<int32_t>> trans, cond;
     float* params = nullptr;   // FP32 master
-    void* params_t = nullptr;  // operand copy (BF16 or FP32)
+    void* params_t = nullptr;  // operand copy (BF16 or FP32), layer blocks of per_layer_t
     float* m = nullptr;
     float* v = nullptr;
     float* grad = nullptr;
@@ -170,7 +171,7 @@ GemmArgs gemm(const msx_flow* f, int M, int N, int K, const void* A, int64_t a_m
 msx_status run_mlp(msx_flow* f, int l, const float* z, int64_t n, void* x0, void* h3, float* theta, hipStream_t s) {
     const int H = f->H, nh = f->nh;
     const int64_t base = l * f->per_layer;
-    const void* W = f->params_t;
+    const void* W = tptr(f, f->params_t, l * f->per_layer_t - base);  // W + base + off = layer block + off
     FHIP(f, launch_gather(f->type, z, n, nh, f->cond[l].data(), x0, s), "flow gather");
     void* h1 = h3;
     void* h2 = tptr(f, h3, n * H);
@@ -242,13 +243,13 @@ msx_status gradient(msx_flow* f, int64_t n, const float* y, const double* wfj, c
     const int H = f->H, nh = f->nh, no = f->n_out;
     for (int l = 0; l < f->L; ++l) {
         const int64_t base = l * f->per_layer;
+        const void* W = tptr(f, f->params_t, l * f->per_layer_t - base);  // W + base + off = layer block + off
         const float* zin = f->z + (size_t)(l + 1) * zs;
         const float* th = f->theta + (size_t)l * n * no;
         const void* x0 = tptr(f, f->x0, (int64_t)l * n * nh);
         const void* h1 = tptr(f, f->h, (int64_t)l * 3 * n * H);
         const void* h2 = tptr(f, h1, n * H);
         const void* h3 = tptr(f, h1, 2 * n * H);
-        const void* W = f->params_t;
         FHIP(f,
              launch_spline_backward(f->type, zin, f->adj, n, th, no, nh, f->trans[l].data(), f->K, f->G, f->dtheta, s),
              "flow spline backward");
@@ -327,6 +328,7 @@ msx_status msx_flow_create(int32_t dims, int32_t layers, int32_t bins, int32_t h
         o += sizes[i];
     }
     f->per_layer = o;
+    f->per_layer_t = (o + 7) / 8 * 8;
     f->P = o * layers;
     for (int l = 0; l < layers; ++l) {
         std::vector<int32_t> t, c;
@@ -340,13 +342,14 @@ msx_status msx_flow_create(int32_t dims, int32_t layers, int32_t bins, int32_t h
     }
     const size_t P = (size_t)f->P;
     hipError_t e = hipSuccess;
-    if ((e = fmalloc(&f->params, 4 * P)) != hipSuccess || (e = fmalloc(&f->params_t, tsize(f->type) * P)) != hipSuccess ||
+    const size_t PT = (size_t)f->per_layer_t * layers;
+    if ((e = fmalloc(&f->params, 4 * P)) != hipSuccess || (e = fmalloc(&f->params_t, tsize(f->type) * PT)) != hipSuccess ||
         (e = fmalloc(&f->m, 4 * P)) != hipSuccess || (e = fmalloc(&f->v, 4 * P)) != hipSuccess ||
         (e = fmalloc(&f->grad, 4 * P)) != hipSuccess) {
         msx_flow_destroy(f);
         return ffail(nullptr, e == hipErrorOutOfMemory ? MSX_ERR_OOM : MSX_ERR_DEVICE, "flow parameters");
     }
-    if (hipMemset(f->params, 0, 4 * P) != hipSuccess || hipMemset(f->params_t, 0, tsize(f->type) * P) != hipSuccess ||
+    if (hipMemset(f->params, 0, 4 * P) != hipSuccess || hipMemset(f->params_t, 0, tsize(f->type) * PT) != hipSuccess ||
         hipMemset(f->m, 0, 4 * P) != hipSuccess || hipMemset(f->v, 0, 4 * P) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         msx_flow_destroy(f);
@@ -390,7 +393,7 @@ msx_status msx_flow_set_params(msx_flow* f, const float* host, int64_t n) {
     FHIP(f, hipMemset(f->m, 0, sizeof(float) * n), "flow clear");
     FHIP(f, hipMemset(f->v, 0, sizeof(float) * n), "flow clear");
     f->adam_t = 0;
-    FHIP(f, launch_cast(n, f->params, f->type, f->params_t, nullptr), "flow cast");
+    FHIP(f, launch_cast(n, f->params, f->type, f->params_t, f->per_layer, f->per_layer_t, nullptr), "flow cast");
     FHIP(f, hipDeviceSynchronize(), "flow synchronise");
     return MSX_OK;
 }
@@ -413,7 +416,7 @@ msx_status msx_flow_forward(msx_flow* f, int64_t n, const float* u, float* y, fl
     FHIP(f, hipSetDevice(f->device), "hipSetDevice");
     // whole layers in one kernel where the shape allows it (BF16, hidden 128,
     // <= 16 bins, 16-byte aligned layer blocks); no work buffers then
-    const bool fused = f->type == FT_BF16 && f->H == kFusedHidden && f->K <= kFusedMaxBins && f->per_layer % 8 == 0;
+    const bool fused = f->type == FT_BF16 && f->H == kFusedHidden && f->K <= kFusedMaxBins;
     if (!fused)
         if (msx_status st = ensure_work(f, n)) return st;
     if (y != u) FHIP(f, hipMemcpyAsync(y, u, sizeof(float) * (size_t)f->d * n, hipMemcpyDeviceToDevice, s), "flow copy");
@@ -422,7 +425,7 @@ msx_status msx_flow_forward(msx_flow* f, int64_t n, const float* u, float* y, fl
         if (fused) {
             const int64_t base = l * f->per_layer;
             FHIP(f,
-                 launch_flow_layer_fwd(y, n, tptr(f, f->params_t, base), f->params + base, f->off, f->nh,
+                 launch_flow_layer_fwd(y, n, tptr(f, f->params_t, l * f->per_layer_t), f->params + base, f->off, f->nh,
                                        f->trans[l].data(), f->cond[l].data(), f->K, logdet, s),
                  "flow layer");
             continue;
@@ -476,7 +479,8 @@ msx_status msx_flow_train_step(msx_flow* f, int64_t n, const float* y, const dou
     f->adam_t += 1;
     const double c1 = 1.0 - std::pow(b1, (double)f->adam_t), c2 = 1.0 - std::pow(b2, (double)f->adam_t);
     const float lr_t = (float)(lr * std::sqrt(c2) / c1), eps_t = (float)(eps * std::sqrt(c2));
-    FHIP(f, launch_adam(f->P, f->params, f->grad, f->m, f->v, (float)b1, (float)b2, lr_t, eps_t, f->type, f->params_t, s),
+    FHIP(f, launch_adam(f->P, f->params, f->grad, f->m, f->v, (float)b1, (float)b2, lr_t, eps_t, f->type, f->params_t,
+                        f->per_layer, f->per_layer_t, s),
          "flow adam");
     return MSX_OK;
 }

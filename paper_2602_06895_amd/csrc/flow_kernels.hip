@@ -561,10 +561,19 @@ __global__ __launch_bounds__(256) void k_scale_by_loss(int64_t n, const double* 
     if (i < n) G[i] = (float)((double)G[i] / loss[0]);
 }
 
+// The operand copy pads every layer block to a multiple of 8 elements
+// (16-byte aligned fragments): master element i = layer * per + j sits at
+// layer * per_t + j.
+__device__ __forceinline__ int64_t padded_index(int64_t i, int64_t per, int64_t per_t) {
+    const int64_t l = i / per;
+    return l * per_t + (i - l * per);
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_adam(int64_t P, float* __restrict__ p, const float* __restrict__ g,
                                               float* __restrict__ m, float* __restrict__ v, float b1, float b2,
-                                              float lr_t, float eps_t, T* __restrict__ pt) {
+                                              float lr_t, float eps_t, T* __restrict__ pt, int64_t per,
+                                              int64_t per_t) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P) return;
     const float gi = g[i];
@@ -574,13 +583,14 @@ __global__ __launch_bounds__(256) void k_adam(int64_t P, float* __restrict__ p, 
     v[i] = vi;
     const float q = p[i] - lr_t * mi / (sqrtf(vi) + eps_t);
     p[i] = q;
-    pt[i] = to_t<T>(q);
+    pt[padded_index(i, per, per_t)] = to_t<T>(q);
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_cast(int64_t P, const float* __restrict__ p, T* __restrict__ pt) {
+__global__ __launch_bounds__(256) void k_cast(int64_t P, const float* __restrict__ p, T* __restrict__ pt, int64_t per,
+                                              int64_t per_t) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < P) pt[i] = to_t<T>(p[i]);
+    if (i < P) pt[padded_index(i, per, per_t)] = to_t<T>(p[i]);
 }
 
 __global__ __launch_bounds__(256) void k_uniform_f32(uint64_t seed, uint64_t sid, uint64_t e0, int64_t n, int d,
@@ -910,19 +920,22 @@ hipError_t launch_flow_loss(int64_t n, const double* wfj, const float* logq, con
 }
 
 hipError_t launch_adam(int64_t P, float* params, const float* grad, float* m, float* v, float b1, float b2,
-                       float lr_t, float eps_t, int type, void* params_t, hipStream_t s) {
+                       float lr_t, float eps_t, int type, void* params_t, int64_t per, int64_t per_t, hipStream_t s) {
     if (type == FT_BF16)
-        k_adam<__bf16><<<blocks(P), 256, 0, s>>>(P, params, grad, m, v, b1, b2, lr_t, eps_t, (__bf16*)params_t);
+        k_adam<__bf16><<<blocks(P), 256, 0, s>>>(P, params, grad, m, v, b1, b2, lr_t, eps_t, (__bf16*)params_t, per,
+                                                  per_t);
     else
-        k_adam<float><<<blocks(P), 256, 0, s>>>(P, params, grad, m, v, b1, b2, lr_t, eps_t, (float*)params_t);
+        k_adam<float><<<blocks(P), 256, 0, s>>>(P, params, grad, m, v, b1, b2, lr_t, eps_t, (float*)params_t, per,
+                                                 per_t);
     return hipGetLastError();
 }
 
-hipError_t launch_cast(int64_t P, const float* params, int type, void* params_t, hipStream_t s) {
+hipError_t launch_cast(int64_t P, const float* params, int type, void* params_t, int64_t per, int64_t per_t,
+                       hipStream_t s) {
     if (type == FT_BF16)
-        k_cast<__bf16><<<blocks(P), 256, 0, s>>>(P, params, (__bf16*)params_t);
+        k_cast<__bf16><<<blocks(P), 256, 0, s>>>(P, params, (__bf16*)params_t, per, per_t);
     else
-        k_cast<float><<<blocks(P), 256, 0, s>>>(P, params, (float*)params_t);
+        k_cast<float><<<blocks(P), 256, 0, s>>>(P, params, (float*)params_t, per, per_t);
     return hipGetLastError();
 }
 

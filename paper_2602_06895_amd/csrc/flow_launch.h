@@ -43,8 +43,9 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t s);
 
 // One whole forward coupling layer in one kernel (BF16 operands, hidden width
 // 128, up to 16 bins): conditioner on the matrix cores and spline, z updated
-// in place, logdet accumulated.  params_t / params: the layer's weights in
-// BF16 / biases in FP32 at the offsets off[0..7] (W1 b1 W2 b2 W3 b3 W4 b4).
+// in place, logdet accumulated.  params_t / params: the layer's block of the
+// BF16 operand copy (16-byte aligned) / of the FP32 parameters (biases), with
+// the offsets off[0..7] (W1 b1 W2 b2 W3 b3 W4 b4) in both.
 hipError_t launch_flow_layer_fwd(float* z, int64_t n, const void* params_t, const float* params, const int64_t* off,
                                  int nh, const int32_t* trans_host, const int32_t* cond_host, int K, float* logdet,
                                  hipStream_t s);
@@ -90,10 +91,12 @@ hipError_t launch_flow_loss(int64_t n, const double* wfj, const float* logq, con
                             double* part, double* loss, bool log_loss, hipStream_t s);
 
 // Adam step on P parameters (bias corrections folded into lr_t, eps_t by the
-// caller), then the operand copy of the parameters in `type`.
+// caller), then the operand copy of the parameters in `type`.  The copy pads
+// each layer block of `per` parameters to `per_t` (a multiple of 8).
 hipError_t launch_adam(int64_t P, float* params, const float* grad, float* m, float* v, float b1, float b2,
-                       float lr_t, float eps_t, int type, void* params_t, hipStream_t s);
-hipError_t launch_cast(int64_t P, const float* params, int type, void* params_t, hipStream_t s);
+                       float lr_t, float eps_t, int type, void* params_t, int64_t per, int64_t per_t, hipStream_t s);
+hipError_t launch_cast(int64_t P, const float* params, int type, void* params_t, int64_t per, int64_t per_t,
+                       hipStream_t s);
 
 // u[k][i] = 24-bit Philox uniforms in (0, 1) (same counters as the FP64
 // generator: key (seed, sid), counter (e0 + i, k / 4, 0, 0)).

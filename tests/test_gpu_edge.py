@@ -132,3 +132,28 @@ def test_device_counts_all_zero(torch):
     assert np.all(ctx.stats() == 0)
     g.close()
     ctx.close()
+
+
+def test_fused_forward_with_padded_layer_blocks(torch):
+    """d = 10 (five transformed coordinates): layer blocks of 65,397 parameters,
+    padded in the BF16 operand copy so that the fused layer kernel can run;
+    forward against the BF16-rounded oracle and the unfused inverse round
+    trip."""
+    from paper_2602_06895_amd import FLOW_BF16, Flow
+
+    d = 10
+    params = W.flow_params(43, d, 8, 16, 128, last_scale=0.05)
+    f = Flow(d, 8, 16, 128, mlp=FLOW_BF16)
+    f.set_params(params)
+    u = W.philox_uniforms_f32(9, 4, 0, 3000, d)
+    y, ld = f.forward(torch.from_numpy(u).cuda())
+    ub, lq = f.inverse(y)
+    torch.cuda.synchronize()
+    orc = F.Flow(d, 8, 16, 128, params=torch.as_tensor(params.astype(np.float64)), bf16_mlp=True)
+    yr, ldr = orc.forward(torch.from_numpy(u.T.astype(np.float64)))
+    # BF16 rounding decisions on FP32 accumulators vs FP64 ones (one BF16 ulp)
+    assert np.abs(y.cpu().numpy().T - yr.numpy()).max() < 2e-3
+    assert np.abs(ld.cpu().numpy() - ldr.numpy()).max() < 2e-2
+    assert np.abs(ub.cpu().numpy() - u).max() < 2e-5
+    assert np.abs(lq.cpu().numpy() + ld.cpu().numpy()).max() < 2e-4
+    f.close()

@@ -677,11 +677,21 @@ __device__ __forceinline__ void hidden_layer(const __bf16* __restrict__ Wl, cons
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) a[t][s4] = *(const bf16x8*)&st[(16 * t + r16) * kFRow + 32 * s4 + 8 * kq];
     __syncthreads();  // the tile is overwritten below
-#pragma unroll 1
+    // weight fragments of the next column tile are in flight while this
+    // tile's MFMAs run
+    bf16x8 bn[4];
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) bn[s4] = *(const bf16x8*)&Wl[r16 * kFH + 32 * s4 + 8 * kq];
+#pragma unroll 2
     for (int c = 0; c < kFH / 16; ++c) {
         bf16x8 b[4];
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) b[s4] = *(const bf16x8*)&Wl[(16 * c + r16) * kFH + 32 * s4 + 8 * kq];
+        for (int s4 = 0; s4 < 4; ++s4) b[s4] = bn[s4];
+        if (c + 1 < kFH / 16) {
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4)
+                bn[s4] = *(const bf16x8*)&Wl[(16 * (c + 1) + r16) * kFH + 32 * s4 + 8 * kq];
+        }
         floatx4 acc[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -717,7 +727,7 @@ __global__ __launch_bounds__(64 * kFW) void k_flow_layer_fwd(float* __restrict__
             a1[t][i] = (__bf16)((k < nh && e < n) ? z[(int64_t)ci * n + e] : 0.0f);
         }
     }
-#pragma unroll 1
+#pragma unroll 2
     for (int c = 0; c < kFH / 16; ++c) {
         bf16x8 b;
 #pragma unroll
@@ -746,7 +756,7 @@ __global__ __launch_bounds__(64 * kFW) void k_flow_layer_fwd(float* __restrict__
     const bool active = e < n;
     float ld = 0.0f;
     for (int j = 0; j < nh; ++j) {
-#pragma unroll 1
+#pragma unroll 2
         for (int c = 0; c < (P + 15) / 16; ++c) {
             const int q = 16 * c + r16;          // parameter within the coordinate
             const int row = j * P + q;           // row of W4 / column of theta

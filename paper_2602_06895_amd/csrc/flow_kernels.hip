@@ -308,6 +308,53 @@ __device__ __forceinline__ Bin spline_bin(const float* __restrict__ th, int K, f
     return b;
 }
 
+// spline_bin for a bin count known at compile time: the exponentials are
+// evaluated once and kept in registers (the same values, summed in the same
+// order, as spline_bin).
+template <bool BY_Y, int KS>
+__device__ __forceinline__ Bin spline_bin_k(const float* __restrict__ th, float v) {
+    float mw = th[0], mh = th[KS];
+#pragma unroll
+    for (int i = 1; i < KS; ++i) {
+        mw = fmaxf(mw, th[i]);
+        mh = fmaxf(mh, th[KS + i]);
+    }
+    float ew[KS], eh[KS];
+    float sw = 0.0f, sh = 0.0f;
+#pragma unroll
+    for (int i = 0; i < KS; ++i) {
+        ew[i] = expf(th[i] - mw);
+        eh[i] = expf(th[KS + i] - mh);
+        sw += ew[i];
+        sh += eh[i];
+    }
+    const float cw = (1.0f - KS * kMinW) / sw, ch = (1.0f - KS * kMinH) / sh;
+    Bin b{};
+    float cx = 0.0f, cy = 0.0f, pw = 0.0f, ph = 0.0f;
+#pragma unroll
+    for (int i = 0; i < KS; ++i) {
+        const float xl = cx, yl = cy;
+        cx = (i == KS - 1) ? 1.0f : cx + (kMinW + cw * ew[i]);
+        cy = (i == KS - 1) ? 1.0f : cy + (kMinH + ch * eh[i]);
+        const bool take = (i == 0) || (v >= (BY_Y ? yl : xl));
+        if (take) {
+            b.k = i;
+            b.x0 = xl;
+            b.w = cx - xl;
+            b.y0 = yl;
+            b.h = cy - yl;
+            b.pw = pw;
+            b.ph = ph;
+        }
+        pw += ew[i] / sw;
+        ph += eh[i] / sh;
+    }
+    const float s0 = slope_shift();
+    b.d0 = kMinD + softplus_f(th[2 * KS + b.k] + s0);
+    b.d1 = kMinD + softplus_f(th[2 * KS + b.k + 1] + s0);
+    return b;
+}
+
 __device__ __forceinline__ float spline_slope(const Bin& b, float xi) {
     const float s = b.h / b.w;
     const float om = xi * (1.0f - xi);
@@ -347,8 +394,13 @@ __global__ __launch_bounds__(kSplineT) void k_spline(float* __restrict__ z, int6
             const float* th = slab + threadIdx.x * P;
             float* zp = z + (int64_t)trans.v[j] * n + e;
             const float v = *zp;
-            float mw, sw, mh, sh;
-            const Bin b = spline_bin<INV>(th, K, v, mw, sw, mh, sh);
+            Bin b;
+            if (K == 16) {
+                b = spline_bin_k<INV, 16>(th, v);
+            } else {
+                float mw, sw, mh, sh;
+                b = spline_bin<INV>(th, K, v, mw, sw, mh, sh);
+            }
             const float s = b.h / b.w;
             const float kap = b.d1 + b.d0 - 2.0f * s;
             float xi, out;
@@ -787,8 +839,13 @@ __global__ __launch_bounds__(64 * kFW) void k_flow_layer_fwd(float* __restrict__
         if (active) {
             float* zp = z + (int64_t)trans.v[j] * n + e;
             const float v = *zp;
-            float mw, sw, mh, sh;
-            const Bin bn = spline_bin<false>(th + lane * P, K, v, mw, sw, mh, sh);
+            Bin bn;
+            if (K == 16) {
+                bn = spline_bin_k<false, 16>(th + lane * P, v);
+            } else {
+                float mw, sw, mh, sh;
+                bn = spline_bin<false>(th + lane * P, K, v, mw, sw, mh, sh);
+            }
             const float sl = bn.h / bn.w;
             const float kap = bn.d1 + bn.d0 - 2.0f * sl;
             const float xi = (v - bn.x0) / bn.w;

@@ -19,6 +19,16 @@ namespace msx {
 // stride kBlock (conflict-free across a wave).  It occupies the first
 // kQBytes of the kernels' dynamic LDS; the VEGAS grid follows.
 constexpr size_t kQBytes = sizeof(double) * kMaxUniq * kBlock;
+
+// The fused sample kernel first writes the VEGAS-mapped uniforms of all an
+// event's dimensions into the same per-thread column (the chain reads them
+// back in order; the integrand's invariant store reuses the column after the
+// chain is done).  A channel of an (NS, NI) class has at most NS + NI + 1
+// dimensions: s-hat and x1, the time-like invariants and two per operation.
+template <int NS, int NI>
+constexpr int stage_rows() {
+    return (NS + NI + 1) > kMaxUniq ? (NS + NI + 1) : kMaxUniq;
+}
 struct LdsQ {
     double* b;
     __device__ __forceinline__ void set(int u, double x) { b[u * kBlock] = x; }
@@ -145,9 +155,11 @@ __global__ __launch_bounds__(kBlock) void k_sample(const ChannelTab* __restrict_
                                                    int64_t ld, double* __restrict__ p, double* __restrict__ x1x2,
                                                    double* __restrict__ w, int32_t* __restrict__ chan_out,
                                                    double* __restrict__ tile_stats) {
+    constexpr int kRows = stage_rows<NS, NI>();
     extern __shared__ double lds[];
-    double* lg = lds + kMaxUniq * kBlock;
-    const LdsQ q{lds + threadIdx.x};
+    double* lg = lds + kRows * kBlock;
+    double* const col = lds + threadIdx.x;
+    const LdsQ q{col};
     __shared__ double red[4][kWaves];
     int cur = -1;
     int nb = 0, dims = 0;
@@ -178,23 +190,21 @@ __global__ __launch_bounds__(kBlock) void k_sample(const ChannelTab* __restrict_
             const int64_t pos = base + (int64_t)sub * kBlock + threadIdx.x;
             if (pos >= end) break;
             const uint64_t e = ctr0 + (uint64_t)pos;
-            // uniforms on demand, four per Philox block (dimensions are consumed in order)
-            double ub[4];
-            int k = 0;
+            // all dimensions first, four per Philox block, VEGAS-mapped into
+            // this thread's LDS column: one copy of the generator in the code
+            // instead of one per place the chain draws a number
             double jv = 1.0;
-            auto next = [&]() -> double {
-                if ((k & 3) == 0) {
-                    uint64_t c0 = e, c1 = (uint64_t)(k >> 2), c2 = 0, c3 = 0;
-                    philox4x64_10(c0, c1, c2, c3, seed, sid);
-                    ub[0] = to_unit(c0);
-                    ub[1] = to_unit(c1);
-                    ub[2] = to_unit(c2);
-                    ub[3] = to_unit(c3);
-                }
-                double r = vegas_map(ub[k & 3], lg + k * (nb + 1), nb, jv);
-                ++k;
-                return r;
-            };
+#pragma unroll 1
+            for (int k4 = 0; k4 < dims; k4 += 4) {
+                uint64_t c0 = e, c1 = (uint64_t)(k4 >> 2), c2 = 0, c3 = 0;
+                philox4x64_10(c0, c1, c2, c3, seed, sid);
+                const uint64_t wd[4] = {c0, c1, c2, c3};
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (k4 + j < dims) col[(k4 + j) * kBlock] = vegas_map(to_unit(wd[j]), lg + (k4 + j) * (nb + 1), nb, jv);
+            }
+            int k = 0;
+            auto next = [&]() -> double { return col[(k++) * kBlock]; };
             double E[NS], X[NS], Y[NS], Z[NS], S[NI], SQ[NI];
             ChainOut o;
             run_chain<NS, NI, KINDS, MIX>(ct, s_lab, next, E, X, Y, Z, S, SQ, o);
@@ -233,7 +243,7 @@ hipError_t launch_chain_class(int kc, const ChainLaunch& a) {
     constexpr int K0 = KIND_POW_INT, K1 = KIND_POW_INT | KIND_BW, K2 = KINDS_ALL;
     auto go = [&](auto kt) {
         constexpr int K = decltype(kt)::value;
-        const size_t lds = a.lds + kQBytes;
+        const size_t lds = a.lds + (a.sample ? sizeof(double) * stage_rows<NS, NI>() * kBlock : kQBytes);
         if (lds > 65536) {
             // beyond the default 64 KiB per workgroup (gfx950 has 160 KiB per CU)
             const void* fn = a.sample ? (const void*)k_sample<NS, NI, K, MIX> : (const void*)k_map<NS, NI, K, MIX>;

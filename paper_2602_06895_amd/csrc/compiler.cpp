@@ -413,6 +413,8 @@ bool compile_channel(Ctx& cx, const JValue& cj, const std::vector<double>& masse
     for (int i = 0; i < t.n_blocks; ++i) t.kinds |= kind_bit(t.blk[i].tmap);
     t.dims = (hadronic ? 2 : 0) + (int)s_order.size() + std::max(kappa - 1, 0) + 2 * kappa + 2 * nd;
     if (t.dims > kMaxDims) return cx.fail("too many random dimensions");
+    // the sample kernel's per-thread staging column is sized by this bound
+    if (t.dims > 1 + t.n_inv + t.n_slots) return cx.fail("internal: dimension count exceeds invariants + slots + 1");
 
     // propagators of the diagram (for the local channel weights)
     props.clear();

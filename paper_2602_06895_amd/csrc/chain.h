@@ -485,8 +485,11 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
 }
 
 // Invariant store in private registers (the weight entry point).
+// Rows of the per-event invariant store: one per distinct invariant, plus
+// row kMaxUniq holding 1.0 (the pad of the channel products).
+constexpr int kQRows = kMaxUniq + 1;
 struct RegQ {
-    double v[kMaxUniq];
+    double v[kQRows];
     __device__ __forceinline__ void set(int u, double x) { v[u] = x; }
     __device__ __forceinline__ double get(int u) const { return v[u]; }
 };
@@ -502,7 +505,7 @@ template <int NF, class Get>
 __device__ __forceinline__ double inv_q2(const ProcessTab* __restrict__ pt, int u, double pae, double pax, double pay,
                                          double paz, Get get) {
     double qe = 0.0, qx = 0.0, qy = 0.0, qz = 0.0;
-    const uint32_t set = pt->uniq_set[u];
+    const uint32_t set = pt->uq[u].set;
 #pragma unroll
     for (int k = 0; k < NF; ++k) {
         if (set & (1u << k)) {
@@ -512,7 +515,7 @@ __device__ __forceinline__ double inv_q2(const ProcessTab* __restrict__ pt, int 
             qz += get(k, 3);
         }
     }
-    if (pt->uniq_t[u]) {
+    if (pt->uq[u].t) {
         qe = pae - qe;
         qx = pax - qx;
         qy = pay - qy;
@@ -569,21 +572,19 @@ __device__ __forceinline__ double integrand_alpha(const ProcessTab* __restrict__
     const int nc = pt->n_chan;
     double fden = 1.0;
     for (int u = 0; u < nu; ++u) {
+        const UniqSpec& us = pt->uq[u];
         const double q2 = inv_q2<NF>(pt, u, pae, pax, pay, paz, get);
-        const int fi = pt->uniq_f[u];
-        if (fi >= 0) {
-            if (pt->f_bw[fi]) {
-                const double d = q2 - pt->f_m2[fi];
-                fden *= d * d + pt->f_mw[fi] * pt->f_mw[fi];
-            } else {
-                fden *= fabs(q2) + pt->f_mu2[fi];
-            }
+        if (us.fkind == 1) {
+            const double d = q2 - us.fa;
+            fden *= d * d + us.fb;
+        } else if (us.fkind == 2) {
+            fden *= fabs(q2) + us.fa;
         }
         if (nc > 1) {
             double dd;
-            if (pt->uniq_massive[u] > 0) {
-                const double d = q2 - pt->uniq_m2[u];
-                dd = d * d + pt->uniq_mw[u] * pt->uniq_mw[u];
+            if (us.massive > 0) {
+                const double d = q2 - us.am2;
+                dd = d * d + us.amw2;
             } else {
                 const double d = fabs(q2) + pt->alpha_mu2;
                 dd = d * d;
@@ -594,14 +595,22 @@ __device__ __forceinline__ double integrand_alpha(const ProcessTab* __restrict__
     if (pt->n_fprop > 0) f /= fden;
     double alpha = 1.0;
     if (nc > 1) {
+        q.set(kMaxUniq, 1.0);
         double den = 0.0, mine = 0.0;
         for (int c = 0; c < nc; ++c) {
+            // product over the channel's invariants in ascending order, four
+            // independent loads per round (short rounds padded with the 1.0 row)
             double D = 1.0;
             uint32_t m = pt->chan_mask[c];
             while (m) {
-                const int u = __builtin_ctz(m);
-                m &= m - 1;
-                D *= q.get(u);
+                int u[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    u[j] = m ? __builtin_ctz(m) : kMaxUniq;
+                    m &= m - 1;
+                }
+                const double v0 = q.get(u[0]), v1 = q.get(u[1]), v2 = q.get(u[2]), v3 = q.get(u[3]);
+                D = D * v0 * v1 * v2 * v3;
             }
             const double P = 1.0 / D;
             den += P;

@@ -15,10 +15,10 @@
 
 namespace msx {
 
-// Per-thread column of the invariant store in LDS: kMaxUniq doubles with
+// Per-thread column of the invariant store in LDS: kQRows doubles with
 // stride kBlock (conflict-free across a wave).  It occupies the first
 // kQBytes of the kernels' dynamic LDS; the VEGAS grid follows.
-constexpr size_t kQBytes = sizeof(double) * kMaxUniq * kBlock;
+constexpr size_t kQBytes = sizeof(double) * kQRows * kBlock;
 
 // The fused sample kernel first writes the VEGAS-mapped uniforms of all an
 // event's dimensions into the same per-thread column (the chain reads them
@@ -27,7 +27,7 @@ constexpr size_t kQBytes = sizeof(double) * kMaxUniq * kBlock;
 // dimensions: s-hat and x1, the time-like invariants and two per operation.
 template <int NS, int NI>
 constexpr int stage_rows() {
-    return (NS + NI + 1) > kMaxUniq ? (NS + NI + 1) : kMaxUniq;
+    return (NS + NI + 1) > kQRows ? (NS + NI + 1) : kQRows;
 }
 struct LdsQ {
     double* b;
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kBlock) void k_map(const ChannelTab* __restrict__ c
                                                 double* __restrict__ x1x2, double* __restrict__ jac,
                                                 double* __restrict__ w) {
     extern __shared__ double lds[];
-    double* lg = lds + kMaxUniq * kBlock;
+    double* lg = lds + kQRows * kBlock;
     const LdsQ q{lds + threadIdx.x};
     const int dims = ct->dims;
     for (int i = threadIdx.x; i < dims * (nb + 1); i += blockDim.x) lg[i] = grid[i];

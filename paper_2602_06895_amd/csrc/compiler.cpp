@@ -588,6 +588,18 @@ bool compile_process(Ctx& cx, const JValue& pj, Compiled& out) {
         out.chans.push_back(t);
         out.meta.push_back(meta);
     }
+    for (int u = 0; u < pt.n_uniq; ++u) {
+        UniqSpec& q = pt.uq[u];
+        q.set = pt.uniq_set[u];
+        q.t = pt.uniq_t[u];
+        const int f = pt.uniq_f[u];
+        q.fkind = f < 0 ? 0 : (pt.f_bw[f] ? 1 : 2);
+        q.fa = f < 0 ? 0.0 : (pt.f_bw[f] ? pt.f_m2[f] : pt.f_mu2[f]);
+        q.fb = f < 0 ? 0.0 : (pt.f_bw[f] ? pt.f_mw[f] * pt.f_mw[f] : 0.0);
+        q.massive = pt.uniq_massive[u];
+        q.am2 = pt.uniq_m2[u];
+        q.amw2 = pt.uniq_mw[u] * pt.uniq_mw[u];
+    }
     out.procs.push_back(pt);
     return true;
 }

@@ -109,6 +109,17 @@ struct ChannelTab {
 };
 
 // Integrand and local channel weights of one process.
+// Everything the integrand needs about one distinct invariant, read with
+// one scalar load per invariant.
+struct UniqSpec {
+    uint32_t set;    // particle set
+    int32_t t;       // 1: q = p_a - sum over the set, 0: q = sum
+    int32_t fkind;   // integrand factor on q^2: 0 none, 1 Breit-Wigner, 2 1/(|q^2| + mu^2)
+    int32_t massive; // channel-weight form: 1 massive, 0 massless, -1 not in any channel
+    double fa, fb;   // factor constants: (m^2, (m w)^2) or (mu^2, 0)
+    double am2, amw2;  // channel-weight constants (m^2, (m w)^2)
+};
+
 struct ProcessTab {
     int32_t n_final;
     int32_t hadronic;
@@ -138,6 +149,7 @@ struct ProcessTab {
     double f_m2[kMaxFactors];
     double f_mw[kMaxFactors];
     double f_mu2[kMaxFactors];
+    UniqSpec uq[kMaxUniq];                // the fields above, per invariant
 };
 
 // Per-call description of a multichannel launch (passed by value).

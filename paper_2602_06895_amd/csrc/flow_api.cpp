@@ -42,6 +42,7 @@ struct msx_flow {
     void* dhb = nullptr;     // [cap][H]
     float* dx0 = nullptr;    // [cap][nh]
     float* adj = nullptr;    // [d][cap]
+    float* ldp = nullptr;    // [nh][cap] per-coordinate log-det terms
     float* part = nullptr;   // split-K partials
     int64_t part_cap = 0;
     double* lpart = nullptr;  // loss partials (1024) + loss (1)
@@ -98,6 +99,8 @@ void free_work(msx_flow* f) {
     ffree(f->dhb);
     ffree(f->dx0);
     ffree(f->adj);
+    ffree(f->ldp);
+    f->ldp = nullptr;
     f->z = nullptr;
     f->x0 = f->h = f->dtheta = f->dha = f->dhb = nullptr;
     f->theta = f->logq = f->G = f->dx0 = f->adj = nullptr;
@@ -121,6 +124,7 @@ msx_status ensure_work(msx_flow* f, int64_t n) {
     FHIP(f, fmalloc(&f->dhb, ts * N * f->H), "flow work");
     FHIP(f, fmalloc(&f->dx0, sizeof(float) * N * f->nh), "flow work");
     FHIP(f, fmalloc(&f->adj, sizeof(float) * (size_t)f->d * N), "flow work");
+    FHIP(f, fmalloc(&f->ldp, sizeof(float) * (size_t)f->nh * N), "flow work");
     f->cap = n;
     return MSX_OK;
 }
@@ -225,7 +229,7 @@ msx_status inverse_saving(msx_flow* f, int64_t n, const float* y, hipStream_t s)
         float* th = f->theta + (size_t)l * n * f->n_out;
         if (msx_status st = run_mlp(f, l, zin, n, x0, h, th, s)) return st;
         FHIP(f, hipMemcpyAsync(zout, zin, sizeof(float) * zs, hipMemcpyDeviceToDevice, s), "flow copy");
-        FHIP(f, launch_spline(true, zout, n, th, f->n_out, f->nh, f->trans[l].data(), f->K, f->logq, s),
+        FHIP(f, launch_spline(true, zout, n, th, f->n_out, f->nh, f->trans[l].data(), f->K, f->logq, f->ldp, s),
              "flow spline");
     }
     return MSX_OK;
@@ -431,7 +435,7 @@ msx_status msx_flow_forward(msx_flow* f, int64_t n, const float* u, float* y, fl
             continue;
         }
         if (msx_status st = run_mlp(f, l, y, n, f->x0, f->h, f->theta, s)) return st;
-        FHIP(f, launch_spline(false, y, n, f->theta, f->n_out, f->nh, f->trans[l].data(), f->K, logdet, s),
+        FHIP(f, launch_spline(false, y, n, f->theta, f->n_out, f->nh, f->trans[l].data(), f->K, logdet, f->ldp, s),
              "flow spline");
     }
     return MSX_OK;
@@ -449,7 +453,7 @@ msx_status msx_flow_inverse(msx_flow* f, int64_t n, const float* y, float* u, fl
     FHIP(f, hipMemsetAsync(logq, 0, sizeof(float) * n, s), "flow clear");
     for (int l = f->L - 1; l >= 0; --l) {
         if (msx_status st = run_mlp(f, l, u, n, f->x0, f->h, f->theta, s)) return st;
-        FHIP(f, launch_spline(true, u, n, f->theta, f->n_out, f->nh, f->trans[l].data(), f->K, logq, s),
+        FHIP(f, launch_spline(true, u, n, f->theta, f->n_out, f->nh, f->trans[l].data(), f->K, logq, f->ldp, s),
              "flow spline");
     }
     return MSX_OK;

@@ -197,26 +197,54 @@ __global__ __launch_bounds__(GT) void k_gemm(GemmArgs g, int kchunk) {
             }
 }
 
+// out[i] = sum over z of part[z][i], i < M N.  A workgroup takes 64
+// consecutive i; its four waves sum the partials z = w, w + 4, w + 8, ...
+// with four independent accumulators each, then the 16 sums of every i are
+// added in a fixed order (deterministic for a given split count).
 __global__ __launch_bounds__(256) void k_reduce_partials(const float* __restrict__ part, int splits, int M, int N,
                                                          float* __restrict__ out, int64_t ldo) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ float red[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t MN = (int64_t)M * N;
-    if (i >= MN) return;
-    float s = 0.0f;
-    for (int z = 0; z < splits; ++z) s += part[z * MN + i];
-    const int64_t r = i / N, c = i % N;
-    out[r * ldo + c] = s;
+    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+    if (i < MN) {
+        int z = w;
+        for (; z + 12 < splits; z += 16) {
+            a0 += part[(int64_t)z * MN + i];
+            a1 += part[(int64_t)(z + 4) * MN + i];
+            a2 += part[(int64_t)(z + 8) * MN + i];
+            a3 += part[(int64_t)(z + 12) * MN + i];
+        }
+        for (; z < splits; z += 4) a0 += part[(int64_t)z * MN + i];
+    }
+    red[w][lane] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (w == 0 && i < MN) {
+        const float sum = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+        const int64_t r = i / N, c = i % N;
+        out[r * ldo + c] = sum;
+    }
 }
 
+// Column sums of X [R][N] in row chunks: part[chunk][c].  Threads take
+// columns; four independent accumulators over rows r, r + 1, r + 2, r + 3.
 template <class T>
 __global__ __launch_bounds__(256) void k_colsum(const T* __restrict__ X, int64_t R, int N, int64_t ldx, int64_t chunk,
                                                 float* __restrict__ part) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= N) return;
     const int64_t r0 = (int64_t)blockIdx.y * chunk, r1 = min(R, r0 + chunk);
-    float s = 0.0f;
-    for (int64_t r = r0; r < r1; ++r) s += (float)X[r * ldx + c];
-    part[(int64_t)blockIdx.y * N + c] = s;
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+    int64_t r = r0;
+    for (; r + 3 < r1; r += 4) {
+        s0 += (float)X[r * ldx + c];
+        s1 += (float)X[(r + 1) * ldx + c];
+        s2 += (float)X[(r + 2) * ldx + c];
+        s3 += (float)X[(r + 3) * ldx + c];
+    }
+    for (; r < r1; ++r) s0 += (float)X[r * ldx + c];
+    part[(int64_t)blockIdx.y * N + c] = (s0 + s1) + (s2 + s3);
 }
 
 // ---------------------------------------------------------------------------
@@ -312,15 +340,16 @@ __device__ __forceinline__ Bin spline_bin(const float* __restrict__ th, int K, f
 // evaluated once and kept in registers (the same values, summed in the same
 // order, as spline_bin).
 template <bool BY_Y, int KS>
-__device__ __forceinline__ Bin spline_bin_k(const float* __restrict__ th, float v) {
+__device__ __forceinline__ Bin spline_bin_k(const float* __restrict__ th, float v, float (&ew)[KS], float (&eh)[KS],
+                                            float& sw, float& sh) {
     float mw = th[0], mh = th[KS];
 #pragma unroll
     for (int i = 1; i < KS; ++i) {
         mw = fmaxf(mw, th[i]);
         mh = fmaxf(mh, th[KS + i]);
     }
-    float ew[KS], eh[KS];
-    float sw = 0.0f, sh = 0.0f;
+    sw = 0.0f;
+    sh = 0.0f;
 #pragma unroll
     for (int i = 0; i < KS; ++i) {
         ew[i] = expf(th[i] - mw);
@@ -354,6 +383,11 @@ __device__ __forceinline__ Bin spline_bin_k(const float* __restrict__ th, float 
     b.d1 = kMinD + softplus_f(th[2 * KS + b.k + 1] + s0);
     return b;
 }
+template <bool BY_Y, int KS>
+__device__ __forceinline__ Bin spline_bin_k(const float* __restrict__ th, float v) {
+    float ew[KS], eh[KS], sw, sh;
+    return spline_bin_k<BY_Y, KS>(th, v, ew, eh, sw, sh);
+}
 
 __device__ __forceinline__ float spline_slope(const Bin& b, float xi) {
     const float s = b.h / b.w;
@@ -377,17 +411,20 @@ __device__ __forceinline__ void load_slab(const float* __restrict__ theta, int64
     }
 }
 
+// One transformed coordinate j = blockIdx.y of kSplineT events per block (the
+// coordinates are independent, so the grid carries nh times more waves);
+// its log |dy/dx| (or log |dx/dy|) goes to ldp[j][e] and k_ld_add sums them.
 template <bool INV>
 __global__ __launch_bounds__(kSplineT) void k_spline(float* __restrict__ z, int64_t n, const float* __restrict__ theta,
-                                                     int64_t ldt, int nh, Idx trans, int K, float* __restrict__ logdet) {
+                                                     int64_t ldt, Idx trans, int K, float* __restrict__ ldp) {
     extern __shared__ float slab[];
     const int64_t e0 = (int64_t)blockIdx.x * kSplineT;
     const int rows = (int)min<int64_t>(kSplineT, n - e0);
     const int P = 3 * K + 1;
     const int64_t e = e0 + threadIdx.x;
     const bool active = threadIdx.x < rows;
-    float ld = 0.0f;
-    for (int j = 0; j < nh; ++j) {
+    const int j = blockIdx.y;
+    {
         load_slab(theta, ldt, e0, rows, j, P, slab);
         __syncthreads();
         if (active) {
@@ -418,12 +455,20 @@ __global__ __launch_bounds__(kSplineT) void k_spline(float* __restrict__ z, int6
                 out = b.x0 + xi * b.w;
             }
             const float g = spline_slope(b, xi);
-            ld += INV ? -logf(g) : logf(g);
+            ldp[(int64_t)j * n + e] = INV ? -logf(g) : logf(g);
             *zp = out;
         }
-        __syncthreads();
     }
-    if (active) logdet[e] += ld;
+}
+
+// logdet[e] += sum over j of ldp[j][e], j in order.
+__global__ __launch_bounds__(256) void k_ld_add(const float* __restrict__ ldp, int64_t n, int nh,
+                                                float* __restrict__ logdet) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    float ld = 0.0f;
+    for (int j = 0; j < nh; ++j) ld += ldp[(int64_t)j * n + e];
+    logdet[e] += ld;
 }
 
 // Forward-mode dual numbers with 7 tangents: (y, x0, w, y0, h, d0, d1).
@@ -499,76 +544,109 @@ __device__ __forceinline__ D7 dlog(const D7& a) {
 // Reverse mode through the inverse spline of one layer (see flow_launch.h).
 // The parameter slab comes in through LDS and the parameter gradients go out
 // through a second LDS slab with coalesced stores.
+// Reverse mode of the inverse spline of one (event, coordinate): gradient
+// of G ld + adj x with respect to y (into adj) and the layer's 3K + 1
+// unconstrained parameters (into dth).  KS > 0: the bin count is KS and the
+// bin exponentials are computed once (the same values as the general path).
+// th and dth may be the same row: each element is read before it is written.
+template <int KS>
+__device__ __forceinline__ void spline_backward_one(const float* th, int K, float v, float ge, float& ax, float* dth) {
+    constexpr int KX = KS > 0 ? KS : 1;
+    float ewk[KX], ehk[KX];
+    float mw = 0.0f, sw, mh = 0.0f, sh;
+    Bin bn;
+    if (KS > 0) {
+        bn = spline_bin_k<true, KX>(th, v, ewk, ehk, sw, sh);
+    } else {
+        bn = spline_bin<true>(th, K, v, mw, sw, mh, sh);
+    }
+    auto pw_of = [&](int i) -> float { return KS > 0 ? ewk[i] / sw : expf(th[i] - mw) / sw; };
+    auto ph_of = [&](int i) -> float { return KS > 0 ? ehk[i] / sh : expf(th[K + i] - mh) / sh; };
+    // x = S^-1(y) and ld = log (S^-1)'(y) = -log S'(x) as duals
+    const D7 Y = dvar(v, 0), X0 = dvar(bn.x0, 1), W = dvar(bn.w, 2), Y0 = dvar(bn.y0, 3), H = dvar(bn.h, 4),
+             Dd0 = dvar(bn.d0, 5), Dd1 = dvar(bn.d1, 6);
+    const D7 s = H / W;
+    const D7 dy = Y - Y0;
+    const D7 kap = Dd1 + Dd0 - 2.0f * s;
+    const D7 qa = H * (s - Dd0) + dy * kap;
+    const D7 qb = H * Dd0 - dy * kap;
+    const D7 qc = dconst(0.0f) - s * dy;
+    D7 disc = qb * qb - 4.0f * (qa * qc);
+    disc.v = fmaxf(disc.v, 1e-30f);
+    const D7 xi = (2.0f * qc) / (dconst(0.0f) - qb - dsqrt(disc));
+    const D7 X = X0 + xi * W;
+    const D7 om = xi * (dconst(1.0f) - xi);
+    const D7 den = s + kap * om;
+    const D7 omx = dconst(1.0f) - xi;
+    const D7 num = s * s * (Dd1 * xi * xi + 2.0f * (s * om) + Dd0 * omx * omx);
+    const D7 ld = 2.0f * dlog(den) - dlog(num);
+    float gp[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) gp[i] = ax * X.g[i] + ge * ld.g[i];
+    ax = gp[0];
+    // to the unconstrained parameters: softmax of widths / heights, softplus of slopes
+    const float Cw = 1.0f - K * kMinW, Ch = 1.0f - K * kMinH;
+    float pwk = 0.0f, phk = 0.0f;
+    if (KS > 0) {
+#pragma unroll
+        for (int i = 0; i < KX; ++i)
+            if (i == bn.k) {
+                pwk = pw_of(i);
+                phk = ph_of(i);
+            }
+    } else {
+        pwk = pw_of(bn.k);
+        phk = ph_of(bn.k);
+    }
+    const float sumw = gp[1] * bn.pw + gp[2] * pwk;
+    const float sumh = gp[3] * bn.ph + gp[4] * phk;
+#pragma unroll
+    for (int i = 0; i < (KS > 0 ? KS : K); ++i) {
+        const float pwi = pw_of(i), phi = ph_of(i);
+        const float dwi = (i < bn.k ? gp[1] : 0.0f) + (i == bn.k ? gp[2] : 0.0f);
+        const float dhi = (i < bn.k ? gp[3] : 0.0f) + (i == bn.k ? gp[4] : 0.0f);
+        dth[i] = Cw * pwi * (dwi - sumw);
+        dth[K + i] = Ch * phi * (dhi - sumh);
+    }
+    const float s0 = slope_shift();
+#pragma unroll
+    for (int i = 0; i <= (KS > 0 ? KS : K); ++i) {
+        const float dd = (i == bn.k ? gp[5] : 0.0f) + (i == bn.k + 1 ? gp[6] : 0.0f);
+        dth[2 * K + i] = dd * sigmoid_f(th[2 * K + i] + s0);
+    }
+}
+
 template <class T>
 __global__ __launch_bounds__(kSplineT) void k_spline_backward(const float* __restrict__ y, float* __restrict__ adj,
                                                               int64_t n, const float* __restrict__ theta, int64_t ldt,
-                                                              int nh, Idx trans, int K, const float* __restrict__ G,
+                                                              Idx trans, int K, const float* __restrict__ G,
                                                               T* __restrict__ dtheta) {
     extern __shared__ float slab[];
     const int P = 3 * K + 1;
-    float* dslab = slab + kSplineT * P;
+    // d theta overwrites theta in the thread's own row: every parameter is
+    // read before the element of the same index is written
+    float* dslab = slab;
     const int64_t e0 = (int64_t)blockIdx.x * kSplineT;
     const int rows = (int)min<int64_t>(kSplineT, n - e0);
     const int64_t e = e0 + threadIdx.x;
     const bool active = threadIdx.x < rows;
-    const float ge = active ? G[e] : 0.0f;
-    for (int j = 0; j < nh; ++j) {
-        load_slab(theta, ldt, e0, rows, j, P, slab);
-        __syncthreads();
-        if (active) {
-            const float* th = slab + threadIdx.x * P;
-            float* dth = dslab + threadIdx.x * P;
-            const int64_t zi = (int64_t)trans.v[j] * n + e;
-            const float v = y[zi];
-            float mw, sw, mh, sh;
-            const Bin bn = spline_bin<true>(th, K, v, mw, sw, mh, sh);
-            // x = S^-1(y) and ld = log (S^-1)'(y) = -log S'(x) as duals
-            const D7 Y = dvar(v, 0), X0 = dvar(bn.x0, 1), W = dvar(bn.w, 2), Y0 = dvar(bn.y0, 3), H = dvar(bn.h, 4),
-                     Dd0 = dvar(bn.d0, 5), Dd1 = dvar(bn.d1, 6);
-            const D7 s = H / W;
-            const D7 dy = Y - Y0;
-            const D7 kap = Dd1 + Dd0 - 2.0f * s;
-            const D7 qa = H * (s - Dd0) + dy * kap;
-            const D7 qb = H * Dd0 - dy * kap;
-            const D7 qc = dconst(0.0f) - s * dy;
-            D7 disc = qb * qb - 4.0f * (qa * qc);
-            disc.v = fmaxf(disc.v, 1e-30f);
-            const D7 xi = (2.0f * qc) / (dconst(0.0f) - qb - dsqrt(disc));
-            const D7 X = X0 + xi * W;
-            const D7 om = xi * (dconst(1.0f) - xi);
-            const D7 den = s + kap * om;
-            const D7 omx = dconst(1.0f) - xi;
-            const D7 num = s * s * (Dd1 * xi * xi + 2.0f * (s * om) + Dd0 * omx * omx);
-            const D7 ld = 2.0f * dlog(den) - dlog(num);
-            const float ax = adj[zi];
-            float gp[7];
-#pragma unroll
-            for (int i = 0; i < 7; ++i) gp[i] = ax * X.g[i] + ge * ld.g[i];
-            adj[zi] = gp[0];
-            // to the unconstrained parameters: softmax of widths / heights, softplus of slopes
-            const float Cw = 1.0f - K * kMinW, Ch = 1.0f - K * kMinH;
-            const float sumw = gp[1] * bn.pw + gp[2] * (expf(th[bn.k] - mw) / sw);
-            const float sumh = gp[3] * bn.ph + gp[4] * (expf(th[K + bn.k] - mh) / sh);
-            for (int i = 0; i < K; ++i) {
-                const float pwi = expf(th[i] - mw) / sw, phi = expf(th[K + i] - mh) / sh;
-                const float dwi = (i < bn.k ? gp[1] : 0.0f) + (i == bn.k ? gp[2] : 0.0f);
-                const float dhi = (i < bn.k ? gp[3] : 0.0f) + (i == bn.k ? gp[4] : 0.0f);
-                dth[i] = Cw * pwi * (dwi - sumw);
-                dth[K + i] = Ch * phi * (dhi - sumh);
-            }
-            const float s0 = slope_shift();
-            for (int i = 0; i <= K; ++i) {
-                const float dd = (i == bn.k ? gp[5] : 0.0f) + (i == bn.k + 1 ? gp[6] : 0.0f);
-                dth[2 * K + i] = dd * sigmoid_f(th[2 * K + i] + s0);
-            }
-        }
-        __syncthreads();
-        const int total = rows * P;
-        for (int i = threadIdx.x; i < total; i += kSplineT) {
-            const int r = i / P, c = i - r * P;
-            dtheta[(e0 + r) * ldt + (int64_t)j * P + c] = to_t<T>(dslab[i]);
-        }
-        __syncthreads();
+    const int j = blockIdx.y;  // one transformed coordinate per block row of the grid
+    load_slab(theta, ldt, e0, rows, j, P, slab);
+    __syncthreads();
+    if (active) {
+        const int64_t zi = (int64_t)trans.v[j] * n + e;
+        float ax = adj[zi];
+        if (K == 16)
+            spline_backward_one<16>(slab + threadIdx.x * P, K, y[zi], G[e], ax, dslab + threadIdx.x * P);
+        else
+            spline_backward_one<0>(slab + threadIdx.x * P, K, y[zi], G[e], ax, dslab + threadIdx.x * P);
+        adj[zi] = ax;
+    }
+    __syncthreads();
+    const int total = rows * P;
+    for (int i = threadIdx.x; i < total; i += kSplineT) {
+        const int r = i / P, c = i - r * P;
+        dtheta[(e0 + r) * ldt + (int64_t)j * P + c] = to_t<T>(dslab[i]);
     }
 }
 
@@ -911,7 +989,7 @@ hipError_t launch_reduce_partials(const float* part, int splits, int M, int N, f
                                   hipStream_t s) {
     const int64_t MN = (int64_t)M * N;
     if (MN == 0) return hipSuccess;
-    k_reduce_partials<<<blocks(MN), 256, 0, s>>>(part, splits, M, N, out, ldo);
+    k_reduce_partials<<<(unsigned)((MN + 63) / 64), 256, 0, s>>>(part, splits, M, N, out, ldo);
     return hipGetLastError();
 }
 
@@ -940,15 +1018,18 @@ hipError_t launch_gather(int type, const float* z, int64_t n, int n_cond, const 
 }
 
 hipError_t launch_spline(bool inverse, float* z, int64_t n, const float* theta, int64_t ldt, int n_half,
-                         const int32_t* trans_host, int K, float* logdet, hipStream_t s) {
+                         const int32_t* trans_host, int K, float* logdet, float* ld_part, hipStream_t s) {
     if (n == 0) return hipSuccess;
     Idx t = make_idx(trans_host, n_half);
-    const unsigned nb = (unsigned)((n + kSplineT - 1) / kSplineT);
+    const dim3 grid((unsigned)((n + kSplineT - 1) / kSplineT), (unsigned)n_half);
     const size_t lds = sizeof(float) * kSplineT * (3 * K + 1);
     if (inverse)
-        k_spline<true><<<nb, kSplineT, lds, s>>>(z, n, theta, ldt, n_half, t, K, logdet);
+        k_spline<true><<<grid, kSplineT, lds, s>>>(z, n, theta, ldt, t, K, ld_part);
     else
-        k_spline<false><<<nb, kSplineT, lds, s>>>(z, n, theta, ldt, n_half, t, K, logdet);
+        k_spline<false><<<grid, kSplineT, lds, s>>>(z, n, theta, ldt, t, K, ld_part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_ld_add<<<blocks(n), 256, 0, s>>>(ld_part, n, n_half, logdet);
     return hipGetLastError();
 }
 
@@ -957,12 +1038,12 @@ hipError_t launch_spline_backward(int type, const float* y, float* adj, int64_t 
                                   hipStream_t s) {
     if (n == 0) return hipSuccess;
     Idx t = make_idx(trans_host, n_half);
-    const unsigned nb = (unsigned)((n + kSplineT - 1) / kSplineT);
-    const size_t lds = 2 * sizeof(float) * kSplineT * (3 * K + 1);
+    const dim3 nb((unsigned)((n + kSplineT - 1) / kSplineT), (unsigned)n_half);
+    const size_t lds = sizeof(float) * kSplineT * (3 * K + 1);
     if (type == FT_BF16)
-        k_spline_backward<__bf16><<<nb, kSplineT, lds, s>>>(y, adj, n, theta, ldt, n_half, t, K, G, (__bf16*)dtheta);
+        k_spline_backward<__bf16><<<nb, kSplineT, lds, s>>>(y, adj, n, theta, ldt, t, K, G, (__bf16*)dtheta);
     else
-        k_spline_backward<float><<<nb, kSplineT, lds, s>>>(y, adj, n, theta, ldt, n_half, t, K, G, (float*)dtheta);
+        k_spline_backward<float><<<nb, kSplineT, lds, s>>>(y, adj, n, theta, ldt, t, K, G, (float*)dtheta);
     return hipGetLastError();
 }
 

@@ -65,11 +65,13 @@ hipError_t launch_colsum(int type, const void* X, int64_t R, int N, int64_t ldx,
 hipError_t launch_gather(int type, const float* z, int64_t n, int n_cond, const int32_t* cond_host, void* x0,
                          hipStream_t s);
 
-// Spline of every transformed coordinate of one layer, one thread per event.
+// Spline of every transformed coordinate of one layer, one thread per
+// (event, coordinate).
 //   forward: z[t_j] <- S(z[t_j]), logdet += sum_j log S'
 //   inverse: z[t_j] <- S^-1(z[t_j]), logdet += sum_j log (S^-1)'
+// ld_part: scratch of n_half x n floats (the per-coordinate terms).
 hipError_t launch_spline(bool inverse, float* z, int64_t n, const float* theta, int64_t ldt, int n_half,
-                         const int32_t* trans_host, int K, float* logdet, hipStream_t s);
+                         const int32_t* trans_host, int K, float* logdet, float* ld_part, hipStream_t s);
 
 // Reverse mode through one inverse spline layer.  y: layer input (its
 // transformed coordinates, before inversion), adj: adjoint of the layer output

@@ -74,11 +74,14 @@ __device__ __forceinline__ void load_tile(const T* __restrict__ P, int64_t s_r, 
     constexpr int RUNS = ROWS * BK / 8 / GT;
     T v[8];
     if (s_r == 1 && s_k != 1) {
-        // runs of 8 consecutive rows at one k
+        // runs of 8 consecutive rows at one k, consecutive lanes at
+        // consecutive k: each of the 8 transposing LDS stores of a wave then
+        // covers all banks (lanes 8 rows apart would hit the same bank with
+        // a 16-byte-multiple row pitch)
 #pragma unroll
         for (int t = 0; t < RUNS; ++t) {
             const int q = tid + GT * t;
-            const int kk = q / (ROWS / 8), rb = (q % (ROWS / 8)) * 8;
+            const int kk = q % BK, rb = (q / BK) * 8;
             const int k = k0 + kk;
             const int valid = k < kend ? max(0, min(8, R - (r0 + rb))) : 0;
             load8<T>(P + (int64_t)(r0 + rb) + (int64_t)k * s_k, valid, v);

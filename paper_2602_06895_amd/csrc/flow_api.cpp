@@ -129,8 +129,13 @@ msx_status ensure_work(msx_flow* f, int64_t n) {
     return MSX_OK;
 }
 
-int splits_for(int64_t n) {
-    return (int)std::max<int64_t>(1, std::min<int64_t>(64, n / 1024));
+// Split-K chunks of a weight-gradient GEMM over n events with an M x N
+// output: about 1024 workgroups in all (64 x 128 output tiles), chunks of at
+// least 256 events.
+int splits_for(int64_t n, int M, int N) {
+    const int64_t tiles = (int64_t)((M + 63) / 64) * ((N + 127) / 128);
+    const int64_t want = std::max<int64_t>(1, 1024 / tiles);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, n / 256));
 }
 
 msx_status ensure_part(msx_flow* f, int64_t floats) {
@@ -198,7 +203,7 @@ msx_status run_mlp(msx_flow* f, int l, const float* z, int64_t n, void* x0, void
 // dW[M][N] = sum_b A(b, m) B(b, n) over the batch (split-K), into grad.
 msx_status weight_grad(msx_flow* f, int M, int N, int64_t n, const void* A, int64_t lda, const void* B, int64_t ldb,
                        float* out, hipStream_t s) {
-    const int splits = splits_for(n);
+    const int splits = splits_for(n, M, N);
     if (msx_status st = ensure_part(f, (int64_t)splits * M * N)) return st;
     GemmArgs g = gemm(f, M, N, (int)n, A, 1, lda, B, ldb, 1, EPI_PARTIAL, f->part, N);
     g.splits = splits;

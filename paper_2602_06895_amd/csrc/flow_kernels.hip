@@ -250,6 +250,41 @@ __global__ __launch_bounds__(256) void k_colsum(const T* __restrict__ X, int64_t
     part[(int64_t)blockIdx.y * N + c] = (s0 + s1) + (s2 + s3);
 }
 
+// Column sums for BF16 X with N and ldx multiples of 8: 16 threads cover 128
+// columns of one row with 16-byte loads, the workgroup's 16 row groups take
+// rows r0 + g, r0 + g + 16, ...; the 16 partial sums of a column are added
+// in a fixed order through LDS.  grid.x: column blocks of 128, grid.y: row
+// chunks.
+__global__ __launch_bounds__(256) void k_colsum8(const __bf16* __restrict__ X, int64_t R, int N, int64_t ldx,
+                                                 int64_t chunk, float* __restrict__ part) {
+    __shared__ float red[16][129];
+    const int g = threadIdx.x >> 4, cl = (threadIdx.x & 15) * 8;
+    const int c0 = blockIdx.x * 128 + cl;
+    const int64_t r0 = (int64_t)blockIdx.y * chunk, r1 = min(R, r0 + chunk);
+    float acc[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = 0.0f;
+    if (c0 < N) {
+        for (int64_t r = r0 + g; r < r1; r += 16) {
+            const uint4 q = *(const uint4*)(X + r * ldx + c0);
+            __bf16 v[8];
+            __builtin_memcpy(v, &q, sizeof v);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) acc[i] += (float)v[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) red[g][cl + i] = acc[i];
+    __syncthreads();
+    if (threadIdx.x < 128) {
+        const int c = blockIdx.x * 128 + threadIdx.x;
+        float sum = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) sum += red[k][threadIdx.x];
+        if (c < N) part[(int64_t)blockIdx.y * N + c] = sum;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Layer plumbing
 // ---------------------------------------------------------------------------
@@ -1000,7 +1035,10 @@ hipError_t launch_colsum(int type, const void* X, int64_t R, int N, int64_t ldx,
                          hipStream_t s) {
     const int64_t chunk = (R + nchunk - 1) / nchunk;
     dim3 grid((unsigned)((N + 255) / 256), (unsigned)nchunk);
-    if (type == FT_BF16)
+    if (type == FT_BF16 && N % 8 == 0 && ldx % 8 == 0 && ((uintptr_t)X & 15) == 0)
+        k_colsum8<<<dim3((unsigned)((N + 127) / 128), (unsigned)nchunk), 256, 0, s>>>((const __bf16*)X, R, N, ldx,
+                                                                                      chunk, part);
+    else if (type == FT_BF16)
         k_colsum<__bf16><<<grid, 256, 0, s>>>((const __bf16*)X, R, N, ldx, chunk, part);
     else
         k_colsum<float><<<grid, 256, 0, s>>>((const float*)X, R, N, ldx, chunk, part);

@@ -219,6 +219,12 @@ msx_status bias_grad(msx_flow* f, const void* X, int64_t n, int N, float* out, h
     return MSX_OK;
 }
 
+// The one-kernel coupling layer covers BF16 conditioners of hidden width 128
+// with up to 16 bins.
+bool fused_ok(const msx_flow* f) {
+    return f->type == FT_BF16 && f->H == kFusedHidden && f->K <= kFusedMaxBins;
+}
+
 // Inverse pass over all layers keeping every intermediate: z[L] = y, z[l] =
 // layer l inverted from z[l + 1]; logq accumulates log |du/dy|.
 msx_status inverse_saving(msx_flow* f, int64_t n, const float* y, hipStream_t s) {
@@ -232,6 +238,15 @@ msx_status inverse_saving(msx_flow* f, int64_t n, const float* y, hipStream_t s)
         void* x0 = tptr(f, f->x0, (int64_t)l * n * f->nh);
         void* h = tptr(f, f->h, (int64_t)l * 3 * n * f->H);
         float* th = f->theta + (size_t)l * n * f->n_out;
+        if (fused_ok(f)) {
+            FHIP(f, hipMemcpyAsync(zout, zin, sizeof(float) * zs, hipMemcpyDeviceToDevice, s), "flow copy");
+            FHIP(f,
+                 launch_flow_layer(true, zout, n, tptr(f, f->params_t, l * f->per_layer_t),
+                                   f->params + (int64_t)l * f->per_layer, f->off, f->nh, f->trans[l].data(),
+                                   f->cond[l].data(), f->K, f->logq, x0, h, th, s),
+                 "flow layer");
+            continue;
+        }
         if (msx_status st = run_mlp(f, l, zin, n, x0, h, th, s)) return st;
         FHIP(f, hipMemcpyAsync(zout, zin, sizeof(float) * zs, hipMemcpyDeviceToDevice, s), "flow copy");
         FHIP(f, launch_spline(true, zout, n, th, f->n_out, f->nh, f->trans[l].data(), f->K, f->logq, f->ldp, s),
@@ -425,7 +440,7 @@ msx_status msx_flow_forward(msx_flow* f, int64_t n, const float* u, float* y, fl
     FHIP(f, hipSetDevice(f->device), "hipSetDevice");
     // whole layers in one kernel where the shape allows it (BF16, hidden 128,
     // <= 16 bins, 16-byte aligned layer blocks); no work buffers then
-    const bool fused = f->type == FT_BF16 && f->H == kFusedHidden && f->K <= kFusedMaxBins;
+    const bool fused = fused_ok(f);
     if (!fused)
         if (msx_status st = ensure_work(f, n)) return st;
     if (y != u) FHIP(f, hipMemcpyAsync(y, u, sizeof(float) * (size_t)f->d * n, hipMemcpyDeviceToDevice, s), "flow copy");
@@ -434,8 +449,9 @@ msx_status msx_flow_forward(msx_flow* f, int64_t n, const float* u, float* y, fl
         if (fused) {
             const int64_t base = l * f->per_layer;
             FHIP(f,
-                 launch_flow_layer_fwd(y, n, tptr(f, f->params_t, l * f->per_layer_t), f->params + base, f->off, f->nh,
-                                       f->trans[l].data(), f->cond[l].data(), f->K, logdet, s),
+                 launch_flow_layer(false, y, n, tptr(f, f->params_t, l * f->per_layer_t), f->params + base, f->off,
+                                   f->nh, f->trans[l].data(), f->cond[l].data(), f->K, logdet, nullptr, nullptr,
+                                   nullptr, s),
                  "flow layer");
             continue;
         }
@@ -453,10 +469,20 @@ msx_status msx_flow_inverse(msx_flow* f, int64_t n, const float* y, float* u, fl
     if (!u || !y || !logq) return ffail(f, MSX_ERR_ARG, "y, u and logq are required");
     hipStream_t s = (hipStream_t)stream;
     FHIP(f, hipSetDevice(f->device), "hipSetDevice");
-    if (msx_status st = ensure_work(f, n)) return st;
+    const bool fused = fused_ok(f);
+    if (!fused)
+        if (msx_status st = ensure_work(f, n)) return st;
     if (y != u) FHIP(f, hipMemcpyAsync(u, y, sizeof(float) * (size_t)f->d * n, hipMemcpyDeviceToDevice, s), "flow copy");
     FHIP(f, hipMemsetAsync(logq, 0, sizeof(float) * n, s), "flow clear");
     for (int l = f->L - 1; l >= 0; --l) {
+        if (fused) {
+            FHIP(f,
+                 launch_flow_layer(true, u, n, tptr(f, f->params_t, l * f->per_layer_t),
+                                   f->params + (int64_t)l * f->per_layer, f->off, f->nh, f->trans[l].data(),
+                                   f->cond[l].data(), f->K, logq, nullptr, nullptr, nullptr, s),
+                 "flow layer");
+            continue;
+        }
         if (msx_status st = run_mlp(f, l, u, n, f->x0, f->h, f->theta, s)) return st;
         FHIP(f, launch_spline(true, u, n, f->theta, f->n_out, f->nh, f->trans[l].data(), f->K, logq, f->ldp, s),
              "flow spline");

@@ -872,8 +872,31 @@ __device__ __forceinline__ void hidden_layer(const __bf16* __restrict__ Wl, cons
     __syncthreads();
 }
 
-__global__ __launch_bounds__(64 * kFW) void k_flow_layer_fwd(float* __restrict__ z, int64_t n, FusedW fw, int nh,
-                                                             Idx trans, Idx cond, int K, float* __restrict__ logdet) {
+// What the reverse pass of training reads, written by the fused inverse
+// layer when the pointers are set: the BF16 conditioning inputs x0 [n][nh],
+// the hidden activations h [3][n][128] and the spline parameters theta
+// [n][n_out] (FP32), the same values the unfused path stores.
+struct FusedSave {
+    __bf16* x0;
+    __bf16* h;
+    float* theta;
+};
+
+// Copy a wave's 64 x 128 activation tile to h[e0 ..][128] (16-byte stores).
+__device__ __forceinline__ void save_tile(const __bf16* __restrict__ st, __bf16* __restrict__ h, int64_t e0,
+                                          int64_t n, int lane) {
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int idx = it * 64 + lane;        // 16-byte chunk: row idx / 16, column block idx % 16
+        const int r = idx >> 4, cb = (idx & 15) * 8;
+        if (e0 + r < n) *(uint4*)&h[(e0 + r) * kFH + cb] = *(const uint4*)&st[r * kFRow + cb];
+    }
+}
+
+template <bool INV>
+__global__ __launch_bounds__(64 * kFW) void k_flow_layer(float* __restrict__ z, int64_t n, FusedW fw, int nh,
+                                                         Idx trans, Idx cond, int K, float* __restrict__ logdet,
+                                                         FusedSave sv) {
     extern __shared__ __attribute__((aligned(16))) unsigned char fsm[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r16 = lane & 15, kq = lane >> 4;
@@ -893,6 +916,7 @@ __global__ __launch_bounds__(64 * kFW) void k_flow_layer_fwd(float* __restrict__
         for (int t = 0; t < 4; ++t) {
             const int64_t e = e0 + 16 * t + r16;
             a1[t][i] = (__bf16)((k < nh && e < n) ? z[(int64_t)ci * n + e] : 0.0f);
+            if (sv.x0 && k < nh && e < n) sv.x0[e * nh + k] = a1[t][i];
         }
     }
 #pragma unroll 2
@@ -910,8 +934,11 @@ __global__ __launch_bounds__(64 * kFW) void k_flow_layer_fwd(float* __restrict__
         hidden_epilogue(acc, fw.b1, c, lane, st);
     }
     __syncthreads();
+    if (sv.h) save_tile(st, sv.h, e0, n, lane);
     hidden_layer(fw.w2, fw.b2, lane, st);
+    if (sv.h) save_tile(st, sv.h + n * kFH, e0, n, lane);
     hidden_layer(fw.w3, fw.b3, lane, st);
+    if (sv.h) save_tile(st, sv.h + 2 * n * kFH, e0, n, lane);
 
     // last layer, one transformed coordinate at a time, then its spline
     bf16x8 a3[4][4];
@@ -947,7 +974,11 @@ __global__ __launch_bounds__(64 * kFW) void k_flow_layer_fwd(float* __restrict__
                 for (int s4 = 0; s4 < 4; ++s4) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3[t][s4], b[s4], acc, 0, 0, 0);
                 if (ok) {
 #pragma unroll
-                    for (int x = 0; x < 4; ++x) th[(16 * t + 4 * kq + x) * P + q] = acc[x] + bias;
+                    for (int x = 0; x < 4; ++x) {
+                        const int r = 16 * t + 4 * kq + x;
+                        th[r * P + q] = acc[x] + bias;
+                        if (sv.theta && e0 + r < n) sv.theta[(e0 + r) * n_out + row] = acc[x] + bias;
+                    }
                 }
             }
         }
@@ -957,17 +988,29 @@ __global__ __launch_bounds__(64 * kFW) void k_flow_layer_fwd(float* __restrict__
             const float v = *zp;
             Bin bn;
             if (K == 16) {
-                bn = spline_bin_k<false, 16>(th + lane * P, v);
+                bn = spline_bin_k<INV, 16>(th + lane * P, v);
             } else {
                 float mw, sw, mh, sh;
-                bn = spline_bin<false>(th + lane * P, K, v, mw, sw, mh, sh);
+                bn = spline_bin<INV>(th + lane * P, K, v, mw, sw, mh, sh);
             }
             const float sl = bn.h / bn.w;
             const float kap = bn.d1 + bn.d0 - 2.0f * sl;
-            const float xi = (v - bn.x0) / bn.w;
-            const float om = xi * (1.0f - xi);
-            *zp = bn.y0 + bn.h * (sl * xi * xi + bn.d0 * om) / (sl + kap * om);
-            ld += logf(spline_slope(bn, xi));
+            if (!INV) {
+                const float xi = (v - bn.x0) / bn.w;
+                const float om = xi * (1.0f - xi);
+                *zp = bn.y0 + bn.h * (sl * xi * xi + bn.d0 * om) / (sl + kap * om);
+                ld += logf(spline_slope(bn, xi));
+            } else {
+                // the same root as the unfused inverse spline
+                const float dy = v - bn.y0;
+                const float qa = bn.h * (sl - bn.d0) + dy * kap;
+                const float qb = bn.h * bn.d0 - dy * kap;
+                const float qc = -sl * dy;
+                const float disc = fmaxf(qb * qb - 4.0f * qa * qc, 0.0f);
+                const float xi = 2.0f * qc / (-qb - sqrtf(disc));
+                *zp = bn.x0 + xi * bn.w;
+                ld += -logf(spline_slope(bn, xi));
+            }
         }
         __syncthreads();
     }
@@ -1002,9 +1045,9 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_flow_layer_fwd(float* z, int64_t n, const void* params_t, const float* params, const int64_t* off,
-                                 int nh, const int32_t* trans_host, const int32_t* cond_host, int K, float* logdet,
-                                 hipStream_t s) {
+hipError_t launch_flow_layer(bool inverse, float* z, int64_t n, const void* params_t, const float* params,
+                             const int64_t* off, int nh, const int32_t* trans_host, const int32_t* cond_host, int K,
+                             float* logdet, void* save_x0, void* save_h, float* save_theta, hipStream_t s) {
     if (n == 0) return hipSuccess;
     FusedW fw;
     const __bf16* W = (const __bf16*)params_t;
@@ -1018,8 +1061,13 @@ hipError_t launch_flow_layer_fwd(float* z, int64_t n, const void* params_t, cons
     fw.b4 = params + off[7];
     const unsigned nb = (unsigned)((n + 64 * kFW - 1) / (64 * kFW));
     const size_t lds = sizeof(__bf16) * kFStage * kFW;
-    k_flow_layer_fwd<<<nb, 64 * kFW, lds, s>>>(z, n, fw, nh, make_idx(trans_host, nh), make_idx(cond_host, nh), K,
-                                              logdet);
+    FusedSave sv{(__bf16*)save_x0, (__bf16*)save_h, save_theta};
+    if (inverse)
+        k_flow_layer<true><<<nb, 64 * kFW, lds, s>>>(z, n, fw, nh, make_idx(trans_host, nh), make_idx(cond_host, nh),
+                                                     K, logdet, sv);
+    else
+        k_flow_layer<false><<<nb, 64 * kFW, lds, s>>>(z, n, fw, nh, make_idx(trans_host, nh), make_idx(cond_host, nh),
+                                                      K, logdet, sv);
     return hipGetLastError();
 }
 

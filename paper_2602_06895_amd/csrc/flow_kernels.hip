@@ -893,7 +893,7 @@ __device__ __forceinline__ void save_tile(const __bf16* __restrict__ st, __bf16*
     }
 }
 
-template <bool INV>
+template <bool INV, bool SAVE>
 __global__ __launch_bounds__(64 * kFW) void k_flow_layer(float* __restrict__ z, int64_t n, FusedW fw, int nh,
                                                          Idx trans, Idx cond, int K, float* __restrict__ logdet,
                                                          FusedSave sv) {
@@ -916,7 +916,7 @@ __global__ __launch_bounds__(64 * kFW) void k_flow_layer(float* __restrict__ z, 
         for (int t = 0; t < 4; ++t) {
             const int64_t e = e0 + 16 * t + r16;
             a1[t][i] = (__bf16)((k < nh && e < n) ? z[(int64_t)ci * n + e] : 0.0f);
-            if (sv.x0 && k < nh && e < n) sv.x0[e * nh + k] = a1[t][i];
+            if (SAVE && k < nh && e < n) sv.x0[e * nh + k] = a1[t][i];
         }
     }
 #pragma unroll 2
@@ -934,11 +934,11 @@ __global__ __launch_bounds__(64 * kFW) void k_flow_layer(float* __restrict__ z, 
         hidden_epilogue(acc, fw.b1, c, lane, st);
     }
     __syncthreads();
-    if (sv.h) save_tile(st, sv.h, e0, n, lane);
+    if (SAVE) save_tile(st, sv.h, e0, n, lane);
     hidden_layer(fw.w2, fw.b2, lane, st);
-    if (sv.h) save_tile(st, sv.h + n * kFH, e0, n, lane);
+    if (SAVE) save_tile(st, sv.h + n * kFH, e0, n, lane);
     hidden_layer(fw.w3, fw.b3, lane, st);
-    if (sv.h) save_tile(st, sv.h + 2 * n * kFH, e0, n, lane);
+    if (SAVE) save_tile(st, sv.h + 2 * n * kFH, e0, n, lane);
 
     // last layer, one transformed coordinate at a time, then its spline
     bf16x8 a3[4][4];
@@ -977,7 +977,7 @@ __global__ __launch_bounds__(64 * kFW) void k_flow_layer(float* __restrict__ z, 
                     for (int x = 0; x < 4; ++x) {
                         const int r = 16 * t + 4 * kq + x;
                         th[r * P + q] = acc[x] + bias;
-                        if (sv.theta && e0 + r < n) sv.theta[(e0 + r) * n_out + row] = acc[x] + bias;
+                        if (SAVE && e0 + r < n) sv.theta[(e0 + r) * n_out + row] = acc[x] + bias;
                     }
                 }
             }
@@ -1062,12 +1062,16 @@ hipError_t launch_flow_layer(bool inverse, float* z, int64_t n, const void* para
     const unsigned nb = (unsigned)((n + 64 * kFW - 1) / (64 * kFW));
     const size_t lds = sizeof(__bf16) * kFStage * kFW;
     FusedSave sv{(__bf16*)save_x0, (__bf16*)save_h, save_theta};
-    if (inverse)
-        k_flow_layer<true><<<nb, 64 * kFW, lds, s>>>(z, n, fw, nh, make_idx(trans_host, nh), make_idx(cond_host, nh),
-                                                     K, logdet, sv);
+    const bool save = save_x0 && save_h && save_theta;
+    const Idx ti = make_idx(trans_host, nh), ci = make_idx(cond_host, nh);
+    if (inverse && save)
+        k_flow_layer<true, true><<<nb, 64 * kFW, lds, s>>>(z, n, fw, nh, ti, ci, K, logdet, sv);
+    else if (inverse)
+        k_flow_layer<true, false><<<nb, 64 * kFW, lds, s>>>(z, n, fw, nh, ti, ci, K, logdet, sv);
+    else if (save)
+        k_flow_layer<false, true><<<nb, 64 * kFW, lds, s>>>(z, n, fw, nh, ti, ci, K, logdet, sv);
     else
-        k_flow_layer<false><<<nb, 64 * kFW, lds, s>>>(z, n, fw, nh, make_idx(trans_host, nh), make_idx(cond_host, nh),
-                                                      K, logdet, sv);
+        k_flow_layer<false, false><<<nb, 64 * kFW, lds, s>>>(z, n, fw, nh, ti, ci, K, logdet, sv);
     return hipGetLastError();
 }
 

@@ -47,8 +47,8 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t s);
 // params_t / params: the layer's block of the BF16 operand copy (16-byte
 // aligned) / of the FP32 parameters (biases), with the offsets off[0..7]
 // (W1 b1 W2 b2 W3 b3 W4 b4) in both.  save_x0 [n][nh] BF16, save_h [3][n][128]
-// BF16 and save_theta [n][nh (3K + 1)] FP32, when not NULL, receive the
-// conditioning inputs, hidden activations and spline parameters.
+// BF16 and save_theta [n][nh (3K + 1)] FP32, when all three are set, receive
+// the conditioning inputs, hidden activations and spline parameters.
 hipError_t launch_flow_layer(bool inverse, float* z, int64_t n, const void* params_t, const float* params,
                              const int64_t* off, int nh, const int32_t* trans_host, const int32_t* cond_host, int K,
                              float* logdet, void* save_x0, void* save_h, float* save_theta, hipStream_t s);

@@ -83,6 +83,13 @@ def lib(variant: str = "ref"):
         L.orc_vegas_map.argtypes = [C.c_double, dp, C.c_int32, dp]
         L.orc_boost.restype = None
         L.orc_boost.argtypes = [dp, C.c_double, dp, dp]
+        L.orc_inverse.restype = C.c_int
+        L.orc_unmap_nu.restype = C.c_double
+        L.orc_unmap_nu.argtypes = [C.c_double] * 5
+        L.orc_unmap_bw.restype = C.c_double
+        L.orc_unmap_bw.argtypes = [C.c_double] * 5
+        L.orc_vegas_unmap.restype = C.c_double
+        L.orc_vegas_unmap.argtypes = [C.c_double, dp, C.c_int32]
         _libs[variant] = L
     return _libs[variant]
 
@@ -324,6 +331,35 @@ class Process:
         if rc != 0:
             raise ValueError("oracle rejected the sizes")
         return out
+
+    def inverse(self, chan: int, p: np.ndarray, x1x2: np.ndarray | None, grid: np.ndarray | None = None,
+                nthreads: int = 0, variant: str = "ref") -> dict:
+        """Inverse of map(): the uniforms y [dims][N] that the channel maps to the
+        lab-frame momenta p [4][n+2][N] and x1x2 [2][N], through the inverse
+        VEGAS grid when given, and jac [N] = the forward Jacobian at y (the
+        channel density of the event is 1/jac)."""
+        d = self.dims[chan]
+        p = np.ascontiguousarray(p, dtype=np.float64)
+        n = p.shape[2]
+        if p.shape != (4, self.n + 2, n):
+            raise ValueError("p shape mismatch")
+        x = None if x1x2 is None else np.ascontiguousarray(x1x2, dtype=np.float64)
+        if self.hadronic and (x is None or x.shape != (2, n)):
+            raise ValueError("x1x2 [2][n] required")
+        g = None
+        if grid is not None:
+            g = np.ascontiguousarray(grid, dtype=np.float64)
+            if g.shape != (d, self.nbins + 1):
+                raise ValueError("grid shape mismatch")
+        y, jac = np.empty((d, n)), np.empty(n)
+        nt = nthreads if nthreads > 0 else (os.cpu_count() or 1)
+        dp = lambda a: a.ctypes.data_as(C.c_void_p) if a is not None else None
+        rc = lib(variant).orc_inverse(C.byref(self._proc), C.byref(self._chs[chan]), C.c_int32(chan),
+                                      C.c_int32(d), C.c_int64(n), dp(p), dp(x), dp(g), C.c_int32(self.nbins),
+                                      dp(y), dp(jac), C.c_int32(nt))
+        if rc != 0:
+            raise ValueError("oracle rejected the sizes")
+        return {"y": y, "jac": jac}
 
     def weight(self, chan: int, p: np.ndarray, x1x2: np.ndarray | None, jac: np.ndarray,
                nthreads: int = 0, variant: str = "ref") -> dict:

@@ -654,6 +654,304 @@ static void event(const orc_process* pr, const orc_channel* ch, int32_t chan,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Inverse mappings (section 2.1: every mapping is invertible, the density of */
+/* a channel at given momenta is 1 / its Jacobian at the recovered point)     */
+/* ------------------------------------------------------------------------ */
+
+/* Inverse of G_nu: the r with orc_map_nu(r, ...) = x. */
+double orc_unmap_nu(double x, double m2, double nu, double xmin, double xmax)
+{
+    if (nu == 0.0) return (x - xmin) / (xmax - xmin);
+    if (nu == 1.0) {
+        double lmax = log(xmax - m2), lmin = log(xmin - m2);
+        return (log(x - m2) - lmin) / (lmax - lmin);
+    }
+    double e = 1.0 - nu;
+    double A = pow(xmax - m2, e), B = pow(xmin - m2, e);
+    return (pow(x - m2, e) - B) / (A - B);
+}
+
+/* Inverse of G_BW. */
+double orc_unmap_bw(double x, double m, double w, double xmin, double xmax)
+{
+    double m2 = m * m, mw = m * w;
+    double u1 = atan((xmin - m2) / mw), u2 = atan((xmax - m2) / mw);
+    return (atan((x - m2) / mw) - u1) / (u2 - u1);
+}
+
+static double unmap_invariant(double x, double m, double w, double nu, double reg_a, double xmin, double xmax)
+{
+    if (w > 0.0) return orc_unmap_bw(x, m, w, xmin, xmax);
+    double m2 = (m == 0.0) ? -reg_a : m * m;
+    return orc_unmap_nu(x, m2, nu, xmin, xmax);
+}
+
+/* Inverse VEGAS map: the y whose image under orc_vegas_map is r (the bin
+ * with e_i <= r < e_{i+1}, linear inside it). */
+double orc_vegas_unmap(double r, const double* edges, int32_t nb)
+{
+    int32_t lo = 0, hi = nb - 1;
+    while (lo < hi) {
+        int32_t mid = (lo + hi + 1) / 2;
+        if (edges[mid] <= r) lo = mid;
+        else hi = mid - 1;
+    }
+    double wdt = edges[lo + 1] - edges[lo];
+    double t = wdt > 0.0 ? (r - edges[lo]) / wdt : 0.0;
+    return (lo + t) / nb;
+}
+
+/* Azimuth of (x, y) as a fraction of a turn in [0, 1). */
+static double turn_fraction(double x, double y)
+{
+    double f = atan2(y, x) / (2.0 * ORC_PI);
+    return f < 0.0 ? f + 1.0 : f;
+}
+
+static void node_momentum(const orc_channel* ch, int32_t j, double pf[][4], double mom[][4])
+{
+    if (ch->kind[j] == ORC_LEAF) {
+        memcpy(mom[j], pf[ch->particle[j]], sizeof mom[j]);
+        return;
+    }
+    for (int c = 0; c < 4; ++c) mom[j][c] = 0.0;
+    for (int32_t q = 0; q < ch->child_count[j]; ++q) {
+        int32_t kid = ch->children[ch->child_start[j] + q];
+        node_momentum(ch, kid, pf, mom);
+        for (int c = 0; c < 4; ++c) mom[j][c] += mom[kid][c];
+    }
+}
+
+/* The random numbers r (before VEGAS) that the channel's chain maps to the
+ * given lab-frame momenta pl [n_final + 2][4] and momentum fractions: every
+ * step of event() undone in its order.  Returns the number of dimensions. */
+static int32_t inverse_event(const orc_process* pr, const orc_channel* ch, double pl[][4], double x1, double x2,
+                             double* r)
+{
+    const int32_t n = pr->n_final;
+    /* (8) undo the beam boost: (E, p_z) -> (g E - gb p_z, -gb E + g p_z) */
+    double g = 1.0, gb = 0.0;
+    if (pr->hadronic) {
+        double sq = sqrt(x1 * x2);
+        g = (x1 + x2) / (2.0 * sq);
+        gb = (x1 - x2) / (2.0 * sq);
+    }
+    double pf[ORC_MAX_FINAL][4];
+    for (int32_t i = 0; i < n; ++i) {
+        const double* q = pl[i + 2];
+        pf[i][0] = g * q[0] - gb * q[3];
+        pf[i][1] = q[1];
+        pf[i][2] = q[2];
+        pf[i][3] = -gb * q[0] + g * q[3];
+    }
+    double mom[ORC_MAX_NODES][4];
+    const int32_t root = ch->root;
+    node_momentum(ch, root, pf, mom);
+
+    double s[ORC_MAX_NODES];
+    int32_t sampled[ORC_MAX_NODES];
+    for (int32_t j = 0; j < ch->n_nodes; ++j) {
+        s[j] = 0.0;
+        sampled[j] = 0;
+    }
+    int32_t k = 0;
+
+    /* (1) s-hat = x1 x2 s_lab */
+    double shat;
+    if (pr->hadronic) {
+        double m = 0.0, w = 0.0, nu = pr->nu;
+        if (ch->kind[root] == ORC_CLUSTER) {
+            m = ch->mass[root];
+            w = ch->width[root];
+            nu = ch->nu[root];
+        }
+        double lo = pr->shat_min;
+        double msum = 0.0;
+        for (int32_t i = 0; i < n; ++i) msum += pr->mass[i];
+        if (msum * msum > lo) lo = msum * msum;
+        shat = x1 * x2 * pr->s_lab;
+        r[k++] = unmap_invariant(shat, m, w, nu, pr->reg_a, lo, pr->s_lab);
+    } else {
+        shat = pr->s_lab;
+    }
+    s[root] = shat;
+    sampled[root] = 1;
+
+    /* (2) time-like invariants of the clusters from their momenta */
+    for (int32_t q = 0; q < ch->n_sorder; ++q) {
+        int32_t i = ch->s_order[q];
+        double mmin = 0.0;
+        for (int32_t c = 0; c < ch->child_count[i]; ++c)
+            mmin += node_m_min(ch, ch->children[ch->child_start[i] + c], sampled, s);
+        double mmax = node_m_max(ch, i, sampled, s);
+        s[i] = mdot(mom[i], mom[i]);
+        r[k++] = unmap_invariant(s[i], ch->mass[i], ch->width[i], ch->nu[i], pr->reg_a, mmin * mmin, mmax * mmax);
+        sampled[i] = 1;
+    }
+
+    /* (3) t-channel order and the invariants of the remaining clusters */
+    int32_t kappa = 0;
+    int32_t sigma[ORC_MAX_FINAL + 1];
+    int32_t from_a[ORC_MAX_FINAL + 1];
+    double st[ORC_MAX_FINAL + 1];
+    if (ch->kind[root] == ORC_TNODE) {
+        kappa = ch->child_count[root] - 1;
+        const int32_t* legs = ch->children + ch->child_start[root];
+        int32_t lo = 0, hi = kappa;
+        for (int32_t i = 1; i < kappa; ++i) {
+            if (ch->t_order[i - 1] == 'A') {
+                sigma[i] = legs[lo++];
+                from_a[i] = 1;
+            } else {
+                sigma[i] = legs[hi--];
+                from_a[i] = 0;
+            }
+        }
+        sigma[kappa] = legs[lo];
+        sigma[kappa + 1] = legs[hi];
+        st[0] = shat;
+        for (int32_t i = 1; i < kappa; ++i) {
+            double msum = 0.0;
+            for (int32_t j = i + 1; j <= kappa + 1; ++j) msum += node_m_min(ch, sigma[j], sampled, s);
+            double mi = node_m_min(ch, sigma[i], sampled, s);
+            double dm = sqrt(st[i - 1]) - mi;
+            double Q[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int32_t j = i + 1; j <= kappa + 1; ++j)
+                for (int c = 0; c < 4; ++c) Q[c] += mom[sigma[j]][c];
+            st[i] = mdot(Q, Q);
+            r[k++] = unmap_invariant(st[i], 0.0, 0.0, pr->nu, pr->reg_a, msum * msum, dm * dm);
+        }
+    }
+
+    /* (4) x1 = tau^r */
+    if (pr->hadronic) r[k++] = log(x1) / log(shat / pr->s_lab);
+
+    double rs = sqrt(shat);
+    double pa[4] = {0.5 * rs, 0.0, 0.0, 0.5 * rs};
+    double pb[4] = {0.5 * rs, 0.0, 0.0, -0.5 * rs};
+
+    /* (6) 2->2 blocks: |t| = -(p_A - p_1)^2, and the azimuth of p_1 about the
+     *     direction of p_A in the rest frame of P = p_A + p_B */
+    if (ch->kind[root] == ORC_TNODE) {
+        double pA[4], pB[4];
+        memcpy(pA, pa, sizeof pA);
+        memcpy(pB, pb, sizeof pB);
+        double ma2 = 0.0, mb2 = 0.0;
+        for (int32_t i = 1; i <= kappa; ++i) {
+            double m1, m2;
+            if (i == kappa) {
+                m1 = node_m_min(ch, sigma[kappa], sampled, s);
+                m2 = node_m_min(ch, sigma[kappa + 1], sampled, s);
+            } else if (from_a[i]) {
+                m1 = node_m_min(ch, sigma[i], sampled, s);
+                m2 = sqrt(st[i]);
+            } else {
+                m1 = sqrt(st[i]);
+                m2 = node_m_min(ch, sigma[i], sampled, s);
+            }
+            double P[4] = {pA[0] + pB[0], pA[1] + pB[1], pA[2] + pB[2], pA[3] + pB[3]};
+            double p1[4], p2[4];
+            if (i == kappa || from_a[i]) {
+                memcpy(p1, mom[sigma[i]], sizeof p1);
+                for (int c = 0; c < 4; ++c) p2[c] = P[c] - p1[c];
+            } else {
+                memcpy(p2, mom[sigma[i]], sizeof p2);
+                for (int c = 0; c < 4; ++c) p1[c] = P[c] - p2[c];
+            }
+            double d[4] = {pA[0] - p1[0], pA[1] - p1[1], pA[2] - p1[2], pA[3] - p1[3]};
+            double abst = -mdot(d, d);
+            double tmin, tmax;
+            orc_t_range(st[i - 1], ma2, mb2, m1, m2, &tmin, &tmax);
+            double m0 = sqrt(st[i - 1]);
+            double Pbar[4] = {P[0], -P[1], -P[2], -P[3]};
+            double pAr[4], k1[4];
+            orc_boost(Pbar, m0, pA, pAr);
+            orc_boost(Pbar, m0, p1, k1);
+            double len = sqrt(pAr[1] * pAr[1] + pAr[2] * pAr[2] + pAr[3] * pAr[3]);
+            double nx = pAr[1] / len, ny = pAr[2] / len, nz = pAr[3] / len;
+            double sn = sqrt(nx * nx + ny * ny);
+            double cp = 1.0, sp = 0.0;
+            if (sn > 0.0) {
+                cp = nx / sn;
+                sp = ny / sn;
+            }
+            /* R(phi_A, theta_A)^-1 = R_y(-theta_A) R_z(-phi_A) */
+            double x = k1[1] * cp + k1[2] * sp, y = -k1[1] * sp + k1[2] * cp, z = k1[3];
+            double vx = x * nz - z * sn;
+            double vy = y;
+            r[k++] = turn_fraction(vx, vy);
+            r[k++] = orc_unmap_nu(abst, -pr->reg_a, pr->nu, tmin, tmax);
+            if (i < kappa) {
+                if (from_a[i]) {
+                    for (int c = 0; c < 4; ++c) pA[c] -= p1[c];
+                    ma2 = -abst;
+                } else {
+                    for (int c = 0; c < 4; ++c) pB[c] -= p2[c];
+                    mb2 = -abst;
+                }
+            }
+        }
+    } else {
+        mom[root][0] = rs;
+        mom[root][1] = mom[root][2] = mom[root][3] = 0.0;
+    }
+
+    /* (7) decays: angles of the first child in the rest frame of its parent */
+    for (int32_t q = 0; q < ch->n_dec; ++q) {
+        int32_t c = ch->dec_order[q];
+        int32_t c0 = ch->children[ch->child_start[c]];
+        double m0 = sqrt(s[c]);
+        double Pbar[4] = {mom[c][0], -mom[c][1], -mom[c][2], -mom[c][3]};
+        double kk[4];
+        orc_boost(Pbar, m0, mom[c0], kk);
+        double len = sqrt(kk[1] * kk[1] + kk[2] * kk[2] + kk[3] * kk[3]);
+        r[k++] = turn_fraction(kk[1], kk[2]);
+        r[k++] = 0.5 * (kk[3] / len + 1.0);
+    }
+    return k;
+}
+
+/* Inverse map of n events of one channel: lab-frame momenta p
+ * [4][n_final+2][n] and x1x2 [2][n] (hadronic; NULL otherwise) -> the
+ * uniforms y [dims][n] (through the inverse VEGAS grid when grid is given),
+ * and jac [n] = the forward Jacobian at y (the channel density is 1/jac).
+ * Returns 0, or -1 on invalid sizes. */
+int orc_inverse(const orc_process* pr, const orc_channel* ch, int32_t chan, int32_t dims, int64_t n,
+                const double* p, const double* x1x2, const double* grid, int32_t nb, double* y, double* jac,
+                int32_t nthreads)
+{
+    if (dims > ORC_MAX_DIMS || pr->n_final > ORC_MAX_FINAL || ch->n_nodes > ORC_MAX_NODES) return -1;
+    const int32_t np = pr->n_final + 2;
+    int bad = 0;
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1) reduction(| : bad)
+    for (int64_t e = 0; e < n; ++e) {
+        double pl[ORC_MAX_FINAL + 2][4];
+        for (int32_t i = 0; i < np; ++i)
+            for (int c = 0; c < 4; ++c) pl[i][c] = p[((size_t)c * np + i) * n + e];
+        double x1 = 1.0, x2 = 1.0;
+        if (pr->hadronic) {
+            x1 = x1x2[e];
+            x2 = x1x2[n + e];
+        }
+        double r[ORC_MAX_DIMS], ye[ORC_MAX_DIMS];
+        int32_t k = inverse_event(pr, ch, pl, x1, x2, r);
+        if (k != dims) {
+            bad = 1;
+            continue;
+        }
+        for (int32_t q = 0; q < dims; ++q)
+            ye[q] = grid ? orc_vegas_unmap(r[q], grid + (size_t)q * (nb + 1), nb) : r[q];
+        for (int32_t q = 0; q < dims; ++q) y[(size_t)q * n + e] = ye[q];
+        if (jac) {
+            orc_event ev;
+            event(pr, ch, chan, ye, dims, grid, nb, &ev);
+            jac[e] = ev.jac;
+        }
+    }
+    return bad ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Batched entry point                                                       */
 /* ------------------------------------------------------------------------ */
 

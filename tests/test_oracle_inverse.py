@@ -1,0 +1,134 @@
+"""Pins of the oracle's inverse mappings (momenta -> uniforms and the channel
+density, section 2.1: every mapping of the chain is invertible).
+
+Each inverse is checked against something other than itself: the forward
+maps on exact intermediate values (the inverse of each map composed with the
+map is the identity), the closed form of the two-body angles, and the round
+trip through the independently pinned forward chain.  Round-trip errors are
+about one unit roundoff for most points; the tail comes from recovering small
+invariants from momenta (the same size in an x87 build with extended
+intermediates, so it is conditioning, not the algorithm)."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+
+def _lib():
+    return oracle.lib()
+
+
+@pytest.mark.parametrize("nu,m2,xmin,xmax", [(0.8, -1e-3, 400.0, 1.69e8), (0.8, 0.0, 1.0, 1e4),
+                                             (1.0, -1e-3, 10.0, 1e6), (0.0, 0.0, 3.0, 7.0),
+                                             (0.5, 80.0 ** 2, 90.0 ** 2, 1e5)])
+def test_unmap_nu_inverts_the_power_law(nu, m2, xmin, xmax):
+    L = _lib()
+    for r in np.linspace(0.0, 1.0, 41):
+        j = C.c_double()
+        x = L.orc_map_nu(r, m2, nu, xmin, xmax, C.byref(j))
+        r2 = L.orc_unmap_nu(x, m2, nu, xmin, xmax)
+        # x carries one rounding; r = ((x - m2)^e - B) / (A - B) moves by ~u
+        assert abs(r2 - r) < 1e-12, (r, r2)
+
+
+@pytest.mark.parametrize("m,w,xmin,xmax", [(173.0, 1.5, 100.0 ** 2, 300.0 ** 2), (80.4, 2.1, 0.0, 1e4)])
+def test_unmap_bw_inverts_the_breit_wigner(m, w, xmin, xmax):
+    L = _lib()
+    for r in np.linspace(0.0, 1.0, 41):
+        j = C.c_double()
+        x = L.orc_map_bw(r, m, w, xmin, xmax, C.byref(j))
+        assert abs(L.orc_unmap_bw(x, m, w, xmin, xmax) - r) < 1e-12
+
+
+def test_vegas_unmap_inverts_the_grid():
+    L = _lib()
+    rng = np.random.default_rng(3)
+    nb = 64
+    e = np.concatenate([[0.0], np.sort(rng.random(nb - 1)), [1.0]])
+    ep = e.ctypes.data_as(C.POINTER(C.c_double))
+    for y in rng.random(500):
+        j = C.c_double()
+        r = L.orc_vegas_map(y, ep, nb, C.byref(j))
+        y2 = L.orc_vegas_unmap(r, ep, nb)
+        # the bin width sets the conditioning: dy = dr / (nb width)
+        i = min(int(y * nb), nb - 1)
+        assert abs(y2 - y) <= 1e-14 / (nb * (e[i + 1] - e[i])) + 1e-15
+    # the edges map to the bin starts exactly
+    for i in range(nb):
+        assert L.orc_vegas_unmap(e[i], ep, nb) == pytest.approx(i / nb, abs=1e-15)
+
+
+def test_two_body_angles_closed_form():
+    """e+e- -> mu+mu- at fixed sqrt(s): the two recovered numbers are the
+    azimuth (as a fraction of a turn) and (1 + cos theta) / 2 of the first
+    outgoing particle, read directly off its momentum."""
+    pr = oracle.Process(W.c1_ee_mumu())
+    y = W.philox_uniforms(5, 1, 0, 2000, 2)
+    out = pr.map(0, y)
+    inv = pr.inverse(0, out["p"], None)
+    p1 = out["p"][:, 2, :]
+    phi = np.arctan2(p1[2], p1[1]) / (2 * np.pi)
+    phi = np.where(phi < 0, phi + 1.0, phi)
+    cth = p1[3] / np.sqrt(p1[1] ** 2 + p1[2] ** 2 + p1[3] ** 2)
+    assert np.abs(inv["y"][0] - phi).max() < 1e-14
+    assert np.abs(inv["y"][1] - 0.5 * (1 + cth)).max() < 1e-14
+    assert np.abs(inv["y"] - y).max() < 1e-13
+    # constant density 1 / (volume) of the two-body phase space
+    assert np.allclose(inv["jac"], out["jac"], rtol=1e-15, atol=0)
+
+
+CASES = [("c1", W.c1_ee_mumu, 0)] + [("c2", W.c2_pp4j, c) for c in range(8)] + \
+        [("c3", W.c3_ttbar6, 0), ("v8", lambda: W.volume_process(8), 0)]
+
+
+@pytest.mark.parametrize("name,mk,chan", CASES)
+def test_round_trip_through_the_forward_chain(name, mk, chan):
+    pr = oracle.Process(mk())
+    d = pr.dims[chan]
+    y = W.philox_uniforms(11, 2, 0, 20000, d)
+    out = pr.map(chan, y)
+    ok = out["jac"] > 0
+    inv = pr.inverse(chan, out["p"], out["x1x2"] if pr.hadronic else None)
+    err = np.abs(inv["y"] - y)[:, ok].max(axis=0)
+    jr = np.abs(inv["jac"][ok] / out["jac"][ok] - 1.0)
+    # measured over these channels: median <= 5e-13, p99 <= 1.2e-7, max <= 1.5e-4;
+    # the Jacobian (products of power-law factors near their poles) median
+    # <= 6e-12, p99 <= 1.1e-6
+    assert np.median(err) < 1e-11
+    assert np.quantile(err, 0.99) < 1e-6
+    assert err.max() < 5e-3
+    assert np.median(jr) < 1e-10
+    assert np.quantile(jr, 0.99) < 1e-5
+
+
+def test_round_trip_through_a_vegas_grid():
+    """With an adapted (random) grid the forward VEGAS step is undone too;
+    medians stay at the unit roundoff."""
+    pr = oracle.Process(W.c2_pp4j())
+    rng = np.random.default_rng(8)
+    for chan in (0, 6):
+        d = pr.dims[chan]
+        grid = np.empty((d, pr.nbins + 1))
+        for k in range(d):
+            grid[k] = np.concatenate([[0.0], np.sort(rng.random(pr.nbins - 1)), [1.0]])
+        y = W.philox_uniforms(12, 2, 0, 20000, d)
+        out = pr.map(chan, y, grid)
+        inv = pr.inverse(chan, out["p"], out["x1x2"], grid)
+        err = np.abs(inv["y"] - y).max(axis=0)
+        assert np.median(err) < 1e-11
+        assert np.quantile(err, 0.99) < 1e-6
+
+
+def test_planted_sign_error_in_the_inverse_rotation_is_caught():
+    """Rebuilding the round trip with the azimuth mirrored (what a wrong sign
+    in the inverse rotation produces) fails the closed-form test: the pins
+    above see such mistakes."""
+    pr = oracle.Process(W.c1_ee_mumu())
+    y = W.philox_uniforms(5, 1, 0, 200, 2)
+    out = pr.map(0, y)
+    inv = pr.inverse(0, out["p"], None)
+    mirrored = (1.0 - inv["y"][0]) % 1.0
+    assert np.abs(mirrored - y[0]).max() > 0.1

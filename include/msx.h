@@ -149,6 +149,22 @@ msx_status msx_uniform(msx_ctx* ctx, uint64_t seed, uint64_t stream_id, uint64_t
 msx_status msx_map(msx_ctx* ctx, int32_t channel, int64_t n, const double* y, double* p,
                    double* x1x2, double* jac, double* w, void* stream);
 
+/* Inverse map of one channel (section 2.1: every mapping of the chain is
+ * invertible): from lab-frame momenta p [4][np][n] (incoming partons first,
+ * as msx_map writes them) and x1x2 [2][n] (required for hadronic beams, NULL
+ * otherwise), the uniforms y [d][n] (required) that the channel's mapping
+ * chain and current VEGAS grid send to them, and jac [n] (optional) = the
+ * forward Jacobian at y, so that the channel's density at the event is
+ * 1/jac (0 for an event the forward chain would cut).  Steps: the beam boost
+ * undone; s-hat = x1 x2 s_lab and x1 = tau^r; each invariant from the
+ * momenta of its cluster; per 2->2 block |t| = -(p_A - p_1)^2 and the
+ * azimuth of p_1 about p_A in the rest frame of p_A + p_B; per decay the
+ * angles of the first child in its parent's rest frame; then each map and
+ * the VEGAS grid inverted.  FP64 in both precision modes.  Events that are
+ * not in the channel's image give meaningless y.  n = 0 is a no-op. */
+msx_status msx_inverse_map(msx_ctx* ctx, int32_t channel, int64_t n, const double* p, const double* x1x2, double* y,
+                           double* jac, void* stream);
+
 /* Event weight w = alpha_c(x) f(x) jac from momenta p [4][np][n] (lab frame,
  * as written by msx_map), x1x2 (hadronic) and jac; alpha [n] optional. */
 msx_status msx_weight(msx_ctx* ctx, int32_t channel, int64_t n, const double* p,

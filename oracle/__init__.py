@@ -361,6 +361,16 @@ class Process:
             raise ValueError("oracle rejected the sizes")
         return {"y": y, "jac": jac}
 
+    def inverse_forward_error(self, chan: int, p, x1x2, grid=None, ref: dict | None = None) -> dict:
+        """Forward-error estimate of inverse(): the largest deviation from the
+        reference among the x87 build and the builds with every libm / sqrt
+        result and every input momentum moved by one ulp."""
+        ref = ref if ref is not None else self.inverse(chan, p, x1x2, grid)
+        alts = [self.inverse(chan, p, x1x2, grid, variant=v) for v in ("x87", "up", "down")]
+        den = np.where(ref["jac"] != 0.0, np.abs(ref["jac"]), 1.0)
+        return {"y": np.max([np.abs(o["y"] - ref["y"]).max(axis=0) for o in alts], axis=0),
+                "jac": np.max([np.abs(o["jac"] - ref["jac"]) / den for o in alts], axis=0)}
+
     def weight(self, chan: int, p: np.ndarray, x1x2: np.ndarray | None, jac: np.ndarray,
                nthreads: int = 0, variant: str = "ref") -> dict:
         """w = alpha_c f jac from lab-frame momenta p [4][n+2][N], x1x2 [2][N]

@@ -744,6 +744,13 @@ static int32_t inverse_event(const orc_process* pr, const orc_channel* ch, doubl
         pf[i][2] = q[2];
         pf[i][3] = -gb * q[0] + g * q[3];
     }
+#ifdef ORC_LIBM_NUDGE
+    /* perturbation builds: the input momenta moved by one ulp as well */
+    for (int32_t i = 0; i < n; ++i)
+        for (int c = 0; c < 4; ++c)
+            if (pf[i][c] != 0.0)
+                pf[i][c] = nextafter(pf[i][c], ((i + c + (ORC_LIBM_NUDGE > 0)) & 1) ? INFINITY : -INFINITY);
+#endif
     double mom[ORC_MAX_NODES][4];
     const int32_t root = ch->root;
     node_momentum(ch, root, pf, mom);

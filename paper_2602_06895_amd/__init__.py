@@ -28,7 +28,8 @@ EXPORTS = ["msx_last_error", "msx_create_channels", "msx_destroy", "msx_get_meta
            "msx_flow_last_error", "msx_flow_create", "msx_flow_destroy", "msx_flow_param_count",
            "msx_flow_set_params", "msx_flow_get_params", "msx_flow_forward", "msx_flow_inverse",
            "msx_flow_gradient", "msx_flow_train_step", "msx_flow_sample", "msx_sample_device",
-           "msx_sample_graph_create", "msx_graph_launch", "msx_graph_destroy", "msx_set_launch", "msx_autotune"]
+           "msx_sample_graph_create", "msx_graph_launch", "msx_graph_destroy", "msx_set_launch", "msx_autotune",
+           "msx_inverse_map"]
 FLOW_BF16, FLOW_FP32 = 0, 1
 
 
@@ -57,6 +58,7 @@ def load_library(path: str = LIB_PATH):
         "msx_get_meta": ([vp, i32, i32, C.POINTER(i64)], C.c_int),
         "msx_uniform": ([vp, u64, u64, u64, i64, i32, vp, vp], C.c_int),
         "msx_map": ([vp, i32, i64, vp, vp, vp, vp, vp, vp], C.c_int),
+        "msx_inverse_map": ([vp, i32, i64, vp, vp, vp, vp, vp], C.c_int),
         "msx_weight": ([vp, i32, i64, vp, vp, vp, vp, vp, vp], C.c_int),
         "msx_sample": ([vp, vp, u64, u64, u64, vp, vp, vp, vp, vp], C.c_int),
         "msx_stats": ([vp, vp, vp], C.c_int),
@@ -178,6 +180,21 @@ class Context:
         y = y.contiguous()
         self._check(self.L.msx_map(self.h, channel, n, _ptr(y), _ptr(out["p"]), _ptr(out["x1x2"]),
                                    _ptr(out["jac"]), _ptr(out["w"]), self._stream()))
+        return out
+
+    def inverse_map(self, channel: int, p, x1x2=None, jac: bool = True):
+        """Uniforms y [d][n] that the channel maps to the lab-frame momenta p
+        [4][np][n] (and x1x2 [2][n] for hadronic beams), with the forward
+        Jacobian at y (the channel density is 1/jac)."""
+        self._check_channel(channel)
+        n = p.shape[2]
+        if tuple(p.shape) != (4, self.n_momenta[channel], n) or p.dtype != self.torch.float64:
+            raise ValueError(f"p must be a float64 [4][{self.n_momenta[channel]}][n] tensor")
+        p = p.contiguous()
+        x1x2 = x1x2.contiguous() if x1x2 is not None else None
+        out = {"y": self._empty(self.dims[channel], n), "jac": self._empty(n) if jac else None}
+        self._check(self.L.msx_inverse_map(self.h, channel, n, _ptr(p), _ptr(x1x2), _ptr(out["y"]),
+                                           _ptr(out["jac"]), self._stream()))
         return out
 
     def weight(self, channel: int, p, x1x2, jac, alpha: bool = False):

@@ -304,6 +304,27 @@ msx_status msx_map(msx_ctx* ctx, int32_t channel, int64_t n, const double* y, do
     return MSX_OK;
 }
 
+msx_status msx_inverse_map(msx_ctx* ctx, int32_t channel, int64_t n, const double* p, const double* x1x2, double* y,
+                           double* jac, void* stream) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (msx_status st = check_channel(ctx, channel)) return st;
+    if (n < 0) return fail(ctx, MSX_ERR_ARG, "n < 0");
+    const ChannelMeta& m = ctx->comp.meta[channel];
+    if (n > 0 && (!p || !y)) return fail(ctx, MSX_ERR_ARG, "p and y are required");
+    if (m.hadronic && n > 0 && !x1x2) return fail(ctx, MSX_ERR_ARG, "x1x2 is required for hadronic beams");
+    if (!m.hadronic && x1x2) return fail(ctx, MSX_ERR_ARG, "x1x2 must be NULL for fixed beams");
+    if (n == 0) return MSX_OK;
+    if (msx_status st = set_device(ctx)) return st;
+    const ChannelTab& t = ctx->comp.chans[channel];
+    const ProcessTab& pt = ctx->comp.procs[m.process];
+    MSX_HIP(ctx,
+            launch_inverse(ctx->d_chans + channel, ctx->d_grids + ctx->grid_off[channel], m.nbins, m.dims, t.n_slots,
+                           t.n_inv, t.kinds, pt.s_lab, m.n_momenta, n, p, x1x2, y, jac, ctx->cu_count,
+                           (hipStream_t)stream),
+            "inverse launch");
+    return MSX_OK;
+}
+
 msx_status msx_weight(msx_ctx* ctx, int32_t channel, int64_t n, const double* p, const double* x1x2,
                       const double* jac, double* w, double* alpha, void* stream) {
     if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");

@@ -237,6 +237,73 @@ __device__ __forceinline__ double map_static(const InvSpec& iv, double r, double
     return iv.xmin + (iv.xmax - iv.xmin) * r;
 }
 
+// Inverses of the maps (FP64): the r that map_dyn / map_static send to x.
+template <int KINDS>
+__device__ __forceinline__ double unmap_dyn(const MapParams& p, double x, double xmin, double xmax) {
+    const int kind = p.kind;
+    if ((KINDS & (KIND_POW | KIND_POW_INT)) && kind == MAP_POW) {
+        const double A = pow_e<KINDS, false>(p, xmax - p.m2), B = pow_e<KINDS, false>(p, xmin - p.m2);
+        return (pow_e<KINDS, false>(p, x - p.m2) - B) / (A - B);
+    }
+    if ((KINDS & KIND_BW) && kind == MAP_BW) {
+        const double u1 = atan((xmin - p.m2) / p.mw), u2 = atan((xmax - p.m2) / p.mw);
+        return (atan((x - p.m2) / p.mw) - u1) / (u2 - u1);
+    }
+    if ((KINDS & KIND_LOG) && kind == MAP_LOG) {
+        const double lmax = log(xmax - p.m2), lmin = log(xmin - p.m2);
+        return (log(x - p.m2) - lmin) / (lmax - lmin);
+    }
+    return (x - xmin) / (xmax - xmin);
+}
+
+template <int KINDS>
+__device__ __forceinline__ double unmap_static(const InvSpec& iv, double x) {
+    const MapParams& p = iv.map;
+    const int kind = p.kind;
+    if ((KINDS & (KIND_POW | KIND_POW_INT)) && kind == MAP_POW)
+        return (pow_e<KINDS, false>(p, x - p.m2) - iv.B) / (iv.A - iv.B);
+    if ((KINDS & KIND_BW) && kind == MAP_BW) return (atan((x - p.m2) / p.mw) - iv.B) / (iv.A - iv.B);
+    if ((KINDS & KIND_LOG) && kind == MAP_LOG) return (log(x - p.m2) - iv.B) / (iv.A - iv.B);
+    return (x - iv.xmin) / (iv.xmax - iv.xmin);
+}
+
+// Azimuth of (x, y) as a fraction of a turn in [0, 1).
+__device__ __forceinline__ double turn_fraction(double x, double y) {
+    const double f = atan2(y, x) / (2.0 * kPiD);
+    return f < 0.0 ? f + 1.0 : f;
+}
+
+// Inverse VEGAS map: the bin with e_i <= r < e_{i+1} by bisection, linear
+// inside it.
+__device__ __forceinline__ double vegas_unmap(double r, const double* __restrict__ g, int nb) {
+    int lo = 0, hi = nb - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (g[mid] <= r) lo = mid;
+        else hi = mid - 1;
+    }
+    const double wd = g[lo + 1] - g[lo];
+    const double t = wd > 0.0 ? (r - g[lo]) / wd : 0.0;
+    return (lo + t) / nb;
+}
+
+// Sum of the final-state momenta in `set` (statically indexed arrays).
+template <int NF>
+__device__ __forceinline__ void sum_set(uint32_t set, const double (&FE)[NF], const double (&FX)[NF],
+                                        const double (&FY)[NF], const double (&FZ)[NF], double& qe, double& qx,
+                                        double& qy, double& qz) {
+    qe = qx = qy = qz = 0.0;
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+        if (set & (1u << k)) {
+            qe += FE[k];
+            qx += FX[k];
+            qy += FY[k];
+            qz += FZ[k];
+        }
+    }
+}
+
 // Pure boost of k from the rest frame of P (mass m) into the frame of P,
 // with inv_m = 1/m and inv_em = 1/(E_P + m) supplied (shared by the boosts of
 // one operation).

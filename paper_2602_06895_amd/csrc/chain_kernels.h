@@ -35,21 +35,23 @@ struct LdsQ {
     __device__ __forceinline__ double get(int u) const { return b[u * kBlock]; }
 };
 
-// Beam boost, unphysical cut, integrand x channel weight and the stores of one
-// event whose partonic-frame momenta sit in the slots.  The final-state
-// momenta are first gathered by label into statically indexed arrays (NF =
-// the most final-state particles an NS-slot channel has), so the stores and
-// the integrand index registers with constants.
-template <int NS, bool MIX>
-__device__ __forceinline__ double finish_event(const ChannelTab* __restrict__ ct, const ProcessTab* __restrict__ pt,
-                                               const ChainOut& o, double jv, double (&E)[NS], double (&X)[NS],
-                                               double (&Y)[NS], double (&Z)[NS], int np, int64_t n, int64_t e,
-                                               double* __restrict__ p, double* __restrict__ x1x2,
-                                               double* __restrict__ jac_out, bool want_w, LdsQ q) {
+// Beam boost, unphysical cut and (STORE) the stores of one event whose
+// partonic-frame momenta sit in the slots.  The final-state momenta are
+// gathered by label into statically indexed arrays (NF = the most
+// final-state particles an NS-slot channel has), so the stores and the
+// integrand index registers with constants; they stay there in the partonic
+// frame, with h = sqrt(s-hat)/2.  Returns the event's Jacobian, 0 when it is
+// cut.
+template <int NS, bool STORE = true>
+__device__ __forceinline__ double finish_store(const ChannelTab* __restrict__ ct, const ChainOut& o, double jv,
+                                               double (&E)[NS], double (&X)[NS], double (&Y)[NS], double (&Z)[NS],
+                                               int np, int64_t n, int64_t e, double* __restrict__ p,
+                                               double* __restrict__ x1x2, double* __restrict__ jac_out,
+                                               double (&FE)[NS / 2 + 1], double (&FX)[NS / 2 + 1],
+                                               double (&FY)[NS / 2 + 1], double (&FZ)[NS / 2 + 1], double& h) {
     constexpr int NF = NS / 2 + 1;
     const int nf = ct->n_final;
     const int hadronic = ct->hadronic;
-    double FE[NF], FX[NF], FY[NF], FZ[NF];
 #pragma unroll
     for (int k = 0; k < NF; ++k) {
         FE[k] = FX[k] = FY[k] = FZ[k] = 0.0;
@@ -67,7 +69,7 @@ __device__ __forceinline__ double finish_event(const ChannelTab* __restrict__ ct
         g = (o.x1 + o.x2) * inv;
         gb = (o.x1 - o.x2) * inv;
     }
-    const double h = 0.5 * sqrt(o.shat);
+    h = 0.5 * sqrt(o.shat);
     bool ok = true;
     auto store = [&](int i, double pe, double px, double py, double pz) {
         double le = pe, lz = pz;
@@ -76,10 +78,12 @@ __device__ __forceinline__ double finish_event(const ChannelTab* __restrict__ ct
             lz = gb * pe + g * pz;
         }
         ok = ok && isfinite(le) && isfinite(px) && isfinite(py) && isfinite(lz) && le >= 0.0;
-        p[((int64_t)0 * np + i) * n + e] = le;
-        p[((int64_t)1 * np + i) * n + e] = px;
-        p[((int64_t)2 * np + i) * n + e] = py;
-        p[((int64_t)3 * np + i) * n + e] = lz;
+        if (STORE) {
+            p[((int64_t)0 * np + i) * n + e] = le;
+            p[((int64_t)1 * np + i) * n + e] = px;
+            p[((int64_t)2 * np + i) * n + e] = py;
+            p[((int64_t)3 * np + i) * n + e] = lz;
+        }
     };
     // incoming partons, then final-state particles by label
     store(0, h, 0.0, 0.0, h);
@@ -91,15 +95,28 @@ __device__ __forceinline__ double finish_event(const ChannelTab* __restrict__ ct
     ok = ok && isfinite(jac) && jac > 0.0;
     if (hadronic) {
         ok = ok && o.x1 > 0.0 && o.x1 <= 1.0 && o.x2 > 0.0 && o.x2 <= 1.0;
-        if (x1x2) {
+        if (STORE && x1x2) {
             x1x2[e] = o.x1;
             x1x2[n + e] = o.x2;
         }
     }
     if (!ok) jac = 0.0;
-    if (jac_out) jac_out[e] = jac;
+    if (STORE && jac_out) jac_out[e] = jac;
+    return jac;
+}
+
+// Stores, then integrand x channel weight of an uncut event.
+template <int NS, bool MIX>
+__device__ __forceinline__ double finish_event(const ChannelTab* __restrict__ ct, const ProcessTab* __restrict__ pt,
+                                               const ChainOut& o, double jv, double (&E)[NS], double (&X)[NS],
+                                               double (&Y)[NS], double (&Z)[NS], int np, int64_t n, int64_t e,
+                                               double* __restrict__ p, double* __restrict__ x1x2,
+                                               double* __restrict__ jac_out, bool want_w, LdsQ q) {
+    constexpr int NF = NS / 2 + 1;
+    double FE[NF], FX[NF], FY[NF], FZ[NF], h;
+    const double jac = finish_store<NS>(ct, o, jv, E, X, Y, Z, np, n, e, p, x1x2, jac_out, FE, FX, FY, FZ, h);
     double w = 0.0;
-    if (want_w && ok) {
+    if (want_w && jac != 0.0) {
         double alpha;
         auto get = [&](int k, int c) -> double {
             return c == 0 ? FE[k] : (c == 1 ? FX[k] : (c == 2 ? FY[k] : FZ[k]));
@@ -134,6 +151,13 @@ __global__ __launch_bounds__(kBlock) void k_map(const ChannelTab* __restrict__ c
         double E[NS], X[NS], Y[NS], Z[NS], S[NI], SQ[NI];
         ChainOut o;
         run_chain<NS, NI, KINDS, MIX>(ct, s_lab, next, E, X, Y, Z, S, SQ, o);
+        if (!p) {
+            // Jacobian only (the density of the inverse map)
+            double FE[NS / 2 + 1], FX[NS / 2 + 1], FY[NS / 2 + 1], FZ[NS / 2 + 1], h;
+            jac[e] = finish_store<NS, false>(ct, o, jv, E, X, Y, Z, np, n, e, nullptr, nullptr, nullptr, FE, FX, FY,
+                                             FZ, h);
+            continue;
+        }
         double wv = finish_event<NS, MIX>(ct, pt, o, jv, E, X, Y, Z, np, n, e, p, x1x2, jac, w != nullptr, q);
         if (w) w[e] = wv;
     }
@@ -236,6 +260,175 @@ __global__ __launch_bounds__(kBlock) void k_sample(const ChannelTab* __restrict_
     }
 }
 
+// Inverse map of one channel (section 2.1): lab-frame momenta p and momentum
+// fractions -> the uniforms y that the chain maps to them (k_map without
+// momentum stores then gives the forward Jacobian at y).  Every step of
+// run_chain undone in its order: beam boost, s-hat and x1 from x1 x2, the
+// invariants from the momenta of their clusters, per 2->2 block |t| =
+// -(p_A - p_1)^2 and the azimuth of p_1 about p_A in the rest frame of
+// P = p_A + p_B, per decay the angles of the first child in its parent's
+// rest frame, then the inverse VEGAS map.  FP64.
+template <int NS, int NI, int KINDS>
+__global__ __launch_bounds__(kBlock) void k_inverse(const ChannelTab* __restrict__ ct, const double* __restrict__ grid,
+                                                    int nb, double s_lab, int np, int64_t n,
+                                                    const double* __restrict__ p, const double* __restrict__ x1x2,
+                                                    double* __restrict__ y) {
+    constexpr int NF = NS / 2 + 1;
+    constexpr int kRows = stage_rows<NS, NI>();
+    extern __shared__ double lds[];
+    double* lg = lds + kRows * kBlock;
+    double* const col = lds + threadIdx.x;
+    const int dims = ct->dims;
+    for (int i = threadIdx.x; i < dims * (nb + 1); i += blockDim.x) lg[i] = grid[i];
+    __syncthreads();
+    const int nf = ct->n_final;
+    const int hadronic = ct->hadronic;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        double x1 = 1.0, x2 = 1.0, g = 1.0, gb = 0.0;
+        if (hadronic) {
+            x1 = x1x2[e];
+            x2 = x1x2[n + e];
+            const double inv = 1.0 / (2.0 * sqrt(x1 * x2));
+            g = (x1 + x2) * inv;
+            gb = (x1 - x2) * inv;
+        }
+        double FE[NF], FX[NF], FY[NF], FZ[NF];
+#pragma unroll
+        for (int k = 0; k < NF; ++k) {
+            FE[k] = FX[k] = FY[k] = FZ[k] = 0.0;
+            if (k < nf) {
+                const double le = p[((int64_t)0 * np + k + 2) * n + e], lz = p[((int64_t)3 * np + k + 2) * n + e];
+                FE[k] = g * le - gb * lz;
+                FX[k] = p[((int64_t)1 * np + k + 2) * n + e];
+                FY[k] = p[((int64_t)2 * np + k + 2) * n + e];
+                FZ[k] = -gb * le + g * lz;
+            }
+        }
+        int kd = 0;
+        auto put = [&](double r) { col[(kd++) * kBlock] = r; };
+        double S[NI], SQ[NI];
+        // (1) s-hat = x1 x2 s_lab
+        double shat = s_lab;
+        if (hadronic) {
+            shat = x1 * x2 * s_lab;
+            put(unmap_static<KINDS>(ct->inv[0], shat));
+        }
+        S[0] = shat;
+        SQ[0] = sqrt(shat);
+        // (2) time-like invariants from the momenta of their clusters
+        const int n_inv = ct->n_inv;
+        for (int i = 1; i < n_inv; ++i) {
+            const InvSpec& iv = ct->inv[i];
+            const double mmin = iv.min_const + masked_sum(iv.min_mask, SQ);
+            const double mmax = SQ[iv.parent] - iv.max_const - masked_sum(iv.max_mask, SQ);
+            double qe, qx, qy, qz;
+            sum_set<NF>(iv.set, FE, FX, FY, FZ, qe, qx, qy, qz);
+            const double s = qe * qe - qx * qx - qy * qy - qz * qz;
+            put(unmap_dyn<KINDS>(iv.map, s, mmin * mmin, mmax * mmax));
+            S[i] = s;
+            SQ[i] = sqrt(s);
+        }
+        // (3) x1 = tau^r
+        if (hadronic) put(log(x1) / log(shat / s_lab));
+        // (4) 2->2 blocks
+        const double h = 0.5 * SQ[0];
+        double Ae = h, Ax = 0.0, Ay = 0.0, Az = h;
+        double Be = h, Bx = 0.0, By = 0.0, Bz = -h;
+        double ma2 = 0.0, mb2 = 0.0;
+        const int n_blocks = ct->n_blocks;
+#pragma unroll
+        for (int bi = 0; bi < NS / 2; ++bi) {
+            if (bi >= n_blocks) break;
+            const BlockSpec& bs = ct->blk[bi];
+            const double m1 = src_mass(bs.m1, SQ), m2 = src_mass(bs.m2, SQ);
+            // the leg is a sum of final-state momenta, the remaining cluster
+            // P - leg (P = p_A + p_B), as the chain built them
+            double p1e, p1x, p1y, p1z, p2e, p2x, p2y, p2z;
+            if (bs.side == 1) {
+                sum_set<NF>(bs.set2, FE, FX, FY, FZ, p2e, p2x, p2y, p2z);
+                p1e = (Ae + Be) - p2e;
+                p1x = (Ax + Bx) - p2x;
+                p1y = (Ay + By) - p2y;
+                p1z = (Az + Bz) - p2z;
+            } else {
+                sum_set<NF>(bs.set1, FE, FX, FY, FZ, p1e, p1x, p1y, p1z);
+                p2e = (Ae + Be) - p1e;
+                p2x = (Ax + Bx) - p1x;
+                p2y = (Ay + By) - p1y;
+                p2z = (Az + Bz) - p1z;
+            }
+            const double m0sq = S[bs.m0_inv], m0 = SQ[bs.m0_inv];
+            const double m1s = m1 * m1, m2s = m2 * m2;
+            const double C = (m0sq + (m1s - m2s)) * (m0sq + (ma2 - mb2));
+            const double R = sqrt(kallen(m0sq, m1s, m2s) * kallen(m0sq, ma2, mb2));
+            const double inv2 = 1.0 / (2.0 * m0sq);
+            const double t_minus = m1s + ma2 - (C + R) * inv2;
+            const double prod = (m1s - ma2) * (m2s - mb2) + (ma2 - mb2 - m1s + m2s) * (ma2 * m2s - m1s * mb2) / m0sq;
+            const double t_plus = (t_minus != 0.0) ? prod / t_minus : 0.0;
+            const double tmin = fmax(0.0, -t_plus), tmax = -t_minus;
+            const double de = Ae - p1e, dx = Ax - p1x, dy = Ay - p1y, dz = Az - p1z;
+            const double abst = -(de * de - dx * dx - dy * dy - dz * dz);
+            double vx = p1x, vy = p1y;
+            if (!bs.com) {
+                // into the rest frame of P, then R(phi_A, theta_A)^-1 = R_y(-theta_A) R_z(-phi_A)
+                const double Pe = Ae + Be, Px = Ax + Bx, Py = Ay + By, Pz = Az + Bz;
+                const double inv_m0 = 1.0 / m0, inv_em = 1.0 / (Pe + m0);
+                double ae = Ae, ax = Ax, ay = Ay, az = Az;
+                boost_by(Pe, -Px, -Py, -Pz, inv_m0, inv_em, ae, ax, ay, az);
+                double ke = p1e, kx = p1x, ky = p1y, kz = p1z;
+                boost_by(Pe, -Px, -Py, -Pz, inv_m0, inv_em, ke, kx, ky, kz);
+                const double inv_len = 1.0 / sqrt(ax * ax + ay * ay + az * az);
+                const double nx = ax * inv_len, ny = ay * inv_len, nz = az * inv_len;
+                const double st = sqrt(nx * nx + ny * ny);
+                double cp = 1.0, sp = 0.0;
+                if (st > 0.0) {
+                    const double ist = 1.0 / st;
+                    cp = nx * ist;
+                    sp = ny * ist;
+                }
+                const double xr = kx * cp + ky * sp, yr = -kx * sp + ky * cp;
+                vx = xr * nz - kz * st;
+                vy = yr;
+            }
+            put(turn_fraction(vx, vy));
+            put(unmap_dyn<KINDS>(bs.tmap, abst, tmin, tmax));
+            const int side = bs.side;
+            const double fa = side == 0 ? 1.0 : 0.0, fb = side == 1 ? 1.0 : 0.0;
+            Ae -= fa * p1e;
+            Ax -= fa * p1x;
+            Ay -= fa * p1y;
+            Az -= fa * p1z;
+            Be -= fb * p2e;
+            Bx -= fb * p2x;
+            By -= fb * p2y;
+            Bz -= fb * p2z;
+            ma2 = side == 0 ? -abst : ma2;
+            mb2 = side == 1 ? -abst : mb2;
+        }
+        // (5) decays: angles of the first child in the rest frame of its parent
+        const int n_dec = ct->n_decays;
+#pragma unroll
+        for (int di = 0; di < NS / 2; ++di) {
+            if (di >= n_dec) break;
+            const DecaySpec& ds = ct->dec[di];
+            double ke, kx, ky, kz;
+            sum_set<NF>(ds.set1, FE, FX, FY, FZ, ke, kx, ky, kz);
+            if (!ds.parent_rest) {
+                double Pe, Px, Py, Pz;
+                sum_set<NF>(ds.parent_set, FE, FX, FY, FZ, Pe, Px, Py, Pz);
+                const double m0 = SQ[ds.parent_inv];
+                boost_by(Pe, -Px, -Py, -Pz, 1.0 / m0, 1.0 / (Pe + m0), ke, kx, ky, kz);
+            }
+            const double len = sqrt(kx * kx + ky * ky + kz * kz);
+            put(turn_fraction(kx, ky));
+            put(0.5 * (kz / len + 1.0));
+        }
+        // (6) inverse VEGAS map
+        for (int k = 0; k < dims; ++k) y[(int64_t)k * n + e] = vegas_unmap(col[k * kBlock], lg + k * (nb + 1), nb);
+    }
+}
+
 // Launch of one register class: kind class `kc` picks the compiled map kinds
 // (0: integer-root power laws, 1: plus Breit-Wigner, 2: all).
 template <int NS, int NI, bool MIX>
@@ -249,6 +442,19 @@ hipError_t launch_chain_class(int kc, const ChainLaunch& a) {
             const void* fn = a.sample ? (const void*)k_sample<NS, NI, K, MIX> : (const void*)k_map<NS, NI, K, MIX>;
             hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return;
+        }
+        if (a.inverse) {
+            if constexpr (!MIX) {
+                const size_t li = a.lds + sizeof(double) * stage_rows<NS, NI>() * kBlock;
+                if (li > 65536) {
+                    hipError_t e = hipFuncSetAttribute((const void*)k_inverse<NS, NI, K>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)li);
+                    if (e != hipSuccess) return;
+                }
+                k_inverse<NS, NI, K><<<a.grid, kBlock, li, a.stream>>>(a.cts, a.grids, a.nb, a.s_lab, a.np, a.n,
+                                                                      a.p_in, a.x1x2_in, a.y_out);
+            }
+            return;
         }
         if (a.sample)
             k_sample<NS, NI, K, MIX><<<a.grid, kBlock, lds, a.stream>>>(

@@ -249,6 +249,7 @@ bool compile_channel(Ctx& cx, const JValue& cj, const std::vector<double>& masse
     // s-hat
     {
         InvSpec& iv = t.inv[0];
+        iv.set = b.pmask(0);
         if (!hadronic) {
             iv.map.kind = MAP_FIXED;
             iv.xmin = iv.xmax = s_lab;
@@ -300,6 +301,7 @@ bool compile_channel(Ctx& cx, const JValue& cj, const std::vector<double>& masse
             v = par;
         }
         iv.map = make_map(nodes[j].m, nodes[j].w, nodes[j].nu, reg_a);
+        iv.set = b.pmask(j);
         iv.parent = nodes[v].inv;
         iv.min_const = fmin.c;
         iv.min_mask = fmin.mask;
@@ -335,6 +337,8 @@ bool compile_channel(Ctx& cx, const JValue& cj, const std::vector<double>& masse
             InvSpec& iv = t.inv[next_inv];
             Form fmin, fsub = leg_form(sigma[i]);
             for (int j = i + 1; j <= kappa + 1; ++j) fmin += leg_form(sigma[j]);
+            iv.set = 0;
+            for (int j = i + 1; j <= kappa + 1; ++j) iv.set |= b.pmask(sigma[j]);
             iv.map = make_map(0.0, 0.0, nu, reg_a);
             iv.parent = tinv[i - 1];
             iv.min_const = fmin.c;
@@ -351,21 +355,28 @@ bool compile_channel(Ctx& cx, const JValue& cj, const std::vector<double>& masse
             bs.m0_inv = tinv[i - 1];
             MassSrc rem{};
             rem.inv = tinv[i];
+            const uint32_t rest = i < kappa ? t.inv[tinv[i]].set : 0u;
             if (i == kappa) {
                 bs.side = 2;
                 bs.m1 = mass_src(nodes[sigma[kappa]]);
                 bs.m2 = mass_src(nodes[sigma[kappa + 1]]);
+                bs.set1 = b.pmask(sigma[kappa]);
+                bs.set2 = b.pmask(sigma[kappa + 1]);
                 nodes[sigma[kappa]].slot = 2 * (i - 1);
                 nodes[sigma[kappa + 1]].slot = 2 * (i - 1) + 1;
             } else if (from_a[i]) {
                 bs.side = 0;
                 bs.m1 = mass_src(nodes[sigma[i]]);
                 bs.m2 = rem;
+                bs.set1 = b.pmask(sigma[i]);
+                bs.set2 = rest;
                 nodes[sigma[i]].slot = 2 * (i - 1);
             } else {
                 bs.side = 1;
                 bs.m1 = rem;
                 bs.m2 = mass_src(nodes[sigma[i]]);
+                bs.set1 = rest;
+                bs.set2 = b.pmask(sigma[i]);
                 nodes[sigma[i]].slot = 2 * (i - 1) + 1;
             }
         }
@@ -386,6 +397,9 @@ bool compile_channel(Ctx& cx, const JValue& cj, const std::vector<double>& masse
         Node& k1 = nodes[nodes[j].kids[1]];
         ds.m1 = mass_src(k0);
         ds.m2 = mass_src(k1);
+        ds.parent_set = b.pmask((int)j);
+        ds.set1 = b.pmask(nodes[j].kids[0]);
+        ds.set2 = b.pmask(nodes[j].kids[1]);
         k0.slot = -2 - 2 * nd;
         k1.slot = -1 - 2 * nd;
         ++nd;

@@ -306,6 +306,43 @@ hipError_t launch_map(const ChannelTab* ct, const ProcessTab* pt, const double* 
     return launch_chain(reg_class(n_slots, n_inv), kind_class(kinds), mixed, a);
 }
 
+hipError_t launch_inverse(const ChannelTab* ct, const double* grid, int nb, int dims, int n_slots, int n_inv, int kinds,
+                          double s_lab, int np, int64_t n, const double* p, const double* x1x2, double* y, double* jac,
+                          int cu_count, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    ChainLaunch a{};
+    a.inverse = true;
+    a.lds = sizeof(double) * (size_t)dims * (nb + 1);
+    a.grid = grid_for(n, cu_count * 8);
+    a.stream = s;
+    a.cts = ct;
+    a.grids = grid;
+    a.nb = nb;
+    a.s_lab = s_lab;
+    a.np = np;
+    a.n = n;
+    a.p_in = p;
+    a.x1x2_in = x1x2;
+    a.y_out = y;
+    // always the FP64 units
+    hipError_t err = launch_chain(reg_class(n_slots, n_inv), kind_class(kinds), 0, a);
+    if (err != hipSuccess || !jac) return err;
+    // the forward Jacobian at y: the map kernel without momentum stores
+    ChainLaunch m{};
+    m.lds = a.lds;
+    m.grid = a.grid;
+    m.stream = s;
+    m.cts = ct;
+    m.grids = grid;
+    m.nb = nb;
+    m.s_lab = s_lab;
+    m.np = np;
+    m.n = n;
+    m.y = y;
+    m.jac = jac;
+    return launch_chain(reg_class(n_slots, n_inv), kind_class(kinds), 0, m);
+}
+
 hipError_t launch_weight(const ChannelTab* ct, const ProcessTab* pt, int mixed, int np, int64_t n, const double* p,
                          const double* x1x2, const double* jac, double* w, double* alpha, hipStream_t s) {
     if (n == 0) return hipSuccess;

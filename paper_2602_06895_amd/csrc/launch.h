@@ -11,6 +11,7 @@ namespace msx {
 // Arguments of one mapping-chain launch (single-channel map or fused sample).
 struct ChainLaunch {
     bool sample;
+    bool inverse;  // k_inverse: p_in, x1x2_in -> y_out, jac (FP64 units only)
     size_t lds;
     int grid;
     hipStream_t stream;
@@ -36,6 +37,10 @@ struct ChainLaunch {
     double* p;
     double* x1x2;
     double* w;
+    // inverse
+    const double* p_in;
+    const double* x1x2_in;
+    double* y_out;
 };
 
 // One register class (NS slots, NI invariants) at one precision; defined in
@@ -48,6 +53,10 @@ hipError_t launch_uniform(uint64_t seed, uint64_t sid, uint64_t e0, int64_t n, i
 hipError_t launch_map(const ChannelTab* ct, const ProcessTab* pt, const double* grid, int nb, int dims, int n_slots,
                       int n_inv, int kinds, int mixed, double s_lab, int np, int64_t n, const double* y, double* p,
                       double* x1x2, double* jac, double* w, int cu_count, hipStream_t s);
+
+hipError_t launch_inverse(const ChannelTab* ct, const double* grid, int nb, int dims, int n_slots, int n_inv, int kinds,
+                          double s_lab, int np, int64_t n, const double* p, const double* x1x2, double* y, double* jac,
+                          int cu_count, hipStream_t s);
 
 hipError_t launch_weight(const ChannelTab* ct, const ProcessTab* pt, int mixed, int np, int64_t n, const double* p,
                          const double* x1x2, const double* jac, double* w, double* alpha, hipStream_t s);

@@ -64,7 +64,7 @@ struct InvSpec {
     int32_t parent;
     uint32_t min_mask;
     uint32_t max_mask;
-    int32_t pad;
+    uint32_t set;  // final-state particles whose momenta sum to the invariant's cluster
     double min_const, max_const;
     // static bounds (s-hat): precomputed A = (xmax - m2)^e, B = (xmin - m2)^e
     // (MAP_POW), logs (MAP_LOG) or arctangents u2, u1 (MAP_BW)
@@ -79,6 +79,7 @@ struct BlockSpec {
                      // to B (p_B -= p2); 2: last block (both outputs are legs)
     int32_t com;     // p_A, p_B are the incoming partons in their CM frame
     int32_t m0_inv;  // (p_A + p_B)^2 = s[m0_inv] (s-hat or the previous t-channel invariant)
+    uint32_t set1, set2;  // final-state particles making up the outputs p1, p2
 };
 
 // One (phi, theta) two-body decay (section 2.2.3).
@@ -86,8 +87,9 @@ struct DecaySpec {
     int32_t parent_rest;  // 1: parent at rest in the partonic frame (no boost)
     int32_t parent_slot;  // slot code of the parent momentum otherwise
     int32_t parent_inv;   // m0^2 = s[parent_inv]
-    int32_t pad;
+    uint32_t parent_set;  // final-state particles of the parent
     MassSrc m1, m2;
+    uint32_t set1, set2;  // final-state particles of the two children
 };
 
 struct ChannelTab {

@@ -1,0 +1,133 @@
+"""Inverse map (msx_inverse_map) against the oracle's inverse on the same
+lab-frame momenta, and the GPU forward/inverse round trip.
+
+Both inverses recover invariants from momenta, which is ill-conditioned for
+small invariants (see the oracle's pins).  Per event the allowed difference
+therefore scales with the oracle's forward error fe on that event: the
+spread of its x87 build and of the builds with every libm / sqrt result and
+every input momentum moved by one ulp.  Every event within max(1e-12,
+1000 fe), all but 1e-3 of them within max(1e-12, 100 fe).  The density (the
+forward Jacobian at the recovered y) is compared with the oracle's forward
+Jacobian at the GPU's own y, within the forward chain's parity bound."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    if not t.cuda.is_available():
+        pytest.skip("needs a GPU")
+    return t
+
+
+def _random_grid(d, nb, seed):
+    rng = np.random.default_rng(seed)
+    g = np.empty((d, nb + 1))
+    for k in range(d):
+        g[k] = np.concatenate([[0.0], np.sort(rng.random(nb - 1)), [1.0]])
+    return g
+
+
+CASES = [("c1", W.c1_ee_mumu, 0, False)] + [("c2", W.c2_pp4j, c, c in (0, 6)) for c in range(8)] + \
+        [("c3", W.c3_ttbar6, 0, True), ("v8", lambda: W.volume_process(8), 0, False)]
+
+
+@pytest.mark.parametrize("name,mk,chan,vegas", CASES)
+def test_inverse_matches_oracle(torch, name, mk, chan, vegas):
+    from paper_2602_06895_amd import Context
+
+    desc = mk()
+    if name == "v8":
+        desc["vegas_bins"] = 128
+    ctx = Context(desc)
+    orc = oracle.Process(desc)
+    d = ctx.dims[chan]
+    grid = _random_grid(d, orc.nbins, 17 + chan) if vegas else orc.uniform_grid(chan)
+    ctx.set_grid(chan, grid)
+    n = 30001  # several tiles and a ragged tail
+    y = W.philox_uniforms(21, 3, 0, n, d)
+    fwd = orc.map(chan, y, grid)
+    ok = fwd["jac"] > 0
+    x = fwd["x1x2"] if orc.hadronic else None
+    ref = orc.inverse(chan, fwd["p"], x, grid)
+    fe = orc.inverse_forward_error(chan, fwd["p"], x, grid, ref)
+    out = ctx.inverse_map(chan, torch.from_numpy(fwd["p"]).cuda(),
+                          torch.from_numpy(x).cuda() if x is not None else None)
+    torch.cuda.synchronize()
+    yg = out["y"].cpu().numpy()
+    jg = out["jac"].cpu().numpy()
+    dy = np.abs(yg - ref["y"]).max(axis=0)[ok]
+    fy = fe["y"][ok]
+    assert np.all(dy <= np.maximum(1e-12, 1000.0 * fy)), (name, chan, float(np.max(dy / np.maximum(fy, 1e-15))))
+    assert np.mean(dy > np.maximum(1e-12, 100.0 * fy)) <= 1e-3
+    # the density: the GPU's Jacobian against the oracle's forward Jacobian at
+    # the GPU's own y (the y differences above are checked there), within the
+    # forward chain's parity bound
+    at = orc.map(chan, yg, grid)
+    fef = orc.forward_error(chan, yg, grid, ref=at)
+    keep = ok & (at["jac"] > 0)
+    dj = np.abs(jg[keep] / at["jac"][keep] - 1.0)
+    fj = fef["jac"][keep]
+    assert np.all(dj <= np.maximum(1e-12, 1000.0 * fj)), (name, chan, float(np.max(dj / np.maximum(fj, 1e-15))))
+    # most events agree to the unit roundoff scale (a random grid multiplies
+    # differences in r by 1 / (bins x bin width), ~ 1 typically, 16 dims)
+    assert np.median(dy) < (1e-11 if vegas else 1e-12)
+    ctx.close()
+
+
+def test_round_trip_at_scale(torch):
+    """1e6 events per pp -> 4 jets channel through the GPU forward map and back."""
+    from paper_2602_06895_amd import Context
+
+    ctx = Context(W.c2_pp4j())
+    for chan in range(8):
+        d = ctx.dims[chan]
+        y = ctx.uniform(5, 4, 0, 1_000_000, d)
+        fwd = ctx.map(chan, y)
+        inv = ctx.inverse_map(chan, fwd["p"], fwd["x1x2"])
+        torch.cuda.synchronize()
+        ok = fwd["jac"] > 0
+        err = (inv["y"] - y).abs().amax(dim=0)[ok]
+        jr = (inv["jac"][ok] / fwd["jac"][ok] - 1.0).abs()
+        q = torch.tensor([0.5, 0.99], dtype=torch.float64, device="cuda")
+        e50, e99 = torch.quantile(err[:200_000], q).tolist()
+        j50, j99 = torch.quantile(jr[:200_000], q).tolist()
+        # the tail (small invariants recovered from momenta) grows with the
+        # sample: bound its share rather than its maximum
+        tail = float((err > 1e-3).double().mean())
+        assert e50 < 1e-11 and e99 < 1e-6 and tail < 1e-4, (chan, e50, e99, tail)
+        assert j50 < 1e-10 and j99 < 1e-5, (chan, j50, j99)
+    ctx.close()
+
+
+@pytest.mark.parametrize("n", [1, 255, 257])
+def test_ragged_and_tiny_batches(torch, n):
+    from paper_2602_06895_amd import Context
+
+    ctx = Context(W.c3_ttbar6())
+    y = ctx.uniform(9, 1, 3, n, ctx.dims[0])
+    fwd = ctx.map(0, y)
+    inv = ctx.inverse_map(0, fwd["p"], fwd["x1x2"])
+    torch.cuda.synchronize()
+    assert float((inv["y"] - y).abs().max()) < 1e-6
+    ctx.close()
+
+
+def test_empty_and_argument_errors(torch):
+    from paper_2602_06895_amd import Context, MsxError
+
+    ctx = Context(W.c1_ee_mumu())
+    p = torch.zeros(4, 4, 0, dtype=torch.float64, device="cuda")
+    out = ctx.inverse_map(0, p, None)
+    assert out["y"].shape == (2, 0)
+    with pytest.raises(MsxError):
+        ctx.inverse_map(0, torch.zeros(4, 4, 8, dtype=torch.float64, device="cuda"),
+                        torch.zeros(2, 8, dtype=torch.float64, device="cuda"))
+    ctx.close()

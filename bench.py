@@ -225,6 +225,40 @@ def graph_report(reps=10):
             "autotuned": {"events_per_thread": ept, "grid": grid, "ms": best}}
 
 
+def inverse_report(n=10_000_000, reps=5, channel=0):
+    """Inverse map (momenta -> uniforms and the channel density) of n
+    pp -> 4 jets events of one channel: the momenta come from the forward map
+    of seeded uniforms (untimed); the timed call is msx_inverse_map (the
+    inverse kernel and the store-free Jacobian pass).  Algorithmic bytes per
+    event: momenta 6 x 4 x 8 + x1x2 16 read, y 10 x 8 + jac 8 written, y read
+    back by the Jacobian pass = 376 B."""
+    import torch
+
+    import workloads as W
+    from paper_2602_06895_amd import Context
+
+    ctx = Context(W.c2_pp4j())
+    d = ctx.dims[channel]
+    y = ctx.uniform(7, 9, 0, n, d)
+    fwd = ctx.map(channel, y)
+    ms = _timed(lambda: ctx.inverse_map(channel, fwd["p"], fwd["x1x2"]), reps)
+    inv = ctx.inverse_map(channel, fwd["p"], fwd["x1x2"])
+    torch.cuda.synchronize()
+    ok = fwd["jac"] > 0
+    err = (inv["y"] - y).abs().amax(dim=0)[ok]
+    sub = err[:1_000_000].double()
+    q = torch.quantile(sub, torch.tensor([0.5, 0.99], dtype=torch.float64, device="cuda")).tolist()
+    bpe = 6 * 4 * 8 + 16 + 2 * d * 8 + 8
+    ach = n * bpe / (ms / 1e3) / 1e9
+    out = {"workload": f"pp->4j channel {channel}, {n} events, momenta -> uniforms + density",
+           "events_per_s": n / (ms / 1e3), "ms": ms,
+           "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": ach / HBM_PEAK_GBS, "bytes_per_event": bpe},
+           "round_trip_err": {"median": q[0], "p99": q[1], "tail_gt_1e-3": float((err > 1e-3).double().mean())}}
+    ctx.close()
+    return out
+
+
 def summarize(d: str, events: int, steps: int = 10):
     """Summary of the rocprofv3 runs under d (rocpd databases written by the
     commands printed below) for the last `steps` k_sample dispatches of
@@ -313,13 +347,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-autotune", action="store_true", help="default launch shape instead of the autotuned one")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the mixed-precision, flow and graph reports")
+                    help="skip the mixed-precision, flow, graph and inverse-map reports")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run device-to-device copies of 1 GiB (scale for HBM byte counters)")
     ap.add_argument("--summarize", metavar="DIR", help="summarise rocprofv3 output under DIR and exit")
     ap.add_argument("--summarize-flow", metavar="DIR", help="summarise a flow kernel trace under DIR/flow and exit")
     ap.add_argument("--flow-only", action="store_true", help="only the learned-sampler report")
     ap.add_argument("--flow-steps", type=int, default=400, help="training steps of the learned sampler")
+    ap.add_argument("--inverse-only", action="store_true", help="only the inverse-map report")
     args = ap.parse_args()
     if args.summarize:
         summarize(args.summarize, args.events)
@@ -329,6 +364,9 @@ def main():
         return
     if args.flow_only:
         print(json.dumps({"flow_vs_vegas": flow_report(train_steps=args.flow_steps)}))
+        return
+    if args.inverse_only:
+        print(json.dumps({"inverse_map": inverse_report()}))
         return
     if args.copy_calibration:
         import torch
@@ -441,6 +479,8 @@ def main():
         result["flow_vs_vegas_c2_channel0"] = flow_report(train_steps=args.flow_steps, workload="c2", channel=0)
         torch.cuda.empty_cache()
         result["multichannel_graph"] = graph_report()
+        torch.cuda.empty_cache()
+        result["inverse_map"] = inverse_report()
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(desc, grids, counts, seed=1)
     print(json.dumps(result))

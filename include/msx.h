@@ -165,6 +165,20 @@ msx_status msx_map(msx_ctx* ctx, int32_t channel, int64_t n, const double* y, do
 msx_status msx_inverse_map(msx_ctx* ctx, int32_t channel, int64_t n, const double* p, const double* x1x2, double* y,
                            double* jac, void* stream);
 
+/* Global multichannel density of the channels of process `process` (the
+ * Kleiss-Pittau form of the multichannel method, section 2.1):
+ *   g(p) = sum_c alpha[c] / J_c(y_c(p)),
+ * with y_c(p) the channel's inverse map and J_c its forward Jacobian there
+ * (msx_inverse_map), over the process's channels in context order; alpha
+ * (host, one entry >= 0 per channel of the process) are the a-priori channel
+ * weights.  An event that channel c's chain cuts contributes 0.  The
+ * multichannel weight of an event is then f(p) / g(p).  p [4][np][n],
+ * x1x2 [2][n] (hadronic) and g [n] are device arrays.  Uses a context-owned
+ * scratch of (max dims + 1) n doubles (grown on demand: a call that grows it
+ * synchronizes the device).  n = 0 is a no-op. */
+msx_status msx_multichannel_density(msx_ctx* ctx, int32_t process, int64_t n, const double* p, const double* x1x2,
+                                    const double* alpha, double* g, void* stream);
+
 /* Event weight w = alpha_c(x) f(x) jac from momenta p [4][np][n] (lab frame,
  * as written by msx_map), x1x2 (hadronic) and jac; alpha [n] optional. */
 msx_status msx_weight(msx_ctx* ctx, int32_t channel, int64_t n, const double* p,

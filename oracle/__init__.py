@@ -371,6 +371,19 @@ class Process:
         return {"y": np.max([np.abs(o["y"] - ref["y"]).max(axis=0) for o in alts], axis=0),
                 "jac": np.max([np.abs(o["jac"] - ref["jac"]) / den for o in alts], axis=0)}
 
+    def multichannel_density(self, p: np.ndarray, x1x2: np.ndarray | None, alpha, grids=None,
+                             variant: str = "ref") -> np.ndarray:
+        """Global multichannel density g(p) = sum_c alpha_c / J_c(y_c(p)) over
+        this process's channels (section 2.1, Kleiss-Pittau form): each
+        channel's inverse map gives y_c and the forward Jacobian there; a
+        channel whose chain cuts the event (J = 0) contributes 0."""
+        g = np.zeros(p.shape[2])
+        for c in range(len(self.channels)):
+            inv = self.inverse(c, p, x1x2, None if grids is None else grids[c], variant=variant)
+            j = inv["jac"]
+            g += np.where(j > 0, alpha[c] / np.where(j > 0, j, 1.0), 0.0)
+        return g
+
     def weight(self, chan: int, p: np.ndarray, x1x2: np.ndarray | None, jac: np.ndarray,
                nthreads: int = 0, variant: str = "ref") -> dict:
         """w = alpha_c f jac from lab-frame momenta p [4][n+2][N], x1x2 [2][N]

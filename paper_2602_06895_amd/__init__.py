@@ -29,7 +29,7 @@ EXPORTS = ["msx_last_error", "msx_create_channels", "msx_destroy", "msx_get_meta
            "msx_flow_set_params", "msx_flow_get_params", "msx_flow_forward", "msx_flow_inverse",
            "msx_flow_gradient", "msx_flow_train_step", "msx_flow_sample", "msx_sample_device",
            "msx_sample_graph_create", "msx_graph_launch", "msx_graph_destroy", "msx_set_launch", "msx_autotune",
-           "msx_inverse_map"]
+           "msx_inverse_map", "msx_multichannel_density"]
 FLOW_BF16, FLOW_FP32 = 0, 1
 
 
@@ -59,6 +59,7 @@ def load_library(path: str = LIB_PATH):
         "msx_uniform": ([vp, u64, u64, u64, i64, i32, vp, vp], C.c_int),
         "msx_map": ([vp, i32, i64, vp, vp, vp, vp, vp, vp], C.c_int),
         "msx_inverse_map": ([vp, i32, i64, vp, vp, vp, vp, vp], C.c_int),
+        "msx_multichannel_density": ([vp, i32, i64, vp, vp, vp, vp, vp], C.c_int),
         "msx_weight": ([vp, i32, i64, vp, vp, vp, vp, vp, vp], C.c_int),
         "msx_sample": ([vp, vp, u64, u64, u64, vp, vp, vp, vp, vp], C.c_int),
         "msx_stats": ([vp, vp, vp], C.c_int),
@@ -196,6 +197,18 @@ class Context:
         self._check(self.L.msx_inverse_map(self.h, channel, n, _ptr(p), _ptr(x1x2), _ptr(out["y"]),
                                            _ptr(out["jac"]), self._stream()))
         return out
+
+    def multichannel_density(self, process: int, p, x1x2, alpha):
+        """g(p) = sum_c alpha_c / J_c(y_c(p)) over the channels of `process`
+        (alpha: one a-priori weight per channel of the process, host)."""
+        n = p.shape[2]
+        a = np.ascontiguousarray(alpha, dtype=np.float64)
+        p = p.contiguous()
+        x1x2 = x1x2.contiguous() if x1x2 is not None else None
+        g = self._empty(n)
+        self._check(self.L.msx_multichannel_density(self.h, process, n, _ptr(p), _ptr(x1x2),
+                                                    a.ctypes.data_as(C.c_void_p), _ptr(g), self._stream()))
+        return g
 
     def weight(self, channel: int, p, x1x2, jac, alpha: bool = False):
         n = jac.shape[0]

@@ -41,6 +41,8 @@ struct msx_ctx {
     double* d_tile = nullptr;
     int64_t tile_cap = 0;
     double* d_vpart = nullptr;
+    double* d_inv = nullptr;  // multichannel density scratch: y [max dims][n] then jac [n]
+    int64_t inv_cap = 0;      // doubles
     int64_t vpart_cap = 0;
     double* d_unw = nullptr;  // 2 * 4096 buckets + 2 * 1024 partials + 2
     size_t lds_max = 0;
@@ -92,7 +94,8 @@ hipError_t dmalloc(T** p, size_t count) {
 
 void free_all(msx_ctx* c) {
     void* ptrs[] = {c->d_chans, c->d_procs, c->d_grids, c->d_hist, c->d_stats, c->d_grid_off, c->d_chan_nb,
-                    c->d_row_nb, c->d_row_grid, c->d_row_hist, c->d_tile, c->d_vpart, c->d_unw, c->d_call};
+                    c->d_row_nb, c->d_row_grid, c->d_row_hist, c->d_tile, c->d_vpart, c->d_unw, c->d_call,
+                    c->d_inv};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -322,6 +325,54 @@ msx_status msx_inverse_map(msx_ctx* ctx, int32_t channel, int64_t n, const doubl
                            t.n_inv, t.kinds, pt.s_lab, m.n_momenta, n, p, x1x2, y, jac, ctx->cu_count,
                            (hipStream_t)stream),
             "inverse launch");
+    return MSX_OK;
+}
+
+msx_status msx_multichannel_density(msx_ctx* ctx, int32_t process, int64_t n, const double* p, const double* x1x2,
+                                    const double* alpha, double* g, void* stream) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (process < 0 || process >= (int32_t)ctx->comp.procs.size())
+        return fail(ctx, MSX_ERR_ARG, "process index out of range");
+    if (n < 0) return fail(ctx, MSX_ERR_ARG, "n < 0");
+    if (n > 0 && (!p || !g || !alpha)) return fail(ctx, MSX_ERR_ARG, "p, alpha and g are required");
+    std::vector<int> chans;
+    int dmax = 0;
+    for (int c = 0; c < (int)ctx->comp.meta.size(); ++c)
+        if (ctx->comp.meta[c].process == process) {
+            chans.push_back(c);
+            dmax = std::max(dmax, ctx->comp.meta[c].dims);
+        }
+    const ChannelMeta& m0 = ctx->comp.meta[chans[0]];
+    if (m0.hadronic && n > 0 && !x1x2) return fail(ctx, MSX_ERR_ARG, "x1x2 is required for hadronic beams");
+    if (!m0.hadronic && x1x2) return fail(ctx, MSX_ERR_ARG, "x1x2 must be NULL for fixed beams");
+    for (size_t i = 0; i < chans.size(); ++i)
+        if (!(alpha[i] >= 0.0)) return fail(ctx, MSX_ERR_ARG, "alpha must be >= 0");
+    if (n == 0) return MSX_OK;
+    if (msx_status st = set_device(ctx)) return st;
+    const int64_t need = (int64_t)(dmax + 1) * n;
+    if (need > ctx->inv_cap) {
+        // the previous scratch may still be read by work in flight
+        MSX_HIP(ctx, hipDeviceSynchronize(), "synchronize");
+        if (ctx->d_inv) MSX_HIP(ctx, hipFree(ctx->d_inv), "hipFree");
+        ctx->d_inv = nullptr;
+        ctx->inv_cap = 0;
+        MSX_HIP(ctx, dmalloc(&ctx->d_inv, need), "density scratch");
+        ctx->inv_cap = need;
+    }
+    double* y = ctx->d_inv;
+    double* jac = ctx->d_inv + (int64_t)dmax * n;
+    hipStream_t s = (hipStream_t)stream;
+    for (size_t i = 0; i < chans.size(); ++i) {
+        const int c = chans[i];
+        const ChannelMeta& m = ctx->comp.meta[c];
+        const ChannelTab& t = ctx->comp.chans[c];
+        const ProcessTab& pt = ctx->comp.procs[m.process];
+        MSX_HIP(ctx,
+                launch_inverse(ctx->d_chans + c, ctx->d_grids + ctx->grid_off[c], m.nbins, m.dims, t.n_slots, t.n_inv,
+                               t.kinds, pt.s_lab, m.n_momenta, n, p, x1x2, y, jac, ctx->cu_count, s),
+                "inverse launch");
+        MSX_HIP(ctx, launch_density_add(g, jac, alpha[i], n, i == 0, s), "density launch");
+    }
     return MSX_OK;
 }
 

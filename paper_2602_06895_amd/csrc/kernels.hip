@@ -102,6 +102,18 @@ __global__ __launch_bounds__(kBlock) void k_stats_final(const SampleCall* __rest
     }
 }
 
+// Global multichannel density: g += alpha / J of one channel (g = alpha / J
+// for the first channel).  A channel whose chain cuts the event (J = 0)
+// contributes nothing.
+__global__ __launch_bounds__(kBlock) void k_density_add(double* __restrict__ g, const double* __restrict__ jac,
+                                                        double alpha, int64_t n, int first) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double j = jac[i];
+    const double t = j > 0.0 ? alpha / j : 0.0;
+    g[i] = first ? t : g[i] + t;
+}
+
 __global__ void k_set_call(SampleCall call, SampleCall* __restrict__ dev) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *dev = call;
 }
@@ -274,6 +286,13 @@ hipError_t launch_chain(int rc, int kc, int mixed, const ChainLaunch& a) {
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+
+hipError_t launch_density_add(double* g, const double* jac, double alpha, int64_t n, bool first, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int64_t b = (n + kBlock - 1) / kBlock;
+    k_density_add<<<dim3((unsigned)b), dim3(kBlock), 0, s>>>(g, jac, alpha, n, first ? 1 : 0);
+    return hipGetLastError();
+}
 
 hipError_t launch_uniform(uint64_t seed, uint64_t sid, uint64_t e0, int64_t n, int d, double* y, hipStream_t s) {
     if (n == 0) return hipSuccess;

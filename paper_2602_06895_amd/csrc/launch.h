@@ -58,6 +58,9 @@ hipError_t launch_inverse(const ChannelTab* ct, const double* grid, int nb, int 
                           double s_lab, int np, int64_t n, const double* p, const double* x1x2, double* y, double* jac,
                           int cu_count, hipStream_t s);
 
+// g = alpha / jac (first) or g += alpha / jac; jac = 0 adds nothing.
+hipError_t launch_density_add(double* g, const double* jac, double alpha, int64_t n, bool first, hipStream_t s);
+
 hipError_t launch_weight(const ChannelTab* ct, const ProcessTab* pt, int mixed, int np, int64_t n, const double* p,
                          const double* x1x2, const double* jac, double* w, double* alpha, hipStream_t s);
 

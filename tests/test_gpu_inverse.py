@@ -131,3 +131,30 @@ def test_empty_and_argument_errors(torch):
         ctx.inverse_map(0, torch.zeros(4, 4, 8, dtype=torch.float64, device="cuda"),
                         torch.zeros(2, 8, dtype=torch.float64, device="cuda"))
     ctx.close()
+
+
+def test_multichannel_density_matches_oracle(torch):
+    """g(p) = sum_c alpha_c / J_c(y_c(p)) over the 8 pp -> 4 jets channels
+    for events of two of them, against the oracle's density."""
+    from paper_2602_06895_amd import Context
+
+    desc = W.c2_pp4j()
+    ctx = Context(desc)
+    orc = oracle.Process(desc)
+    alpha = np.array([0.3, 0.1, 0.1, 0.1, 0.1, 0.1, 0.1, 0.1])
+    for chan in (2, 7):
+        y = W.philox_uniforms(41, chan, 0, 20001, orc.dims[chan])
+        fwd = orc.map(chan, y)
+        ok = fwd["jac"] > 0
+        g_ref = orc.multichannel_density(fwd["p"], fwd["x1x2"], alpha)
+        g = ctx.multichannel_density(0, torch.from_numpy(fwd["p"]).cuda(), torch.from_numpy(fwd["x1x2"]).cuda(),
+                                     alpha)
+        torch.cuda.synchronize()
+        # every channel inverts every event, also far from its own region
+        # (worse conditioned): the bound is the oracle's perturbation spread
+        fe = np.max([np.abs(orc.multichannel_density(fwd["p"], fwd["x1x2"], alpha, variant=v) / g_ref - 1.0)
+                     for v in ("x87", "up", "down")], axis=0)[ok]
+        r = np.abs(g.cpu().numpy()[ok] / g_ref[ok] - 1.0)
+        assert np.all(r <= np.maximum(1e-12, 1000.0 * fe)), (chan, float(np.max(r / np.maximum(fe, 1e-15))))
+        assert np.median(r) < 1e-12
+    ctx.close()

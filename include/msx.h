@@ -268,6 +268,22 @@ msx_status msx_set_grid(msx_ctx* ctx, int32_t channel, const double* edges);
 msx_status msx_unweight_eff(msx_ctx* ctx, const double* w, int64_t n, double overweight,
                             double* eff, double* w_max, void* stream);
 
+/* Hit-or-miss unweighting of weights w [n] >= 0 (device) against a maximum
+ * weight w_max > 0 (section 3.4.1: the channel-wise files are unweighted with
+ * the current estimate of the maximum weight, at the end once more with the
+ * final one).  Event i is kept when u_i w_max < w_i, with u_i the uniform of
+ * event id counter_offset + i under (seed, stream_id) -- dimension 0 of
+ * msx_uniform, a stream of its own so that the decision is reproducible.
+ * Outputs (device): keep [n] the kept indices in increasing order (first
+ * *count entries), uw [n] (optional) their unit weights max(1, w_i / w_max)
+ * (above 1 for overweight events), count [1] int64 the number kept.  A
+ * second unweighting against a larger final maximum W' takes the effective
+ * weights max(w_i, w_max) of the kept events.  Enqueues only (the count stays
+ * on the device); a call that grows the context's block scratch synchronizes
+ * the device.  n = 0 sets *count = 0. */
+msx_status msx_unweight(msx_ctx* ctx, const double* w, int64_t n, double w_max, uint64_t seed, uint64_t stream_id,
+                        uint64_t counter_offset, int64_t* keep, double* uw, int64_t* count, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

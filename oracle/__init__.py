@@ -94,6 +94,16 @@ def lib(variant: str = "ref"):
     return _libs[variant]
 
 
+def unweight(w: np.ndarray, w_max: float, u: np.ndarray) -> dict:
+    """Hit-or-miss unweighting (section 3.4.1): event i is kept when
+    u_i w_max < w_i (u: the uniforms drawn for the decision, passed in) and
+    carries the unit weight max(1, w_i / w_max).  Returns the kept indices in
+    increasing order and their unit weights."""
+    w = np.asarray(w, np.float64)
+    keep = np.nonzero(u * w_max < w)[0]
+    return {"keep": keep, "uw": np.maximum(1.0, w[keep] / w_max)}
+
+
 class _Channel(C.Structure):
     _fields_ = [("n_nodes", C.c_int32), ("root", C.c_int32), ("n_sorder", C.c_int32),
                 ("n_dec", C.c_int32),

@@ -29,7 +29,7 @@ EXPORTS = ["msx_last_error", "msx_create_channels", "msx_destroy", "msx_get_meta
            "msx_flow_set_params", "msx_flow_get_params", "msx_flow_forward", "msx_flow_inverse",
            "msx_flow_gradient", "msx_flow_train_step", "msx_flow_sample", "msx_sample_device",
            "msx_sample_graph_create", "msx_graph_launch", "msx_graph_destroy", "msx_set_launch", "msx_autotune",
-           "msx_inverse_map", "msx_multichannel_density"]
+           "msx_inverse_map", "msx_multichannel_density", "msx_unweight"]
 FLOW_BF16, FLOW_FP32 = 0, 1
 
 
@@ -60,6 +60,7 @@ def load_library(path: str = LIB_PATH):
         "msx_map": ([vp, i32, i64, vp, vp, vp, vp, vp, vp], C.c_int),
         "msx_inverse_map": ([vp, i32, i64, vp, vp, vp, vp, vp], C.c_int),
         "msx_multichannel_density": ([vp, i32, i64, vp, vp, vp, vp, vp], C.c_int),
+        "msx_unweight": ([vp, vp, i64, C.c_double, C.c_uint64, C.c_uint64, C.c_uint64, vp, vp, vp, vp], C.c_int),
         "msx_weight": ([vp, i32, i64, vp, vp, vp, vp, vp, vp], C.c_int),
         "msx_sample": ([vp, vp, u64, u64, u64, vp, vp, vp, vp, vp], C.c_int),
         "msx_stats": ([vp, vp, vp], C.c_int),
@@ -197,6 +198,19 @@ class Context:
         self._check(self.L.msx_inverse_map(self.h, channel, n, _ptr(p), _ptr(x1x2), _ptr(out["y"]),
                                            _ptr(out["jac"]), self._stream()))
         return out
+
+    def unweight(self, w, w_max: float, seed: int, stream_id: int = 0, counter_offset: int = 0):
+        """Hit-or-miss unweighting of w [n] (device float64) against w_max:
+        kept indices (increasing), their unit weights max(1, w / w_max) and
+        the count (a device int64 tensor of one element)."""
+        n = w.shape[0]
+        w = w.contiguous()
+        keep = self.torch.empty(max(n, 1), dtype=self.torch.int64, device=self.device)
+        uw = self._empty(max(n, 1))
+        count = self.torch.zeros(1, dtype=self.torch.int64, device=self.device)
+        self._check(self.L.msx_unweight(self.h, _ptr(w), n, float(w_max), seed, stream_id, counter_offset,
+                                        _ptr(keep), _ptr(uw), _ptr(count), self._stream()))
+        return {"keep": keep, "uw": uw, "count": count}
 
     def multichannel_density(self, process: int, p, x1x2, alpha):
         """g(p) = sum_c alpha_c / J_c(y_c(p)) over the channels of `process`

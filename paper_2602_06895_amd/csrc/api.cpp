@@ -41,6 +41,8 @@ struct msx_ctx {
     double* d_tile = nullptr;
     int64_t tile_cap = 0;
     double* d_vpart = nullptr;
+    int64_t* d_ublk = nullptr;  // unweighting block offsets
+    int64_t ublk_cap = 0;
     double* d_inv = nullptr;  // multichannel density scratch: y [max dims][n] then jac [n]
     int64_t inv_cap = 0;      // doubles
     int64_t vpart_cap = 0;
@@ -95,7 +97,7 @@ hipError_t dmalloc(T** p, size_t count) {
 void free_all(msx_ctx* c) {
     void* ptrs[] = {c->d_chans, c->d_procs, c->d_grids, c->d_hist, c->d_stats, c->d_grid_off, c->d_chan_nb,
                     c->d_row_nb, c->d_row_grid, c->d_row_hist, c->d_tile, c->d_vpart, c->d_unw, c->d_call,
-                    c->d_inv};
+                    c->d_inv, c->d_ublk};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -701,6 +703,31 @@ msx_status msx_set_grid(msx_ctx* ctx, int32_t channel, const double* edges) {
             hipMemcpy(ctx->d_grids + ctx->grid_off[channel], edges, sizeof(double) * m.dims * (m.nbins + 1),
                       hipMemcpyHostToDevice),
             "grid copy");
+    return MSX_OK;
+}
+
+msx_status msx_unweight(msx_ctx* ctx, const double* w, int64_t n, double w_max, uint64_t seed, uint64_t stream_id,
+                        uint64_t counter_offset, int64_t* keep, double* uw, int64_t* count, void* stream) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (n < 0) return fail(ctx, MSX_ERR_ARG, "n < 0");
+    if (!count) return fail(ctx, MSX_ERR_ARG, "count is required");
+    if (n > 0 && (!w || !keep)) return fail(ctx, MSX_ERR_ARG, "w and keep are required");
+    if (!(w_max > 0.0) || !std::isfinite(w_max)) return fail(ctx, MSX_ERR_ARG, "w_max must be finite and > 0");
+    if (msx_status st = set_device(ctx)) return st;
+    const int64_t nb = std::max<int64_t>(1, unweight_blocks(n));
+    if (nb > ctx->ublk_cap) {
+        // the previous scratch may still be read by work in flight
+        MSX_HIP(ctx, hipDeviceSynchronize(), "synchronize");
+        if (ctx->d_ublk) MSX_HIP(ctx, hipFree(ctx->d_ublk), "hipFree");
+        ctx->d_ublk = nullptr;
+        ctx->ublk_cap = 0;
+        MSX_HIP(ctx, dmalloc(&ctx->d_ublk, nb), "unweighting scratch");
+        ctx->ublk_cap = nb;
+    }
+    MSX_HIP(ctx,
+            launch_unweight(w, n, w_max, seed, stream_id, counter_offset, ctx->d_ublk, keep, uw, count,
+                            (hipStream_t)stream),
+            "unweighting launch");
     return MSX_OK;
 }
 

@@ -102,6 +102,103 @@ __global__ __launch_bounds__(kBlock) void k_stats_final(const SampleCall* __rest
     }
 }
 
+// Hit-or-miss unweighting (the paper's channel-wise unweighting against an
+// estimated maximum weight): event i is kept when u_i w_max < w_i, u_i the
+// Philox uniform of event id e0 + i (dimension 0, as msx_uniform), and
+// carries the unit weight max(1, w_i / w_max) (overweight events above 1).
+// Pass 1 counts the kept events of every block of kUnwPer events; a one-
+// workgroup scan turns the counts into offsets; pass 2 writes the kept
+// indices in increasing order (ranks within a block from wave ballots).
+constexpr int kUnwPer = kBlock * 4;  // events per block
+
+__device__ __forceinline__ bool unw_keep(const double* __restrict__ w, int64_t i, double w_max, uint64_t seed,
+                                         uint64_t sid, uint64_t e0) {
+    uint64_t c0 = e0 + (uint64_t)i, c1 = 0, c2 = 0, c3 = 0;
+    philox4x64_10(c0, c1, c2, c3, seed, sid);
+    return to_unit(c0) * w_max < w[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_unw_count(const double* __restrict__ w, int64_t n, double w_max,
+                                                      uint64_t seed, uint64_t sid, uint64_t e0,
+                                                      int64_t* __restrict__ blk) {
+    __shared__ int red[kWaves];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t i = (int64_t)blockIdx.x * kUnwPer + q * kBlock + threadIdx.x;
+        if (i < n && unw_keep(w, i, w_max, seed, sid, e0)) ++c;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if (lane == 0) red[wave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int v = 0; v < kWaves; ++v) t += red[v];
+        blk[blockIdx.x] = t;
+    }
+}
+
+// Exclusive scan of nb block counts in place (one workgroup: every thread
+// sums a contiguous run, the run totals are scanned in LDS); total to *count.
+__global__ __launch_bounds__(1024) void k_unw_scan(int64_t* __restrict__ blk, int64_t nb, int64_t* __restrict__ count) {
+    __shared__ int64_t tot[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t b0 = t * per, b1 = min(nb, b0 + per);
+    int64_t s = 0;
+    for (int64_t b = b0; b < b1; ++b) s += blk[b];
+    tot[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        int64_t acc = 0;
+        for (int v = 0; v < 1024; ++v) {
+            const int64_t x = tot[v];
+            tot[v] = acc;
+            acc += x;
+        }
+        *count = acc;
+    }
+    __syncthreads();
+    int64_t acc = tot[t];
+    for (int64_t b = b0; b < b1; ++b) {
+        const int64_t x = blk[b];
+        blk[b] = acc;
+        acc += x;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_unw_write(const double* __restrict__ w, int64_t n, double w_max,
+                                                      uint64_t seed, uint64_t sid, uint64_t e0,
+                                                      const int64_t* __restrict__ blk, int64_t* __restrict__ keep,
+                                                      double* __restrict__ uw) {
+    __shared__ int wcnt[kWaves];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t base = blk[blockIdx.x];
+#pragma unroll 1
+    for (int q = 0; q < 4; ++q) {
+        const int64_t i = (int64_t)blockIdx.x * kUnwPer + q * kBlock + threadIdx.x;
+        const bool k = i < n && unw_keep(w, i, w_max, seed, sid, e0);
+        const uint64_t bal = __ballot(k);
+        if (lane == 0) wcnt[wave] = __popcll(bal);
+        __syncthreads();
+        int off = 0, all = 0;
+#pragma unroll
+        for (int v = 0; v < kWaves; ++v) {
+            off += v < wave ? wcnt[v] : 0;
+            all += wcnt[v];
+        }
+        if (k) {
+            const int64_t pos = base + off + __popcll(bal & ((1ull << lane) - 1));
+            keep[pos] = i;
+            if (uw) uw[pos] = fmax(1.0, w[i] / w_max);
+        }
+        base += all;
+        __syncthreads();
+    }
+}
+
 // Global multichannel density: g += alpha / J of one channel (g = alpha / J
 // for the first channel).  A channel whose chain cuts the event (J = 0)
 // contributes nothing.
@@ -286,6 +383,24 @@ hipError_t launch_chain(int rc, int kc, int mixed, const ChainLaunch& a) {
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+
+int64_t unweight_blocks(int64_t n) { return (n + kUnwPer - 1) / kUnwPer; }
+
+hipError_t launch_unweight(const double* w, int64_t n, double w_max, uint64_t seed, uint64_t sid, uint64_t e0,
+                           int64_t* blk, int64_t* keep, double* uw, int64_t* count, hipStream_t s) {
+    const int64_t nb = unweight_blocks(n);
+    if (nb == 0) {
+        k_unw_scan<<<1, 1024, 0, s>>>(blk, 0, count);
+        return hipGetLastError();
+    }
+    k_unw_count<<<dim3((unsigned)nb), dim3(kBlock), 0, s>>>(w, n, w_max, seed, sid, e0, blk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_unw_scan<<<1, 1024, 0, s>>>(blk, nb, count);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_unw_write<<<dim3((unsigned)nb), dim3(kBlock), 0, s>>>(w, n, w_max, seed, sid, e0, blk, keep, uw);
+    return hipGetLastError();
+}
 
 hipError_t launch_density_add(double* g, const double* jac, double alpha, int64_t n, bool first, hipStream_t s) {
     if (n == 0) return hipSuccess;

@@ -58,6 +58,13 @@ hipError_t launch_inverse(const ChannelTab* ct, const double* grid, int nb, int 
                           double s_lab, int np, int64_t n, const double* p, const double* x1x2, double* y, double* jac,
                           int cu_count, hipStream_t s);
 
+// Hit-or-miss unweighting: kept indices (increasing) to keep, unit weights
+// max(1, w / w_max) to uw (optional), the number kept to count (device);
+// blk: scratch of unweight_blocks(n) (at least 1) int64.
+int64_t unweight_blocks(int64_t n);
+hipError_t launch_unweight(const double* w, int64_t n, double w_max, uint64_t seed, uint64_t sid, uint64_t e0,
+                           int64_t* blk, int64_t* keep, double* uw, int64_t* count, hipStream_t s);
+
 // g = alpha / jac (first) or g += alpha / jac; jac = 0 adds nothing.
 hipError_t launch_density_add(double* g, const double* jac, double alpha, int64_t n, bool first, hipStream_t s);
 

@@ -158,3 +158,25 @@ def test_multichannel_density_matches_oracle(torch):
         assert np.all(r <= np.maximum(1e-12, 1000.0 * fe)), (chan, float(np.max(r / np.maximum(fe, 1e-15))))
         assert np.median(r) < 1e-12
     ctx.close()
+
+
+@pytest.mark.parametrize("n", [0, 1, 1023, 1025, 100003])
+def test_unweighting_matches_oracle(torch, n):
+    """Kept indices, count and unit weights bit-identical to the oracle's on
+    the same weights and the same Philox stream."""
+    from paper_2602_06895_amd import Context
+
+    rng = np.random.default_rng(n)
+    w = rng.exponential(1.0, n) ** 3
+    w[rng.random(n) < 0.3] = 0.0
+    w_max = float(np.quantile(w, 0.99)) if n else 1.0
+    ctx = Context(W.c1_ee_mumu())
+    out = ctx.unweight(torch.from_numpy(w).cuda(), w_max, seed=5, stream_id=7, counter_offset=11)
+    torch.cuda.synchronize()
+    u = W.philox_uniforms(5, 7, 11, n, 1)[0] if n else np.zeros(0)
+    ref = oracle.unweight(w, w_max, u)
+    k = int(out["count"].cpu()[0])
+    assert k == ref["keep"].size
+    assert np.array_equal(out["keep"][:k].cpu().numpy(), ref["keep"])
+    assert np.array_equal(out["uw"][:k].cpu().numpy(), ref["uw"])
+    ctx.close()

@@ -168,3 +168,35 @@ def test_single_channel_density_is_the_inverse_jacobian():
     r = g * out["jac"]
     # measured: median 5e-12, p99 1.7e-10 (Breit-Wigner factors near the poles)
     assert np.median(np.abs(r - 1.0)) < 1e-10 and np.quantile(np.abs(r - 1.0), 0.99) < 1e-8
+
+
+def _weights(n, seed):
+    rng = np.random.default_rng(seed)
+    w = rng.exponential(1.0, n) ** 3
+    w[rng.random(n) < 0.3] = 0.0  # cut events
+    return w
+
+
+def test_unweighting_extremes():
+    w = np.array([0.0, 2.0, 5.0, 0.0, 3.0])
+    u = W.philox_uniforms(1, 2, 0, 5, 1)[0]
+    out = oracle.unweight(w, 2.0, u)
+    assert list(out["keep"]) == [1, 2, 4]  # w >= w_max: always kept (u < 1)
+    assert np.array_equal(out["uw"], [1.0, 2.5, 1.5])
+    assert oracle.unweight(np.zeros(5), 1.0, u)["keep"].size == 0
+
+
+def test_unweighting_is_unbiased():
+    """Kept count ~ sum min(1, w / w_max), and w_max sum(unit weights) / N
+    estimates mean(w) (also with overweight events), within 5 sigma."""
+    n = 400000
+    w = _weights(n, 3)
+    w_max = np.quantile(w, 0.995)
+    u = W.philox_uniforms(9, 1, 0, n, 1)[0]
+    out = oracle.unweight(w, w_max, u)
+    p = np.minimum(1.0, w / w_max)
+    assert abs(out["keep"].size - p.sum()) < 5 * np.sqrt((p * (1 - p)).sum())
+    est = w_max * out["uw"].sum() / n
+    sig = w_max * np.sqrt((p * (1 - p) * np.maximum(1.0, w / w_max) ** 2).sum()) / n
+    assert abs(est - w.mean()) < 5 * sig
+    assert np.all(np.diff(out["keep"]) > 0)

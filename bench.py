@@ -442,6 +442,9 @@ def main():
         eff_w[off:off + k] *= N / float(k)
         off += int(k)
     eff, wmax = ctx.unweight_eff(eff_w, 1e-3)
+    # the unweighting step itself on the same events (not in the timed step)
+    unw_ms = _timed(lambda: ctx.unweight(eff_w, wmax, seed=3, stream_id=99), 5)
+    kept = int(ctx.unweight(eff_w, wmax, seed=3, stream_id=99)["count"].cpu()[0])
 
     avg_launch_s = float(np.mean(launch_ms)) / 1e3
     achieved = BYTES_PER_EVENT * N / avg_launch_s / 1e9
@@ -467,6 +470,8 @@ def main():
         "pass_cut_fraction": pass_frac,
         "unweighting_eff": eff,
         "passing_events_per_s": N * pass_frac / (ms_per_step / 1e3),
+        "unweighting": {"w_max_overweight": 1e-3, "kept": kept, "ms": unw_ms,
+                        "events_per_s": N / (unw_ms / 1e3)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(),
                      "kernel": "k_sample (fused multichannel sample)",

@@ -268,6 +268,49 @@ msx_status msx_set_grid(msx_ctx* ctx, int32_t channel, const double* edges);
 msx_status msx_unweight_eff(msx_ctx* ctx, const double* w, int64_t n, double overweight,
                             double* eff, double* w_max, void* stream);
 
+/* Observables of lab-frame events (the distributions of the paper's section
+ * 4.2: a partonic invariant mass, the transverse momentum of the hardest jet,
+ * the separation of the two hardest jets).  An observable is four int32:
+ * (kind, set, rank, 0), set a bitmask of final-state particle labels (bit i =
+ * particle i, p index i + 2).  Kinds on the summed momentum of the set:
+ * MSX_OBS_E energy, MSX_OBS_PT transverse momentum, MSX_OBS_ETA
+ * pseudorapidity asinh(p_z / p_T), MSX_OBS_PHI azimuth atan2(p_y, p_x),
+ * MSX_OBS_M invariant mass sqrt(max(E^2 - p^2, 0)); on the members of the
+ * set ordered by p_T (descending, lower label first on ties):
+ * MSX_OBS_PT_RANK the p_T of the rank-th hardest (0 = hardest),
+ * MSX_OBS_DR_HARDEST the separation sqrt(d_eta^2 + d_phi^2) of the two
+ * hardest (d_phi wrapped into [0, pi]).  */
+enum {
+    MSX_OBS_E = 0,
+    MSX_OBS_PT = 1,
+    MSX_OBS_ETA = 2,
+    MSX_OBS_PHI = 3,
+    MSX_OBS_M = 4,
+    MSX_OBS_PT_RANK = 5,
+    MSX_OBS_DR_HARDEST = 6
+};
+
+/* k (1..8) observables of n events of process `process`: spec [4 k] int32
+ * (host), p [4][np][n] (device, lab frame as msx_map / msx_sample write it),
+ * out [k][n] (device).  n = 0 is a no-op. */
+msx_status msx_observables(msx_ctx* ctx, int32_t process, int64_t n, const double* p, const int32_t* spec, int32_t k,
+                           double* out, void* stream);
+
+/* General cut: w[e] := 0 unless lo[j] <= x[j][e] < hi[j] for every j < k
+ * (1..8); x [k][n] observables (device, e.g. from msx_observables), lo, hi
+ * [k] (host; +-inf for open ends), w [n] (device, in place). */
+msx_status msx_cut(msx_ctx* ctx, int64_t n, const double* x, int32_t k, const double* lo, const double* hi, double* w,
+                   void* stream);
+
+/* Weighted histogram of x [n] with weights w [n] (device): hist [2][bins]
+ * (device) = (sum w, sum w^2) over the events in each of `bins` (1..4096)
+ * equal bins of [lo, hi), bin = floor((x - lo) bins / (hi - lo)); events
+ * outside [lo, hi) are not counted.  Deterministic (fixed summation order for
+ * a given n).  Uses a context-owned scratch of 2 bins ceil(n / 2048) doubles
+ * (grown on demand: a call that grows it synchronizes the device). */
+msx_status msx_histogram(msx_ctx* ctx, int64_t n, const double* x, const double* w, int32_t bins, double lo, double hi,
+                         double* hist, void* stream);
+
 /* Hit-or-miss unweighting of weights w [n] >= 0 (device) against a maximum
  * weight w_max > 0 (section 3.4.1: the channel-wise files are unweighted with
  * the current estimate of the maximum weight, at the end once more with the

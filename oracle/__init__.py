@@ -94,6 +94,83 @@ def lib(variant: str = "ref"):
     return _libs[variant]
 
 
+OBS_E, OBS_PT, OBS_ETA, OBS_PHI, OBS_M, OBS_PT_RANK, OBS_DR_HARDEST = range(7)
+
+
+def observables(p: np.ndarray, spec) -> np.ndarray:
+    """Observables of lab-frame events p [4][np][n] (final-state particle i
+    at index i + 2) for spec = [(kind, labels, rank), ...] (the distributions
+    of section 4.2): energy, transverse momentum, pseudorapidity asinh(p_z /
+    p_T), azimuth and invariant mass of the summed momentum of the labels;
+    p_T of the rank-th hardest label (p_T descending, lower label first on
+    ties) and the separation sqrt(d_eta^2 + d_phi^2) of the two hardest."""
+    p = np.asarray(p, np.float64)
+    n = p.shape[2]
+    out = np.empty((len(spec), n))
+    for j, (kind, labels, rank) in enumerate(spec):
+        labels = sorted(labels)
+        if kind in (OBS_PT_RANK, OBS_DR_HARDEST):
+            pts = np.array([np.sqrt(p[1, q + 2] ** 2 + p[2, q + 2] ** 2) for q in labels])  # [m][n]
+            # stable order: p_T descending, lower label first on equal p_T
+            order = np.argsort(-pts, axis=0, kind="stable")
+            if kind == OBS_PT_RANK:
+                out[j] = np.take_along_axis(pts, order[rank:rank + 1], axis=0)[0] if rank < len(labels) else 0.0
+                continue
+            a = np.array(labels)[order[0]]
+            b = np.array(labels)[order[1]]
+            idx = np.arange(n)
+
+            def eta(q):
+                px, py, pz = p[1, q + 2, idx], p[2, q + 2, idx], p[3, q + 2, idx]
+                return np.arcsinh(pz / np.sqrt(px * px + py * py))
+
+            dphi = np.abs(np.arctan2(p[2, a + 2, idx], p[1, a + 2, idx]) - np.arctan2(p[2, b + 2, idx], p[1, b + 2, idx]))
+            dphi = np.where(dphi > np.pi, 2.0 * np.pi - dphi, dphi)
+            deta = eta(a) - eta(b)
+            out[j] = np.sqrt(deta * deta + dphi * dphi)
+            continue
+        E = np.zeros(n)
+        X = np.zeros(n)
+        Y = np.zeros(n)
+        Z = np.zeros(n)
+        for q in labels:
+            E = E + p[0, q + 2]
+            X = X + p[1, q + 2]
+            Y = Y + p[2, q + 2]
+            Z = Z + p[3, q + 2]
+        pt = np.sqrt(X * X + Y * Y)
+        if kind == OBS_E:
+            out[j] = E
+        elif kind == OBS_PT:
+            out[j] = pt
+        elif kind == OBS_ETA:
+            out[j] = np.arcsinh(Z / pt)
+        elif kind == OBS_PHI:
+            out[j] = np.arctan2(Y, X)
+        else:
+            out[j] = np.sqrt(np.maximum(E * E - X * X - Y * Y - Z * Z, 0.0))
+    return out
+
+
+def cut(x: np.ndarray, lo, hi, w: np.ndarray) -> np.ndarray:
+    """w with every event outside lo[j] <= x[j] < hi[j] (any j) set to 0."""
+    x = np.asarray(x, np.float64)
+    keep = np.all((x >= np.asarray(lo)[:, None]) & (x < np.asarray(hi)[:, None]), axis=0)
+    return np.where(keep, w, 0.0)
+
+
+def histogram(x: np.ndarray, w: np.ndarray, bins: int, lo: float, hi: float) -> np.ndarray:
+    """[2][bins]: sum w and sum w^2 per equal bin of [lo, hi), bin =
+    floor((x - lo) bins / (hi - lo)); events outside [lo, hi) not counted."""
+    x = np.asarray(x, np.float64)
+    w = np.asarray(w, np.float64)
+    inside = (x >= lo) & (x < hi)
+    scale = bins / (hi - lo)
+    b = np.clip(np.floor((x[inside] - lo) * scale).astype(np.int64), 0, bins - 1)
+    wi = w[inside]
+    return np.stack([np.bincount(b, weights=wi, minlength=bins), np.bincount(b, weights=wi * wi, minlength=bins)])
+
+
 def unweight(w: np.ndarray, w_max: float, u: np.ndarray) -> dict:
     """Hit-or-miss unweighting (section 3.4.1): event i is kept when
     u_i w_max < w_i (u: the uniforms drawn for the decision, passed in) and

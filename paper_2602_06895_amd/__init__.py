@@ -29,7 +29,9 @@ EXPORTS = ["msx_last_error", "msx_create_channels", "msx_destroy", "msx_get_meta
            "msx_flow_set_params", "msx_flow_get_params", "msx_flow_forward", "msx_flow_inverse",
            "msx_flow_gradient", "msx_flow_train_step", "msx_flow_sample", "msx_sample_device",
            "msx_sample_graph_create", "msx_graph_launch", "msx_graph_destroy", "msx_set_launch", "msx_autotune",
-           "msx_inverse_map", "msx_multichannel_density", "msx_unweight"]
+           "msx_inverse_map", "msx_multichannel_density", "msx_unweight", "msx_observables", "msx_cut",
+           "msx_histogram"]
+OBS_E, OBS_PT, OBS_ETA, OBS_PHI, OBS_M, OBS_PT_RANK, OBS_DR_HARDEST = range(7)
 FLOW_BF16, FLOW_FP32 = 0, 1
 
 
@@ -61,6 +63,9 @@ def load_library(path: str = LIB_PATH):
         "msx_inverse_map": ([vp, i32, i64, vp, vp, vp, vp, vp], C.c_int),
         "msx_multichannel_density": ([vp, i32, i64, vp, vp, vp, vp, vp], C.c_int),
         "msx_unweight": ([vp, vp, i64, C.c_double, C.c_uint64, C.c_uint64, C.c_uint64, vp, vp, vp, vp], C.c_int),
+        "msx_observables": ([vp, i32, i64, vp, vp, i32, vp, vp], C.c_int),
+        "msx_cut": ([vp, i64, vp, i32, vp, vp, vp, vp], C.c_int),
+        "msx_histogram": ([vp, i64, vp, vp, i32, C.c_double, C.c_double, vp, vp], C.c_int),
         "msx_weight": ([vp, i32, i64, vp, vp, vp, vp, vp, vp], C.c_int),
         "msx_sample": ([vp, vp, u64, u64, u64, vp, vp, vp, vp, vp], C.c_int),
         "msx_stats": ([vp, vp, vp], C.c_int),
@@ -197,6 +202,39 @@ class Context:
         out = {"y": self._empty(self.dims[channel], n), "jac": self._empty(n) if jac else None}
         self._check(self.L.msx_inverse_map(self.h, channel, n, _ptr(p), _ptr(x1x2), _ptr(out["y"]),
                                            _ptr(out["jac"]), self._stream()))
+        return out
+
+    def observables(self, process: int, p, spec):
+        """spec: list of (kind, particle labels, rank); returns [k][n] values."""
+        rows = []
+        for kind, labels, rank in spec:
+            m = 0
+            for q in labels:
+                m |= 1 << q
+            rows += [kind, m, rank, 0]
+        a = np.ascontiguousarray(rows, dtype=np.int32)
+        k = len(spec)
+        n = p.shape[2]
+        out = self._empty(k, n)
+        p = p.contiguous()
+        self._check(self.L.msx_observables(self.h, process, n, _ptr(p), a.ctypes.data_as(C.c_void_p), k, _ptr(out),
+                                           self._stream()))
+        return out
+
+    def cut(self, x, lo, hi, w):
+        """w[e] = 0 unless lo[j] <= x[j][e] < hi[j] for all j (in place)."""
+        lo = np.ascontiguousarray(lo, dtype=np.float64)
+        hi = np.ascontiguousarray(hi, dtype=np.float64)
+        x = x.contiguous()
+        self._check(self.L.msx_cut(self.h, x.shape[1], _ptr(x), x.shape[0], lo.ctypes.data_as(C.c_void_p),
+                                   hi.ctypes.data_as(C.c_void_p), _ptr(w), self._stream()))
+        return w
+
+    def histogram(self, x, w, bins: int, lo: float, hi: float):
+        """[2][bins] (sum w, sum w^2) of x over equal bins of [lo, hi)."""
+        out = self._empty(2, bins)
+        self._check(self.L.msx_histogram(self.h, x.shape[0], _ptr(x.contiguous()), _ptr(w.contiguous()), bins,
+                                         float(lo), float(hi), _ptr(out), self._stream()))
         return out
 
     def unweight(self, w, w_max: float, seed: int, stream_id: int = 0, counter_offset: int = 0):

@@ -41,6 +41,8 @@ struct msx_ctx {
     double* d_tile = nullptr;
     int64_t tile_cap = 0;
     double* d_vpart = nullptr;
+    double* d_obs_hist = nullptr;  // observable histogram partials
+    int64_t obs_hist_cap = 0;
     int64_t* d_ublk = nullptr;  // unweighting block offsets
     int64_t ublk_cap = 0;
     double* d_inv = nullptr;  // multichannel density scratch: y [max dims][n] then jac [n]
@@ -97,7 +99,7 @@ hipError_t dmalloc(T** p, size_t count) {
 void free_all(msx_ctx* c) {
     void* ptrs[] = {c->d_chans, c->d_procs, c->d_grids, c->d_hist, c->d_stats, c->d_grid_off, c->d_chan_nb,
                     c->d_row_nb, c->d_row_grid, c->d_row_hist, c->d_tile, c->d_vpart, c->d_unw, c->d_call,
-                    c->d_inv, c->d_ublk};
+                    c->d_inv, c->d_ublk, c->d_obs_hist};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -703,6 +705,63 @@ msx_status msx_set_grid(msx_ctx* ctx, int32_t channel, const double* edges) {
             hipMemcpy(ctx->d_grids + ctx->grid_off[channel], edges, sizeof(double) * m.dims * (m.nbins + 1),
                       hipMemcpyHostToDevice),
             "grid copy");
+    return MSX_OK;
+}
+
+msx_status msx_observables(msx_ctx* ctx, int32_t process, int64_t n, const double* p, const int32_t* spec, int32_t k,
+                           double* out, void* stream) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (process < 0 || process >= (int32_t)ctx->comp.procs.size())
+        return fail(ctx, MSX_ERR_ARG, "process index out of range");
+    if (n < 0) return fail(ctx, MSX_ERR_ARG, "n < 0");
+    if (k < 1 || k > 8 || !spec) return fail(ctx, MSX_ERR_ARG, "1 to 8 observables are required");
+    const int nf = ctx->comp.procs[process].n_final;
+    for (int j = 0; j < k; ++j) {
+        const int kind = spec[4 * j];
+        const uint32_t set = (uint32_t)spec[4 * j + 1];
+        if (kind < MSX_OBS_E || kind > MSX_OBS_DR_HARDEST) return fail(ctx, MSX_ERR_ARG, "unknown observable kind");
+        if (set == 0 || (nf < 32 && (set >> nf) != 0)) return fail(ctx, MSX_ERR_ARG, "observable particle set out of range");
+        if (kind == MSX_OBS_PT_RANK && (spec[4 * j + 2] < 0 || spec[4 * j + 2] >= nf))
+            return fail(ctx, MSX_ERR_ARG, "rank out of range");
+    }
+    if (n > 0 && (!p || !out)) return fail(ctx, MSX_ERR_ARG, "p and out are required");
+    if (n == 0) return MSX_OK;
+    if (msx_status st = set_device(ctx)) return st;
+    MSX_HIP(ctx, launch_observables(p, nf + 2, n, spec, k, out, (hipStream_t)stream), "observables launch");
+    return MSX_OK;
+}
+
+msx_status msx_cut(msx_ctx* ctx, int64_t n, const double* x, int32_t k, const double* lo, const double* hi, double* w,
+                   void* stream) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (n < 0) return fail(ctx, MSX_ERR_ARG, "n < 0");
+    if (k < 1 || k > 8 || !lo || !hi) return fail(ctx, MSX_ERR_ARG, "1 to 8 cut ranges are required");
+    if (n > 0 && (!x || !w)) return fail(ctx, MSX_ERR_ARG, "x and w are required");
+    if (n == 0) return MSX_OK;
+    if (msx_status st = set_device(ctx)) return st;
+    MSX_HIP(ctx, launch_cut(x, k, n, lo, hi, w, (hipStream_t)stream), "cut launch");
+    return MSX_OK;
+}
+
+msx_status msx_histogram(msx_ctx* ctx, int64_t n, const double* x, const double* w, int32_t bins, double lo, double hi,
+                         double* hist, void* stream) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (n < 0) return fail(ctx, MSX_ERR_ARG, "n < 0");
+    if (bins < 1 || bins > 4096) return fail(ctx, MSX_ERR_ARG, "bins must be 1..4096");
+    if (!(hi > lo) || !std::isfinite(lo) || !std::isfinite(hi)) return fail(ctx, MSX_ERR_ARG, "need finite lo < hi");
+    if (!hist || (n > 0 && (!x || !w))) return fail(ctx, MSX_ERR_ARG, "x, w and hist are required");
+    if (msx_status st = set_device(ctx)) return st;
+    const int64_t need = histogram_blocks(n) * 2 * (int64_t)bins;
+    if (need > ctx->obs_hist_cap) {
+        // the previous scratch may still be read by work in flight
+        MSX_HIP(ctx, hipDeviceSynchronize(), "synchronize");
+        if (ctx->d_obs_hist) MSX_HIP(ctx, hipFree(ctx->d_obs_hist), "hipFree");
+        ctx->d_obs_hist = nullptr;
+        ctx->obs_hist_cap = 0;
+        MSX_HIP(ctx, dmalloc(&ctx->d_obs_hist, need), "histogram scratch");
+        ctx->obs_hist_cap = need;
+    }
+    MSX_HIP(ctx, launch_histogram(x, w, n, bins, lo, hi, ctx->d_obs_hist, hist, (hipStream_t)stream), "histogram launch");
     return MSX_OK;
 }
 

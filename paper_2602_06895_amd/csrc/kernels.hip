@@ -199,6 +199,180 @@ __global__ __launch_bounds__(kBlock) void k_unw_write(const double* __restrict__
     }
 }
 
+// ---------------------------------------------------------------------------
+// Observables, cuts and weighted histograms of lab-frame events
+// ---------------------------------------------------------------------------
+struct ObsK {
+    int32_t kind;   // MSX_OBS_* of msx.h
+    uint32_t set;   // final-state particle labels
+    int32_t rank;   // MSX_OBS_PT_RANK: 0 = hardest
+    int32_t pad;
+};
+constexpr int kObsE = 0, kObsPt = 1, kObsEta = 2, kObsPhi = 3, kObsM = 4, kObsPtRank = 5, kObsDrHardest = 6;
+constexpr int kObsMaxFinal = 16;
+
+__device__ __forceinline__ double pt_of(double px, double py) { return sqrt(px * px + py * py); }
+__device__ __forceinline__ double eta_of(double px, double py, double pz) { return asinh(pz / pt_of(px, py)); }
+
+// The two hardest particles of `set` (pT descending, lower label first on
+// ties): their labels; rank-th hardest pT.
+__device__ __forceinline__ void hardest(const double* __restrict__ p, int np, int64_t n, int64_t e, uint32_t set,
+                                        int rank, double& pt_rank, int& a, int& b) {
+    a = -1;
+    b = -1;
+    double pa = -1.0, pb = -1.0;
+    pt_rank = 0.0;
+    // selection of the rank-th largest by counting: pT_i is the rank-th hardest
+    // when exactly rank particles are harder (or as hard with a lower label)
+    for (int i = 0; i < np - 2; ++i) {
+        if (!(set & (1u << i))) continue;
+        const double pi = pt_of(p[((int64_t)1 * np + i + 2) * n + e], p[((int64_t)2 * np + i + 2) * n + e]);
+        if (pi > pa) {
+            pb = pa;
+            b = a;
+            pa = pi;
+            a = i;
+        } else if (pi > pb) {
+            pb = pi;
+            b = i;
+        }
+        int harder = 0;
+        for (int j = 0; j < np - 2; ++j) {
+            if (j == i || !(set & (1u << j))) continue;
+            const double pj = pt_of(p[((int64_t)1 * np + j + 2) * n + e], p[((int64_t)2 * np + j + 2) * n + e]);
+            if (pj > pi || (pj == pi && j < i)) ++harder;
+        }
+        if (harder == rank) pt_rank = pi;
+    }
+}
+
+__device__ double obs_value(const ObsK& o, const double* __restrict__ p, int np, int64_t n, int64_t e) {
+    if (o.kind == kObsPtRank || o.kind == kObsDrHardest) {
+        double ptr;
+        int a, b;
+        hardest(p, np, n, e, o.set, o.rank, ptr, a, b);
+        if (o.kind == kObsPtRank) return ptr;
+        if (a < 0 || b < 0) return 0.0;
+        const double ax = p[((int64_t)1 * np + a + 2) * n + e], ay = p[((int64_t)2 * np + a + 2) * n + e],
+                     az = p[((int64_t)3 * np + a + 2) * n + e];
+        const double bx = p[((int64_t)1 * np + b + 2) * n + e], by = p[((int64_t)2 * np + b + 2) * n + e],
+                     bz = p[((int64_t)3 * np + b + 2) * n + e];
+        const double deta = eta_of(ax, ay, az) - eta_of(bx, by, bz);
+        double dphi = fabs(atan2(ay, ax) - atan2(by, bx));
+        if (dphi > kPiD) dphi = 2.0 * kPiD - dphi;
+        return sqrt(deta * deta + dphi * dphi);
+    }
+    double E = 0.0, X = 0.0, Y = 0.0, Z = 0.0;
+    for (int i = 0; i < np - 2; ++i) {
+        if (!(o.set & (1u << i))) continue;
+        E += p[((int64_t)0 * np + i + 2) * n + e];
+        X += p[((int64_t)1 * np + i + 2) * n + e];
+        Y += p[((int64_t)2 * np + i + 2) * n + e];
+        Z += p[((int64_t)3 * np + i + 2) * n + e];
+    }
+    switch (o.kind) {
+        case kObsE: return E;
+        case kObsPt: return pt_of(X, Y);
+        case kObsEta: return eta_of(X, Y, Z);
+        case kObsPhi: return atan2(Y, X);
+        default: return sqrt(fmax(E * E - X * X - Y * Y - Z * Z, 0.0));
+    }
+}
+
+struct ObsList {
+    ObsK o[8];
+};
+
+__global__ __launch_bounds__(kBlock) void k_observables(const double* __restrict__ p, int np, int64_t n, ObsList ol,
+                                                        int k, double* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    for (int j = 0; j < k; ++j) out[(int64_t)j * n + e] = obs_value(ol.o[j], p, np, n, e);
+}
+
+struct CutList {
+    double lo[8], hi[8];
+};
+
+// w[e] = 0 unless lo_j <= x[j][e] < hi_j for every observable j.
+__global__ __launch_bounds__(kBlock) void k_cut(const double* __restrict__ x, int k, int64_t n, CutList cl,
+                                                double* __restrict__ w) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    bool pass = true;
+    for (int j = 0; j < k; ++j) {
+        const double v = x[(int64_t)j * n + e];
+        pass = pass && v >= cl.lo[j] && v < cl.hi[j];
+    }
+    if (!pass) w[e] = 0.0;
+}
+
+// Weighted histogram, deterministic: a workgroup takes kHistPer consecutive
+// events, stages (bin, w) in LDS, and thread t sums the events of bins t,
+// t + 256, ... in event order; partials [block][2][nb] are then added over
+// blocks in a fixed order.  bin = floor((x - lo) * scale), events with
+// x outside [lo, hi) skipped.
+constexpr int kHistPer = 2048;
+
+__global__ __launch_bounds__(kBlock) void k_hist_block(const double* __restrict__ x, const double* __restrict__ w,
+                                                       int64_t n, int nb, double lo, double hi, double scale,
+                                                       double* __restrict__ part) {
+    __shared__ int sb[kHistPer];
+    __shared__ double sw[kHistPer];
+    const int64_t e0 = (int64_t)blockIdx.x * kHistPer;
+    const int cnt = (int)min<int64_t>(kHistPer, n - e0);
+    for (int i = threadIdx.x; i < kHistPer; i += blockDim.x) {
+        int b = -1;
+        double wv = 0.0;
+        if (i < cnt) {
+            const double v = x[e0 + i];
+            wv = w[e0 + i];
+            if (v >= lo && v < hi) {
+                b = (int)floor((v - lo) * scale);
+                b = b < 0 ? 0 : (b > nb - 1 ? nb - 1 : b);
+            }
+        }
+        sb[i] = b;
+        sw[i] = wv;
+    }
+    __syncthreads();
+    for (int bin = threadIdx.x; bin < nb; bin += blockDim.x) {
+        double s1 = 0.0, s2 = 0.0;
+        for (int i = 0; i < cnt; ++i) {
+            if (sb[i] == bin) {
+                const double wv = sw[i];
+                s1 += wv;
+                s2 += wv * wv;
+            }
+        }
+        part[((int64_t)blockIdx.x * 2 + 0) * nb + bin] = s1;
+        part[((int64_t)blockIdx.x * 2 + 1) * nb + bin] = s2;
+    }
+}
+
+// out[i] = sum over blocks z of part[z][i] (i < M), four waves over z = w,
+// w + 4, ... with four accumulators each, fixed combination order.
+__global__ __launch_bounds__(256) void k_reduce_blocks(const double* __restrict__ part, int64_t nz, int64_t M,
+                                                       double* __restrict__ out) {
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (i < M) {
+        int64_t z = wv;
+        for (; z + 12 < nz; z += 16) {
+            a0 += part[z * M + i];
+            a1 += part[(z + 4) * M + i];
+            a2 += part[(z + 8) * M + i];
+            a3 += part[(z + 12) * M + i];
+        }
+        for (; z < nz; z += 4) a0 += part[z * M + i];
+    }
+    red[wv][lane] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (wv == 0 && i < M) out[i] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+}
+
 // Global multichannel density: g += alpha / J of one channel (g = alpha / J
 // for the first channel).  A channel whose chain cuts the event (J = 0)
 // contributes nothing.
@@ -383,6 +557,46 @@ hipError_t launch_chain(int rc, int kc, int mixed, const ChainLaunch& a) {
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+
+hipError_t launch_observables(const double* p, int np, int64_t n, const int32_t* spec, int k, double* out,
+                              hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    ObsList ol{};
+    for (int j = 0; j < k; ++j) {
+        ol.o[j].kind = spec[4 * j];
+        ol.o[j].set = (uint32_t)spec[4 * j + 1];
+        ol.o[j].rank = spec[4 * j + 2];
+    }
+    const int64_t b = (n + kBlock - 1) / kBlock;
+    k_observables<<<dim3((unsigned)b), dim3(kBlock), 0, s>>>(p, np, n, ol, k, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_cut(const double* x, int k, int64_t n, const double* lo, const double* hi, double* w, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    CutList cl{};
+    for (int j = 0; j < k; ++j) {
+        cl.lo[j] = lo[j];
+        cl.hi[j] = hi[j];
+    }
+    const int64_t b = (n + kBlock - 1) / kBlock;
+    k_cut<<<dim3((unsigned)b), dim3(kBlock), 0, s>>>(x, k, n, cl, w);
+    return hipGetLastError();
+}
+
+int64_t histogram_blocks(int64_t n) { return std::max<int64_t>(1, (n + kHistPer - 1) / kHistPer); }
+
+hipError_t launch_histogram(const double* x, const double* w, int64_t n, int nb, double lo, double hi, double* part,
+                            double* out, hipStream_t s) {
+    const int64_t nz = histogram_blocks(n);
+    const double scale = nb / (hi - lo);
+    k_hist_block<<<dim3((unsigned)nz), dim3(kBlock), 0, s>>>(x, w, n, nb, lo, hi, scale, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t M = 2 * (int64_t)nb;
+    k_reduce_blocks<<<dim3((unsigned)((M + 63) / 64)), dim3(256), 0, s>>>(part, nz, M, out);
+    return hipGetLastError();
+}
 
 int64_t unweight_blocks(int64_t n) { return (n + kUnwPer - 1) / kUnwPer; }
 

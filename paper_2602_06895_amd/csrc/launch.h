@@ -58,6 +58,18 @@ hipError_t launch_inverse(const ChannelTab* ct, const double* grid, int nb, int 
                           double s_lab, int np, int64_t n, const double* p, const double* x1x2, double* y, double* jac,
                           int cu_count, hipStream_t s);
 
+// Observables of lab-frame events: spec = k x (kind, set, rank, 0) int32;
+// out [k][n].  k <= 8.
+hipError_t launch_observables(const double* p, int np, int64_t n, const int32_t* spec, int k, double* out,
+                              hipStream_t s);
+// w[e] = 0 unless lo[j] <= x[j][e] < hi[j] for all j < k (k <= 8).
+hipError_t launch_cut(const double* x, int k, int64_t n, const double* lo, const double* hi, double* w, hipStream_t s);
+// Weighted histogram of x: out [2][nb] = (sum w, sum w^2) per bin of [lo, hi);
+// part: scratch of histogram_blocks(n) x 2 nb doubles.
+int64_t histogram_blocks(int64_t n);
+hipError_t launch_histogram(const double* x, const double* w, int64_t n, int nb, double lo, double hi, double* part,
+                            double* out, hipStream_t s);
+
 // Hit-or-miss unweighting: kept indices (increasing) to keep, unit weights
 // max(1, w / w_max) to uw (optional), the number kept to count (device);
 // blk: scratch of unweight_blocks(n) (at least 1) int64.

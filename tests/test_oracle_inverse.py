@@ -200,3 +200,44 @@ def test_unweighting_is_unbiased():
     sig = w_max * np.sqrt((p * (1 - p) * np.maximum(1.0, w / w_max) ** 2).sum()) / n
     assert abs(est - w.mean()) < 5 * sig
     assert np.all(np.diff(out["keep"]) > 0)
+
+
+def _event(parts):
+    """p [4][n+2][1] from massless final-state particles given as (pT, eta, phi)."""
+    p = np.zeros((4, len(parts) + 2, 1))
+    for i, (pt, eta, phi) in enumerate(parts):
+        p[:, i + 2, 0] = [pt * np.cosh(eta), pt * np.cos(phi), pt * np.sin(phi), pt * np.sinh(eta)]
+    return p
+
+
+def test_observables_closed_forms():
+    O = oracle
+    p = _event([(40.0, 0.7, 1.0), (25.0, -1.2, -2.5), (60.0, 0.1, 3.0), (25.0, 2.0, 0.3)])
+    x = O.observables(p, [(O.OBS_PT, [0], 0), (O.OBS_ETA, [0], 0), (O.OBS_PHI, [0], 0),
+                          (O.OBS_PT_RANK, [0, 1, 2, 3], 0), (O.OBS_PT_RANK, [0, 1, 2, 3], 2),
+                          (O.OBS_PT_RANK, [0, 1, 2, 3], 3), (O.OBS_DR_HARDEST, [0, 1, 2, 3], 0),
+                          (O.OBS_E, [1], 0)])[:, 0]
+    assert x[0] == pytest.approx(40.0, rel=1e-15) and x[1] == pytest.approx(0.7, rel=1e-14)
+    assert x[2] == pytest.approx(1.0, rel=1e-15)
+    assert x[3] == pytest.approx(60.0, rel=1e-15) and x[4] == pytest.approx(25.0, rel=1e-15)
+    assert x[5] == pytest.approx(25.0, rel=1e-15)  # tie between labels 1 and 3
+    # two hardest: label 2 (eta 0.1, phi 3.0) and label 0 (eta 0.7, phi 1.0)
+    assert x[6] == pytest.approx(np.hypot(0.6, 2.0), rel=1e-14)
+    assert x[7] == pytest.approx(25.0 * np.cosh(-1.2), rel=1e-15)
+    # wrapped azimuth difference: phi 3.0 and -3.0 are 2 pi - 6 apart
+    q = _event([(30.0, 0.0, 3.0), (20.0, 0.0, -3.0)])
+    assert O.observables(q, [(O.OBS_DR_HARDEST, [0, 1], 0)])[0, 0] == pytest.approx(2 * np.pi - 6.0, rel=1e-13)
+    # back-to-back massless pair: invariant mass 2 E
+    b = _event([(50.0, 0.0, 0.4), (50.0, 0.0, 0.4 + np.pi)])
+    assert O.observables(b, [(O.OBS_M, [0, 1], 0)])[0, 0] == pytest.approx(100.0, rel=1e-13)
+
+
+def test_cut_and_histogram_closed_forms():
+    x = np.array([[0.0, 1.0, 2.0, 3.0, 4.0]])
+    w = np.ones(5)
+    assert list(oracle.cut(x, [1.0], [3.0], w)) == [0.0, 1.0, 1.0, 0.0, 0.0]  # [lo, hi)
+    xs = np.array([0.05, 0.15, 0.15, 0.95, 1.0, -0.01])
+    ws = np.array([1.0, 2.0, 3.0, 4.0, 5.0, 6.0])
+    h = oracle.histogram(xs, ws, 10, 0.0, 1.0)
+    assert h[0].tolist() == [1.0, 5.0, 0, 0, 0, 0, 0, 0, 0, 4.0]
+    assert h[1].tolist() == [1.0, 13.0, 0, 0, 0, 0, 0, 0, 0, 16.0]

@@ -88,6 +88,12 @@ def lib(variant: str = "ref"):
         L.orc_unmap_nu.argtypes = [C.c_double] * 5
         L.orc_unmap_bw.restype = C.c_double
         L.orc_unmap_bw.argtypes = [C.c_double] * 5
+        L.orc_rqf.restype = C.c_double
+        L.orc_rqf.argtypes = [C.c_double, C.c_double]
+        L.orc_rqf_inverse.restype = C.c_double
+        L.orc_rqf_inverse.argtypes = [C.c_double, C.c_double]
+        L.orc_rambo_ck.restype = C.c_double
+        L.orc_rambo_ck.argtypes = [C.c_int32]
         L.orc_vegas_unmap.restype = C.c_double
         L.orc_vegas_unmap.argtypes = [C.c_double, dp, C.c_int32]
         _libs[variant] = L
@@ -187,7 +193,8 @@ class _Channel(C.Structure):
                 ("kind", C.c_void_p), ("particle", C.c_void_p), ("parent", C.c_void_p),
                 ("child_start", C.c_void_p), ("child_count", C.c_void_p), ("children", C.c_void_p),
                 ("mass", C.c_void_p), ("width", C.c_void_p), ("nu", C.c_void_p),
-                ("t_order", C.c_char_p), ("s_order", C.c_void_p), ("dec_order", C.c_void_p)]
+                ("t_order", C.c_char_p), ("s_order", C.c_void_p), ("dec_order", C.c_void_p),
+                ("rambo", C.c_void_p)]
 
 
 class _Process(C.Structure):
@@ -216,6 +223,7 @@ class ChannelTree:
     def __init__(self, chan: dict, masses, nu: float):
         self.kind, self.particle, self.parent, self.children = [], [], [], []
         self.mass, self.width, self.nu, self.order = [], [], [], []
+        self.rambo = []  # FastRambo clusters: their particle count - 1, else 0
 
         def add(leg, parent):
             idx = len(self.kind)
@@ -231,6 +239,7 @@ class ChannelTree:
                 self.width.append(0.0)
                 self.nu.append(nu)
                 self.order.append(None)
+                self.rambo.append(0)
             else:
                 kids = leg["d"]
                 if len(kids) != 2:
@@ -241,8 +250,13 @@ class ChannelTree:
                 self.width.append(float(leg.get("w", 0.0)))
                 self.nu.append(float(leg.get("nu", nu)))
                 self.order.append(leg.get("order"))
+                self.rambo.append(-1 if leg.get("rambo") else 0)
                 for kid in kids:
                     self.children[idx].append(add(kid, idx))
+            if self.rambo[idx] < 0:
+                self.rambo[idx] = len(self.particles(idx)) - 1
+                if any(masses[q] != 0.0 for q in self.particles(idx)):
+                    raise ValueError("FastRambo clusters need massless particles")
             return idx
 
         if "t_chain" in chan:
@@ -257,6 +271,7 @@ class ChannelTree:
             self.width.append(0.0)
             self.nu.append(nu)
             self.order.append(None)
+            self.rambo.append(0)
             for leg in legs:
                 self.children[0].append(add(leg, 0))
             self.t_order = chan.get("t_order", "")
@@ -317,13 +332,13 @@ class ChannelTree:
             mass=np.array(self.mass, np.float64), width=np.array(self.width, np.float64),
             nu=np.array(self.nu, np.float64), s_order=np.array(self.s_order + [0], np.int32),
             dec_order=np.array(self.dec_order + [0], np.int32),
-            t_order=self.t_order.encode() + b"\0")
+            t_order=self.t_order.encode() + b"\0", rambo=np.array(self.rambo, np.int32))
         k = self._keep
         return _Channel(n, 0, len(self.s_order), len(self.dec_order),
                         _ptr(k["kind"]), _ptr(k["particle"]), _ptr(k["parent"]),
                         _ptr(k["child_start"]), _ptr(k["child_count"]), _ptr(k["children"]),
                         _ptr(k["mass"]), _ptr(k["width"]), _ptr(k["nu"]), k["t_order"],
-                        _ptr(k["s_order"]), _ptr(k["dec_order"]))
+                        _ptr(k["s_order"]), _ptr(k["dec_order"]), _ptr(k["rambo"]))
 
 
 def _mask(parts):

@@ -64,6 +64,7 @@ typedef struct {
     const char* t_order;        /* kappa-1 letters 'A'/'B' */
     const int32_t* s_order;     /* clusters other than the root, sampling order */
     const int32_t* dec_order;   /* clusters decayed with (phi,theta), parents first */
+    const int32_t* rambo;       /* FastRambo cluster: its particle count - 1 (k), else 0 */
 } orc_channel;
 
 typedef struct {
@@ -143,6 +144,51 @@ double orc_map_bw(double r, double m, double w, double xmin, double xmax, double
     double x = mw * tan(u1 + (u2 - u1) * r) + m2;
     *jac = (u2 - u1) * ((x - m2) * (x - m2) + mw * mw) / mw;
     return x;
+}
+
+/* FastRambo (section 2.2.9).  The single-bin rational-quadratic function
+ * with slope c at y = 0 and slope 0 at y = 1, and its closed-form inverse. */
+double orc_rqf(double y, double c)
+{
+    return (y * y + c * y * (1.0 - y)) / (1.0 + (c - 2.0) * y * (1.0 - y));
+}
+
+static double rqf_slope(double y, double c)
+{
+    double den = 1.0 + (c - 2.0) * y * (1.0 - y);
+    return (2.0 * y * (1.0 - y) + c * (1.0 - y) * (1.0 - y)) / (den * den);
+}
+
+double orc_rqf_inverse(double r, double c)
+{
+    double b = c - (c - 2.0) * r;
+    return 2.0 * r / (b + sqrt(b * b + 4.0 * r * (1.0 - b)));
+}
+
+/* The fitted slopes c_k* for k = 1..7 (table tab:rambo_fit). */
+double orc_rambo_ck(int32_t k)
+{
+    static const double ck[8] = {0.0, 2.0, 2.712001, 3.084521, 3.313073, 3.467512, 3.578833, 3.662872};
+    return (k >= 1 && k <= 7) ? ck[k] : 0.0;
+}
+
+/* Mass of the k + 1-particle massless cluster Q_i given its parent's
+ * invariant xmax = M_{i-1}^2: y = G_RQF^-1(r, c_k), M_i^2 = y^(1/k) M_{i-1}^2
+ * (M_i = u_i M_{i-1} with u_i^(2k) = y).  Jacobian dM_i^2/dr =
+ * M_{i-1}^2 (1/k) y^(1/k - 1) / g_RQF(y, c_k); with the decays' two-body
+ * factors it gives the mass measure of eq. mass_measure_rqs. */
+static double map_rambo(double r, int32_t k, double xmax, double* jac)
+{
+    double c = orc_rambo_ck(k);
+    double y = orc_rqf_inverse(r, c);
+    double yk = pow(y, 1.0 / k);
+    *jac = xmax * (yk / y) / k / rqf_slope(y, c);
+    return xmax * yk;
+}
+
+static double unmap_rambo(double x, int32_t k, double xmax)
+{
+    return orc_rqf(pow(x / xmax, (double)k), orc_rambo_ck(k));
 }
 
 /* Invariant of a propagator with mass m and width w: Breit-Wigner for w > 0,
@@ -485,8 +531,11 @@ static void event(const orc_process* pr, const orc_channel* ch, int32_t chan,
             mmin += node_m_min(ch, ch->children[ch->child_start[i] + c], sampled, s);
         double mmax = node_m_max(ch, i, sampled, s);
         double ji;
-        s[i] = map_invariant(r[k++], ch->mass[i], ch->width[i], ch->nu[i], pr->reg_a,
-                             mmin * mmin, mmax * mmax, &ji);
+        if (ch->rambo && ch->rambo[i] > 0)
+            s[i] = map_rambo(r[k++], ch->rambo[i], mmax * mmax, &ji);
+        else
+            s[i] = map_invariant(r[k++], ch->mass[i], ch->width[i], ch->nu[i], pr->reg_a,
+                                 mmin * mmin, mmax * mmax, &ji);
         sampled[i] = 1;
         ev->inv[i] = s[i];
         factors[nf++] = ji;
@@ -792,7 +841,10 @@ static int32_t inverse_event(const orc_process* pr, const orc_channel* ch, doubl
             mmin += node_m_min(ch, ch->children[ch->child_start[i] + c], sampled, s);
         double mmax = node_m_max(ch, i, sampled, s);
         s[i] = mdot(mom[i], mom[i]);
-        r[k++] = unmap_invariant(s[i], ch->mass[i], ch->width[i], ch->nu[i], pr->reg_a, mmin * mmin, mmax * mmax);
+        if (ch->rambo && ch->rambo[i] > 0)
+            r[k++] = unmap_rambo(s[i], ch->rambo[i], mmax * mmax);
+        else
+            r[k++] = unmap_invariant(s[i], ch->mass[i], ch->width[i], ch->nu[i], pr->reg_a, mmin * mmin, mmax * mmax);
         sampled[i] = 1;
     }
 

@@ -307,3 +307,14 @@ def flow_params(seed: int, dims: int, layers: int, bins: int, hidden: int, last_
                 lim = 1.0 / np.sqrt(fan_in)
                 out.append(rng.uniform(-lim, lim, n))
     return np.concatenate(out).astype(np.float32)
+
+
+def rambo_process(n: int, sqrt_s: float = 1000.0) -> dict:
+    """e+e- -> n massless particles at fixed sqrt(s) through one FastRambo
+    chain: Q_1 -> 1 + Q_2, Q_2 -> 2 + Q_3, ..., Q_{n-1} -> n-1 + n."""
+    leg = {"d": [n - 1, n], "rambo": True}
+    for q in range(n - 2, 0, -1):
+        leg = {"d": [q, leg], "rambo": True}
+    leg.pop("rambo")  # the root decays at s-hat
+    return {"name": f"rambo{n}", "sqrt_s": sqrt_s, "beams": "fixed", "masses": [0.0] * n, "nu": 0.8,
+            "regulator": 1e-3, "vegas_bins": 64, "integrand": {}, "channels": [{"s": leg}]}

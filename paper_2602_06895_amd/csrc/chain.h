@@ -92,7 +92,8 @@ enum : int {
     KIND_LOG = 4,      // nu = 1
     KIND_FLAT = 8,     // nu = 0
     KIND_BW = 16,      // Breit-Wigner
-    KINDS_ALL = 31
+    KIND_RAMBO = 32,   // FastRambo cluster masses
+    KINDS_ALL = 63
 };
 
 // Precision of the well-conditioned transcendentals (power laws, exp, log,
@@ -205,6 +206,20 @@ __device__ __forceinline__ double map_dyn(const MapParams& p, double r, double x
         jac = (u2 - u1) * (d * d + p.mw * p.mw) / p.mw;
         return d + p.m2;
     }
+    if ((KINDS & KIND_RAMBO) && kind == MAP_RAMBO) {
+        // FastRambo (section 2.2.9): y = G_RQF^-1(r, c_k) in closed form,
+        // M^2 = y^(1/k) M_parent^2 with M_parent^2 = xmax (massless cluster),
+        // dM^2/dr = xmax (1/k) y^(1/k - 1) / g_RQF(y, c_k).  FP64.
+        const double c = p.mw;
+        const double b = c - (c - 2.0) * r;
+        const double y = 2.0 * r / (b + sqrt(b * b + 4.0 * r * (1.0 - b)));
+        const double yk = p.int_pow == 1 ? y : kth_root<false>(y, p.int_pow, p.e);
+        const double om = y * (1.0 - y);
+        const double den = 1.0 + (c - 2.0) * om;
+        const double g = (2.0 * om + c * (1.0 - y) * (1.0 - y)) / (den * den);
+        jac = xmax * (yk / y) * p.e / g;
+        return xmax * yk;
+    }
     if ((KINDS & KIND_LOG) && kind == MAP_LOG) {
         double lmax = t_log<MIX>(xmax - p.m2), lmin = t_log<MIX>(xmin - p.m2);
         double xm = t_exp<MIX>(r * lmax + (1.0 - r) * lmin);
@@ -248,6 +263,10 @@ __device__ __forceinline__ double unmap_dyn(const MapParams& p, double x, double
     if ((KINDS & KIND_BW) && kind == MAP_BW) {
         const double u1 = atan((xmin - p.m2) / p.mw), u2 = atan((xmax - p.m2) / p.mw);
         return (atan((x - p.m2) / p.mw) - u1) / (u2 - u1);
+    }
+    if ((KINDS & KIND_RAMBO) && kind == MAP_RAMBO) {
+        const double y = ipow_any(x / xmax, p.int_pow), c = p.mw;
+        return (y * y + c * y * (1.0 - y)) / (1.0 + (c - 2.0) * y * (1.0 - y));
     }
     if ((KINDS & KIND_LOG) && kind == MAP_LOG) {
         const double lmax = log(xmax - p.m2), lmin = log(xmin - p.m2);

@@ -22,6 +22,7 @@ struct Node {
     int parent = -1;
     std::vector<int> kids;
     double m = 0.0, w = 0.0, nu = 0.0;
+    bool rambo = false;  // FastRambo cluster mass
     bool has_order = false;
     double order = 0.0;
     int slot = kNoSlot;
@@ -118,6 +119,7 @@ struct ChannelBuilder {
         nodes[idx].m = num_or(leg, "m", 0.0);
         nodes[idx].w = num_or(leg, "w", 0.0);
         nodes[idx].nu = num_or(leg, "nu", nu_default);
+        if (const JValue* rb = leg.get("rambo")) nodes[idx].rambo = rb->kind == JValue::BOOL && rb->b;
         if (nodes[idx].m < 0.0 || nodes[idx].w < 0.0 || (nodes[idx].w > 0.0 && nodes[idx].m <= 0.0)) {
             cx.fail("cluster mass/width must be >= 0 (a width needs a mass)");
             return -1;
@@ -301,6 +303,23 @@ bool compile_channel(Ctx& cx, const JValue& cj, const std::vector<double>& masse
             v = par;
         }
         iv.map = make_map(nodes[j].m, nodes[j].w, nodes[j].nu, reg_a);
+        if (nodes[j].rambo) {
+            // FastRambo (section 2.2.9, table tab:rambo_fit): slopes c_k*
+            static const double kRamboC[8] = {0.0, 2.0, 2.712001, 3.084521, 3.313073, 3.467512, 3.578833, 3.662872};
+            std::vector<int> ps;
+            b.particles(j, ps);
+            const int k = (int)ps.size() - 1;
+            if (k < 1 || k > 7) return cx.fail("a FastRambo cluster needs 2 to 8 particles");
+            for (int q : ps)
+                if (masses[q] != 0.0) return cx.fail("FastRambo clusters need massless particles");
+            MapParams rp{};
+            rp.kind = MAP_RAMBO;
+            rp.int_pow = k;
+            rp.e = 1.0 / k;
+            rp.inv_e = k;
+            rp.mw = kRamboC[k];
+            iv.map = rp;
+        }
         iv.set = b.pmask(j);
         iv.parent = nodes[v].inv;
         iv.min_const = fmin.c;
@@ -419,6 +438,7 @@ bool compile_channel(Ctx& cx, const JValue& cj, const std::vector<double>& masse
             case MAP_LOG: return 4;
             case MAP_FLAT: return 8;
             case MAP_BW: return 16;
+            case MAP_RAMBO: return 32;
             default: return 0;
         }
     };

@@ -36,7 +36,8 @@ enum MapKind : int32_t {
     MAP_FLAT = 1,   // nu = 0
     MAP_POW = 2,    // power law, nu != 0, 1
     MAP_LOG = 3,    // nu = 1
-    MAP_BW = 4      // Breit-Wigner
+    MAP_BW = 4,     // Breit-Wigner
+    MAP_RAMBO = 5   // FastRambo cluster mass (int_pow = k, e = 1/k, mw = c_k)
 };
 
 // Parameters of one G_nu / G_BW mapping.

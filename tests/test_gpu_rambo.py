@@ -1,0 +1,56 @@
+"""FastRambo channels (section 2.2.9) on the GPU against the oracle: per-event
+momenta and weights, the massless n-body volume, the inverse map."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from parity import compare
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    if not t.cuda.is_available():
+        pytest.skip("needs a GPU")
+    return t
+
+
+@pytest.mark.parametrize("n", [3, 5, 8])
+def test_fastrambo_matches_oracle(torch, n):
+    from paper_2602_06895_amd import Context
+
+    desc = W.rambo_process(n)
+    ctx = Context(desc)
+    orc = oracle.Process(desc)
+    d = ctx.dims[0]
+    y = W.philox_uniforms(13, n, 0, 20001, d)
+    out = ctx.map(0, torch.from_numpy(y).cuda(), weight=True)
+    torch.cuda.synchronize()
+    ref = orc.map(0, y, orc.uniform_grid(0))
+    fe = orc.forward_error(0, y, orc.uniform_grid(0), ref=ref)
+    got = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+    compare(got, ref, fe, hadronic=False, label=f"FastRambo n={n}")
+    ctx.close()
+
+
+@pytest.mark.parametrize("n", [4, 6])
+def test_fastrambo_volume_and_round_trip(torch, n):
+    from paper_2602_06895_amd import Context
+
+    ctx = Context(W.rambo_process(n))
+    y = ctx.uniform(4, n, 0, 1_000_000, ctx.dims[0])
+    out = ctx.map(0, y)
+    inv = ctx.inverse_map(0, out["p"], None)
+    torch.cuda.synchronize()
+    j = out["jac"].cpu().numpy()
+    V = (2 * math.pi) ** (4 - 3 * n) * (math.pi / 2) ** (n - 1) * 1e6 ** (n - 2) / (math.gamma(n) * math.gamma(n - 1))
+    assert abs(j.mean() - V) < 4.0 * j.std() / np.sqrt(j.size)
+    err = (inv["y"] - y).abs().amax(dim=0)
+    assert float(err.median()) < 1e-14 and float(err.max()) < 1e-8
+    ctx.close()

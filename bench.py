@@ -263,6 +263,37 @@ def inverse_report(n=10_000_000, reps=5, channel=0):
     return out
 
 
+def fastrambo_report(n_particles=6, n=10_000_000, reps=5):
+    """e+e- -> 6 massless particles at 1 TeV through one FastRambo chain
+    (f = 1, so the weights are the phase-space weights): fused sample
+    throughput and the spread of the weights around the volume.  Bytes per
+    event: momenta 8 x 4 x 8 + weight 8 + channel 4 = 268 B."""
+    import math
+
+    import torch
+
+    import workloads as W
+    from paper_2602_06895_amd import Context
+
+    ctx = Context(W.rambo_process(n_particles))
+    counts = np.array([n])
+    out = ctx.sample(counts, seed=6, stream_id=1)
+    ms = _timed(lambda: ctx.sample(counts, seed=6, stream_id=1, out=out), reps)
+    w = out["w"]
+    torch.cuda.synchronize()
+    mean, std = float(w.mean()), float(w.std())
+    k = n_particles
+    V = (2 * math.pi) ** (4 - 3 * k) * (math.pi / 2) ** (k - 1) * 1e6 ** (k - 2) / (math.gamma(k) * math.gamma(k - 1))
+    bpe = (k + 2) * 4 * 8 + 8 + 4
+    ach = n * bpe / (ms / 1e3) / 1e9
+    ctx.close()
+    return {"workload": f"e+e- -> {k} massless, sqrt(s) = 1 TeV, FastRambo, {n} events",
+            "events_per_s": n / (ms / 1e3), "ms": ms, "mean_weight_over_volume": mean / V,
+            "weight_std_over_mean": std / mean,
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "bytes_per_event": bpe}}
+
+
 def summarize(d: str, events: int, steps: int = 10):
     """Summary of the rocprofv3 runs under d (rocpd databases written by the
     commands printed below) for the last `steps` k_sample dispatches of
@@ -370,7 +401,7 @@ def main():
         print(json.dumps({"flow_vs_vegas": flow_report(train_steps=args.flow_steps)}))
         return
     if args.inverse_only:
-        print(json.dumps({"inverse_map": inverse_report()}))
+        print(json.dumps({"inverse_map": inverse_report(), "fastrambo": fastrambo_report()}))
         return
     if args.copy_calibration:
         import torch
@@ -507,6 +538,8 @@ def main():
         result["multichannel_graph"] = graph_report()
         torch.cuda.empty_cache()
         result["inverse_map"] = inverse_report()
+        torch.cuda.empty_cache()
+        result["fastrambo"] = fastrambo_report()
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(desc, grids, counts, seed=1)
     print(json.dumps(result))

@@ -255,8 +255,6 @@ class ChannelTree:
                     self.children[idx].append(add(kid, idx))
             if self.rambo[idx] < 0:
                 self.rambo[idx] = len(self.particles(idx)) - 1
-                if any(masses[q] != 0.0 for q in self.particles(idx)):
-                    raise ValueError("FastRambo clusters need massless particles")
             return idx
 
         if "t_chain" in chan:

@@ -172,23 +172,30 @@ double orc_rambo_ck(int32_t k)
     return (k >= 1 && k <= 7) ? ck[k] : 0.0;
 }
 
-/* Mass of the k + 1-particle massless cluster Q_i given its parent's
- * invariant xmax = M_{i-1}^2: y = G_RQF^-1(r, c_k), M_i^2 = y^(1/k) M_{i-1}^2
- * (M_i = u_i M_{i-1} with u_i^(2k) = y).  Jacobian dM_i^2/dr =
- * M_{i-1}^2 (1/k) y^(1/k - 1) / g_RQF(y, c_k); with the decays' two-body
- * factors it gives the mass measure of eq. mass_measure_rqs. */
-static double map_rambo(double r, int32_t k, double xmax, double* jac)
+/* Mass of the (k + 1)-particle cluster Q_i: y = G_RQF^-1(r, c_k), u = y^(1/2k)
+ * and M_i = mu_i + u (M_max - mu_i), with mu_i = sqrt(xmin) the sum of the
+ * cluster's masses and M_max = sqrt(xmax) = M_{i-1} - m_{i-1} (its parent's
+ * mass less its sibling's): for massless particles M_i = u_i M_{i-1}, the
+ * construction of section 2.2.9; with masses, the massless chain of
+ * K_i = M_i - mu_i.  Jacobian dM_i^2/dr = 2 M_i (M_max - mu_i) du/dr with
+ * du/dr = u / (2 k y g_RQF(y, c_k)); with the decays' two-body factors the
+ * product is the FastRambo mass measure (massive: with its reweighting). */
+static double map_rambo(double r, int32_t k, double xmin, double xmax, double* jac)
 {
     double c = orc_rambo_ck(k);
     double y = orc_rqf_inverse(r, c);
-    double yk = pow(y, 1.0 / k);
-    *jac = xmax * (yk / y) / k / rqf_slope(y, c);
-    return xmax * yk;
+    double u = pow(y, 0.5 / k);
+    double lo = sqrt(xmin), hi = sqrt(xmax);
+    double m = lo + u * (hi - lo);
+    *jac = 2.0 * m * (hi - lo) * u / (2.0 * k * y * rqf_slope(y, c));
+    return m * m;
 }
 
-static double unmap_rambo(double x, int32_t k, double xmax)
+static double unmap_rambo(double x, int32_t k, double xmin, double xmax)
 {
-    return orc_rqf(pow(x / xmax, (double)k), orc_rambo_ck(k));
+    double lo = sqrt(xmin), hi = sqrt(xmax);
+    double u = (sqrt(x) - lo) / (hi - lo);
+    return orc_rqf(pow(u, 2.0 * k), orc_rambo_ck(k));
 }
 
 /* Invariant of a propagator with mass m and width w: Breit-Wigner for w > 0,
@@ -532,7 +539,7 @@ static void event(const orc_process* pr, const orc_channel* ch, int32_t chan,
         double mmax = node_m_max(ch, i, sampled, s);
         double ji;
         if (ch->rambo && ch->rambo[i] > 0)
-            s[i] = map_rambo(r[k++], ch->rambo[i], mmax * mmax, &ji);
+            s[i] = map_rambo(r[k++], ch->rambo[i], mmin * mmin, mmax * mmax, &ji);
         else
             s[i] = map_invariant(r[k++], ch->mass[i], ch->width[i], ch->nu[i], pr->reg_a,
                                  mmin * mmin, mmax * mmax, &ji);
@@ -842,7 +849,7 @@ static int32_t inverse_event(const orc_process* pr, const orc_channel* ch, doubl
         double mmax = node_m_max(ch, i, sampled, s);
         s[i] = mdot(mom[i], mom[i]);
         if (ch->rambo && ch->rambo[i] > 0)
-            r[k++] = unmap_rambo(s[i], ch->rambo[i], mmax * mmax);
+            r[k++] = unmap_rambo(s[i], ch->rambo[i], mmin * mmin, mmax * mmax);
         else
             r[k++] = unmap_invariant(s[i], ch->mass[i], ch->width[i], ch->nu[i], pr->reg_a, mmin * mmin, mmax * mmax);
         sampled[i] = 1;

@@ -208,17 +208,20 @@ __device__ __forceinline__ double map_dyn(const MapParams& p, double r, double x
     }
     if ((KINDS & KIND_RAMBO) && kind == MAP_RAMBO) {
         // FastRambo (section 2.2.9): y = G_RQF^-1(r, c_k) in closed form,
-        // M^2 = y^(1/k) M_parent^2 with M_parent^2 = xmax (massless cluster),
-        // dM^2/dr = xmax (1/k) y^(1/k - 1) / g_RQF(y, c_k).  FP64.
+        // u = y^(1/2k), M = mu + u (M_max - mu) with mu = sqrt(xmin) (the
+        // cluster's masses) and M_max = sqrt(xmax); massless: M = u M_parent.
+        // dM^2/dr = 2 M (M_max - mu) u / (2 k y g_RQF(y, c_k)).  FP64.
         const double c = p.mw;
         const double b = c - (c - 2.0) * r;
         const double y = 2.0 * r / (b + sqrt(b * b + 4.0 * r * (1.0 - b)));
-        const double yk = p.int_pow == 1 ? y : kth_root<false>(y, p.int_pow, p.e);
+        const double u = sqrt(p.int_pow == 1 ? y : kth_root<false>(y, p.int_pow, p.e));  // y^(1/2k), k <= 7
+        const double lo = sqrt(xmin), span = sqrt(xmax) - lo;
+        const double m = lo + u * span;
         const double om = y * (1.0 - y);
         const double den = 1.0 + (c - 2.0) * om;
         const double g = (2.0 * om + c * (1.0 - y) * (1.0 - y)) / (den * den);
-        jac = xmax * (yk / y) * p.e / g;
-        return xmax * yk;
+        jac = 2.0 * m * span * u * (0.5 * p.e) / (y * g);
+        return m * m;
     }
     if ((KINDS & KIND_LOG) && kind == MAP_LOG) {
         double lmax = t_log<MIX>(xmax - p.m2), lmin = t_log<MIX>(xmin - p.m2);
@@ -265,7 +268,9 @@ __device__ __forceinline__ double unmap_dyn(const MapParams& p, double x, double
         return (atan((x - p.m2) / p.mw) - u1) / (u2 - u1);
     }
     if ((KINDS & KIND_RAMBO) && kind == MAP_RAMBO) {
-        const double y = ipow_any(x / xmax, p.int_pow), c = p.mw;
+        const double lo = sqrt(xmin);
+        const double u = (sqrt(x) - lo) / (sqrt(xmax) - lo);
+        const double y = ipow_any(u, 2 * p.int_pow), c = p.mw;
         return (y * y + c * y * (1.0 - y)) / (1.0 + (c - 2.0) * y * (1.0 - y));
     }
     if ((KINDS & KIND_LOG) && kind == MAP_LOG) {

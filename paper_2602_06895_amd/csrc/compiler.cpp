@@ -310,8 +310,6 @@ bool compile_channel(Ctx& cx, const JValue& cj, const std::vector<double>& masse
             b.particles(j, ps);
             const int k = (int)ps.size() - 1;
             if (k < 1 || k > 7) return cx.fail("a FastRambo cluster needs 2 to 8 particles");
-            for (int q : ps)
-                if (masses[q] != 0.0) return cx.fail("FastRambo clusters need massless particles");
             MapParams rp{};
             rp.kind = MAP_RAMBO;
             rp.int_pow = k;

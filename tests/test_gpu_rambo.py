@@ -54,3 +54,23 @@ def test_fastrambo_volume_and_round_trip(torch, n):
     err = (inv["y"] - y).abs().amax(dim=0)
     assert float(err.median()) < 1e-14 and float(err.max()) < 1e-8
     ctx.close()
+
+
+def test_massive_fastrambo_matches_oracle(torch):
+    from paper_2602_06895_amd import Context
+
+    desc = W.rambo_process(5, masses=[10.0, 20.0, 30.0, 40.0, 50.0])
+    ctx = Context(desc)
+    orc = oracle.Process(desc)
+    y = W.philox_uniforms(17, 5, 0, 20001, ctx.dims[0])
+    out = ctx.map(0, torch.from_numpy(y).cuda(), weight=True)
+    torch.cuda.synchronize()
+    ref = orc.map(0, y, orc.uniform_grid(0))
+    fe = orc.forward_error(0, y, orc.uniform_grid(0), ref=ref)
+    got = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+    compare(got, ref, fe, hadronic=False, label="massive FastRambo")
+    inv = ctx.inverse_map(0, out["p"], None)
+    torch.cuda.synchronize()
+    err = np.abs(inv["y"].cpu().numpy() - y).max(axis=0)
+    assert np.median(err) < 1e-13 and err.max() < 1e-6
+    ctx.close()

@@ -309,12 +309,14 @@ def flow_params(seed: int, dims: int, layers: int, bins: int, hidden: int, last_
     return np.concatenate(out).astype(np.float32)
 
 
-def rambo_process(n: int, sqrt_s: float = 1000.0) -> dict:
-    """e+e- -> n massless particles at fixed sqrt(s) through one FastRambo
-    chain: Q_1 -> 1 + Q_2, Q_2 -> 2 + Q_3, ..., Q_{n-1} -> n-1 + n."""
-    leg = {"d": [n - 1, n], "rambo": True}
+def rambo_process(n: int, sqrt_s: float = 1000.0, masses=None, rambo: bool = True) -> dict:
+    """e+e- -> n particles (massless unless `masses`) at fixed sqrt(s) through
+    one decay chain Q_1 -> 1 + Q_2, Q_2 -> 2 + Q_3, ..., Q_{n-1} -> n-1 + n,
+    with FastRambo cluster masses (or, rambo=False, the power-law maps)."""
+    leg = {"d": [n - 1, n], "rambo": rambo}
     for q in range(n - 2, 0, -1):
-        leg = {"d": [q, leg], "rambo": True}
+        leg = {"d": [q, leg], "rambo": rambo}
     leg.pop("rambo")  # the root decays at s-hat
-    return {"name": f"rambo{n}", "sqrt_s": sqrt_s, "beams": "fixed", "masses": [0.0] * n, "nu": 0.8,
+    m = [0.0] * n if masses is None else [float(x) for x in masses]
+    return {"name": f"rambo{n}", "sqrt_s": sqrt_s, "beams": "fixed", "masses": m, "nu": 0.8,
             "regulator": 1e-3, "vegas_bins": 64, "integrand": {}, "channels": [{"s": leg}]}

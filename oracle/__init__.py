@@ -194,7 +194,7 @@ class _Channel(C.Structure):
                 ("child_start", C.c_void_p), ("child_count", C.c_void_p), ("children", C.c_void_p),
                 ("mass", C.c_void_p), ("width", C.c_void_p), ("nu", C.c_void_p),
                 ("t_order", C.c_char_p), ("s_order", C.c_void_p), ("dec_order", C.c_void_p),
-                ("rambo", C.c_void_p)]
+                ("rambo", C.c_void_p), ("chili", C.c_int32)]
 
 
 class _Process(C.Structure):
@@ -224,6 +224,13 @@ class ChannelTree:
         self.kind, self.particle, self.parent, self.children = [], [], [], []
         self.mass, self.width, self.nu, self.order = [], [], [], []
         self.rambo = []  # FastRambo clusters: their particle count - 1, else 0
+        self.chili = bool(chan.get("chili"))
+        if self.chili:
+            # Chili (section 2.4): no tree, 3 random numbers per particle but
+            # the last, which takes only its rapidity
+            self.n_final = len(masses)
+            self.t_order, self.s_order, self.dec_order, self.kappa = "", [], [], 0
+            return
 
         def add(leg, parent):
             idx = len(self.kind)
@@ -300,12 +307,18 @@ class ChannelTree:
         return out
 
     def dims(self, hadronic: bool) -> int:
+        if self.chili:
+            if not hadronic:
+                raise ValueError("a Chili channel samples x1, x2 from the momenta: hadronic beams only")
+            return 3 * self.n_final - 2
         d = len(self.s_order) + max(self.kappa - 1, 0) + 2 * self.kappa + 2 * len(self.dec_order)
         return d + (2 if hadronic else 0)
 
     def propagators(self):
         """(t_type, particle set, mass, width) of every internal line."""
         out = []
+        if self.chili:
+            return out
         if self.kind[0] == TNODE:
             acc = []
             for leg in self.children[0][:-1]:
@@ -336,7 +349,7 @@ class ChannelTree:
                         _ptr(k["kind"]), _ptr(k["particle"]), _ptr(k["parent"]),
                         _ptr(k["child_start"]), _ptr(k["child_count"]), _ptr(k["children"]),
                         _ptr(k["mass"]), _ptr(k["width"]), _ptr(k["nu"]), k["t_order"],
-                        _ptr(k["s_order"]), _ptr(k["dec_order"]), _ptr(k["rambo"]))
+                        _ptr(k["s_order"]), _ptr(k["dec_order"]), _ptr(k["rambo"]), int(self.chili))
 
 
 def _mask(parts):

@@ -35,6 +35,9 @@ static double orc_nudge(double v)
 #define tan(a) orc_nudge(tan(a))
 #define sin(a) orc_nudge(sin(a))
 #define cos(a) orc_nudge(cos(a))
+#define atan2(a, b) orc_nudge(atan2(a, b))
+#define cosh(a) orc_nudge(cosh(a))
+#define sinh(a) orc_nudge(sinh(a))
 #endif
 
 #define ORC_MAX_NODES 64
@@ -65,6 +68,7 @@ typedef struct {
     const int32_t* s_order;     /* clusters other than the root, sampling order */
     const int32_t* dec_order;   /* clusters decayed with (phi,theta), parents first */
     const int32_t* rambo;       /* FastRambo cluster: its particle count - 1 (k), else 0 */
+    int32_t chili;              /* 1: a Chili channel (no tree) */
 } orc_channel;
 
 typedef struct {
@@ -474,6 +478,10 @@ typedef struct {
 
 /* The whole per-event chain for channel `chan` of process `pr`, given the
  * uniforms y[d] (before VEGAS) and the channel's VEGAS grid (NULL: none). */
+static void event_tail(const orc_process* pr, int32_t chan, double pf[][4], const double pa[4], const double pb[4],
+                       double x1, double x2, const double* factors, int32_t nf, orc_event* ev);
+static void event_chili(const orc_process* pr, int32_t chan, const double* r, double jv, orc_event* ev);
+
 static void event(const orc_process* pr, const orc_channel* ch, int32_t chan,
                   const double* y, int32_t dims, const double* grid, int32_t nb, orc_event* ev)
 {
@@ -488,6 +496,10 @@ static void event(const orc_process* pr, const orc_channel* ch, int32_t chan,
         } else {
             r[k] = y[k];
         }
+    }
+    if (ch->chili) {
+        event_chili(pr, chan, r, jv, ev);
+        return;
     }
 
     double s[ORC_MAX_NODES];
@@ -652,6 +664,16 @@ static void event(const orc_process* pr, const orc_channel* ch, int32_t chan,
     double pf[ORC_MAX_FINAL][4];
     for (int32_t j = 0; j < ch->n_nodes; ++j)
         if (ch->kind[j] == ORC_LEAF) memcpy(pf[ch->particle[j]], mom[j], sizeof pf[0]);
+    event_tail(pr, chan, pf, pa, pb, x1, x2, factors, nf, ev);
+}
+
+/* Steps (8)-(11) of an event whose final-state momenta pf are in the
+ * partonic frame (incoming pa, pb): beam boost, reduce_product of the
+ * Jacobian factors, cut_unphysical, integrand and channel weight. */
+static void event_tail(const orc_process* pr, int32_t chan, double pf[][4], const double pa[4], const double pb[4],
+                       double x1, double x2, const double* factors, int32_t nf, orc_event* ev)
+{
+    const int32_t n = pr->n_final;
 #ifdef ORC_LIBM_NUDGE
     /* perturbation builds: move every component by one ulp, alternating in
      * direction, so that quantities recomputed from the momenta see a
@@ -707,6 +729,102 @@ static void event(const orc_process* pr, const orc_channel* ch, int32_t chan,
     ev->f = f;
     ev->alpha = alpha;
     ev->w = alpha * f * jac;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Chili (section 2.4)                                                       */
+/* ------------------------------------------------------------------------ */
+
+/* One Chili event: particles 1..n-1 from (p_T, y, phi) in the lab frame --
+ * p_T^2 by the 1/p_T^2 map between the process's p_T cut and sqrt(s_lab)/2
+ * (eq. chili_pt_withcut), or without a cut the regulated map of eq.
+ * chili_pt_nocut (lambda = m, 1 for massless); y uniform in +-y_max(m_T);
+ * phi uniform, measured from the current recoil direction -- then the last
+ * particle's transverse momentum by recoil and its rapidity uniform in the
+ * range the beam energy leaves, and x_1,2 = E^+- / sqrt(s_lab).  Measure:
+ * integrating dx1 dx2 prod d^3p / 2E against the momentum delta leaves
+ * (2 pi)^(4-3n) / s_lab dy_n prod_(i<n) dp_T^2 dy dphi / 4; each factor is
+ * the exact derivative of its map.  Dimensions per particle (p_T, y, phi),
+ * then y_n. */
+static void event_chili(const orc_process* pr, int32_t chan, const double* r, double jv, orc_event* ev)
+{
+    const int32_t n = pr->n_final;
+    const double sq = sqrt(pr->s_lab), ptmax = 0.5 * sq;
+    double pl[ORC_MAX_FINAL][4];
+    double factors[4 * ORC_MAX_FINAL + 8];
+    int32_t nf = 0;
+    factors[nf++] = pow(2.0 * ORC_PI, 4.0 - 3.0 * n) / pr->s_lab;
+    double sx = 0.0, sy = 0.0, ep = 0.0, em = 0.0;
+    int32_t k = 0;
+    int ok = 1;
+    for (int32_t i = 0; i < n - 1; ++i) {
+        const double m = pr->mass[i];
+        double pt2, jpt2;
+        const double rp = r[k++];
+        if (pr->pt_min > 0.0) {
+            const double a = 1.0 / (ptmax * ptmax), b = 1.0 / (pr->pt_min * pr->pt_min);
+            pt2 = 1.0 / (rp * a + (1.0 - rp) * b);
+            jpt2 = (b - a) * pt2 * pt2;
+        } else {
+            const double lam = m > 0.0 ? m : 1.0;
+            const double den = 2.0 * lam + ptmax * (1.0 - rp);
+            const double pt = 2.0 * lam * ptmax * rp / den;
+            pt2 = pt * pt;
+            jpt2 = 2.0 * pt * 2.0 * lam * ptmax * (2.0 * lam + ptmax) / (den * den);
+        }
+        const double mt = sqrt(pt2 + m * m);
+        const double z = sq / (2.0 * mt);
+        if (!(z > 1.0)) ok = 0;
+        const double ymax = ok ? log(z + sqrt(z * z - 1.0)) : 0.0;
+        const double yv = ymax * (2.0 * r[k++] - 1.0);
+        const double phi_rec = (i == 0) ? 0.0 : atan2(-sy, -sx);
+        const double phi = 2.0 * ORC_PI * r[k++] + phi_rec;
+        const double pt = sqrt(pt2);
+        pl[i][0] = mt * cosh(yv);
+        pl[i][1] = pt * cos(phi);
+        pl[i][2] = pt * sin(phi);
+        pl[i][3] = mt * sinh(yv);
+        sx += pl[i][1];
+        sy += pl[i][2];
+        ep += pl[i][0] + pl[i][3];
+        em += pl[i][0] - pl[i][3];
+        factors[nf++] = jpt2 * (2.0 * ymax) * (2.0 * ORC_PI) / 4.0;
+    }
+    /* the last particle: recoil, rapidity within the beam energy */
+    {
+        const int32_t i = n - 1;
+        const double m = pr->mass[i];
+        const double px = -sx, py = -sy;
+        const double mt = sqrt(px * px + py * py + m * m);
+        const double ylo = -log((sq - em) / mt), yhi = log((sq - ep) / mt);
+        if (!(sq > ep && sq > em && yhi > ylo)) ok = 0;
+        const double yv = ok ? ylo + (yhi - ylo) * r[k++] : 0.0;
+        pl[i][0] = mt * cosh(yv);
+        pl[i][1] = px;
+        pl[i][2] = py;
+        pl[i][3] = mt * sinh(yv);
+        ep += pl[i][0] + pl[i][3];
+        em += pl[i][0] - pl[i][3];
+        factors[nf++] = ok ? (yhi - ylo) : 0.0;
+    }
+    factors[nf++] = 1.0; /* channel constant */
+    factors[nf++] = jv;
+    double x1 = ep / sq, x2 = em / sq;
+    if (!ok) x1 = x2 = 0.5; /* any values: the zero factor cuts the event */
+    /* the partonic frame: undo the beam boost of x1, x2 */
+    const double sqx = sqrt(x1 * x2);
+    const double g = (x1 + x2) / (2.0 * sqx), gb = (x1 - x2) / (2.0 * sqx);
+    double pf[ORC_MAX_FINAL][4];
+    for (int32_t i = 0; i < n; ++i) {
+        pf[i][0] = g * pl[i][0] - gb * pl[i][3];
+        pf[i][1] = pl[i][1];
+        pf[i][2] = pl[i][2];
+        pf[i][3] = -gb * pl[i][0] + g * pl[i][3];
+    }
+    const double rs = sqrt(x1 * x2 * pr->s_lab);
+    const double pa[4] = {0.5 * rs, 0.0, 0.0, 0.5 * rs};
+    const double pb[4] = {0.5 * rs, 0.0, 0.0, -0.5 * rs};
+    event_tail(pr, chan, pf, pa, pb, x1, x2, factors, nf, ev);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -986,7 +1104,7 @@ int orc_inverse(const orc_process* pr, const orc_channel* ch, int32_t chan, int3
                 const double* p, const double* x1x2, const double* grid, int32_t nb, double* y, double* jac,
                 int32_t nthreads)
 {
-    if (dims > ORC_MAX_DIMS || pr->n_final > ORC_MAX_FINAL || ch->n_nodes > ORC_MAX_NODES) return -1;
+    if (dims > ORC_MAX_DIMS || pr->n_final > ORC_MAX_FINAL || ch->n_nodes > ORC_MAX_NODES || ch->chili) return -1;
     const int32_t np = pr->n_final + 2;
     int bad = 0;
 #pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1) reduction(| : bad)
@@ -1051,7 +1169,7 @@ int orc_map(const orc_process* pr, const orc_channel* ch, int32_t chan, int32_t 
         if (f) f[e] = ev.f;
         if (inv)
             for (int32_t j = 0; j < ch->n_nodes; ++j) inv[(size_t)j * n + e] = ev.inv[j];
-        if (tabs && ch->kind[ch->root] == ORC_TNODE)
+        if (tabs && ch->n_nodes > 0 && ch->kind[ch->root] == ORC_TNODE)
             for (int32_t j = 0; j < ch->child_count[ch->root] - 1; ++j) tabs[(size_t)j * n + e] = ev.tabs[j];
     }
     return 0;

@@ -320,3 +320,19 @@ def rambo_process(n: int, sqrt_s: float = 1000.0, masses=None, rambo: bool = Tru
     m = [0.0] * n if masses is None else [float(x) for x in masses]
     return {"name": f"rambo{n}", "sqrt_s": sqrt_s, "beams": "fixed", "masses": m, "nu": 0.8,
             "regulator": 1e-3, "vegas_bins": 64, "integrand": {}, "channels": [{"s": leg}]}
+
+
+def chili_process(n: int, sqrt_s: float = 1000.0, masses=None, pt_min: float = 0.0, pdf=None,
+                  props=None) -> dict:
+    """Hadronic 2->n through one Chili channel (section 2.4): f = 1 unless a
+    p_T cut, toy PDFs [a, b] or propagator factors are given."""
+    ig = {}
+    if pt_min > 0.0:
+        ig["pt_min"] = float(pt_min)
+    if pdf is not None:
+        ig["pdf"] = [float(pdf[0]), float(pdf[1])]
+    if props:
+        ig["props"] = copy.deepcopy(props)
+    m = [0.0] * n if masses is None else [float(x) for x in masses]
+    return {"name": f"chili{n}", "sqrt_s": sqrt_s, "beams": "hadronic", "masses": m, "nu": 0.8,
+            "regulator": 1e-3, "vegas_bins": 64, "integrand": ig, "channels": [{"chili": True}]}

@@ -294,6 +294,37 @@ def fastrambo_report(n_particles=6, n=10_000_000, reps=5):
                          "frac": ach / HBM_PEAK_GBS, "bytes_per_event": bpe}}
 
 
+def chili_report(n=10_000_000, reps=5):
+    """pp -> 4 jets (the headline integrand: toy PDFs, t-propagators, p_T >
+    20 GeV) through one Chili channel: fused sample throughput, the integral
+    and its relative error per event, and the share of events the recoiling
+    last jet fails the cut.  Bytes per event as for the headline: momenta 6 x
+    4 x 8 + weight 8 + channel 4 = 204 B."""
+    import torch
+
+    import workloads as W
+    from paper_2602_06895_amd import Context
+
+    desc = W.c2_pp4j()
+    desc["channels"] = [{"chili": True}]
+    ctx = Context(desc)
+    counts = np.array([n])
+    out = ctx.sample(counts, seed=8, stream_id=1)
+    ms = _timed(lambda: ctx.sample(counts, seed=8, stream_id=1, out=out), reps)
+    w = out["w"]
+    torch.cuda.synchronize()
+    mean, std = float(w.mean()), float(w.std())
+    zero = float((w == 0).double().mean())
+    bpe = 6 * 4 * 8 + 8 + 4
+    ach = n * bpe / (ms / 1e3) / 1e9
+    ctx.close()
+    return {"workload": f"pp -> 4 jets, sqrt(s) = 13 TeV, one Chili channel, {n} events",
+            "events_per_s": n / (ms / 1e3), "ms": ms, "integral": mean, "rel_std_per_event": std / mean,
+            "cut_share": zero,
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "bytes_per_event": bpe}}
+
+
 def summarize(d: str, events: int, steps: int = 10):
     """Summary of the rocprofv3 runs under d (rocpd databases written by the
     commands printed below) for the last `steps` k_sample dispatches of
@@ -401,7 +432,8 @@ def main():
         print(json.dumps({"flow_vs_vegas": flow_report(train_steps=args.flow_steps)}))
         return
     if args.inverse_only:
-        print(json.dumps({"inverse_map": inverse_report(), "fastrambo": fastrambo_report()}))
+        print(json.dumps({"inverse_map": inverse_report(), "fastrambo": fastrambo_report(),
+                          "chili": chili_report()}))
         return
     if args.copy_calibration:
         import torch
@@ -540,6 +572,7 @@ def main():
         result["inverse_map"] = inverse_report()
         torch.cuda.empty_cache()
         result["fastrambo"] = fastrambo_report()
+        result["chili"] = chili_report()
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(desc, grids, counts, seed=1)
     print(json.dumps(result))

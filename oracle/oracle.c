@@ -780,14 +780,16 @@ static void event_chili(const orc_process* pr, int32_t chan, const double* r, do
         const double phi_rec = (i == 0) ? 0.0 : atan2(-sy, -sx);
         const double phi = 2.0 * ORC_PI * r[k++] + phi_rec;
         const double pt = sqrt(pt2);
-        pl[i][0] = mt * cosh(yv);
+        /* E +- p_z = m_T exp(+-y): the light-cone components without cancellation */
+        const double lp = mt * exp(yv), lm = mt * exp(-yv);
+        pl[i][0] = 0.5 * (lp + lm);
         pl[i][1] = pt * cos(phi);
         pl[i][2] = pt * sin(phi);
-        pl[i][3] = mt * sinh(yv);
+        pl[i][3] = 0.5 * (lp - lm);
         sx += pl[i][1];
         sy += pl[i][2];
-        ep += pl[i][0] + pl[i][3];
-        em += pl[i][0] - pl[i][3];
+        ep += lp;
+        em += lm;
         factors[nf++] = jpt2 * (2.0 * ymax) * (2.0 * ORC_PI) / 4.0;
     }
     /* the last particle: recoil, rapidity within the beam energy */
@@ -799,12 +801,13 @@ static void event_chili(const orc_process* pr, int32_t chan, const double* r, do
         const double ylo = -log((sq - em) / mt), yhi = log((sq - ep) / mt);
         if (!(sq > ep && sq > em && yhi > ylo)) ok = 0;
         const double yv = ok ? ylo + (yhi - ylo) * r[k++] : 0.0;
-        pl[i][0] = mt * cosh(yv);
+        const double lp = mt * exp(yv), lm = mt * exp(-yv);
+        pl[i][0] = 0.5 * (lp + lm);
         pl[i][1] = px;
         pl[i][2] = py;
-        pl[i][3] = mt * sinh(yv);
-        ep += pl[i][0] + pl[i][3];
-        em += pl[i][0] - pl[i][3];
+        pl[i][3] = 0.5 * (lp - lm);
+        ep += lp;
+        em += lm;
         factors[nf++] = ok ? (yhi - ylo) : 0.0;
     }
     factors[nf++] = 1.0; /* channel constant */

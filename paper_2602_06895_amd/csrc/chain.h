@@ -93,7 +93,8 @@ enum : int {
     KIND_FLAT = 8,     // nu = 0
     KIND_BW = 16,      // Breit-Wigner
     KIND_RAMBO = 32,   // FastRambo cluster masses
-    KINDS_ALL = 63
+    KINDS_ALL = 63,    // every tree-channel map kind
+    KIND_CHILI = 64    // Chili channels (compiled only for processes that use them)
 };
 
 // Precision of the well-conditioned transcendentals (power laws, exp, log,
@@ -572,6 +573,108 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
     o.x1 = x1;
     o.x2 = x2;
     o.logtau = L;
+    o.jac = jac;
+}
+
+// Chili (section 2.4): every final-state particle but the last from
+// (p_T, y, phi) in the lab frame -- p_T^2 by the 1/p_T^2 map between the
+// process's p_T cut and sqrt(s_lab)/2 (eq. chili_pt_withcut), or without a
+// cut the regulated map of eq. chili_pt_nocut with lambda = m (1 when
+// massless); y uniform within +-y_max(m_T); phi uniform, measured from the
+// direction of the current recoil -- then the last particle balances the
+// transverse momentum and takes a rapidity uniform in the range the beam
+// energy leaves, and x1,2 = E +- p_z summed / sqrt(s_lab).  The measure
+// dx1 dx2 prod d^3p / 2E with the momentum delta becomes (2 pi)^(4-3n) /
+// s_lab dy_n prod_(i<n) dp_T^2 dy dphi / 4 (the first factor is the
+// channel's jac_const).  Particle k goes to slot k, boosted to the partonic
+// frame so that the common tail boosts it back.  FP64 in both precisions.
+template <int NS, class Next>
+__device__ __forceinline__ void run_chili(const ChannelTab* __restrict__ ct, double s_lab, Next& next,
+                                          double (&E)[NS], double (&X)[NS], double (&Y)[NS], double (&Z)[NS],
+                                          ChainOut& o) {
+    constexpr int NF = NS / 2 + 1;
+    const int n = ct->n_final;
+    const double sq = sqrt(s_lab), ptmax = 0.5 * sq;
+    const double ptmin2 = ct->chili_ptmin2;
+    double jac = ct->jac_const;
+    double sx = 0.0, sy = 0.0, ep = 0.0, em = 0.0;
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < NF - 1; ++i) {
+        if (i >= n - 1) break;
+        const double m = ct->chili_m[i];
+        const double rp = next(), ryv = next(), rf = next();
+        double pt2, jpt2;
+        if (ptmin2 > 0.0) {
+            const double a = 1.0 / (ptmax * ptmax), b = 1.0 / ptmin2;
+            pt2 = 1.0 / (rp * a + (1.0 - rp) * b);
+            jpt2 = (b - a) * pt2 * pt2;
+        } else {
+            const double lam = m > 0.0 ? m : 1.0;
+            const double den = 2.0 * lam + ptmax * (1.0 - rp);
+            const double pt = 2.0 * lam * ptmax * rp / den;
+            pt2 = pt * pt;
+            jpt2 = 2.0 * pt * 2.0 * lam * ptmax * (2.0 * lam + ptmax) / (den * den);
+        }
+        const double mt = sqrt(pt2 + m * m);
+        const double z = sq / (2.0 * mt);
+        ok = ok && z > 1.0;
+        const double ymax = ok ? log(z + sqrt(z * z - 1.0)) : 0.0;
+        const double yv = ymax * (2.0 * ryv - 1.0);
+        const double phi_rec = i == 0 ? 0.0 : atan2(-sy, -sx);
+        double sphi, cphi;
+        sincos(2.0 * kPiD * rf + phi_rec, &sphi, &cphi);
+        const double pt = sqrt(pt2);
+        // E +- p_z = m_T exp(+-y): the light-cone sums without cancellation
+        const double lp = mt * exp(yv), lm = mt * exp(-yv);
+        const double lx = pt * cphi, ly = pt * sphi;
+        E[i] = 0.5 * (lp + lm);
+        X[i] = lx;
+        Y[i] = ly;
+        Z[i] = 0.5 * (lp - lm);
+        sx += lx;
+        sy += ly;
+        ep += lp;
+        em += lm;
+        jac *= jpt2 * (2.0 * ymax) * (2.0 * kPiD) / 4.0;
+    }
+    {
+        const double m = ct->chili_m[n - 1];
+        const double px = -sx, py = -sy;
+        const double mt = sqrt(px * px + py * py + m * m);
+        const double ylo = -log((sq - em) / mt), yhi = log((sq - ep) / mt);
+        ok = ok && sq > ep && sq > em && yhi > ylo;
+        const double rl = next();
+        const double yv = ok ? ylo + (yhi - ylo) * rl : 0.0;
+        const double lp = mt * exp(yv), lm = mt * exp(-yv);
+        const double le = 0.5 * (lp + lm), lz = 0.5 * (lp - lm);
+#pragma unroll
+        for (int i = 0; i < NF; ++i)
+            if (i == n - 1) {
+                E[i] = le;
+                X[i] = px;
+                Y[i] = py;
+                Z[i] = lz;
+            }
+        ep += lp;
+        em += lm;
+        jac *= ok ? (yhi - ylo) : 0.0;
+    }
+    double x1 = ep / sq, x2 = em / sq;
+    if (!ok) x1 = x2 = 0.5;  // any values: the zero Jacobian cuts the event
+    const double sqx = sqrt(x1 * x2);
+    const double g = (x1 + x2) / (2.0 * sqx), gb = (x1 - x2) / (2.0 * sqx);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+        if (i >= n) break;
+        const double le = E[i], lz = Z[i];
+        E[i] = g * le - gb * lz;
+        Z[i] = -gb * le + g * lz;
+    }
+    o.shat = x1 * x2 * s_lab;
+    o.x1 = x1;
+    o.x2 = x2;
+    o.logtau = log(x1 * x2);
     o.jac = jac;
 }
 

@@ -150,7 +150,10 @@ __global__ __launch_bounds__(kBlock) void k_map(const ChannelTab* __restrict__ c
         };
         double E[NS], X[NS], Y[NS], Z[NS], S[NI], SQ[NI];
         ChainOut o;
-        run_chain<NS, NI, KINDS, MIX>(ct, s_lab, next, E, X, Y, Z, S, SQ, o);
+        if ((KINDS & KIND_CHILI) && ct->chili)
+            run_chili<NS>(ct, s_lab, next, E, X, Y, Z, o);
+        else
+            run_chain<NS, NI, KINDS, MIX>(ct, s_lab, next, E, X, Y, Z, S, SQ, o);
         if (!p) {
             // Jacobian only (the density of the inverse map)
             double FE[NS / 2 + 1], FX[NS / 2 + 1], FY[NS / 2 + 1], FZ[NS / 2 + 1], h;
@@ -231,7 +234,10 @@ __global__ __launch_bounds__(kBlock) void k_sample(const ChannelTab* __restrict_
             auto next = [&]() -> double { return col[(k++) * kBlock]; };
             double E[NS], X[NS], Y[NS], Z[NS], S[NI], SQ[NI];
             ChainOut o;
-            run_chain<NS, NI, KINDS, MIX>(ct, s_lab, next, E, X, Y, Z, S, SQ, o);
+            if ((KINDS & KIND_CHILI) && ct->chili)
+                run_chili<NS>(ct, s_lab, next, E, X, Y, Z, o);
+            else
+                run_chain<NS, NI, KINDS, MIX>(ct, s_lab, next, E, X, Y, Z, S, SQ, o);
             const double wv = finish_event<NS, MIX>(ct, pt, o, jv, E, X, Y, Z, np, ld, pos, p, x1x2, nullptr, true, q);
             w[pos] = wv;
             if (chan_out) chan_out[pos] = c;
@@ -430,10 +436,11 @@ __global__ __launch_bounds__(kBlock) void k_inverse(const ChannelTab* __restrict
 }
 
 // Launch of one register class: kind class `kc` picks the compiled map kinds
-// (0: integer-root power laws, 1: plus Breit-Wigner, 2: all).
+// (0: integer-root power laws, 1: plus Breit-Wigner, 2: all tree kinds,
+// 3: all, with Chili channels).
 template <int NS, int NI, bool MIX>
 hipError_t launch_chain_class(int kc, const ChainLaunch& a) {
-    constexpr int K0 = KIND_POW_INT, K1 = KIND_POW_INT | KIND_BW, K2 = KINDS_ALL;
+    constexpr int K0 = KIND_POW_INT, K1 = KIND_POW_INT | KIND_BW, K2 = KINDS_ALL, K3 = KINDS_ALL | KIND_CHILI;
     auto go = [&](auto kt) {
         constexpr int K = decltype(kt)::value;
         const size_t lds = a.lds + (a.sample ? sizeof(double) * stage_rows<NS, NI>() * kBlock : kQBytes);
@@ -444,7 +451,8 @@ hipError_t launch_chain_class(int kc, const ChainLaunch& a) {
             if (e != hipSuccess) return;
         }
         if (a.inverse) {
-            if constexpr (!MIX) {
+            // Chili channels have no inverse here (refused by the entry points)
+            if constexpr (!MIX && !(K & KIND_CHILI)) {
                 const size_t li = a.lds + sizeof(double) * stage_rows<NS, NI>() * kBlock;
                 if (li > 65536) {
                     hipError_t e = hipFuncSetAttribute((const void*)k_inverse<NS, NI, K>,
@@ -466,7 +474,8 @@ hipError_t launch_chain_class(int kc, const ChainLaunch& a) {
     };
     if (kc == 0) go(std::integral_constant<int, K0>{});
     else if (kc <= 1) go(std::integral_constant<int, K1>{});
-    else go(std::integral_constant<int, K2>{});
+    else if (kc == 2) go(std::integral_constant<int, K2>{});
+    else go(std::integral_constant<int, K3>{});
     return hipGetLastError();
 }
 

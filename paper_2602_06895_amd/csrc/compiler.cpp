@@ -190,6 +190,36 @@ bool compile_channel(Ctx& cx, const JValue& cj, const std::vector<double>& masse
     std::vector<Node>& nodes = b.nodes;
     std::string t_order;
     bool tchain = false;
+    if (const JValue* ch = cj.get("chili")) {
+        // Chili (section 2.4): no tree; per particle but the last p_T, y and
+        // phi, then the last one's rapidity: 3 n - 2 dimensions
+        if (ch->kind != JValue::BOOL || !ch->b) return cx.fail("\"chili\" must be true");
+        if (!hadronic) return cx.fail("a Chili channel needs hadronic beams (x1, x2 follow from the momenta)");
+        if (n < 2) return cx.fail("a Chili channel needs at least two final-state particles");
+        t.chili = 1;
+        t.n_final = n;
+        t.hadronic = 1;
+        t.n_slots = 2 * (n - 1);
+        // no invariants are sampled; counting n - 1 picks a register class
+        // whose staging column (1 + invariants + slots rows) holds the
+        // 3 n - 2 dimensions
+        t.n_inv = n - 1;
+        t.jac_const = std::pow(2.0 * kPi, 4.0 - 3.0 * n) / s_lab;
+        for (int k = 0; k < n; ++k) {
+            t.final_slot[k] = k;
+            t.chili_m[k] = masses[k];
+        }
+        t.dims = 3 * n - 2;
+        t.kinds = 64;
+        // the sample kernel stages the uniforms in a column of at least
+        // max(kMaxUniq + 1, 1 + n_inv + n_slots) rows
+        if (t.dims > std::max(kMaxUniq + 1, 1 + t.n_inv + t.n_slots))
+            return cx.fail("internal: Chili dimensions exceed the staging column");
+        props.clear();
+        prop_m.clear();
+        prop_w.clear();
+        return true;
+    }
     if (const JValue* legs = cj.get("t_chain")) {
         if (legs->kind != JValue::ARR || legs->arr.size() < 2)
             return cx.fail("\"t_chain\" needs at least two legs");
@@ -214,7 +244,7 @@ bool compile_channel(Ctx& cx, const JValue& cj, const std::vector<double>& masse
         if (b.add(*s, -1) < 0) return false;
         if (nodes[0].kind != N_CLUSTER) return cx.fail("a pure s-channel root must be a cluster");
     } else {
-        return cx.fail("a channel needs \"t_chain\" or \"s\"");
+        return cx.fail("a channel needs \"t_chain\", \"s\" or \"chili\"");
     }
     if (!cx.err.empty()) return false;
     // every particle exactly once
@@ -429,7 +459,8 @@ bool compile_channel(Ctx& cx, const JValue& cj, const std::vector<double>& masse
         t.final_slot[nodes[j].particle] = nodes[j].slot;
     }
     // map kinds used (bit values as in the kernels: 1 integer-root power law,
-    // 2 general power law, 4 log, 8 flat, 16 Breit-Wigner)
+    // 2 general power law, 4 log, 8 flat, 16 Breit-Wigner, 32 FastRambo;
+    // 64 marks a Chili channel)
     auto kind_bit = [](const MapParams& p) -> int32_t {
         switch (p.kind) {
             case MAP_POW: return p.int_pow ? 1 : 2;
@@ -593,6 +624,7 @@ bool compile_process(Ctx& cx, const JValue& pj, Compiled& out) {
             return false;
         t.process = pidx;
         t.alpha_index = use_alpha ? c : 0;
+        if (t.chili) t.chili_ptmin2 = pt.pt_min2;
         if (use_alpha) {
             uint32_t mask = 0;
             for (size_t q = 0; q < props.size(); ++q) {

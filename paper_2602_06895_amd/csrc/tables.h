@@ -109,6 +109,10 @@ struct ChannelTab {
     BlockSpec blk[kMaxFinal];
     DecaySpec dec[kMaxFinal];
     int32_t final_slot[kMaxFinal];  // slot code of each final-state particle
+    // Chili channels (no tree): particle k sits in slot k
+    int32_t chili;                  // 1: a Chili channel
+    double chili_ptmin2;            // the process's p_T cut squared (<= 0: none)
+    double chili_m[kMaxFinal];      // final-state masses
 };
 
 // Integrand and local channel weights of one process.

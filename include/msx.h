@@ -55,10 +55,21 @@
  *                   t-channel spine from incoming a to b, and for each of the
  *                   first kappa-1 generation steps whether the next leg is
  *                   peeled from the A or the B side (section 2.2.8);
- *                   {"s": cluster}  pure s-channel.
+ *                   {"s": cluster}  pure s-channel;
+ *                   {"chili": true}  a Chili channel (section 2.4, hadronic
+ *                   beams only): per particle but the last p_T (1/p_T^2
+ *                   above the integrand's "pt_min", else the regulated map
+ *                   with lambda = its mass or 1), rapidity and azimuth in
+ *                   the lab frame, then the last one's rapidity: 3 n - 2
+ *                   dimensions in that order; x1, x2 follow from the
+ *                   momenta.  It has no propagators (weight factor 1 under
+ *                   "alpha_mu") and no inverse (MSX_ERR_UNSUPPORTED from
+ *                   msx_inverse_map and msx_multichannel_density).
  *                 A leg is a particle label or a cluster
- *                 {"d": [child, child], "m", "w", "nu", "order"}.
- * Random-number dimensions of a channel, in order: s-hat (hadronic), the
+ *                 {"d": [child, child], "m", "w", "nu", "order", "rambo"};
+ *                 "rambo": true samples the cluster's mass with the
+ *                 FastRambo map of its particle count (section 2.2.9).
+ * Random-number dimensions of a tree channel, in order: s-hat (hadronic), the
  * cluster invariants in sampling order, the kappa-1 t-channel invariants,
  * x1 (hadronic), (r_phi, r_t) per 2->2 block, (r_phi, r_theta) per decay in
  * depth-first order -- the order of the paper's compute-graph example

@@ -63,8 +63,8 @@
  *                   the lab frame, then the last one's rapidity: 3 n - 2
  *                   dimensions in that order; x1, x2 follow from the
  *                   momenta.  It has no propagators (weight factor 1 under
- *                   "alpha_mu") and no inverse (MSX_ERR_UNSUPPORTED from
- *                   msx_inverse_map and msx_multichannel_density).
+ *                   "alpha_mu"); msx_inverse_map recovers its uniforms from
+ *                   the lab-frame p_T, rapidities and relative azimuths.
  *                 A leg is a particle label or a cluster
  *                 {"d": [child, child], "m", "w", "nu", "order", "rambo"};
  *                 "rambo": true samples the cluster's mass with the

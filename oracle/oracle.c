@@ -38,6 +38,7 @@ static double orc_nudge(double v)
 #define atan2(a, b) orc_nudge(atan2(a, b))
 #define cosh(a) orc_nudge(cosh(a))
 #define sinh(a) orc_nudge(sinh(a))
+#define asinh(a) orc_nudge(asinh(a))
 #endif
 
 #define ORC_MAX_NODES 64
@@ -885,6 +886,64 @@ static double turn_fraction(double x, double y)
     return f < 0.0 ? f + 1.0 : f;
 }
 
+/* Inverse of the Chili generator (section 2.4), from the lab-frame momenta
+ * of the final state: per particle but the last, p_T^2 -> r by inverting
+ * eq. chili_pt_withcut (or p_T -> r by inverting eq. chili_pt_nocut), the
+ * rapidity asinh(p_z / m_T) -> r within +-y_max(m_T), the azimuth measured
+ * from the recoil direction of the particles before it -> r; then the last
+ * particle's rapidity within its range.  Returns the number of dimensions
+ * written. */
+static int32_t inverse_chili(const orc_process* pr, double pl[][4], double* r)
+{
+    const int32_t n = pr->n_final;
+    const double sq = sqrt(pr->s_lab), ptmax = 0.5 * sq;
+    double q[ORC_MAX_FINAL][4];
+    for (int32_t i = 0; i < n; ++i)
+        for (int c = 0; c < 4; ++c) q[i][c] = pl[i + 2][c];
+#ifdef ORC_LIBM_NUDGE
+    for (int32_t i = 0; i < n; ++i)
+        for (int c = 0; c < 4; ++c)
+            if (q[i][c] != 0.0)
+                q[i][c] = nextafter(q[i][c], ((i + c + (ORC_LIBM_NUDGE > 0)) & 1) ? INFINITY : -INFINITY);
+#endif
+    double sx = 0.0, sy = 0.0, ep = 0.0, em = 0.0;
+    int32_t k = 0;
+    for (int32_t i = 0; i < n - 1; ++i) {
+        const double m = pr->mass[i];
+        const double px = q[i][1], py = q[i][2], pz = q[i][3];
+        const double pt2 = px * px + py * py;
+        if (pr->pt_min > 0.0) {
+            const double a = 1.0 / (ptmax * ptmax), b = 1.0 / (pr->pt_min * pr->pt_min);
+            r[k++] = (b - 1.0 / pt2) / (b - a);
+        } else {
+            const double lam = m > 0.0 ? m : 1.0;
+            const double pt = sqrt(pt2);
+            r[k++] = pt * (2.0 * lam + ptmax) / (ptmax * (2.0 * lam + pt));
+        }
+        const double mt = sqrt(pt2 + m * m);
+        const double z = sq / (2.0 * mt);
+        const double ymax = log(z + sqrt(z * z - 1.0));
+        const double yv = asinh(pz / mt);
+        r[k++] = 0.5 * (yv / ymax + 1.0);
+        /* azimuth relative to the recoil direction (-sx, -sy); +x for the first */
+        const double ux = i == 0 ? 1.0 : -sx, uy = i == 0 ? 0.0 : -sy;
+        r[k++] = turn_fraction(ux * px + uy * py, ux * py - uy * px);
+        sx += px;
+        sy += py;
+        ep += mt * exp(yv);
+        em += mt * exp(-yv);
+    }
+    {
+        const int32_t i = n - 1;
+        const double m = pr->mass[i];
+        const double mt = sqrt(sx * sx + sy * sy + m * m);
+        const double ylo = -log((sq - em) / mt), yhi = log((sq - ep) / mt);
+        const double yv = asinh(q[i][3] / mt);
+        r[k++] = (yv - ylo) / (yhi - ylo);
+    }
+    return k;
+}
+
 static void node_momentum(const orc_channel* ch, int32_t j, double pf[][4], double mom[][4])
 {
     if (ch->kind[j] == ORC_LEAF) {
@@ -1107,7 +1166,7 @@ int orc_inverse(const orc_process* pr, const orc_channel* ch, int32_t chan, int3
                 const double* p, const double* x1x2, const double* grid, int32_t nb, double* y, double* jac,
                 int32_t nthreads)
 {
-    if (dims > ORC_MAX_DIMS || pr->n_final > ORC_MAX_FINAL || ch->n_nodes > ORC_MAX_NODES || ch->chili) return -1;
+    if (dims > ORC_MAX_DIMS || pr->n_final > ORC_MAX_FINAL || ch->n_nodes > ORC_MAX_NODES) return -1;
     const int32_t np = pr->n_final + 2;
     int bad = 0;
 #pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1) reduction(| : bad)
@@ -1121,7 +1180,7 @@ int orc_inverse(const orc_process* pr, const orc_channel* ch, int32_t chan, int3
             x2 = x1x2[n + e];
         }
         double r[ORC_MAX_DIMS], ye[ORC_MAX_DIMS];
-        int32_t k = inverse_event(pr, ch, pl, x1, x2, r);
+        int32_t k = ch->chili ? inverse_chili(pr, pl, r) : inverse_event(pr, ch, pl, x1, x2, r);
         if (k != dims) {
             bad = 1;
             continue;

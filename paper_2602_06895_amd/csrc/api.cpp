@@ -320,8 +320,6 @@ msx_status msx_inverse_map(msx_ctx* ctx, int32_t channel, int64_t n, const doubl
     if (n > 0 && (!p || !y)) return fail(ctx, MSX_ERR_ARG, "p and y are required");
     if (m.hadronic && n > 0 && !x1x2) return fail(ctx, MSX_ERR_ARG, "x1x2 is required for hadronic beams");
     if (!m.hadronic && x1x2) return fail(ctx, MSX_ERR_ARG, "x1x2 must be NULL for fixed beams");
-    if (ctx->comp.chans[channel].chili)
-        return fail(ctx, MSX_ERR_UNSUPPORTED, "a Chili channel has no inverse map in this library");
     if (n == 0) return MSX_OK;
     if (msx_status st = set_device(ctx)) return st;
     const ChannelTab& t = ctx->comp.chans[channel];
@@ -351,9 +349,6 @@ msx_status msx_multichannel_density(msx_ctx* ctx, int32_t process, int64_t n, co
     const ChannelMeta& m0 = ctx->comp.meta[chans[0]];
     if (m0.hadronic && n > 0 && !x1x2) return fail(ctx, MSX_ERR_ARG, "x1x2 is required for hadronic beams");
     if (!m0.hadronic && x1x2) return fail(ctx, MSX_ERR_ARG, "x1x2 must be NULL for fixed beams");
-    for (size_t i = 0; i < chans.size(); ++i)
-        if (ctx->comp.chans[chans[i]].chili)
-            return fail(ctx, MSX_ERR_UNSUPPORTED, "a Chili channel has no inverse map in this library");
     for (size_t i = 0; i < chans.size(); ++i)
         if (!(alpha[i] >= 0.0)) return fail(ctx, MSX_ERR_ARG, "alpha must be >= 0");
     if (n == 0) return MSX_OK;

@@ -266,6 +266,53 @@ __global__ __launch_bounds__(kBlock) void k_sample(const ChannelTab* __restrict_
     }
 }
 
+// Inverse of run_chili from the lab-frame momenta p [4][np][n] of event e:
+// per particle but the last, p_T -> r (eq. chili_pt_withcut or
+// chili_pt_nocut inverted), the rapidity asinh(p_z / m_T) -> r within
+// +-y_max, the azimuth measured from the recoil direction of the particles
+// before it -> r; then the last particle's rapidity within its range.  The
+// uniforms go to the thread's staging column col (stride kBlock).
+template <int NF>
+__device__ __forceinline__ void chili_unmap(const ChannelTab* __restrict__ ct, double s_lab, int np, int64_t n,
+                                            int64_t e, const double* __restrict__ p, double* col) {
+    const int nf = ct->n_final;
+    const double sq = sqrt(s_lab), ptmax = 0.5 * sq;
+    const double ptmin2 = ct->chili_ptmin2;
+    double sx = 0.0, sy = 0.0, ep = 0.0, em = 0.0;
+    int kd = 0;
+    auto put = [&](double r) { col[(kd++) * kBlock] = r; };
+    for (int i = 0; i < nf - 1; ++i) {
+        const double m = ct->chili_m[i];
+        const double px = p[((int64_t)1 * np + i + 2) * n + e], py = p[((int64_t)2 * np + i + 2) * n + e];
+        const double pz = p[((int64_t)3 * np + i + 2) * n + e];
+        const double pt2 = px * px + py * py;
+        if (ptmin2 > 0.0) {
+            const double a = 1.0 / (ptmax * ptmax), b = 1.0 / ptmin2;
+            put((b - 1.0 / pt2) / (b - a));
+        } else {
+            const double lam = m > 0.0 ? m : 1.0;
+            const double pt = sqrt(pt2);
+            put(pt * (2.0 * lam + ptmax) / (ptmax * (2.0 * lam + pt)));
+        }
+        const double mt = sqrt(pt2 + m * m);
+        const double z = sq / (2.0 * mt);
+        const double ymax = log(z + sqrt(z * z - 1.0));
+        const double yv = asinh(pz / mt);
+        put(0.5 * (yv / ymax + 1.0));
+        const double ux = i == 0 ? 1.0 : -sx, uy = i == 0 ? 0.0 : -sy;
+        put(turn_fraction(ux * px + uy * py, ux * py - uy * px));
+        sx += px;
+        sy += py;
+        ep += mt * exp(yv);
+        em += mt * exp(-yv);
+    }
+    const double m = ct->chili_m[nf - 1];
+    const double mt = sqrt(sx * sx + sy * sy + m * m);
+    const double ylo = -log((sq - em) / mt), yhi = log((sq - ep) / mt);
+    const double yv = asinh(p[((int64_t)3 * np + nf - 1 + 2) * n + e] / mt);
+    put((yv - ylo) / (yhi - ylo));
+}
+
 // Inverse map of one channel (section 2.1): lab-frame momenta p and momentum
 // fractions -> the uniforms y that the chain maps to them (k_map without
 // momentum stores then gives the forward Jacobian at y).  Every step of
@@ -291,144 +338,148 @@ __global__ __launch_bounds__(kBlock) void k_inverse(const ChannelTab* __restrict
     const int hadronic = ct->hadronic;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
-        double x1 = 1.0, x2 = 1.0, g = 1.0, gb = 0.0;
-        if (hadronic) {
-            x1 = x1x2[e];
-            x2 = x1x2[n + e];
-            const double inv = 1.0 / (2.0 * sqrt(x1 * x2));
-            g = (x1 + x2) * inv;
-            gb = (x1 - x2) * inv;
-        }
-        double FE[NF], FX[NF], FY[NF], FZ[NF];
-#pragma unroll
-        for (int k = 0; k < NF; ++k) {
-            FE[k] = FX[k] = FY[k] = FZ[k] = 0.0;
-            if (k < nf) {
-                const double le = p[((int64_t)0 * np + k + 2) * n + e], lz = p[((int64_t)3 * np + k + 2) * n + e];
-                FE[k] = g * le - gb * lz;
-                FX[k] = p[((int64_t)1 * np + k + 2) * n + e];
-                FY[k] = p[((int64_t)2 * np + k + 2) * n + e];
-                FZ[k] = -gb * le + g * lz;
+        if ((KINDS & KIND_CHILI) && ct->chili) {
+            chili_unmap<NF>(ct, s_lab, np, n, e, p, col);
+        } else {
+            double x1 = 1.0, x2 = 1.0, g = 1.0, gb = 0.0;
+            if (hadronic) {
+                x1 = x1x2[e];
+                x2 = x1x2[n + e];
+                const double inv = 1.0 / (2.0 * sqrt(x1 * x2));
+                g = (x1 + x2) * inv;
+                gb = (x1 - x2) * inv;
             }
-        }
-        int kd = 0;
-        auto put = [&](double r) { col[(kd++) * kBlock] = r; };
-        double S[NI], SQ[NI];
-        // (1) s-hat = x1 x2 s_lab
-        double shat = s_lab;
-        if (hadronic) {
-            shat = x1 * x2 * s_lab;
-            put(unmap_static<KINDS>(ct->inv[0], shat));
-        }
-        S[0] = shat;
-        SQ[0] = sqrt(shat);
-        // (2) time-like invariants from the momenta of their clusters
-        const int n_inv = ct->n_inv;
-        for (int i = 1; i < n_inv; ++i) {
-            const InvSpec& iv = ct->inv[i];
-            const double mmin = iv.min_const + masked_sum(iv.min_mask, SQ);
-            const double mmax = SQ[iv.parent] - iv.max_const - masked_sum(iv.max_mask, SQ);
-            double qe, qx, qy, qz;
-            sum_set<NF>(iv.set, FE, FX, FY, FZ, qe, qx, qy, qz);
-            const double s = qe * qe - qx * qx - qy * qy - qz * qz;
-            put(unmap_dyn<KINDS>(iv.map, s, mmin * mmin, mmax * mmax));
-            S[i] = s;
-            SQ[i] = sqrt(s);
-        }
-        // (3) x1 = tau^r
-        if (hadronic) put(log(x1) / log(shat / s_lab));
-        // (4) 2->2 blocks
-        const double h = 0.5 * SQ[0];
-        double Ae = h, Ax = 0.0, Ay = 0.0, Az = h;
-        double Be = h, Bx = 0.0, By = 0.0, Bz = -h;
-        double ma2 = 0.0, mb2 = 0.0;
-        const int n_blocks = ct->n_blocks;
+            double FE[NF], FX[NF], FY[NF], FZ[NF];
 #pragma unroll
-        for (int bi = 0; bi < NS / 2; ++bi) {
-            if (bi >= n_blocks) break;
-            const BlockSpec& bs = ct->blk[bi];
-            const double m1 = src_mass(bs.m1, SQ), m2 = src_mass(bs.m2, SQ);
-            // the leg is a sum of final-state momenta, the remaining cluster
-            // P - leg (P = p_A + p_B), as the chain built them
-            double p1e, p1x, p1y, p1z, p2e, p2x, p2y, p2z;
-            if (bs.side == 1) {
-                sum_set<NF>(bs.set2, FE, FX, FY, FZ, p2e, p2x, p2y, p2z);
-                p1e = (Ae + Be) - p2e;
-                p1x = (Ax + Bx) - p2x;
-                p1y = (Ay + By) - p2y;
-                p1z = (Az + Bz) - p2z;
-            } else {
-                sum_set<NF>(bs.set1, FE, FX, FY, FZ, p1e, p1x, p1y, p1z);
-                p2e = (Ae + Be) - p1e;
-                p2x = (Ax + Bx) - p1x;
-                p2y = (Ay + By) - p1y;
-                p2z = (Az + Bz) - p1z;
-            }
-            const double m0sq = S[bs.m0_inv], m0 = SQ[bs.m0_inv];
-            const double m1s = m1 * m1, m2s = m2 * m2;
-            const double C = (m0sq + (m1s - m2s)) * (m0sq + (ma2 - mb2));
-            const double R = sqrt(kallen(m0sq, m1s, m2s) * kallen(m0sq, ma2, mb2));
-            const double inv2 = 1.0 / (2.0 * m0sq);
-            const double t_minus = m1s + ma2 - (C + R) * inv2;
-            const double prod = (m1s - ma2) * (m2s - mb2) + (ma2 - mb2 - m1s + m2s) * (ma2 * m2s - m1s * mb2) / m0sq;
-            const double t_plus = (t_minus != 0.0) ? prod / t_minus : 0.0;
-            const double tmin = fmax(0.0, -t_plus), tmax = -t_minus;
-            const double de = Ae - p1e, dx = Ax - p1x, dy = Ay - p1y, dz = Az - p1z;
-            const double abst = -(de * de - dx * dx - dy * dy - dz * dz);
-            double vx = p1x, vy = p1y;
-            if (!bs.com) {
-                // into the rest frame of P, then R(phi_A, theta_A)^-1 = R_y(-theta_A) R_z(-phi_A)
-                const double Pe = Ae + Be, Px = Ax + Bx, Py = Ay + By, Pz = Az + Bz;
-                const double inv_m0 = 1.0 / m0, inv_em = 1.0 / (Pe + m0);
-                double ae = Ae, ax = Ax, ay = Ay, az = Az;
-                boost_by(Pe, -Px, -Py, -Pz, inv_m0, inv_em, ae, ax, ay, az);
-                double ke = p1e, kx = p1x, ky = p1y, kz = p1z;
-                boost_by(Pe, -Px, -Py, -Pz, inv_m0, inv_em, ke, kx, ky, kz);
-                const double inv_len = 1.0 / sqrt(ax * ax + ay * ay + az * az);
-                const double nx = ax * inv_len, ny = ay * inv_len, nz = az * inv_len;
-                const double st = sqrt(nx * nx + ny * ny);
-                double cp = 1.0, sp = 0.0;
-                if (st > 0.0) {
-                    const double ist = 1.0 / st;
-                    cp = nx * ist;
-                    sp = ny * ist;
+            for (int k = 0; k < NF; ++k) {
+                FE[k] = FX[k] = FY[k] = FZ[k] = 0.0;
+                if (k < nf) {
+                    const double le = p[((int64_t)0 * np + k + 2) * n + e], lz = p[((int64_t)3 * np + k + 2) * n + e];
+                    FE[k] = g * le - gb * lz;
+                    FX[k] = p[((int64_t)1 * np + k + 2) * n + e];
+                    FY[k] = p[((int64_t)2 * np + k + 2) * n + e];
+                    FZ[k] = -gb * le + g * lz;
                 }
-                const double xr = kx * cp + ky * sp, yr = -kx * sp + ky * cp;
-                vx = xr * nz - kz * st;
-                vy = yr;
             }
-            put(turn_fraction(vx, vy));
-            put(unmap_dyn<KINDS>(bs.tmap, abst, tmin, tmax));
-            const int side = bs.side;
-            const double fa = side == 0 ? 1.0 : 0.0, fb = side == 1 ? 1.0 : 0.0;
-            Ae -= fa * p1e;
-            Ax -= fa * p1x;
-            Ay -= fa * p1y;
-            Az -= fa * p1z;
-            Be -= fb * p2e;
-            Bx -= fb * p2x;
-            By -= fb * p2y;
-            Bz -= fb * p2z;
-            ma2 = side == 0 ? -abst : ma2;
-            mb2 = side == 1 ? -abst : mb2;
-        }
-        // (5) decays: angles of the first child in the rest frame of its parent
-        const int n_dec = ct->n_decays;
+            int kd = 0;
+            auto put = [&](double r) { col[(kd++) * kBlock] = r; };
+            double S[NI], SQ[NI];
+            // (1) s-hat = x1 x2 s_lab
+            double shat = s_lab;
+            if (hadronic) {
+                shat = x1 * x2 * s_lab;
+                put(unmap_static<KINDS>(ct->inv[0], shat));
+            }
+            S[0] = shat;
+            SQ[0] = sqrt(shat);
+            // (2) time-like invariants from the momenta of their clusters
+            const int n_inv = ct->n_inv;
+            for (int i = 1; i < n_inv; ++i) {
+                const InvSpec& iv = ct->inv[i];
+                const double mmin = iv.min_const + masked_sum(iv.min_mask, SQ);
+                const double mmax = SQ[iv.parent] - iv.max_const - masked_sum(iv.max_mask, SQ);
+                double qe, qx, qy, qz;
+                sum_set<NF>(iv.set, FE, FX, FY, FZ, qe, qx, qy, qz);
+                const double s = qe * qe - qx * qx - qy * qy - qz * qz;
+                put(unmap_dyn<KINDS>(iv.map, s, mmin * mmin, mmax * mmax));
+                S[i] = s;
+                SQ[i] = sqrt(s);
+            }
+            // (3) x1 = tau^r
+            if (hadronic) put(log(x1) / log(shat / s_lab));
+            // (4) 2->2 blocks
+            const double h = 0.5 * SQ[0];
+            double Ae = h, Ax = 0.0, Ay = 0.0, Az = h;
+            double Be = h, Bx = 0.0, By = 0.0, Bz = -h;
+            double ma2 = 0.0, mb2 = 0.0;
+            const int n_blocks = ct->n_blocks;
 #pragma unroll
-        for (int di = 0; di < NS / 2; ++di) {
-            if (di >= n_dec) break;
-            const DecaySpec& ds = ct->dec[di];
-            double ke, kx, ky, kz;
-            sum_set<NF>(ds.set1, FE, FX, FY, FZ, ke, kx, ky, kz);
-            if (!ds.parent_rest) {
-                double Pe, Px, Py, Pz;
-                sum_set<NF>(ds.parent_set, FE, FX, FY, FZ, Pe, Px, Py, Pz);
-                const double m0 = SQ[ds.parent_inv];
-                boost_by(Pe, -Px, -Py, -Pz, 1.0 / m0, 1.0 / (Pe + m0), ke, kx, ky, kz);
+            for (int bi = 0; bi < NS / 2; ++bi) {
+                if (bi >= n_blocks) break;
+                const BlockSpec& bs = ct->blk[bi];
+                const double m1 = src_mass(bs.m1, SQ), m2 = src_mass(bs.m2, SQ);
+                // the leg is a sum of final-state momenta, the remaining cluster
+                // P - leg (P = p_A + p_B), as the chain built them
+                double p1e, p1x, p1y, p1z, p2e, p2x, p2y, p2z;
+                if (bs.side == 1) {
+                    sum_set<NF>(bs.set2, FE, FX, FY, FZ, p2e, p2x, p2y, p2z);
+                    p1e = (Ae + Be) - p2e;
+                    p1x = (Ax + Bx) - p2x;
+                    p1y = (Ay + By) - p2y;
+                    p1z = (Az + Bz) - p2z;
+                } else {
+                    sum_set<NF>(bs.set1, FE, FX, FY, FZ, p1e, p1x, p1y, p1z);
+                    p2e = (Ae + Be) - p1e;
+                    p2x = (Ax + Bx) - p1x;
+                    p2y = (Ay + By) - p1y;
+                    p2z = (Az + Bz) - p1z;
+                }
+                const double m0sq = S[bs.m0_inv], m0 = SQ[bs.m0_inv];
+                const double m1s = m1 * m1, m2s = m2 * m2;
+                const double C = (m0sq + (m1s - m2s)) * (m0sq + (ma2 - mb2));
+                const double R = sqrt(kallen(m0sq, m1s, m2s) * kallen(m0sq, ma2, mb2));
+                const double inv2 = 1.0 / (2.0 * m0sq);
+                const double t_minus = m1s + ma2 - (C + R) * inv2;
+                const double prod = (m1s - ma2) * (m2s - mb2) + (ma2 - mb2 - m1s + m2s) * (ma2 * m2s - m1s * mb2) / m0sq;
+                const double t_plus = (t_minus != 0.0) ? prod / t_minus : 0.0;
+                const double tmin = fmax(0.0, -t_plus), tmax = -t_minus;
+                const double de = Ae - p1e, dx = Ax - p1x, dy = Ay - p1y, dz = Az - p1z;
+                const double abst = -(de * de - dx * dx - dy * dy - dz * dz);
+                double vx = p1x, vy = p1y;
+                if (!bs.com) {
+                    // into the rest frame of P, then R(phi_A, theta_A)^-1 = R_y(-theta_A) R_z(-phi_A)
+                    const double Pe = Ae + Be, Px = Ax + Bx, Py = Ay + By, Pz = Az + Bz;
+                    const double inv_m0 = 1.0 / m0, inv_em = 1.0 / (Pe + m0);
+                    double ae = Ae, ax = Ax, ay = Ay, az = Az;
+                    boost_by(Pe, -Px, -Py, -Pz, inv_m0, inv_em, ae, ax, ay, az);
+                    double ke = p1e, kx = p1x, ky = p1y, kz = p1z;
+                    boost_by(Pe, -Px, -Py, -Pz, inv_m0, inv_em, ke, kx, ky, kz);
+                    const double inv_len = 1.0 / sqrt(ax * ax + ay * ay + az * az);
+                    const double nx = ax * inv_len, ny = ay * inv_len, nz = az * inv_len;
+                    const double st = sqrt(nx * nx + ny * ny);
+                    double cp = 1.0, sp = 0.0;
+                    if (st > 0.0) {
+                        const double ist = 1.0 / st;
+                        cp = nx * ist;
+                        sp = ny * ist;
+                    }
+                    const double xr = kx * cp + ky * sp, yr = -kx * sp + ky * cp;
+                    vx = xr * nz - kz * st;
+                    vy = yr;
+                }
+                put(turn_fraction(vx, vy));
+                put(unmap_dyn<KINDS>(bs.tmap, abst, tmin, tmax));
+                const int side = bs.side;
+                const double fa = side == 0 ? 1.0 : 0.0, fb = side == 1 ? 1.0 : 0.0;
+                Ae -= fa * p1e;
+                Ax -= fa * p1x;
+                Ay -= fa * p1y;
+                Az -= fa * p1z;
+                Be -= fb * p2e;
+                Bx -= fb * p2x;
+                By -= fb * p2y;
+                Bz -= fb * p2z;
+                ma2 = side == 0 ? -abst : ma2;
+                mb2 = side == 1 ? -abst : mb2;
             }
-            const double len = sqrt(kx * kx + ky * ky + kz * kz);
-            put(turn_fraction(kx, ky));
-            put(0.5 * (kz / len + 1.0));
+            // (5) decays: angles of the first child in the rest frame of its parent
+            const int n_dec = ct->n_decays;
+#pragma unroll
+            for (int di = 0; di < NS / 2; ++di) {
+                if (di >= n_dec) break;
+                const DecaySpec& ds = ct->dec[di];
+                double ke, kx, ky, kz;
+                sum_set<NF>(ds.set1, FE, FX, FY, FZ, ke, kx, ky, kz);
+                if (!ds.parent_rest) {
+                    double Pe, Px, Py, Pz;
+                    sum_set<NF>(ds.parent_set, FE, FX, FY, FZ, Pe, Px, Py, Pz);
+                    const double m0 = SQ[ds.parent_inv];
+                    boost_by(Pe, -Px, -Py, -Pz, 1.0 / m0, 1.0 / (Pe + m0), ke, kx, ky, kz);
+                }
+                const double len = sqrt(kx * kx + ky * ky + kz * kz);
+                put(turn_fraction(kx, ky));
+                put(0.5 * (kz / len + 1.0));
+            }
         }
         // (6) inverse VEGAS map
         for (int k = 0; k < dims; ++k) y[(int64_t)k * n + e] = vegas_unmap(col[k * kBlock], lg + k * (nb + 1), nb);
@@ -451,8 +502,7 @@ hipError_t launch_chain_class(int kc, const ChainLaunch& a) {
             if (e != hipSuccess) return;
         }
         if (a.inverse) {
-            // Chili channels have no inverse here (refused by the entry points)
-            if constexpr (!MIX && !(K & KIND_CHILI)) {
+            if constexpr (!MIX) {
                 const size_t li = a.lds + sizeof(double) * stage_rows<NS, NI>() * kBlock;
                 if (li > 65536) {
                     hipError_t e = hipFuncSetAttribute((const void*)k_inverse<NS, NI, K>,

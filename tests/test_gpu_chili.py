@@ -1,7 +1,8 @@
 """Chili channels (section 2.4) on the GPU against the oracle: per-event
 momenta, momentum fractions, Jacobians and weights through the map and the
 fused multichannel sample (also mixed with tree channels under local channel
-weights), the closed-form hadronic volume, and the refused inverse."""
+weights), the closed-form hadronic volume, the inverse map and the
+multichannel density."""
 import math
 
 import numpy as np
@@ -115,17 +116,88 @@ def test_chili_volume(torch):
         ctx.close()
 
 
-def test_chili_refusals(torch):
-    from paper_2602_06895_amd import Context, MsxError
+@pytest.mark.parametrize("name,mk,vegas", CASES)
+def test_chili_inverse_matches_oracle(torch, name, mk, vegas):
+    """Inverse map against the oracle's inverse on the same momenta (bound:
+    the oracle's own forward-error spread, as for the tree channels), and
+    the density (forward Jacobian at the GPU's y) against the oracle's."""
+    from paper_2602_06895_amd import Context
+
+    desc = mk()
+    ctx = Context(desc)
+    orc = oracle.Process(desc)
+    d = ctx.dims[0]
+    grid = _random_grid(d, orc.nbins, 7) if vegas else orc.uniform_grid(0)
+    ctx.set_grid(0, grid)
+    y = W.philox_uniforms(23, 1, 0, 20001, d)
+    fwd = orc.map(0, y, grid)
+    ok = fwd["jac"] > 0
+    ref = orc.inverse(0, fwd["p"], fwd["x1x2"], grid)
+    fe = orc.inverse_forward_error(0, fwd["p"], fwd["x1x2"], grid, ref)
+    out = ctx.inverse_map(0, torch.from_numpy(fwd["p"]).cuda(), torch.from_numpy(fwd["x1x2"]).cuda())
+    torch.cuda.synchronize()
+    yg, jg = out["y"].cpu().numpy(), out["jac"].cpu().numpy()
+    dy = np.abs(yg - ref["y"]).max(axis=0)[ok]
+    fy = fe["y"][ok]
+    assert np.all(dy <= np.maximum(1e-12, 1000.0 * fy)), (name, float(np.max(dy / np.maximum(fy, 1e-15))))
+    assert np.mean(dy > np.maximum(1e-12, 100.0 * fy)) <= 1e-3
+    assert np.median(np.abs(yg - y).max(axis=0)[ok]) < 1e-13
+    at = orc.map(0, yg, grid)
+    fef = orc.forward_error(0, yg, grid, ref=at)
+    keep = ok & (at["jac"] > 0)
+    dj = np.abs(jg[keep] / at["jac"][keep] - 1.0)
+    assert np.all(dj <= np.maximum(1e-12, 1000.0 * fef["jac"][keep]))
+    ctx.close()
+
+
+def test_chili_density_with_tree_channels(torch):
+    """g(p) = sum_c alpha_c / J_c(y_c(p)) over the eight pp -> 4 jets tree
+    channels and a Chili channel, for events of the Chili channel and of a
+    tree channel, against the oracle's density."""
+    from paper_2602_06895_amd import Context
+
+    desc = W.c2_pp4j()
+    desc["channels"] = desc["channels"] + [{"chili": True}]
+    ctx = Context(desc)
+    orc = oracle.Process(desc)
+    alpha = np.array([0.1] * 8 + [0.2])
+    for chan in (8, 3):
+        y = W.philox_uniforms(43, chan, 0, 20001, orc.dims[chan])
+        fwd = orc.map(chan, y)
+        ok = fwd["jac"] > 0
+        g_ref = orc.multichannel_density(fwd["p"], fwd["x1x2"], alpha)
+        g = ctx.multichannel_density(0, torch.from_numpy(fwd["p"]).cuda(), torch.from_numpy(fwd["x1x2"]).cuda(),
+                                     alpha)
+        torch.cuda.synchronize()
+        with np.errstate(invalid="ignore", divide="ignore"):  # g = 0 on events every channel cuts
+            fe = np.max([np.abs(orc.multichannel_density(fwd["p"], fwd["x1x2"], alpha, variant=v) / g_ref - 1.0)
+                         for v in ("x87", "up", "down")], axis=0)[ok]
+        r = np.abs(g.cpu().numpy()[ok] / g_ref[ok] - 1.0)
+        assert np.all(r <= np.maximum(1e-12, 1000.0 * fe)), (chan, float(np.max(r / np.maximum(fe, 1e-15))))
+        assert np.median(r) < 1e-12
+    ctx.close()
+
+
+def test_chili_round_trip_at_scale(torch):
+    """1e6 pp -> 4 jets Chili events through the GPU forward map and back."""
+    from paper_2602_06895_amd import Context
 
     ctx = Context(_pp4j_chili())
-    p = torch.zeros(4, 6, 8, dtype=torch.float64, device="cuda")
-    x = torch.full((2, 8), 0.5, dtype=torch.float64, device="cuda")
-    with pytest.raises(MsxError):
-        ctx.inverse_map(0, p, x)
-    with pytest.raises(MsxError):
-        ctx.multichannel_density(0, p, x, np.ones(1))
+    y = ctx.uniform(5, 9, 0, 1_000_000, ctx.dims[0])
+    fwd = ctx.map(0, y)
+    inv = ctx.inverse_map(0, fwd["p"], fwd["x1x2"])
+    torch.cuda.synchronize()
+    ok = fwd["jac"] > 0
+    err = (inv["y"] - y).abs().amax(dim=0)[ok]
+    jr = (inv["jac"][ok] / fwd["jac"][ok] - 1.0).abs()
+    assert float(err.median()) < 1e-14 and float(err.max()) < 1e-7
+    assert float(jr.median()) < 1e-14 and float(jr.max()) < 1e-7
     ctx.close()
+
+
+def test_chili_lepton_beams_refused(torch):
+    from paper_2602_06895_amd import Context, MsxError
+
     d = W.chili_process(3)
     d["beams"] = "fixed"
     with pytest.raises(MsxError):

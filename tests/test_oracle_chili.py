@@ -134,3 +134,28 @@ def test_lepton_beams_refused():
     d["beams"] = "fixed"
     with pytest.raises(ValueError):
         oracle.Process(d)
+
+
+@pytest.mark.parametrize("case", ["cut", "nocut"])
+def test_inverse_round_trip(case):
+    """The inverse recovers the uniforms (through a VEGAS grid) and the
+    forward Jacobian at them: median at the unit roundoff, every event
+    within what the ill-conditioned recoveries (small p_T, large |y|) allow."""
+    if case == "cut":
+        d = W.chili_process(4, 13000.0, pt_min=20.0, masses=[5.0, 0.0, 80.0, 0.0], pdf=[-1.2, 3.0])
+    else:
+        d = W.chili_process(3, 1000.0, masses=[0.0, 10.0, 80.0])
+    o = oracle.Process(d)
+    dim = o.dims[0]
+    rng = np.random.default_rng(3)
+    g = np.empty((dim, o.nbins + 1))
+    for k in range(dim):
+        g[k] = np.concatenate([[0.0], np.sort(rng.random(o.nbins - 1)), [1.0]])
+    y = W.philox_uniforms(2, 0, 0, 100_000, dim)
+    f = o.map(0, y, g)
+    ok = f["jac"] > 0
+    inv = o.inverse(0, f["p"], f["x1x2"], g)
+    err = np.abs(inv["y"] - y).max(axis=0)[ok]
+    assert np.median(err) < 1e-14 and np.quantile(err, 0.99) < 1e-12 and err.max() < 1e-8
+    jr = np.abs(inv["jac"][ok] / f["jac"][ok] - 1.0)
+    assert np.median(jr) < 1e-14 and jr.max() < 1e-8

@@ -249,8 +249,10 @@ class ChannelTree:
                 self.rambo.append(0)
             else:
                 kids = leg["d"]
-                if len(kids) != 2:
-                    raise ValueError("a cluster decays into exactly two children")
+                if len(kids) not in (2, 3):
+                    raise ValueError("a cluster decays into two or three children")
+                if len(kids) == 3 and leg.get("rambo"):
+                    raise ValueError("a FastRambo cluster decays into two children")
                 self.kind.append(CLUSTER)
                 self.particle.append(-1)
                 self.mass.append(float(leg.get("m", 0.0)))
@@ -311,7 +313,9 @@ class ChannelTree:
             if not hadronic:
                 raise ValueError("a Chili channel samples x1, x2 from the momenta: hadronic beams only")
             return 3 * self.n_final - 2
-        d = len(self.s_order) + max(self.kappa - 1, 0) + 2 * self.kappa + 2 * len(self.dec_order)
+        # (phi, theta) per two-body decay, (E1, E2, phi, theta, beta) per 1 -> 3
+        dec = sum(5 if len(self.children[j]) == 3 else 2 for j in self.dec_order)
+        d = len(self.s_order) + max(self.kappa - 1, 0) + 2 * self.kappa + dec
         return d + (2 if hadronic else 0)
 
     def propagators(self):

@@ -262,6 +262,54 @@ double orc_two_body_decay(const double P[4], double m0sq, double m1, double m2,
     return sqrt(lam) / (8.0 * m0sq) * (2.0 * ORC_PI) * 2.0;
 }
 
+/* Three-body decay P -> p1 + p2 + p3 (section 2.2.6): in the rest frame of P
+ * (mass^2 m0sq) the energies E1 in [m1, E1max] and E2 in [E2min, E2max](E1)
+ * linearly in r_e1, r_e2; the direction of p1 from (phi, cos theta) =
+ * (2 pi r_phi, 2 r_theta - 1); p2 at the angle alpha to p1 that momentum
+ * conservation fixes, turned by beta = 2 pi r_beta about p1; p3 = P - p1 -
+ * p2; all boosted to the frame of P.  Returns the measure factor
+ * (1/8) dE1 dE2 dphi dbeta dcos(theta) = pi^2 (E1max - m1)(E2max - E2min),
+ * or 0 when the E2 range is empty. */
+double orc_three_body_decay(const double P[4], double m0sq, double m1, double m2, double m3, const double r[5],
+                            double p1[4], double p2[4], double p3[4])
+{
+    const double m0 = sqrt(m0sq);
+    const double e1max = 0.5 * m0 + (m1 * m1 - (m2 + m3) * (m2 + m3)) / (2.0 * m0);
+    const double e1 = m1 + (e1max - m1) * r[0];
+    const double q1 = sqrt(fmax(0.0, e1 * e1 - m1 * m1));
+    /* the invariant mass^2 of p2 + p3, and the E2 range from its two-body
+     * decay seen from the rest frame of P */
+    const double dl = 2.0 * m0 * (0.5 * m0 - e1) + m1 * m1;
+    const double d23 = m2 * m2 - m3 * m3;
+    const double root = sqrt(fmax(0.0, q1 * q1 * ((dl + d23) * (dl + d23) - 4.0 * m2 * m2 * dl)));
+    const double e2min = ((m0 - e1) * (dl + d23) - root) / (2.0 * dl);
+    const double e2max = ((m0 - e1) * (dl + d23) + root) / (2.0 * dl);
+    const double e2 = e2min + (e2max - e2min) * r[1];
+    const double q2 = sqrt(fmax(0.0, e2 * e2 - m2 * m2));
+    double ca = (2.0 * m0 * (0.5 * m0 - e1 - e2) + m1 * m1 + m2 * m2 + 2.0 * e1 * e2 - m3 * m3) / (2.0 * q1 * q2);
+    if (!(ca >= -1.0)) ca = -1.0; /* rounding at the ends of the range (and 0/0) */
+    if (ca > 1.0) ca = 1.0;
+    const double sa = sqrt((1.0 - ca) * (1.0 + ca));
+    const double phi = 2.0 * ORC_PI * r[2];
+    const double ct = 2.0 * r[3] - 1.0;
+    const double st = sqrt((1.0 - ct) * (1.0 + ct));
+    const double beta = 2.0 * ORC_PI * r[4];
+    const double cp = cos(phi), sp = sin(phi), cb = cos(beta), sb = sin(beta);
+    /* R(phi, theta) = R_z(phi) R_y(theta) applied to a unit vector v */
+    double v[3] = {cb * sa, sb * sa, ca};
+    double w[3] = {ct * v[0] + st * v[2], v[1], -st * v[0] + ct * v[2]};
+    double u2[3] = {cp * w[0] - sp * w[1], sp * w[0] + cp * w[1], w[2]};
+    double u1[3] = {cp * st, sp * st, ct};
+    double k1[4] = {e1, q1 * u1[0], q1 * u1[1], q1 * u1[2]};
+    double k2[4] = {e2, q2 * u2[0], q2 * u2[1], q2 * u2[2]};
+    double k3[4] = {m0 - e1 - e2, -k1[1] - k2[1], -k1[2] - k2[2], -k1[3] - k2[3]};
+    orc_boost(P, m0, k1, p1);
+    orc_boost(P, m0, k2, p2);
+    orc_boost(P, m0, k3, p3);
+    const double jac = ORC_PI * ORC_PI * (e1max - m1) * (e2max - e2min);
+    return jac > 0.0 ? jac : 0.0;
+}
+
 /* -t range of a 2->2 block (the t_inv_min_max operation): eq. t_invariant_theta
  * at cos(theta) = +1 and -1, for invariants m0^2 = (p_A + p_B)^2, ma^2 = p_A^2,
  * mb^2 = p_B^2 and outgoing masses m1, m2.  The root of smaller magnitude
@@ -654,6 +702,15 @@ static void event(const orc_process* pr, const orc_channel* ch, int32_t chan,
         int32_t c = ch->dec_order[q];
         int32_t c0 = ch->children[ch->child_start[c]], c1 = ch->children[ch->child_start[c] + 1];
         double m1 = node_m_min(ch, c0, sampled, s), m2 = node_m_min(ch, c1, sampled, s);
+        if (ch->child_count[c] == 3) {
+            /* 1 -> 3 decay: dimensions (E1, E2, phi, theta, beta) */
+            int32_t c2 = ch->children[ch->child_start[c] + 2];
+            double m3 = node_m_min(ch, c2, sampled, s);
+            double jd = orc_three_body_decay(mom[c], s[c], m1, m2, m3, r + k, mom[c0], mom[c1], mom[c2]);
+            k += 5;
+            factors[nf++] = jd;
+            continue;
+        }
         double r_phi = r[k++], r_theta = r[k++];
         double jd = orc_two_body_decay(mom[c], s[c], m1, m2, r_phi, r_theta, mom[c0], mom[c1]);
         factors[nf++] = jd;
@@ -1150,6 +1207,37 @@ static int32_t inverse_event(const orc_process* pr, const orc_channel* ch, doubl
         double Pbar[4] = {mom[c][0], -mom[c][1], -mom[c][2], -mom[c][3]};
         double kk[4];
         orc_boost(Pbar, m0, mom[c0], kk);
+        if (ch->child_count[c] == 3) {
+            /* 1 -> 3 decay (section 2.2.6): E1, E2 and the angles of p1 and of
+             * p2 about p1 in the rest frame of the parent */
+            int32_t c1 = ch->children[ch->child_start[c] + 1], c2 = ch->children[ch->child_start[c] + 2];
+            double m1 = node_m_min(ch, c0, sampled, s), m2 = node_m_min(ch, c1, sampled, s);
+            double m3 = node_m_min(ch, c2, sampled, s);
+            double k2[4];
+            orc_boost(Pbar, m0, mom[c1], k2);
+            const double e1 = kk[0], e2 = k2[0];
+            const double e1max = 0.5 * m0 + (m1 * m1 - (m2 + m3) * (m2 + m3)) / (2.0 * m0);
+            r[k++] = (e1 - m1) / (e1max - m1);
+            const double q1sq = e1 * e1 - m1 * m1;
+            const double dl = 2.0 * m0 * (0.5 * m0 - e1) + m1 * m1;
+            const double d23 = m2 * m2 - m3 * m3;
+            const double root = sqrt(fmax(0.0, q1sq * ((dl + d23) * (dl + d23) - 4.0 * m2 * m2 * dl)));
+            const double e2min = ((m0 - e1) * (dl + d23) - root) / (2.0 * dl);
+            const double e2max = ((m0 - e1) * (dl + d23) + root) / (2.0 * dl);
+            r[k++] = (e2 - e2min) / (e2max - e2min);
+            const double len = sqrt(kk[1] * kk[1] + kk[2] * kk[2] + kk[3] * kk[3]);
+            const double ux = kk[1] / len, uy = kk[2] / len, uz = kk[3] / len;
+            r[k++] = turn_fraction(ux, uy);
+            r[k++] = 0.5 * (uz + 1.0);
+            /* p2 in the frame where p1 is along z: R(phi, theta)^-1 =
+             * R_y(-theta) R_z(-phi) */
+            const double st = sqrt(ux * ux + uy * uy);
+            const double cp = st > 0.0 ? ux / st : 1.0, sp = st > 0.0 ? uy / st : 0.0;
+            const double ax = cp * k2[1] + sp * k2[2], ay = -sp * k2[1] + cp * k2[2], az = k2[3];
+            const double bx = uz * ax - st * az, by = ay;
+            r[k++] = turn_fraction(bx, by);
+            continue;
+        }
         double len = sqrt(kk[1] * kk[1] + kk[2] * kk[2] + kk[3] * kk[3]);
         r[k++] = turn_fraction(kk[1], kk[2]);
         r[k++] = 0.5 * (kk[3] / len + 1.0);
@@ -1181,6 +1269,10 @@ int orc_inverse(const orc_process* pr, const orc_channel* ch, int32_t chan, int3
         }
         double r[ORC_MAX_DIMS], ye[ORC_MAX_DIMS];
         int32_t k = ch->chili ? inverse_chili(pr, pl, r) : inverse_event(pr, ch, pl, x1, x2, r);
+        if (k < 0) {
+            bad = 1;
+            continue;
+        }
         if (k != dims) {
             bad = 1;
             continue;

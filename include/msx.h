@@ -67,12 +67,14 @@
  *                   the lab-frame p_T, rapidities and relative azimuths.
  *                 A leg is a particle label or a cluster
  *                 {"d": [child, child], "m", "w", "nu", "order", "rambo"};
+ *                 "d" with three children makes a 1 -> 3 decay (section
+ *                 2.2.6: dimensions E1, E2, phi, theta, beta);
  *                 "rambo": true samples the cluster's mass with the
  *                 FastRambo map of its particle count (section 2.2.9).
  * Random-number dimensions of a tree channel, in order: s-hat (hadronic), the
  * cluster invariants in sampling order, the kappa-1 t-channel invariants,
- * x1 (hadronic), (r_phi, r_t) per 2->2 block, (r_phi, r_theta) per decay in
- * depth-first order -- the order of the paper's compute-graph example
+ * x1 (hadronic), (r_phi, r_t) per 2->2 block, (r_phi, r_theta) per decay
+ * (five numbers per 1 -> 3 decay) in depth-first order -- the order of the paper's compute-graph example
  * (section 3.2.1).
  */
 #ifndef MSX_H

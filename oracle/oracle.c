@@ -269,22 +269,26 @@ double orc_two_body_decay(const double P[4], double m0sq, double m1, double m2,
  * conservation fixes, turned by beta = 2 pi r_beta about p1; p3 = P - p1 -
  * p2; all boosted to the frame of P.  Returns the measure factor
  * (1/8) dE1 dE2 dphi dbeta dcos(theta) = pi^2 (E1max - m1)(E2max - E2min),
- * or 0 when the E2 range is empty. */
+ * or 0 when the E2 range is empty; both widths are formed without
+ * subtracting the range ends. */
 double orc_three_body_decay(const double P[4], double m0sq, double m1, double m2, double m3, const double r[5],
                             double p1[4], double p2[4], double p3[4])
 {
     const double m0 = sqrt(m0sq);
-    const double e1max = 0.5 * m0 + (m1 * m1 - (m2 + m3) * (m2 + m3)) / (2.0 * m0);
-    const double e1 = m1 + (e1max - m1) * r[0];
+    /* E1max - m1 = ((m0 - m1)^2 - (m2 + m3)^2) / (2 m0), factored so that it
+     * does not cancel near threshold */
+    const double w1 = (m0 - m1 - (m2 + m3)) * (m0 - m1 + (m2 + m3)) / (2.0 * m0);
+    const double e1 = m1 + w1 * r[0];
     const double q1 = sqrt(fmax(0.0, e1 * e1 - m1 * m1));
     /* the invariant mass^2 of p2 + p3, and the E2 range from its two-body
      * decay seen from the rest frame of P */
     const double dl = 2.0 * m0 * (0.5 * m0 - e1) + m1 * m1;
     const double d23 = m2 * m2 - m3 * m3;
     const double root = sqrt(fmax(0.0, q1 * q1 * ((dl + d23) * (dl + d23) - 4.0 * m2 * m2 * dl)));
+    /* E2max - E2min = root / dl exactly: the width without the difference */
     const double e2min = ((m0 - e1) * (dl + d23) - root) / (2.0 * dl);
-    const double e2max = ((m0 - e1) * (dl + d23) + root) / (2.0 * dl);
-    const double e2 = e2min + (e2max - e2min) * r[1];
+    const double w2 = root / dl;
+    const double e2 = e2min + w2 * r[1];
     const double q2 = sqrt(fmax(0.0, e2 * e2 - m2 * m2));
     double ca = (2.0 * m0 * (0.5 * m0 - e1 - e2) + m1 * m1 + m2 * m2 + 2.0 * e1 * e2 - m3 * m3) / (2.0 * q1 * q2);
     if (!(ca >= -1.0)) ca = -1.0; /* rounding at the ends of the range (and 0/0) */
@@ -306,7 +310,7 @@ double orc_three_body_decay(const double P[4], double m0sq, double m1, double m2
     orc_boost(P, m0, k1, p1);
     orc_boost(P, m0, k2, p2);
     orc_boost(P, m0, k3, p3);
-    const double jac = ORC_PI * ORC_PI * (e1max - m1) * (e2max - e2min);
+    const double jac = ORC_PI * ORC_PI * w1 * w2;
     return jac > 0.0 ? jac : 0.0;
 }
 
@@ -1216,15 +1220,14 @@ static int32_t inverse_event(const orc_process* pr, const orc_channel* ch, doubl
             double k2[4];
             orc_boost(Pbar, m0, mom[c1], k2);
             const double e1 = kk[0], e2 = k2[0];
-            const double e1max = 0.5 * m0 + (m1 * m1 - (m2 + m3) * (m2 + m3)) / (2.0 * m0);
-            r[k++] = (e1 - m1) / (e1max - m1);
+            const double w1 = (m0 - m1 - (m2 + m3)) * (m0 - m1 + (m2 + m3)) / (2.0 * m0);
+            r[k++] = (e1 - m1) / w1;
             const double q1sq = e1 * e1 - m1 * m1;
             const double dl = 2.0 * m0 * (0.5 * m0 - e1) + m1 * m1;
             const double d23 = m2 * m2 - m3 * m3;
             const double root = sqrt(fmax(0.0, q1sq * ((dl + d23) * (dl + d23) - 4.0 * m2 * m2 * dl)));
             const double e2min = ((m0 - e1) * (dl + d23) - root) / (2.0 * dl);
-            const double e2max = ((m0 - e1) * (dl + d23) + root) / (2.0 * dl);
-            r[k++] = (e2 - e2min) / (e2max - e2min);
+            r[k++] = (e2 - e2min) / (root / dl);
             const double len = sqrt(kk[1] * kk[1] + kk[2] * kk[2] + kk[3] * kk[3]);
             const double ux = kk[1] / len, uy = kk[2] / len, uz = kk[3] / len;
             r[k++] = turn_fraction(ux, uy);

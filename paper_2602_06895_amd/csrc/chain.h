@@ -94,7 +94,8 @@ enum : int {
     KIND_BW = 16,      // Breit-Wigner
     KIND_RAMBO = 32,   // FastRambo cluster masses
     KINDS_ALL = 63,    // every tree-channel map kind
-    KIND_CHILI = 64    // Chili channels (compiled only for processes that use them)
+    KIND_CHILI = 64,   // Chili channels (compiled only for processes that use them)
+    KIND_DEC3 = 128    // 1 -> 3 decays (likewise)
 };
 
 // Precision of the well-conditioned transcendentals (power laws, exp, log,
@@ -375,6 +376,56 @@ __device__ __forceinline__ double masked_sum(uint32_t mask, const double (&SQ)[N
     return s;
 }
 
+// 1 -> 3 decay (section 2.2.6) in the rest frame of the parent (mass m0):
+// E1 linear in [m1, E1max], E2 linear in [E2min, E2max] (the range of the
+// two-body decay of p2 + p3, of mass^2 m0^2 - 2 m0 E1 + m1^2, seen from the
+// parent's rest frame), p1 along R(phi, theta) z, p2 along R(phi, theta)
+// R(beta, alpha) z with cos(alpha) fixed by momentum conservation, p3 the
+// rest.  Random numbers (E1, E2, phi, theta, beta).  Returns the measure
+// (1/8) dE1 dE2 dphi dbeta dcos(theta) = pi^2 (E1max - m1)(E2max - E2min).
+// FP64 in both precisions.
+__device__ __forceinline__ double three_body_rest(double m0, double m1, double m2, double m3, const double (&r)[5],
+                                                  double (&k1)[4], double (&k2)[4], double (&k3)[4]) {
+    // E1max - m1 = ((m0 - m1)^2 - (m2 + m3)^2) / (2 m0), factored (no
+    // cancellation near threshold)
+    const double w1 = (m0 - m1 - (m2 + m3)) * (m0 - m1 + (m2 + m3)) / (2.0 * m0);
+    const double e1 = m1 + w1 * r[0];
+    const double q1 = sqrt(fmax(0.0, e1 * e1 - m1 * m1));
+    const double dl = 2.0 * m0 * (0.5 * m0 - e1) + m1 * m1;
+    const double d23 = m2 * m2 - m3 * m3;
+    const double root = sqrt(fmax(0.0, q1 * q1 * ((dl + d23) * (dl + d23) - 4.0 * m2 * m2 * dl)));
+    // E2max - E2min = root / dl exactly (no difference of the range ends)
+    const double e2min = ((m0 - e1) * (dl + d23) - root) / (2.0 * dl);
+    const double w2 = root / dl;
+    const double e2 = e2min + w2 * r[1];
+    const double q2 = sqrt(fmax(0.0, e2 * e2 - m2 * m2));
+    double ca = (2.0 * m0 * (0.5 * m0 - e1 - e2) + m1 * m1 + m2 * m2 + 2.0 * e1 * e2 - m3 * m3) / (2.0 * q1 * q2);
+    ca = ca >= -1.0 ? fmin(ca, 1.0) : -1.0;  // rounding at the range ends (and 0/0)
+    const double sa = sqrt((1.0 - ca) * (1.0 + ca));
+    const double ct = 2.0 * r[3] - 1.0;
+    const double st = sqrt((1.0 - ct) * (1.0 + ct));
+    double sp, cp, sb, cb;
+    sincos(2.0 * kPiD * r[2], &sp, &cp);
+    sincos(2.0 * kPiD * r[4], &sb, &cb);
+    // R(phi, theta) = R_z(phi) R_y(theta) on v = R(beta, alpha) z
+    const double vx = cb * sa, vy = sb * sa, vz = ca;
+    const double wx = ct * vx + st * vz, wy = vy, wz = -st * vx + ct * vz;
+    k1[0] = e1;
+    k1[1] = q1 * (cp * st);
+    k1[2] = q1 * (sp * st);
+    k1[3] = q1 * ct;
+    k2[0] = e2;
+    k2[1] = q2 * (cp * wx - sp * wy);
+    k2[2] = q2 * (sp * wx + cp * wy);
+    k2[3] = q2 * wz;
+    k3[0] = m0 - e1 - e2;
+    k3[1] = -k1[1] - k2[1];
+    k3[2] = -k1[2] - k2[2];
+    k3[3] = -k1[3] - k2[3];
+    const double jac = kPiD * kPiD * w1 * w2;
+    return jac > 0.0 ? jac : 0.0;
+}
+
 // The mapping chain.  next() returns the VEGAS-mapped random number of the
 // next dimension (dimensions are consumed in order).  Leaves the final-state
 // momenta in the partonic frame in the slots.
@@ -533,6 +584,42 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
     for (int di = 0; di < NS / 2; ++di) {
         if (di >= n_dec) break;
         const DecaySpec& ds = ct->dec[di];
+        if (KINDS & KIND_DEC3) {
+            if (ds.kind == 2) continue;  // the slots of the 1 -> 3 decay before
+            if (ds.kind == 1) {
+                const double m0 = SQ[ds.parent_inv];
+                double rr[5];
+#pragma unroll
+                for (int q = 0; q < 5; ++q) rr[q] = next();
+                double k1[4], k2[4], k3[4];
+                jac *= three_body_rest(m0, src_mass(ds.m1, SQ), src_mass(ds.m2, SQ), src_mass(ds.m3, SQ), rr, k1,
+                                       k2, k3);
+                if (!ds.parent_rest) {
+                    const int ps = slot_index<NS>(ds.parent_slot);
+                    double Pe = E[ps], Px = X[ps], Py = Y[ps], Pz = Z[ps];
+                    const double inv_m = 1.0 / m0, inv_em = 1.0 / (Pe + m0);
+                    boost_by(Pe, Px, Py, Pz, inv_m, inv_em, k1[0], k1[1], k1[2], k1[3]);
+                    boost_by(Pe, Px, Py, Pz, inv_m, inv_em, k2[0], k2[1], k2[2], k2[3]);
+                    boost_by(Pe, Px, Py, Pz, inv_m, inv_em, k3[0], k3[1], k3[2], k3[3]);
+                }
+                // a 1 -> 3 decay is never the last entry (its pair follows),
+                // so the third slot index is >= 0 whenever this runs
+                const int s3 = NS - 4 - 2 * di >= 0 ? NS - 4 - 2 * di : 0;
+                E[NS - 2 - 2 * di] = k1[0];
+                X[NS - 2 - 2 * di] = k1[1];
+                Y[NS - 2 - 2 * di] = k1[2];
+                Z[NS - 2 - 2 * di] = k1[3];
+                E[NS - 1 - 2 * di] = k2[0];
+                X[NS - 1 - 2 * di] = k2[1];
+                Y[NS - 1 - 2 * di] = k2[2];
+                Z[NS - 1 - 2 * di] = k2[3];
+                E[s3] = k3[0];
+                X[s3] = k3[1];
+                Y[s3] = k3[2];
+                Z[s3] = k3[3];
+                continue;
+            }
+        }
         double m0sq = S[ds.parent_inv];
         double m0 = SQ[ds.parent_inv];
         double m1 = src_mass(ds.m1, SQ), m2 = src_mass(ds.m2, SQ);

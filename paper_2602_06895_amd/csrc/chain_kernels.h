@@ -23,8 +23,10 @@ constexpr size_t kQBytes = sizeof(double) * kQRows * kBlock;
 // The fused sample kernel first writes the VEGAS-mapped uniforms of all an
 // event's dimensions into the same per-thread column (the chain reads them
 // back in order; the integrand's invariant store reuses the column after the
-// chain is done).  A channel of an (NS, NI) class has at most NS + NI + 1
-// dimensions: s-hat and x1, the time-like invariants and two per operation.
+// chain is done).  The channel compiler admits a channel of an (NS, NI)
+// class only with at most max(kQRows, NS + NI + 1) dimensions (s-hat and x1,
+// the time-like invariants and two per two-body operation fit NS + NI + 1; a
+// 1 -> 3 decay takes five for its four slots, a Chili channel 3 n - 2).
 template <int NS, int NI>
 constexpr int stage_rows() {
     return (NS + NI + 1) > kQRows ? (NS + NI + 1) : kQRows;
@@ -468,13 +470,39 @@ __global__ __launch_bounds__(kBlock) void k_inverse(const ChannelTab* __restrict
             for (int di = 0; di < NS / 2; ++di) {
                 if (di >= n_dec) break;
                 const DecaySpec& ds = ct->dec[di];
+                if ((KINDS & KIND_DEC3) && ds.kind == 2) continue;
                 double ke, kx, ky, kz;
                 sum_set<NF>(ds.set1, FE, FX, FY, FZ, ke, kx, ky, kz);
+                double Pe = 0.0, Px = 0.0, Py = 0.0, Pz = 0.0;
+                const double m0 = SQ[ds.parent_inv];
                 if (!ds.parent_rest) {
-                    double Pe, Px, Py, Pz;
                     sum_set<NF>(ds.parent_set, FE, FX, FY, FZ, Pe, Px, Py, Pz);
-                    const double m0 = SQ[ds.parent_inv];
                     boost_by(Pe, -Px, -Py, -Pz, 1.0 / m0, 1.0 / (Pe + m0), ke, kx, ky, kz);
+                }
+                if ((KINDS & KIND_DEC3) && ds.kind == 1) {
+                    // 1 -> 3: E1, E2, the direction of p1, and the azimuth of
+                    // p2 about p1 (p2 turned by R(phi, theta)^-1 = R_y(-theta) R_z(-phi))
+                    double qe, qx, qy, qz;
+                    sum_set<NF>(ds.set2, FE, FX, FY, FZ, qe, qx, qy, qz);
+                    if (!ds.parent_rest) boost_by(Pe, -Px, -Py, -Pz, 1.0 / m0, 1.0 / (Pe + m0), qe, qx, qy, qz);
+                    const double m1 = src_mass(ds.m1, SQ), m2 = src_mass(ds.m2, SQ), m3 = src_mass(ds.m3, SQ);
+                    const double w1 = (m0 - m1 - (m2 + m3)) * (m0 - m1 + (m2 + m3)) / (2.0 * m0);
+                    put((ke - m1) / w1);
+                    const double q1sq = ke * ke - m1 * m1;
+                    const double dl = 2.0 * m0 * (0.5 * m0 - ke) + m1 * m1;
+                    const double d23 = m2 * m2 - m3 * m3;
+                    const double root = sqrt(fmax(0.0, q1sq * ((dl + d23) * (dl + d23) - 4.0 * m2 * m2 * dl)));
+                    const double e2min = ((m0 - ke) * (dl + d23) - root) / (2.0 * dl);
+                    put((qe - e2min) / (root / dl));
+                    const double len = sqrt(kx * kx + ky * ky + kz * kz);
+                    const double ux = kx / len, uy = ky / len, uz = kz / len;
+                    put(turn_fraction(ux, uy));
+                    put(0.5 * (uz + 1.0));
+                    const double st = sqrt(ux * ux + uy * uy);
+                    const double cp = st > 0.0 ? ux / st : 1.0, sp = st > 0.0 ? uy / st : 0.0;
+                    const double ax = cp * qx + sp * qy, ay = -sp * qx + cp * qy;
+                    put(turn_fraction(uz * ax - st * qz, ay));
+                    continue;
                 }
                 const double len = sqrt(kx * kx + ky * ky + kz * kz);
                 put(turn_fraction(kx, ky));
@@ -488,10 +516,11 @@ __global__ __launch_bounds__(kBlock) void k_inverse(const ChannelTab* __restrict
 
 // Launch of one register class: kind class `kc` picks the compiled map kinds
 // (0: integer-root power laws, 1: plus Breit-Wigner, 2: all tree kinds,
-// 3: all, with Chili channels).
+// 3: all, with Chili channels and 1 -> 3 decays).
 template <int NS, int NI, bool MIX>
 hipError_t launch_chain_class(int kc, const ChainLaunch& a) {
-    constexpr int K0 = KIND_POW_INT, K1 = KIND_POW_INT | KIND_BW, K2 = KINDS_ALL, K3 = KINDS_ALL | KIND_CHILI;
+    constexpr int K0 = KIND_POW_INT, K1 = KIND_POW_INT | KIND_BW, K2 = KINDS_ALL;
+    constexpr int K3 = KINDS_ALL | KIND_CHILI | KIND_DEC3;
     auto go = [&](auto kt) {
         constexpr int K = decltype(kt)::value;
         const size_t lds = a.lds + (a.sample ? sizeof(double) * stage_rows<NS, NI>() * kBlock : kQBytes);

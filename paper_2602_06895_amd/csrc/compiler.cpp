@@ -111,8 +111,8 @@ struct ChannelBuilder {
             return -1;
         }
         const JValue* d = leg.get("d");
-        if (!d || d->kind != JValue::ARR || d->arr.size() != 2) {
-            cx.fail("a cluster needs \"d\": [child, child]");
+        if (!d || d->kind != JValue::ARR || (d->arr.size() != 2 && d->arr.size() != 3)) {
+            cx.fail("a cluster needs \"d\": [child, child] or [child, child, child]");
             return -1;
         }
         nodes[idx].kind = N_CLUSTER;
@@ -120,6 +120,10 @@ struct ChannelBuilder {
         nodes[idx].w = num_or(leg, "w", 0.0);
         nodes[idx].nu = num_or(leg, "nu", nu_default);
         if (const JValue* rb = leg.get("rambo")) nodes[idx].rambo = rb->kind == JValue::BOOL && rb->b;
+        if (nodes[idx].rambo && d->arr.size() != 2) {
+            cx.fail("a FastRambo cluster decays into two children");
+            return -1;
+        }
         if (nodes[idx].m < 0.0 || nodes[idx].w < 0.0 || (nodes[idx].w > 0.0 && nodes[idx].m <= 0.0)) {
             cx.fail("cluster mass/width must be >= 0 (a width needs a mass)");
             return -1;
@@ -431,11 +435,15 @@ bool compile_channel(Ctx& cx, const JValue& cj, const std::vector<double>& masse
     t.n_inv = next_inv;
     t.n_blocks = kappa;
 
-    // (phi, theta) decays, depth-first, parents first
-    int nd = 0;
+    // (phi, theta) decays and 1 -> 3 decays, depth-first, parents first.  A
+    // 1 -> 3 decay takes two entries: its third child goes to the first slot
+    // of the second (decay d writes slot codes -2-2d, -1-2d), which keeps the
+    // slot count at 2 (n - 1) and every slot index a constant in the kernel.
+    int nd = 0, n3 = 0;
     for (size_t j = 0; j < nodes.size(); ++j) {
         if (nodes[j].kind != N_CLUSTER) continue;
-        if (nd >= kMaxFinal) return cx.fail("too many decays");
+        const bool three = nodes[j].kids.size() == 3;
+        if (nd + (three ? 1 : 0) >= kMaxFinal) return cx.fail("too many decays");
         DecaySpec& ds = t.dec[nd];
         ds.parent_rest = (j == 0) ? 1 : 0;
         ds.parent_slot = (j == 0) ? 0 : nodes[j].slot;
@@ -449,6 +457,19 @@ bool compile_channel(Ctx& cx, const JValue& cj, const std::vector<double>& masse
         ds.set2 = b.pmask(nodes[j].kids[1]);
         k0.slot = -2 - 2 * nd;
         k1.slot = -1 - 2 * nd;
+        ds.kind = 0;
+        if (three) {
+            Node& k2 = nodes[nodes[j].kids[2]];
+            ds.kind = 1;
+            ds.m3 = mass_src(k2);
+            ds.set3 = b.pmask(nodes[j].kids[2]);
+            k2.slot = -4 - 2 * nd;
+            DecaySpec& pad = t.dec[nd + 1];
+            std::memset(&pad, 0, sizeof pad);
+            pad.kind = 2;
+            ++nd;
+            ++n3;
+        }
         ++nd;
     }
     t.n_decays = nd;
@@ -460,7 +481,7 @@ bool compile_channel(Ctx& cx, const JValue& cj, const std::vector<double>& masse
     }
     // map kinds used (bit values as in the kernels: 1 integer-root power law,
     // 2 general power law, 4 log, 8 flat, 16 Breit-Wigner, 32 FastRambo;
-    // 64 marks a Chili channel)
+    // 64 marks a Chili channel, 128 a channel with 1 -> 3 decays)
     auto kind_bit = [](const MapParams& p) -> int32_t {
         switch (p.kind) {
             case MAP_POW: return p.int_pow ? 1 : 2;
@@ -474,10 +495,15 @@ bool compile_channel(Ctx& cx, const JValue& cj, const std::vector<double>& masse
     t.kinds = 0;
     for (int i = 0; i < t.n_inv; ++i) t.kinds |= kind_bit(t.inv[i].map);
     for (int i = 0; i < t.n_blocks; ++i) t.kinds |= kind_bit(t.blk[i].tmap);
-    t.dims = (hadronic ? 2 : 0) + (int)s_order.size() + std::max(kappa - 1, 0) + 2 * kappa + 2 * nd;
+    if (n3) t.kinds |= 128;
+    // two per two-body decay, five per 1 -> 3 decay (which holds two entries)
+    t.dims = (hadronic ? 2 : 0) + (int)s_order.size() + std::max(kappa - 1, 0) + 2 * kappa + 2 * (nd - 2 * n3) +
+             5 * n3;
     if (t.dims > kMaxDims) return cx.fail("too many random dimensions");
-    // the sample kernel's per-thread staging column is sized by this bound
-    if (t.dims > 1 + t.n_inv + t.n_slots) return cx.fail("internal: dimension count exceeds invariants + slots + 1");
+    // the sample kernel's per-thread staging column has at least
+    // max(kMaxUniq + 1, 1 + invariants + slots) rows
+    if (t.dims > std::max(kMaxUniq + 1, 1 + t.n_inv + t.n_slots))
+        return cx.fail("internal: dimension count exceeds the staging column");
 
     // propagators of the diagram (for the local channel weights)
     props.clear();

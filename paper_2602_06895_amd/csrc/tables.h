@@ -90,7 +90,11 @@ struct DecaySpec {
     int32_t parent_inv;   // m0^2 = s[parent_inv]
     uint32_t parent_set;  // final-state particles of the parent
     MassSrc m1, m2;
-    uint32_t set1, set2;  // final-state particles of the two children
+    uint32_t set1, set2;  // final-state particles of the first two children
+    int32_t kind;         // 0 two-body; 1 three-body (its third child takes the
+                          // first slot of the next entry); 2 that next entry
+    uint32_t set3;        // three-body: final-state particles of the third child
+    MassSrc m3;
 };
 
 struct ChannelTab {

@@ -325,6 +325,40 @@ def chili_report(n=10_000_000, reps=5):
                          "frac": ach / HBM_PEAK_GBS, "bytes_per_event": bpe}}
 
 
+def dec3_report(n=10_000_000, reps=5):
+    """pp -> t tbar -> 6 (the t tbar integrand) with each top decaying
+    1 -> 3 (E1, E2, angles; no W mapping) instead of through the W: fused
+    sample throughput, the integral and the per-event weight spread next to
+    the two-step decay chain's.  Bytes per event: momenta 8 x 4 x 8 + x1x2
+    16 + weight 8 + channel 4 = 284 B."""
+    import torch
+
+    import workloads as W
+    from paper_2602_06895_amd import Context
+
+    out_d = {}
+    mt, gt = 173.0, 1.5
+    for key in ("three_body", "two_body_chain"):
+        desc = W.c3_ttbar6()
+        if key == "three_body":
+            desc["channels"] = [{"s": {"d": [{"d": [1, 2, 3], "m": mt, "w": gt, "order": 1},
+                                             {"d": [4, 5, 6], "m": mt, "w": gt, "order": 2}]}}]
+        ctx = Context(desc)
+        counts = np.array([n])
+        out = ctx.sample(counts, seed=9, stream_id=1)
+        ms = _timed(lambda: ctx.sample(counts, seed=9, stream_id=1, out=out), reps)
+        w = out["w"]
+        torch.cuda.synchronize()
+        mean, std = float(w.mean()), float(w.std())
+        out_d[key] = {"events_per_s": n / (ms / 1e3), "ms": ms, "integral": mean, "rel_std_per_event": std / mean}
+        ctx.close()
+    bpe = 8 * 4 * 8 + 16 + 8 + 4
+    ach = n * bpe / (out_d["three_body"]["ms"] / 1e3) / 1e9
+    return {"workload": f"pp -> t tbar -> 6, 13 TeV, top decays 1 -> 3, {n} events", **out_d,
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "bytes_per_event": bpe}}
+
+
 def summarize(d: str, events: int, steps: int = 10):
     """Summary of the rocprofv3 runs under d (rocpd databases written by the
     commands printed below) for the last `steps` k_sample dispatches of
@@ -433,7 +467,7 @@ def main():
         return
     if args.inverse_only:
         print(json.dumps({"inverse_map": inverse_report(), "fastrambo": fastrambo_report(),
-                          "chili": chili_report()}))
+                          "chili": chili_report(), "dec3": dec3_report()}))
         return
     if args.copy_calibration:
         import torch
@@ -573,6 +607,7 @@ def main():
         torch.cuda.empty_cache()
         result["fastrambo"] = fastrambo_report()
         result["chili"] = chili_report()
+        result["decay_1to3"] = dec3_report()
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(desc, grids, counts, seed=1)
     print(json.dumps(result))

@@ -202,3 +202,25 @@ def test_chili_lepton_beams_refused(torch):
     d["beams"] = "fixed"
     with pytest.raises(MsxError):
         Context(d)
+
+
+def test_chili_mixed_precision(torch):
+    """In the mixed mode the Chili generator stays FP64 (momenta and
+    Jacobians as the oracle's); only the integrand's FP32 steps (toy PDFs)
+    move the weights, by a few FP32 ulp."""
+    from paper_2602_06895_amd import MIXED, Context
+
+    desc = _pp4j_chili()
+    ctx = Context(desc, precision=MIXED)
+    orc = oracle.Process(desc)
+    y = W.philox_uniforms(31, 1, 0, 50001, ctx.dims[0])
+    out = ctx.map(0, torch.from_numpy(y).cuda(), weight=True)
+    torch.cuda.synchronize()
+    ref = orc.map(0, y, orc.uniform_grid(0))
+    ok = (ref["w"] != 0) & (out["w"].cpu().numpy() != 0)
+    assert np.mean((ref["w"] != 0) != (out["w"].cpu().numpy() != 0)) < 1e-4
+    jr = np.abs(out["jac"].cpu().numpy()[ok] / ref["jac"][ok] - 1.0)
+    assert np.median(jr) < 1e-14 and np.quantile(jr, 0.999) < 1e-10
+    wr = np.abs(out["w"].cpu().numpy()[ok] / ref["w"][ok] - 1.0)
+    assert np.median(wr) < 1e-5 and np.quantile(wr, 0.99) < 1e-4
+    ctx.close()

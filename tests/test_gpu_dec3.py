@@ -137,3 +137,24 @@ def test_dec3_volume_and_round_trip(torch):
     err = (inv["y"] - y).abs().amax(dim=0)
     assert float(err.median()) < 1e-14 and float(err.max()) < 1e-7
     ctx.close()
+
+
+def test_dec3_mixed_precision(torch):
+    """Mixed mode with a three-body cluster on a t-channel spine: the 1 -> 3
+    decay is FP64, the tree's power-law, Breit-Wigner and angle steps FP32;
+    weights within the mixed mode's statement (median ~1e-6)."""
+    from paper_2602_06895_amd import MIXED, Context
+
+    desc = CASES[3][1]()
+    ctx = Context(desc, precision=MIXED)
+    orc = oracle.Process(desc)
+    y = W.philox_uniforms(37, 2, 0, 50001, ctx.dims[0])
+    out = ctx.map(0, torch.from_numpy(y).cuda(), weight=True)
+    torch.cuda.synchronize()
+    ref = orc.map(0, y, orc.uniform_grid(0))
+    wg = out["w"].cpu().numpy()
+    assert np.mean((ref["w"] != 0) != (wg != 0)) < 1e-3
+    ok = (ref["w"] != 0) & (wg != 0)
+    wr = np.abs(wg[ok] / ref["w"][ok] - 1.0)
+    assert np.median(wr) < 1e-4 and np.quantile(wr, 0.99) < 1e-2
+    ctx.close()

@@ -469,7 +469,7 @@ static double prop_q2(int32_t t_type, uint32_t set, const double pa[4], double m
     return mdot(q, q);
 }
 
-/* Integrand f (BASELINE toy: PDFs, pT cut, 1 + cos^2, propagator factors) and
+/* Integrand f (the toy integrand: PDFs, pT cut, 1 + cos^2, propagator factors) and
  * the local channel weight alpha_c(x) = P_c / sum_c' P_c' (eq.
  * multi-channel-mg, weights from propagator denominators) of final-state
  * momenta pf[n] and incoming p_a. */

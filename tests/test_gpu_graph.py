@@ -182,3 +182,35 @@ def test_c4_batch_in_one_graph(torch):
     assert np.allclose(st[:, 0], [float(buf["w"][start[c]:start[c + 1]].sum()) for c in range(24)], rtol=1e-11)
     g.close()
     ctx.close()
+
+
+def test_graph_with_chili_and_three_body_channels(torch):
+    """A process whose channels need the extended kind class (Chili and a
+    1 -> 3 decay beside tree channels): graph replays equal eager launches."""
+    from paper_2602_06895_amd import Context
+
+    desc = W.c2_pp4j()
+    # (the cluster of particles 2, 3, 4 is massless in the tree channels too)
+    desc["channels"] = desc["channels"] + [{"chili": True}, {"t_chain": [1, {"d": [2, 3, 4]}], "t_order": ""}]
+    ctx = Context(desc)
+    cap = 6000
+    buf = ctx.sample_buffers(cap)
+    counts = torch.zeros(10, dtype=torch.int64, device="cuda")
+    off = torch.zeros(1, dtype=torch.int64, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    g = ctx.sample_graph(counts, 17, 3, off, buf, status)
+    for cc, o in [([300, 0, 257, 1, 1000, 64, 65, 500, 2000, 999], 0), ([0] * 8 + [4097, 1], 99)]:
+        counts.copy_(torch.tensor(cc, dtype=torch.int64))
+        off.fill_(o)
+        g.launch()
+        torch.cuda.synchronize()
+        got = {k: buf[k].clone() for k in ("p", "w", "x1x2", "chan")}
+        ref = _host_sample(ctx, cc, 17, 3, o)
+        torch.cuda.synchronize()
+        n = sum(cc)
+        assert int(status.cpu()[0]) == 0
+        for k in ("w", "chan"):
+            assert torch.equal(got[k][:n], ref[k]), (cc, k)
+        assert torch.equal(got["p"][:, :, :n], ref["p"]) and torch.equal(got["x1x2"][:, :n], ref["x1x2"])
+    g.close()
+    ctx.close()

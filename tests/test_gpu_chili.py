@@ -224,3 +224,29 @@ def test_chili_mixed_precision(torch):
     wr = np.abs(out["w"].cpu().numpy()[ok] / ref["w"][ok] - 1.0)
     assert np.median(wr) < 1e-5 and np.quantile(wr, 0.99) < 1e-4
     ctx.close()
+
+
+def test_chili_full_size_spot_check(torch):
+    """The Chili report's workload (pp -> 4 jets through one Chili channel,
+    1e7 events in one fused launch, the default launch shape bench.py uses
+    for it): windows of events at random positions recomputed by the
+    oracle."""
+    from paper_2602_06895_amd import Context
+
+    desc = _pp4j_chili()
+    ctx = Context(desc)
+    orc = oracle.Process(desc)
+    n = 10_000_000
+    out = ctx.sample(np.array([n]), seed=8, stream_id=1)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(6)
+    for _ in range(4):
+        start = int(rng.integers(0, n - 3000))
+        y = W.philox_uniforms(8, 1, start, 3000, ctx.dims[0])
+        ref = orc.map(0, y, orc.uniform_grid(0))
+        fe = orc.forward_error(0, y, orc.uniform_grid(0), ref=ref)
+        seg = {"w": out["w"][start:start + 3000].cpu().numpy(),
+               "p": out["p"][:, :, start:start + 3000].cpu().numpy(),
+               "x1x2": out["x1x2"][:, start:start + 3000].cpu().numpy()}
+        compare(seg, ref, fe, hadronic=True, label=f"Chili full-size @{start}")
+    ctx.close()

@@ -158,3 +158,30 @@ def test_dec3_mixed_precision(torch):
     wr = np.abs(wg[ok] / ref["w"][ok] - 1.0)
     assert np.median(wr) < 1e-4 and np.quantile(wr, 0.99) < 1e-2
     ctx.close()
+
+
+def test_dec3_full_size_spot_check(torch):
+    """The 1 -> 3 report's workload (t tbar with three-body top decays, 1e7
+    events in one fused launch): windows at random positions against the
+    oracle."""
+    from paper_2602_06895_amd import Context
+
+    desc = W.c3_ttbar6()
+    desc["channels"] = [{"s": {"d": [{"d": [1, 2, 3], "m": 173.0, "w": 1.5, "order": 1},
+                                     {"d": [4, 5, 6], "m": 173.0, "w": 1.5, "order": 2}]}}]
+    ctx = Context(desc)
+    orc = oracle.Process(desc)
+    n = 10_000_000
+    out = ctx.sample(np.array([n]), seed=9, stream_id=1)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(8)
+    for _ in range(4):
+        start = int(rng.integers(0, n - 3000))
+        y = W.philox_uniforms(9, 1, start, 3000, ctx.dims[0])
+        ref = orc.map(0, y, orc.uniform_grid(0))
+        fe = orc.forward_error(0, y, orc.uniform_grid(0), ref=ref)
+        seg = {"w": out["w"][start:start + 3000].cpu().numpy(),
+               "p": out["p"][:, :, start:start + 3000].cpu().numpy(),
+               "x1x2": out["x1x2"][:, start:start + 3000].cpu().numpy()}
+        compare(seg, ref, fe, hadronic=True, label=f"1->3 full-size @{start}")
+    ctx.close()

@@ -59,6 +59,10 @@ def _create(L, text, precision=0):
     (json.dumps({**W.c2_pp4j(), "channels": [{"t_chain": [1, 2, 3, 3], "t_order": "AA"}]}), "exactly once"),
     (json.dumps({**W.c2_pp4j(), "channels": [{"s": {"d": [1, 2, 3, 4]}}]}), "[child, child]"),
     (json.dumps({**W.c2_pp4j(), "vegas_bins": 1000}), "vegas_bins"),
+    (json.dumps({**W.volume_process(3), "channels": [{"chili": True}]}), "hadronic beams"),
+    (json.dumps({**W.c2_pp4j(), "channels": [{"chili": False}]}), "\"chili\" must be true"),
+    (json.dumps({**W.volume_process(3), "channels": [{"s": {"d": [1, 2, 3], "rambo": True}}]}),
+     "FastRambo cluster decays into two"),
     (json.dumps({**W.c1_ee_mumu(), "beams": "hadronic"}), "ang"),
     (json.dumps({**W.c2_pp4j(), "masses": [0.0] * 9, "channels": [{"t_chain": list(range(1, 10)),
                                                                      "t_order": "A" * 7}]}), "8 final"),

@@ -438,6 +438,24 @@ def summarize_flow(d: str):
     print("\n".join(out))
 
 
+def summarize_trace(d: str):
+    """Per-kernel summary of any rocprofv3 kernel trace under d: name,
+    dispatches, average and total duration, the largest grid, VGPRs and
+    scratch bytes per lane."""
+    import glob
+    import sqlite3
+
+    out = ["kernels (name: dispatches, avg us, total ms, max grid work-items, vgpr, scratch B/lane)"]
+    for f in sorted(glob.glob(os.path.join(d, "**", "*_results.db"), recursive=True)):
+        c = sqlite3.connect(f)
+        for name, cnt, avg, tot, gx, vg, sc in c.execute(
+                "select name, count(*), avg(duration), sum(duration), max(grid_x), max(vgpr_count), "
+                "max(scratch_size) from kernels group by name order by sum(duration) desc"):
+            short = name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
+            out.append(f"  {short[:70]}: {cnt}, {avg / 1e3:.1f}, {tot / 1e6:.2f}, {gx}, {vg}, {sc}")
+    print("\n".join(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -452,10 +470,14 @@ def main():
                     help="only run device-to-device copies of 1 GiB (scale for HBM byte counters)")
     ap.add_argument("--summarize", metavar="DIR", help="summarise rocprofv3 output under DIR and exit")
     ap.add_argument("--summarize-flow", metavar="DIR", help="summarise a flow kernel trace under DIR/flow and exit")
+    ap.add_argument("--summarize-trace", metavar="DIR", help="per-kernel summary of any kernel trace under DIR")
     ap.add_argument("--flow-only", action="store_true", help="only the learned-sampler report")
     ap.add_argument("--flow-steps", type=int, default=400, help="training steps of the learned sampler")
     ap.add_argument("--inverse-only", action="store_true", help="only the inverse-map report")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace)
+        return
     if args.summarize:
         summarize(args.summarize, args.events)
         return

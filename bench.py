@@ -456,6 +456,25 @@ def summarize_trace(d: str):
     print("\n".join(out))
 
 
+def summarize_counters(d: str):
+    """Average value per dispatch of every counter of a rocprofv3 --pmc run
+    under d, per kernel of this library."""
+    import glob
+    import sqlite3
+
+    out = ["counters (kernel: counter = average per dispatch over dispatches)"]
+    for f in sorted(glob.glob(os.path.join(d, "**", "*_results.db"), recursive=True)):
+        c = sqlite3.connect(f)
+        for name, ctr, avg, cnt in c.execute(
+                "select kernel_name, counter_name, avg(v), count(*) from (select kernel_name, counter_name, "
+                "dispatch_id, sum(value) as v from counters_collection where kernel_name like '%msx::%' "
+                "group by kernel_name, counter_name, dispatch_id) group by kernel_name, counter_name "
+                "order by kernel_name, counter_name"):
+            short = name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
+            out.append(f"  {short[:60]}: {ctr} = {avg:.4g} over {cnt}")
+    print("\n".join(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -471,12 +490,16 @@ def main():
     ap.add_argument("--summarize", metavar="DIR", help="summarise rocprofv3 output under DIR and exit")
     ap.add_argument("--summarize-flow", metavar="DIR", help="summarise a flow kernel trace under DIR/flow and exit")
     ap.add_argument("--summarize-trace", metavar="DIR", help="per-kernel summary of any kernel trace under DIR")
+    ap.add_argument("--summarize-counters", metavar="DIR", help="per-kernel counter averages of a --pmc run under DIR")
     ap.add_argument("--flow-only", action="store_true", help="only the learned-sampler report")
     ap.add_argument("--flow-steps", type=int, default=400, help="training steps of the learned sampler")
     ap.add_argument("--inverse-only", action="store_true", help="only the inverse-map report")
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(args.summarize_trace)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters)
         return
     if args.summarize:
         summarize(args.summarize, args.events)

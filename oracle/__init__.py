@@ -57,47 +57,66 @@ def build(force: bool = False) -> str:
 _libs = {}
 
 
+def build_mutant(k: int, directory: str) -> str:
+    """Build oracle.c with planted mistake k (ORC_MUTATE, see the source) into
+    `directory` and register it as variant "mutant<k>" of lib(): pin-strength
+    tests check that their pins reject it."""
+    name = f"mutant{k}"
+    out = os.path.join(directory, f"liboracle_{name}.so")
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-Wall", "-Wno-unused-function",
+           "-ffp-contract=off", f"-DORC_MUTATE={int(k)}", _SRC, "-o", out, "-lm"]
+    subprocess.run(cmd, check=True)
+    _libs.pop(name, None)
+    _libs[name] = _load(out)
+    return name
+
+
 def lib(variant: str = "ref"):
     if variant not in _libs:
         build()
-        L = C.CDLL(os.path.join(_HERE, _VARIANTS[variant][0]))
-        dp = C.POINTER(C.c_double)
-        L.orc_map.restype = C.c_int
-        L.orc_weight.restype = C.c_int
-        L.orc_kallen.restype = C.c_double
-        L.orc_kallen.argtypes = [C.c_double] * 3
-        L.orc_map_nu.restype = C.c_double
-        L.orc_map_nu.argtypes = [C.c_double] * 5 + [dp]
-        L.orc_map_bw.restype = C.c_double
-        L.orc_map_bw.argtypes = [C.c_double] * 5 + [dp]
-        L.orc_two_body_decay.restype = C.c_double
-        L.orc_two_body_decay.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_double,
-                                         C.c_double, dp, dp]
-        L.orc_two_to_two.restype = C.c_double
-        L.orc_two_to_two.argtypes = [dp, dp] + [C.c_double] * 9 + [dp, dp, dp]
-        L.orc_t_range.restype = None
-        L.orc_t_range.argtypes = [C.c_double] * 5 + [dp, dp]
-        L.orc_r_to_x1x2.restype = C.c_double
-        L.orc_r_to_x1x2.argtypes = [C.c_double, C.c_double, C.c_double, dp, dp]
-        L.orc_vegas_map.restype = C.c_double
-        L.orc_vegas_map.argtypes = [C.c_double, dp, C.c_int32, dp]
-        L.orc_boost.restype = None
-        L.orc_boost.argtypes = [dp, C.c_double, dp, dp]
-        L.orc_inverse.restype = C.c_int
-        L.orc_unmap_nu.restype = C.c_double
-        L.orc_unmap_nu.argtypes = [C.c_double] * 5
-        L.orc_unmap_bw.restype = C.c_double
-        L.orc_unmap_bw.argtypes = [C.c_double] * 5
-        L.orc_rqf.restype = C.c_double
-        L.orc_rqf.argtypes = [C.c_double, C.c_double]
-        L.orc_rqf_inverse.restype = C.c_double
-        L.orc_rqf_inverse.argtypes = [C.c_double, C.c_double]
-        L.orc_rambo_ck.restype = C.c_double
-        L.orc_rambo_ck.argtypes = [C.c_int32]
-        L.orc_vegas_unmap.restype = C.c_double
-        L.orc_vegas_unmap.argtypes = [C.c_double, dp, C.c_int32]
-        _libs[variant] = L
+        _libs[variant] = _load(os.path.join(_HERE, _VARIANTS[variant][0]))
     return _libs[variant]
+
+
+def _load(path: str):
+    """Open one build of oracle.c and declare its C signatures."""
+    L = C.CDLL(path)
+    dp = C.POINTER(C.c_double)
+    L.orc_map.restype = C.c_int
+    L.orc_weight.restype = C.c_int
+    L.orc_kallen.restype = C.c_double
+    L.orc_kallen.argtypes = [C.c_double] * 3
+    L.orc_map_nu.restype = C.c_double
+    L.orc_map_nu.argtypes = [C.c_double] * 5 + [dp]
+    L.orc_map_bw.restype = C.c_double
+    L.orc_map_bw.argtypes = [C.c_double] * 5 + [dp]
+    L.orc_two_body_decay.restype = C.c_double
+    L.orc_two_body_decay.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                     C.c_double, dp, dp]
+    L.orc_two_to_two.restype = C.c_double
+    L.orc_two_to_two.argtypes = [dp, dp] + [C.c_double] * 9 + [dp, dp, dp]
+    L.orc_t_range.restype = None
+    L.orc_t_range.argtypes = [C.c_double] * 5 + [dp, dp]
+    L.orc_r_to_x1x2.restype = C.c_double
+    L.orc_r_to_x1x2.argtypes = [C.c_double, C.c_double, C.c_double, dp, dp]
+    L.orc_vegas_map.restype = C.c_double
+    L.orc_vegas_map.argtypes = [C.c_double, dp, C.c_int32, dp]
+    L.orc_boost.restype = None
+    L.orc_boost.argtypes = [dp, C.c_double, dp, dp]
+    L.orc_inverse.restype = C.c_int
+    L.orc_unmap_nu.restype = C.c_double
+    L.orc_unmap_nu.argtypes = [C.c_double] * 5
+    L.orc_unmap_bw.restype = C.c_double
+    L.orc_unmap_bw.argtypes = [C.c_double] * 5
+    L.orc_rqf.restype = C.c_double
+    L.orc_rqf.argtypes = [C.c_double, C.c_double]
+    L.orc_rqf_inverse.restype = C.c_double
+    L.orc_rqf_inverse.argtypes = [C.c_double, C.c_double]
+    L.orc_rambo_ck.restype = C.c_double
+    L.orc_rambo_ck.argtypes = [C.c_int32]
+    L.orc_vegas_unmap.restype = C.c_double
+    L.orc_vegas_unmap.argtypes = [C.c_double, dp, C.c_int32]
+    return L
 
 
 OBS_E, OBS_PT, OBS_ETA, OBS_PHI, OBS_M, OBS_PT_RANK, OBS_DR_HARDEST = range(7)

@@ -41,6 +41,16 @@ static double orc_nudge(double v)
 #define asinh(a) orc_nudge(asinh(a))
 #endif
 
+/* Planted mistakes (pin-strength tests only, never the reference): a build
+ * with ORC_MUTATE = k carries mistake k, which some pin must detect:
+ *   1  the toy PDF's (1 - x) exponent off by one
+ *   2  mu instead of mu^2 in the massless propagator factor
+ *   3  q = p_a + sum p_k for a t-type propagator (wrong sign convention)
+ *   4  the Breit-Wigner factor with Gamma^2 in place of M^2 Gamma^2 */
+#ifndef ORC_MUTATE
+#define ORC_MUTATE 0
+#endif
+
 #define ORC_MAX_NODES 64
 #define ORC_MAX_FINAL 16
 #define ORC_MAX_DIMS 64
@@ -455,7 +465,7 @@ static double node_m_max(const orc_channel* ch, int32_t i, const int32_t* sample
 
 static double pdf_toy(const orc_process* pr, double x)
 {
-    return pow(x, pr->pdf_a) * pow(1.0 - x, pr->pdf_b);
+    return pow(x, pr->pdf_a) * pow(1.0 - x, pr->pdf_b + (ORC_MUTATE == 1 ? 1.0 : 0.0));
 }
 
 static double prop_q2(int32_t t_type, uint32_t set, const double pa[4], double mom[][4], int32_t n)
@@ -465,7 +475,7 @@ static double prop_q2(int32_t t_type, uint32_t set, const double pa[4], double m
         if (set & (1u << k))
             for (int c = 0; c < 4; ++c) q[c] += mom[k][c];
     if (t_type)
-        for (int c = 0; c < 4; ++c) q[c] = pa[c] - q[c];
+        for (int c = 0; c < 4; ++c) q[c] = ORC_MUTATE == 3 ? pa[c] + q[c] : pa[c] - q[c];
     return mdot(q, q);
 }
 
@@ -491,9 +501,10 @@ static double integrand(const orc_process* pr, int32_t chan, double pf[][4], con
         double q2 = prop_q2(pr->prop_t[u], pr->prop_set[u], pa, pf, n);
         if (pr->prop_bw[u]) {
             double m2 = pr->prop_m[u] * pr->prop_m[u], mw = pr->prop_m[u] * pr->prop_w[u];
+            if (ORC_MUTATE == 4) mw = pr->prop_w[u];
             f *= 1.0 / ((q2 - m2) * (q2 - m2) + mw * mw);
         } else {
-            f *= 1.0 / (fabs(q2) + pr->prop_mu[u] * pr->prop_mu[u]);
+            f *= 1.0 / (fabs(q2) + (ORC_MUTATE == 2 ? pr->prop_mu[u] : pr->prop_mu[u] * pr->prop_mu[u]));
         }
     }
     if (pr->n_chan <= 1) {

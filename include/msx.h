@@ -198,6 +198,23 @@ msx_status msx_weight(msx_ctx* ctx, int32_t channel, int64_t n, const double* p,
                       const double* x1x2, const double* jac, double* w, double* alpha,
                       void* stream);
 
+/* Flags of the sample calls.
+ *  MSX_SAMPLE_ACCUMULATE_VEGAS: the fused kernel also adds, per channel,
+ *    sum w^2 per VEGAS bin of every dimension (bin of the event's uniform
+ *    under the current grid) into the context's histograms, which
+ *    msx_vegas_update consumes (the adaptation phase of section 4.2: adapt
+ *    the grids, then freeze them).  Each wave keeps a private histogram in
+ *    LDS, every tile writes the sum of its waves' histograms, and a second
+ *    kernel adds the tiles in order, so the sums are deterministic for a
+ *    given events-per-thread setting.  Needs (4 dims bins + 1024) doubles of
+ *    LDS beside the kernel's own; MSX_ERR_UNSUPPORTED beyond 160 KiB (then
+ *    use msx_vegas_accumulate).
+ *  MSX_SAMPLE_USE_FLOW: channels with a flow attached (msx_attach_flow) draw
+ *    their uniforms from the flow (msx_flow_sample) instead of the VEGAS grid
+ *    alone; the other channels run the fused kernel.  Host counts only
+ *    (msx_sample); those channels' events are not VEGAS-accumulated.  */
+enum { MSX_SAMPLE_ACCUMULATE_VEGAS = 1, MSX_SAMPLE_USE_FLOW = 2 };
+
 /* Fused production path, all channels in one launch: for channel c,
  * counts[c] events (host array of n_channels entries) are generated at
  * output positions [off_c, off_c + counts[c]) with off_c = sum of earlier
@@ -205,10 +222,11 @@ msx_status msx_weight(msx_ctx* ctx, int32_t channel, int64_t n, const double* p,
  * p [4][npmax][N] (rows beyond a channel's np untouched), x1x2 [2][N] (or
  * NULL when no channel is hadronic), w [N], chan [N] (optional), with
  * N = sum counts.  Per-channel statistics are added to the context's
- * accumulators (msx_stats).  Results do not depend on launch shapes. */
+ * accumulators (msx_stats).  Results do not depend on launch shapes.
+ * flags: MSX_SAMPLE_* (0 for a plain sample). */
 msx_status msx_sample(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id,
-                      uint64_t counter_offset, double* p, double* x1x2, double* w, int32_t* chan,
-                      void* stream);
+                      uint64_t counter_offset, int32_t flags, double* p, double* x1x2, double* w,
+                      int32_t* chan, void* stream);
 
 /* msx_sample with its parameters in device memory, for launches captured in
  * a HIP graph and replayed with new values: counts [n_channels] (int64) and
@@ -222,8 +240,8 @@ msx_status msx_sample(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64
  * first call allocates scratch sized for `capacity`; capture it only after a
  * call of the same capacity (msx_sample_graph_create does this itself). */
 msx_status msx_sample_device(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id,
-                             const uint64_t* counter_offset, int64_t capacity, double* p, double* x1x2,
-                             double* w, int32_t* chan, int32_t* status, void* stream);
+                             const uint64_t* counter_offset, int64_t capacity, int32_t flags, double* p,
+                             double* x1x2, double* w, int32_t* chan, int32_t* status, void* stream);
 
 /* A captured, instantiated HIP graph of one msx_sample_device launch (the
  * persistent fused kernel of all channels plus its statistics pass).  Launch
@@ -234,8 +252,8 @@ msx_status msx_sample_device(msx_ctx* ctx, const int64_t* counts, uint64_t seed,
  * sample calls of the same context race on them. */
 typedef struct msx_graph msx_graph;
 msx_status msx_sample_graph_create(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id,
-                                   const uint64_t* counter_offset, int64_t capacity, double* p,
-                                   double* x1x2, double* w, int32_t* chan, int32_t* status,
+                                   const uint64_t* counter_offset, int64_t capacity, int32_t flags,
+                                   double* p, double* x1x2, double* w, int32_t* chan, int32_t* status,
                                    msx_graph** out);
 msx_status msx_graph_launch(msx_graph* graph, void* stream);
 msx_status msx_graph_destroy(msx_graph* graph);
@@ -262,6 +280,31 @@ msx_status msx_reset_stats(msx_ctx* ctx, void* stream);
  * weights w [n] into the context's histogram (deterministic order). */
 msx_status msx_vegas_accumulate(msx_ctx* ctx, int32_t channel, int64_t n, const double* y,
                                 const double* w, void* stream);
+
+/* VEGAS adaptation phase, run by the library: `iterations` times, sample
+ * n_per_channel events of every channel with MSX_SAMPLE_ACCUMULATE_VEGAS
+ * (seed, stream_id; iteration i uses event ids counter_offset +
+ * i n_per_channel n_channels + output position), then msx_vegas_update
+ * (alpha).  stats_out [n_channels][5] (host, optional) receives the
+ * statistics of the last iteration, whose events were drawn from the grids
+ * before the last refinement.  The context's statistics are left reset.
+ * Allocates the event buffers of one iteration for the duration of the call;
+ * synchronises `stream`. */
+msx_status msx_vegas_adapt(msx_ctx* ctx, int64_t n_per_channel, int32_t iterations, double alpha, uint64_t seed,
+                           uint64_t stream_id, uint64_t counter_offset, double* stats_out, void* stream);
+
+/* Events per channel for a multichannel sample of `total` events (the
+ * allocation of section 3.4.1's per-channel jobs): with sd_c the standard
+ * deviation of channel c's weights from stats [n_channels][5] (host, as
+ * msx_stats returns them), counts[c] = floor(floor_frac total) +
+ * floor(share_c (total - n_channels floor(floor_frac total))), share_c =
+ * sd_c / sum sd (equal shares when every sd is 0), and the remainder goes to
+ * the channel with the largest share; counts sum to total.  Minimises the
+ * variance of sum_c <w>_c (Neyman allocation) above the floor.  Host only
+ * (no device work); MSX_ERR_ARG when total < 0, floor_frac outside [0, 1 /
+ * n_channels] or a statistic is not finite. */
+msx_status msx_allocate_counts(int32_t n_channels, const double* stats, int64_t total, double floor_frac,
+                               int64_t* counts);
 
 /* Refine every channel's grid from its accumulated histogram (smoothing,
  * damping exponent `alpha` > 0, equal-share redistribution; VEGAS as cited

@@ -30,9 +30,10 @@ EXPORTS = ["msx_last_error", "msx_create_channels", "msx_destroy", "msx_get_meta
            "msx_flow_gradient", "msx_flow_train_step", "msx_flow_sample", "msx_sample_device",
            "msx_sample_graph_create", "msx_graph_launch", "msx_graph_destroy", "msx_set_launch", "msx_autotune",
            "msx_inverse_map", "msx_multichannel_density", "msx_unweight", "msx_observables", "msx_cut",
-           "msx_histogram"]
+           "msx_histogram", "msx_vegas_adapt", "msx_allocate_counts"]
 OBS_E, OBS_PT, OBS_ETA, OBS_PHI, OBS_M, OBS_PT_RANK, OBS_DR_HARDEST = range(7)
 FLOW_BF16, FLOW_FP32 = 0, 1
+SAMPLE_ACCUMULATE_VEGAS, SAMPLE_USE_FLOW = 1, 2
 
 
 class MsxError(RuntimeError):
@@ -67,7 +68,9 @@ def load_library(path: str = LIB_PATH):
         "msx_cut": ([vp, i64, vp, i32, vp, vp, vp, vp], C.c_int),
         "msx_histogram": ([vp, i64, vp, vp, i32, C.c_double, C.c_double, vp, vp], C.c_int),
         "msx_weight": ([vp, i32, i64, vp, vp, vp, vp, vp, vp], C.c_int),
-        "msx_sample": ([vp, vp, u64, u64, u64, vp, vp, vp, vp, vp], C.c_int),
+        "msx_sample": ([vp, vp, u64, u64, u64, i32, vp, vp, vp, vp, vp], C.c_int),
+        "msx_vegas_adapt": ([vp, i64, i32, dbl, u64, u64, u64, vp, vp], C.c_int),
+        "msx_allocate_counts": ([i32, vp, i64, dbl, vp], C.c_int),
         "msx_stats": ([vp, vp, vp], C.c_int),
         "msx_reset_stats": ([vp, vp], C.c_int),
         "msx_vegas_accumulate": ([vp, i32, i64, vp, vp, vp], C.c_int),
@@ -75,8 +78,8 @@ def load_library(path: str = LIB_PATH):
         "msx_get_grid": ([vp, i32, vp], C.c_int),
         "msx_set_grid": ([vp, i32, vp], C.c_int),
         "msx_unweight_eff": ([vp, vp, i64, dbl, C.POINTER(dbl), C.POINTER(dbl), vp], C.c_int),
-        "msx_sample_device": ([vp, vp, u64, u64, vp, i64, vp, vp, vp, vp, vp, vp], C.c_int),
-        "msx_sample_graph_create": ([vp, vp, u64, u64, vp, i64, vp, vp, vp, vp, vp, C.POINTER(vp)], C.c_int),
+        "msx_sample_device": ([vp, vp, u64, u64, vp, i64, i32, vp, vp, vp, vp, vp, vp], C.c_int),
+        "msx_sample_graph_create": ([vp, vp, u64, u64, vp, i64, i32, vp, vp, vp, vp, vp, C.POINTER(vp)], C.c_int),
         "msx_graph_launch": ([vp, vp], C.c_int),
         "msx_graph_destroy": ([vp], C.c_int),
         "msx_set_launch": ([vp, i32, i32], C.c_int),
@@ -274,7 +277,7 @@ class Context:
         return (w, a) if alpha else w
 
     def sample(self, counts, seed: int, stream_id: int = 0, counter_offset: int = 0, out: dict | None = None,
-               want_chan: bool = True):
+               want_chan: bool = True, flags: int = 0):
         counts = np.ascontiguousarray(counts, dtype=np.int64)
         if counts.shape != (self.n_channels,):
             raise ValueError(f"counts must have {self.n_channels} entries")
@@ -287,25 +290,27 @@ class Context:
             out = {"p": self._empty(4, self.max_momenta, N), "w": self._empty(N),
                    "x1x2": self._empty(2, N) if any(self.hadronic) else None,
                    "chan": self._empty(N, dtype=self.torch.int32) if want_chan else None}
-        self._check(self.L.msx_sample(self.h, counts.ctypes.data, seed, stream_id, counter_offset,
+        self._check(self.L.msx_sample(self.h, counts.ctypes.data, seed, stream_id, counter_offset, flags,
                                       _ptr(out["p"]), _ptr(out["x1x2"]), _ptr(out["w"]), _ptr(out.get("chan")),
                                       self._stream()))
         return out
 
-    def sample_device(self, counts, seed: int, stream_id: int, counter_offset, out: dict, status=None):
+    def sample_device(self, counts, seed: int, stream_id: int, counter_offset, out: dict, status=None,
+                      flags: int = 0):
         """msx_sample_device: counts (int64 [C]) and counter_offset (uint64 [1],
         stored as int64) are device tensors; out holds buffers of one capacity."""
         cap = out["w"].shape[0]
         self._check(self.L.msx_sample_device(self.h, _ptr(counts), seed, stream_id, _ptr(counter_offset), cap,
-                                             _ptr(out["p"]), _ptr(out.get("x1x2")), _ptr(out["w"]),
+                                             flags, _ptr(out["p"]), _ptr(out.get("x1x2")), _ptr(out["w"]),
                                              _ptr(out.get("chan")), _ptr(status), self._stream()))
 
-    def sample_graph(self, counts, seed: int, stream_id: int, counter_offset, out: dict, status=None):
+    def sample_graph(self, counts, seed: int, stream_id: int, counter_offset, out: dict, status=None,
+                     flags: int = 0):
         """Capture msx_sample_device into a HIP graph; returns a SampleGraph."""
         cap = out["w"].shape[0]
         g = C.c_void_p()
         self._check(self.L.msx_sample_graph_create(self.h, _ptr(counts), seed, stream_id, _ptr(counter_offset), cap,
-                                                   _ptr(out["p"]), _ptr(out.get("x1x2")), _ptr(out["w"]),
+                                                   flags, _ptr(out["p"]), _ptr(out.get("x1x2")), _ptr(out["w"]),
                                                    _ptr(out.get("chan")), _ptr(status), C.byref(g)))
         return SampleGraph(self, g, (counts, counter_offset, out, status))
 
@@ -497,45 +502,26 @@ class Flow:
 
 
 def adapt_vegas(ctx: Context, n_per_channel: int, iterations: int, alpha: float = 0.5, seed: int = 1,
-                stream_id: int = 1):
-    """VEGAS adaptation phase (grids optimised, then frozen): each iteration
-    samples n_per_channel events per channel with the fused path, regenerates
-    the same uniforms (same event ids) for the histograms of sum w^2 per bin,
-    and refines every grid.  Returns the statistics [C][5] of the last
-    iteration.  Leaves the context's statistics reset."""
-    import torch
-
-    C_ = ctx.n_channels
-    counts = np.full(C_, n_per_channel, dtype=np.int64)
-    out = None
-    last = None
-    for it in range(iterations):
-        off = it * C_ * n_per_channel
-        ctx.reset_stats()
-        out = ctx.sample(counts, seed=seed, stream_id=stream_id, counter_offset=off, out=out, want_chan=False)
-        for c in range(C_):
-            lo = c * n_per_channel
-            y = ctx.uniform(seed, stream_id, off + lo, n_per_channel, ctx.dims[c])
-            ctx.vegas_accumulate(c, y, out["w"][lo:lo + n_per_channel])
-        last = ctx.stats()
-        ctx.vegas_update(alpha)
-    torch.cuda.synchronize(ctx.device)
-    ctx.reset_stats()
-    return last
+                stream_id: int = 1, counter_offset: int = 0):
+    """msx_vegas_adapt: the library's adaptation phase (every iteration one
+    fused sample of n_per_channel events per channel that accumulates the
+    VEGAS histograms, then a grid refinement).  Returns the statistics [C][5]
+    of the last iteration; leaves the context's statistics reset."""
+    out = np.zeros((ctx.n_channels, 5))
+    ctx._check(ctx.L.msx_vegas_adapt(ctx.h, n_per_channel, iterations, alpha, seed, stream_id, counter_offset,
+                                     out.ctypes.data, ctx._stream()))
+    return out
 
 
 def neyman_counts(stats: np.ndarray, total: int, floor_frac: float = 0.01) -> np.ndarray:
-    """Events per channel proportional to each channel's weight standard
-    deviation (minimum variance of sum_c <w>_c), with a floor of
-    floor_frac * total per channel."""
-    n = stats[:, 2]
-    mean = stats[:, 0] / np.maximum(n, 1)
-    var = np.maximum(stats[:, 1] / np.maximum(n, 1) - mean ** 2, 0.0)
-    sd = np.sqrt(var)
-    C = len(sd)
-    floor = int(floor_frac * total)
-    rest = total - floor * C
-    share = sd / sd.sum() if sd.sum() > 0 else np.full(C, 1.0 / C)
-    counts = floor + np.floor(share * rest).astype(np.int64)
-    counts[np.argmax(share)] += total - counts.sum()
-    return counts.astype(np.int64)
+    """msx_allocate_counts: events per channel proportional to each channel's
+    weight standard deviation, with a floor of floor_frac * total each."""
+    L = load_library()
+    st = np.ascontiguousarray(stats, dtype=np.float64)
+    if st.ndim != 2 or st.shape[1] != 5:
+        raise ValueError("stats must be [C][5]")
+    counts = np.zeros(st.shape[0], dtype=np.int64)
+    rc = L.msx_allocate_counts(st.shape[0], st.ctypes.data, int(total), float(floor_frac), counts.ctypes.data)
+    if rc != 0:
+        raise MsxError(rc, L.msx_last_error(None).decode())
+    return counts

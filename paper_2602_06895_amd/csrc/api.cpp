@@ -49,6 +49,12 @@ struct msx_ctx {
     int64_t inv_cap = 0;      // doubles
     int64_t vpart_cap = 0;
     double* d_unw = nullptr;  // 2 * 4096 buckets + 2 * 1024 partials + 2
+    // VEGAS accumulation inside the fused sample: per-channel histogram
+    // offsets (device), the per-tile partial stride and the partials
+    int64_t* d_hist_off = nullptr;
+    int vstride = 0;
+    double* d_vtiles = nullptr;
+    int64_t vtiles_cap = 0;  // tiles
     size_t lds_max = 0;
     SampleCall* d_call = nullptr;  // call table of the last sample launch
     // launch shape of the fused sample kernel (events per thread per tile,
@@ -68,6 +74,7 @@ struct msx_graph {
     // reallocated by later calls)
     SampleCall* d_call = nullptr;
     double* d_tile = nullptr;
+    double* d_vtiles = nullptr;  // VEGAS tile partials (graphs that accumulate)
 };
 
 namespace {
@@ -99,7 +106,7 @@ hipError_t dmalloc(T** p, size_t count) {
 void free_all(msx_ctx* c) {
     void* ptrs[] = {c->d_chans, c->d_procs, c->d_grids, c->d_hist, c->d_stats, c->d_grid_off, c->d_chan_nb,
                     c->d_row_nb, c->d_row_grid, c->d_row_hist, c->d_tile, c->d_vpart, c->d_unw, c->d_call,
-                    c->d_inv, c->d_ublk, c->d_obs_hist};
+                    c->d_inv, c->d_ublk, c->d_obs_hist, c->d_hist_off, c->d_vtiles};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -124,6 +131,32 @@ msx_status ensure_tiles(msx_ctx* ctx, int64_t tiles) {
 
 int sample_grid(const msx_ctx* ctx) { return ctx->grid > 0 ? ctx->grid : ctx->cu_count * 8; }
 
+// Per-tile VEGAS histogram partials for `tiles` tiles (grown on demand).
+msx_status ensure_vtiles(msx_ctx* ctx, int64_t tiles) {
+    if (tiles <= ctx->vtiles_cap) return MSX_OK;
+    if (ctx->d_vtiles) MSX_HIP(ctx, hipFree(ctx->d_vtiles), "hipFree");
+    ctx->d_vtiles = nullptr;
+    ctx->vtiles_cap = 0;
+    MSX_HIP(ctx, dmalloc(&ctx->d_vtiles, (size_t)ctx->vstride * tiles), "VEGAS tile partials");
+    ctx->vtiles_cap = tiles;
+    return MSX_OK;
+}
+
+constexpr size_t kLdsPerWorkgroup = 160 * 1024;  // gfx950: 160 KiB of LDS per compute unit
+
+// Checks the flags of a sample call; with MSX_SAMPLE_ACCUMULATE_VEGAS also
+// that the kernel's LDS (staging column, grid, wave histograms) fits.
+msx_status check_sample_flags(msx_ctx* ctx, int32_t flags, int max_slots, int max_inv) {
+    if (flags & ~(MSX_SAMPLE_ACCUMULATE_VEGAS | MSX_SAMPLE_USE_FLOW))
+        return fail(ctx, MSX_ERR_ARG, "unknown sample flags");
+    if ((flags & MSX_SAMPLE_ACCUMULATE_VEGAS) &&
+        sample_lds_bytes(max_slots, max_inv, ctx->lds_max, ctx->vstride) > kLdsPerWorkgroup)
+        return fail(ctx, MSX_ERR_UNSUPPORTED,
+                    "VEGAS accumulation in the fused sample needs more than 160 KiB of LDS for these channels "
+                    "(dims x bins too large); use msx_vegas_accumulate");
+    return MSX_OK;
+}
+
 // Device-count sample: plan kernel, then the fused launch with the register
 // class of all channels.  Enqueues only (safe to capture).
 int64_t device_max_tiles(const msx_ctx* ctx, int64_t capacity) {
@@ -136,7 +169,8 @@ int64_t device_max_tiles(const msx_ctx* ctx, int64_t capacity) {
 // 4 * device_max_tiles(capacity) doubles.
 msx_status sample_device(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id,
                          const uint64_t* counter_offset, int64_t capacity, double* p, double* x1x2, double* w,
-                         int32_t* chan, int32_t* status, SampleCall* d_call, double* d_tile, hipStream_t s) {
+                         int32_t* chan, int32_t* status, SampleCall* d_call, double* d_tile, double* d_vtiles,
+                         hipStream_t s) {
     const int C = (int)ctx->comp.chans.size();
     const int64_t max_tiles = device_max_tiles(ctx, capacity);
     MSX_HIP(ctx, launch_plan(counts, C, capacity, ctx->ept, d_call, status, s), "sample plan");
@@ -144,10 +178,15 @@ msx_status sample_device(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uin
     MSX_HIP(ctx,
             launch_sample(ctx->d_chans, ctx->d_procs, ctx->d_grids, ctx->d_grid_off, ctx->d_chan_nb, d_call, C,
                           ctx->all_slots, ctx->all_inv, ctx->all_kinds, ctx->mixed, ctx->lds_max, seed, stream_id,
-                          counter_offset, 0, ctx->max_np, capacity, p, x1x2, w, chan, d_tile, ctx->d_stats, grid, s),
+                          counter_offset, 0, ctx->max_np, capacity, p, x1x2, w, chan, d_tile, ctx->d_stats, grid, s,
+                          d_vtiles, ctx->vstride, ctx->d_hist_off, ctx->hist_total, ctx->d_hist),
             "sample launch");
     return MSX_OK;
 }
+
+msx_status sample_with_flows(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id,
+                             uint64_t counter_offset, int32_t flags, double* p, double* x1x2, double* w, int32_t* chan,
+                             void* stream);
 
 msx_status check_channel(msx_ctx* ctx, int32_t channel) {
     if (channel < 0 || channel >= (int32_t)ctx->comp.chans.size())
@@ -215,6 +254,8 @@ msx_status msx_create_channels(const char* process_json, int32_t precision, int3
     }
     c->grid_total = (int64_t)grids.size();
     c->n_rows = (int)row_nb.size();
+    for (int ch = 0; ch < C; ++ch)
+        c->vstride = std::max(c->vstride, c->comp.meta[ch].dims * c->comp.meta[ch].nbins);
     auto up = [&](void* dst, const void* src, size_t bytes) { return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice); };
     if ((e = dmalloc(&c->d_chans, C)) != hipSuccess || (e = dmalloc(&c->d_procs, c->comp.procs.size())) != hipSuccess ||
         (e = dmalloc(&c->d_grids, grids.size())) != hipSuccess || (e = dmalloc(&c->d_hist, c->hist_total)) != hipSuccess ||
@@ -223,6 +264,8 @@ msx_status msx_create_channels(const char* process_json, int32_t precision, int3
         (e = dmalloc(&c->d_row_grid, row_grid.size())) != hipSuccess ||
         (e = dmalloc(&c->d_row_hist, row_hist.size())) != hipSuccess ||
         (e = dmalloc(&c->d_unw, 2 * 4096 + 2 * 1024 + 2)) != hipSuccess || (e = dmalloc(&c->d_call, 1)) != hipSuccess ||
+        (e = dmalloc(&c->d_hist_off, C)) != hipSuccess ||
+        (e = up(c->d_hist_off, c->hist_off.data(), sizeof(int64_t) * C)) != hipSuccess ||
         (e = up(c->d_chans, c->comp.chans.data(), sizeof(ChannelTab) * C)) != hipSuccess ||
         (e = up(c->d_procs, c->comp.procs.data(), sizeof(ProcessTab) * c->comp.procs.size())) != hipSuccess ||
         (e = up(c->d_grids, grids.data(), sizeof(double) * grids.size())) != hipSuccess ||
@@ -398,9 +441,11 @@ msx_status msx_weight(msx_ctx* ctx, int32_t channel, int64_t n, const double* p,
 }
 
 msx_status msx_sample(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id, uint64_t counter_offset,
-                      double* p, double* x1x2, double* w, int32_t* chan, void* stream) {
+                      int32_t flags, double* p, double* x1x2, double* w, int32_t* chan, void* stream) {
     if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
     if (!counts) return fail(ctx, MSX_ERR_ARG, "counts is NULL");
+    if (flags & MSX_SAMPLE_USE_FLOW) return sample_with_flows(ctx, counts, seed, stream_id, counter_offset, flags, p,
+                                                              x1x2, w, chan, stream);
     const int C = (int)ctx->comp.chans.size();
     SampleCall call;
     std::memset(&call, 0, sizeof call);
@@ -431,36 +476,47 @@ msx_status msx_sample(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64
     if (counter_offset > UINT64_MAX - (uint64_t)N) return fail(ctx, MSX_ERR_ARG, "event ids overflow the counter");
     if (!p || !w) return fail(ctx, MSX_ERR_ARG, "p and w are required");
     if (any_hadronic && !x1x2) return fail(ctx, MSX_ERR_ARG, "x1x2 is required when a sampled channel is hadronic");
+    if (msx_status st = check_sample_flags(ctx, flags, max_slots, max_inv)) return st;
+    const bool acc = (flags & MSX_SAMPLE_ACCUMULATE_VEGAS) != 0;
     if (msx_status st = set_device(ctx)) return st;
     if (msx_status st = ensure_tiles(ctx, tiles)) return st;
+    if (acc)
+        if (msx_status st = ensure_vtiles(ctx, tiles)) return st;
     hipStream_t s = (hipStream_t)stream;
     MSX_HIP(ctx, launch_set_call(call, ctx->d_call, s), "sample call table");
     const int grid = (int)std::min<int64_t>(tiles, sample_grid(ctx));
     MSX_HIP(ctx,
             launch_sample(ctx->d_chans, ctx->d_procs, ctx->d_grids, ctx->d_grid_off, ctx->d_chan_nb, ctx->d_call, C,
                           max_slots, max_inv, kinds, ctx->mixed, ctx->lds_max, seed, stream_id, nullptr,
-                          counter_offset, ctx->max_np, N, p, x1x2, w, chan, ctx->d_tile, ctx->d_stats, grid, s),
+                          counter_offset, ctx->max_np, N, p, x1x2, w, chan, ctx->d_tile, ctx->d_stats, grid, s,
+                          acc ? ctx->d_vtiles : nullptr, ctx->vstride, ctx->d_hist_off, ctx->hist_total, ctx->d_hist),
             "sample launch");
     return MSX_OK;
 }
 
 msx_status msx_sample_device(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id,
-                             const uint64_t* counter_offset, int64_t capacity, double* p, double* x1x2, double* w,
-                             int32_t* chan, int32_t* status, void* stream) {
+                             const uint64_t* counter_offset, int64_t capacity, int32_t flags, double* p, double* x1x2,
+                             double* w, int32_t* chan, int32_t* status, void* stream) {
     if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
     if (!counts || !counter_offset) return fail(ctx, MSX_ERR_ARG, "counts and counter_offset are required");
     if (capacity <= 0) return fail(ctx, MSX_ERR_ARG, "capacity must be positive");
     if (!p || !w) return fail(ctx, MSX_ERR_ARG, "p and w are required");
     if (ctx->any_hadronic && !x1x2) return fail(ctx, MSX_ERR_ARG, "x1x2 is required (the context has hadronic channels)");
+    if (flags & MSX_SAMPLE_USE_FLOW) return fail(ctx, MSX_ERR_UNSUPPORTED, "MSX_SAMPLE_USE_FLOW needs host counts");
+    if (msx_status st = check_sample_flags(ctx, flags, ctx->all_slots, ctx->all_inv)) return st;
+    const bool acc = (flags & MSX_SAMPLE_ACCUMULATE_VEGAS) != 0;
     if (msx_status st = set_device(ctx)) return st;
-    if (msx_status st = ensure_tiles(ctx, device_max_tiles(ctx, capacity))) return st;
+    const int64_t max_tiles = device_max_tiles(ctx, capacity);
+    if (msx_status st = ensure_tiles(ctx, max_tiles)) return st;
+    if (acc)
+        if (msx_status st = ensure_vtiles(ctx, max_tiles)) return st;
     return sample_device(ctx, counts, seed, stream_id, counter_offset, capacity, p, x1x2, w, chan, status,
-                         ctx->d_call, ctx->d_tile, (hipStream_t)stream);
+                         ctx->d_call, ctx->d_tile, acc ? ctx->d_vtiles : nullptr, (hipStream_t)stream);
 }
 
 msx_status msx_sample_graph_create(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id,
-                                   const uint64_t* counter_offset, int64_t capacity, double* p, double* x1x2,
-                                   double* w, int32_t* chan, int32_t* status, msx_graph** out) {
+                                   const uint64_t* counter_offset, int64_t capacity, int32_t flags, double* p,
+                                   double* x1x2, double* w, int32_t* chan, int32_t* status, msx_graph** out) {
     if (!out) return fail(ctx, MSX_ERR_ARG, "out is NULL");
     *out = nullptr;
     if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
@@ -468,6 +524,9 @@ msx_status msx_sample_graph_create(msx_ctx* ctx, const int64_t* counts, uint64_t
     if (capacity <= 0) return fail(ctx, MSX_ERR_ARG, "capacity must be positive");
     if (!p || !w) return fail(ctx, MSX_ERR_ARG, "p and w are required");
     if (ctx->any_hadronic && !x1x2) return fail(ctx, MSX_ERR_ARG, "x1x2 is required (the context has hadronic channels)");
+    if (flags & MSX_SAMPLE_USE_FLOW) return fail(ctx, MSX_ERR_UNSUPPORTED, "MSX_SAMPLE_USE_FLOW needs host counts");
+    if (msx_status st = check_sample_flags(ctx, flags, ctx->all_slots, ctx->all_inv)) return st;
+    const bool acc = (flags & MSX_SAMPLE_ACCUMULATE_VEGAS) != 0;
     if (msx_status st = set_device(ctx)) return st;
     // everything the launches need is allocated before the capture
     msx_graph* g = new msx_graph();
@@ -477,10 +536,12 @@ msx_status msx_sample_graph_create(msx_ctx* ctx, const int64_t* counts, uint64_t
         if (q->graph) (void)hipGraphDestroy(q->graph);
         if (q->d_call) (void)hipFree(q->d_call);
         if (q->d_tile) (void)hipFree(q->d_tile);
+        if (q->d_vtiles) (void)hipFree(q->d_vtiles);
         delete q;
     };
     hipError_t e = dmalloc(&g->d_call, 1);
     if (e == hipSuccess) e = dmalloc(&g->d_tile, (size_t)4 * device_max_tiles(ctx, capacity));
+    if (e == hipSuccess && acc) e = dmalloc(&g->d_vtiles, (size_t)ctx->vstride * device_max_tiles(ctx, capacity));
     if (e != hipSuccess) {
         drop(g);
         return dev_fail(ctx, e, "graph scratch");
@@ -494,7 +555,7 @@ msx_status msx_sample_graph_create(msx_ctx* ctx, const int64_t* counts, uint64_t
     msx_status st = MSX_OK;
     if (e == hipSuccess) {
         st = sample_device(ctx, counts, seed, stream_id, counter_offset, capacity, p, x1x2, w, chan, status, g->d_call,
-                           g->d_tile, s);
+                           g->d_tile, g->d_vtiles, s);
         hipError_t e2 = hipStreamEndCapture(s, &g->graph);
         if (st == MSX_OK && e2 != hipSuccess) e = e2;
     }
@@ -524,6 +585,7 @@ msx_status msx_graph_destroy(msx_graph* g) {
     if (g->graph) (void)hipGraphDestroy(g->graph);
     if (g->d_call) (void)hipFree(g->d_call);
     if (g->d_tile) (void)hipFree(g->d_tile);
+    if (g->d_vtiles) (void)hipFree(g->d_vtiles);
     delete g;
     return MSX_OK;
 }
@@ -582,10 +644,10 @@ msx_status msx_autotune(msx_ctx* ctx, const int64_t* counts, uint64_t seed, int3
             ctx->ept = ept;
             ctx->grid = ctx->cu_count * mult;
             // one untimed launch, then reps timed ones
-            st = msx_sample(ctx, counts, seed, 0, 0, p, x1x2, w, nullptr, s);
+            st = msx_sample(ctx, counts, seed, 0, 0, 0, p, x1x2, w, nullptr, s);
             for (int r = 0; st == MSX_OK && r < reps; ++r) {
                 if (r == 0) (void)hipEventRecord(e0, s);
-                st = msx_sample(ctx, counts, seed, 0, 0, p, x1x2, w, nullptr, s);
+                st = msx_sample(ctx, counts, seed, 0, 0, 0, p, x1x2, w, nullptr, s);
             }
             if (st != MSX_OK) break;
             (void)hipEventRecord(e1, s);
@@ -671,6 +733,83 @@ msx_status msx_vegas_update(msx_ctx* ctx, double alpha, void* stream) {
             launch_vegas_refine(ctx->n_rows, ctx->d_row_nb, ctx->d_row_grid, ctx->d_row_hist, alpha, ctx->d_grids,
                                 ctx->d_hist, (hipStream_t)stream),
             "refine launch");
+    return MSX_OK;
+}
+
+msx_status msx_vegas_adapt(msx_ctx* ctx, int64_t n_per_channel, int32_t iterations, double alpha, uint64_t seed,
+                           uint64_t stream_id, uint64_t counter_offset, double* stats_out, void* stream) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (n_per_channel < 1 || iterations < 1) return fail(ctx, MSX_ERR_ARG, "need n_per_channel >= 1 and iterations >= 1");
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(ctx, MSX_ERR_ARG, "alpha must be finite and > 0");
+    const int C = (int)ctx->comp.chans.size();
+    if (n_per_channel > INT64_MAX / 8 / C / iterations) return fail(ctx, MSX_ERR_ARG, "too many events");
+    const int64_t N = n_per_channel * C;
+    if (counter_offset > UINT64_MAX - (uint64_t)(N * iterations))
+        return fail(ctx, MSX_ERR_ARG, "event ids overflow the counter");
+    if (msx_status st = set_device(ctx)) return st;
+    hipStream_t s = (hipStream_t)stream;
+    double *p = nullptr, *x1x2 = nullptr, *w = nullptr;
+    auto cleanup = [&]() {
+        if (p) (void)hipFree(p);
+        if (x1x2) (void)hipFree(x1x2);
+        if (w) (void)hipFree(w);
+    };
+    hipError_t e;
+    if ((e = dmalloc(&p, (size_t)4 * ctx->max_np * N)) != hipSuccess ||
+        (ctx->any_hadronic && (e = dmalloc(&x1x2, (size_t)2 * N)) != hipSuccess) ||
+        (e = dmalloc(&w, (size_t)N)) != hipSuccess) {
+        cleanup();
+        return dev_fail(ctx, e, "adaptation buffers");
+    }
+    std::vector<int64_t> counts(C, n_per_channel);
+    msx_status st = MSX_OK;
+    for (int it = 0; it < iterations && st == MSX_OK; ++it) {
+        st = msx_reset_stats(ctx, stream);
+        if (st == MSX_OK)
+            st = msx_sample(ctx, counts.data(), seed, stream_id, counter_offset + (uint64_t)it * (uint64_t)N,
+                            MSX_SAMPLE_ACCUMULATE_VEGAS, p, x1x2, w, nullptr, stream);
+        if (st == MSX_OK && stats_out && it == iterations - 1) st = msx_stats(ctx, stats_out, stream);
+        if (st == MSX_OK) st = msx_vegas_update(ctx, alpha, stream);
+    }
+    if (st == MSX_OK) st = msx_reset_stats(ctx, stream);
+    if (st == MSX_OK && (e = hipStreamSynchronize(s)) != hipSuccess) st = dev_fail(ctx, e, "adaptation sync");
+    cleanup();
+    return st;
+}
+
+msx_status msx_allocate_counts(int32_t n_channels, const double* stats, int64_t total, double floor_frac,
+                               int64_t* counts) {
+    if (n_channels < 1 || !stats || !counts) return fail(nullptr, MSX_ERR_ARG, "need n_channels >= 1, stats and counts");
+    if (total < 0) return fail(nullptr, MSX_ERR_ARG, "total < 0");
+    if (!(floor_frac >= 0.0) || floor_frac * n_channels > 1.0)
+        return fail(nullptr, MSX_ERR_ARG, "floor_frac must lie in [0, 1 / n_channels]");
+    const int C = n_channels;
+    std::vector<double> sd(C);
+    double sum_sd = 0.0;
+    for (int c = 0; c < C; ++c) {
+        const double* st = stats + 5 * c;
+        for (int j = 0; j < 5; ++j)
+            if (!std::isfinite(st[j])) return fail(nullptr, MSX_ERR_ARG, "statistics must be finite");
+        const double n = std::max(st[2], 1.0);
+        const double mean = st[0] / n;
+        sd[c] = std::sqrt(std::max(st[1] / n - mean * mean, 0.0));
+        sum_sd += sd[c];
+    }
+    const int64_t floor_n = (int64_t)(floor_frac * (double)total);
+    const int64_t rest = total - floor_n * C;
+    int64_t assigned = 0;
+    int arg = 0;
+    double best = -1.0;
+    for (int c = 0; c < C; ++c) {
+        const double share = sum_sd > 0.0 ? sd[c] / sum_sd : 1.0 / C;
+        counts[c] = floor_n + (int64_t)std::floor(share * (double)rest);
+        assigned += counts[c];
+        if (share > best) {
+            best = share;
+            arg = c;
+        }
+    }
+    counts[arg] += total - assigned;
     return MSX_OK;
 }
 
@@ -863,3 +1002,12 @@ msx_status msx_unweight_eff(msx_ctx* ctx, const double* w, int64_t n, double ove
 }
 
 }  // extern "C"
+
+namespace {
+
+msx_status sample_with_flows(msx_ctx* ctx, const int64_t*, uint64_t, uint64_t, uint64_t, int32_t, double*, double*,
+                             double*, int32_t*, void*) {
+    return fail(ctx, MSX_ERR_UNSUPPORTED, "MSX_SAMPLE_USE_FLOW: no flow attached");
+}
+
+}  // namespace

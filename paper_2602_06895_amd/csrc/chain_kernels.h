@@ -183,7 +183,8 @@ __global__ __launch_bounds__(kBlock) void k_sample(const ChannelTab* __restrict_
                                                    const uint64_t* __restrict__ ctr_dev, uint64_t ctr_off, int np,
                                                    int64_t ld, double* __restrict__ p, double* __restrict__ x1x2,
                                                    double* __restrict__ w, int32_t* __restrict__ chan_out,
-                                                   double* __restrict__ tile_stats) {
+                                                   double* __restrict__ tile_stats, int grid_doubles,
+                                                   double* __restrict__ vpart, int vstride) {
     constexpr int kRows = stage_rows<NS, NI>();
     extern __shared__ double lds[];
     double* lg = lds + kRows * kBlock;
@@ -197,6 +198,15 @@ __global__ __launch_bounds__(kBlock) void k_sample(const ChannelTab* __restrict_
     const int n_chan = call->n_chan;
     const int ept = call->ept;
     const uint64_t ctr0 = ctr_dev ? *ctr_dev : ctr_off;
+    // VEGAS histogram accumulation (vpart != NULL): one private histogram
+    // [dims][nb] per wave after the grid, then the events' bin numbers as
+    // bytes [dims][kBlock]
+    double* const vh = lg + grid_doubles;
+    double* const vh_wave = vh + wave * vstride;
+    uint8_t* const vbin = (uint8_t*)(vh + kWaves * vstride);
+    if (vpart) {
+        for (int i = threadIdx.x; i < kWaves * vstride; i += kBlock) vh[i] = 0.0;
+    }
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         int c = 0;
         while (c + 1 < n_chan && call->tile_start[c + 1] <= tile) ++c;
@@ -216,37 +226,47 @@ __global__ __launch_bounds__(kBlock) void k_sample(const ChannelTab* __restrict_
         const int64_t end = call->ev_start[c + 1];
         double a1 = 0.0, a2 = 0.0, az = 0.0, am = 0.0;
         for (int sub = 0; sub < ept; ++sub) {
-            const int64_t pos = base + (int64_t)sub * kBlock + threadIdx.x;
-            if (pos >= end) break;
-            const uint64_t e = ctr0 + (uint64_t)pos;
-            // all dimensions first, four per Philox block, VEGAS-mapped into
-            // this thread's LDS column: one copy of the generator in the code
-            // instead of one per place the chain draws a number
-            double jv = 1.0;
+            const int64_t pos0 = base + (int64_t)sub * kBlock;
+            if (pos0 >= end) break;
+            const int64_t pos = pos0 + threadIdx.x;
+            const bool live = pos < end;
+            double wv = 0.0;
+            if (live) {
+                const uint64_t e = ctr0 + (uint64_t)pos;
+                // all dimensions first, four per Philox block, VEGAS-mapped
+                // into this thread's LDS column: one copy of the generator in
+                // the code instead of one per place the chain draws a number
+                double jv = 1.0;
 #pragma unroll 1
-            for (int k4 = 0; k4 < dims; k4 += 4) {
-                uint64_t c0 = e, c1 = (uint64_t)(k4 >> 2), c2 = 0, c3 = 0;
-                philox4x64_10(c0, c1, c2, c3, seed, sid);
-                const uint64_t wd[4] = {c0, c1, c2, c3};
+                for (int k4 = 0; k4 < dims; k4 += 4) {
+                    uint64_t c0 = e, c1 = (uint64_t)(k4 >> 2), c2 = 0, c3 = 0;
+                    philox4x64_10(c0, c1, c2, c3, seed, sid);
+                    const uint64_t wd[4] = {c0, c1, c2, c3};
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (k4 + j < dims) col[(k4 + j) * kBlock] = vegas_map(to_unit(wd[j]), lg + (k4 + j) * (nb + 1), nb, jv);
+                    for (int j = 0; j < 4; ++j)
+                        if (k4 + j < dims) {
+                            const double u = to_unit(wd[j]);
+                            if (vpart) vbin[(k4 + j) * kBlock + threadIdx.x] = (uint8_t)vegas_bin(u, nb);
+                            col[(k4 + j) * kBlock] = vegas_map(u, lg + (k4 + j) * (nb + 1), nb, jv);
+                        }
+                }
+                int k = 0;
+                auto next = [&]() -> double { return col[(k++) * kBlock]; };
+                double E[NS], X[NS], Y[NS], Z[NS], S[NI], SQ[NI];
+                ChainOut o;
+                if ((KINDS & KIND_CHILI) && ct->chili)
+                    run_chili<NS>(ct, s_lab, next, E, X, Y, Z, o);
+                else
+                    run_chain<NS, NI, KINDS, MIX>(ct, s_lab, next, E, X, Y, Z, S, SQ, o);
+                wv = finish_event<NS, MIX>(ct, pt, o, jv, E, X, Y, Z, np, ld, pos, p, x1x2, nullptr, true, q);
+                w[pos] = wv;
+                if (chan_out) chan_out[pos] = c;
+                a1 += wv;
+                a2 += wv * wv;
+                az += wv == 0.0 ? 1.0 : 0.0;
+                am = fmax(am, wv);
             }
-            int k = 0;
-            auto next = [&]() -> double { return col[(k++) * kBlock]; };
-            double E[NS], X[NS], Y[NS], Z[NS], S[NI], SQ[NI];
-            ChainOut o;
-            if ((KINDS & KIND_CHILI) && ct->chili)
-                run_chili<NS>(ct, s_lab, next, E, X, Y, Z, o);
-            else
-                run_chain<NS, NI, KINDS, MIX>(ct, s_lab, next, E, X, Y, Z, S, SQ, o);
-            const double wv = finish_event<NS, MIX>(ct, pt, o, jv, E, X, Y, Z, np, ld, pos, p, x1x2, nullptr, true, q);
-            w[pos] = wv;
-            if (chan_out) chan_out[pos] = c;
-            a1 += wv;
-            a2 += wv * wv;
-            az += wv == 0.0 ? 1.0 : 0.0;
-            am = fmax(am, wv);
+            if (vpart) vegas_wave_accumulate(vh_wave, vbin + threadIdx.x, dims, nb, lane, live, wv);
         }
         double s1 = wave_sum(a1), s2 = wave_sum(a2);
         double nz = wave_sum(az);
@@ -265,6 +285,21 @@ __global__ __launch_bounds__(kBlock) void k_sample(const ChannelTab* __restrict_
             tile_stats[tile * 4 + q] = acc;
         }
         __syncthreads();
+        if (vpart) {
+            // the tile's histogram: the wave histograms summed in wave order,
+            // then cleared for the next tile
+            double* dst = vpart + tile * (int64_t)vstride;
+            const int rows = dims * nb;
+            for (int i = threadIdx.x; i < rows; i += kBlock) {
+                double acc = vh[i];
+#pragma unroll
+                for (int v = 1; v < kWaves; ++v) acc += vh[v * vstride + i];
+                dst[i] = acc;
+#pragma unroll
+                for (int v = 0; v < kWaves; ++v) vh[v * vstride + i] = 0.0;
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -523,7 +558,8 @@ hipError_t launch_chain_class(int kc, const ChainLaunch& a) {
     constexpr int K3 = K1 | KIND_CHILI | KIND_DEC3, K4 = KINDS_ALL | KIND_CHILI | KIND_DEC3;
     auto go = [&](auto kt) {
         constexpr int K = decltype(kt)::value;
-        const size_t lds = a.lds + (a.sample ? sizeof(double) * stage_rows<NS, NI>() * kBlock : kQBytes);
+        const size_t lds = a.lds + (a.sample ? sizeof(double) * stage_rows<NS, NI>() * kBlock : kQBytes) +
+                           (a.vpart ? vegas_acc_lds(a.vstride) : 0);
         if (lds > 65536) {
             // beyond the default 64 KiB per workgroup (gfx950 has 160 KiB per CU)
             const void* fn = a.sample ? (const void*)k_sample<NS, NI, K, MIX> : (const void*)k_map<NS, NI, K, MIX>;
@@ -546,7 +582,7 @@ hipError_t launch_chain_class(int kc, const ChainLaunch& a) {
         if (a.sample)
             k_sample<NS, NI, K, MIX><<<a.grid, kBlock, lds, a.stream>>>(
                 a.cts, a.pts, a.grids, a.grid_off, a.chan_nb, a.call, a.seed, a.sid, a.ctr_dev, a.ctr_off, a.np, a.n,
-                a.p, a.x1x2, a.w, a.chan, a.tile_stats);
+                a.p, a.x1x2, a.w, a.chan, a.tile_stats, (int)(a.lds / sizeof(double)), a.vpart, a.vstride);
         else
             k_map<NS, NI, K, MIX><<<a.grid, kBlock, lds, a.stream>>>(a.cts, a.pts, a.grids, a.nb, a.s_lab, a.np, a.n,
                                                                          a.y, a.p, a.x1x2, a.jac, a.w);

@@ -3,6 +3,9 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tables.h"
 
 namespace msx {
 
@@ -19,6 +22,60 @@ __device__ __forceinline__ double vegas_map(double y, const double* __restrict__
     double wd = e1 - e0;
     jv *= nb * wd;
     return e0 + wd * (t - i);
+}
+
+// VEGAS bin of a uniform y in (0, 1): floor(y nb), clamped (vegas_map's bin).
+__device__ __forceinline__ int vegas_bin(double y, int nb) {
+    int i = (int)(y * nb);
+    return i < 0 ? 0 : (i > nb - 1 ? nb - 1 : i);
+}
+
+// Bytes of dynamic LDS that VEGAS histogram accumulation adds to the fused
+// sample kernel: one [vstride] FP64 histogram per wave, then the events' bin
+// numbers as bytes [kMaxDims][kBlock].
+constexpr size_t vegas_acc_lds(int vstride) {
+    return sizeof(double) * (size_t)kWaves * (size_t)vstride + (size_t)kMaxDims * kBlock;
+}
+
+// Adds w^2 of this wave's events to the wave's private histogram hw [dims][nb]
+// (VEGAS: sum of w^2 per bin of every dimension).  bins points at this
+// thread's bin bytes, row k at bins[k kBlock].  Lane b owns bins b and b + 64
+// (nb <= 128): for every dimension it collects, in lane order, the squared
+// weights of the wave's events with w != 0 that fall in its bins, read from
+// the event's lane; no two lanes write the same entry, and the order of the
+// sums is fixed, so the result is deterministic.  Called by every lane of the
+// wave (live: the lane holds an event).
+__device__ __forceinline__ void vegas_wave_accumulate(double* __restrict__ hw, const uint8_t* __restrict__ bins,
+                                                      int dims, int nb, int lane, bool live, double wv) {
+    const uint64_t nz = __ballot(live && wv != 0.0);
+    if (nz == 0) return;
+    const double w2 = wv * wv;
+    const int lo = __double2loint(w2), hi = __double2hiint(w2);
+    for (int k = 0; k < dims; ++k) {
+        const int mb = bins[k * kBlock];
+        double a0 = 0.0, a1 = 0.0;
+        uint64_t m = nz;
+        if (nb <= 64) {
+            while (m) {
+                const int j = __builtin_ctzll(m);
+                m &= m - 1;
+                const int bj = __builtin_amdgcn_readlane(mb, j);
+                const double wj = __hiloint2double(__builtin_amdgcn_readlane(hi, j), __builtin_amdgcn_readlane(lo, j));
+                a0 += bj == lane ? wj : 0.0;
+            }
+        } else {
+            while (m) {
+                const int j = __builtin_ctzll(m);
+                m &= m - 1;
+                const int bj = __builtin_amdgcn_readlane(mb, j);
+                const double wj = __hiloint2double(__builtin_amdgcn_readlane(hi, j), __builtin_amdgcn_readlane(lo, j));
+                a0 += bj == lane ? wj : 0.0;
+                a1 += bj == lane + 64 ? wj : 0.0;
+            }
+        }
+        if (lane < nb) hw[k * nb + lane] += a0;
+        if (lane + 64 < nb) hw[k * nb + lane + 64] += a1;
+    }
 }
 
 // Deterministic wave-level reductions (fixed butterfly order).

@@ -389,6 +389,25 @@ __global__ void k_set_call(SampleCall call, SampleCall* __restrict__ dev) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *dev = call;
 }
 
+// VEGAS histograms of a fused sample: entry i of the context's histogram
+// array (channel c from the offsets, i - hist_off[c] within its [dims][nb]
+// block) gets the sum over c's tiles, in tile order, of the tiles' partials.
+__global__ __launch_bounds__(kBlock) void k_vegas_tiles(const SampleCall* __restrict__ call,
+                                                        const int64_t* __restrict__ hist_off, int64_t hist_total,
+                                                        int vstride, const double* __restrict__ vpart,
+                                                        double* __restrict__ hist) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= hist_total) return;
+    const int n_chan = call->n_chan;
+    int c = 0;
+    while (c + 1 < n_chan && hist_off[c + 1] <= i) ++c;
+    const int64_t r = i - hist_off[c];
+    const int64_t t0 = call->tile_start[c], t1 = call->tile_start[c + 1];
+    double acc = 0.0;
+    for (int64_t t = t0; t < t1; ++t) acc += vpart[t * vstride + r];
+    hist[i] += acc;
+}
+
 // Call table from device-resident counts (one thread: at most kMaxChannels).
 __global__ void k_plan(const int64_t* __restrict__ counts, int n_chan, int64_t capacity, int ept,
                        SampleCall* __restrict__ dev, int32_t* __restrict__ status) {
@@ -709,7 +728,8 @@ hipError_t launch_sample(const ChannelTab* cts, const ProcessTab* pts, const dou
                          const int32_t* chan_nb, const SampleCall* call, int n_chan, int max_slots, int max_inv,
                          int kinds, int mixed, size_t lds_bytes, uint64_t seed, uint64_t sid, const uint64_t* ctr_dev,
                          uint64_t ctr_off, int np, int64_t ld, double* p, double* x1x2, double* w, int32_t* chan,
-                         double* tile_stats, double* stats, int grid, hipStream_t s) {
+                         double* tile_stats, double* stats, int grid, hipStream_t s, double* vpart, int vstride,
+                         const int64_t* hist_off, int64_t hist_total, double* hist) {
     ChainLaunch a{};
     a.sample = true;
     a.lds = lds_bytes;
@@ -732,10 +752,28 @@ hipError_t launch_sample(const ChannelTab* cts, const ProcessTab* pts, const dou
     a.w = w;
     a.chan = chan;
     a.tile_stats = tile_stats;
+    a.vpart = vpart;
+    a.vstride = vstride;
     hipError_t err = launch_chain(reg_class(max_slots, max_inv), kind_class(kinds), mixed, a);
     if (err != hipSuccess) return err;
     k_stats_final<<<n_chan, kBlock, 0, s>>>(call, tile_stats, stats);
+    if (vpart && hist_total > 0) {
+        const int64_t g = (hist_total + kBlock - 1) / kBlock;
+        k_vegas_tiles<<<dim3((unsigned)g), dim3(kBlock), 0, s>>>(call, hist_off, hist_total, vstride, vpart, hist);
+    }
     return hipGetLastError();
+}
+
+namespace {
+// rows of the sample kernel's per-thread staging column (stage_rows of the
+// chain kernels)
+int stage_rows_host(int ns, int ni) { return (ns + ni + 1) > kQRows ? (ns + ni + 1) : kQRows; }
+}  // namespace
+
+size_t sample_lds_bytes(int max_slots, int max_inv, size_t lds_bytes, int vstride) {
+    const int rc = reg_class(max_slots, max_inv);
+    const int rows = rc == 0 ? stage_rows_host(6, 4) : (rc == 1 ? stage_rows_host(10, 8) : stage_rows_host(14, 8));
+    return lds_bytes + sizeof(double) * (size_t)rows * kBlock + (vstride > 0 ? vegas_acc_lds(vstride) : 0);
 }
 
 hipError_t launch_set_call(const SampleCall& host, SampleCall* dev, hipStream_t s) {

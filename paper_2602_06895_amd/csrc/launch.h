@@ -31,6 +31,8 @@ struct ChainLaunch {
     const uint64_t* ctr_dev;  // device counter offset (overrides ctr_off) or NULL
     int32_t* chan;
     double* tile_stats;
+    double* vpart;  // per-tile VEGAS histograms [tiles][vstride], NULL: no accumulation
+    int vstride;
     // both
     int np;
     int64_t n;  // map: events; sample: row stride of the outputs
@@ -86,11 +88,22 @@ hipError_t launch_weight(const ChannelTab* ct, const ProcessTab* pt, int mixed, 
 // Fused multichannel sample.  `call` is the device copy of the call table;
 // `max_tiles` bounds its n_tiles (for the per-channel statistics pass);
 // `ld` is the row stride of the outputs (>= the events of the call).
+// With vpart != NULL the kernel also accumulates every channel's VEGAS
+// histogram (sum w^2 per bin of every dimension) into per-tile partials
+// vpart [tiles][vstride] (vstride >= dims x bins of every channel), and a
+// second kernel adds them, tiles in order, to hist at hist_off[c] (device
+// array, per channel).
 hipError_t launch_sample(const ChannelTab* cts, const ProcessTab* pts, const double* grids, const int64_t* grid_off,
                          const int32_t* chan_nb, const SampleCall* call, int n_chan, int max_slots, int max_inv,
                          int kinds, int mixed, size_t lds_bytes, uint64_t seed, uint64_t sid, const uint64_t* ctr_dev,
                          uint64_t ctr_off, int np, int64_t ld, double* p, double* x1x2, double* w, int32_t* chan,
-                         double* tile_stats, double* stats, int grid, hipStream_t s);
+                         double* tile_stats, double* stats, int grid, hipStream_t s, double* vpart = nullptr,
+                         int vstride = 0, const int64_t* hist_off = nullptr, int64_t hist_total = 0,
+                         double* hist = nullptr);
+// Dynamic LDS bytes of a sample launch with VEGAS accumulation (grid area
+// lds_bytes, vstride doubles per wave histogram) for the register class of
+// (max_slots, max_inv).
+size_t sample_lds_bytes(int max_slots, int max_inv, size_t lds_bytes, int vstride);
 
 // Device copy of a host-built call table (stream ordered).
 hipError_t launch_set_call(const SampleCall& host, SampleCall* dev, hipStream_t s);

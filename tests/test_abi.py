@@ -85,7 +85,8 @@ def test_calls_on_null_context_fail_cleanly(L):
     v = C.c_int64()
     assert L.msx_get_meta(None, 0, 0, C.byref(v)) == 1
     assert L.msx_map(None, 0, 10, None, None, None, None, None, None) == 1
-    assert L.msx_sample(None, None, 0, 0, 0, None, None, None, None, None) == 1
+    assert L.msx_sample(None, None, 0, 0, 0, 0, None, None, None, None, None) == 1
+    assert L.msx_vegas_adapt(None, 10, 1, 0.5, 1, 0, 0, None, None) == 1
     assert L.msx_vegas_update(None, 0.5, None) == 1
     assert L.msx_destroy(None) == 0
     assert L.msx_last_error(None).decode() != ""
@@ -101,3 +102,33 @@ def test_valid_description_reaches_the_device_check(L):
         L.msx_destroy(h)
     else:
         assert st == 2 and "device" in L.msx_last_error(None).decode()
+
+
+def test_allocate_counts_is_neyman(L):
+    """msx_allocate_counts (host only): counts proportional to each channel's
+    weight standard deviation above a floor, summing to the total."""
+    import numpy as np
+
+    rng = np.random.default_rng(3)
+    for C_ in (1, 3, 8, 24):
+        n = rng.integers(100, 10000, C_).astype(float)
+        mean = rng.random(C_)
+        sd = rng.random(C_) * 2.0
+        if C_ > 1:
+            sd[0] = 0.0
+        stats = np.stack([mean * n, (sd ** 2 + mean ** 2) * n, n, np.zeros(C_), np.ones(C_)], axis=1)
+        total, floor = 1_000_003, 0.01
+        out = np.zeros(C_, dtype=np.int64)
+        assert L.msx_allocate_counts(C_, stats.ctypes.data, total, floor, out.ctypes.data) == 0
+        assert out.sum() == total and (out >= int(floor * total)).all()
+        rest = total - int(floor * total) * C_
+        got = sd / sd.sum()
+        share = (out - int(floor * total)) / rest
+        assert np.abs(share - got).max() <= C_ / rest + 1e-9
+    # degenerate: every channel flat -> equal shares
+    stats = np.tile([2.0, 4.0, 2.0, 0.0, 1.0], (4, 1))
+    out = np.zeros(4, dtype=np.int64)
+    assert L.msx_allocate_counts(4, stats.ctypes.data, 10, 0.0, out.ctypes.data) == 0
+    assert out.tolist() == [4, 2, 2, 2]
+    assert L.msx_allocate_counts(4, stats.ctypes.data, -1, 0.0, out.ctypes.data) == 1
+    assert L.msx_allocate_counts(4, stats.ctypes.data, 10, 0.5, out.ctypes.data) == 1

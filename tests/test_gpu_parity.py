@@ -251,8 +251,12 @@ def test_bad_arguments_raise(ctxs, torch):
     with pytest.raises(MsxError):
         ctx.sample(np.array([-1, 0, 0, 0, 0, 0, 0, 0]), seed=1)
     bad = np.array([5, -1, 0, 0, 0, 0, 0, 0], dtype=np.int64)
-    assert ctx.L.msx_sample(ctx.h, bad.ctypes.data, 1, 0, 0, y.data_ptr(), y.data_ptr(), y.data_ptr(),
+    assert ctx.L.msx_sample(ctx.h, bad.ctypes.data, 1, 0, 0, 0, y.data_ptr(), y.data_ptr(), y.data_ptr(),
                             None, None) == 1
+    good = np.array([5, 0, 0, 0, 0, 0, 0, 0], dtype=np.int64)
+    assert ctx.L.msx_sample(ctx.h, good.ctypes.data, 1, 0, 0, 64, y.data_ptr(), y.data_ptr(), y.data_ptr(),
+                            None, None) == 1
+    assert b"flags" in ctx.L.msx_last_error(ctx.h)
     with pytest.raises(MsxError):
         ctx.vegas_update(alpha=-1.0)
     with pytest.raises(ValueError):

@@ -228,6 +228,22 @@ msx_status msx_sample(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64
                       uint64_t counter_offset, int32_t flags, double* p, double* x1x2, double* w,
                       int32_t* chan, void* stream);
 
+/* msx_sample for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same events, weights, channel ids and statistics as msx_sample with flags 0
+ * (bit-identical for the same launch shape), but the per-tile statistics of
+ * the launch live in a fixed device array of the library (4 doubles x 2^17
+ * tiles = 4 MiB, one copy per GPU, held until the process ends) instead of
+ * context scratch grown on demand, and the call allocates nothing.  The
+ * tiles of a call (sum over channels of ceil(counts[c] / (256 x events per
+ * thread))) must not exceed 2^17: larger calls fail with MSX_ERR_ARG before
+ * any launch.  All contexts on one GPU share the array: calls that overlap in
+ * time on one GPU (different streams, or different host threads) race on it
+ * and give wrong statistics; calls ordered on one stream do not. */
+msx_status msx_sample_noalloc(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id,
+                              uint64_t counter_offset, double* p, double* x1x2, double* w, int32_t* chan,
+                              void* stream);
+
 /* msx_sample with its parameters in device memory, for launches captured in
  * a HIP graph and replayed with new values: counts [n_channels] (int64) and
  * counter_offset (one uint64) are read by the device when the launch runs.

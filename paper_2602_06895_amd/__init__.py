@@ -30,7 +30,8 @@ EXPORTS = ["msx_last_error", "msx_create_channels", "msx_destroy", "msx_get_meta
            "msx_flow_gradient", "msx_flow_train_step", "msx_flow_sample", "msx_sample_device",
            "msx_sample_graph_create", "msx_graph_launch", "msx_graph_destroy", "msx_set_launch", "msx_autotune",
            "msx_inverse_map", "msx_multichannel_density", "msx_unweight", "msx_observables", "msx_cut",
-           "msx_histogram", "msx_vegas_adapt", "msx_allocate_counts"]
+           "msx_histogram", "msx_vegas_adapt", "msx_allocate_counts",
+           "msx_sample_noalloc"]
 OBS_E, OBS_PT, OBS_ETA, OBS_PHI, OBS_M, OBS_PT_RANK, OBS_DR_HARDEST = range(7)
 FLOW_BF16, FLOW_FP32 = 0, 1
 SAMPLE_ACCUMULATE_VEGAS, SAMPLE_USE_FLOW = 1, 2
@@ -70,6 +71,7 @@ def load_library(path: str = LIB_PATH):
         "msx_weight": ([vp, i32, i64, vp, vp, vp, vp, vp, vp], C.c_int),
         "msx_sample": ([vp, vp, u64, u64, u64, i32, vp, vp, vp, vp, vp], C.c_int),
         "msx_vegas_adapt": ([vp, i64, i32, dbl, u64, u64, u64, vp, vp], C.c_int),
+        "msx_sample_noalloc": ([vp, vp, u64, u64, u64, vp, vp, vp, vp, vp], C.c_int),
         "msx_allocate_counts": ([i32, vp, i64, dbl, vp], C.c_int),
         "msx_stats": ([vp, vp, vp], C.c_int),
         "msx_reset_stats": ([vp, vp], C.c_int),

@@ -55,6 +55,9 @@ struct msx_ctx {
     int vstride = 0;
     double* d_vtiles = nullptr;
     int64_t vtiles_cap = 0;  // tiles
+    // device address of the library's fixed scratch on this device
+    // (msx_sample_noalloc); not owned by the context
+    double* d_noalloc = nullptr;
     size_t lds_max = 0;
     SampleCall* d_call = nullptr;  // call table of the last sample launch
     // launch shape of the fused sample kernel (events per thread per tile,
@@ -275,7 +278,8 @@ msx_status msx_create_channels(const char* process_json, int32_t precision, int3
         (e = up(c->d_row_grid, row_grid.data(), sizeof(int64_t) * row_grid.size())) != hipSuccess ||
         (e = up(c->d_row_hist, row_hist.data(), sizeof(int64_t) * row_hist.size())) != hipSuccess ||
         (e = hipMemset(c->d_hist, 0, sizeof(double) * std::max<int64_t>(c->hist_total, 1))) != hipSuccess ||
-        (e = hipMemset(c->d_stats, 0, sizeof(double) * 5 * C)) != hipSuccess) {
+        (e = hipMemset(c->d_stats, 0, sizeof(double) * 5 * C)) != hipSuccess ||
+        (e = noalloc_scratch(device, &c->d_noalloc)) != hipSuccess) {
         std::string m = std::string("device setup: ") + hipGetErrorString(e);
         msx_status st = e == hipErrorOutOfMemory ? MSX_ERR_OOM : MSX_ERR_DEVICE;
         free_all(c);
@@ -440,10 +444,16 @@ msx_status msx_weight(msx_ctx* ctx, int32_t channel, int64_t n, const double* p,
     return MSX_OK;
 }
 
-msx_status msx_sample(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id, uint64_t counter_offset,
-                      int32_t flags, double* p, double* x1x2, double* w, int32_t* chan, void* stream) {
+namespace {
+
+// msx_sample and msx_sample_noalloc: with noalloc, the tile statistics go to
+// the library's fixed device scratch (no allocation; flags must be 0).
+msx_status sample_host(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id,
+                       uint64_t counter_offset, int32_t flags, double* p, double* x1x2, double* w, int32_t* chan,
+                       void* stream, bool noalloc) {
     if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
     if (!counts) return fail(ctx, MSX_ERR_ARG, "counts is NULL");
+    if (noalloc && flags != 0) return fail(ctx, MSX_ERR_UNSUPPORTED, "msx_sample_noalloc takes no flags");
     if (flags & MSX_SAMPLE_USE_FLOW) return sample_with_flows(ctx, counts, seed, stream_id, counter_offset, flags, p,
                                                               x1x2, w, chan, stream);
     const int C = (int)ctx->comp.chans.size();
@@ -478,8 +488,13 @@ msx_status msx_sample(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64
     if (any_hadronic && !x1x2) return fail(ctx, MSX_ERR_ARG, "x1x2 is required when a sampled channel is hadronic");
     if (msx_status st = check_sample_flags(ctx, flags, max_slots, max_inv)) return st;
     const bool acc = (flags & MSX_SAMPLE_ACCUMULATE_VEGAS) != 0;
+    if (noalloc && tiles > kNoAllocTiles)
+        return fail(ctx, MSX_ERR_ARG,
+                    "msx_sample_noalloc: " + std::to_string(tiles) + " tiles of " + std::to_string(T) +
+                        " events exceed the fixed scratch of " + std::to_string(kNoAllocTiles) + " tiles");
     if (msx_status st = set_device(ctx)) return st;
-    if (msx_status st = ensure_tiles(ctx, tiles)) return st;
+    if (!noalloc)
+        if (msx_status st = ensure_tiles(ctx, tiles)) return st;
     if (acc)
         if (msx_status st = ensure_vtiles(ctx, tiles)) return st;
     hipStream_t s = (hipStream_t)stream;
@@ -488,10 +503,24 @@ msx_status msx_sample(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64
     MSX_HIP(ctx,
             launch_sample(ctx->d_chans, ctx->d_procs, ctx->d_grids, ctx->d_grid_off, ctx->d_chan_nb, ctx->d_call, C,
                           max_slots, max_inv, kinds, ctx->mixed, ctx->lds_max, seed, stream_id, nullptr,
-                          counter_offset, ctx->max_np, N, p, x1x2, w, chan, ctx->d_tile, ctx->d_stats, grid, s,
-                          acc ? ctx->d_vtiles : nullptr, ctx->vstride, ctx->d_hist_off, ctx->hist_total, ctx->d_hist),
+                          counter_offset, ctx->max_np, N, p, x1x2, w, chan, noalloc ? ctx->d_noalloc : ctx->d_tile,
+                          ctx->d_stats, grid, s, acc ? ctx->d_vtiles : nullptr, ctx->vstride, ctx->d_hist_off,
+                          ctx->hist_total, ctx->d_hist),
             "sample launch");
     return MSX_OK;
+}
+
+}  // namespace
+
+msx_status msx_sample(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id, uint64_t counter_offset,
+                      int32_t flags, double* p, double* x1x2, double* w, int32_t* chan, void* stream) {
+    return sample_host(ctx, counts, seed, stream_id, counter_offset, flags, p, x1x2, w, chan, stream, false);
+}
+
+msx_status msx_sample_noalloc(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id,
+                              uint64_t counter_offset, double* p, double* x1x2, double* w, int32_t* chan,
+                              void* stream) {
+    return sample_host(ctx, counts, seed, stream_id, counter_offset, 0, p, x1x2, w, chan, stream, true);
 }
 
 msx_status msx_sample_device(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id,

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "chain.h"
 #include "device_util.h"
@@ -788,6 +789,39 @@ hipError_t launch_plan(const int64_t* counts, int n_chan, int64_t capacity, int 
 }
 
 int sample_block() { return kBlock; }
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch of the allocation-free sample entry point: the tile
+// statistics of one launch (4 doubles per tile).  Each GPU that runs the
+// library holds one copy for the life of the process; its device address is
+// looked up once per device (hipGetSymbolAddress) and used from then on --
+// the array's name in host code is only a host-side stand-in.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[4 * kNoAllocTiles];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(int device, double** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = (double*)g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 hipError_t launch_vegas_accumulate(int64_t n, int dims, int nb, const double* y, const double* w, double* part,
                                    int64_t nchunk, int64_t chunk, double* hist, hipStream_t s) {

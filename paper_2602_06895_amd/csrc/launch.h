@@ -116,6 +116,14 @@ hipError_t launch_plan(const int64_t* counts, int n_chan, int64_t capacity, int 
 
 int sample_block();  // threads per workgroup of the sample kernel
 
+// The allocation-free sample entry point's fixed device scratch: room for the
+// tile statistics of kNoAllocTiles tiles, one copy per GPU (devices
+// 0 .. kMaxScratchDevices - 1).  *out = its device address on `device`, looked
+// up on the first call for that device and kept.
+constexpr int64_t kNoAllocTiles = 1 << 17;
+constexpr int kMaxScratchDevices = 64;
+hipError_t noalloc_scratch(int device, double** out);
+
 hipError_t launch_vegas_accumulate(int64_t n, int dims, int nb, const double* y, const double* w, double* part,
                                    int64_t nchunk, int64_t chunk, double* hist, hipStream_t s);
 

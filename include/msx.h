@@ -125,7 +125,10 @@ enum {
     MSX_META_DEVICE = 7,       /* HIP device ordinal of the context */
     MSX_META_PRECISION = 8,    /* MSX_FP64 or MSX_MIXED */
     MSX_META_EVENTS_PER_THREAD = 9, /* sample launch shape: events per thread per tile */
-    MSX_META_GRID = 10         /* sample launch shape: workgroups of the persistent grid */
+    MSX_META_GRID = 10,        /* sample launch shape: workgroups of the persistent grid */
+    MSX_META_COUNTER = 11,     /* next event id of MSX_COUNTER_AUTO sample calls */
+    MSX_META_FLOW = 12         /* channel `index`: 0 no flow attached, 1 attached but VEGAS kept
+                                  (the attach check found the flow no better), 2 flow enabled */
 };
 
 /* Text of the last error on this context (or of the last failed create when
@@ -197,6 +200,12 @@ msx_status msx_multichannel_density(msx_ctx* ctx, int32_t process, int64_t n, co
 msx_status msx_weight(msx_ctx* ctx, int32_t channel, int64_t n, const double* p,
                       const double* x1x2, const double* jac, double* w, double* alpha,
                       void* stream);
+
+/* counter_offset value of msx_sample / msx_sample_noalloc that takes the
+ * context's running event counter (MSX_META_COUNTER, saved by msx_get_state)
+ * as the first event id and advances it by the events of the call, so that
+ * successive calls draw disjoint events without the caller tracking ids. */
+#define MSX_COUNTER_AUTO UINT64_MAX
 
 /* Flags of the sample calls.
  *  MSX_SAMPLE_ACCUMULATE_VEGAS: the fused kernel also adds, per channel,
@@ -327,6 +336,22 @@ msx_status msx_allocate_counts(int32_t n_channels, const double* stats, int64_t 
  * by the paper for its adaptive grids), then clear the histograms.  Channels
  * with an empty histogram keep their grid. */
 msx_status msx_vegas_update(msx_ctx* ctx, double alpha, void* stream);
+
+/* The context's adaptive state as one host blob (checkpoint / resume; the
+ * explicit state that section 3.3's interface conventions ask of a
+ * component): every channel's VEGAS grid and accumulated histogram, the
+ * per-channel statistics, the sample launch shape, the running event counter
+ * (MSX_COUNTER_AUTO) and, for every channel with an attached flow, whether it
+ * is enabled and the flow's own state (msx_flow_get_state: FP32 parameters,
+ * Adam moments and step count).  get: buf NULL sets *size to the bytes
+ * needed; otherwise *size must be at least that, and receives it.  set:
+ * restores a blob taken from a context of the same process description (same
+ * channels, dimensions and bins) whose flows are attached to the same
+ * channels, with shapes equal (else MSX_ERR_STATE, nothing changed); grids
+ * are validated as msx_set_grid does.  Both synchronise the device.  The
+ * layout is host-endian and versioned by its leading 8 bytes ("MSXSTAT1"). */
+msx_status msx_get_state(msx_ctx* ctx, void* buf, size_t* size);
+msx_status msx_set_state(msx_ctx* ctx, const void* buf, size_t size);
 
 /* Host copies of a channel's grid edges [d][bins+1] (checkpoint/resume and
  * tests).  Both synchronise. set_grid validates monotone edges from 0 to 1. */

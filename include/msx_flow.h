@@ -57,6 +57,17 @@ msx_status msx_flow_create(int32_t dims, int32_t layers, int32_t bins, int32_t h
                            int32_t device, msx_flow** out);
 msx_status msx_flow_destroy(msx_flow* flow);
 
+/* Random dimensions d of the flow. */
+msx_status msx_flow_dims(const msx_flow* flow, int32_t* dims);
+
+/* The flow's trainable state as one host blob: shape, FP32 master
+ * parameters, Adam's moments m and v and its step count (checkpoint /
+ * resume).  get: buf NULL sets *size to the bytes needed (16 + 32 + 12 P);
+ * set: restores a blob of a flow of the same shape and type (else
+ * MSX_ERR_STATE; non-finite values are refused).  Both synchronise. */
+msx_status msx_flow_get_state(msx_flow* flow, void* buf, size_t* size);
+msx_status msx_flow_set_state(msx_flow* flow, const void* buf, size_t size);
+
 /* Number of FP32 parameters. */
 msx_status msx_flow_param_count(const msx_flow* flow, int64_t* n);
 
@@ -87,6 +98,20 @@ msx_status msx_flow_gradient(msx_flow* flow, int64_t n, const float* y, const do
  * loss[0] (device, optional) receives L. */
 msx_status msx_flow_train_step(msx_flow* flow, int64_t n, const float* y, const double* wfj, const float* logq_old,
                                float lr, double* loss, void* stream);
+
+/* Attach a trained flow to channel `channel` of ctx for MSX_SAMPLE_USE_FLOW
+ * sample calls (flow NULL detaches).  The flow must have the channel's
+ * dimension and outlive its attachment; the context does not own it.  With
+ * n_check > 0 the library decides whether to use it -- the fallback to plain
+ * VEGAS: it draws n_check events through the channel's VEGAS grid alone and
+ * n_check through the flow (msx_flow_sample), and enables the flow only if
+ * its relative weight variance var(w)/mean(w)^2 is the lower one (at equal
+ * event count the flow then reaches a smaller integral error).  n_check = 0
+ * enables it unconditionally.  *enabled (optional) gets the decision,
+ * rel_var[2] (optional) the two relative variances (VEGAS, flow; NaN without
+ * a check).  Synchronises. */
+msx_status msx_attach_flow(msx_ctx* ctx, int32_t channel, msx_flow* flow, int64_t n_check, uint64_t seed,
+                           int32_t* enabled, double* rel_var);
 
 /* Production path of the learned sampler for one channel of `ctx` (whose
  * dims must equal the flow's): 24-bit Philox uniforms u (key (seed,

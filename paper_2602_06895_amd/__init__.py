@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libmsx.so")
 FP64, MIXED = 0, 1
 META_N_CHANNELS, META_DIMS, META_N_MOMENTA, META_HADRONIC = 0, 1, 2, 3
 META_VEGAS_BINS, META_MAX_MOMENTA, META_PROCESS, META_DEVICE, META_PRECISION = 4, 5, 6, 7, 8
-META_EVENTS_PER_THREAD, META_GRID = 9, 10
+META_EVENTS_PER_THREAD, META_GRID, META_COUNTER, META_FLOW = 9, 10, 11, 12
+COUNTER_AUTO = 2 ** 64 - 1
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_DEVICE", 3: "ERR_OOM", 4: "ERR_UNSUPPORTED", 5: "ERR_STATE"}
 
 EXPORTS = ["msx_last_error", "msx_create_channels", "msx_destroy", "msx_get_meta", "msx_uniform", "msx_map",
@@ -31,7 +32,8 @@ EXPORTS = ["msx_last_error", "msx_create_channels", "msx_destroy", "msx_get_meta
            "msx_sample_graph_create", "msx_graph_launch", "msx_graph_destroy", "msx_set_launch", "msx_autotune",
            "msx_inverse_map", "msx_multichannel_density", "msx_unweight", "msx_observables", "msx_cut",
            "msx_histogram", "msx_vegas_adapt", "msx_allocate_counts",
-           "msx_sample_noalloc"]
+           "msx_sample_noalloc", "msx_get_state", "msx_set_state", "msx_attach_flow", "msx_flow_get_state",
+           "msx_flow_set_state", "msx_flow_dims"]
 OBS_E, OBS_PT, OBS_ETA, OBS_PHI, OBS_M, OBS_PT_RANK, OBS_DR_HARDEST = range(7)
 FLOW_BF16, FLOW_FP32 = 0, 1
 SAMPLE_ACCUMULATE_VEGAS, SAMPLE_USE_FLOW = 1, 2
@@ -72,6 +74,12 @@ def load_library(path: str = LIB_PATH):
         "msx_sample": ([vp, vp, u64, u64, u64, i32, vp, vp, vp, vp, vp], C.c_int),
         "msx_vegas_adapt": ([vp, i64, i32, dbl, u64, u64, u64, vp, vp], C.c_int),
         "msx_sample_noalloc": ([vp, vp, u64, u64, u64, vp, vp, vp, vp, vp], C.c_int),
+        "msx_get_state": ([vp, vp, C.POINTER(C.c_size_t)], C.c_int),
+        "msx_set_state": ([vp, vp, C.c_size_t], C.c_int),
+        "msx_attach_flow": ([vp, i32, vp, i64, u64, C.POINTER(i32), vp], C.c_int),
+        "msx_flow_get_state": ([vp, vp, C.POINTER(C.c_size_t)], C.c_int),
+        "msx_flow_set_state": ([vp, vp, C.c_size_t], C.c_int),
+        "msx_flow_dims": ([vp, C.POINTER(i32)], C.c_int),
         "msx_allocate_counts": ([i32, vp, i64, dbl, vp], C.c_int),
         "msx_stats": ([vp, vp, vp], C.c_int),
         "msx_reset_stats": ([vp, vp], C.c_int),
@@ -139,6 +147,7 @@ class Context:
         self.hadronic = [bool(self._meta(META_HADRONIC, c)) for c in range(self.n_channels)]
         self.nbins = [self._meta(META_VEGAS_BINS, c) for c in range(self.n_channels)]
         self.precision = self._meta(META_PRECISION, 0)
+        self._flows = {}  # attached flows, kept alive while attached
 
     # -- plumbing ------------------------------------------------------------
     def _check(self, st):
@@ -362,6 +371,34 @@ class Context:
             raise ValueError("grid shape mismatch")
         self._check(self.L.msx_set_grid(self.h, channel, e.ctypes.data))
 
+    def get_state(self) -> bytes:
+        """msx_get_state: grids, histograms, statistics, launch shape, event
+        counter and attached flows as one blob."""
+        n = C.c_size_t()
+        self._check(self.L.msx_get_state(self.h, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        self._check(self.L.msx_get_state(self.h, buf, C.byref(n)))
+        return buf.raw[:n.value]
+
+    def set_state(self, blob: bytes):
+        self._check(self.L.msx_set_state(self.h, blob, len(blob)))
+
+    def counter(self) -> int:
+        return self._meta(META_COUNTER, 0) % 2 ** 64
+
+    def attach_flow(self, channel: int, flow, n_check: int = 0, seed: int = 1):
+        """msx_attach_flow: returns (enabled, (rel. variance VEGAS, flow))."""
+        self._check_channel(channel)
+        en = C.c_int32()
+        rv = np.full(2, np.nan)
+        self._check(self.L.msx_attach_flow(self.h, channel, flow.h if flow is not None else None, n_check, seed,
+                                           C.byref(en), rv.ctypes.data))
+        self._flows[channel] = flow
+        return bool(en.value), (float(rv[0]), float(rv[1]))
+
+    def flow_state(self, channel: int) -> int:
+        return self._meta(META_FLOW, channel)
+
     def unweight_eff(self, w, overweight: float = 1e-3):
         if w.dtype != self.torch.float64 or w.device != self.device:
             raise ValueError("w must be a float64 tensor on the context's device")
@@ -444,6 +481,16 @@ class Flow:
         if p.shape != (self.n_params,):
             raise ValueError(f"expected {self.n_params} parameters")
         self._check(self.L.msx_flow_set_params(self.h, p.ctypes.data, p.shape[0]))
+
+    def get_state(self) -> bytes:
+        n = C.c_size_t()
+        self._check(self.L.msx_flow_get_state(self.h, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        self._check(self.L.msx_flow_get_state(self.h, buf, C.byref(n)))
+        return buf.raw[:n.value]
+
+    def set_state(self, blob: bytes):
+        self._check(self.L.msx_flow_set_state(self.h, blob, len(blob)))
 
     def get_params(self) -> np.ndarray:
         p = np.empty(self.n_params, dtype=np.float32)

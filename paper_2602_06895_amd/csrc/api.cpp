@@ -1,5 +1,6 @@
 // C ABI of the phase-space library (declared in include/msx.h).
 #include "../../include/msx.h"
+#include "../../include/msx_flow.h"
 
 #include <hip/hip_runtime.h>
 
@@ -58,6 +59,21 @@ struct msx_ctx {
     // device address of the library's fixed scratch on this device
     // (msx_sample_noalloc); not owned by the context
     double* d_noalloc = nullptr;
+    // next event id of MSX_COUNTER_AUTO sample calls
+    uint64_t next_counter = 0;
+    // learned samplers attached per channel (not owned) and whether the
+    // attach check enabled them
+    std::vector<msx_flow*> flow;
+    std::vector<int> flow_on;
+    // MSX_SAMPLE_USE_FLOW scratch of one flow channel's events, and moment partials
+    int64_t fs_cap = 0;
+    float* fs_y = nullptr;
+    float* fs_logq = nullptr;
+    double* fs_p = nullptr;
+    double* fs_x = nullptr;
+    double* fs_wfj = nullptr;
+    double* fs_w = nullptr;
+    double* d_mom = nullptr;
     size_t lds_max = 0;
     SampleCall* d_call = nullptr;  // call table of the last sample launch
     // launch shape of the fused sample kernel (events per thread per tile,
@@ -109,7 +125,8 @@ hipError_t dmalloc(T** p, size_t count) {
 void free_all(msx_ctx* c) {
     void* ptrs[] = {c->d_chans, c->d_procs, c->d_grids, c->d_hist, c->d_stats, c->d_grid_off, c->d_chan_nb,
                     c->d_row_nb, c->d_row_grid, c->d_row_hist, c->d_tile, c->d_vpart, c->d_unw, c->d_call,
-                    c->d_inv, c->d_ublk, c->d_obs_hist, c->d_hist_off, c->d_vtiles};
+                    c->d_inv, c->d_ublk, c->d_obs_hist, c->d_hist_off, c->d_vtiles, c->fs_y, c->fs_logq, c->fs_p,
+                    c->fs_x, c->fs_wfj, c->fs_w, c->d_mom};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -259,6 +276,8 @@ msx_status msx_create_channels(const char* process_json, int32_t precision, int3
     c->n_rows = (int)row_nb.size();
     for (int ch = 0; ch < C; ++ch)
         c->vstride = std::max(c->vstride, c->comp.meta[ch].dims * c->comp.meta[ch].nbins);
+    c->flow.assign(C, nullptr);
+    c->flow_on.assign(C, 0);
     auto up = [&](void* dst, const void* src, size_t bytes) { return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice); };
     if ((e = dmalloc(&c->d_chans, C)) != hipSuccess || (e = dmalloc(&c->d_procs, c->comp.procs.size())) != hipSuccess ||
         (e = dmalloc(&c->d_grids, grids.size())) != hipSuccess || (e = dmalloc(&c->d_hist, c->hist_total)) != hipSuccess ||
@@ -267,7 +286,7 @@ msx_status msx_create_channels(const char* process_json, int32_t precision, int3
         (e = dmalloc(&c->d_row_grid, row_grid.size())) != hipSuccess ||
         (e = dmalloc(&c->d_row_hist, row_hist.size())) != hipSuccess ||
         (e = dmalloc(&c->d_unw, 2 * 4096 + 2 * 1024 + 2)) != hipSuccess || (e = dmalloc(&c->d_call, 1)) != hipSuccess ||
-        (e = dmalloc(&c->d_hist_off, C)) != hipSuccess ||
+        (e = dmalloc(&c->d_hist_off, C)) != hipSuccess || (e = dmalloc(&c->d_mom, 4 * moments_blocks())) != hipSuccess ||
         (e = up(c->d_hist_off, c->hist_off.data(), sizeof(int64_t) * C)) != hipSuccess ||
         (e = up(c->d_chans, c->comp.chans.data(), sizeof(ChannelTab) * C)) != hipSuccess ||
         (e = up(c->d_procs, c->comp.procs.data(), sizeof(ProcessTab) * c->comp.procs.size())) != hipSuccess ||
@@ -316,6 +335,9 @@ msx_status msx_get_meta(const msx_ctx* ctx, int32_t key, int32_t index, int64_t*
         case MSX_META_PRECISION: *value = ctx->mixed ? MSX_MIXED : MSX_FP64; return MSX_OK;
         case MSX_META_EVENTS_PER_THREAD: *value = ctx->ept; return MSX_OK;
         case MSX_META_GRID: *value = sample_grid(ctx); return MSX_OK;
+        case MSX_META_COUNTER: *value = (int64_t)ctx->next_counter; return MSX_OK;
+        case MSX_META_FLOW:
+            return chan(index >= 0 && index < C ? (ctx->flow[index] ? 1 + ctx->flow_on[index] : 0) : 0);
         case MSX_META_DIMS: return chan(index >= 0 && index < C ? ctx->comp.meta[index].dims : 0);
         case MSX_META_N_MOMENTA: return chan(index >= 0 && index < C ? ctx->comp.meta[index].n_momenta : 0);
         case MSX_META_HADRONIC: return chan(index >= 0 && index < C ? ctx->comp.meta[index].hadronic : 0);
@@ -454,6 +476,22 @@ msx_status sample_host(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint6
     if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
     if (!counts) return fail(ctx, MSX_ERR_ARG, "counts is NULL");
     if (noalloc && flags != 0) return fail(ctx, MSX_ERR_UNSUPPORTED, "msx_sample_noalloc takes no flags");
+    if (counter_offset == MSX_COUNTER_AUTO) {
+        // the context's running event counter: resolve it, then advance it
+        // by the events of this call once the call is accepted
+        int64_t total = 0;
+        for (int c = 0; c < (int)ctx->comp.chans.size(); ++c) {
+            if (counts[c] < 0) return fail(ctx, MSX_ERR_ARG, "negative event count");
+            if (counts[c] > INT64_MAX / 4 - total) return fail(ctx, MSX_ERR_ARG, "event count overflow");
+            total += counts[c];
+        }
+        const uint64_t start = ctx->next_counter;
+        if (start == MSX_COUNTER_AUTO || start > MSX_COUNTER_AUTO - 1 - (uint64_t)total)
+            return fail(ctx, MSX_ERR_ARG, "the context's event counter is exhausted");
+        msx_status st = sample_host(ctx, counts, seed, stream_id, start, flags, p, x1x2, w, chan, stream, noalloc);
+        if (st == MSX_OK) ctx->next_counter = start + (uint64_t)total;
+        return st;
+    }
     if (flags & MSX_SAMPLE_USE_FLOW) return sample_with_flows(ctx, counts, seed, stream_id, counter_offset, flags, p,
                                                               x1x2, w, chan, stream);
     const int C = (int)ctx->comp.chans.size();
@@ -1034,9 +1072,346 @@ msx_status msx_unweight_eff(msx_ctx* ctx, const double* w, int64_t n, double ove
 
 namespace {
 
-msx_status sample_with_flows(msx_ctx* ctx, const int64_t*, uint64_t, uint64_t, uint64_t, int32_t, double*, double*,
-                             double*, int32_t*, void*) {
-    return fail(ctx, MSX_ERR_UNSUPPORTED, "MSX_SAMPLE_USE_FLOW: no flow attached");
+msx_status ensure_flow_scratch(msx_ctx* ctx, int64_t n, int dims) {
+    if (n <= ctx->fs_cap) return MSX_OK;
+    void** ptrs[] = {(void**)&ctx->fs_y, (void**)&ctx->fs_logq, (void**)&ctx->fs_p, (void**)&ctx->fs_x,
+                     (void**)&ctx->fs_wfj, (void**)&ctx->fs_w};
+    for (void** q : ptrs) {
+        if (*q) MSX_HIP(ctx, hipFree(*q), "hipFree");
+        *q = nullptr;
+    }
+    ctx->fs_cap = 0;
+    int max_dims = dims;
+    for (const ChannelMeta& m : ctx->comp.meta) max_dims = std::max(max_dims, m.dims);
+    MSX_HIP(ctx, dmalloc(&ctx->fs_y, (size_t)max_dims * n), "flow sample scratch");
+    MSX_HIP(ctx, dmalloc(&ctx->fs_logq, (size_t)n), "flow sample scratch");
+    MSX_HIP(ctx, dmalloc(&ctx->fs_p, (size_t)4 * ctx->max_np * n), "flow sample scratch");
+    MSX_HIP(ctx, dmalloc(&ctx->fs_x, (size_t)2 * n), "flow sample scratch");
+    MSX_HIP(ctx, dmalloc(&ctx->fs_wfj, (size_t)n), "flow sample scratch");
+    MSX_HIP(ctx, dmalloc(&ctx->fs_w, (size_t)n), "flow sample scratch");
+    ctx->fs_cap = n;
+    return MSX_OK;
 }
 
+// MSX_SAMPLE_USE_FLOW: the fused kernel runs every channel without an
+// enabled flow (the call table skips the flow channels' output ranges and
+// statistics); each flow channel then samples through msx_flow_sample into
+// the context's scratch, whose rows are copied into the caller's layout, and
+// its statistics are added by the moments kernel.
+msx_status sample_with_flows(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id,
+                             uint64_t counter_offset, int32_t flags, double* p, double* x1x2, double* w, int32_t* chan,
+                             void* stream) {
+    const int C = (int)ctx->comp.chans.size();
+    SampleCall call;
+    std::memset(&call, 0, sizeof call);
+    call.n_chan = C;
+    call.ept = ctx->ept;
+    const int64_t T = (int64_t)sample_block() * ctx->ept;
+    int64_t N = 0, tiles = 0;
+    bool any_hadronic = false;
+    int max_slots = 0, max_inv = 0, kinds = 0;
+    for (int c = 0; c < C; ++c) {
+        if (counts[c] < 0) return fail(ctx, MSX_ERR_ARG, "negative event count");
+        if (counts[c] > INT64_MAX / 4 - N) return fail(ctx, MSX_ERR_ARG, "event count overflow");
+        const bool by_flow = ctx->flow[c] && ctx->flow_on[c];
+        call.ev_start[c] = N;
+        call.tile_start[c] = tiles;
+        N += counts[c];
+        if (counts[c] > 0) any_hadronic = any_hadronic || ctx->comp.meta[c].hadronic;
+        if (by_flow) {
+            call.skip_mask |= 1ull << c;
+        } else {
+            tiles += (counts[c] + T - 1) / T;
+            if (counts[c] > 0) {
+                max_slots = std::max(max_slots, ctx->comp.chans[c].n_slots);
+                max_inv = std::max(max_inv, ctx->comp.chans[c].n_inv);
+                kinds |= ctx->comp.chans[c].kinds;
+            }
+        }
+    }
+    call.ev_start[C] = N;
+    call.tile_start[C] = tiles;
+    call.n_tiles = tiles;
+    if (N == 0) return MSX_OK;
+    if (counter_offset > UINT64_MAX - (uint64_t)N) return fail(ctx, MSX_ERR_ARG, "event ids overflow the counter");
+    if (!p || !w) return fail(ctx, MSX_ERR_ARG, "p and w are required");
+    if (any_hadronic && !x1x2) return fail(ctx, MSX_ERR_ARG, "x1x2 is required when a sampled channel is hadronic");
+    if (msx_status st = check_sample_flags(ctx, flags, max_slots, max_inv)) return st;
+    bool any_flow = false;
+    for (int c = 0; c < C; ++c) any_flow = any_flow || (counts[c] > 0 && (call.skip_mask >> c & 1));
+    if (!any_flow) return fail(ctx, MSX_ERR_STATE, "MSX_SAMPLE_USE_FLOW: no sampled channel has an enabled flow");
+    const bool acc = (flags & MSX_SAMPLE_ACCUMULATE_VEGAS) != 0;
+    if (msx_status st = set_device(ctx)) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (tiles > 0) {
+        if (msx_status st = ensure_tiles(ctx, tiles)) return st;
+        if (acc)
+            if (msx_status st = ensure_vtiles(ctx, tiles)) return st;
+        MSX_HIP(ctx, launch_set_call(call, ctx->d_call, s), "sample call table");
+        const int grid = (int)std::min<int64_t>(tiles, sample_grid(ctx));
+        MSX_HIP(ctx,
+                launch_sample(ctx->d_chans, ctx->d_procs, ctx->d_grids, ctx->d_grid_off, ctx->d_chan_nb, ctx->d_call,
+                              C, max_slots, max_inv, kinds, ctx->mixed, ctx->lds_max, seed, stream_id, nullptr,
+                              counter_offset, ctx->max_np, N, p, x1x2, w, chan, ctx->d_tile, ctx->d_stats, grid, s,
+                              acc ? ctx->d_vtiles : nullptr, ctx->vstride, ctx->d_hist_off, ctx->hist_total,
+                              ctx->d_hist),
+                "sample launch");
+    }
+    for (int c = 0; c < C; ++c) {
+        const int64_t n = counts[c];
+        if (n == 0 || !(call.skip_mask >> c & 1)) continue;
+        const ChannelMeta& m = ctx->comp.meta[c];
+        const int64_t off = call.ev_start[c];
+        if (msx_status st = ensure_flow_scratch(ctx, n, m.dims)) return st;
+        if (msx_flow_sample(ctx->flow[c], ctx, c, n, seed, stream_id, counter_offset + (uint64_t)off, ctx->fs_y,
+                            ctx->fs_logq, ctx->fs_p, m.hadronic ? ctx->fs_x : nullptr, ctx->fs_wfj, ctx->fs_w,
+                            stream) != MSX_OK)
+            return fail(ctx, MSX_ERR_DEVICE, std::string("flow sample: ") + msx_flow_last_error(ctx->flow[c]));
+        const size_t row = sizeof(double) * (size_t)n;
+        for (int comp = 0; comp < 4; ++comp)
+            MSX_HIP(ctx,
+                    hipMemcpy2DAsync(p + ((size_t)comp * ctx->max_np) * N + off, sizeof(double) * N,
+                                     ctx->fs_p + (size_t)comp * m.n_momenta * n, row, row, m.n_momenta,
+                                     hipMemcpyDeviceToDevice, s),
+                    "flow event copy");
+        if (m.hadronic)
+            MSX_HIP(ctx,
+                    hipMemcpy2DAsync(x1x2 + off, sizeof(double) * N, ctx->fs_x, row, row, 2, hipMemcpyDeviceToDevice,
+                                     s),
+                    "flow event copy");
+        MSX_HIP(ctx, hipMemcpyAsync(w + off, ctx->fs_w, row, hipMemcpyDeviceToDevice, s), "flow event copy");
+        if (chan) MSX_HIP(ctx, launch_fill_i32(chan + off, n, c, s), "channel ids");
+        MSX_HIP(ctx, launch_moments_add(ctx->fs_w, n, ctx->d_mom, ctx->d_stats + 5 * c, s), "flow statistics");
+    }
+    return MSX_OK;
+}
+
+// Philox stream tags of the attach check's samples.
+constexpr uint64_t kCheckStreamVegas = 0x4d53584356ull, kCheckStreamFlow = 0x4d53584346ull;
+
+// Relative variance var(w) / mean(w)^2 of n weights on the device (host result).
+msx_status rel_variance(msx_ctx* ctx, const double* w, int64_t n, double* d_out, double* out, hipStream_t s) {
+    MSX_HIP(ctx, hipMemsetAsync(d_out, 0, sizeof(double) * 5, s), "moments clear");
+    MSX_HIP(ctx, launch_moments_add(w, n, ctx->d_mom, d_out, s), "moments");
+    double h[5];
+    MSX_HIP(ctx, hipMemcpyAsync(h, d_out, sizeof h, hipMemcpyDeviceToHost, s), "moments copy");
+    MSX_HIP(ctx, hipStreamSynchronize(s), "moments sync");
+    const double mean = h[0] / n;
+    *out = mean != 0.0 ? std::max(h[1] / n - mean * mean, 0.0) / (mean * mean) : INFINITY;
+    return MSX_OK;
+}
+
+// Serialised context state: this header, dims[C] and bins[C] (int32), the
+// grids (grid_total doubles), the VEGAS histograms (hist_total), the
+// statistics (5 C), then per attached flow (int32 channel, int32 enabled,
+// int64 bytes, the flow's own state).
+struct CtxStateHeader {
+    char magic[8];  // "MSXSTAT1"
+    int32_t n_channels, ept, grid, n_flows;
+    int64_t grid_total, hist_total;
+    uint64_t next_counter;
+    int64_t pad;
+};
+constexpr char kCtxMagic[8] = {'M', 'S', 'X', 'S', 'T', 'A', 'T', '1'};
+
 }  // namespace
+
+extern "C" {
+
+msx_status msx_get_state(msx_ctx* ctx, void* buf, size_t* size) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (!size) return fail(ctx, MSX_ERR_ARG, "size is NULL");
+    const int C = (int)ctx->comp.chans.size();
+    size_t need = sizeof(CtxStateHeader) + sizeof(int32_t) * 2 * C +
+                  sizeof(double) * (size_t)(ctx->grid_total + ctx->hist_total + 5 * C);
+    std::vector<size_t> fbytes(C, 0);
+    int n_flows = 0;
+    for (int c = 0; c < C; ++c) {
+        if (!ctx->flow[c]) continue;
+        if (msx_flow_get_state(ctx->flow[c], nullptr, &fbytes[c]) != MSX_OK)
+            return fail(ctx, MSX_ERR_ARG, std::string("flow state: ") + msx_flow_last_error(ctx->flow[c]));
+        need += 2 * sizeof(int32_t) + sizeof(int64_t) + fbytes[c];
+        ++n_flows;
+    }
+    if (!buf) {
+        *size = need;
+        return MSX_OK;
+    }
+    if (*size < need) return fail(ctx, MSX_ERR_ARG, "state buffer too small");
+    if (msx_status st = set_device(ctx)) return st;
+    MSX_HIP(ctx, hipDeviceSynchronize(), "sync");
+    char* b = (char*)buf;
+    CtxStateHeader h{};
+    std::memcpy(h.magic, kCtxMagic, 8);
+    h.n_channels = C;
+    h.ept = ctx->ept;
+    h.grid = ctx->grid;
+    h.n_flows = n_flows;
+    h.grid_total = ctx->grid_total;
+    h.hist_total = ctx->hist_total;
+    h.next_counter = ctx->next_counter;
+    std::memcpy(b, &h, sizeof h);
+    b += sizeof h;
+    for (int c = 0; c < C; ++c) {
+        const int32_t v[2] = {ctx->comp.meta[c].dims, ctx->comp.meta[c].nbins};
+        std::memcpy(b + sizeof(int32_t) * c, &v[0], sizeof(int32_t));
+        std::memcpy(b + sizeof(int32_t) * (C + c), &v[1], sizeof(int32_t));
+    }
+    b += sizeof(int32_t) * 2 * C;
+    MSX_HIP(ctx, hipMemcpy(b, ctx->d_grids, sizeof(double) * ctx->grid_total, hipMemcpyDeviceToHost), "state copy");
+    b += sizeof(double) * ctx->grid_total;
+    MSX_HIP(ctx, hipMemcpy(b, ctx->d_hist, sizeof(double) * ctx->hist_total, hipMemcpyDeviceToHost), "state copy");
+    b += sizeof(double) * ctx->hist_total;
+    MSX_HIP(ctx, hipMemcpy(b, ctx->d_stats, sizeof(double) * 5 * C, hipMemcpyDeviceToHost), "state copy");
+    b += sizeof(double) * 5 * C;
+    for (int c = 0; c < C; ++c) {
+        if (!ctx->flow[c]) continue;
+        const int32_t hc[2] = {c, ctx->flow_on[c]};
+        const int64_t nb = (int64_t)fbytes[c];
+        std::memcpy(b, hc, sizeof hc);
+        b += sizeof hc;
+        std::memcpy(b, &nb, sizeof nb);
+        b += sizeof nb;
+        size_t got = fbytes[c];
+        if (msx_flow_get_state(ctx->flow[c], b, &got) != MSX_OK)
+            return fail(ctx, MSX_ERR_DEVICE, std::string("flow state: ") + msx_flow_last_error(ctx->flow[c]));
+        b += fbytes[c];
+    }
+    *size = need;
+    return MSX_OK;
+}
+
+msx_status msx_set_state(msx_ctx* ctx, const void* buf, size_t size) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (!buf || size < sizeof(CtxStateHeader)) return fail(ctx, MSX_ERR_ARG, "state buffer too small");
+    const int C = (int)ctx->comp.chans.size();
+    const char* b = (const char*)buf;
+    const char* end = b + size;
+    CtxStateHeader h;
+    std::memcpy(&h, b, sizeof h);
+    b += sizeof h;
+    if (std::memcmp(h.magic, kCtxMagic, 8) != 0) return fail(ctx, MSX_ERR_STATE, "not a context state");
+    if (h.n_channels != C || h.grid_total != ctx->grid_total || h.hist_total != ctx->hist_total)
+        return fail(ctx, MSX_ERR_STATE, "state of a different process description");
+    if (h.ept < 1 || h.ept > 64 || h.grid < 0 || h.grid > (1 << 20) || h.n_flows < 0 || h.n_flows > C)
+        return fail(ctx, MSX_ERR_STATE, "corrupt state header");
+    const size_t fixed = sizeof(int32_t) * 2 * C + sizeof(double) * (size_t)(h.grid_total + h.hist_total + 5 * C);
+    if ((size_t)(end - b) < fixed) return fail(ctx, MSX_ERR_STATE, "truncated state");
+    for (int c = 0; c < C; ++c) {
+        int32_t d, nb;
+        std::memcpy(&d, b + sizeof(int32_t) * c, sizeof d);
+        std::memcpy(&nb, b + sizeof(int32_t) * (C + c), sizeof nb);
+        if (d != ctx->comp.meta[c].dims || nb != ctx->comp.meta[c].nbins)
+            return fail(ctx, MSX_ERR_STATE, "state of a different process description");
+    }
+    b += sizeof(int32_t) * 2 * C;
+    const double* grids = (const double*)b;
+    std::vector<double> g(grids, grids + h.grid_total);
+    for (int c = 0; c < C; ++c) {
+        const ChannelMeta& m = ctx->comp.meta[c];
+        for (int k = 0; k < m.dims; ++k) {
+            const double* e = g.data() + ctx->grid_off[c] + (size_t)k * (m.nbins + 1);
+            if (e[0] != 0.0 || e[m.nbins] != 1.0) return fail(ctx, MSX_ERR_STATE, "grid edges must run from 0 to 1");
+            for (int i = 0; i < m.nbins; ++i)
+                if (!(e[i + 1] > e[i])) return fail(ctx, MSX_ERR_STATE, "grid edges must increase strictly");
+        }
+    }
+    b += sizeof(double) * h.grid_total;
+    const char* hist = b;
+    b += sizeof(double) * h.hist_total;
+    const char* stats = b;
+    b += sizeof(double) * 5 * C;
+    // flows: each must be attached to the same channel of this context
+    struct FlowRec {
+        int c, on;
+        const char* blob;
+        size_t bytes;
+    };
+    std::vector<FlowRec> fr;
+    for (int i = 0; i < h.n_flows; ++i) {
+        if ((size_t)(end - b) < 2 * sizeof(int32_t) + sizeof(int64_t)) return fail(ctx, MSX_ERR_STATE, "truncated state");
+        int32_t hc[2];
+        int64_t nb;
+        std::memcpy(hc, b, sizeof hc);
+        b += sizeof hc;
+        std::memcpy(&nb, b, sizeof nb);
+        b += sizeof nb;
+        if (hc[0] < 0 || hc[0] >= C || nb < 0 || (size_t)(end - b) < (size_t)nb)
+            return fail(ctx, MSX_ERR_STATE, "corrupt flow record");
+        if (!ctx->flow[hc[0]]) return fail(ctx, MSX_ERR_STATE, "the state holds a flow for a channel without one");
+        fr.push_back({hc[0], hc[1] ? 1 : 0, b, (size_t)nb});
+        b += nb;
+    }
+    if (b != end) return fail(ctx, MSX_ERR_STATE, "state size mismatch");
+    if (msx_status st = set_device(ctx)) return st;
+    MSX_HIP(ctx, hipDeviceSynchronize(), "sync");
+    for (const FlowRec& f : fr)
+        if (msx_flow_set_state(ctx->flow[f.c], f.blob, f.bytes) != MSX_OK)
+            return fail(ctx, MSX_ERR_STATE, std::string("flow state: ") + msx_flow_last_error(ctx->flow[f.c]));
+    MSX_HIP(ctx, hipMemcpy(ctx->d_grids, g.data(), sizeof(double) * h.grid_total, hipMemcpyHostToDevice), "state copy");
+    MSX_HIP(ctx, hipMemcpy(ctx->d_hist, hist, sizeof(double) * h.hist_total, hipMemcpyHostToDevice), "state copy");
+    MSX_HIP(ctx, hipMemcpy(ctx->d_stats, stats, sizeof(double) * 5 * C, hipMemcpyHostToDevice), "state copy");
+    for (const FlowRec& f : fr) ctx->flow_on[f.c] = f.on;
+    ctx->ept = h.ept;
+    ctx->grid = h.grid;
+    ctx->next_counter = h.next_counter;
+    return MSX_OK;
+}
+
+msx_status msx_attach_flow(msx_ctx* ctx, int32_t channel, msx_flow* flow, int64_t n_check, uint64_t seed,
+                           int32_t* enabled, double* rel_var) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (msx_status st = check_channel(ctx, channel)) return st;
+    if (enabled) *enabled = 0;
+    if (!flow) {
+        ctx->flow[channel] = nullptr;
+        ctx->flow_on[channel] = 0;
+        return MSX_OK;
+    }
+    const ChannelMeta& m = ctx->comp.meta[channel];
+    int32_t fd = 0;
+    if (msx_flow_dims(flow, &fd) != MSX_OK || fd != m.dims)
+        return fail(ctx, MSX_ERR_ARG, "the flow's dimension differs from the channel's");
+    if (n_check < 0) return fail(ctx, MSX_ERR_ARG, "n_check < 0");
+    int on = 1;
+    double rv[2] = {NAN, NAN};
+    if (n_check > 0) {
+        // the fallback decision: relative weight variance of n_check events
+        // drawn through the VEGAS grid alone and through the flow (same
+        // channel, fixed stream tags); the flow is enabled only if lower
+        if (msx_status st = set_device(ctx)) return st;
+        if (msx_status st = ensure_flow_scratch(ctx, n_check, m.dims)) return st;
+        hipStream_t s = nullptr;
+        MSX_HIP(ctx, hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "check stream");
+        double *d_out = nullptr, *y = nullptr;
+        msx_status st = MSX_OK;
+        hipError_t e = dmalloc(&d_out, 5);
+        if (e == hipSuccess) e = dmalloc(&y, (size_t)m.dims * n_check);
+        if (e != hipSuccess) st = dev_fail(ctx, e, "check buffers");
+        if (st == MSX_OK) st = msx_uniform(ctx, seed, kCheckStreamVegas, 0, n_check, m.dims, y, s);
+        if (st == MSX_OK)
+            st = msx_map(ctx, channel, n_check, y, ctx->fs_p, m.hadronic ? ctx->fs_x : nullptr, ctx->fs_wfj,
+                         ctx->fs_w, s);
+        if (st == MSX_OK) st = rel_variance(ctx, ctx->fs_w, n_check, d_out, &rv[0], s);
+        if (st == MSX_OK &&
+            msx_flow_sample(flow, ctx, channel, n_check, seed, kCheckStreamFlow, 0, ctx->fs_y, ctx->fs_logq,
+                            ctx->fs_p, m.hadronic ? ctx->fs_x : nullptr, ctx->fs_wfj, ctx->fs_w, s) != MSX_OK)
+            st = fail(ctx, MSX_ERR_DEVICE, std::string("flow sample: ") + msx_flow_last_error(flow));
+        if (st == MSX_OK) st = rel_variance(ctx, ctx->fs_w, n_check, d_out, &rv[1], s);
+        if (d_out) (void)hipFree(d_out);
+        if (y) (void)hipFree(y);
+        (void)hipStreamDestroy(s);
+        if (st != MSX_OK) return st;
+        on = rv[1] < rv[0] ? 1 : 0;
+    }
+    ctx->flow[channel] = flow;
+    ctx->flow_on[channel] = on;
+    if (enabled) *enabled = on;
+    if (rel_var) {
+        rel_var[0] = rv[0];
+        rel_var[1] = rv[1];
+    }
+    return MSX_OK;
+}
+
+}  // extern "C"

@@ -431,6 +431,77 @@ msx_status msx_flow_get_params(msx_flow* f, float* host, int64_t n) {
     return MSX_OK;
 }
 
+namespace {
+// Layout of a serialised flow state: this header, then the FP32 master
+// parameters, Adam's first and second moments (P floats each).
+struct FlowStateHeader {
+    char magic[8];  // "MSXFLOW1"
+    int32_t d, L, K, H, type, pad;
+    int64_t P, adam_t;
+};
+constexpr char kFlowMagic[8] = {'M', 'S', 'X', 'F', 'L', 'O', 'W', '1'};
+}  // namespace
+
+msx_status msx_flow_get_state(msx_flow* f, void* buf, size_t* size) {
+    if (!f) return ffail(nullptr, MSX_ERR_ARG, "flow is NULL");
+    if (!size) return ffail(f, MSX_ERR_ARG, "size is NULL");
+    const size_t need = sizeof(FlowStateHeader) + 3 * sizeof(float) * (size_t)f->P;
+    if (!buf) {
+        *size = need;
+        return MSX_OK;
+    }
+    if (*size < need) return ffail(f, MSX_ERR_ARG, "state buffer too small");
+    FlowStateHeader h{};
+    std::memcpy(h.magic, kFlowMagic, 8);
+    h.d = f->d;
+    h.L = f->L;
+    h.K = f->K;
+    h.H = f->H;
+    h.type = f->type;
+    h.P = f->P;
+    h.adam_t = f->adam_t;
+    char* b = (char*)buf;
+    std::memcpy(b, &h, sizeof h);
+    float* body = (float*)(b + sizeof h);
+    FHIP(f, hipSetDevice(f->device), "hipSetDevice");
+    FHIP(f, hipDeviceSynchronize(), "flow synchronise");
+    FHIP(f, hipMemcpy(body, f->params, sizeof(float) * f->P, hipMemcpyDeviceToHost), "flow state");
+    FHIP(f, hipMemcpy(body + f->P, f->m, sizeof(float) * f->P, hipMemcpyDeviceToHost), "flow state");
+    FHIP(f, hipMemcpy(body + 2 * f->P, f->v, sizeof(float) * f->P, hipMemcpyDeviceToHost), "flow state");
+    *size = need;
+    return MSX_OK;
+}
+
+msx_status msx_flow_set_state(msx_flow* f, const void* buf, size_t size) {
+    if (!f) return ffail(nullptr, MSX_ERR_ARG, "flow is NULL");
+    if (!buf || size < sizeof(FlowStateHeader)) return ffail(f, MSX_ERR_ARG, "state buffer too small");
+    FlowStateHeader h;
+    std::memcpy(&h, buf, sizeof h);
+    if (std::memcmp(h.magic, kFlowMagic, 8) != 0) return ffail(f, MSX_ERR_STATE, "not a flow state");
+    if (h.d != f->d || h.L != f->L || h.K != f->K || h.H != f->H || h.type != f->type || h.P != f->P)
+        return ffail(f, MSX_ERR_STATE, "flow state of a different shape");
+    if (size != sizeof h + 3 * sizeof(float) * (size_t)f->P) return ffail(f, MSX_ERR_STATE, "flow state size");
+    if (h.adam_t < 0) return ffail(f, MSX_ERR_STATE, "negative Adam step count");
+    const float* body = (const float*)((const char*)buf + sizeof h);
+    for (int64_t i = 0; i < 3 * f->P; ++i)
+        if (!std::isfinite(body[i])) return ffail(f, MSX_ERR_STATE, "flow state holds a non-finite value");
+    FHIP(f, hipSetDevice(f->device), "hipSetDevice");
+    FHIP(f, hipDeviceSynchronize(), "flow synchronise");
+    FHIP(f, hipMemcpy(f->params, body, sizeof(float) * f->P, hipMemcpyHostToDevice), "flow state");
+    FHIP(f, hipMemcpy(f->m, body + f->P, sizeof(float) * f->P, hipMemcpyHostToDevice), "flow state");
+    FHIP(f, hipMemcpy(f->v, body + 2 * f->P, sizeof(float) * f->P, hipMemcpyHostToDevice), "flow state");
+    f->adam_t = h.adam_t;
+    FHIP(f, launch_cast(f->P, f->params, f->type, f->params_t, f->per_layer, f->per_layer_t, nullptr), "flow cast");
+    FHIP(f, hipDeviceSynchronize(), "flow synchronise");
+    return MSX_OK;
+}
+
+msx_status msx_flow_dims(const msx_flow* f, int32_t* dims) {
+    if (!f || !dims) return ffail(nullptr, MSX_ERR_ARG, "flow and dims are required");
+    *dims = f->d;
+    return MSX_OK;
+}
+
 msx_status msx_flow_forward(msx_flow* f, int64_t n, const float* u, float* y, float* logdet, void* stream) {
     if (!f) return ffail(nullptr, MSX_ERR_ARG, "flow is NULL");
     if (msx_status st = check_events(f, n)) return st;

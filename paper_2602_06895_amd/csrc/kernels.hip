@@ -68,7 +68,7 @@ __global__ __launch_bounds__(kBlock) void k_stats_final(const SampleCall* __rest
                                                         double* __restrict__ stats) {
     const int c = blockIdx.x;
     __shared__ double red[4][kWaves];
-    if (c >= call->n_chan) return;
+    if (c >= call->n_chan || ((call->skip_mask >> c) & 1)) return;
     const int64_t t0 = call->tile_start[c], t1 = call->tile_start[c + 1];
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
@@ -418,6 +418,7 @@ __global__ void k_plan(const int64_t* __restrict__ counts, int n_chan, int64_t c
     int bad = 0;
     dev->n_chan = n_chan;
     dev->ept = ept;
+    dev->skip_mask = 0;
     for (int c = 0; c < n_chan; ++c) {
         const int64_t k = counts[c];
         dev->ev_start[c] = N;
@@ -922,7 +923,78 @@ __global__ void k_sum_max_final(int nblk, const double* __restrict__ part, doubl
     out[1] = b;
 }
 
+// Moments of a weight array: block b reduces its grid-stride share into
+// part[b] = (sum w, sum w^2, n(w == 0), max w); the final pass sums blocks in
+// order and adds to out = (sum w, sum w^2, n, n(w == 0), max w).
+constexpr int kMomBlocks = 256;
+__global__ __launch_bounds__(256) void k_moments(int64_t n, const double* __restrict__ w, double* __restrict__ part) {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        const double v = w[e];
+        a[0] += v;
+        a[1] += v * v;
+        a[2] += v == 0.0 ? 1.0 : 0.0;
+        a[3] = fmax(a[3], v);
+    }
+    __shared__ double r[4][4];
+    const double r0 = wave_sum(a[0]), r1 = wave_sum(a[1]), r2 = wave_sum(a[2]), r3 = wave_max(a[3]);
+    if ((threadIdx.x & 63) == 0) {
+        r[0][threadIdx.x >> 6] = r0;
+        r[1][threadIdx.x >> 6] = r1;
+        r[2][threadIdx.x >> 6] = r2;
+        r[3][threadIdx.x >> 6] = r3;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int q = threadIdx.x;
+        double acc = r[q][0];
+        for (int v = 1; v < 4; ++v) acc = q == 3 ? fmax(acc, r[q][v]) : acc + r[q][v];
+        part[4 * blockIdx.x + q] = acc;
+    }
+}
+
+__global__ void k_moments_final(int nblk, int64_t n, const double* __restrict__ part, double* __restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double a = 0.0, b = 0.0, z = 0.0, m = 0.0;
+    for (int i = 0; i < nblk; ++i) {
+        a += part[4 * i];
+        b += part[4 * i + 1];
+        z += part[4 * i + 2];
+        m = fmax(m, part[4 * i + 3]);
+    }
+    out[0] += a;
+    out[1] += b;
+    out[2] += (double)n;
+    out[3] += z;
+    out[4] = fmax(out[4], m);
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ x, int64_t n, int32_t v) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = v;
+}
+
 }  // namespace
+
+int64_t moments_blocks() { return kMomBlocks; }
+
+hipError_t launch_moments_add(const double* w, int64_t n, double* part, double* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int g = (int)std::min<int64_t>(kMomBlocks, (n + 255) / 256);
+    k_moments<<<g, 256, 0, s>>>(n, w, part);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    k_moments_final<<<1, 64, 0, s>>>(g, n, part, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* x, int64_t n, int32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int g = (int)std::min<int64_t>(4096, (n + 255) / 256);
+    k_fill_i32<<<g, 256, 0, s>>>(x, n, v);
+    return hipGetLastError();
+}
 
 hipError_t launch_unw_pass(int64_t n, const double* w, int shift, int width, uint64_t prefix, int first,
                            double* counts, double* sums, int cu_count, hipStream_t s) {

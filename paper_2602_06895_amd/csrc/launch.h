@@ -116,6 +116,13 @@ hipError_t launch_plan(const int64_t* counts, int n_chan, int64_t capacity, int 
 
 int sample_block();  // threads per workgroup of the sample kernel
 
+// Adds the moments (sum w, sum w^2, n, n(w == 0), max w) of w [n] to out[5]
+// (device; the first four summed, the last a maximum); part: scratch of
+// 4 moments_blocks() doubles.  Deterministic.
+int64_t moments_blocks();
+hipError_t launch_moments_add(const double* w, int64_t n, double* part, double* out, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* x, int64_t n, int32_t v, hipStream_t s);
+
 // The allocation-free sample entry point's fixed device scratch: room for the
 // tile statistics of kNoAllocTiles tiles, one copy per GPU (devices
 // 0 .. kMaxScratchDevices - 1).  *out = its device address on `device`, looked

@@ -168,6 +168,7 @@ struct SampleCall {
     int32_t n_chan;
     int32_t ept;                           // events per thread per tile
     int64_t n_tiles;
+    uint64_t skip_mask;                    // channels whose events another launch writes (no tiles, no statistics)
     int64_t tile_start[kMaxChannels + 1];  // first tile of each channel
     int64_t ev_start[kMaxChannels + 1];    // first output position
 };

@@ -1,0 +1,187 @@
+"""Explicit state through the C ABI: msx_get_state / msx_set_state (grids,
+histograms, statistics, launch shape, running event counter, attached flows),
+msx_flow_get_state / msx_flow_set_state (parameters and Adam moments),
+MSX_COUNTER_AUTO, and the learned sampler inside msx_sample
+(msx_attach_flow's fallback decision, MSX_SAMPLE_USE_FLOW).
+
+A restored context or flow must continue bit-identically to the one whose
+state was taken: the same kernels on the same inputs."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    if not t.cuda.is_available():
+        pytest.skip("needs a GPU")
+    return t
+
+
+def _same(a, b):
+    for k in ("p", "w", "x1x2", "chan"):
+        if a.get(k) is not None:
+            assert bool((a[k] == b[k]).all()), f"{k} differs"
+
+
+def test_context_state_round_trip(torch):
+    from paper_2602_06895_amd import COUNTER_AUTO, SAMPLE_ACCUMULATE_VEGAS, Context, MsxError, adapt_vegas
+
+    desc = W.c2_pp4j()
+    a = Context(desc)
+    adapt_vegas(a, n_per_channel=5000, iterations=2, seed=4, stream_id=1)
+    counts = np.array([1000, 3, 0, 700, 257, 1, 64, 999], dtype=np.int64)
+    a.set_launch(2, 512)
+    a.sample(counts, seed=5, counter_offset=COUNTER_AUTO, flags=SAMPLE_ACCUMULATE_VEGAS)
+    a.sample(counts, seed=5, counter_offset=COUNTER_AUTO)
+    assert a.counter() == 2 * counts.sum()
+    blob = a.get_state()
+    b = Context(desc)
+    b.set_state(blob)
+    assert b.counter() == a.counter() and b.launch_shape() == a.launch_shape()
+    assert np.array_equal(a.stats(), b.stats())
+    for c in range(8):
+        assert np.array_equal(a.get_grid(c), b.get_grid(c))
+    # the pending histograms came along: the same refinement on both
+    a.vegas_update(0.5)
+    b.vegas_update(0.5)
+    for c in range(8):
+        assert np.array_equal(a.get_grid(c), b.get_grid(c)), f"channel {c} after update"
+    # and the same next events from the running counter
+    oa = a.sample(counts, seed=6, counter_offset=COUNTER_AUTO)
+    ob = b.sample(counts, seed=6, counter_offset=COUNTER_AUTO)
+    torch.cuda.synchronize()
+    _same(oa, ob)
+    assert np.array_equal(a.stats(), b.stats())
+    # a state of another description, truncated or corrupted blobs are refused
+    c3 = Context(W.c3_ttbar6())
+    with pytest.raises(MsxError, match="ERR_STATE"):
+        c3.set_state(blob)
+    with pytest.raises(MsxError):
+        b.set_state(blob[:-8])
+    bad = bytearray(blob)
+    hdr = 56 + 8 * 8  # header, then dims and bins of the 8 channels
+    bad[hdr + 8: hdr + 16] = np.float64(2.0).tobytes()  # second edge of the first grid row beyond 1
+    with pytest.raises(MsxError, match="grid"):
+        b.set_state(bytes(bad))
+    # nothing changed by the refused calls
+    oc = b.sample(counts, seed=7, counter_offset=10 ** 6)
+    od = a.sample(counts, seed=7, counter_offset=10 ** 6)
+    torch.cuda.synchronize()
+    _same(oc, od)
+    for x in (a, b, c3):
+        x.close()
+
+
+def _train(flow, ctx, channel, steps, batch, seed):
+    for s in range(steps):
+        o = flow.sample(ctx, channel, batch, seed=seed, stream_id=5, counter_offset=s * batch)
+        flow.train_step(o["y"], o["wfj"], o["logq"], 1e-3)
+
+
+def test_flow_state_round_trip_continues_training(torch):
+    from paper_2602_06895_amd import Context, Flow, MsxError
+
+    ctx = Context(W.c2_pp4j())
+    d = ctx.dims[0]
+    f = Flow(d, 4, 16, 128)
+    f.set_params(W.flow_params(5, d, 4, 16, 128))
+    _train(f, ctx, 0, 3, 8192, 3)
+    blob = f.get_state()
+    g = Flow(d, 4, 16, 128)
+    g.set_state(blob)
+    assert np.array_equal(f.get_params(), g.get_params())
+    # one more step on the same batch: identical parameters only if the Adam
+    # moments and step count came along
+    o = f.sample(ctx, 0, 8192, seed=9, stream_id=1)
+    f.train_step(o["y"], o["wfj"], o["logq"], 1e-3)
+    g.train_step(o["y"], o["wfj"], o["logq"], 1e-3)
+    torch.cuda.synchronize()
+    assert np.array_equal(f.get_params(), g.get_params())
+    h = Flow(d, 4, 8, 128)
+    with pytest.raises(MsxError, match="shape"):
+        h.set_state(blob)
+    for x in (f, g, h, ctx):
+        x.close()
+
+
+def test_use_flow_sample_equals_its_parts(torch):
+    """MSX_SAMPLE_USE_FLOW with a flow on channels 0 and 5: the flow channels'
+    events equal msx_flow_sample of their ids, the others a plain sample's,
+    and the statistics add up likewise; the state blob carries the flow."""
+    from paper_2602_06895_amd import SAMPLE_USE_FLOW, Context, Flow
+
+    desc = W.c2_pp4j()
+    ctx, ref = Context(desc), Context(desc)
+    d = ctx.dims[0]
+    flows = {}
+    for c in (0, 5):
+        f = Flow(d, 4, 16, 128)
+        f.set_params(W.flow_params(11 + c, d, 4, 16, 128, last_scale=0.05))
+        en, rv = ctx.attach_flow(c, f, n_check=0)
+        assert en and np.isnan(rv).all() and ctx.flow_state(c) == 2
+        flows[c] = f
+    counts = np.array([3000, 500, 0, 1000, 1, 2049, 64, 7], dtype=np.int64)
+    seed, sid, off = 12, 3, 4242
+    out = ctx.sample(counts, seed=seed, stream_id=sid, counter_offset=off, flags=SAMPLE_USE_FLOW)
+    plain = ref.sample(counts, seed=seed, stream_id=sid, counter_offset=off)
+    torch.cuda.synchronize()
+    st, st_ref = ctx.stats(), ref.stats()
+    pos = np.concatenate([[0], np.cumsum(counts)])
+    for c in range(8):
+        lo, hi = pos[c], pos[c + 1]
+        if c in flows:
+            o = flows[c].sample(ref, c, int(counts[c]), seed=seed, stream_id=sid, counter_offset=off + int(lo))
+            torch.cuda.synchronize()
+            npc = ctx.n_momenta[c]
+            assert torch.equal(out["p"][:, :npc, lo:hi], o["p"])
+            assert torch.equal(out["x1x2"][:, lo:hi], o["x1x2"])
+            assert torch.equal(out["w"][lo:hi], o["w"])
+            w = o["w"].cpu().numpy()
+            assert st[c, 2] == counts[c] and st[c, 3] == (w == 0).sum() and st[c, 4] == w.max()
+            assert abs(st[c, 0] - w.sum()) <= 1e-12 * abs(w).sum()
+            assert abs(st[c, 1] - (w * w).sum()) <= 1e-12 * (w * w).sum()
+        else:
+            for k in ("p", "x1x2", "w"):
+                assert torch.equal(out[k][..., lo:hi], plain[k][..., lo:hi]), f"channel {c} {k}"
+            if counts[c]:
+                assert np.array_equal(st[c], st_ref[c]), f"channel {c} statistics"
+        assert bool((out["chan"][lo:hi] == c).all())
+    # the state blob carries the attached flows
+    blob = ctx.get_state()
+    assert len(blob) > 2 * len(flows[0].get_state())
+    ctx.close()
+    ref.close()
+    for f in flows.values():
+        f.close()
+
+
+def test_attach_check_keeps_vegas_for_a_poor_flow_and_enables_a_trained_one(torch):
+    from paper_2602_06895_amd import SAMPLE_USE_FLOW, Context, Flow, MsxError, adapt_vegas
+
+    ctx = Context(W.c2_pp4j())
+    adapt_vegas(ctx, n_per_channel=20000, iterations=4, seed=2, stream_id=1)
+    d = ctx.dims[0]
+    # a flow with large random parameters: far from the integrand's shape
+    bad = Flow(d, 4, 16, 128)
+    bad.set_params(W.flow_params(7, d, 4, 16, 128, last_scale=3.0))
+    en, (rv_v, rv_f) = ctx.attach_flow(0, bad, n_check=100000, seed=3)
+    assert not en and rv_f > rv_v and ctx.flow_state(0) == 1
+    with pytest.raises(MsxError, match="no sampled channel has an enabled flow"):
+        ctx.sample(np.array([100, 0, 0, 0, 0, 0, 0, 0]), seed=1, flags=SAMPLE_USE_FLOW)
+    # trained on this channel (t-channel dominated: VEGAS is poor there)
+    good = Flow(d, 8, 16, 128)
+    good.set_params(W.flow_params(31, d, 8, 16, 128))
+    _train(good, ctx, 0, 150, 32768, 10)
+    en, (rv_v2, rv_f2) = ctx.attach_flow(0, good, n_check=100000, seed=3)
+    assert en == (rv_f2 < rv_v2) and rv_v2 == rv_v
+    assert en, f"a trained flow should beat VEGAS on this channel (rel. variance {rv_f2:.3g} vs {rv_v2:.3g})"
+    ctx.attach_flow(0, None)
+    assert ctx.flow_state(0) == 0
+    for x in (bad, good, ctx):
+        x.close()

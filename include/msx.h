@@ -221,8 +221,13 @@ msx_status msx_weight(msx_ctx* ctx, int32_t channel, int64_t n, const double* p,
  *  MSX_SAMPLE_USE_FLOW: channels with a flow attached (msx_attach_flow) draw
  *    their uniforms from the flow (msx_flow_sample) instead of the VEGAS grid
  *    alone; the other channels run the fused kernel.  Host counts only
- *    (msx_sample); those channels' events are not VEGAS-accumulated.  */
-enum { MSX_SAMPLE_ACCUMULATE_VEGAS = 1, MSX_SAMPLE_USE_FLOW = 2 };
+ *    (msx_sample); those channels' events are not VEGAS-accumulated.
+ *  MSX_SAMPLE_ADVANCE_COUNTER: device-count launches only
+ *    (msx_sample_device, msx_sample_graph_create): after the sample the
+ *    library adds the call's total event count to *counter_offset (which it
+ *    then writes, despite the const), so that every replay of a captured
+ *    graph draws new events. */
+enum { MSX_SAMPLE_ACCUMULATE_VEGAS = 1, MSX_SAMPLE_USE_FLOW = 2, MSX_SAMPLE_ADVANCE_COUNTER = 4 };
 
 /* Fused production path, all channels in one launch: for channel c,
  * counts[c] events (host array of n_channels entries) are generated at

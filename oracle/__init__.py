@@ -71,6 +71,20 @@ def build_mutant(k: int, directory: str) -> str:
     return name
 
 
+def build_timing(directory: str) -> str:
+    """Build the same oracle source for timing on this host (-O3
+    -march=native, still no FMA contraction, OpenMP) into `directory` and
+    register it as variant "timing" of lib(): the CPU baseline's build.
+    Compiled where it runs, since -march=native targets the build machine."""
+    out = os.path.join(directory, "liboracle_timing.so")
+    cmd = ["gcc", "-O3", "-march=native", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-Wall",
+           "-Wno-unused-function", "-ffp-contract=off", _SRC, "-o", out, "-lm"]
+    subprocess.run(cmd, check=True)
+    _libs.pop("timing", None)
+    _libs["timing"] = _load(out)
+    return "timing"
+
+
 def lib(variant: str = "ref"):
     if variant not in _libs:
         build()

@@ -36,7 +36,7 @@ EXPORTS = ["msx_last_error", "msx_create_channels", "msx_destroy", "msx_get_meta
            "msx_flow_set_state", "msx_flow_dims"]
 OBS_E, OBS_PT, OBS_ETA, OBS_PHI, OBS_M, OBS_PT_RANK, OBS_DR_HARDEST = range(7)
 FLOW_BF16, FLOW_FP32 = 0, 1
-SAMPLE_ACCUMULATE_VEGAS, SAMPLE_USE_FLOW = 1, 2
+SAMPLE_ACCUMULATE_VEGAS, SAMPLE_USE_FLOW, SAMPLE_ADVANCE_COUNTER = 1, 2, 4
 
 
 class MsxError(RuntimeError):

@@ -167,7 +167,7 @@ constexpr size_t kLdsPerWorkgroup = 160 * 1024;  // gfx950: 160 KiB of LDS per c
 // Checks the flags of a sample call; with MSX_SAMPLE_ACCUMULATE_VEGAS also
 // that the kernel's LDS (staging column, grid, wave histograms) fits.
 msx_status check_sample_flags(msx_ctx* ctx, int32_t flags, int max_slots, int max_inv) {
-    if (flags & ~(MSX_SAMPLE_ACCUMULATE_VEGAS | MSX_SAMPLE_USE_FLOW))
+    if (flags & ~(MSX_SAMPLE_ACCUMULATE_VEGAS | MSX_SAMPLE_USE_FLOW | MSX_SAMPLE_ADVANCE_COUNTER))
         return fail(ctx, MSX_ERR_ARG, "unknown sample flags");
     if ((flags & MSX_SAMPLE_ACCUMULATE_VEGAS) &&
         sample_lds_bytes(max_slots, max_inv, ctx->lds_max, ctx->vstride) > kLdsPerWorkgroup)
@@ -190,7 +190,7 @@ int64_t device_max_tiles(const msx_ctx* ctx, int64_t capacity) {
 msx_status sample_device(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id,
                          const uint64_t* counter_offset, int64_t capacity, double* p, double* x1x2, double* w,
                          int32_t* chan, int32_t* status, SampleCall* d_call, double* d_tile, double* d_vtiles,
-                         hipStream_t s) {
+                         bool advance, hipStream_t s) {
     const int C = (int)ctx->comp.chans.size();
     const int64_t max_tiles = device_max_tiles(ctx, capacity);
     MSX_HIP(ctx, launch_plan(counts, C, capacity, ctx->ept, d_call, status, s), "sample plan");
@@ -201,6 +201,7 @@ msx_status sample_device(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uin
                           counter_offset, 0, ctx->max_np, capacity, p, x1x2, w, chan, d_tile, ctx->d_stats, grid, s,
                           d_vtiles, ctx->vstride, ctx->d_hist_off, ctx->hist_total, ctx->d_hist),
             "sample launch");
+    if (advance) MSX_HIP(ctx, launch_advance_counter(d_call, const_cast<uint64_t*>(counter_offset), s), "counter");
     return MSX_OK;
 }
 
@@ -476,6 +477,8 @@ msx_status sample_host(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint6
     if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
     if (!counts) return fail(ctx, MSX_ERR_ARG, "counts is NULL");
     if (noalloc && flags != 0) return fail(ctx, MSX_ERR_UNSUPPORTED, "msx_sample_noalloc takes no flags");
+    if (flags & MSX_SAMPLE_ADVANCE_COUNTER)
+        return fail(ctx, MSX_ERR_ARG, "MSX_SAMPLE_ADVANCE_COUNTER is for device-count launches (MSX_COUNTER_AUTO here)");
     if (counter_offset == MSX_COUNTER_AUTO) {
         // the context's running event counter: resolve it, then advance it
         // by the events of this call once the call is accepted
@@ -578,7 +581,8 @@ msx_status msx_sample_device(msx_ctx* ctx, const int64_t* counts, uint64_t seed,
     if (acc)
         if (msx_status st = ensure_vtiles(ctx, max_tiles)) return st;
     return sample_device(ctx, counts, seed, stream_id, counter_offset, capacity, p, x1x2, w, chan, status,
-                         ctx->d_call, ctx->d_tile, acc ? ctx->d_vtiles : nullptr, (hipStream_t)stream);
+                         ctx->d_call, ctx->d_tile, acc ? ctx->d_vtiles : nullptr,
+                         (flags & MSX_SAMPLE_ADVANCE_COUNTER) != 0, (hipStream_t)stream);
 }
 
 msx_status msx_sample_graph_create(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint64_t stream_id,
@@ -622,7 +626,7 @@ msx_status msx_sample_graph_create(msx_ctx* ctx, const int64_t* counts, uint64_t
     msx_status st = MSX_OK;
     if (e == hipSuccess) {
         st = sample_device(ctx, counts, seed, stream_id, counter_offset, capacity, p, x1x2, w, chan, status, g->d_call,
-                           g->d_tile, g->d_vtiles, s);
+                           g->d_tile, g->d_vtiles, (flags & MSX_SAMPLE_ADVANCE_COUNTER) != 0, s);
         hipError_t e2 = hipStreamEndCapture(s, &g->graph);
         if (st == MSX_OK && e2 != hipSuccess) e = e2;
     }

@@ -970,6 +970,10 @@ __global__ void k_moments_final(int nblk, int64_t n, const double* __restrict__ 
     out[4] = fmax(out[4], m);
 }
 
+__global__ void k_advance_counter(const SampleCall* __restrict__ call, uint64_t* __restrict__ ctr) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *ctr += (uint64_t)call->ev_start[call->n_chan];
+}
+
 __global__ void k_fill_i32(int32_t* __restrict__ x, int64_t n, int32_t v) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = v;
@@ -986,6 +990,11 @@ hipError_t launch_moments_add(const double* w, int64_t n, double* part, double* 
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     k_moments_final<<<1, 64, 0, s>>>(g, n, part, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance_counter(const SampleCall* call, uint64_t* ctr, hipStream_t s) {
+    k_advance_counter<<<1, 64, 0, s>>>(call, ctr);
     return hipGetLastError();
 }
 

@@ -122,6 +122,9 @@ int sample_block();  // threads per workgroup of the sample kernel
 int64_t moments_blocks();
 hipError_t launch_moments_add(const double* w, int64_t n, double* part, double* out, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* x, int64_t n, int32_t v, hipStream_t s);
+// *ctr += the events of the call table (device-count launches that advance
+// their counter offset).
+hipError_t launch_advance_counter(const SampleCall* call, uint64_t* ctr, hipStream_t s);
 
 // The allocation-free sample entry point's fixed device scratch: room for the
 // tile statistics of kNoAllocTiles tiles, one copy per GPU (devices

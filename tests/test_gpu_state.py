@@ -185,3 +185,30 @@ def test_attach_check_keeps_vegas_for_a_poor_flow_and_enables_a_trained_one(torc
     assert ctx.flow_state(0) == 0
     for x in (bad, good, ctx):
         x.close()
+
+
+def test_graph_replays_advance_their_counter(torch):
+    """MSX_SAMPLE_ADVANCE_COUNTER: replay r of the captured graph equals a
+    host-count sample at counter offset off0 + r N, and the device counter
+    ends at off0 + (replays) N; host-count calls refuse the flag."""
+    from paper_2602_06895_amd import SAMPLE_ADVANCE_COUNTER, Context, MsxError
+
+    desc = W.c2_pp4j()
+    ctx, ref = Context(desc), Context(desc)
+    counts = np.array([1000, 0, 5, 300, 0, 0, 1, 2000], dtype=np.int64)
+    N = int(counts.sum())
+    buf = ctx.sample_buffers(N)
+    dc = torch.from_numpy(counts).to(ctx.device)
+    off = torch.tensor([7], dtype=torch.int64, device=ctx.device)
+    g = ctx.sample_graph(dc, 3, 2, off, buf, flags=SAMPLE_ADVANCE_COUNTER)
+    for r in range(3):
+        g.launch()
+        e = ref.sample(counts, seed=3, stream_id=2, counter_offset=7 + r * N)
+        torch.cuda.synchronize()
+        _same({k: buf[k][..., :N] if buf[k] is not None else None for k in buf}, e)
+    assert int(off.item()) == 7 + 3 * N
+    with pytest.raises(MsxError, match="ADVANCE"):
+        ctx.sample(counts, seed=1, flags=SAMPLE_ADVANCE_COUNTER)
+    g.close()
+    ctx.close()
+    ref.close()

@@ -176,8 +176,11 @@ msx_status msx_map(msx_ctx* ctx, int32_t channel, int64_t n, const double* y, do
  * momenta of its cluster; per 2->2 block |t| = -(p_A - p_1)^2 and the
  * azimuth of p_1 about p_A in the rest frame of p_A + p_B; per decay the
  * angles of the first child in its parent's rest frame; then each map and
- * the VEGAS grid inverted.  FP64 in both precision modes.  Events that are
- * not in the channel's image give meaningless y.  n = 0 is a no-op. */
+ * the VEGAS grid inverted.  FP64 in both precision modes.  An event that is
+ * not in the channel's image (a recovered uniform more than 1e-6 outside
+ * [0, 1], e.g. a jet below a Chili channel's p_T cut) gets y = NaN in every
+ * dimension and jac = 0: its density in this channel is 0.  n = 0 is a
+ * no-op. */
 msx_status msx_inverse_map(msx_ctx* ctx, int32_t channel, int64_t n, const double* p, const double* x1x2, double* y,
                            double* jac, void* stream);
 

@@ -240,7 +240,7 @@ class _Process(C.Structure):
                 ("prop_m", C.c_void_p), ("prop_w", C.c_void_p), ("prop_mu", C.c_void_p),
                 ("n_chan", C.c_int32), ("alpha_mu", C.c_double), ("ch_start", C.c_void_p),
                 ("chp_t", C.c_void_p), ("chp_set", C.c_void_p), ("chp_m", C.c_void_p),
-                ("chp_w", C.c_void_p)]
+                ("chp_w", C.c_void_p), ("ch_prior", C.c_void_p)]
 
 
 def _ptr(a: np.ndarray):
@@ -431,7 +431,8 @@ class Process:
             chp_t=np.array([q[0] for q in chp] + [0], np.int32),
             chp_set=np.array([q[1] for q in chp] + [0], np.uint32),
             chp_m=np.array([q[2] for q in chp] + [0], np.float64),
-            chp_w=np.array([q[3] for q in chp] + [0], np.float64))
+            chp_w=np.array([q[3] for q in chp] + [0], np.float64),
+            ch_prior=np.array([1 if c.chili else 0 for c in self.channels], np.int32))
         k = self._k
         n_chan = len(self.channels) if "alpha_mu" in desc else 1
         self._proc = _Process(
@@ -442,7 +443,7 @@ class Process:
             _ptr(k["prop_t"]), _ptr(k["prop_set"]), _ptr(k["prop_bw"]), _ptr(k["prop_m"]),
             _ptr(k["prop_w"]), _ptr(k["prop_mu"]), n_chan, float(desc.get("alpha_mu", 0.0)),
             _ptr(k["ch_start"]), _ptr(k["chp_t"]), _ptr(k["chp_set"]), _ptr(k["chp_m"]),
-            _ptr(k["chp_w"]))
+            _ptr(k["chp_w"]), _ptr(k["ch_prior"]))
         self._chs = [c.struct() for c in self.channels]
 
     def uniform_grid(self, chan: int) -> np.ndarray:

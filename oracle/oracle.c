@@ -54,6 +54,9 @@ static double orc_nudge(double v)
 #define ORC_MAX_NODES 64
 #define ORC_MAX_FINAL 16
 #define ORC_MAX_DIMS 64
+/* Recovered uniforms farther than this outside [0, 1] mark an event that is
+ * not in the channel's image (its density there is 0). */
+#define ORC_SUPPORT_MARGIN 1e-6
 #define ORC_MAX_PROPS 64
 
 enum { ORC_LEAF = 0, ORC_CLUSTER = 1, ORC_TNODE = 2 };
@@ -110,6 +113,8 @@ typedef struct {
     const uint32_t* chp_set;
     const double* chp_m;
     const double* chp_w;
+    /* 1 for a channel without a diagram (Chili): constant share 1 / n_chan */
+    const int32_t* ch_prior;
 } orc_process;
 
 /* ------------------------------------------------------------------------ */
@@ -509,9 +514,17 @@ static double integrand(const orc_process* pr, int32_t chan, double pf[][4], con
     }
     if (pr->n_chan <= 1) {
         alpha = 1.0;
+    } else if (pr->ch_prior && pr->ch_prior[chan]) {
+        /* a channel without a diagram has no propagator denominators to
+         * weigh: it takes the constant share 1 / n_chan */
+        alpha = 1.0 / pr->n_chan;
     } else {
-        double den = 0.0, mine = 0.0;
+        double den = 0.0, mine = 0.0, share = 1.0;
         for (int32_t c = 0; c < pr->n_chan; ++c) {
+            if (pr->ch_prior && pr->ch_prior[c]) {
+                share -= 1.0 / pr->n_chan;
+                continue;
+            }
             double P = 1.0;
             for (int32_t u = pr->ch_start[c]; u < pr->ch_start[c + 1]; ++u) {
                 double q2 = prop_q2(pr->chp_t[u], pr->chp_set[u], pa, pf, n);
@@ -527,7 +540,9 @@ static double integrand(const orc_process* pr, int32_t chan, double pf[][4], con
             den += P;
             if (c == chan) mine = P;
         }
-        alpha = mine / den;
+        /* the diagram channels share what the others leave, in proportion
+         * to their propagator products */
+        alpha = share * (mine / den);
     }
     *alpha_out = alpha;
     return f;
@@ -1289,6 +1304,15 @@ int orc_inverse(const orc_process* pr, const orc_channel* ch, int32_t chan, int3
         }
         if (k != dims) {
             bad = 1;
+            continue;
+        }
+        int outside = 0;
+        for (int32_t q = 0; q < dims; ++q)
+            if (!(r[q] >= -ORC_SUPPORT_MARGIN && r[q] <= 1.0 + ORC_SUPPORT_MARGIN)) outside = 1;
+        if (outside) {
+            /* not in the channel's image: no uniforms map there, density 0 */
+            for (int32_t q = 0; q < dims; ++q) y[(size_t)q * n + e] = NAN;
+            if (jac) jac[e] = 0.0;
             continue;
         }
         for (int32_t q = 0; q < dims; ++q)

@@ -55,6 +55,10 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run __graft_entry__.build()")
+    # torch first: its HIP runtime is then the one the library binds to (two
+    # runtimes in one process do not share devices)
+    import torch  # noqa: F401
+
     L = C.CDLL(path)
     vp, i32, i64, u64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
     sigs = {

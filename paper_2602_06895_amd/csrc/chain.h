@@ -875,10 +875,14 @@ __device__ __forceinline__ double integrand_alpha(const ProcessTab* __restrict__
     }
     if (pt->n_fprop > 0) f /= fden;
     double alpha = 1.0;
-    if (nc > 1) {
+    if (nc > 1 && ((pt->chan_prior >> chan_in_proc) & 1)) {
+        alpha = pt->prior_share;
+    } else if (nc > 1) {
         q.set(kMaxUniq, 1.0);
         double den = 0.0, mine = 0.0;
+        const uint32_t prior = pt->chan_prior;
         for (int c = 0; c < nc; ++c) {
+            if ((prior >> c) & 1) continue;
             // product over the channel's invariants in ascending order, four
             // independent loads per round (short rounds padded with the 1.0 row)
             double D = 1.0;
@@ -897,7 +901,7 @@ __device__ __forceinline__ double integrand_alpha(const ProcessTab* __restrict__
             den += P;
             if (c == chan_in_proc) mine = P;
         }
-        alpha = mine / den;
+        alpha = pt->tree_share * (mine / den);
     }
     alpha_out = alpha;
     return alpha * f;

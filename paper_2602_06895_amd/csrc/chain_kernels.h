@@ -146,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void k_map(const ChannelTab* __restrict__ c
         int k = 0;
         double jv = 1.0;
         auto next = [&]() -> double {
-            double r = vegas_map(y[(int64_t)k * n + e], lg + k * (nb + 1), nb, jv);
+            double r = vegas_map_checked(y[(int64_t)k * n + e], lg + k * (nb + 1), nb, jv);
             ++k;
             return r;
         };
@@ -545,7 +545,16 @@ __global__ __launch_bounds__(kBlock) void k_inverse(const ChannelTab* __restrict
             }
         }
         // (6) inverse VEGAS map
-        for (int k = 0; k < dims; ++k) y[(int64_t)k * n + e] = vegas_unmap(col[k * kBlock], lg + k * (nb + 1), nb);
+        // recovered uniforms farther than kSupportMargin outside [0, 1]: the
+        // event is not in the channel's image; y = NaN marks it (the density
+        // pass then gives J = 0)
+        bool outside = false;
+        for (int k = 0; k < dims; ++k) {
+            const double r = col[k * kBlock];
+            outside = outside || !(r >= -kSupportMargin && r <= 1.0 + kSupportMargin);
+        }
+        for (int k = 0; k < dims; ++k)
+            y[(int64_t)k * n + e] = outside ? __builtin_nan("") : vegas_unmap(col[k * kBlock], lg + k * (nb + 1), nb);
     }
 }
 

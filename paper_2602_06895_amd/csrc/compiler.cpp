@@ -668,6 +668,7 @@ bool compile_process(Ctx& cx, const JValue& pj, Compiled& out) {
                 mask |= 1u << u;
             }
             pt.chan_mask[c] = mask;
+            if (t.chili) pt.chan_prior |= 1u << c;
         }
         ChannelMeta meta;
         meta.process = pidx;
@@ -678,6 +679,13 @@ bool compile_process(Ctx& cx, const JValue& pj, Compiled& out) {
         out.chans.push_back(t);
         out.meta.push_back(meta);
     }
+    // a channel without a diagram takes the constant local weight 1 / n;
+    // the diagram channels share the rest (subtracted one share at a time,
+    // as the weight evaluation order defines it)
+    pt.prior_share = 1.0 / pt.n_chan;
+    pt.tree_share = 1.0;
+    for (int c = 0; c < pt.n_chan; ++c)
+        if ((pt.chan_prior >> c) & 1) pt.tree_share -= 1.0 / pt.n_chan;
     for (int u = 0; u < pt.n_uniq; ++u) {
         UniqSpec& q = pt.uq[u];
         q.set = pt.uniq_set[u];

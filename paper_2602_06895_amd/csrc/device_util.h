@@ -24,6 +24,23 @@ __device__ __forceinline__ double vegas_map(double y, const double* __restrict__
     return e0 + wd * (t - i);
 }
 
+// vegas_map for caller-supplied y, which may lie outside [0, 1] or be NaN
+// (the inverse map marks events outside a channel's image with NaN): the bin
+// index is formed without converting a NaN or an out-of-range value to int;
+// a NaN y stays NaN, so the chain cuts the event.
+__device__ __forceinline__ double vegas_map_checked(double y, const double* __restrict__ g, int nb, double& jv) {
+    const double t = y * nb;
+    const int i = t >= 1.0 ? (t < nb - 1 ? (int)t : nb - 1) : 0;
+    const double e0 = g[i], e1 = g[i + 1];
+    const double wd = e1 - e0;
+    jv *= nb * wd;
+    return e0 + wd * (t - i);
+}
+
+// Recovered uniforms farther than this outside [0, 1] mark an event that is
+// not in a channel's image (its density there is 0).
+constexpr double kSupportMargin = 1e-6;
+
 // VEGAS bin of a uniform y in (0, 1): floor(y nb), clamped (vegas_map's bin).
 __device__ __forceinline__ int vegas_bin(double y, int nb) {
     int i = (int)(y * nb);

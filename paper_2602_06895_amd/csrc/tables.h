@@ -161,6 +161,11 @@ struct ProcessTab {
     double f_mw[kMaxFactors];
     double f_mu2[kMaxFactors];
     UniqSpec uq[kMaxUniq];                // the fields above, per invariant
+    // channels without a diagram (Chili): constant local weight prior_share;
+    // the diagram channels share tree_share by their propagator products
+    uint32_t chan_prior;
+    int32_t pad_prior;
+    double prior_share, tree_share;
 };
 
 // Per-call description of a multichannel launch (passed by value).

@@ -1,40 +1,44 @@
 """Per-event parity of the HIP path against the FP64 oracle.
 
-The benchmark spec's tolerance is 1e-12 relative per event.  Where the paper's
-formulas are worse conditioned than that at an event (small invariants under
-large boosts, cos(theta) within 1e-8 of 1, (1 - x) and log(tau) as tau -> 1,
-invariants recomputed from TeV-scale momenta), no FP64 evaluation can meet it;
-there the bound scales with the oracle's own forward error fe at that event,
-estimated from re-evaluations of the same formulas with other roundings
-(x87 build, every libm result moved one ulp up / down, momenta moved one ulp,
-inputs moved one ulp: oracle.Process.forward_error).  The criterion:
-    every event           |gpu - oracle| <= max(1e-12, K_HARD * fe)
-    all but max(2, 1e-5 n) events          <= max(1e-12, K * fe)
-and the fraction meeting the bare 1e-12 is reported.  (Measured on the
-pp -> 4j channels the ratio |gpu - oracle| / fe has p99 ~ 3.5, max ~ 65.)
+The benchmark spec's tolerance is 1e-12 relative per event.  Momenta and Jacobians
+meet it for >= 99.6% of events; the weights cannot everywhere: the toy
+integrand and the local channel weights recompute propagator invariants
+q^2 = E^2 - |p|^2 from TeV-scale momenta (and then q^2 - m^2 near a
+resonance, |t| + mu^2 with |t| << E^2), which amplifies a rounding of the
+momenta by the condition number kappa = sum over lines of (E_q^2 + |p_q|^2)
+|d log(factor) / d q^2| (weight_condition below): kappa ~ 1e5 on the median
+pp -> t tbar -> 6 event, so no FP64 evaluation of the same formulas agrees
+with another to 1e-12 there.  The bound therefore scales with the oracle's
+own per-event forward error fe, estimated from re-evaluations of the same
+source with other roundings (x87 build, every libm result moved one ulp up /
+down, momenta moved one ulp, inputs moved one ulp:
+oracle.Process.forward_error):
+    every event           |gpu - oracle| <= max(1e-12, K * fe),  K = 100
+(measured on 4.5e6 pp -> 4 jets and pp -> t tbar -> 6 events: the ratio
+|gpu - oracle| / fe has median 0.4-1.2, p99 1.9-7.3 and maximum 63), and the
+fraction of events meeting the bare 1e-12 is asserted per configuration
+against floors (STRICT_FLOOR in test_gpu_parity.py) measured on 5e5 events
+per channel.
 """
 import numpy as np
 
 STRICT = 1e-12
 K = 100.0
-K_HARD = 1000.0
 
 
-def _check(label, what, rel, fe, mask, soft_frac=1e-5):
+def _check(label, what, rel, fe, mask):
     tol = np.maximum(STRICT, K * fe)
-    hard = np.maximum(STRICT, K_HARD * fe)
-    bad_hard = mask & (rel > hard)
-    assert not bad_hard.any(), (f"{label}: {what} parity fails at {bad_hard.sum()} events; worst rel "
-                                f"{rel[bad_hard].max():.3e} vs {K_HARD:g} x forward error "
-                                f"(events {np.flatnonzero(bad_hard)[:5]})")
-    soft = mask & (rel > tol)
-    allowed = max(2, int(soft_frac * mask.sum()))
-    assert soft.sum() <= allowed, (f"{label}: {what}: {soft.sum()} events beyond {K:g} x forward error "
-                                   f"(allowed {allowed}); worst rel {rel[soft].max():.3e}")
-    return int(soft.sum())
+    bad = mask & (rel > tol)
+    assert not bad.any(), (f"{label}: {what} parity fails at {bad.sum()} events; worst rel "
+                           f"{rel[bad].max():.3e} vs {K:g} x forward error (events {np.flatnonzero(bad)[:5]})")
+    ratio = rel[mask] / np.maximum(fe[mask], 1e-300)
+    return float(ratio.max()) if ratio.size else 0.0
 
 
-def compare(gpu: dict, ref: dict, fe: dict, hadronic: bool, label: str = "", soft_frac: float = 1e-5) -> dict:
+def compare(gpu: dict, ref: dict, fe: dict, hadronic: bool, label: str = "", detail: bool = False) -> dict:
+    """Asserts the per-event bound; returns the strict fractions, the largest
+    ratio to the forward error and (detail) the indices of the weights beyond
+    1e-12 with every event's relative weight difference."""
     w_g, w_o = np.asarray(gpu["w"]), ref["w"]
     n = w_o.size
     zero_g, zero_o = w_g == 0.0, w_o == 0.0
@@ -45,9 +49,12 @@ def compare(gpu: dict, ref: dict, fe: dict, hadronic: bool, label: str = "", sof
     keep = ~zero_o & ~zero_g
     rel_w = np.zeros(n)
     rel_w[keep] = np.abs(w_g[keep] - w_o[keep]) / np.abs(w_o[keep])
-    soft_w = _check(label, "weight", rel_w, fe["w"], keep, soft_frac)
+    ratio_w = _check(label, "weight", rel_w, fe["w"], keep)
     out = {"n": n, "cut_flips": int(mismatch.sum()), "w_strict_frac": float((rel_w[keep] <= STRICT).mean()) if keep.any() else 1.0,
-           "w_max_rel": float(rel_w.max()) if n else 0.0, "w_beyond_K": soft_w}
+           "w_max_rel": float(rel_w.max()) if n else 0.0, "w_max_over_fe": ratio_w}
+    if detail:
+        out["w_beyond_strict"] = np.flatnonzero(keep & (rel_w > STRICT))
+        out["w_rel"] = rel_w
     if "jac" in gpu and gpu["jac"] is not None:
         j_g, j_o = np.asarray(gpu["jac"]), ref["jac"]
         kj = (j_o != 0) & (j_g != 0)
@@ -71,3 +78,55 @@ def compare(gpu: dict, ref: dict, fe: dict, hadronic: bool, label: str = "", sof
         relx = np.abs(x_g - x_o)[:, ok] / np.abs(x_o[:, ok])
         assert relx.size == 0 or relx.max() <= 1e-12, f"{label}: x1/x2 parity {relx.max():.3e}"
     return out
+
+
+U64 = 2.0 ** -53  # FP64 unit roundoff
+
+
+def weight_condition(desc: dict, p: np.ndarray, channel_props=None) -> np.ndarray:
+    """Condition estimate of the event weight: how much a relative rounding u
+    of the momenta moves the weight, in units of u.  Each propagator
+    invariant q^2 = E_q^2 - |p_q|^2 recomputed from momenta (q = p_a - sum p
+    for t-channel lines) moves by about u (E_q^2 + |p_q|^2); the integrand's
+    factor 1 / ((q^2 - m^2)^2 + (m Gamma)^2) then moves by the relative
+    amount 2 |q^2 - m^2| / ((q^2 - m^2)^2 + (m Gamma)^2) per unit of q^2, and
+    1 / (|q^2| + mu^2) by 1 / (|q^2| + mu^2).  The local channel weight
+    P_mine / sum P adds at most twice the largest channel's sum (P_c is a
+    product of squared denominators).  p: lab-frame momenta [4][np][n]
+    (index 0 is p_a); channel_props: per channel, the (t, set, m, w) lines of
+    oracle.ChannelTree.propagators(), with desc["alpha_mu"] for massless
+    lines; None for a single channel."""
+    pa = p[:, 0]
+
+    def q_of(t, parts):
+        q = np.zeros((4, p.shape[2]))
+        for k in parts:
+            q += p[:, k + 2]
+        if t:
+            q = pa - q
+        return q
+
+    def sens(q, m, w, mu):
+        q2 = q[0] ** 2 - q[1] ** 2 - q[2] ** 2 - q[3] ** 2
+        scale = (q ** 2).sum(axis=0)
+        if m > 0.0:
+            d = q2 - m * m
+            return scale * 2.0 * np.abs(d) / (d * d + (m * w) ** 2)
+        return scale / (np.abs(q2) + mu * mu)
+
+    kappa = np.zeros(p.shape[2])
+    for pr in desc.get("integrand", {}).get("props", []):
+        m = float(pr.get("m", 0.0)) if pr.get("bw") else 0.0
+        kappa += sens(q_of(pr.get("t"), [k - 1 for k in pr["particles"]]), m, float(pr.get("w", 0.0)),
+                      float(pr.get("mu", 0.0)))
+    if channel_props:
+        mu = float(desc.get("alpha_mu", 0.0))
+        worst = np.zeros(p.shape[2])
+        for lines in channel_props:
+            kc = np.zeros(p.shape[2])
+            for t, s, m, w in lines:
+                parts = [k for k in range(32) if (s >> k) & 1]
+                kc += 2.0 * sens(q_of(t, parts), m, w, mu)
+            worst = np.maximum(worst, kc)
+        kappa += 2.0 * worst
+    return kappa

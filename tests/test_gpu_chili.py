@@ -71,8 +71,10 @@ def test_chili_map_matches_oracle(torch, name, mk, vegas):
 
 def test_chili_with_tree_channels_in_sample(torch):
     """The eight pp -> 4 jets tree channels plus a Chili channel under local
-    channel weights (the Chili channel has no propagators: its weight
-    factor is 1), through the fused multichannel sample."""
+    channel weights (the Chili channel has no propagators: it takes the
+    constant weight 1/9, the tree channels share 8/9 by their propagator
+    products), through the fused multichannel sample; every channel's events
+    carry a visible share of the weight."""
     from paper_2602_06895_amd import Context
 
     desc = W.c2_pp4j()
@@ -95,6 +97,11 @@ def test_chili_with_tree_channels_in_sample(torch):
             seg = {"w": got["w"][sl], "p": got["p"][:, :, sl], "x1x2": got["x1x2"][:, sl]}
             compare(seg, ref, fe, hadronic=True, label=f"tree + Chili sample ch{c}")
             assert np.all(got["chan"][sl] == c)
+            if k > 200:
+                kept = ref["jac"] > 0
+                assert ref["alpha"][kept].mean() > 1e-3, f"channel {c}: negligible channel weight"
+                if c == 8:
+                    assert np.all(ref["alpha"][kept] == 1.0 / 9.0)
         off += k
     ctx.close()
 
@@ -249,4 +256,45 @@ def test_chili_full_size_spot_check(torch):
                "p": out["p"][:, :, start:start + 3000].cpu().numpy(),
                "x1x2": out["x1x2"][:, start:start + 3000].cpu().numpy()}
         compare(seg, ref, fe, hadronic=True, label=f"Chili full-size @{start}")
+    ctx.close()
+
+
+def test_inverse_marks_events_outside_the_chili_image(torch):
+    """Tree-channel events with a jet below the Chili channel's p_T cut are
+    outside its image: the GPU inverse gives y = NaN and J = 0 for exactly the
+    events the oracle marks, and the global density over the tree channels
+    plus Chili matches the oracle's."""
+    from paper_2602_06895_amd import Context
+
+    d = W.c2_pp4j()
+    d["channels"] = d["channels"] + [{"chili": True}]
+    ctx = Context(d)
+    orc = oracle.Process(d)
+    d0 = W.c2_pp4j()
+    d0["integrand"] = dict(d0["integrand"], pt_min=0.0)
+    o0 = oracle.Process(d0)
+    y = W.philox_uniforms(8, 2, 0, 20_000, o0.dims[0])
+    ev = o0.map(0, y)
+    keep = ev["jac"] > 0
+    p, x = ev["p"][:, :, keep], ev["x1x2"][:, keep]
+    ref = orc.inverse(8, p, x)
+    pt_ = torch.from_numpy(np.ascontiguousarray(p)).cuda()
+    xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    got = ctx.inverse_map(8, pt_, xt)
+    torch.cuda.synchronize()
+    yg, jg = got["y"].cpu().numpy(), got["jac"].cpu().numpy()
+    marked_o = np.isnan(ref["y"]).all(axis=0)
+    marked_g = np.isnan(yg).all(axis=0)
+    assert marked_o.sum() > 100
+    assert np.array_equal(marked_o, marked_g)
+    assert np.all(jg[marked_g] == 0.0) and np.all(jg[~marked_g] > 0.0)
+    # the global density adds the channels in order, Chili last: where its
+    # density is 0 the nine-channel sum equals the eight tree channels' sum
+    alpha = np.full(9, 1.0 / 9.0)
+    g9 = ctx.multichannel_density(0, pt_, xt, alpha).cpu().numpy()
+    c8 = Context(W.c2_pp4j())
+    g8 = c8.multichannel_density(0, pt_, xt, alpha[:8]).cpu().numpy()
+    assert np.array_equal(g9[marked_g], g8[marked_g])
+    assert np.all(g9[~marked_g] >= g8[~marked_g]) and (g9[~marked_g] > g8[~marked_g]).mean() > 0.5
+    c8.close()
     ctx.close()

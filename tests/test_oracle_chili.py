@@ -159,3 +159,48 @@ def test_inverse_round_trip(case):
     assert np.median(err) < 1e-14 and np.quantile(err, 0.99) < 1e-12 and err.max() < 1e-8
     jr = np.abs(inv["jac"][ok] / f["jac"][ok] - 1.0)
     assert np.median(jr) < 1e-14 and jr.max() < 1e-8
+
+
+def test_chili_beside_tree_channels_keeps_every_channel_weighted():
+    """A Chili channel beside the eight pp -> 4 jets diagram channels under
+    local channel weights: the Chili channel has no propagator denominators,
+    so it takes the constant share 1/9 and the diagram channels share 8/9 by
+    their propagator products (a reading: the paper's local weights are
+    defined for diagram channels only).  Pins: the nine weights of one event
+    sum to 1 and the Chili one equals 1/9 exactly; no channel's mean weight is
+    negligible; the nine-channel multichannel integral equals the eight
+    tree channels' integral without the Chili channel."""
+    d = W.c2_pp4j()
+    d["channels"] = d["channels"] + [{"chili": True}]
+    o = oracle.Process(d)
+    C_ = len(o.dims)
+    assert C_ == 9
+    # alpha of every channel at the same events (channel 8's events)
+    y = W.philox_uniforms(4, 1, 0, 20_000, o.dims[8])
+    ev = o.map(8, y)
+    keep = ev["jac"] > 0
+    alphas = []
+    for c in range(C_):
+        alphas.append(o.weight(c, ev["p"][:, :, keep], ev["x1x2"][:, keep], ev["jac"][keep])["alpha"])
+    alphas = np.array(alphas)
+    ok = np.isfinite(alphas).all(axis=0)
+    assert np.all(alphas[8][ok] == 1.0 / 9.0)
+    assert np.abs(alphas[:, ok].sum(axis=0) - 1.0).max() < 1e-13
+    # every channel's own events: its mean alpha is a visible share
+    tot, var = 0.0, 0.0
+    for c in range(C_):
+        yc = W.philox_uniforms(5, 10 + c, 0, 200_000, o.dims[c])
+        r = o.map(c, yc)
+        k = r["jac"] > 0
+        assert r["alpha"][k].mean() > 1e-3, f"channel {c}: mean alpha {r['alpha'][k].mean():.3g}"
+        tot += r["w"].mean()
+        var += r["w"].var() / r["w"].size
+    o2 = oracle.Process(W.c2_pp4j())
+    t2, v2 = 0.0, 0.0
+    for c in range(8):
+        yc = W.philox_uniforms(6, 3 + c, 0, 200_000, o2.dims[c])
+        w = o2.map(c, yc)["w"]
+        t2 += w.mean()
+        v2 += w.var() / w.size
+    pull = (tot - t2) / math.sqrt(var + v2)
+    assert abs(pull) < 4.0, (tot, t2, math.sqrt(var), math.sqrt(v2))

@@ -241,3 +241,39 @@ def test_cut_and_histogram_closed_forms():
     h = oracle.histogram(xs, ws, 10, 0.0, 1.0)
     assert h[0].tolist() == [1.0, 5.0, 0, 0, 0, 0, 0, 0, 0, 4.0]
     assert h[1].tolist() == [1.0, 13.0, 0, 0, 0, 0, 0, 0, 0, 16.0]
+
+
+def test_events_outside_a_channels_image_get_zero_density():
+    """pp -> 4 jets tree-channel events with a jet below 20 GeV are outside
+    the image of a Chili channel with that p_T cut: its inverse marks them
+    (y = NaN, J = 0) and the global density takes nothing from it there,
+    while events inside (the Chili channel's own) are never marked."""
+    d = W.c2_pp4j()
+    d["channels"] = d["channels"] + [{"chili": True}]
+    o = oracle.Process(d)
+    # a process without the cut generates jets of any p_T
+    d_nocut = W.c2_pp4j()
+    d_nocut["integrand"] = dict(d_nocut["integrand"], pt_min=0.0)
+    o0 = oracle.Process(d_nocut)
+    y = W.philox_uniforms(8, 2, 0, 20_000, o0.dims[0])
+    ev = o0.map(0, y)
+    keep = ev["jac"] > 0
+    p, x = ev["p"][:, :, keep], ev["x1x2"][:, keep]
+    pt = np.hypot(p[1, 2:], p[2, 2:])
+    below = (pt[:3] < 20.0).any(axis=0)  # the first three Chili particles carry the cut map
+    assert below.sum() > 100 and (~below).sum() > 100
+    inv = o.inverse(8, p, x)
+    assert np.all(np.isnan(inv["y"][:, below])) and np.all(inv["jac"][below] == 0.0)
+    assert np.all(np.isfinite(inv["y"][:, ~below])) and np.all(inv["jac"][~below] > 0.0)
+    # the global density over the nine channels: no Chili term where it is 0
+    alpha = np.full(9, 1.0 / 9.0)
+    g9 = o.multichannel_density(p, x, alpha)
+    g8 = oracle.Process(W.c2_pp4j()).multichannel_density(p, x, alpha[:8])
+    assert np.allclose(g9[below], g8[below], rtol=1e-14, atol=0.0)
+    assert np.all(g9[~below] >= g8[~below]) and (g9[~below] > g8[~below]).mean() > 0.5
+    # the Chili channel's own events are in its image
+    yc = W.philox_uniforms(9, 2, 0, 20_000, o.dims[8])
+    evc = o.map(8, yc)
+    kc = evc["jac"] > 0
+    invc = o.inverse(8, evc["p"][:, :, kc], evc["x1x2"][:, kc])
+    assert np.all(np.isfinite(invc["y"])) and np.all(invc["jac"] > 0.0)

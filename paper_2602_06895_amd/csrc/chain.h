@@ -627,7 +627,8 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
         double r_th = next();
         double m1s = m1 * m1, m2s = m2 * m2;
         double lam = kallen(m0sq, m1s, m2s);
-        double inv_2m0 = 1.0 / (2.0 * m0);
+        const double inv_m = 1.0 / m0;
+        const double inv_2m0 = 0.5 * inv_m;
         double e1 = (m0sq + (m1s - m2s)) * inv_2m0;
         double e2 = (m0sq - (m1s - m2s)) * inv_2m0;
         double sl = sqrt(lam);
@@ -641,7 +642,7 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
         if (!ds.parent_rest) {
             const int ps = slot_index<NS>(ds.parent_slot);
             double Pe = E[ps], Px = X[ps], Py = Y[ps], Pz = Z[ps];
-            const double inv_m = 1.0 / m0, inv_em = 1.0 / (Pe + m0);
+            const double inv_em = 1.0 / (Pe + m0);
             boost_by(Pe, Px, Py, Pz, inv_m, inv_em, k1e, k1x, k1y, k1z);
             boost_by(Pe, Px, Py, Pz, inv_m, inv_em, k2e, k2x, k2y, k2z);
         }
@@ -653,7 +654,9 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
         X[NS - 1 - 2 * di] = k2x;
         Y[NS - 1 - 2 * di] = k2y;
         Z[NS - 1 - 2 * di] = k2z;
-        jac *= sl / (8.0 * m0sq) * (4.0 * kPiD);
+        // two-body factor pi |p| / (2 m0) = pi sqrt(lambda) / (4 m0^2) ... as
+        // sqrt(lambda) / (8 m0^2) times the 4 pi of the angles
+        jac *= sl * (inv_m * inv_m) * (0.5 * kPiD);
     }
 
     o.shat = shat;

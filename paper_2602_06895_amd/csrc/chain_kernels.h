@@ -560,11 +560,13 @@ __global__ __launch_bounds__(kBlock) void k_inverse(const ChannelTab* __restrict
 
 // Launch of one register class: kind class `kc` picks the compiled map kinds
 // (0: integer-root power laws, 1: plus Breit-Wigner, 2: all tree kinds;
-// with Chili channels or 1 -> 3 decays, 3: those of class 1, 4: all).
+// 3: those of class 1 with Chili channels, 4: those of class 1 with 1 -> 3
+// decays, 5: everything).  Chili and 1 -> 3 decays have classes of their
+// own because compiled together they overflow the register file.
 template <int NS, int NI, bool MIX>
 hipError_t launch_chain_class(int kc, const ChainLaunch& a) {
     constexpr int K0 = KIND_POW_INT, K1 = KIND_POW_INT | KIND_BW, K2 = KINDS_ALL;
-    constexpr int K3 = K1 | KIND_CHILI | KIND_DEC3, K4 = KINDS_ALL | KIND_CHILI | KIND_DEC3;
+    constexpr int K3 = K1 | KIND_CHILI, K4 = K1 | KIND_DEC3, K5 = KINDS_ALL | KIND_CHILI | KIND_DEC3;
     auto go = [&](auto kt) {
         constexpr int K = decltype(kt)::value;
         const size_t lds = a.lds + (a.sample ? sizeof(double) * stage_rows<NS, NI>() * kBlock : kQBytes) +
@@ -600,7 +602,8 @@ hipError_t launch_chain_class(int kc, const ChainLaunch& a) {
     else if (kc <= 1) go(std::integral_constant<int, K1>{});
     else if (kc == 2) go(std::integral_constant<int, K2>{});
     else if (kc == 3) go(std::integral_constant<int, K3>{});
-    else go(std::integral_constant<int, K4>{});
+    else if (kc == 4) go(std::integral_constant<int, K4>{});
+    else go(std::integral_constant<int, K5>{});
     return hipGetLastError();
 }
 

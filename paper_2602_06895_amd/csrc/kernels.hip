@@ -548,11 +548,14 @@ int reg_class(int slots, int inv) {
 }
 
 // Map-kind class of a launch: 0 integer-root power laws only, 1 plus
-// Breit-Wigner, 2 every tree kind; with Chili channels or 1 -> 3 decays, 3
-// when the tree kinds fit class 1, else 4.
+// Breit-Wigner, 2 every tree kind; when the tree kinds fit class 1, 3 with
+// Chili channels, 4 with 1 -> 3 decays; 5 for anything else.
 int kind_class(int kinds) {
-    if (kinds & (KIND_CHILI | KIND_DEC3))
-        return (kinds & ~(KIND_POW_INT | KIND_BW | KIND_CHILI | KIND_DEC3)) == 0 ? 3 : 4;
+    if (kinds & (KIND_CHILI | KIND_DEC3)) {
+        if (kinds & ~(KIND_POW_INT | KIND_BW | KIND_CHILI | KIND_DEC3)) return 5;
+        if ((kinds & KIND_CHILI) && (kinds & KIND_DEC3)) return 5;
+        return (kinds & KIND_CHILI) ? 3 : 4;
+    }
     if ((kinds & ~KIND_POW_INT) == 0) return 0;
     if ((kinds & ~(KIND_POW_INT | KIND_BW)) == 0) return 1;
     return 2;

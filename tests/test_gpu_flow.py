@@ -195,3 +195,60 @@ def test_bad_arguments(torch):
         f.sample(ctx, 0, 10, seed=1)
     ctx.close()
     f.close()
+
+
+@pytest.mark.parametrize("mlp", [1, 0])
+def test_gradient_per_parameter_block(torch, mlp):
+    """The gradient block by block (W1 b1 W2 b2 W3 b3 W4 b4 of each of the 8
+    layers), so that a wrong block cannot hide in the norm of the whole.
+    FP32 mode: every block within 1e-3 relative of the FP64 oracle on the
+    same float32 parameters.  BF16 mode: the tolerance of a block is derived
+    from BF16 rounding itself -- the oracle's gradient with BF16 rounding of
+    MLP inputs, weights and hidden activations differs from its FP64 gradient
+    by d_bf16 (per block); the GPU must agree with the BF16 oracle within
+    2 d_bf16 + 1e-3 (rounding decisions taken on FP32 accumulators here and
+    FP64 ones in the oracle differ, each worth at most one such rounding),
+    and every block's direction within cos >= 0.99."""
+    params = W.flow_params(23, D, L, K, H, last_scale=0.05)
+    f = _flow(mlp, params)
+    n = 2048
+    u = _u(n, seed=5)
+    y, ld = f.forward(torch.from_numpy(u).cuda())
+    rng = np.random.default_rng(6)
+    wfj = torch.from_numpy(rng.uniform(0.5, 2.0, n)).cuda()
+    lqo = -ld
+    g, _ = f.gradient(y, wfj, lqo)
+    torch.cuda.synchronize()
+    yy = _t.from_numpy(y.cpu().numpy().T.astype(np.float64))
+    fj2 = _t.from_numpy(wfj.cpu().numpy()) ** 2
+    lq = _t.from_numpy(lqo.cpu().numpy().astype(np.float64))
+    _, g64 = _oracle(params, bf16=False).loss_and_grad(yy, fj2, lq)
+    g64 = g64.numpy()
+    if mlp == 0:
+        _, gbf = _oracle(params, bf16=True).loss_and_grad(yy, fj2, lq)
+        gref = gbf.numpy()
+    else:
+        gref = g64
+    gg = g.cpu().numpy().astype(np.float64)
+    shapes = [(H, D // 2), (H,), (H, H), (H,), (H, H), (H,), (D // 2 * (3 * K + 1), H), (D // 2 * (3 * K + 1),)]
+    sizes = [int(np.prod(s)) for s in shapes]
+    off, worst = 0, 0.0
+    total = np.linalg.norm(gref)
+    for layer in range(L):
+        for b, sz in enumerate(sizes):
+            a, r, r64 = gg[off:off + sz], gref[off:off + sz], g64[off:off + sz]
+            off += sz
+            nr = np.linalg.norm(r)
+            if nr < 1e-9 * total:
+                assert np.linalg.norm(a) < 1e-6 * total, (layer, b)
+                continue
+            rel = np.linalg.norm(a - r) / nr
+            cos = float(a @ r / (np.linalg.norm(a) * nr))
+            if mlp == 1:
+                tol = 1e-3
+            else:
+                tol = 2.0 * np.linalg.norm(r - r64) / nr + 1e-3
+            worst = max(worst, rel / tol)
+            assert rel <= tol and cos >= 0.99, f"layer {layer} block {b}: rel {rel:.3g} (tol {tol:.3g}) cos {cos:.5f}"
+    assert off == gg.size
+    print(f"mlp={mlp}: worst block error / tolerance {worst:.3f}")

@@ -109,6 +109,10 @@ def _load(path: str):
                                      C.c_double, dp, dp]
     L.orc_two_to_two.restype = C.c_double
     L.orc_two_to_two.argtypes = [dp, dp] + [C.c_double] * 9 + [dp, dp, dp]
+    L.orc_two_to_two_st.restype = C.c_double
+    L.orc_two_to_two_st.argtypes = [dp, dp, dp] + [C.c_double] * 9 + [dp, dp, dp, dp]
+    L.orc_two_to_two_st_inverse.restype = None
+    L.orc_two_to_two_st_inverse.argtypes = [dp, dp, dp] + [C.c_double] * 5 + [dp, C.c_double, C.c_double, dp, dp]
     L.orc_t_range.restype = None
     L.orc_t_range.argtypes = [C.c_double] * 5 + [dp, dp]
     L.orc_r_to_x1x2.restype = C.c_double
@@ -227,7 +231,7 @@ class _Channel(C.Structure):
                 ("child_start", C.c_void_p), ("child_count", C.c_void_p), ("children", C.c_void_p),
                 ("mass", C.c_void_p), ("width", C.c_void_p), ("nu", C.c_void_p),
                 ("t_order", C.c_char_p), ("s_order", C.c_void_p), ("dec_order", C.c_void_p),
-                ("rambo", C.c_void_p), ("chili", C.c_int32)]
+                ("rambo", C.c_void_p), ("chili", C.c_int32), ("st", C.c_int32)]
 
 
 class _Process(C.Structure):
@@ -258,6 +262,8 @@ class ChannelTree:
         self.mass, self.width, self.nu, self.order = [], [], [], []
         self.rambo = []  # FastRambo clusters: their particle count - 1, else 0
         self.chili = bool(chan.get("chili"))
+        # t-chain blocks after the first in the (s~, t) parametrisation
+        self.st = bool(chan.get("st"))
         if self.chili:
             # Chili (section 2.4): no tree, 3 random numbers per particle but
             # the last, which takes only its rapidity
@@ -386,7 +392,8 @@ class ChannelTree:
                         _ptr(k["kind"]), _ptr(k["particle"]), _ptr(k["parent"]),
                         _ptr(k["child_start"]), _ptr(k["child_count"]), _ptr(k["children"]),
                         _ptr(k["mass"]), _ptr(k["width"]), _ptr(k["nu"]), k["t_order"],
-                        _ptr(k["s_order"]), _ptr(k["dec_order"]), _ptr(k["rambo"]), int(self.chili))
+                        _ptr(k["s_order"]), _ptr(k["dec_order"]), _ptr(k["rambo"]), int(self.chili),
+                        int(self.st))
 
 
 def _mask(parts):

@@ -83,6 +83,7 @@ typedef struct {
     const int32_t* dec_order;   /* clusters decayed with (phi,theta), parents first */
     const int32_t* rambo;       /* FastRambo cluster: its particle count - 1 (k), else 0 */
     int32_t chili;              /* 1: a Chili channel (no tree) */
+    int32_t st;                 /* 1: t-chain blocks with a recoil use (s~, t) */
 } orc_channel;
 
 typedef struct {
@@ -409,6 +410,149 @@ double orc_two_to_two(const double pA[4], const double pB[4], double m0sq, doubl
     return jt * (2.0 * ORC_PI) / (4.0 * sqrt(lamab));
 }
 
+double orc_unmap_nu(double x, double m2, double nu, double xmin, double xmax);
+
+/* Inverse of rotate (R(phi, theta)^-1 = R_y(-theta) R_z(-phi)). */
+static void unrotate(double cphi, double sphi, double cth, double sth, const double v[3], double out[3])
+{
+    double x = v[0] * cphi + v[1] * sphi;
+    double y = -v[0] * sphi + v[1] * cphi;
+    out[0] = x * cth - v[2] * sth;
+    out[1] = y;
+    out[2] = x * sth + v[2] * cth;
+}
+
+/* The (s~, t) double-invariant block (section 2.2.5, eqs. byckling,
+ * t_invariant_theta_23, s_to_phi): as the (phi, t) block, P = p_A + p_B of
+ * mass^2 m0sq goes to p1 (mass m1, the leg next to A) and p2 (mass m2) with
+ * |t| = -(p_A - p1)^2 from G_nu, but the azimuth of p1 about p_A in the rest
+ * frame of P is fixed by the time-like invariant s~ = (p1 + rec)^2 of p1
+ * and the recoil momentum rec (the leg the previous block peeled on this
+ * side), measured from the plane of p_A and rec.  In that frame s~ = A - B
+ * cos(phi) with A = m1^2 + rec^2 + 2 (E1 E_rec - |p1| cos(theta) rec_z),
+ * B = 2 |p1| sin(theta) |rec_perp|, so s~ is linear in r between A - B and
+ * A + B.  s~ fixes cos(phi) only (reading): the half of [0, 1) that r_s
+ * falls in gives the sign of sin(phi), and r_s rescaled to the half gives s~.
+ * Measure: d|t| dphi / (4 sqrt(lambda_ab)) as in the (phi, t) block, with
+ * dphi = ds~ / (B |sin phi|) per branch -- on each branch the paper's density
+ * 1 / (8 sqrt(-Delta_4)) in ds~ d|t| (here sqrt(-Delta_4) = sqrt(lambda_ab) B
+ * |sin phi| / 2), so the two branches together carry twice it.  Jacobian
+ * dr_s d r_t -> phase space: J_|t| / (sqrt(lambda_ab) |sin phi|).  *stil_out
+ * (optional) receives s~. */
+double orc_two_to_two_st(const double pA[4], const double pB[4], const double rec[4], double m0sq, double ma2,
+                         double mb2, double m1, double m2, double r_s, double r_t, double nu, double reg_a,
+                         double p1[4], double p2[4], double* abst_out, double* stil_out)
+{
+    double P[4] = {pA[0] + pB[0], pA[1] + pB[1], pA[2] + pB[2], pA[3] + pB[3]};
+    double m0 = sqrt(m0sq);
+    double m1s = m1 * m1, m2s = m2 * m2;
+    double lam12 = orc_kallen(m0sq, m1s, m2s), lamab = orc_kallen(m0sq, ma2, mb2);
+    double C = (m0sq + (m1s - m2s)) * (m0sq + (ma2 - mb2));
+    double R = sqrt(lam12 * lamab);
+    double tmin_abs, tmax_abs;
+    orc_t_range(m0sq, ma2, mb2, m1, m2, &tmin_abs, &tmax_abs);
+    double jt;
+    double abst = orc_map_nu(r_t, -reg_a, nu, tmin_abs, tmax_abs, &jt);
+    double cth = (C - 2.0 * m0sq * (m1s + ma2 + abst)) / R;
+    if (cth > 1.0) cth = 1.0;
+    if (cth < -1.0) cth = -1.0;
+    double sth = sqrt((1.0 - cth) * (1.0 + cth));
+    double q = sqrt(lam12) / (2.0 * m0);
+    double e1 = (m0sq + (m1s - m2s)) / (2.0 * m0);
+    double e2 = (m0sq - (m1s - m2s)) / (2.0 * m0);
+    /* p_A along z in the rest frame of P */
+    double Pbar[4] = {P[0], -P[1], -P[2], -P[3]};
+    double pAr[4];
+    orc_boost(Pbar, m0, pA, pAr);
+    double len = sqrt(pAr[1] * pAr[1] + pAr[2] * pAr[2] + pAr[3] * pAr[3]);
+    double nx = pAr[1] / len, ny = pAr[2] / len, nz = pAr[3] / len;
+    double st = sqrt(nx * nx + ny * ny);
+    double cp = 1.0, sp = 0.0;
+    if (st > 0.0) {
+        cp = nx / st;
+        sp = ny / st;
+    }
+    /* the recoil in the same frame */
+    double recr[4], rz[3];
+    orc_boost(Pbar, m0, rec, recr);
+    unrotate(cp, sp, nz, st, recr + 1, rz);
+    double rperp = sqrt(rz[0] * rz[0] + rz[1] * rz[1]);
+    double mrec2 = rec[0] * rec[0] - rec[1] * rec[1] - rec[2] * rec[2] - rec[3] * rec[3];
+    double A = m1s + mrec2 + 2.0 * (e1 * recr[0] - q * cth * rz[2]);
+    double B = 2.0 * q * sth * rperp;
+    double sgn = 1.0, u = 2.0 * r_s;
+    if (r_s >= 0.5) {
+        sgn = -1.0;
+        u = 2.0 * r_s - 1.0;
+    }
+    double stil = (A - B) + 2.0 * B * u;
+    double cphi = (A - stil) / B;
+    if (cphi > 1.0) cphi = 1.0;
+    if (cphi < -1.0) cphi = -1.0;
+    double sphi = sgn * sqrt((1.0 - cphi) * (1.0 + cphi));
+    /* azimuth of p1 = that of the recoil plus phi */
+    double ux = rz[0] / rperp, uy = rz[1] / rperp;
+    double c1 = ux * cphi - uy * sphi, s1 = uy * cphi + ux * sphi;
+    double v1[3] = {q * sth * c1, q * sth * s1, q * cth};
+    double w1[3];
+    rotate(cp, sp, nz, st, v1, w1);
+    double k1[4] = {e1, w1[0], w1[1], w1[2]};
+    double k2[4] = {e2, -w1[0], -w1[1], -w1[2]};
+    orc_boost(P, m0, k1, p1);
+    orc_boost(P, m0, k2, p2);
+    if (abst_out) *abst_out = abst;
+    if (stil_out) *stil_out = stil;
+    return jt / (sqrt(lamab) * fabs(sphi));
+}
+
+/* Inverse of orc_two_to_two_st: from p1 (and p_A, p_B, rec) the uniforms
+ * (r_s, r_t). */
+void orc_two_to_two_st_inverse(const double pA[4], const double pB[4], const double rec[4], double m0sq,
+                               double ma2, double mb2, double m1, double m2, const double p1[4], double nu,
+                               double reg_a, double* r_s, double* r_t)
+{
+    double P[4] = {pA[0] + pB[0], pA[1] + pB[1], pA[2] + pB[2], pA[3] + pB[3]};
+    double m0 = sqrt(m0sq);
+    double m1s = m1 * m1, m2s = m2 * m2;
+    double lam12 = orc_kallen(m0sq, m1s, m2s);
+    double d[4] = {pA[0] - p1[0], pA[1] - p1[1], pA[2] - p1[2], pA[3] - p1[3]};
+    double abst = -(d[0] * d[0] - d[1] * d[1] - d[2] * d[2] - d[3] * d[3]);
+    double tmin_abs, tmax_abs;
+    orc_t_range(m0sq, ma2, mb2, m1, m2, &tmin_abs, &tmax_abs);
+    *r_t = orc_unmap_nu(abst, -reg_a, nu, tmin_abs, tmax_abs);
+    double q = sqrt(lam12) / (2.0 * m0);
+    double e1 = (m0sq + (m1s - m2s)) / (2.0 * m0);
+    double Pbar[4] = {P[0], -P[1], -P[2], -P[3]};
+    double pAr[4], recr[4], k1[4];
+    orc_boost(Pbar, m0, pA, pAr);
+    orc_boost(Pbar, m0, rec, recr);
+    orc_boost(Pbar, m0, p1, k1);
+    double len = sqrt(pAr[1] * pAr[1] + pAr[2] * pAr[2] + pAr[3] * pAr[3]);
+    double nx = pAr[1] / len, ny = pAr[2] / len, nz = pAr[3] / len;
+    double st = sqrt(nx * nx + ny * ny);
+    double cp = 1.0, sp = 0.0;
+    if (st > 0.0) {
+        cp = nx / st;
+        sp = ny / st;
+    }
+    double rz[3], kz[3];
+    unrotate(cp, sp, nz, st, recr + 1, rz);
+    unrotate(cp, sp, nz, st, k1 + 1, kz);
+    double rperp = sqrt(rz[0] * rz[0] + rz[1] * rz[1]);
+    double kperp = sqrt(kz[0] * kz[0] + kz[1] * kz[1]);
+    double cth = kz[2] / q;
+    double mrec2 = rec[0] * rec[0] - rec[1] * rec[1] - rec[2] * rec[2] - rec[3] * rec[3];
+    double A = m1s + mrec2 + 2.0 * (e1 * recr[0] - q * cth * rz[2]);
+    double B = 2.0 * kperp * rperp;
+    /* s~ from the momenta, the branch from the orientation of p1 about the
+     * plane of p_A and the recoil */
+    double sum[4] = {p1[0] + rec[0], p1[1] + rec[1], p1[2] + rec[2], p1[3] + rec[3]};
+    double stil = sum[0] * sum[0] - sum[1] * sum[1] - sum[2] * sum[2] - sum[3] * sum[3];
+    double cross = rz[0] * kz[1] - rz[1] * kz[0];
+    double u = (stil - (A - B)) / (2.0 * B);
+    *r_s = cross >= 0.0 ? 0.5 * u : 0.5 * (u + 1.0);
+}
+
 /* PDF convolution (section 2.2.2, eqs. pdf_conv, pdf_sampling): x1 = tau^r,
  * x2 = tau^(1-r), Jacobian -log(tau)/s_lab (the r_to_x1x2 operation). */
 double orc_r_to_x1x2(double r, double shat, double s_lab, double* x1, double* x2)
@@ -706,8 +850,13 @@ static void event(const orc_process* pr, const orc_channel* ch, int32_t chan,
             }
             double r_phi = r[k++], r_t = r[k++];
             double p1[4], p2[4];
-            double jb = orc_two_to_two(pA, pB, st[i - 1], ma2, mb2, m1, m2, r_phi, r_t, pr->nu,
-                                       pr->reg_a, p1, p2, &ev->tabs[i - 1]);
+            /* with st, a block after the first replaces phi by s~ = (p1 +
+             * the leg the previous block peeled)^2 */
+            double jb = (ch->st && i >= 2)
+                            ? orc_two_to_two_st(pA, pB, mom[sigma[i - 1]], st[i - 1], ma2, mb2, m1, m2, r_phi, r_t,
+                                                pr->nu, pr->reg_a, p1, p2, &ev->tabs[i - 1], NULL)
+                            : orc_two_to_two(pA, pB, st[i - 1], ma2, mb2, m1, m2, r_phi, r_t, pr->nu,
+                                             pr->reg_a, p1, p2, &ev->tabs[i - 1]);
             factors[nf++] = jb;
             if (i == kappa) {
                 memcpy(mom[sigma[kappa]], p1, sizeof p1);
@@ -1193,6 +1342,23 @@ static int32_t inverse_event(const orc_process* pr, const orc_channel* ch, doubl
             }
             double d[4] = {pA[0] - p1[0], pA[1] - p1[1], pA[2] - p1[2], pA[3] - p1[3]};
             double abst = -mdot(d, d);
+            if (ch->st && i >= 2) {
+                double rs_, rt_;
+                orc_two_to_two_st_inverse(pA, pB, mom[sigma[i - 1]], st[i - 1], ma2, mb2, m1, m2, p1, pr->nu,
+                                          pr->reg_a, &rs_, &rt_);
+                r[k++] = rs_;
+                r[k++] = rt_;
+                if (i < kappa) {
+                    if (from_a[i]) {
+                        for (int c = 0; c < 4; ++c) pA[c] -= p1[c];
+                        ma2 = -abst;
+                    } else {
+                        for (int c = 0; c < 4; ++c) pB[c] -= p2[c];
+                        mb2 = -abst;
+                    }
+                }
+                continue;
+            }
             double tmin, tmax;
             orc_t_range(st[i - 1], ma2, mb2, m1, m2, &tmin, &tmax);
             double m0 = sqrt(st[i - 1]);

@@ -55,6 +55,11 @@
  *                   t-channel spine from incoming a to b, and for each of the
  *                   first kappa-1 generation steps whether the next leg is
  *                   peeled from the A or the B side (section 2.2.8);
+ *                   with "st": true every block after the first is the
+ *                   (s~, t) double-invariant block (section 2.2.5): its
+ *                   r_phi gives s~ = (p1 + the leg the previous block
+ *                   peeled)^2, uniform between its bounds, on the half of
+ *                   the azimuth its half of [0, 1) selects;
  *                   {"s": cluster}  pure s-channel;
  *                   {"chili": true}  a Chili channel (section 2.4, hadronic
  *                   beams only): per particle but the last p_T (1/p_T^2
@@ -62,8 +67,9 @@
  *                   with lambda = its mass or 1), rapidity and azimuth in
  *                   the lab frame, then the last one's rapidity: 3 n - 2
  *                   dimensions in that order; x1, x2 follow from the
- *                   momenta.  It has no propagators (weight factor 1 under
- *                   "alpha_mu"); msx_inverse_map recovers its uniforms from
+ *                   momenta.  It has no propagators: under "alpha_mu" it
+ *                   takes the constant weight 1 / (channels of the
+ *                   process); msx_inverse_map recovers its uniforms from
  *                   the lab-frame p_T, rapidities and relative azimuths.
  *                 A leg is a particle label or a cluster
  *                 {"d": [child, child], "m", "w", "nu", "order", "rambo"};

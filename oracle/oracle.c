@@ -486,10 +486,10 @@ double orc_two_to_two_st(const double pA[4], const double pB[4], const double re
         u = 2.0 * r_s - 1.0;
     }
     double stil = (A - B) + 2.0 * B * u;
-    double cphi = (A - stil) / B;
-    if (cphi > 1.0) cphi = 1.0;
-    if (cphi < -1.0) cphi = -1.0;
-    double sphi = sgn * sqrt((1.0 - cphi) * (1.0 + cphi));
+    /* eq. s_to_phi inverted: cos(phi) = (A - s~) / B, which for s~ linear in
+     * u is exactly 1 - 2 u (formed so, without A cancelling against s~) */
+    double cphi = 1.0 - 2.0 * u;
+    double sphi = sgn * 2.0 * sqrt(u * (1.0 - u));
     /* azimuth of p1 = that of the recoil plus phi */
     double ux = rz[0] / rperp, uy = rz[1] / rperp;
     double c1 = ux * cphi - uy * sphi, s1 = uy * cphi + ux * sphi;
@@ -540,17 +540,18 @@ void orc_two_to_two_st_inverse(const double pA[4], const double pB[4], const dou
     unrotate(cp, sp, nz, st, k1 + 1, kz);
     double rperp = sqrt(rz[0] * rz[0] + rz[1] * rz[1]);
     double kperp = sqrt(kz[0] * kz[0] + kz[1] * kz[1]);
-    double cth = kz[2] / q;
-    double mrec2 = rec[0] * rec[0] - rec[1] * rec[1] - rec[2] * rec[2] - rec[3] * rec[3];
-    double A = m1s + mrec2 + 2.0 * (e1 * recr[0] - q * cth * rz[2]);
-    double B = 2.0 * kperp * rperp;
-    /* s~ from the momenta, the branch from the orientation of p1 about the
-     * plane of p_A and the recoil */
-    double sum[4] = {p1[0] + rec[0], p1[1] + rec[1], p1[2] + rec[2], p1[3] + rec[3]};
-    double stil = sum[0] * sum[0] - sum[1] * sum[1] - sum[2] * sum[2] - sum[3] * sum[3];
+    /* u = (s~ - (A - B)) / (2 B) = (1 - cos(phi)) / 2 with phi the angle
+     * between the transverse parts of the recoil and p1 (formed from them,
+     * without the cancellation of s~ against A); the branch from the
+     * orientation of p1 about the plane of p_A and the recoil */
+    double cphi = (rz[0] * kz[0] + rz[1] * kz[1]) / (rperp * kperp);
+    if (cphi > 1.0) cphi = 1.0;
+    if (cphi < -1.0) cphi = -1.0;
     double cross = rz[0] * kz[1] - rz[1] * kz[0];
-    double u = (stil - (A - B)) / (2.0 * B);
+    double u = 0.5 * (1.0 - cphi);
     *r_s = cross >= 0.0 ? 0.5 * u : 0.5 * (u + 1.0);
+    (void)q;
+    (void)e1;
 }
 
 /* PDF convolution (section 2.2.2, eqs. pdf_conv, pdf_sampling): x1 = tau^r,

@@ -95,7 +95,8 @@ enum : int {
     KIND_RAMBO = 32,   // FastRambo cluster masses
     KINDS_ALL = 63,    // every tree-channel map kind
     KIND_CHILI = 64,   // Chili channels (compiled only for processes that use them)
-    KIND_DEC3 = 128    // 1 -> 3 decays (likewise)
+    KIND_DEC3 = 128,   // 1 -> 3 decays (likewise)
+    KIND_ST = 256      // (s~, t) blocks in the t-channel chain (likewise)
 };
 
 // Precision of the well-conditioned transcendentals (power laws, exp, log,
@@ -511,11 +512,58 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
         cth = fmin(1.0, fmax(-1.0, cth));
         double sth = sqrt((1.0 - cth) * (1.0 + cth));
         double sphi, cphi;
-        t_sincospi<MIX>(2.0 * r_phi, &sphi, &cphi);
         double inv_2m0 = 1.0 / (2.0 * m0);
         double q = sqrt(lam12) * inv_2m0;
         double e1 = (m0sq + (m1s - m2s)) * inv_2m0;
         double e2 = (m0sq - (m1s - m2s)) * inv_2m0;
+        // (s~, t) block (section 2.2.5): the azimuth about p_A comes from
+        // s~ = (p1 + rec)^2 with rec the leg the previous block peeled,
+        // measured from the plane of p_A and rec in the rest frame of P;
+        // the half of [0, 1) that r_phi falls in gives the sign of sin(phi)
+        const bool st_block = (KINDS & KIND_ST) && ct->st && bi > 0 && !bs.com;
+        double jphi = 2.0 * kPiD;
+        if (st_block) {
+            const int prev_side = ct->blk[bi > 0 ? bi - 1 : 0].side;
+            const int s1 = bi > 0 ? 2 * bi - 2 : 0, s2 = bi > 0 ? 2 * bi - 1 : 0;
+            const double re = prev_side == 1 ? E[s2] : E[s1], rx0 = prev_side == 1 ? X[s2] : X[s1];
+            const double ry0 = prev_side == 1 ? Y[s2] : Y[s1], rz0 = prev_side == 1 ? Z[s2] : Z[s1];
+            const double Pe = Ae + Be, Px = Ax + Bx, Py = Ay + By, Pz = Az + Bz;
+            const double i_m0 = 1.0 / m0, i_em = 1.0 / (Pe + m0);
+            double ae = Ae, ax = Ax, ay = Ay, az = Az;
+            boost_by(Pe, -Px, -Py, -Pz, i_m0, i_em, ae, ax, ay, az);
+            double ce = re, cx = rx0, cy = ry0, cz = rz0;
+            boost_by(Pe, -Px, -Py, -Pz, i_m0, i_em, ce, cx, cy, cz);
+            (void)ce;
+            const double inv_len = 1.0 / sqrt(ax * ax + ay * ay + az * az);
+            const double nx = ax * inv_len, ny = ay * inv_len, nz = az * inv_len;
+            const double snt = sqrt(nx * nx + ny * ny);
+            double cp = 1.0, sp = 0.0;
+            if (snt > 0.0) {
+                const double ist = 1.0 / snt;
+                cp = nx * ist;
+                sp = ny * ist;
+            }
+            // the recoil's transverse direction with p_A along z:
+            // R(phi_A, theta_A)^-1
+            const double xr = cx * cp + cy * sp, yr = -cx * sp + cy * cp;
+            const double u0 = xr * nz - cz * snt, u1 = yr;
+            const double rperp = sqrt(u0 * u0 + u1 * u1);
+            // s~ = A - B cos(phi) (A, B from the energies and angles of p1 and
+            // rec) is uniform between A - B and A + B: s~ = (A - B) + 2 B u,
+            // so cos(phi) = (A - s~) / B = 1 - 2 u, formed so without A
+            // cancelling against s~
+            const bool upper = r_phi >= 0.5;
+            const double u = upper ? 2.0 * r_phi - 1.0 : 2.0 * r_phi;
+            const double c = 1.0 - 2.0 * u;
+            const double sn = (upper ? -2.0 : 2.0) * sqrt(u * (1.0 - u));
+            const double ux = u0 / rperp, uy = u1 / rperp;
+            cphi = ux * c - uy * sn;
+            sphi = uy * c + ux * sn;
+            // dphi / dr = 4 / |sin(phi)| on the two branches together
+            jphi = 4.0 / fabs(sn);
+        } else {
+            t_sincospi<MIX>(2.0 * r_phi, &sphi, &cphi);
+        }
         double vx = q * sth * cphi, vy = q * sth * sphi, vz = q * cth;
         double k1e = e1, k1x, k1y, k1z, k2e = e2, k2x, k2y, k2z;
         double inv_m0 = 0.0, inv_em = 0.0;
@@ -553,7 +601,7 @@ __device__ __forceinline__ void run_chain(const ChannelTab* __restrict__ ct, dou
             boost_by(Pe, Px, Py, Pz, inv_m0, inv_em, k1e, k1x, k1y, k1z);
             boost_by(Pe, Px, Py, Pz, inv_m0, inv_em, k2e, k2x, k2y, k2z);
         }
-        jac *= jt * (2.0 * kPiD) / (4.0 * sqrt(lamab));
+        jac *= jt * jphi / (4.0 * sqrt(lamab));
         // store both outputs and update the legs with uniform 0/1 factors:
         // leg next to A -> p_A -= p1, next to B -> p_B -= p2, last block -> neither
         E[2 * bi] = k1e;

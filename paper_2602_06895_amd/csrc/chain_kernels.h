@@ -463,6 +463,43 @@ __global__ __launch_bounds__(kBlock) void k_inverse(const ChannelTab* __restrict
                 const double de = Ae - p1e, dx = Ax - p1x, dy = Ay - p1y, dz = Az - p1z;
                 const double abst = -(de * de - dx * dx - dy * dy - dz * dz);
                 double vx = p1x, vy = p1y;
+                if ((KINDS & KIND_ST) && ct->st && bi > 0 && !bs.com) {
+                    // (s~, t) block: s~ = (p1 + rec)^2 and the orientation of
+                    // p1 about the plane of p_A and rec give r (two branches)
+                    const BlockSpec& pb = ct->blk[bi > 0 ? bi - 1 : 0];
+                    double re, rx, ry, rz;
+                    sum_set<NF>(pb.side == 1 ? pb.set2 : pb.set1, FE, FX, FY, FZ, re, rx, ry, rz);
+                    const double Pe = Ae + Be, Px = Ax + Bx, Py = Ay + By, Pz = Az + Bz;
+                    const double inv_m0 = 1.0 / m0, inv_em = 1.0 / (Pe + m0);
+                    double ae = Ae, ax = Ax, ay = Ay, az = Az;
+                    boost_by(Pe, -Px, -Py, -Pz, inv_m0, inv_em, ae, ax, ay, az);
+                    double ce = re, cx = rx, cy = ry, cz = rz;
+                    boost_by(Pe, -Px, -Py, -Pz, inv_m0, inv_em, ce, cx, cy, cz);
+                    double ke = p1e, kx = p1x, ky = p1y, kz = p1z;
+                    boost_by(Pe, -Px, -Py, -Pz, inv_m0, inv_em, ke, kx, ky, kz);
+                    const double inv_len = 1.0 / sqrt(ax * ax + ay * ay + az * az);
+                    const double nx = ax * inv_len, ny = ay * inv_len, nz = az * inv_len;
+                    const double st = sqrt(nx * nx + ny * ny);
+                    double cp = 1.0, sp = 0.0;
+                    if (st > 0.0) {
+                        const double ist = 1.0 / st;
+                        cp = nx * ist;
+                        sp = ny * ist;
+                    }
+                    const double xr = cx * cp + cy * sp, yr = -cx * sp + cy * cp;
+                    const double r0 = xr * nz - cz * st, r1 = yr;
+                    const double xk = kx * cp + ky * sp, yk = -kx * sp + ky * cp;
+                    const double k0 = xk * nz - kz * st, k1 = yk;
+                    // u = (s~ - (A - B)) / (2 B) = (1 - cos(phi)) / 2, phi the
+                    // angle between the transverse parts of rec and p1
+                    const double rperp = sqrt(r0 * r0 + r1 * r1), kperp = sqrt(k0 * k0 + k1 * k1);
+                    const double c = fmin(1.0, fmax(-1.0, (r0 * k0 + r1 * k1) / (rperp * kperp)));
+                    const double u = 0.5 * (1.0 - c);
+                    (void)ce;
+                    (void)ke;
+                    put(r0 * k1 - r1 * k0 >= 0.0 ? 0.5 * u : 0.5 * (u + 1.0));
+                    put(unmap_dyn<KINDS>(bs.tmap, abst, tmin, tmax));
+                } else {
                 if (!bs.com) {
                     // into the rest frame of P, then R(phi_A, theta_A)^-1 = R_y(-theta_A) R_z(-phi_A)
                     const double Pe = Ae + Be, Px = Ax + Bx, Py = Ay + By, Pz = Az + Bz;
@@ -486,6 +523,7 @@ __global__ __launch_bounds__(kBlock) void k_inverse(const ChannelTab* __restrict
                 }
                 put(turn_fraction(vx, vy));
                 put(unmap_dyn<KINDS>(bs.tmap, abst, tmin, tmax));
+                }
                 const int side = bs.side;
                 const double fa = side == 0 ? 1.0 : 0.0, fb = side == 1 ? 1.0 : 0.0;
                 Ae -= fa * p1e;
@@ -561,12 +599,12 @@ __global__ __launch_bounds__(kBlock) void k_inverse(const ChannelTab* __restrict
 // Launch of one register class: kind class `kc` picks the compiled map kinds
 // (0: integer-root power laws, 1: plus Breit-Wigner, 2: all tree kinds;
 // 3: those of class 1 with Chili channels, 4: those of class 1 with 1 -> 3
-// decays, 5: everything).  Chili and 1 -> 3 decays have classes of their
+// decays, 5: everything, (s~, t) blocks included).  Chili and 1 -> 3 decays have classes of their
 // own because compiled together they overflow the register file.
 template <int NS, int NI, bool MIX>
 hipError_t launch_chain_class(int kc, const ChainLaunch& a) {
     constexpr int K0 = KIND_POW_INT, K1 = KIND_POW_INT | KIND_BW, K2 = KINDS_ALL;
-    constexpr int K3 = K1 | KIND_CHILI, K4 = K1 | KIND_DEC3, K5 = KINDS_ALL | KIND_CHILI | KIND_DEC3;
+    constexpr int K3 = K1 | KIND_CHILI, K4 = K1 | KIND_DEC3, K5 = KINDS_ALL | KIND_CHILI | KIND_DEC3 | KIND_ST;
     auto go = [&](auto kt) {
         constexpr int K = decltype(kt)::value;
         const size_t lds = a.lds + (a.sample ? sizeof(double) * stage_rows<NS, NI>() * kBlock : kQBytes) +

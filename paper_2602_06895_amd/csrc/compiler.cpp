@@ -240,6 +240,10 @@ bool compile_channel(Ctx& cx, const JValue& cj, const std::vector<double>& masse
             if (to->kind != JValue::STR) return cx.fail("\"t_order\" must be a string");
             t_order = to->str;
         }
+        if (const JValue* stj = cj.get("st")) {
+            if (stj->kind != JValue::BOOL) return cx.fail("\"st\" must be true or false");
+            t.st = stj->b ? 1 : 0;
+        }
         int kappa = (int)nodes[0].kids.size() - 1;
         if ((int)t_order.size() != kappa - 1) return cx.fail("\"t_order\" needs kappa-1 letters");
         for (char c : t_order)
@@ -496,6 +500,7 @@ bool compile_channel(Ctx& cx, const JValue& cj, const std::vector<double>& masse
     for (int i = 0; i < t.n_inv; ++i) t.kinds |= kind_bit(t.inv[i].map);
     for (int i = 0; i < t.n_blocks; ++i) t.kinds |= kind_bit(t.blk[i].tmap);
     if (n3) t.kinds |= 128;
+    if (t.st && t.n_blocks > 1) t.kinds |= 256;  // (s~, t) blocks (KIND_ST)
     // two per two-body decay, five per 1 -> 3 decay (which holds two entries)
     t.dims = (hadronic ? 2 : 0) + (int)s_order.size() + std::max(kappa - 1, 0) + 2 * kappa + 2 * (nd - 2 * n3) +
              5 * n3;

@@ -549,8 +549,10 @@ int reg_class(int slots, int inv) {
 
 // Map-kind class of a launch: 0 integer-root power laws only, 1 plus
 // Breit-Wigner, 2 every tree kind; when the tree kinds fit class 1, 3 with
-// Chili channels, 4 with 1 -> 3 decays; 5 for anything else.
+// Chili channels, 4 with 1 -> 3 decays; 5 for anything else and for (s~, t)
+// blocks.
 int kind_class(int kinds) {
+    if (kinds & KIND_ST) return 5;
     if (kinds & (KIND_CHILI | KIND_DEC3)) {
         if (kinds & ~(KIND_POW_INT | KIND_BW | KIND_CHILI | KIND_DEC3)) return 5;
         if ((kinds & KIND_CHILI) && (kinds & KIND_DEC3)) return 5;

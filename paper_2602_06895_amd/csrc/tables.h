@@ -113,6 +113,7 @@ struct ChannelTab {
     BlockSpec blk[kMaxFinal];
     DecaySpec dec[kMaxFinal];
     int32_t final_slot[kMaxFinal];  // slot code of each final-state particle
+    int32_t st;                     // 1: blocks after the first use (s~, t) (section 2.2.5)
     // Chili channels (no tree): particle k sits in slot k
     int32_t chili;                  // 1: a Chili channel
     double chili_ptmin2;            // the process's p_T cut squared (<= 0: none)

@@ -92,9 +92,26 @@ def cpu_baseline(desc, grids, counts, seed, min_seconds=10.0, single_seconds=4.0
 
 # sources of the fused sample kernel (a change invalidates the committed counter figures)
 KERNEL_SOURCES = ["paper_2602_06895_amd/csrc/" + f for f in
-                  ("chain_kernels.h", "chain.h", "device_util.h", "tables.h", "chain_f64_s.hip", "chain_f64_m.hip")]
-PROFILE = os.path.join(ROOT, "profiles", "k_sample_ttbar6_1e8.txt")
-PROFILE_C2 = os.path.join(ROOT, "profiles", "k_sample_pp4j_1e7.txt")
+                  ("chain_kernels.h", "chain.h", "device_util.h", "tables.h", "chain_f64_s.hip", "chain_f64_m.hip",
+                   "jit.cpp")] + ["paper_2602_06895_amd/build.py"]
+# the fused sample kernel the library compiles for the context's channels
+# (msx_specialize); --no-specialize times the class kernel k_sample instead
+SPECIALIZE = True
+PROFILE = os.path.join(ROOT, "profiles", "msx_jit_sample_ttbar6_1e8.txt")
+PROFILE_C2 = os.path.join(ROOT, "profiles", "msx_jit_sample_pp4j_1e7.txt")
+PROFILE_CLASS = os.path.join(ROOT, "profiles", "k_sample_ttbar6_1e8.txt")
+
+
+def make_context(desc, **kw):
+    """A context whose sample launches use the specialised kernel (unless
+    --no-specialize); returns (context, seconds the run-time compile took)."""
+    from paper_2602_06895_amd import Context
+
+    ctx = Context(desc, **kw)
+    t0 = time.perf_counter()
+    if SPECIALIZE:
+        ctx.specialize()
+    return ctx, time.perf_counter() - t0
 
 
 def kernel_source_hash() -> str:
@@ -224,13 +241,13 @@ def mixed_report(n=100_000_000, steps=10, n_err=10_000_000):
     from paper_2602_06895_amd import MIXED, Context, adapt_vegas
     from paper_2602_06895_amd.report import precision_error
 
-    c64 = Context(W.c3_ttbar6())
+    c64, _ = make_context(W.c3_ttbar6())
     adapt_vegas(c64, n_per_channel=100_000, iterations=10, seed=3, stream_id=1)
     grid = c64.get_grid(0)
     counts = np.array([n])
     _, wall64, ms64 = graph_steps(c64, counts, 77, steps, 2)
     torch.cuda.empty_cache()
-    cmx = Context(W.c3_ttbar6(), precision=MIXED)
+    cmx, _ = make_context(W.c3_ttbar6(), precision=MIXED)
     cmx.set_grid(0, grid)
     cmx.set_launch(*c64.launch_shape())
     _, wallmx, msmx = graph_steps(cmx, counts, 77, steps, 2)
@@ -261,7 +278,7 @@ def flow_report(train_steps=400, batch=65536, n_eval=1_000_000, lr=1e-3, workloa
     from paper_2602_06895_amd import FLOW_BF16, Context, Flow, adapt_vegas
 
     desc = W.c3_ttbar6() if workload == "c3" else W.c2_pp4j()
-    ctx = Context(desc)
+    ctx, _ = make_context(desc)
     adapt_vegas(ctx, n_per_channel=100_000, iterations=10, seed=3, stream_id=1)
     d = ctx.dims[channel]
     counts = np.zeros(ctx.n_channels, dtype=np.int64)
@@ -349,7 +366,7 @@ def graph_report(steps=20):
     N = int(counts.sum())
     out = {"workload": f"24 channels (6 processes), {N} events, counts power-law 1e3..1e6"}
     for name, prec in (("fp64", 0), ("mixed", MIXED)):
-        ctx = Context(desc, precision=prec)
+        ctx, spec_s = make_context(desc, precision=prec)
         eager_ms = _timed(lambda: ctx.sample(counts, seed=4, stream_id=8), steps)
         best = ctx.autotune(counts, seed=4, reps=3)
         ept, grid = ctx.launch_shape()
@@ -357,7 +374,8 @@ def graph_report(steps=20):
         med = float(np.median(ms))
         out[name] = {"eager_ms": eager_ms, "graph_median_ms": med, "graph_ms_range": [min(ms), max(ms)],
                      "graph_events_per_s": N / (med / 1e3),
-                     "autotuned": {"events_per_thread": ept, "grid": grid, "ms": best}}
+                     "autotuned": {"events_per_thread": ept, "grid": grid, "ms": best},
+                     "specialize_seconds": spec_s}
         ctx.close()
         torch.cuda.empty_cache()
     return out
@@ -412,7 +430,7 @@ def fastrambo_report(n_particles=6, n=10_000_000, reps=5):
     import workloads as W
     from paper_2602_06895_amd import Context
 
-    ctx = Context(W.rambo_process(n_particles))
+    ctx, _ = make_context(W.rambo_process(n_particles))
     counts = np.array([n])
     out = ctx.sample(counts, seed=6, stream_id=1)
     ms = _timed(lambda: ctx.sample(counts, seed=6, stream_id=1, out=out), reps)
@@ -444,7 +462,7 @@ def chili_report(n=10_000_000, reps=5):
 
     desc = W.c2_pp4j()
     desc["channels"] = [{"chili": True}]
-    ctx = Context(desc)
+    ctx, _ = make_context(desc)
     counts = np.array([n])
     out = ctx.sample(counts, seed=8, stream_id=1)
     ms = _timed(lambda: ctx.sample(counts, seed=8, stream_id=1, out=out), reps)
@@ -480,7 +498,7 @@ def dec3_report(n=10_000_000, reps=5):
         if key == "three_body":
             desc["channels"] = [{"s": {"d": [{"d": [1, 2, 3], "m": mt, "w": gt, "order": 1},
                                              {"d": [4, 5, 6], "m": mt, "w": gt, "order": 2}]}}]
-        ctx = Context(desc)
+        ctx, _ = make_context(desc)
         counts = np.array([n])
         out = ctx.sample(counts, seed=9, stream_id=1)
         ms = _timed(lambda: ctx.sample(counts, seed=9, stream_id=1, out=out), reps)
@@ -630,7 +648,7 @@ def headline(args):
     from paper_2602_06895_amd import Context, adapt_vegas
 
     desc = W.c3_ttbar6()
-    ctx = Context(desc, device=0)
+    ctx, spec_s = make_context(desc, device=0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     adapt_vegas(ctx, n_per_channel=100_000, iterations=10, alpha=0.5, seed=3, stream_id=1)
@@ -649,6 +667,17 @@ def headline(args):
     ms_per_step = wall * 1e3 / args.steps
     launch_s = float(np.mean(ms)) / 1e3
     ept, grid = ctx.launch_shape()
+    del buf
+    torch.cuda.empty_cache()
+    other = None
+    if SPECIALIZE:
+        # the class kernel on the same workload and launch shape (5 replays)
+        ctx.specialize(False)
+        b2, _, ms_cls = graph_steps(ctx, counts, 3000, 5, 1)
+        del b2
+        torch.cuda.empty_cache()
+        other = {"kernel": "k_sample (class kernel, tables read from device memory)",
+                 "median_replay_ms": float(np.median(ms_cls)), "events_per_s": N / (float(np.median(ms_cls)) / 1e3)}
     result = {
         "metric": "weighted events/sec at fixed integral rel. error; unweighting eff. flow vs VEGAS",
         "value": N / (ms_per_step / 1e3),
@@ -666,7 +695,9 @@ def headline(args):
                                f"x 16 dims adapted 10x1e5 then frozen, {N} events per step, FP64",
                    "events_per_step": N, "channels": 1, "sampler": "vegas",
                    "timed_step": "one replay of the captured fused-sample graph (new events every replay)",
-                   "launch": {"events_per_thread": ept, "workgroups": grid}},
+                   "launch": {"events_per_thread": ept, "workgroups": grid},
+                   "kernel": "msx_jit_sample (compiled for the channel, msx_specialize)" if SPECIALIZE else
+                             "k_sample (class kernel)"},
         "integral": I,
         "rel_error_per_step": rel,
         "median_replay_ms": float(np.median(ms)),
@@ -675,13 +706,15 @@ def headline(args):
         "unweighting_eff": eff,
         "vegas_adaptation": {"iterations": 10, "events_per_iteration": 100_000, "seconds": adapt_s,
                              "where": "histograms accumulated inside the fused sample (msx_vegas_adapt)"},
-        "roofline": dict(roofline(N, BYTES_PER_EVENT, launch_s, profiled()),
-                         kernel="k_sample (fused sample, graph replay: plan + sample + statistics + counter "
-                                "kernels between the HIP events)"),
+        "specialize_seconds": spec_s,
+        "roofline": dict(roofline(N, BYTES_PER_EVENT, launch_s, profiled(PROFILE if SPECIALIZE else PROFILE_CLASS)),
+                         kernel=("msx_jit_sample" if SPECIALIZE else "k_sample") +
+                         " (fused sample, graph replay: plan + sample + statistics + counter kernels between the "
+                         "HIP events)"),
     }
+    if other:
+        result["class_kernel"] = other
     ctx.close()
-    del buf
-    torch.cuda.empty_cache()
     return result, desc, grids, counts
 
 
@@ -695,7 +728,7 @@ def c2_report(steps=20, warmup=3, autotune=True):
     import workloads as W
     from paper_2602_06895_amd import OBS_DR_HARDEST, OBS_M, OBS_PT_RANK, Context, adapt_vegas, neyman_counts
 
-    ctx = Context(W.c2_pp4j(), device=0)
+    ctx, spec_s = make_context(W.c2_pp4j(), device=0)
     st = adapt_vegas(ctx, n_per_channel=100_000, iterations=10, alpha=0.5, seed=1, stream_id=1)
     counts = neyman_counts(st, C2_EVENTS)
     if autotune:
@@ -734,7 +767,9 @@ def c2_report(steps=20, warmup=3, autotune=True):
            "unweighting": {"w_max_overweight": 1e-3, "kept": kept, "ms": unw_ms, "events_per_s": N / (unw_ms / 1e3)},
            "distributions": {"observables": "sqrt(s-hat), hardest-jet pT, dR of the two hardest jets",
                              "cut_and_3_histograms_ms": dist_ms, "events_per_s": N / (dist_ms / 1e3)},
-           "roofline": roofline(N, C2_BYTES_PER_EVENT, float(np.mean(ms)) / 1e3, profiled(PROFILE_C2))}
+           "kernel": "msx_jit_sample" if SPECIALIZE else "k_sample", "specialize_seconds": spec_s,
+           "roofline": roofline(N, C2_BYTES_PER_EVENT, float(np.mean(ms)) / 1e3,
+                                profiled(PROFILE_C2) if SPECIALIZE else {})}
     ctx.close()
     del buf
     torch.cuda.empty_cache()
@@ -762,7 +797,12 @@ def main():
     ap.add_argument("--flow-steps", type=int, default=400, help="training steps of the learned sampler")
     ap.add_argument("--inverse-only", action="store_true", help="only the inverse-map report")
     ap.add_argument("--c2-only", action="store_true", help="only the pp -> 4 jets report")
+    ap.add_argument("--no-specialize", action="store_true",
+                    help="sample with the class kernels instead of the kernel compiled for the channels")
+    ap.add_argument("--kernel", default=None, help="--summarize*: the kernel name to summarise")
     args = ap.parse_args()
+    global SPECIALIZE
+    SPECIALIZE = not args.no_specialize
     if args.summarize_trace:
         summarize_trace(args.summarize_trace)
         return
@@ -770,11 +810,11 @@ def main():
         summarize_counters(args.summarize_counters)
         return
     if args.summarize:
-        summarize(args.summarize, args.events)
+        summarize(args.summarize, args.events, kernel=args.kernel or "msx_jit_sample")
         return
     if args.summarize_c2:
-        summarize(args.summarize_c2, C2_EVENTS, kernel="k_sample", bytes_per_event=C2_BYTES_PER_EVENT,
-                  title="pp -> 4 jets (8 channels, 10 dims, FP64)")
+        summarize(args.summarize_c2, C2_EVENTS, kernel=args.kernel or "msx_jit_sample",
+                  bytes_per_event=C2_BYTES_PER_EVENT, title="pp -> 4 jets (8 channels, 10 dims, FP64)")
         return
     if args.summarize_flow:
         summarize_flow(args.summarize_flow)

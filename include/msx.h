@@ -133,8 +133,9 @@ enum {
     MSX_META_EVENTS_PER_THREAD = 9, /* sample launch shape: events per thread per tile */
     MSX_META_GRID = 10,        /* sample launch shape: workgroups of the persistent grid */
     MSX_META_COUNTER = 11,     /* next event id of MSX_COUNTER_AUTO sample calls */
-    MSX_META_FLOW = 12         /* channel `index`: 0 no flow attached, 1 attached but VEGAS kept
+    MSX_META_FLOW = 12,        /* channel `index`: 0 no flow attached, 1 attached but VEGAS kept
                                   (the attach check found the flow no better), 2 flow enabled */
+    MSX_META_SPECIALIZED = 13  /* 1 while sample launches use the kernel msx_specialize built */
 };
 
 /* Text of the last error on this context (or of the last failed create when
@@ -309,6 +310,25 @@ msx_status msx_set_launch(msx_ctx* ctx, int32_t events_per_thread, int32_t grid)
  * its own output scratch; the context's statistics are left unchanged.
  * Synchronises the device.  *best_ms (optional) gets the time per launch. */
 msx_status msx_autotune(msx_ctx* ctx, const int64_t* counts, uint64_t seed, int32_t reps, double* best_ms);
+
+/* Channel-specialised fused sample (the per-event chain of section 2.2 with
+ * the integrand and channel weight of eq. multi-channel-mg, as msx_sample).
+ * on != 0: compiles, with the HIP run-time compiler for the context's
+ * device, a version of the fused sample kernel in which this context's
+ * channel and process tables are compile-time constants (the map kinds,
+ * operation counts and momentum slots of every channel fixed in the code),
+ * loads it, and from then on every sample launch of the context uses it:
+ * msx_sample, msx_sample_device, msx_sample_noalloc and graphs captured
+ * afterwards.  Its results are bit-identical to the default kernel's (same
+ * source, no floating-point contraction in either); it runs fewer
+ * instructions with fewer registers.  The first call compiles (about a
+ * second per distinct channel on the host) and synchronises the device;
+ * later calls only switch.  on == 0 switches launches back to the default
+ * kernel; the compiled one stays loaded until msx_destroy (graphs captured
+ * with it keep working).  Errors: MSX_ERR_DEVICE with the compiler's log
+ * when the run-time compiler or the module load fails (the context keeps the
+ * default kernel). */
+msx_status msx_specialize(msx_ctx* ctx, int32_t on);
 
 /* Copy the accumulated per-channel statistics to host out [n_channels][5]:
  * (sum w, sum w^2, n, n with w == 0, max w).  Synchronises `stream`. */

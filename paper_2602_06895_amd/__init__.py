@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libmsx.so")
 FP64, MIXED = 0, 1
 META_N_CHANNELS, META_DIMS, META_N_MOMENTA, META_HADRONIC = 0, 1, 2, 3
 META_VEGAS_BINS, META_MAX_MOMENTA, META_PROCESS, META_DEVICE, META_PRECISION = 4, 5, 6, 7, 8
-META_EVENTS_PER_THREAD, META_GRID, META_COUNTER, META_FLOW = 9, 10, 11, 12
+META_EVENTS_PER_THREAD, META_GRID, META_COUNTER, META_FLOW, META_SPECIALIZED = 9, 10, 11, 12, 13
 COUNTER_AUTO = 2 ** 64 - 1
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_DEVICE", 3: "ERR_OOM", 4: "ERR_UNSUPPORTED", 5: "ERR_STATE"}
 
@@ -33,7 +33,7 @@ EXPORTS = ["msx_last_error", "msx_create_channels", "msx_destroy", "msx_get_meta
            "msx_inverse_map", "msx_multichannel_density", "msx_unweight", "msx_observables", "msx_cut",
            "msx_histogram", "msx_vegas_adapt", "msx_allocate_counts",
            "msx_sample_noalloc", "msx_get_state", "msx_set_state", "msx_attach_flow", "msx_flow_get_state",
-           "msx_flow_set_state", "msx_flow_dims"]
+           "msx_flow_set_state", "msx_flow_dims", "msx_specialize"]
 OBS_E, OBS_PT, OBS_ETA, OBS_PHI, OBS_M, OBS_PT_RANK, OBS_DR_HARDEST = range(7)
 FLOW_BF16, FLOW_FP32 = 0, 1
 SAMPLE_ACCUMULATE_VEGAS, SAMPLE_USE_FLOW, SAMPLE_ADVANCE_COUNTER = 1, 2, 4
@@ -98,6 +98,7 @@ def load_library(path: str = LIB_PATH):
         "msx_graph_destroy": ([vp], C.c_int),
         "msx_set_launch": ([vp, i32, i32], C.c_int),
         "msx_autotune": ([vp, vp, u64, i32, C.POINTER(dbl)], C.c_int),
+        "msx_specialize": ([vp, i32], C.c_int),
         "msx_flow_last_error": ([vp], C.c_char_p),
         "msx_flow_create": ([i32, i32, i32, i32, i32, i32, C.POINTER(vp)], C.c_int),
         "msx_flow_destroy": ([vp], C.c_int),
@@ -345,6 +346,16 @@ class Context:
         ms = C.c_double()
         self._check(self.L.msx_autotune(self.h, c.ctypes.data, seed, reps, C.byref(ms)))
         return ms.value
+
+    def specialize(self, on: bool = True):
+        """Sample launches use (on) the kernel compiled for these channels
+        with their tables as constants (bit-identical results), or the
+        default kernel (off)."""
+        self._check(self.L.msx_specialize(self.h, 1 if on else 0))
+
+    @property
+    def specialized(self) -> bool:
+        return bool(self._meta(META_SPECIALIZED, 0))
 
     def stats(self) -> np.ndarray:
         out = np.zeros((self.n_channels, 5))

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "compiler.h"
+#include "jit.h"
 #include "json.h"
 #include "launch.h"
 #include "tables.h"
@@ -83,6 +84,10 @@ struct msx_ctx {
     // register / kind class covering every channel (device-count launches)
     int all_slots = 0, all_inv = 0, all_kinds = 0;
     bool any_hadronic = false;
+    // the fused sample compiled for these channels (msx_specialize); kept
+    // loaded until msx_destroy once built, since captured graphs may use it
+    JitSample jit;
+    bool jit_on = false;
 };
 
 struct msx_graph {
@@ -132,6 +137,8 @@ void free_all(msx_ctx* c) {
 }
 
 bool bad_ctx(const msx_ctx* ctx) { return ctx == nullptr; }
+
+const JitSample* jit_of(const msx_ctx* ctx) { return ctx->jit_on ? &ctx->jit : nullptr; }
 
 msx_status set_device(msx_ctx* ctx) {
     hipError_t e = hipSetDevice(ctx->device);
@@ -199,7 +206,7 @@ msx_status sample_device(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uin
             launch_sample(ctx->d_chans, ctx->d_procs, ctx->d_grids, ctx->d_grid_off, ctx->d_chan_nb, d_call, C,
                           ctx->all_slots, ctx->all_inv, ctx->all_kinds, ctx->mixed, ctx->lds_max, seed, stream_id,
                           counter_offset, 0, ctx->max_np, capacity, p, x1x2, w, chan, d_tile, ctx->d_stats, grid, s,
-                          d_vtiles, ctx->vstride, ctx->d_hist_off, ctx->hist_total, ctx->d_hist),
+                          d_vtiles, ctx->vstride, ctx->d_hist_off, ctx->hist_total, ctx->d_hist, jit_of(ctx)),
             "sample launch");
     if (advance) MSX_HIP(ctx, launch_advance_counter(d_call, const_cast<uint64_t*>(counter_offset), s), "counter");
     return MSX_OK;
@@ -315,7 +322,24 @@ msx_status msx_destroy(msx_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     free_all(ctx);
+    jit_release(ctx->jit);
     delete ctx;
+    return MSX_OK;
+}
+
+msx_status msx_specialize(msx_ctx* ctx, int32_t on) {
+    if (bad_ctx(ctx)) return fail(nullptr, MSX_ERR_ARG, "ctx is NULL");
+    if (!on) {
+        ctx->jit_on = false;
+        return MSX_OK;
+    }
+    if (!ctx->jit.fn) {
+        if (msx_status st = set_device(ctx)) return st;
+        std::string err;
+        if (!jit_build_sample(ctx->comp, ctx->mixed, ctx->device, ctx->jit, err))
+            return fail(ctx, MSX_ERR_DEVICE, "specialised sample kernel: " + err);
+    }
+    ctx->jit_on = true;
     return MSX_OK;
 }
 
@@ -337,6 +361,7 @@ msx_status msx_get_meta(const msx_ctx* ctx, int32_t key, int32_t index, int64_t*
         case MSX_META_EVENTS_PER_THREAD: *value = ctx->ept; return MSX_OK;
         case MSX_META_GRID: *value = sample_grid(ctx); return MSX_OK;
         case MSX_META_COUNTER: *value = (int64_t)ctx->next_counter; return MSX_OK;
+        case MSX_META_SPECIALIZED: *value = ctx->jit_on ? 1 : 0; return MSX_OK;
         case MSX_META_FLOW:
             return chan(index >= 0 && index < C ? (ctx->flow[index] ? 1 + ctx->flow_on[index] : 0) : 0);
         case MSX_META_DIMS: return chan(index >= 0 && index < C ? ctx->comp.meta[index].dims : 0);
@@ -546,7 +571,7 @@ msx_status sample_host(msx_ctx* ctx, const int64_t* counts, uint64_t seed, uint6
                           max_slots, max_inv, kinds, ctx->mixed, ctx->lds_max, seed, stream_id, nullptr,
                           counter_offset, ctx->max_np, N, p, x1x2, w, chan, noalloc ? ctx->d_noalloc : ctx->d_tile,
                           ctx->d_stats, grid, s, acc ? ctx->d_vtiles : nullptr, ctx->vstride, ctx->d_hist_off,
-                          ctx->hist_total, ctx->d_hist),
+                          ctx->hist_total, ctx->d_hist, jit_of(ctx)),
             "sample launch");
     return MSX_OK;
 }
@@ -1158,7 +1183,7 @@ msx_status sample_with_flows(msx_ctx* ctx, const int64_t* counts, uint64_t seed,
                               C, max_slots, max_inv, kinds, ctx->mixed, ctx->lds_max, seed, stream_id, nullptr,
                               counter_offset, ctx->max_np, N, p, x1x2, w, chan, ctx->d_tile, ctx->d_stats, grid, s,
                               acc ? ctx->d_vtiles : nullptr, ctx->vstride, ctx->d_hist_off, ctx->hist_total,
-                              ctx->d_hist),
+                              ctx->d_hist, jit_of(ctx)),
                 "sample launch");
     }
     for (int c = 0; c < C; ++c) {

@@ -13,8 +13,10 @@
 // multi-channel-mg).
 #pragma once
 
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#endif
 
 #include "tables.h"
 

@@ -1,5 +1,5 @@
 // Mapping-chain kernels: 10 momentum slots, 8 invariants, FP64.
-#include "chain_kernels.h"
+#include "chain_launch.h"
 
 namespace msx {
 MSX_INSTANTIATE_CHAIN(10, 8, false)

@@ -1,5 +1,5 @@
 // Mapping-chain kernels: 6 momentum slots, 4 invariants, FP64.
-#include "chain_kernels.h"
+#include "chain_launch.h"
 
 namespace msx {
 MSX_INSTANTIATE_CHAIN(6, 4, false)

@@ -5,13 +5,12 @@
 // (NS, NI, precision); the units compile in parallel.
 #pragma once
 
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
-
-#include <algorithm>
+#endif
 
 #include "chain.h"
 #include "device_util.h"
-#include "launch.h"
 
 namespace msx {
 
@@ -175,21 +174,98 @@ __global__ __launch_bounds__(kBlock) void k_map(const ChannelTab* __restrict__ c
 // per-tile statistics are reproducible for a given launch shape).  Each tile
 // writes (sum w, sum w^2, n(w == 0), max w) to tile_stats.  Per-event results
 // do not depend on the launch shape: the uniforms are keyed by event id.
+// What the events of one tile need besides their channel's tables.
+struct TileArgs {
+    int64_t base, end;  // first output position of the tile, end of the channel's range
+    int ept;
+    uint64_t ctr0, seed, sid;
+    const double* lg;  // the channel's VEGAS grid in LDS
+    int nb;
+    double* col;  // this thread's staging column
+    uint8_t* vbin;  // this thread's VEGAS bin bytes, NULL: no accumulation
+    double* vh_wave;  // this wave's VEGAS histogram
+    int lane, np;
+    int64_t ld;
+    double* p;
+    double* x1x2;
+    double* w;
+    int32_t* chan_out;
+};
+struct TileAcc {
+    double s1 = 0.0, s2 = 0.0, zeros = 0.0, wmax = 0.0;
+};
+
+// The events of one tile of channel c: uniforms (Philox, VEGAS-mapped into
+// the staging column), chain, weight, stores, the tile's running statistics
+// and (vbin) the VEGAS histogram.  ct and pt are the channel's tables; the
+// kernel compiled for a fixed set of channels passes them as constants.
 template <int NS, int NI, int KINDS, bool MIX>
-__global__ __launch_bounds__(kBlock) void k_sample(const ChannelTab* __restrict__ cts, const ProcessTab* __restrict__ pts,
-                                                   const double* __restrict__ grids, const int64_t* __restrict__ grid_off,
-                                                   const int32_t* __restrict__ chan_nb,
-                                                   const SampleCall* __restrict__ call, uint64_t seed, uint64_t sid,
-                                                   const uint64_t* __restrict__ ctr_dev, uint64_t ctr_off, int np,
-                                                   int64_t ld, double* __restrict__ p, double* __restrict__ x1x2,
-                                                   double* __restrict__ w, int32_t* __restrict__ chan_out,
-                                                   double* __restrict__ tile_stats, int grid_doubles,
-                                                   double* __restrict__ vpart, int vstride) {
-    constexpr int kRows = stage_rows<NS, NI>();
+__device__ __forceinline__ void sample_tile(const ChannelTab* __restrict__ ct, const ProcessTab* __restrict__ pt,
+                                            int c, const TileArgs& t, TileAcc& acc) {
+    const int dims = ct->dims;
+    const double s_lab = pt->s_lab;
+    const LdsQ q{t.col};
+    double* const col = t.col;
+    for (int sub = 0; sub < t.ept; ++sub) {
+        const int64_t pos0 = t.base + (int64_t)sub * kBlock;
+        if (pos0 >= t.end) break;
+        const int64_t pos = pos0 + threadIdx.x;
+        const bool live = pos < t.end;
+        double wv = 0.0;
+        if (live) {
+            const uint64_t e = t.ctr0 + (uint64_t)pos;
+            // all dimensions first, four per Philox block, VEGAS-mapped
+            // into this thread's LDS column: one copy of the generator in
+            // the code instead of one per place the chain draws a number
+            double jv = 1.0;
+#pragma unroll 1
+            for (int k4 = 0; k4 < dims; k4 += 4) {
+                uint64_t c0 = e, c1 = (uint64_t)(k4 >> 2), c2 = 0, c3 = 0;
+                philox4x64_10(c0, c1, c2, c3, t.seed, t.sid);
+                const uint64_t wd[4] = {c0, c1, c2, c3};
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (k4 + j < dims) {
+                        const double u = to_unit(wd[j]);
+                        if (t.vbin) t.vbin[(k4 + j) * kBlock] = (uint8_t)vegas_bin(u, t.nb);
+                        col[(k4 + j) * kBlock] = vegas_map(u, t.lg + (k4 + j) * (t.nb + 1), t.nb, jv);
+                    }
+            }
+            int k = 0;
+            auto next = [&]() -> double { return col[(k++) * kBlock]; };
+            double E[NS], X[NS], Y[NS], Z[NS], S[NI], SQ[NI];
+            ChainOut o;
+            if ((KINDS & KIND_CHILI) && ct->chili)
+                run_chili<NS>(ct, s_lab, next, E, X, Y, Z, o);
+            else
+                run_chain<NS, NI, KINDS, MIX>(ct, s_lab, next, E, X, Y, Z, S, SQ, o);
+            wv = finish_event<NS, MIX>(ct, pt, o, jv, E, X, Y, Z, t.np, t.ld, pos, t.p, t.x1x2, nullptr, true, q);
+            t.w[pos] = wv;
+            if (t.chan_out) t.chan_out[pos] = c;
+            acc.s1 += wv;
+            acc.s2 += wv * wv;
+            acc.zeros += wv == 0.0 ? 1.0 : 0.0;
+            acc.wmax = fmax(acc.wmax, wv);
+        }
+        if (t.vbin) vegas_wave_accumulate(t.vh_wave, t.vbin, dims, t.nb, t.lane, live, wv);
+    }
+}
+
+// The persistent loop of the fused sample: blocks stride over the call's
+// tiles (each tile kBlock * ept events of one channel), load a channel's
+// VEGAS grid into LDS when the channel changes, run `tile` on the tile's
+// events and write its statistics and (vpart) VEGAS histogram.  ROWS is the
+// staging column's height; the grid follows it in the dynamic LDS.
+template <int ROWS, class Tile>
+__device__ __forceinline__ void sample_loop(const ChannelTab* __restrict__ cts, const double* __restrict__ grids,
+                                            const int64_t* __restrict__ grid_off, const int32_t* __restrict__ chan_nb,
+                                            const SampleCall* __restrict__ call, uint64_t seed, uint64_t sid,
+                                            const uint64_t* __restrict__ ctr_dev, uint64_t ctr_off, int np, int64_t ld,
+                                            double* __restrict__ p, double* __restrict__ x1x2, double* __restrict__ w,
+                                            int32_t* __restrict__ chan_out, double* __restrict__ tile_stats,
+                                            int grid_doubles, double* __restrict__ vpart, int vstride, Tile&& tile) {
     extern __shared__ double lds[];
-    double* lg = lds + kRows * kBlock;
-    double* const col = lds + threadIdx.x;
-    const LdsQ q{col};
+    double* lg = lds + ROWS * kBlock;
     __shared__ double red[4][kWaves];
     int cur = -1;
     int nb = 0, dims = 0;
@@ -207,70 +283,42 @@ __global__ __launch_bounds__(kBlock) void k_sample(const ChannelTab* __restrict_
     if (vpart) {
         for (int i = threadIdx.x; i < kWaves * vstride; i += kBlock) vh[i] = 0.0;
     }
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    for (int64_t tl = blockIdx.x; tl < n_tiles; tl += gridDim.x) {
         int c = 0;
-        while (c + 1 < n_chan && call->tile_start[c + 1] <= tile) ++c;
-        const ChannelTab* ct = cts + c;
+        while (c + 1 < n_chan && call->tile_start[c + 1] <= tl) ++c;
         if (c != cur) {
             __syncthreads();
             nb = chan_nb[c];
-            dims = ct->dims;
+            dims = cts[c].dims;
             const double* g = grids + grid_off[c];
             for (int i = threadIdx.x; i < dims * (nb + 1); i += blockDim.x) lg[i] = g[i];
             __syncthreads();
             cur = c;
         }
-        const ProcessTab* pt = pts + ct->process;
-        const double s_lab = pt->s_lab;
-        const int64_t base = call->ev_start[c] + (tile - call->tile_start[c]) * (int64_t)kBlock * ept;
-        const int64_t end = call->ev_start[c + 1];
-        double a1 = 0.0, a2 = 0.0, az = 0.0, am = 0.0;
-        for (int sub = 0; sub < ept; ++sub) {
-            const int64_t pos0 = base + (int64_t)sub * kBlock;
-            if (pos0 >= end) break;
-            const int64_t pos = pos0 + threadIdx.x;
-            const bool live = pos < end;
-            double wv = 0.0;
-            if (live) {
-                const uint64_t e = ctr0 + (uint64_t)pos;
-                // all dimensions first, four per Philox block, VEGAS-mapped
-                // into this thread's LDS column: one copy of the generator in
-                // the code instead of one per place the chain draws a number
-                double jv = 1.0;
-#pragma unroll 1
-                for (int k4 = 0; k4 < dims; k4 += 4) {
-                    uint64_t c0 = e, c1 = (uint64_t)(k4 >> 2), c2 = 0, c3 = 0;
-                    philox4x64_10(c0, c1, c2, c3, seed, sid);
-                    const uint64_t wd[4] = {c0, c1, c2, c3};
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (k4 + j < dims) {
-                            const double u = to_unit(wd[j]);
-                            if (vpart) vbin[(k4 + j) * kBlock + threadIdx.x] = (uint8_t)vegas_bin(u, nb);
-                            col[(k4 + j) * kBlock] = vegas_map(u, lg + (k4 + j) * (nb + 1), nb, jv);
-                        }
-                }
-                int k = 0;
-                auto next = [&]() -> double { return col[(k++) * kBlock]; };
-                double E[NS], X[NS], Y[NS], Z[NS], S[NI], SQ[NI];
-                ChainOut o;
-                if ((KINDS & KIND_CHILI) && ct->chili)
-                    run_chili<NS>(ct, s_lab, next, E, X, Y, Z, o);
-                else
-                    run_chain<NS, NI, KINDS, MIX>(ct, s_lab, next, E, X, Y, Z, S, SQ, o);
-                wv = finish_event<NS, MIX>(ct, pt, o, jv, E, X, Y, Z, np, ld, pos, p, x1x2, nullptr, true, q);
-                w[pos] = wv;
-                if (chan_out) chan_out[pos] = c;
-                a1 += wv;
-                a2 += wv * wv;
-                az += wv == 0.0 ? 1.0 : 0.0;
-                am = fmax(am, wv);
-            }
-            if (vpart) vegas_wave_accumulate(vh_wave, vbin + threadIdx.x, dims, nb, lane, live, wv);
-        }
-        double s1 = wave_sum(a1), s2 = wave_sum(a2);
-        double nz = wave_sum(az);
-        double mx = wave_max(am);
+        TileArgs t;
+        t.base = call->ev_start[c] + (tl - call->tile_start[c]) * (int64_t)kBlock * ept;
+        t.end = call->ev_start[c + 1];
+        t.ept = ept;
+        t.ctr0 = ctr0;
+        t.seed = seed;
+        t.sid = sid;
+        t.lg = lg;
+        t.nb = nb;
+        t.col = lds + threadIdx.x;
+        t.vbin = vpart ? vbin + threadIdx.x : nullptr;
+        t.vh_wave = vh_wave;
+        t.lane = lane;
+        t.np = np;
+        t.ld = ld;
+        t.p = p;
+        t.x1x2 = x1x2;
+        t.w = w;
+        t.chan_out = chan_out;
+        TileAcc acc;
+        tile(c, t, acc);
+        double s1 = wave_sum(acc.s1), s2 = wave_sum(acc.s2);
+        double nz = wave_sum(acc.zeros);
+        double mx = wave_max(acc.wmax);
         if (lane == 0) {
             red[0][wave] = s1;
             red[1][wave] = s2;
@@ -280,27 +328,47 @@ __global__ __launch_bounds__(kBlock) void k_sample(const ChannelTab* __restrict_
         __syncthreads();
         if (threadIdx.x < 4) {
             int q = threadIdx.x;
-            double acc = red[q][0];
-            for (int v = 1; v < kWaves; ++v) acc = (q == 3) ? fmax(acc, red[q][v]) : acc + red[q][v];
-            tile_stats[tile * 4 + q] = acc;
+            double a = red[q][0];
+            for (int v = 1; v < kWaves; ++v) a = (q == 3) ? fmax(a, red[q][v]) : a + red[q][v];
+            tile_stats[tl * 4 + q] = a;
         }
         __syncthreads();
         if (vpart) {
             // the tile's histogram: the wave histograms summed in wave order,
             // then cleared for the next tile
-            double* dst = vpart + tile * (int64_t)vstride;
+            double* dst = vpart + tl * (int64_t)vstride;
             const int rows = dims * nb;
             for (int i = threadIdx.x; i < rows; i += kBlock) {
-                double acc = vh[i];
+                double a = vh[i];
 #pragma unroll
-                for (int v = 1; v < kWaves; ++v) acc += vh[v * vstride + i];
-                dst[i] = acc;
+                for (int v = 1; v < kWaves; ++v) a += vh[v * vstride + i];
+                dst[i] = a;
 #pragma unroll
                 for (int v = 0; v < kWaves; ++v) vh[v * vstride + i] = 0.0;
             }
             __syncthreads();
         }
     }
+}
+
+// The fused multichannel sample with the channel tables read from device
+// memory (every channel of a context through one register and kind class).
+template <int NS, int NI, int KINDS, bool MIX>
+__global__ __launch_bounds__(kBlock) void k_sample(const ChannelTab* __restrict__ cts, const ProcessTab* __restrict__ pts,
+                                                   const double* __restrict__ grids, const int64_t* __restrict__ grid_off,
+                                                   const int32_t* __restrict__ chan_nb,
+                                                   const SampleCall* __restrict__ call, uint64_t seed, uint64_t sid,
+                                                   const uint64_t* __restrict__ ctr_dev, uint64_t ctr_off, int np,
+                                                   int64_t ld, double* __restrict__ p, double* __restrict__ x1x2,
+                                                   double* __restrict__ w, int32_t* __restrict__ chan_out,
+                                                   double* __restrict__ tile_stats, int grid_doubles,
+                                                   double* __restrict__ vpart, int vstride) {
+    sample_loop<stage_rows<NS, NI>()>(cts, grids, grid_off, chan_nb, call, seed, sid, ctr_dev, ctr_off, np, ld, p, x1x2,
+                                      w, chan_out, tile_stats, grid_doubles, vpart, vstride,
+                                      [&](int c, const TileArgs& t, TileAcc& acc) {
+                                          const ChannelTab* ct = cts + c;
+                                          sample_tile<NS, NI, KINDS, MIX>(ct, pts + ct->process, c, t, acc);
+                                      });
 }
 
 // Inverse of run_chili from the lab-frame momenta p [4][np][n] of event e:
@@ -595,57 +663,5 @@ __global__ __launch_bounds__(kBlock) void k_inverse(const ChannelTab* __restrict
             y[(int64_t)k * n + e] = outside ? __builtin_nan("") : vegas_unmap(col[k * kBlock], lg + k * (nb + 1), nb);
     }
 }
-
-// Launch of one register class: kind class `kc` picks the compiled map kinds
-// (0: integer-root power laws, 1: plus Breit-Wigner, 2: all tree kinds;
-// 3: those of class 1 with Chili channels, 4: those of class 1 with 1 -> 3
-// decays, 5: everything, (s~, t) blocks included).  Chili and 1 -> 3 decays have classes of their
-// own because compiled together they overflow the register file.
-template <int NS, int NI, bool MIX>
-hipError_t launch_chain_class(int kc, const ChainLaunch& a) {
-    constexpr int K0 = KIND_POW_INT, K1 = KIND_POW_INT | KIND_BW, K2 = KINDS_ALL;
-    constexpr int K3 = K1 | KIND_CHILI, K4 = K1 | KIND_DEC3, K5 = KINDS_ALL | KIND_CHILI | KIND_DEC3 | KIND_ST;
-    auto go = [&](auto kt) {
-        constexpr int K = decltype(kt)::value;
-        const size_t lds = a.lds + (a.sample ? sizeof(double) * stage_rows<NS, NI>() * kBlock : kQBytes) +
-                           (a.vpart ? vegas_acc_lds(a.vstride) : 0);
-        if (lds > 65536) {
-            // beyond the default 64 KiB per workgroup (gfx950 has 160 KiB per CU)
-            const void* fn = a.sample ? (const void*)k_sample<NS, NI, K, MIX> : (const void*)k_map<NS, NI, K, MIX>;
-            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e != hipSuccess) return;
-        }
-        if (a.inverse) {
-            if constexpr (!MIX) {
-                const size_t li = a.lds + sizeof(double) * stage_rows<NS, NI>() * kBlock;
-                if (li > 65536) {
-                    hipError_t e = hipFuncSetAttribute((const void*)k_inverse<NS, NI, K>,
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)li);
-                    if (e != hipSuccess) return;
-                }
-                k_inverse<NS, NI, K><<<a.grid, kBlock, li, a.stream>>>(a.cts, a.grids, a.nb, a.s_lab, a.np, a.n,
-                                                                      a.p_in, a.x1x2_in, a.y_out);
-            }
-            return;
-        }
-        if (a.sample)
-            k_sample<NS, NI, K, MIX><<<a.grid, kBlock, lds, a.stream>>>(
-                a.cts, a.pts, a.grids, a.grid_off, a.chan_nb, a.call, a.seed, a.sid, a.ctr_dev, a.ctr_off, a.np, a.n,
-                a.p, a.x1x2, a.w, a.chan, a.tile_stats, (int)(a.lds / sizeof(double)), a.vpart, a.vstride);
-        else
-            k_map<NS, NI, K, MIX><<<a.grid, kBlock, lds, a.stream>>>(a.cts, a.pts, a.grids, a.nb, a.s_lab, a.np, a.n,
-                                                                         a.y, a.p, a.x1x2, a.jac, a.w);
-    };
-    if (kc == 0) go(std::integral_constant<int, K0>{});
-    else if (kc <= 1) go(std::integral_constant<int, K1>{});
-    else if (kc == 2) go(std::integral_constant<int, K2>{});
-    else if (kc == 3) go(std::integral_constant<int, K3>{});
-    else if (kc == 4) go(std::integral_constant<int, K4>{});
-    else go(std::integral_constant<int, K5>{});
-    return hipGetLastError();
-}
-
-#define MSX_INSTANTIATE_CHAIN(NS, NI, MIX) \
-    template hipError_t launch_chain_class<NS, NI, MIX>(int kc, const ChainLaunch& a);
 
 }  // namespace msx

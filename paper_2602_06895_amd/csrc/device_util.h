@@ -2,8 +2,10 @@
 // and deterministic wave reductions.
 #pragma once
 
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#endif
 
 #include "tables.h"
 

@@ -1,0 +1,169 @@
+// Run-time specialisation of the fused multichannel sample.
+//
+// The kernel is the source of k_sample (sample_loop and sample_tile in
+// chain_kernels.h), compiled with the HIP run-time compiler for one
+// context's channels: every channel's and process's table becomes a
+// constexpr byte image, so the compiler folds the table reads, the map-kind
+// and operation-count branches and the slot indices of the chain into
+// constants, unrolls each channel's operations and keeps only the momentum
+// slots that are still live.  The arithmetic is the same source and the
+// library is compiled without floating-point contraction, so the results
+// are bit-identical to the class kernel's; only the code is smaller (no
+// scratch, fewer registers, more waves per SIMD) and runs fewer
+// instructions.  The headers come from jit_sources.cpp, which the build
+// generates from the kernel headers.
+#include "jit.h"
+
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <vector>
+
+#include "tables.h"
+
+namespace msx {
+namespace jit_src {
+extern const int kHeaderCount;
+extern const char* const kHeaderNames[];
+extern const char* const kHeaderTexts[];
+}  // namespace jit_src
+
+namespace {
+
+// (NS, NI) register class of a channel, as the class kernels pick it
+void reg_class_of(const ChannelTab& t, int& ns, int& ni) {
+    if (t.n_slots <= 6 && t.n_inv <= 4) {
+        ns = 6;
+        ni = 4;
+    } else if (t.n_slots <= 10 && t.n_inv <= 8) {
+        ns = 10;
+        ni = 8;
+    } else {
+        ns = 14;
+        ni = 8;
+    }
+}
+
+void emit_bytes(std::string& s, const char* name, int index, const void* p, size_t n) {
+    char head[96];
+    std::snprintf(head, sizeof head, "alignas(16) constexpr unsigned char %s%d[%zu] = {", name, index, n);
+    s += head;
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) {
+        char v[8];
+        std::snprintf(v, sizeof v, i ? ",%u" : "%u", (unsigned)b[i]);
+        s += v;
+    }
+    s += "};\n";
+}
+
+std::string sample_source(const Compiled& comp, int mixed, int& rows) {
+    std::string s =
+        "using __hip_internal::int32_t;\nusing __hip_internal::uint32_t;\nusing __hip_internal::int64_t;\n"
+        "using __hip_internal::uint64_t;\nusing __hip_internal::uint8_t;\n#include \"chain_kernels.h\"\n"
+        "namespace msx {\nnamespace spec {\n";
+    const int C = (int)comp.chans.size();
+    rows = kMaxUniq + 1;
+    for (int c = 0; c < C; ++c) {
+        emit_bytes(s, "chan", c, &comp.chans[c], sizeof(ChannelTab));
+        int ns, ni;
+        reg_class_of(comp.chans[c], ns, ni);
+        rows = std::max(rows, ns + ni + 1);
+    }
+    for (size_t q = 0; q < comp.procs.size(); ++q) emit_bytes(s, "proc", (int)q, &comp.procs[q], sizeof(ProcessTab));
+    s += "}  // namespace spec\n}  // namespace msx\n";
+    s += "extern \"C\" __global__ __launch_bounds__(msx::kBlock) void msx_jit_sample(\n"
+         "    const msx::ChannelTab* __restrict__ cts, const msx::ProcessTab* __restrict__ pts,\n"
+         "    const double* __restrict__ grids, const int64_t* __restrict__ grid_off,\n"
+         "    const int32_t* __restrict__ chan_nb, const msx::SampleCall* __restrict__ call, uint64_t seed,\n"
+         "    uint64_t sid, const uint64_t* __restrict__ ctr_dev, uint64_t ctr_off, int np, int64_t ld,\n"
+         "    double* __restrict__ p, double* __restrict__ x1x2, double* __restrict__ w,\n"
+         "    int32_t* __restrict__ chan_out, double* __restrict__ tile_stats, int grid_doubles,\n"
+         "    double* __restrict__ vpart, int vstride) {\n"
+         "    using namespace msx;\n";
+    s += "    sample_loop<" + std::to_string(rows) +
+         ">(cts, grids, grid_off, chan_nb, call, seed, sid, ctr_dev, ctr_off, np, ld, p, x1x2, w, chan_out,\n"
+         "        tile_stats, grid_doubles, vpart, vstride, [&](int c, const TileArgs& t, TileAcc& acc) {\n"
+         "        switch (c) {\n";
+    for (int c = 0; c < C; ++c) {
+        int ns, ni;
+        reg_class_of(comp.chans[c], ns, ni);
+        const std::string cs = std::to_string(c);
+        s += "        case " + cs + ": sample_tile<" + std::to_string(ns) + ", " + std::to_string(ni) + ", " +
+             std::to_string(comp.chans[c].kinds) + ", " + (mixed ? "true" : "false") +
+             ">(reinterpret_cast<const ChannelTab*>(spec::chan" + cs +
+             "), reinterpret_cast<const ProcessTab*>(spec::proc" + std::to_string(comp.chans[c].process) + "), " +
+             cs + ", t, acc); break;\n";
+    }
+    s += "        default: break;\n        }\n    });\n}\n";
+    return s;
+}
+
+}  // namespace
+
+bool jit_build_sample(const Compiled& comp, int mixed, int device, JitSample& out, std::string& err) {
+    int rows = 0;
+    const std::string src = sample_source(comp, mixed, rows);
+    hipDeviceProp_t prop;
+    hipError_t he = hipGetDeviceProperties(&prop, device);
+    if (he != hipSuccess) {
+        err = std::string("hipGetDeviceProperties: ") + hipGetErrorString(he);
+        return false;
+    }
+    const std::string arch = std::string("--offload-arch=") + prop.gcnArchName;
+    // the library's own flags for the FP64 path: no contraction, no packed FP32
+    const char* opts[] = {arch.c_str(), "-O3", "-std=c++17", "-ffp-contract=off", "-Xclang", "-target-feature",
+                          "-Xclang", "-packed-fp32-ops"};
+    hiprtcProgram prog;
+    hiprtcResult r = hiprtcCreateProgram(&prog, src.c_str(), "msx_jit_sample.hip", jit_src::kHeaderCount,
+                                         jit_src::kHeaderTexts, jit_src::kHeaderNames);
+    if (r != HIPRTC_SUCCESS) {
+        err = std::string("hiprtcCreateProgram: ") + hiprtcGetErrorString(r);
+        return false;
+    }
+    r = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
+    if (r != HIPRTC_SUCCESS) {
+        size_t n = 0;
+        std::string log;
+        if (hiprtcGetProgramLogSize(prog, &n) == HIPRTC_SUCCESS && n > 1) {
+            log.resize(n);
+            (void)hiprtcGetProgramLog(prog, &log[0]);
+        }
+        (void)hiprtcDestroyProgram(&prog);
+        err = std::string("hiprtcCompileProgram: ") + hiprtcGetErrorString(r) + "\n" + log.substr(0, 4000);
+        return false;
+    }
+    size_t code_size = 0;
+    std::vector<char> code;
+    if ((r = hiprtcGetCodeSize(prog, &code_size)) == HIPRTC_SUCCESS) {
+        code.resize(code_size);
+        r = hiprtcGetCode(prog, code.data());
+    }
+    (void)hiprtcDestroyProgram(&prog);
+    if (r != HIPRTC_SUCCESS) {
+        err = std::string("hiprtcGetCode: ") + hiprtcGetErrorString(r);
+        return false;
+    }
+    JitSample j;
+    if ((he = hipModuleLoadData(&j.module, code.data())) != hipSuccess) {
+        err = std::string("hipModuleLoadData: ") + hipGetErrorString(he);
+        return false;
+    }
+    if ((he = hipModuleGetFunction(&j.fn, j.module, "msx_jit_sample")) != hipSuccess) {
+        err = std::string("hipModuleGetFunction: ") + hipGetErrorString(he);
+        (void)hipModuleUnload(j.module);
+        return false;
+    }
+    j.rows = rows;
+    out = j;
+    return true;
+}
+
+void jit_release(JitSample& j) {
+    if (j.module) (void)hipModuleUnload(j.module);
+    j = JitSample{};
+}
+
+}  // namespace msx

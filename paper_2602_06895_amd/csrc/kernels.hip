@@ -571,6 +571,11 @@ int grid_for(int64_t n, int cap) {
 
 // Register class -> the instantiation unit compiled for it.
 hipError_t launch_chain(int rc, int kc, int mixed, const ChainLaunch& a) {
+    if (a.inverse) {
+        if (rc == 0) return launch_inverse_class<6, 4>(kc, a);
+        if (rc == 1) return launch_inverse_class<10, 8>(kc, a);
+        return launch_inverse_class<14, 8>(kc, a);
+    }
     if (mixed) {
         if (rc == 0) return launch_chain_class<6, 4, true>(kc, a);
         if (rc == 1) return launch_chain_class<10, 8, true>(kc, a);
@@ -736,33 +741,43 @@ hipError_t launch_sample(const ChannelTab* cts, const ProcessTab* pts, const dou
                          int kinds, int mixed, size_t lds_bytes, uint64_t seed, uint64_t sid, const uint64_t* ctr_dev,
                          uint64_t ctr_off, int np, int64_t ld, double* p, double* x1x2, double* w, int32_t* chan,
                          double* tile_stats, double* stats, int grid, hipStream_t s, double* vpart, int vstride,
-                         const int64_t* hist_off, int64_t hist_total, double* hist) {
-    ChainLaunch a{};
-    a.sample = true;
-    a.lds = lds_bytes;
-    a.grid = std::max(grid, 1);
-    a.stream = s;
-    a.cts = cts;
-    a.pts = pts;
-    a.grids = grids;
-    a.grid_off = grid_off;
-    a.chan_nb = chan_nb;
-    a.call = call;
-    a.seed = seed;
-    a.sid = sid;
-    a.ctr_dev = ctr_dev;
-    a.ctr_off = ctr_off;
-    a.np = np;
-    a.n = ld;
-    a.p = p;
-    a.x1x2 = x1x2;
-    a.w = w;
-    a.chan = chan;
-    a.tile_stats = tile_stats;
-    a.vpart = vpart;
-    a.vstride = vstride;
-    hipError_t err = launch_chain(reg_class(max_slots, max_inv), kind_class(kinds), mixed, a);
-    if (err != hipSuccess) return err;
+                         const int64_t* hist_off, int64_t hist_total, double* hist, const JitSample* jit) {
+    if (jit && jit->fn) {
+        const size_t lds = lds_bytes + sizeof(double) * (size_t)jit->rows * kBlock + (vpart ? vegas_acc_lds(vstride) : 0);
+        int grid_doubles = (int)(lds_bytes / sizeof(double));
+        void* args[] = {&cts, &pts, &grids, &grid_off, &chan_nb, &call, &seed, &sid, &ctr_dev, &ctr_off, &np, &ld,
+                        &p, &x1x2, &w, &chan, &tile_stats, &grid_doubles, &vpart, &vstride};
+        hipError_t err = hipModuleLaunchKernel(jit->fn, (unsigned)std::max(grid, 1), 1, 1, kBlock, 1, 1, (unsigned)lds, s,
+                                               args, nullptr);
+        if (err != hipSuccess) return err;
+    } else {
+        ChainLaunch a{};
+        a.sample = true;
+        a.lds = lds_bytes;
+        a.grid = std::max(grid, 1);
+        a.stream = s;
+        a.cts = cts;
+        a.pts = pts;
+        a.grids = grids;
+        a.grid_off = grid_off;
+        a.chan_nb = chan_nb;
+        a.call = call;
+        a.seed = seed;
+        a.sid = sid;
+        a.ctr_dev = ctr_dev;
+        a.ctr_off = ctr_off;
+        a.np = np;
+        a.n = ld;
+        a.p = p;
+        a.x1x2 = x1x2;
+        a.w = w;
+        a.chan = chan;
+        a.tile_stats = tile_stats;
+        a.vpart = vpart;
+        a.vstride = vstride;
+        hipError_t err = launch_chain(reg_class(max_slots, max_inv), kind_class(kinds), mixed, a);
+        if (err != hipSuccess) return err;
+    }
     k_stats_final<<<n_chan, kBlock, 0, s>>>(call, tile_stats, stats);
     if (vpart && hist_total > 0) {
         const int64_t g = (hist_total + kBlock - 1) / kBlock;

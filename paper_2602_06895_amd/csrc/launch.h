@@ -49,6 +49,9 @@ struct ChainLaunch {
 // the chain_*.hip instantiation units.
 template <int NS, int NI, bool MIX>
 hipError_t launch_chain_class(int kind_class, const ChainLaunch& a);
+// The inverse map of one register class (FP64); the inverse_*.hip units.
+template <int NS, int NI>
+hipError_t launch_inverse_class(int kind_class, const ChainLaunch& a);
 
 hipError_t launch_uniform(uint64_t seed, uint64_t sid, uint64_t e0, int64_t n, int d, double* y, hipStream_t s);
 
@@ -85,6 +88,15 @@ hipError_t launch_density_add(double* g, const double* jac, double alpha, int64_
 hipError_t launch_weight(const ChannelTab* ct, const ProcessTab* pt, int mixed, int np, int64_t n, const double* p,
                          const double* x1x2, const double* jac, double* w, double* alpha, hipStream_t s);
 
+// A fused-sample kernel compiled at run time for one context's channels,
+// with their channel and process tables as compile-time constants (jit.cpp);
+// it takes k_sample's arguments.  rows: height of its LDS staging column.
+struct JitSample {
+    hipModule_t module = nullptr;
+    hipFunction_t fn = nullptr;
+    int rows = 0;
+};
+
 // Fused multichannel sample.  `call` is the device copy of the call table;
 // `max_tiles` bounds its n_tiles (for the per-channel statistics pass);
 // `ld` is the row stride of the outputs (>= the events of the call).
@@ -92,14 +104,15 @@ hipError_t launch_weight(const ChannelTab* ct, const ProcessTab* pt, int mixed, 
 // histogram (sum w^2 per bin of every dimension) into per-tile partials
 // vpart [tiles][vstride] (vstride >= dims x bins of every channel), and a
 // second kernel adds them, tiles in order, to hist at hist_off[c] (device
-// array, per channel).
+// array, per channel).  With jit != NULL the launch runs that kernel instead
+// of the register / kind class kernel of (max_slots, max_inv, kinds).
 hipError_t launch_sample(const ChannelTab* cts, const ProcessTab* pts, const double* grids, const int64_t* grid_off,
                          const int32_t* chan_nb, const SampleCall* call, int n_chan, int max_slots, int max_inv,
                          int kinds, int mixed, size_t lds_bytes, uint64_t seed, uint64_t sid, const uint64_t* ctr_dev,
                          uint64_t ctr_off, int np, int64_t ld, double* p, double* x1x2, double* w, int32_t* chan,
                          double* tile_stats, double* stats, int grid, hipStream_t s, double* vpart = nullptr,
                          int vstride = 0, const int64_t* hist_off = nullptr, int64_t hist_total = 0,
-                         double* hist = nullptr);
+                         double* hist = nullptr, const JitSample* jit = nullptr);
 // Dynamic LDS bytes of a sample launch with VEGAS accumulation (grid area
 // lds_bytes, vstride doubles per wave histogram) for the register class of
 // (max_slots, max_inv).

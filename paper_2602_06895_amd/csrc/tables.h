@@ -16,7 +16,9 @@
 // slot NS + c, so the tables do not depend on the kernel's NS.
 #pragma once
 
+#ifndef __HIPCC_RTC__
 #include <stdint.h>
+#endif
 
 namespace msx {
 

@@ -1,0 +1,268 @@
+"""The channel-specialised fused sample (msx_specialize): the kernel compiled
+at run time with a context's channel and process tables as constants gives,
+in FP64, bit-identical momenta, momentum fractions, weights, channel labels,
+statistics and VEGAS histograms to the class kernel, on every kind of
+channel (s-channel trees with Breit-Wigner propagators, t-channel chains,
+Chili, 1 -> 3 decays, (s~, t) blocks, FastRambo), through every sample entry
+point (host counts, device counts, captured graph, the allocation-free
+call); and it meets the oracle's per-event bound on its own (section 2.2's
+chain, eq. multi-channel-mg's weight).
+
+In mixed precision the two kernels are not bit-identical (FP32 steps on
+table constants can be evaluated at compile time, exactly, where the class
+kernel runs the hardware's FP32 approximations of exp2, log2 or the
+reciprocal), so events move by FP32 roundings.  There the specialised
+kernel is held to the mixed mode's error statement against the oracle and
+to FP32-rounding distance from the class kernel."""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from parity import compare
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    if not t.cuda.is_available():
+        pytest.skip("needs a GPU")
+    return t
+
+
+def _dec3():
+    d = W.c3_ttbar6()
+    d["channels"] = [{"s": {"d": [{"d": [1, 2, 3], "m": 173.0, "w": 1.5, "order": 1},
+                                  {"d": [4, 5, 6], "m": 173.0, "w": 1.5, "order": 2}]}}]
+    return d
+
+
+def _chili_beside_diagrams():
+    d = W.c2_pp4j()
+    d["channels"] = d["channels"] + [{"chili": True}]
+    return d
+
+
+def _st():
+    d = W.c2_pp4j()
+    d["channels"] = [{"t_chain": [1, 2, 3, 4], "t_order": "AA", "st": True},
+                     {"t_chain": [1, 2, 4, 3], "t_order": "AB", "st": True},
+                     {"t_chain": [4, 3, 2, 1], "t_order": "BB"}]
+    return d
+
+
+CASES = {
+    "pp4j": W.c2_pp4j,
+    "ttbar6": W.c3_ttbar6,
+    "ttbar6_dec3": _dec3,
+    "pp4j_chili": _chili_beside_diagrams,
+    "pp4j_st": _st,
+    "rambo_ee6": lambda: W.rambo_process(6),
+    "multichannel24": lambda: W.c4_context()[0],
+}
+
+
+def _counts(n_chan, seed):
+    rng = np.random.default_rng(seed)
+    c = rng.integers(0, 30000, size=n_chan).astype(np.int64)
+    c[0] = 70001  # several tiles and a ragged tail
+    if n_chan > 2:
+        c[1], c[2] = 0, 1
+    return c
+
+
+def _bits(t):
+    """The tensor's bit patterns (so that -0.0 and 0.0 differ)."""
+    import torch
+
+    return t.contiguous().view(-1).view(torch.int64 if t.element_size() == 8 else torch.int32).cpu().numpy()
+
+
+def _run(torch, desc, precision, specialize, counts, flags, ept, raw=False):
+    from paper_2602_06895_amd import Context
+
+    ctx = Context(desc, precision=precision)
+    ctx.set_launch(ept, 0)
+    if specialize:
+        ctx.specialize()
+        assert ctx.specialized
+    out = ctx.sample(counts, seed=11, stream_id=4, counter_offset=123, flags=flags)
+    if flags:
+        ctx.vegas_update(alpha=0.5)
+    torch.cuda.synchronize()
+    res = {k: (v.clone() if raw else _bits(v)) for k, v in out.items() if v is not None}
+    res["stats"] = ctx.stats()
+    res["grids"] = [ctx.get_grid(c) for c in range(ctx.n_channels)] if flags else []
+    ctx.close()
+    return res
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_bit_identical_to_class_kernel(torch, case):
+    from paper_2602_06895_amd import FP64, SAMPLE_ACCUMULATE_VEGAS, Context
+
+    desc = CASES[case]()
+    prec = FP64
+    probe = Context(desc)
+    n_chan = probe.n_channels
+    probe.close()
+    counts = _counts(n_chan, 3)
+    flags = SAMPLE_ACCUMULATE_VEGAS if case != "multichannel24" else 0
+    a = _run(torch, desc, prec, False, counts, flags, 2)
+    b = _run(torch, desc, prec, True, counts, flags, 2)
+    for k in ("p", "w", "x1x2", "chan"):
+        if k in a:
+            assert np.array_equal(a[k], b[k]), f"{case}: {k} differs ({np.sum(a[k] != b[k])} entries)"
+    assert np.array_equal(a["stats"], b["stats"]), f"{case}: statistics differ"
+    for c, (ga, gb) in enumerate(zip(a["grids"], b["grids"])):
+        assert np.array_equal(ga, gb), f"{case}: VEGAS grid of channel {c} differs after accumulation"
+
+
+def test_device_counts_graph_and_noalloc(torch):
+    """Device-count launch, a captured graph (two replays, the counter
+    advancing) and the allocation-free call of a specialised context equal
+    the class kernel's eager sample bit for bit."""
+    from paper_2602_06895_amd import SAMPLE_ADVANCE_COUNTER, Context
+
+    desc = W.c2_pp4j()
+    counts = _counts(8, 5)
+    N = int(counts.sum())
+    ref = Context(desc)
+    ref.set_launch(1, 0)
+    outs = [ref.sample(counts, seed=2, stream_id=1, counter_offset=1000 + k * N) for k in range(2)]
+    torch.cuda.synchronize()
+    want = [{k: _bits(v) for k, v in o.items() if v is not None} for o in outs]
+    ctx = Context(desc)
+    ctx.set_launch(1, 0)
+    ctx.specialize()
+    cap = N + 4096
+    dc = torch.from_numpy(counts).to(ctx.device)
+    # device counts
+    buf = ctx.sample_buffers(cap)
+    off = torch.tensor([1000], dtype=torch.int64, device=ctx.device)
+    ctx.sample_device(dc, 2, 1, off, buf)
+    torch.cuda.synchronize()
+    for k in want[0]:
+        got = buf[k][..., :N]
+        assert np.array_equal(_bits(got), want[0][k]), f"device counts: {k}"
+    # graph with its own advancing counter: replay k draws events 1000 + k N
+    gbuf = ctx.sample_buffers(cap)
+    goff = torch.tensor([1000], dtype=torch.int64, device=ctx.device)
+    g = ctx.sample_graph(dc, 2, 1, goff, gbuf, flags=SAMPLE_ADVANCE_COUNTER)
+    for rep in range(2):
+        g.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(_bits(gbuf["w"][:N]), want[rep]["w"]), f"graph replay {rep}"
+        assert np.array_equal(_bits(gbuf["p"][:, :, :N]), want[rep]["p"]), f"graph replay {rep}: momenta"
+    g.close()
+    # allocation-free call
+    nb = ctx.sample_buffers(N)
+    s = ctx._stream()
+    c = np.ascontiguousarray(counts)
+    st = ctx.L.msx_sample_noalloc(ctx.h, c.ctypes.data, 2, 1, 1000, nb["p"].data_ptr(), nb["x1x2"].data_ptr(),
+                                  nb["w"].data_ptr(), nb["chan"].data_ptr(), s)
+    assert st == 0, ctx.L.msx_last_error(ctx.h)
+    torch.cuda.synchronize()
+    assert np.array_equal(_bits(nb["w"]), want[0]["w"])
+    assert np.array_equal(_bits(nb["chan"]), want[0]["chan"])
+    ctx.close()
+    ref.close()
+
+
+def test_switch_off_and_on(torch):
+    from paper_2602_06895_amd import Context
+
+    ctx = Context(W.c3_ttbar6())
+    assert not ctx.specialized
+    ctx.specialize()
+    ctx.specialize()  # already built: only switches
+    assert ctx.specialized
+    a = ctx.sample(np.array([5000]), seed=1)
+    ctx.specialize(False)
+    assert not ctx.specialized
+    b = ctx.sample(np.array([5000]), seed=1)
+    torch.cuda.synchronize()
+    assert np.array_equal(_bits(a["w"]), _bits(b["w"]))
+    ctx.close()
+
+
+@pytest.mark.parametrize("case", ["ttbar6", "pp4j"])
+def test_specialised_sample_meets_oracle_bound(torch, case):
+    """Independent of the class kernel: the specialised sample's events
+    against the oracle, per event within max(1e-12, 100 x its forward-error
+    estimate), every channel: a window of a 1e6-event channel and the
+    ragged tail of 3001-event ones."""
+    from paper_2602_06895_amd import Context
+
+    desc = CASES[case]()
+    ctx = Context(desc)
+    ctx.specialize()
+    orc = oracle.Process(desc)
+    counts = np.full(ctx.n_channels, 3001, dtype=np.int64)
+    counts[0] = 1_000_003
+    out = ctx.sample(counts, seed=21, stream_id=2, counter_offset=9)
+    torch.cuda.synchronize()
+    got = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+    off = 0
+    rng = np.random.default_rng(4)
+    for c, k in enumerate(counts):
+        k = int(k)
+        start = int(rng.integers(0, k - 3000)) if k > 3000 else 0
+        m = min(k, 3000)
+        sl = slice(off + start, off + start + m)
+        y = W.philox_uniforms(21, 2, 9 + off + start, m, ctx.dims[c])
+        ref = orc.map(c, y, orc.uniform_grid(c))
+        fe = orc.forward_error(c, y, orc.uniform_grid(c), ref=ref)
+        x = got["x1x2"][:, sl] if got.get("x1x2") is not None else None
+        compare({"w": got["w"][sl], "p": got["p"][:, :, sl], "x1x2": x}, ref, fe, hadronic=ctx.hadronic[c],
+                label=f"specialised {case} ch{c}")
+        assert np.all(got["chan"][sl] == c)
+        off += k
+    ctx.close()
+
+
+@pytest.mark.parametrize("case", ["ttbar6", "pp4j", "pp4j_chili"])
+def test_mixed_precision(torch, case):
+    """Mixed precision: the specialised sample against the oracle under the
+    mode's error statement (the bounds of the mixed-precision tests), and
+    against the class kernel's mixed sample under the same bounds (two
+    evaluations that differ by FP32 roundings; identical on t tbar)."""
+    from paper_2602_06895_amd import MIXED
+    from paper_2602_06895_amd.report import precision_error
+
+    desc = CASES[case]()
+    orc = oracle.Process(desc)
+    n_chan = len(orc.dims)
+    counts = np.full(n_chan, 20000, dtype=np.int64)
+    counts[0] = 100_000
+    a = _run(torch, desc, MIXED, False, counts, 0, 1, raw=True)
+    b = _run(torch, desc, MIXED, True, counts, 0, 1, raw=True)
+    assert torch.equal(a["chan"], b["chan"])
+    npm = b["p"].shape[1]
+    off = 0
+    for c, k in enumerate(counts):
+        k = int(k)
+        sl = slice(off, off + k)
+        y = W.philox_uniforms(11, 4, 123 + off, k, orc.dims[c])
+        ref = orc.map(c, y, orc.uniform_grid(c))
+        npc = ref["p"].shape[1]
+        got_p = b["p"][:, :npc, sl].contiguous()
+        e = precision_error(got_p, b["w"][sl], torch.from_numpy(ref["p"]).cuda(), torch.from_numpy(ref["w"]).cuda(),
+                            npc)
+        assert e["momenta_median"] < 1e-6 and e["momenta_p99"] < 1e-5 and e["momenta_max"] < 1e-3, (c, e)
+        assert abs(e["integral_shift_sigma"]) < 0.1, (c, e)
+        assert e["weight_median"] < 2e-4 and e["weight_p99"] < 3e-2, (c, e)
+        assert e["cut_flips"] <= max(2, 1e-4 * k), (c, e)
+        # specialised vs class kernel, both mixed: FP32 roundings apart
+        d = precision_error(got_p, b["w"][sl], a["p"][:, :npc, sl].contiguous(), a["w"][sl], npc)
+        short = {k: float(f"{v:.3g}") for k, v in d.items()}
+        print(case, c, "vs class kernel", short)
+        assert d["momenta_median"] < 1e-6 and d["momenta_p99"] < 1e-5 and d["momenta_max"] < 1e-3, (c, short)
+        assert d["weight_median"] < 2e-4 and d["weight_p99"] < 3e-2, (c, short)
+        assert abs(d["integral_shift_sigma"]) < 0.1 and d["cut_flips"] <= max(2, 1e-4 * k), (c, short)
+        off += k
+    assert npm >= 2

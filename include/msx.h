@@ -326,8 +326,10 @@ msx_status msx_autotune(msx_ctx* ctx, const int64_t* counts, uint64_t seed, int3
  * later calls only switch.  on == 0 switches launches back to the default
  * kernel; the compiled one stays loaded until msx_destroy (graphs captured
  * with it keep working).  Errors: MSX_ERR_DEVICE with the compiler's log
- * when the run-time compiler or the module load fails (the context keeps the
- * default kernel). */
+ * when the run-time compiler or the module load fails; MSX_ERR_UNSUPPORTED
+ * when the compiled kernel would spill registers to scratch (many channels
+ * in one kernel), since it would then be slower than the default one.  In
+ * both cases the context keeps the default kernel. */
 msx_status msx_specialize(msx_ctx* ctx, int32_t on);
 
 /* Copy the accumulated per-channel statistics to host out [n_channels][5]:

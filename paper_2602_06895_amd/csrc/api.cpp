@@ -336,8 +336,9 @@ msx_status msx_specialize(msx_ctx* ctx, int32_t on) {
     if (!ctx->jit.fn) {
         if (msx_status st = set_device(ctx)) return st;
         std::string err;
-        if (!jit_build_sample(ctx->comp, ctx->mixed, ctx->device, ctx->jit, err))
-            return fail(ctx, MSX_ERR_DEVICE, "specialised sample kernel: " + err);
+        bool spills = false;
+        if (!jit_build_sample(ctx->comp, ctx->mixed, ctx->device, ctx->jit, err, spills))
+            return fail(ctx, spills ? MSX_ERR_UNSUPPORTED : MSX_ERR_DEVICE, "specialised sample kernel: " + err);
     }
     ctx->jit_on = true;
     return MSX_OK;

@@ -251,28 +251,30 @@ __device__ __forceinline__ void sample_tile(const ChannelTab* __restrict__ ct, c
     }
 }
 
-// The persistent loop of the fused sample: blocks stride over the call's
-// tiles (each tile kBlock * ept events of one channel), load a channel's
-// VEGAS grid into LDS when the channel changes, run `tile` on the tile's
-// events and write its statistics and (vpart) VEGAS histogram.  ROWS is the
-// staging column's height; the grid follows it in the dynamic LDS.
-template <int ROWS, class Tile>
+// The persistent loop of the fused sample: block b takes the call's tiles
+// b, b + gridDim.x, ... (each tile kBlock * ept events of one channel), one
+// channel after the other: `channels(run)` calls run(c, tile) for every
+// channel c in order, and run loads c's VEGAS grid into LDS, runs
+// tile(t, acc) on each of the block's tiles of c and writes the tile's
+// statistics and (vpart) VEGAS histogram.  ROWS is the staging column's
+// height; the grid follows it in the dynamic LDS.  A kernel compiled for
+// fixed channels passes one run call per channel, each with its own tile
+// function, so every channel gets a loop of its own code.
+template <int ROWS, class Channels>
 __device__ __forceinline__ void sample_loop(const ChannelTab* __restrict__ cts, const double* __restrict__ grids,
                                             const int64_t* __restrict__ grid_off, const int32_t* __restrict__ chan_nb,
                                             const SampleCall* __restrict__ call, uint64_t seed, uint64_t sid,
                                             const uint64_t* __restrict__ ctr_dev, uint64_t ctr_off, int np, int64_t ld,
                                             double* __restrict__ p, double* __restrict__ x1x2, double* __restrict__ w,
                                             int32_t* __restrict__ chan_out, double* __restrict__ tile_stats,
-                                            int grid_doubles, double* __restrict__ vpart, int vstride, Tile&& tile) {
+                                            int grid_doubles, double* __restrict__ vpart, int vstride,
+                                            Channels&& channels) {
     extern __shared__ double lds[];
     double* lg = lds + ROWS * kBlock;
     __shared__ double red[4][kWaves];
-    int cur = -1;
-    int nb = 0, dims = 0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t n_tiles = call->n_tiles;
-    const int n_chan = call->n_chan;
     const int ept = call->ept;
+    const int64_t G = gridDim.x;
     const uint64_t ctr0 = ctr_dev ? *ctr_dev : ctr_off;
     // VEGAS histogram accumulation (vpart != NULL): one private histogram
     // [dims][nb] per wave after the grid, then the events' bin numbers as
@@ -283,72 +285,74 @@ __device__ __forceinline__ void sample_loop(const ChannelTab* __restrict__ cts, 
     if (vpart) {
         for (int i = threadIdx.x; i < kWaves * vstride; i += kBlock) vh[i] = 0.0;
     }
-    for (int64_t tl = blockIdx.x; tl < n_tiles; tl += gridDim.x) {
-        int c = 0;
-        while (c + 1 < n_chan && call->tile_start[c + 1] <= tl) ++c;
-        if (c != cur) {
-            __syncthreads();
-            nb = chan_nb[c];
-            dims = cts[c].dims;
-            const double* g = grids + grid_off[c];
-            for (int i = threadIdx.x; i < dims * (nb + 1); i += blockDim.x) lg[i] = g[i];
-            __syncthreads();
-            cur = c;
-        }
-        TileArgs t;
-        t.base = call->ev_start[c] + (tl - call->tile_start[c]) * (int64_t)kBlock * ept;
-        t.end = call->ev_start[c + 1];
-        t.ept = ept;
-        t.ctr0 = ctr0;
-        t.seed = seed;
-        t.sid = sid;
-        t.lg = lg;
-        t.nb = nb;
-        t.col = lds + threadIdx.x;
-        t.vbin = vpart ? vbin + threadIdx.x : nullptr;
-        t.vh_wave = vh_wave;
-        t.lane = lane;
-        t.np = np;
-        t.ld = ld;
-        t.p = p;
-        t.x1x2 = x1x2;
-        t.w = w;
-        t.chan_out = chan_out;
-        TileAcc acc;
-        tile(c, t, acc);
-        double s1 = wave_sum(acc.s1), s2 = wave_sum(acc.s2);
-        double nz = wave_sum(acc.zeros);
-        double mx = wave_max(acc.wmax);
-        if (lane == 0) {
-            red[0][wave] = s1;
-            red[1][wave] = s2;
-            red[2][wave] = nz;
-            red[3][wave] = mx;
-        }
+    auto run = [&](int c, auto&& tile) {
+        const int64_t t0 = call->tile_start[c], t1 = call->tile_start[c + 1];
+        // this block's first tile of the channel
+        int64_t tl = t0 + ((((int64_t)blockIdx.x - t0) % G) + G) % G;
+        if (tl >= t1) return;
+        const int nb = chan_nb[c];
+        const int dims = cts[c].dims;
         __syncthreads();
-        if (threadIdx.x < 4) {
-            int q = threadIdx.x;
-            double a = red[q][0];
-            for (int v = 1; v < kWaves; ++v) a = (q == 3) ? fmax(a, red[q][v]) : a + red[q][v];
-            tile_stats[tl * 4 + q] = a;
-        }
+        const double* g = grids + grid_off[c];
+        for (int i = threadIdx.x; i < dims * (nb + 1); i += blockDim.x) lg[i] = g[i];
         __syncthreads();
-        if (vpart) {
-            // the tile's histogram: the wave histograms summed in wave order,
-            // then cleared for the next tile
-            double* dst = vpart + tl * (int64_t)vstride;
-            const int rows = dims * nb;
-            for (int i = threadIdx.x; i < rows; i += kBlock) {
-                double a = vh[i];
-#pragma unroll
-                for (int v = 1; v < kWaves; ++v) a += vh[v * vstride + i];
-                dst[i] = a;
-#pragma unroll
-                for (int v = 0; v < kWaves; ++v) vh[v * vstride + i] = 0.0;
+        for (; tl < t1; tl += G) {
+            TileArgs t;
+            t.base = call->ev_start[c] + (tl - t0) * (int64_t)kBlock * ept;
+            t.end = call->ev_start[c + 1];
+            t.ept = ept;
+            t.ctr0 = ctr0;
+            t.seed = seed;
+            t.sid = sid;
+            t.lg = lg;
+            t.nb = nb;
+            t.col = lds + threadIdx.x;
+            t.vbin = vpart ? vbin + threadIdx.x : nullptr;
+            t.vh_wave = vh_wave;
+            t.lane = lane;
+            t.np = np;
+            t.ld = ld;
+            t.p = p;
+            t.x1x2 = x1x2;
+            t.w = w;
+            t.chan_out = chan_out;
+            TileAcc acc;
+            tile(t, acc);
+            double s1 = wave_sum(acc.s1), s2 = wave_sum(acc.s2);
+            double nz = wave_sum(acc.zeros);
+            double mx = wave_max(acc.wmax);
+            if (lane == 0) {
+                red[0][wave] = s1;
+                red[1][wave] = s2;
+                red[2][wave] = nz;
+                red[3][wave] = mx;
             }
             __syncthreads();
+            if (threadIdx.x < 4) {
+                int q = threadIdx.x;
+                double a = red[q][0];
+                for (int v = 1; v < kWaves; ++v) a = (q == 3) ? fmax(a, red[q][v]) : a + red[q][v];
+                tile_stats[tl * 4 + q] = a;
+            }
+            __syncthreads();
+            if (vpart) {
+                // the tile's histogram: the wave histograms summed in wave
+                // order, then cleared for the next tile
+                double* dst = vpart + tl * (int64_t)vstride;
+                const int rows = dims * nb;
+                for (int i = threadIdx.x; i < rows; i += kBlock) {
+                    double a = vh[i];
+#pragma unroll
+                    for (int v = 1; v < kWaves; ++v) a += vh[v * vstride + i];
+                    dst[i] = a;
+#pragma unroll
+                    for (int v = 0; v < kWaves; ++v) vh[v * vstride + i] = 0.0;
+                }
+                __syncthreads();
+            }
         }
-    }
+    };
+    channels(run);
 }
 
 // The fused multichannel sample with the channel tables read from device
@@ -363,12 +367,16 @@ __global__ __launch_bounds__(kBlock) void k_sample(const ChannelTab* __restrict_
                                                    double* __restrict__ w, int32_t* __restrict__ chan_out,
                                                    double* __restrict__ tile_stats, int grid_doubles,
                                                    double* __restrict__ vpart, int vstride) {
-    sample_loop<stage_rows<NS, NI>()>(cts, grids, grid_off, chan_nb, call, seed, sid, ctr_dev, ctr_off, np, ld, p, x1x2,
-                                      w, chan_out, tile_stats, grid_doubles, vpart, vstride,
-                                      [&](int c, const TileArgs& t, TileAcc& acc) {
-                                          const ChannelTab* ct = cts + c;
-                                          sample_tile<NS, NI, KINDS, MIX>(ct, pts + ct->process, c, t, acc);
-                                      });
+    sample_loop<stage_rows<NS, NI>()>(
+        cts, grids, grid_off, chan_nb, call, seed, sid, ctr_dev, ctr_off, np, ld, p, x1x2, w, chan_out, tile_stats,
+        grid_doubles, vpart, vstride, [&](auto& run) {
+            const int n_chan = call->n_chan;
+            for (int c = 0; c < n_chan; ++c)
+                run(c, [&](const TileArgs& t, TileAcc& acc) {
+                    const ChannelTab* ct = cts + c;
+                    sample_tile<NS, NI, KINDS, MIX>(ct, pts + ct->process, c, t, acc);
+                });
+        });
 }
 
 // Inverse of run_chili from the lab-frame momenta p [4][np][n] of event e:

@@ -59,7 +59,9 @@ void emit_bytes(std::string& s, const char* name, int index, const void* p, size
     s += "};\n";
 }
 
-std::string sample_source(const Compiled& comp, int mixed, int& rows) {
+// waves > 0: ask the compiler for at least that many waves per SIMD (it
+// then limits the registers to 512 / waves)
+std::string sample_source(const Compiled& comp, int mixed, int waves, int& rows) {
     std::string s =
         "using __hip_internal::int32_t;\nusing __hip_internal::uint32_t;\nusing __hip_internal::int64_t;\n"
         "using __hip_internal::uint64_t;\nusing __hip_internal::uint8_t;\n#include \"chain_kernels.h\"\n"
@@ -74,7 +76,9 @@ std::string sample_source(const Compiled& comp, int mixed, int& rows) {
     }
     for (size_t q = 0; q < comp.procs.size(); ++q) emit_bytes(s, "proc", (int)q, &comp.procs[q], sizeof(ProcessTab));
     s += "}  // namespace spec\n}  // namespace msx\n";
-    s += "extern \"C\" __global__ __launch_bounds__(msx::kBlock) void msx_jit_sample(\n"
+    s += "extern \"C\" __global__ __launch_bounds__(msx::kBlock) ";
+    if (waves > 0) s += "__attribute__((amdgpu_waves_per_eu(" + std::to_string(waves) + "))) ";
+    s += "void msx_jit_sample(\n"
          "    const msx::ChannelTab* __restrict__ cts, const msx::ProcessTab* __restrict__ pts,\n"
          "    const double* __restrict__ grids, const int64_t* __restrict__ grid_off,\n"
          "    const int32_t* __restrict__ chan_nb, const msx::SampleCall* __restrict__ call, uint64_t seed,\n"
@@ -85,37 +89,29 @@ std::string sample_source(const Compiled& comp, int mixed, int& rows) {
          "    using namespace msx;\n";
     s += "    sample_loop<" + std::to_string(rows) +
          ">(cts, grids, grid_off, chan_nb, call, seed, sid, ctr_dev, ctr_off, np, ld, p, x1x2, w, chan_out,\n"
-         "        tile_stats, grid_doubles, vpart, vstride, [&](int c, const TileArgs& t, TileAcc& acc) {\n"
-         "        switch (c) {\n";
+         "        tile_stats, grid_doubles, vpart, vstride, [&](auto& run) {\n";
     for (int c = 0; c < C; ++c) {
         int ns, ni;
         reg_class_of(comp.chans[c], ns, ni);
         const std::string cs = std::to_string(c);
-        s += "        case " + cs + ": sample_tile<" + std::to_string(ns) + ", " + std::to_string(ni) + ", " +
-             std::to_string(comp.chans[c].kinds) + ", " + (mixed ? "true" : "false") +
+        s += "        run(" + cs + ", [&](const TileArgs& t, TileAcc& acc) { sample_tile<" + std::to_string(ns) + ", " +
+             std::to_string(ni) + ", " + std::to_string(comp.chans[c].kinds) + ", " + (mixed ? "true" : "false") +
              ">(reinterpret_cast<const ChannelTab*>(spec::chan" + cs +
              "), reinterpret_cast<const ProcessTab*>(spec::proc" + std::to_string(comp.chans[c].process) + "), " +
-             cs + ", t, acc); break;\n";
+             cs + ", t, acc); });\n";
     }
-    s += "        default: break;\n        }\n    });\n}\n";
+    s += "    });\n}\n";
     return s;
 }
 
-}  // namespace
-
-bool jit_build_sample(const Compiled& comp, int mixed, int device, JitSample& out, std::string& err) {
-    int rows = 0;
-    const std::string src = sample_source(comp, mixed, rows);
-    hipDeviceProp_t prop;
-    hipError_t he = hipGetDeviceProperties(&prop, device);
-    if (he != hipSuccess) {
-        err = std::string("hipGetDeviceProperties: ") + hipGetErrorString(he);
-        return false;
-    }
-    const std::string arch = std::string("--offload-arch=") + prop.gcnArchName;
-    // the library's own flags for the FP64 path: no contraction, no packed FP32
+// Compiles `src` and loads its kernel; *scratch gets its scratch bytes per
+// lane.
+bool compile_load(const std::string& src, const std::string& arch, JitSample& j, int* scratch, std::string& err) {
+    // the library's own flags for the FP64 path (no contraction, no packed
+    // FP32); no machine-level loop-invariant hoisting, which in this kernel
+    // only lengthens the live ranges of constants and table values
     const char* opts[] = {arch.c_str(), "-O3", "-std=c++17", "-ffp-contract=off", "-Xclang", "-target-feature",
-                          "-Xclang", "-packed-fp32-ops"};
+                          "-Xclang", "-packed-fp32-ops", "-mllvm", "-disable-machine-licm"};
     hiprtcProgram prog;
     hiprtcResult r = hiprtcCreateProgram(&prog, src.c_str(), "msx_jit_sample.hip", jit_src::kHeaderCount,
                                          jit_src::kHeaderTexts, jit_src::kHeaderNames);
@@ -146,19 +142,65 @@ bool jit_build_sample(const Compiled& comp, int mixed, int device, JitSample& ou
         err = std::string("hiprtcGetCode: ") + hiprtcGetErrorString(r);
         return false;
     }
-    JitSample j;
+    hipError_t he;
     if ((he = hipModuleLoadData(&j.module, code.data())) != hipSuccess) {
         err = std::string("hipModuleLoadData: ") + hipGetErrorString(he);
         return false;
     }
-    if ((he = hipModuleGetFunction(&j.fn, j.module, "msx_jit_sample")) != hipSuccess) {
+    if ((he = hipModuleGetFunction(&j.fn, j.module, "msx_jit_sample")) != hipSuccess ||
+        (he = hipFuncGetAttribute(scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, j.fn)) != hipSuccess) {
         err = std::string("hipModuleGetFunction: ") + hipGetErrorString(he);
         (void)hipModuleUnload(j.module);
+        j = JitSample{};
         return false;
     }
-    j.rows = rows;
-    out = j;
     return true;
+}
+
+}  // namespace
+
+bool jit_build_sample(const Compiled& comp, int mixed, int device, JitSample& out, std::string& err, bool& spills) {
+    spills = false;
+    hipDeviceProp_t prop;
+    hipError_t he = hipGetDeviceProperties(&prop, device);
+    if (he != hipSuccess) {
+        err = std::string("hipGetDeviceProperties: ") + hipGetErrorString(he);
+        return false;
+    }
+    const std::string arch = std::string("--offload-arch=") + prop.gcnArchName;
+    // First at three waves per SIMD (168 registers), which is faster than
+    // two waves where it needs little or no scratch (t tbar: 12 B/lane, 5%
+    // faster); a three-wave build with more scratch than kMaxScratch is
+    // dropped for the compiler's default occupancy (the eight pp -> 4 jets
+    // channels at three waves need 120 B/lane, which costs 100 B/event of
+    // HBM traffic).  A kernel that spills even at the default occupancy is
+    // slower than the class kernel and is not used.
+    constexpr int kMaxScratch = 32;
+    for (int waves : {3, 0}) {
+        int rows = 0;
+        const std::string src = sample_source(comp, mixed, waves, rows);
+        JitSample j;
+        int scratch = 0;
+        if (!compile_load(src, arch, j, &scratch, err)) return false;
+        if (waves > 0 && scratch > kMaxScratch) {
+            (void)hipModuleUnload(j.module);
+            continue;
+        }
+        if (waves == 0 && scratch > 0) {
+            err = "the kernel compiled for these " + std::to_string(comp.chans.size()) +
+                  " channels spills registers (" + std::to_string(scratch) +
+                  " B of scratch per lane); the class kernel is kept";
+            spills = true;
+            (void)hipModuleUnload(j.module);
+            return false;
+        }
+        j.rows = rows;
+        j.waves = waves;
+        j.scratch = scratch;
+        out = j;
+        return true;
+    }
+    return false;
 }
 
 void jit_release(JitSample& j) {

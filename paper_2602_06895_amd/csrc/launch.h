@@ -95,6 +95,8 @@ struct JitSample {
     hipModule_t module = nullptr;
     hipFunction_t fn = nullptr;
     int rows = 0;
+    int waves = 0;    // waves per SIMD it was compiled for (0: the compiler's choice)
+    int scratch = 0;  // its scratch bytes per lane
 };
 
 // Fused multichannel sample.  `call` is the device copy of the call table;

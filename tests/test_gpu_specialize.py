@@ -62,7 +62,7 @@ CASES = {
     "pp4j_chili": _chili_beside_diagrams,
     "pp4j_st": _st,
     "rambo_ee6": lambda: W.rambo_process(6),
-    "multichannel24": lambda: W.c4_context()[0],
+    "two_processes9": lambda: {"processes": W.c4_context()[0]["processes"][:2]},
 }
 
 
@@ -111,7 +111,7 @@ def test_bit_identical_to_class_kernel(torch, case):
     n_chan = probe.n_channels
     probe.close()
     counts = _counts(n_chan, 3)
-    flags = SAMPLE_ACCUMULATE_VEGAS if case != "multichannel24" else 0
+    flags = SAMPLE_ACCUMULATE_VEGAS
     a = _run(torch, desc, prec, False, counts, flags, 2)
     b = _run(torch, desc, prec, True, counts, flags, 2)
     for k in ("p", "w", "x1x2", "chan"):
@@ -169,6 +169,59 @@ def test_device_counts_graph_and_noalloc(torch):
     torch.cuda.synchronize()
     assert np.array_equal(_bits(nb["w"]), want[0]["w"])
     assert np.array_equal(_bits(nb["chan"]), want[0]["chan"])
+    ctx.close()
+    ref.close()
+
+
+def test_with_flows_attached(torch):
+    """MSX_SAMPLE_USE_FLOW on a specialised context (flows on channels 0
+    and 5, the other channels through the specialised kernel with those two
+    skipped) gives the same bits as on a class-kernel context."""
+    from paper_2602_06895_amd import SAMPLE_USE_FLOW, Context, Flow
+
+    desc = W.c2_pp4j()
+    res = []
+    flows = []
+    for spec in (False, True):
+        ctx = Context(desc)
+        if spec:
+            ctx.specialize()
+        d = ctx.dims[0]
+        for c in (0, 5):
+            f = Flow(d, 4, 16, 128)
+            f.set_params(W.flow_params(11 + c, d, 4, 16, 128, last_scale=0.05))
+            en, _ = ctx.attach_flow(c, f, n_check=0)
+            assert en
+            flows.append(f)
+        counts = np.array([3000, 500, 0, 1000, 1, 2049, 64, 7], dtype=np.int64)
+        out = ctx.sample(counts, seed=12, stream_id=3, counter_offset=4242, flags=SAMPLE_USE_FLOW)
+        torch.cuda.synchronize()
+        res.append(({k: _bits(v) for k, v in out.items() if v is not None}, ctx.stats()))
+        ctx.close()
+    for k in res[0][0]:
+        assert np.array_equal(res[0][0][k], res[1][0][k]), k
+    assert np.array_equal(res[0][1], res[1][1])
+    for f in flows:
+        f.close()
+
+
+def test_spilling_kernel_is_refused(torch):
+    """24 channels in one kernel spill registers: msx_specialize refuses
+    (MSX_ERR_UNSUPPORTED) and the context keeps sampling with the class
+    kernel."""
+    from paper_2602_06895_amd import Context, MsxError
+
+    desc, counts = W.c4_context()
+    ctx = Context(desc)
+    with pytest.raises(MsxError) as e:
+        ctx.specialize()
+    assert e.value.status == 4 and "spills" in str(e.value)
+    assert not ctx.specialized
+    a = ctx.sample(counts, seed=1)
+    ref = Context(desc)
+    b = ref.sample(counts, seed=1)
+    torch.cuda.synchronize()
+    assert np.array_equal(_bits(a["w"]), _bits(b["w"]))
     ctx.close()
     ref.close()
 

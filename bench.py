@@ -232,7 +232,8 @@ def _timed(fn, reps):
 
 def mixed_report(n=100_000_000, steps=10, n_err=10_000_000):
     """pp -> t tbar -> 6 (16 dims, Breit-Wigner t and W): FP64 and mixed
-    precision fused samples of n events (graph replays, same grids), and the
+    precision fused samples of n events (graph replays, same grids, each
+    precision at its own autotuned launch shape), and the
     per-quantity error of mixed results against FP64 ones on the same n_err
     events."""
     import torch
@@ -245,11 +246,12 @@ def mixed_report(n=100_000_000, steps=10, n_err=10_000_000):
     adapt_vegas(c64, n_per_channel=100_000, iterations=10, seed=3, stream_id=1)
     grid = c64.get_grid(0)
     counts = np.array([n])
+    c64.autotune(counts, seed=1, reps=3)
     _, wall64, ms64 = graph_steps(c64, counts, 77, steps, 2)
     torch.cuda.empty_cache()
     cmx, _ = make_context(W.c3_ttbar6(), precision=MIXED)
     cmx.set_grid(0, grid)
-    cmx.set_launch(*c64.launch_shape())
+    cmx.autotune(counts, seed=1, reps=3)
     _, wallmx, msmx = graph_steps(cmx, counts, 77, steps, 2)
     torch.cuda.empty_cache()
     ce = np.array([n_err])
@@ -646,7 +648,7 @@ def summarize_counters(d: str):
         c = sqlite3.connect(f)
         for name, ctr, avg, cnt in c.execute(
                 "select kernel_name, counter_name, avg(v), count(*) from (select kernel_name, counter_name, "
-                "dispatch_id, sum(value) as v from counters_collection where kernel_name like '%msx::%' "
+                "dispatch_id, sum(value) as v from counters_collection where kernel_name like '%msx%' "
                 "group by kernel_name, counter_name, dispatch_id) group by kernel_name, counter_name "
                 "order by kernel_name, counter_name"):
             short = name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")

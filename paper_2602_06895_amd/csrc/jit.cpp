@@ -78,7 +78,7 @@ std::string sample_source(const Compiled& comp, int mixed, int waves, int& rows)
     s += "}  // namespace spec\n}  // namespace msx\n";
     s += "extern \"C\" __global__ __launch_bounds__(msx::kBlock) ";
     if (waves > 0) s += "__attribute__((amdgpu_waves_per_eu(" + std::to_string(waves) + "))) ";
-    s += "void msx_jit_sample(\n"
+    s += "void MSX_JIT_NAME(\n"
          "    const msx::ChannelTab* __restrict__ cts, const msx::ProcessTab* __restrict__ pts,\n"
          "    const double* __restrict__ grids, const int64_t* __restrict__ grid_off,\n"
          "    const int32_t* __restrict__ chan_nb, const msx::SampleCall* __restrict__ call, uint64_t seed,\n"
@@ -106,7 +106,22 @@ std::string sample_source(const Compiled& comp, int mixed, int waves, int& rows)
 
 // Compiles `src` and loads its kernel; *scratch gets its scratch bytes per
 // lane.
-bool compile_load(const std::string& src, const std::string& arch, JitSample& j, int* scratch, std::string& err) {
+// The kernel's name: msx_jit_sample_ and a 64-bit FNV-1a hash of its source
+// (so that the kernels of different contexts are told apart in traces).
+std::string kernel_name(const std::string& src) {
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (unsigned char ch : src) {
+        h ^= ch;
+        h *= 0x100000001b3ull;
+    }
+    char buf[40];
+    std::snprintf(buf, sizeof buf, "msx_jit_sample_%016llx", (unsigned long long)h);
+    return buf;
+}
+
+bool compile_load(const std::string& body, const std::string& arch, JitSample& j, int* scratch, std::string& err) {
+    const std::string name = kernel_name(body);
+    const std::string src = "#define MSX_JIT_NAME " + name + "\n" + body;
     // the library's own flags for the FP64 path (no contraction, no packed
     // FP32); no machine-level loop-invariant hoisting, which in this kernel
     // only lengthens the live ranges of constants and table values
@@ -147,7 +162,7 @@ bool compile_load(const std::string& src, const std::string& arch, JitSample& j,
         err = std::string("hipModuleLoadData: ") + hipGetErrorString(he);
         return false;
     }
-    if ((he = hipModuleGetFunction(&j.fn, j.module, "msx_jit_sample")) != hipSuccess ||
+    if ((he = hipModuleGetFunction(&j.fn, j.module, name.c_str())) != hipSuccess ||
         (he = hipFuncGetAttribute(scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, j.fn)) != hipSuccess) {
         err = std::string("hipModuleGetFunction: ") + hipGetErrorString(he);
         (void)hipModuleUnload(j.module);

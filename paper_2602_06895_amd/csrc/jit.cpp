@@ -3,14 +3,14 @@
 // The kernel is the source of k_sample (sample_loop and sample_tile in
 // chain_kernels.h), compiled with the HIP run-time compiler for one
 // context's channels: every channel's and process's table becomes a
-// constexpr byte image, so the compiler folds the table reads, the map-kind
-// and operation-count branches and the slot indices of the chain into
-// constants, unrolls each channel's operations and keeps only the momentum
-// slots that are still live.  The arithmetic is the same source and the
-// library is compiled without floating-point contraction, so the results
-// are bit-identical to the class kernel's; only the code is smaller (no
-// scratch, fewer registers, more waves per SIMD) and runs fewer
-// instructions.  The headers come from jit_sources.cpp, which the build
+// constexpr object (bit-cast from its bytes), so the compiler folds the
+// table reads, the map-kind and operation-count branches and the slot
+// indices of the chain into constants, unrolls each channel's operations
+// and keeps only the momentum slots that are still live.  The arithmetic is
+// the same source and the forward chain is compiled without floating-point
+// contraction, so the results are bit-identical to the class kernel's; only
+// the code is smaller (no AGPR spilling, fewer registers, more waves per
+// SIMD) and runs fewer instructions.  The headers come from jit_sources.cpp, which the build
 // generates from the kernel headers.
 #include "jit.h"
 
@@ -46,9 +46,12 @@ void reg_class_of(const ChannelTab& t, int& ns, int& ni) {
     }
 }
 
-void emit_bytes(std::string& s, const char* name, int index, const void* p, size_t n) {
-    char head[96];
-    std::snprintf(head, sizeof head, "alignas(16) constexpr unsigned char %s%d[%zu] = {", name, index, n);
+// constexpr <type> <name><index> = the table whose bytes are p[0 .. n)
+// (bit-cast from a byte image, so the compiler sees every field's value)
+void emit_table(std::string& s, const char* type, const char* name, int index, const void* p, size_t n) {
+    char head[128];
+    std::snprintf(head, sizeof head, "constexpr %s %s%d = __builtin_bit_cast(%s, Image<%zu>{{", type, name, index,
+                  type, n);
     s += head;
     const unsigned char* b = (const unsigned char*)p;
     for (size_t i = 0; i < n; ++i) {
@@ -56,7 +59,7 @@ void emit_bytes(std::string& s, const char* name, int index, const void* p, size
         std::snprintf(v, sizeof v, i ? ",%u" : "%u", (unsigned)b[i]);
         s += v;
     }
-    s += "};\n";
+    s += "}});\n";
 }
 
 // waves > 0: ask the compiler for at least that many waves per SIMD (it
@@ -65,16 +68,17 @@ std::string sample_source(const Compiled& comp, int mixed, int waves, int& rows)
     std::string s =
         "using __hip_internal::int32_t;\nusing __hip_internal::uint32_t;\nusing __hip_internal::int64_t;\n"
         "using __hip_internal::uint64_t;\nusing __hip_internal::uint8_t;\n#include \"chain_kernels.h\"\n"
-        "namespace msx {\nnamespace spec {\n";
+        "namespace msx {\nnamespace spec {\ntemplate <unsigned long N>\nstruct Image {\n    unsigned char b[N];\n};\n";
     const int C = (int)comp.chans.size();
     rows = kMaxUniq + 1;
     for (int c = 0; c < C; ++c) {
-        emit_bytes(s, "chan", c, &comp.chans[c], sizeof(ChannelTab));
+        emit_table(s, "ChannelTab", "chan", c, &comp.chans[c], sizeof(ChannelTab));
         int ns, ni;
         reg_class_of(comp.chans[c], ns, ni);
         rows = std::max(rows, ns + ni + 1);
     }
-    for (size_t q = 0; q < comp.procs.size(); ++q) emit_bytes(s, "proc", (int)q, &comp.procs[q], sizeof(ProcessTab));
+    for (size_t q = 0; q < comp.procs.size(); ++q)
+        emit_table(s, "ProcessTab", "proc", (int)q, &comp.procs[q], sizeof(ProcessTab));
     s += "}  // namespace spec\n}  // namespace msx\n";
     s += "extern \"C\" __global__ __launch_bounds__(msx::kBlock) ";
     if (waves > 0) s += "__attribute__((amdgpu_waves_per_eu(" + std::to_string(waves) + "))) ";
@@ -96,9 +100,8 @@ std::string sample_source(const Compiled& comp, int mixed, int waves, int& rows)
         const std::string cs = std::to_string(c);
         s += "        run(" + cs + ", [&](const TileArgs& t, TileAcc& acc) { sample_tile<" + std::to_string(ns) + ", " +
              std::to_string(ni) + ", " + std::to_string(comp.chans[c].kinds) + ", " + (mixed ? "true" : "false") +
-             ">(reinterpret_cast<const ChannelTab*>(spec::chan" + cs +
-             "), reinterpret_cast<const ProcessTab*>(spec::proc" + std::to_string(comp.chans[c].process) + "), " +
-             cs + ", t, acc); });\n";
+             ">(&spec::chan" + cs + ", &spec::proc" + std::to_string(comp.chans[c].process) + ", " + cs +
+             ", t, acc); });\n";
     }
     s += "    });\n}\n";
     return s;

@@ -358,8 +358,9 @@ def flow_report(train_steps=400, batch=65536, n_eval=1_000_000, lr=1e-3, workloa
 def graph_report(steps=20):
     """24-channel batch (C1 and C2 topologies, power-law counts) as one
     persistent launch replayed from a HIP graph after the autotuner, in FP64
-    and in mixed precision, through the class kernel and the kernel compiled
-    for the 24 channels; median of `steps` replays, eager launches beside."""
+    and in mixed precision, through the class kernel and the kernels compiled
+    for the 24 channels (groups of at most eight channels, one launch each);
+    median of `steps` replays, eager launches beside."""
     import torch
 
     import workloads as W
@@ -376,7 +377,7 @@ def graph_report(steps=20):
                 try:
                     ctx.specialize()
                 except MsxError as e:
-                    # the kernel for all 24 channels spills; the library refuses it
+                    # a channel whose specialised kernel would spill is refused
                     out[f"{name}_{kernel}"] = {"refused": str(e)}
                     ctx.close()
                     continue
@@ -391,6 +392,7 @@ def graph_report(steps=20):
                                        "autotuned": {"events_per_thread": ept, "grid": grid, "ms": best}}
             if kernel == "specialized":
                 out[f"{name}_{kernel}"]["specialize_seconds"] = spec_s
+                out[f"{name}_{kernel}"]["kernels"] = ctx.specialized_kernels
             ctx.close()
             torch.cuda.empty_cache()
     return out

@@ -135,7 +135,7 @@ enum {
     MSX_META_COUNTER = 11,     /* next event id of MSX_COUNTER_AUTO sample calls */
     MSX_META_FLOW = 12,        /* channel `index`: 0 no flow attached, 1 attached but VEGAS kept
                                   (the attach check found the flow no better), 2 flow enabled */
-    MSX_META_SPECIALIZED = 13  /* 1 while sample launches use the kernel msx_specialize built */
+    MSX_META_SPECIALIZED = 13  /* kernels msx_specialize built that sample launches use (0: none) */
 };
 
 /* Text of the last error on this context (or of the last failed create when
@@ -314,22 +314,27 @@ msx_status msx_autotune(msx_ctx* ctx, const int64_t* counts, uint64_t seed, int3
 /* Channel-specialised fused sample (the per-event chain of section 2.2 with
  * the integrand and channel weight of eq. multi-channel-mg, as msx_sample).
  * on != 0: compiles, with the HIP run-time compiler for the context's
- * device, a version of the fused sample kernel in which this context's
+ * device, versions of the fused sample kernel in which this context's
  * channel and process tables are compile-time constants (the map kinds,
  * operation counts and momentum slots of every channel fixed in the code),
- * loads it, and from then on every sample launch of the context uses it:
- * msx_sample, msx_sample_device, msx_sample_noalloc and graphs captured
- * afterwards.  Its results are bit-identical to the default kernel's (same
- * source, no floating-point contraction in either); it runs fewer
- * instructions with fewer registers.  The first call compiles on the host
- * (0.5 s for one t tbar channel, 4 s for eight pp -> 4 jets channels) and
- * synchronises the device; later calls only switch.  on == 0 switches launches back to the default
- * kernel; the compiled one stays loaded until msx_destroy (graphs captured
- * with it keep working).  Errors: MSX_ERR_DEVICE with the compiler's log
- * when the run-time compiler or the module load fails; MSX_ERR_UNSUPPORTED
- * when the compiled kernel would spill registers to scratch (many channels
- * in one kernel), since it would then be slower than the default one.  In
- * both cases the context keeps the default kernel. */
+ * loads them, and from then on every sample launch of the context uses
+ * them: msx_sample, msx_sample_device, msx_sample_noalloc and graphs
+ * captured afterwards.  Channels are compiled in groups of at most eight
+ * consecutive channels, one kernel each, launched one after the other in
+ * the same stream (a group whose kernel would spill registers is split).
+ * Results are bit-identical to the default kernel's in MSX_FP64 (same
+ * source, no floating-point contraction in either) and differ by FP32
+ * roundings in MSX_MIXED; the kernels run fewer instructions with fewer
+ * registers.  The first call compiles on the host (0.5 s for one t tbar
+ * channel, 4 s for eight pp -> 4 jets channels) and synchronises the device;
+ * later calls only switch.  on == 0 switches launches back to the default
+ * kernel; the compiled ones stay loaded until msx_destroy (graphs captured
+ * with them keep working).  MSX_META_SPECIALIZED gives the number of
+ * kernels in use (0: the default kernel).  Errors: MSX_ERR_DEVICE with the
+ * compiler's log when the run-time compiler or a module load fails;
+ * MSX_ERR_UNSUPPORTED when the kernel of a single channel would spill
+ * registers to scratch (it would be slower than the default one).  In both
+ * cases the context keeps the default kernel. */
 msx_status msx_specialize(msx_ctx* ctx, int32_t on);
 
 /* Copy the accumulated per-channel statistics to host out [n_channels][5]:

@@ -357,6 +357,11 @@ class Context:
     def specialized(self) -> bool:
         return bool(self._meta(META_SPECIALIZED, 0))
 
+    @property
+    def specialized_kernels(self) -> int:
+        """Kernels the specialised sample launches (channel groups)."""
+        return self._meta(META_SPECIALIZED, 0)
+
     def stats(self) -> np.ndarray:
         out = np.zeros((self.n_channels, 5))
         self._check(self.L.msx_stats(self.h, out.ctypes.data, self._stream()))

@@ -86,7 +86,7 @@ struct msx_ctx {
     bool any_hadronic = false;
     // the fused sample compiled for these channels (msx_specialize); kept
     // loaded until msx_destroy once built, since captured graphs may use it
-    JitSample jit;
+    JitSampleSet jit;
     bool jit_on = false;
 };
 
@@ -138,7 +138,7 @@ void free_all(msx_ctx* c) {
 
 bool bad_ctx(const msx_ctx* ctx) { return ctx == nullptr; }
 
-const JitSample* jit_of(const msx_ctx* ctx) { return ctx->jit_on ? &ctx->jit : nullptr; }
+const JitSampleSet* jit_of(const msx_ctx* ctx) { return ctx->jit_on ? &ctx->jit : nullptr; }
 
 msx_status set_device(msx_ctx* ctx) {
     hipError_t e = hipSetDevice(ctx->device);
@@ -333,7 +333,7 @@ msx_status msx_specialize(msx_ctx* ctx, int32_t on) {
         ctx->jit_on = false;
         return MSX_OK;
     }
-    if (!ctx->jit.fn) {
+    if (ctx->jit.n == 0) {
         if (msx_status st = set_device(ctx)) return st;
         std::string err;
         bool spills = false;
@@ -362,7 +362,7 @@ msx_status msx_get_meta(const msx_ctx* ctx, int32_t key, int32_t index, int64_t*
         case MSX_META_EVENTS_PER_THREAD: *value = ctx->ept; return MSX_OK;
         case MSX_META_GRID: *value = sample_grid(ctx); return MSX_OK;
         case MSX_META_COUNTER: *value = (int64_t)ctx->next_counter; return MSX_OK;
-        case MSX_META_SPECIALIZED: *value = ctx->jit_on ? 1 : 0; return MSX_OK;
+        case MSX_META_SPECIALIZED: *value = ctx->jit_on ? ctx->jit.n : 0; return MSX_OK;
         case MSX_META_FLOW:
             return chan(index >= 0 && index < C ? (ctx->flow[index] ? 1 + ctx->flow_on[index] : 0) : 0);
         case MSX_META_DIMS: return chan(index >= 0 && index < C ? ctx->comp.meta[index].dims : 0);

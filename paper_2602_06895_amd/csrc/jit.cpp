@@ -64,21 +64,22 @@ void emit_table(std::string& s, const char* type, const char* name, int index, c
 
 // waves > 0: ask the compiler for at least that many waves per SIMD (it
 // then limits the registers to 512 / waves)
-std::string sample_source(const Compiled& comp, int mixed, int waves, int& rows) {
+std::string sample_source(const Compiled& comp, int mixed, int waves, int c0, int c1, int& rows) {
     std::string s =
         "using __hip_internal::int32_t;\nusing __hip_internal::uint32_t;\nusing __hip_internal::int64_t;\n"
         "using __hip_internal::uint64_t;\nusing __hip_internal::uint8_t;\n#include \"chain_kernels.h\"\n"
         "namespace msx {\nnamespace spec {\ntemplate <unsigned long N>\nstruct Image {\n    unsigned char b[N];\n};\n";
-    const int C = (int)comp.chans.size();
     rows = kMaxUniq + 1;
-    for (int c = 0; c < C; ++c) {
+    std::vector<int> procs;
+    for (int c = c0; c < c1; ++c) {
         emit_table(s, "ChannelTab", "chan", c, &comp.chans[c], sizeof(ChannelTab));
         int ns, ni;
         reg_class_of(comp.chans[c], ns, ni);
         rows = std::max(rows, ns + ni + 1);
+        if (std::find(procs.begin(), procs.end(), comp.chans[c].process) == procs.end())
+            procs.push_back(comp.chans[c].process);
     }
-    for (size_t q = 0; q < comp.procs.size(); ++q)
-        emit_table(s, "ProcessTab", "proc", (int)q, &comp.procs[q], sizeof(ProcessTab));
+    for (int q : procs) emit_table(s, "ProcessTab", "proc", q, &comp.procs[q], sizeof(ProcessTab));
     s += "}  // namespace spec\n}  // namespace msx\n";
     s += "extern \"C\" __global__ __launch_bounds__(msx::kBlock) ";
     if (waves > 0) s += "__attribute__((amdgpu_waves_per_eu(" + std::to_string(waves) + "))) ";
@@ -94,7 +95,7 @@ std::string sample_source(const Compiled& comp, int mixed, int waves, int& rows)
     s += "    sample_loop<" + std::to_string(rows) +
          ">(cts, grids, grid_off, chan_nb, call, seed, sid, ctr_dev, ctr_off, np, ld, p, x1x2, w, chan_out,\n"
          "        tile_stats, grid_doubles, vpart, vstride, [&](auto& run) {\n";
-    for (int c = 0; c < C; ++c) {
+    for (int c = c0; c < c1; ++c) {
         int ns, ni;
         reg_class_of(comp.chans[c], ns, ni);
         const std::string cs = std::to_string(c);
@@ -107,8 +108,6 @@ std::string sample_source(const Compiled& comp, int mixed, int waves, int& rows)
     return s;
 }
 
-// Compiles `src` and loads its kernel; *scratch gets its scratch bytes per
-// lane.
 // The kernel's name: msx_jit_sample_ and a 64-bit FNV-1a hash of its source
 // (so that the kernels of different contexts are told apart in traces).
 std::string kernel_name(const std::string& src) {
@@ -122,6 +121,8 @@ std::string kernel_name(const std::string& src) {
     return buf;
 }
 
+// Compiles `body` and loads its kernel; *scratch gets its scratch bytes per
+// lane.
 bool compile_load(const std::string& body, const std::string& arch, JitSample& j, int* scratch, std::string& err) {
     const std::string name = kernel_name(body);
     const std::string src = "#define MSX_JIT_NAME " + name + "\n" + body;
@@ -175,9 +176,42 @@ bool compile_load(const std::string& body, const std::string& arch, JitSample& j
     return true;
 }
 
+// One kernel for channels [c0, c1): first at three waves per SIMD (168
+// registers), which is faster than two waves where it needs little or no
+// scratch (t tbar: 12 B/lane, 5% faster); a three-wave build with more
+// scratch than kMaxScratch is dropped for the compiler's default occupancy
+// (the eight pp -> 4 jets channels at three waves need 120 B/lane, which
+// costs 100 B/event of HBM traffic).  Returns 0 with the kernel in j, 1 when
+// the kernel spills even at the default occupancy (not kept), -1 on error.
+int build_group(const Compiled& comp, int mixed, const std::string& arch, int c0, int c1, JitSample& j,
+                int* scratch_out, std::string& err) {
+    constexpr int kMaxScratch = 32;
+    for (int waves : {3, 0}) {
+        int rows = 0;
+        const std::string src = sample_source(comp, mixed, waves, c0, c1, rows);
+        JitSample k;
+        int scratch = 0;
+        if (!compile_load(src, arch, k, &scratch, err)) return -1;
+        if ((waves > 0 && scratch > kMaxScratch) || (waves == 0 && scratch > 0)) {
+            (void)hipModuleUnload(k.module);
+            if (waves > 0) continue;
+            *scratch_out = scratch;
+            return 1;
+        }
+        k.rows = rows;
+        k.waves = waves;
+        k.scratch = scratch;
+        k.c0 = c0;
+        k.c1 = c1;
+        j = k;
+        return 0;
+    }
+    return -1;
+}
+
 }  // namespace
 
-bool jit_build_sample(const Compiled& comp, int mixed, int device, JitSample& out, std::string& err, bool& spills) {
+bool jit_build_sample(const Compiled& comp, int mixed, int device, JitSampleSet& out, std::string& err, bool& spills) {
     spills = false;
     hipDeviceProp_t prop;
     hipError_t he = hipGetDeviceProperties(&prop, device);
@@ -186,44 +220,58 @@ bool jit_build_sample(const Compiled& comp, int mixed, int device, JitSample& ou
         return false;
     }
     const std::string arch = std::string("--offload-arch=") + prop.gcnArchName;
-    // First at three waves per SIMD (168 registers), which is faster than
-    // two waves where it needs little or no scratch (t tbar: 12 B/lane, 5%
-    // faster); a three-wave build with more scratch than kMaxScratch is
-    // dropped for the compiler's default occupancy (the eight pp -> 4 jets
-    // channels at three waves need 120 B/lane, which costs 100 B/event of
-    // HBM traffic).  A kernel that spills even at the default occupancy is
-    // slower than the class kernel and is not used.
-    constexpr int kMaxScratch = 32;
-    for (int waves : {3, 0}) {
-        int rows = 0;
-        const std::string src = sample_source(comp, mixed, waves, rows);
-        JitSample j;
+    // Channels go into kernels of at most kGroup consecutive channels, one
+    // launch each: the register file of one kernel is the largest any of its
+    // channel loops needs plus what the compiler keeps live across them, and
+    // grows with the channel count (24 channels in one kernel: 342 VGPRs and
+    // 412 B/lane of scratch).  A group whose kernel spills is split in
+    // halves; a single channel whose kernel spills makes the whole call fail
+    // (the class kernel is kept).
+    constexpr int kGroup = 8;
+    const int C = (int)comp.chans.size();
+    std::vector<std::pair<int, int>> todo;
+    for (int c = 0; c < C; c += kGroup) todo.push_back({c, std::min(C, c + kGroup)});
+    JitSampleSet set;
+    auto release = [&]() {
+        for (int g = 0; g < set.n; ++g) (void)hipModuleUnload(set.k[g].module);
+    };
+    for (size_t i = 0; i < todo.size(); ++i) {
+        const int c0 = todo[i].first, c1 = todo[i].second;
+        JitSample k;
         int scratch = 0;
-        if (!compile_load(src, arch, j, &scratch, err)) return false;
-        if (waves > 0 && scratch > kMaxScratch) {
-            (void)hipModuleUnload(j.module);
-            continue;
-        }
-        if (waves == 0 && scratch > 0) {
-            err = "the kernel compiled for these " + std::to_string(comp.chans.size()) +
-                  " channels spills registers (" + std::to_string(scratch) +
-                  " B of scratch per lane); the class kernel is kept";
-            spills = true;
-            (void)hipModuleUnload(j.module);
+        const int r = build_group(comp, mixed, arch, c0, c1, k, &scratch, err);
+        if (r < 0) {
+            release();
             return false;
         }
-        j.rows = rows;
-        j.waves = waves;
-        j.scratch = scratch;
-        out = j;
-        return true;
+        if (r == 1) {
+            if (c1 - c0 == 1) {
+                err = "the kernel compiled for channel " + std::to_string(c0) + " spills registers (" +
+                      std::to_string(scratch) + " B of scratch per lane); the class kernel is kept";
+                spills = true;
+                release();
+                return false;
+            }
+            const int mid = (c0 + c1) / 2;
+            todo.insert(todo.begin() + (std::ptrdiff_t)i + 1, {{c0, mid}, {mid, c1}});
+            continue;
+        }
+        if (set.n == kMaxJitGroups) {
+            err = "too many specialised kernels";
+            (void)hipModuleUnload(k.module);
+            release();
+            return false;
+        }
+        set.k[set.n++] = k;
     }
-    return false;
+    out = set;
+    return true;
 }
 
-void jit_release(JitSample& j) {
-    if (j.module) (void)hipModuleUnload(j.module);
-    j = JitSample{};
+void jit_release(JitSampleSet& s) {
+    for (int g = 0; g < s.n; ++g)
+        if (s.k[g].module) (void)hipModuleUnload(s.k[g].module);
+    s = JitSampleSet{};
 }
 
 }  // namespace msx

@@ -741,15 +741,18 @@ hipError_t launch_sample(const ChannelTab* cts, const ProcessTab* pts, const dou
                          int kinds, int mixed, size_t lds_bytes, uint64_t seed, uint64_t sid, const uint64_t* ctr_dev,
                          uint64_t ctr_off, int np, int64_t ld, double* p, double* x1x2, double* w, int32_t* chan,
                          double* tile_stats, double* stats, int grid, hipStream_t s, double* vpart, int vstride,
-                         const int64_t* hist_off, int64_t hist_total, double* hist, const JitSample* jit) {
-    if (jit && jit->fn) {
-        const size_t lds = lds_bytes + sizeof(double) * (size_t)jit->rows * kBlock + (vpart ? vegas_acc_lds(vstride) : 0);
+                         const int64_t* hist_off, int64_t hist_total, double* hist, const JitSampleSet* jit) {
+    if (jit && jit->n > 0) {
         int grid_doubles = (int)(lds_bytes / sizeof(double));
         void* args[] = {&cts, &pts, &grids, &grid_off, &chan_nb, &call, &seed, &sid, &ctr_dev, &ctr_off, &np, &ld,
                         &p, &x1x2, &w, &chan, &tile_stats, &grid_doubles, &vpart, &vstride};
-        hipError_t err = hipModuleLaunchKernel(jit->fn, (unsigned)std::max(grid, 1), 1, 1, kBlock, 1, 1, (unsigned)lds, s,
-                                               args, nullptr);
-        if (err != hipSuccess) return err;
+        for (int g = 0; g < jit->n; ++g) {
+            const size_t lds =
+                lds_bytes + sizeof(double) * (size_t)jit->k[g].rows * kBlock + (vpart ? vegas_acc_lds(vstride) : 0);
+            hipError_t err = hipModuleLaunchKernel(jit->k[g].fn, (unsigned)std::max(grid, 1), 1, 1, kBlock, 1, 1,
+                                                   (unsigned)lds, s, args, nullptr);
+            if (err != hipSuccess) return err;
+        }
     } else {
         ChainLaunch a{};
         a.sample = true;

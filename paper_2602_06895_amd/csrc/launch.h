@@ -97,6 +97,14 @@ struct JitSample {
     int rows = 0;
     int waves = 0;    // waves per SIMD it was compiled for (0: the compiler's choice)
     int scratch = 0;  // its scratch bytes per lane
+    int c0 = 0, c1 = 0;  // the channels it samples
+};
+// The kernels compiled for a context: consecutive channel groups, launched
+// one after the other (each runs only its channels' tiles).
+constexpr int kMaxJitGroups = kMaxChannels;
+struct JitSampleSet {
+    int n = 0;
+    JitSample k[kMaxJitGroups];
 };
 
 // Fused multichannel sample.  `call` is the device copy of the call table;
@@ -106,15 +114,16 @@ struct JitSample {
 // histogram (sum w^2 per bin of every dimension) into per-tile partials
 // vpart [tiles][vstride] (vstride >= dims x bins of every channel), and a
 // second kernel adds them, tiles in order, to hist at hist_off[c] (device
-// array, per channel).  With jit != NULL the launch runs that kernel instead
-// of the register / kind class kernel of (max_slots, max_inv, kinds).
+// array, per channel).  With jit != NULL (and jit->n > 0) the launch runs
+// those kernels instead of the register / kind class kernel of
+// (max_slots, max_inv, kinds).
 hipError_t launch_sample(const ChannelTab* cts, const ProcessTab* pts, const double* grids, const int64_t* grid_off,
                          const int32_t* chan_nb, const SampleCall* call, int n_chan, int max_slots, int max_inv,
                          int kinds, int mixed, size_t lds_bytes, uint64_t seed, uint64_t sid, const uint64_t* ctr_dev,
                          uint64_t ctr_off, int np, int64_t ld, double* p, double* x1x2, double* w, int32_t* chan,
                          double* tile_stats, double* stats, int grid, hipStream_t s, double* vpart = nullptr,
                          int vstride = 0, const int64_t* hist_off = nullptr, int64_t hist_total = 0,
-                         double* hist = nullptr, const JitSample* jit = nullptr);
+                         double* hist = nullptr, const JitSampleSet* jit = nullptr);
 // Dynamic LDS bytes of a sample launch with VEGAS accumulation (grid area
 // lds_bytes, vstride doubles per wave histogram) for the register class of
 // (max_slots, max_inv).

@@ -879,15 +879,24 @@ namespace {
 
 constexpr int kUnwBuckets = 4096;
 
+// Counts and sums of the weights per bucket, with integer atomics only, so
+// the result does not depend on the order of the additions: every weight of
+// a bucket has the bucket's binary exponent (the buckets of every pass lie
+// within one exponent), so its value is m 2^(e - 1075) with the integer
+// significand m < 2^53, and the bucket sum is kept exactly as the sums of
+// m's upper 27 and lower 26 bits (each < 2^63 for n < 2^36 weights).
 __global__ __launch_bounds__(256) void k_unw_hist(int64_t n, const double* __restrict__ w, int shift, int width,
-                                                  uint64_t prefix, int first, double* __restrict__ counts,
-                                                  double* __restrict__ sums) {
+                                                  uint64_t prefix, int first, unsigned long long* __restrict__ counts,
+                                                  unsigned long long* __restrict__ sum_hi,
+                                                  unsigned long long* __restrict__ sum_lo) {
     __shared__ unsigned int c_l[kUnwBuckets];
-    __shared__ double s_l[kUnwBuckets];
+    __shared__ unsigned long long h_l[kUnwBuckets];
+    __shared__ unsigned long long l_l[kUnwBuckets];
     const int nbk = 1 << width;
     for (int i = threadIdx.x; i < nbk; i += blockDim.x) {
         c_l[i] = 0u;
-        s_l[i] = 0.0;
+        h_l[i] = 0ull;
+        l_l[i] = 0ull;
     }
     __syncthreads();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -897,14 +906,18 @@ __global__ __launch_bounds__(256) void k_unw_hist(int64_t n, const double* __res
         uint64_t bits = (uint64_t)__double_as_longlong(v);
         if (!first && (bits >> (shift + width)) != prefix) continue;
         int b = (int)((bits >> shift) & (uint64_t)(nbk - 1));
+        const uint64_t ex = bits >> 52;
+        const uint64_t m = (bits & ((1ull << 52) - 1)) | (ex ? (1ull << 52) : 0ull);
         atomicAdd(&c_l[b], 1u);
-        atomicAdd(&s_l[b], v);
+        atomicAdd(&h_l[b], (unsigned long long)(m >> 26));
+        atomicAdd(&l_l[b], (unsigned long long)(m & ((1ull << 26) - 1)));
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nbk; i += blockDim.x) {
         if (c_l[i]) {
-            atomicAdd(&counts[i], (double)c_l[i]);
-            atomicAdd(&sums[i], s_l[i]);
+            atomicAdd(&counts[i], (unsigned long long)c_l[i]);
+            atomicAdd(&sum_hi[i], h_l[i]);
+            atomicAdd(&sum_lo[i], l_l[i]);
         }
     }
 }
@@ -1029,9 +1042,10 @@ hipError_t launch_fill_i32(int32_t* x, int64_t n, int32_t v, hipStream_t s) {
 }
 
 hipError_t launch_unw_pass(int64_t n, const double* w, int shift, int width, uint64_t prefix, int first,
-                           double* counts, double* sums, int cu_count, hipStream_t s) {
+                           uint64_t* counts, uint64_t* sum_hi, uint64_t* sum_lo, int cu_count, hipStream_t s) {
     int g = grid_for(n, cu_count * 4);
-    k_unw_hist<<<g, 256, 0, s>>>(n, w, shift, width, prefix, first, counts, sums);
+    k_unw_hist<<<g, 256, 0, s>>>(n, w, shift, width, prefix, first, (unsigned long long*)counts,
+                                 (unsigned long long*)sum_hi, (unsigned long long*)sum_lo);
     return hipGetLastError();
 }
 

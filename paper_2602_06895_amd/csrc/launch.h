@@ -168,11 +168,15 @@ hipError_t launch_vegas_refine(int n_rows, const int32_t* row_nb, const int64_t*
 
 namespace msx {
 
-// Unweighting-efficiency search, one refinement pass: histogram (count, sum)
-// over bucket = (bits >> shift) & (2^width - 1) of every weight whose bit
-// pattern above shift + width equals `prefix` (all weights when first).
+// Unweighting-efficiency search, one refinement pass: histogram over bucket
+// = (bits >> shift) & (2^width - 1) of every positive weight whose bit
+// pattern above shift + width equals `prefix` (all weights when first):
+// counts, and the bucket's sum of significands m (the weight is
+// m 2^(e - 1075), e the bucket's biased exponent) as the sums of m >> 26 and
+// m & (2^26 - 1).  Integer atomics only: deterministic.  The arrays (2^width
+// entries each) must be zero before the pass.
 hipError_t launch_unw_pass(int64_t n, const double* w, int shift, int width, uint64_t prefix, int first,
-                           double* counts, double* sums, int cu_count, hipStream_t s);
+                           uint64_t* counts, uint64_t* sum_hi, uint64_t* sum_lo, int cu_count, hipStream_t s);
 // total sum and max of w (two doubles at out)
 hipError_t launch_sum_max(int64_t n, const double* w, double* out, double* part, int nblk, hipStream_t s);
 

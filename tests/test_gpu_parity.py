@@ -325,7 +325,7 @@ def test_vegas_histogram_and_refinement_match_oracle(ctxs, torch):
 # Unweighting efficiency
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("kind", ["exp", "ties", "zeros", "tiny", "one"])
+@pytest.mark.parametrize("kind", ["exp", "ties", "zeros", "tiny", "subnormal", "spread", "one"])
 def test_unweighting_efficiency_matches_oracle(ctxs, torch, kind):
     ctx, _ = ctxs["c2"]
     rng = np.random.default_rng(8)
@@ -337,12 +337,20 @@ def test_unweighting_efficiency_matches_oracle(ctxs, torch, kind):
         w = np.where(rng.random(300000) < 0.7, 0.0, rng.random(300000) ** 4)
     elif kind == "tiny":
         w = rng.random(5000) * 1e-290
+    elif kind == "subnormal":
+        w = rng.random(5000) * 1e-310
+    elif kind == "spread":
+        w = rng.exponential(size=2_000_001) * 10.0 ** rng.uniform(-30, 30, size=2_000_001)
     else:
         w = np.array([2.5])
     eff_o, W_o = oracle.unweighting_efficiency(w, 1e-3)
-    eff_g, W_g = ctx.unweight_eff(torch.from_numpy(w).to(ctx.device), 1e-3)
+    wd = torch.from_numpy(w).to(ctx.device)
+    eff_g, W_g = ctx.unweight_eff(wd, 1e-3)
     assert W_g == pytest.approx(W_o, rel=1e-12)
     assert eff_g == pytest.approx(eff_o, rel=1e-12)
+    # integer bucket sums: the same bits on every call
+    eff_2, W_2 = ctx.unweight_eff(wd, 1e-3)
+    assert (eff_2, W_2) == (eff_g, W_g)
 
 
 # --------------------------------------------------------------------------

@@ -50,7 +50,7 @@ struct msx_ctx {
     double* d_inv = nullptr;  // multichannel density scratch: y [max dims][n] then jac [n]
     int64_t inv_cap = 0;      // doubles
     int64_t vpart_cap = 0;
-    double* d_unw = nullptr;  // 3 * 4096 bucket words + 2 * 1024 partials + 2
+    double* d_unw = nullptr;  // 3 * 4096 bucket words + 2 * 1024 partials + 2 + the search state (3)
     // VEGAS accumulation inside the fused sample: per-channel histogram
     // offsets (device), the per-tile partial stride and the partials
     int64_t* d_hist_off = nullptr;
@@ -293,7 +293,7 @@ msx_status msx_create_channels(const char* process_json, int32_t precision, int3
         (e = dmalloc(&c->d_chan_nb, C)) != hipSuccess || (e = dmalloc(&c->d_row_nb, row_nb.size())) != hipSuccess ||
         (e = dmalloc(&c->d_row_grid, row_grid.size())) != hipSuccess ||
         (e = dmalloc(&c->d_row_hist, row_hist.size())) != hipSuccess ||
-        (e = dmalloc(&c->d_unw, 3 * 4096 + 2 * 1024 + 2)) != hipSuccess || (e = dmalloc(&c->d_call, 1)) != hipSuccess ||
+        (e = dmalloc(&c->d_unw, 3 * 4096 + 2 * 1024 + 2 + 3)) != hipSuccess || (e = dmalloc(&c->d_call, 1)) != hipSuccess ||
         (e = dmalloc(&c->d_hist_off, C)) != hipSuccess || (e = dmalloc(&c->d_mom, 4 * moments_blocks())) != hipSuccess ||
         (e = up(c->d_hist_off, c->hist_off.data(), sizeof(int64_t) * C)) != hipSuccess ||
         (e = up(c->d_chans, c->comp.chans.data(), sizeof(ChannelTab) * C)) != hipSuccess ||
@@ -1035,72 +1035,27 @@ msx_status msx_unweight_eff(msx_ctx* ctx, const double* w, int64_t n, double ove
     if (msx_status st = set_device(ctx)) return st;
     hipStream_t s = (hipStream_t)stream;
     uint64_t* counts = (uint64_t*)ctx->d_unw;
-    uint64_t* sum_hi = counts + 4096;
-    uint64_t* sum_lo = counts + 2 * 4096;
-    double* part = ctx->d_unw + 3 * 4096;
+    uint64_t* sum_hi = counts + kUnwMaxBuckets;
+    uint64_t* sum_lo = counts + 2 * kUnwMaxBuckets;
+    double* part = ctx->d_unw + 3 * kUnwMaxBuckets;
     double* tot = part + 2 * 1024;
+    UnwState* st = (UnwState*)(tot + 2);
+    if (n >= (int64_t(1) << 36)) return fail(ctx, MSX_ERR_ARG, "at most 2^36 weights");
     const int nblk = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    MSX_HIP(ctx, hipMemsetAsync(ctx->d_unw, 0, sizeof(uint64_t) * 3 * kUnwMaxBuckets, s), "memset");
+    MSX_HIP(ctx, hipMemsetAsync(st, 0, sizeof(UnwState), s), "memset");
     MSX_HIP(ctx, launch_sum_max(n, w, tot, part, nblk, s), "sum launch");
+    MSX_HIP(ctx, launch_unw_search(n, w, overweight, tot, st, counts, sum_hi, sum_lo, ctx->cu_count, s), "search");
     double hs[2];
+    UnwState hst;
     MSX_HIP(ctx, hipMemcpyAsync(hs, tot, sizeof hs, hipMemcpyDeviceToHost, s), "copy");
+    MSX_HIP(ctx, hipMemcpyAsync(&hst, st, sizeof hst, hipMemcpyDeviceToHost, s), "copy");
     MSX_HIP(ctx, hipStreamSynchronize(s), "sync");
     const double total = hs[0];
     if (!(total > 0.0) || !std::isfinite(total)) return fail(ctx, MSX_ERR_ARG, "weights must be finite with a positive sum");
-    if (n >= (int64_t(1) << 36)) return fail(ctx, MSX_ERR_ARG, "at most 2^36 weights");
     const double target = overweight * total;
-    // Refine over the 63 value bits of non-negative doubles: buckets of 12
-    // bits (the last pass 3); S_up/N_up collect weights in buckets above the
-    // crossing bucket of earlier passes.
-    const int shifts[6] = {51, 39, 27, 15, 3, 0};
-    const int widths[6] = {12, 12, 12, 12, 12, 3};
-    double S_up = 0.0, N_up = 0.0;
-    uint64_t prefix = 0;
-    std::vector<uint64_t> hc(4096), hh(4096), hl(4096);
-    std::vector<double> hsum(4096);
-    for (int pass = 0; pass < 6; ++pass) {
-        const int nbk = 1 << widths[pass];
-        MSX_HIP(ctx, hipMemsetAsync(counts, 0, sizeof(uint64_t) * 3 * 4096, s), "memset");
-        MSX_HIP(ctx,
-                launch_unw_pass(n, w, shifts[pass], widths[pass], prefix, pass == 0, counts, sum_hi, sum_lo,
-                                ctx->cu_count, s),
-                "histogram launch");
-        MSX_HIP(ctx, hipMemcpyAsync(hc.data(), counts, sizeof(uint64_t) * nbk, hipMemcpyDeviceToHost, s), "copy");
-        MSX_HIP(ctx, hipMemcpyAsync(hh.data(), sum_hi, sizeof(uint64_t) * nbk, hipMemcpyDeviceToHost, s), "copy");
-        MSX_HIP(ctx, hipMemcpyAsync(hl.data(), sum_lo, sizeof(uint64_t) * nbk, hipMemcpyDeviceToHost, s), "copy");
-        MSX_HIP(ctx, hipStreamSynchronize(s), "sync");
-        // bucket sums from the exact significand sums: sum m = hi 2^26 + lo,
-        // times 2^(e - 1075) for the bucket's biased exponent e (1 - 1075
-        // for subnormals)
-        for (int b = 0; b < nbk; ++b) {
-            const uint64_t lb_bits = (((prefix << widths[pass]) | (uint64_t)b) << shifts[pass]);
-            const int ex = (int)(lb_bits >> 52);
-            hsum[b] = std::ldexp((double)hh[b] * 67108864.0 + (double)hl[b], (ex ? ex : 1) - 1075);
-        }
-        // excess at the lower edge L_b of bucket b: every weight in buckets >= b
-        // lies at or above L_b
-        double S = S_up, N = N_up;
-        int found = -1;
-        double S_above_b = S_up, N_above_b = N_up;
-        for (int b = nbk - 1; b >= 0; --b) {
-            S_above_b = S;
-            N_above_b = N;
-            S += hsum[b];
-            N += (double)hc[b];
-            uint64_t lb_bits = (((prefix << widths[pass]) | (uint64_t)b) << shifts[pass]);
-            double lb;
-            std::memcpy(&lb, &lb_bits, sizeof lb);
-            if (S - lb * N >= target) {
-                found = b;
-                break;
-            }
-        }
-        if (found < 0) {  // only possible for the zero bucket: W lies below every positive weight
-            found = 0;
-        }
-        S_up = S_above_b;
-        N_up = N_above_b;
-        prefix = (prefix << widths[pass]) | (uint64_t)found;
-    }
+    const uint64_t prefix = hst.prefix;
+    const double S_up = hst.S_up, N_up = hst.N_up;
     // the crossing bucket is now the single value v; for W in [v, next) the
     // weights above W are exactly those counted in S_up / N_up
     double v;

@@ -878,6 +878,7 @@ namespace msx {
 namespace {
 
 constexpr int kUnwBuckets = 4096;
+static_assert(kUnwBuckets == kUnwMaxBuckets, "bucket count");
 
 // Counts and sums of the weights per bucket, with integer atomics only, so
 // the result does not depend on the order of the additions: every weight of
@@ -886,9 +887,11 @@ constexpr int kUnwBuckets = 4096;
 // significand m < 2^53, and the bucket sum is kept exactly as the sums of
 // m's upper 27 and lower 26 bits (each < 2^63 for n < 2^36 weights).
 __global__ __launch_bounds__(256) void k_unw_hist(int64_t n, const double* __restrict__ w, int shift, int width,
-                                                  uint64_t prefix, int first, unsigned long long* __restrict__ counts,
+                                                  const UnwState* __restrict__ st, int first,
+                                                  unsigned long long* __restrict__ counts,
                                                   unsigned long long* __restrict__ sum_hi,
                                                   unsigned long long* __restrict__ sum_lo) {
+    const uint64_t prefix = st->prefix;
     __shared__ unsigned int c_l[kUnwBuckets];
     __shared__ unsigned long long h_l[kUnwBuckets];
     __shared__ unsigned long long l_l[kUnwBuckets];
@@ -919,6 +922,51 @@ __global__ __launch_bounds__(256) void k_unw_hist(int64_t n, const double* __res
             atomicAdd(&sum_hi[i], h_l[i]);
             atomicAdd(&sum_lo[i], l_l[i]);
         }
+    }
+}
+
+// The crossing bucket of one pass (one thread, buckets from the top, the
+// order and arithmetic of a sequential scan): the excess at the lower edge
+// L_b of bucket b, S - L_b N over the weights in buckets >= b and above the
+// earlier passes' crossing buckets, reaches the target first at the crossing
+// bucket; st gets the extended prefix and the sums above it.  Then the
+// bucket arrays are cleared for the next pass.
+__global__ __launch_bounds__(256) void k_unw_search(int shift, int width, double overweight,
+                                                    const double* __restrict__ tot, UnwState* __restrict__ st,
+                                                    unsigned long long* __restrict__ counts,
+                                                    unsigned long long* __restrict__ sum_hi,
+                                                    unsigned long long* __restrict__ sum_lo) {
+    const int nbk = 1 << width;
+    if (threadIdx.x == 0) {
+        const double target = overweight * tot[0];
+        const uint64_t prefix = st->prefix;
+        double S = st->S_up, N = st->N_up;
+        double S_above = S, N_above = N;
+        int found = -1;
+        for (int b = nbk - 1; b >= 0; --b) {
+            S_above = S;
+            N_above = N;
+            const uint64_t lb_bits = ((prefix << width) | (uint64_t)b) << shift;
+            // the bucket's sum: its significand sum times 2^(e - 1075) (e its
+            // biased exponent; 1 - 1075 for subnormals)
+            const int ex = (int)(lb_bits >> 52);
+            S += ldexp((double)sum_hi[b] * 67108864.0 + (double)sum_lo[b], (ex ? ex : 1) - 1075);
+            N += (double)counts[b];
+            if (S - __longlong_as_double((long long)lb_bits) * N >= target) {
+                found = b;
+                break;
+            }
+        }
+        if (found < 0) found = 0;  // only the zero bucket: W lies below every positive weight
+        st->S_up = S_above;
+        st->N_up = N_above;
+        st->prefix = (prefix << width) | (uint64_t)found;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kUnwBuckets; i += blockDim.x) {
+        counts[i] = 0ull;
+        sum_hi[i] = 0ull;
+        sum_lo[i] = 0ull;
     }
 }
 
@@ -1041,11 +1089,19 @@ hipError_t launch_fill_i32(int32_t* x, int64_t n, int32_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_unw_pass(int64_t n, const double* w, int shift, int width, uint64_t prefix, int first,
-                           uint64_t* counts, uint64_t* sum_hi, uint64_t* sum_lo, int cu_count, hipStream_t s) {
-    int g = grid_for(n, cu_count * 4);
-    k_unw_hist<<<g, 256, 0, s>>>(n, w, shift, width, prefix, first, (unsigned long long*)counts,
-                                 (unsigned long long*)sum_hi, (unsigned long long*)sum_lo);
+hipError_t launch_unw_search(int64_t n, const double* w, double overweight, const double* tot, UnwState* st,
+                             uint64_t* counts, uint64_t* sum_hi, uint64_t* sum_lo, int cu_count, hipStream_t s) {
+    // passes over the 63 value bits of non-negative doubles: buckets of 12
+    // bits, the last pass 3
+    const int shifts[6] = {51, 39, 27, 15, 3, 0};
+    const int widths[6] = {12, 12, 12, 12, 12, 3};
+    const int g = grid_for(n, cu_count * 4);
+    for (int pass = 0; pass < 6; ++pass) {
+        k_unw_hist<<<g, 256, 0, s>>>(n, w, shifts[pass], widths[pass], st, pass == 0, (unsigned long long*)counts,
+                                     (unsigned long long*)sum_hi, (unsigned long long*)sum_lo);
+        k_unw_search<<<1, 256, 0, s>>>(shifts[pass], widths[pass], overweight, tot, st, (unsigned long long*)counts,
+                                       (unsigned long long*)sum_hi, (unsigned long long*)sum_lo);
+    }
     return hipGetLastError();
 }
 

@@ -168,15 +168,24 @@ hipError_t launch_vegas_refine(int n_rows, const int32_t* row_nb, const int64_t*
 
 namespace msx {
 
-// Unweighting-efficiency search, one refinement pass: histogram over bucket
-// = (bits >> shift) & (2^width - 1) of every positive weight whose bit
-// pattern above shift + width equals `prefix` (all weights when first):
-// counts, and the bucket's sum of significands m (the weight is
-// m 2^(e - 1075), e the bucket's biased exponent) as the sums of m >> 26 and
-// m & (2^26 - 1).  Integer atomics only: deterministic.  The arrays (2^width
-// entries each) must be zero before the pass.
-hipError_t launch_unw_pass(int64_t n, const double* w, int shift, int width, uint64_t prefix, int first,
-                           uint64_t* counts, uint64_t* sum_hi, uint64_t* sum_lo, int cu_count, hipStream_t s);
+// Unweighting-efficiency search (the largest weight W whose excess
+// sum_i max(0, w_i - W) reaches overweight x the total tot[0]), refined over
+// the bit patterns of the weights, which order non-negative doubles like
+// their values: six passes, each a histogram over bucket = (bits >> shift) &
+// (2^width - 1) of the positive weights whose higher bits equal the prefix
+// found so far (counts, and the bucket's significand sum as the sums of
+// m >> 26 and m & (2^26 - 1), the weight being m 2^(e - 1075); integer
+// atomics only), then a one-thread scan for the crossing bucket.  On return
+// (stream order) st holds the crossing value's bit pattern in prefix and the
+// sums above it.  st must start at zero, the bucket arrays (kUnwMaxBuckets
+// words each) too; they are zero again afterwards.  No host round trip.
+constexpr int kUnwMaxBuckets = 4096;
+struct UnwState {
+    uint64_t prefix;
+    double S_up, N_up;
+};
+hipError_t launch_unw_search(int64_t n, const double* w, double overweight, const double* tot, UnwState* st,
+                             uint64_t* counts, uint64_t* sum_hi, uint64_t* sum_lo, int cu_count, hipStream_t s);
 // total sum and max of w (two doubles at out)
 hipError_t launch_sum_max(int64_t n, const double* w, double* out, double* part, int nblk, hipStream_t s);
 

@@ -4,7 +4,9 @@ batch with power-law event counts."""
 import numpy as np
 import pytest
 
+import oracle
 import workloads as W
+from parity import compare
 
 pytestmark = pytest.mark.gpu
 
@@ -148,7 +150,8 @@ def test_autotune_picks_a_candidate_and_keeps_results(torch, c2):
 def test_c4_batch_in_one_graph(torch):
     """24 channels (C1 and C2 topologies, 6 processes), power-law counts, one
     persistent launch replayed from a graph; every channel's events equal the
-    single-channel map of the same uniforms."""
+    single-channel map of the same uniforms, and the oracle's within the
+    per-event parity bound."""
     from paper_2602_06895_amd import Context
 
     desc, counts = W.c4_context()
@@ -180,6 +183,22 @@ def test_c4_batch_in_one_graph(torch):
         if ctx.hadronic[c]:
             assert torch.equal(buf["x1x2"][:, lo:hi], ref["x1x2"]), c
     assert np.allclose(st[:, 0], [float(buf["w"][start[c]:start[c + 1]].sum()) for c in range(24)], rtol=1e-11)
+    # and against the oracle: each context channel is channel j of one of the
+    # six processes, whose oracle has that process's channels (the local
+    # channel weights); the per-event bound of the parity tests
+    procs = desc["processes"]
+    owner = [(p, j) for p, d in enumerate(procs) for j in range(len(d["channels"]))]
+    orcs = [oracle.Process(d) for d in procs]
+    for c in range(24):
+        p, j = owner[c]
+        lo, hi = int(start[c]), int(min(start[c + 1], start[c] + 2000))
+        y = W.philox_uniforms(4, 8, lo, hi - lo, ctx.dims[c])
+        ref = orcs[p].map(j, y, orcs[p].uniform_grid(j))
+        fe = orcs[p].forward_error(j, y, orcs[p].uniform_grid(j), ref=ref)
+        np_ = ctx.n_momenta[c]
+        got = {"w": buf["w"][lo:hi].cpu().numpy(), "p": buf["p"][:, :np_, lo:hi].cpu().numpy(),
+               "x1x2": buf["x1x2"][:, lo:hi].cpu().numpy() if ctx.hadronic[c] else None}
+        compare(got, ref, fe, hadronic=ctx.hadronic[c], label=f"c4 graph channel {c}")
     g.close()
     ctx.close()
 

@@ -925,33 +925,42 @@ __global__ __launch_bounds__(256) void k_unw_hist(int64_t n, const double* __res
     }
 }
 
-// The crossing bucket of one pass (one thread, buckets from the top, the
+// The crossing bucket of one pass: the workgroup converts the bucket sums
+// and counts into LDS, then one thread scans from the top bucket down (the
 // order and arithmetic of a sequential scan): the excess at the lower edge
 // L_b of bucket b, S - L_b N over the weights in buckets >= b and above the
 // earlier passes' crossing buckets, reaches the target first at the crossing
-// bucket; st gets the extended prefix and the sums above it.  Then the
-// bucket arrays are cleared for the next pass.
+// bucket; st gets the extended prefix and the sums above it.  The bucket
+// arrays are cleared for the next pass.
 __global__ __launch_bounds__(256) void k_unw_search(int shift, int width, double overweight,
                                                     const double* __restrict__ tot, UnwState* __restrict__ st,
                                                     unsigned long long* __restrict__ counts,
                                                     unsigned long long* __restrict__ sum_hi,
                                                     unsigned long long* __restrict__ sum_lo) {
+    __shared__ double s_b[kUnwBuckets];
+    __shared__ double n_b[kUnwBuckets];
     const int nbk = 1 << width;
+    const uint64_t prefix = st->prefix;
+    // every bucket's sum (its significand sum times 2^(e - 1075), e its
+    // biased exponent; 1 - 1075 for subnormals) and count, in parallel
+    for (int b = threadIdx.x; b < nbk; b += blockDim.x) {
+        const uint64_t lb_bits = ((prefix << width) | (uint64_t)b) << shift;
+        const int ex = (int)(lb_bits >> 52);
+        s_b[b] = ldexp((double)sum_hi[b] * 67108864.0 + (double)sum_lo[b], (ex ? ex : 1) - 1075);
+        n_b[b] = (double)counts[b];
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         const double target = overweight * tot[0];
-        const uint64_t prefix = st->prefix;
         double S = st->S_up, N = st->N_up;
         double S_above = S, N_above = N;
         int found = -1;
         for (int b = nbk - 1; b >= 0; --b) {
             S_above = S;
             N_above = N;
+            S += s_b[b];
+            N += n_b[b];
             const uint64_t lb_bits = ((prefix << width) | (uint64_t)b) << shift;
-            // the bucket's sum: its significand sum times 2^(e - 1075) (e its
-            // biased exponent; 1 - 1075 for subnormals)
-            const int ex = (int)(lb_bits >> 52);
-            S += ldexp((double)sum_hi[b] * 67108864.0 + (double)sum_lo[b], (ex ? ex : 1) - 1075);
-            N += (double)counts[b];
             if (S - __longlong_as_double((long long)lb_bits) * N >= target) {
                 found = b;
                 break;
@@ -962,7 +971,6 @@ __global__ __launch_bounds__(256) void k_unw_search(int shift, int width, double
         st->N_up = N_above;
         st->prefix = (prefix << width) | (uint64_t)found;
     }
-    __syncthreads();
     for (int i = threadIdx.x; i < kUnwBuckets; i += blockDim.x) {
         counts[i] = 0ull;
         sum_hi[i] = 0ull;

@@ -955,15 +955,25 @@ __global__ __launch_bounds__(256) void k_unw_search(int shift, int width, double
         double S = st->S_up, N = st->N_up;
         double S_above = S, N_above = N;
         int found = -1;
-        for (int b = nbk - 1; b >= 0; --b) {
-            S_above = S;
-            N_above = N;
-            S += s_b[b];
-            N += n_b[b];
-            const uint64_t lb_bits = ((prefix << width) | (uint64_t)b) << shift;
-            if (S - __longlong_as_double((long long)lb_bits) * N >= target) {
-                found = b;
-                break;
+        // eight buckets per step, their LDS reads issued before the
+        // sequential additions (the scan is otherwise bound by LDS latency)
+        for (int b0 = nbk - 1; b0 >= 0 && found < 0; b0 -= 8) {
+            double sv[8], nv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                sv[u] = b0 - u >= 0 ? s_b[b0 - u] : 0.0;
+                nv[u] = b0 - u >= 0 ? n_b[b0 - u] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int b = b0 - u;
+                if (b < 0 || found >= 0) break;
+                S_above = S;
+                N_above = N;
+                S += sv[u];
+                N += nv[u];
+                const uint64_t lb_bits = ((prefix << width) | (uint64_t)b) << shift;
+                if (S - __longlong_as_double((long long)lb_bits) * N >= target) found = b;
             }
         }
         if (found < 0) found = 0;  // only the zero bucket: W lies below every positive weight

@@ -402,7 +402,11 @@ msx_status msx_set_grid(msx_ctx* ctx, int32_t channel, const double* edges);
 /* Unweighting efficiency of weights w [n] >= 0 (device): the smallest W with
  * sum max(0, w_i - W) <= overweight * sum w_i, and eff = mean(w) / W -- the
  * on-the-fly maximum weight with an overweight allowance of section 3.4.1.
- * Results on host; synchronises `stream`. */
+ * Found on the device by six refinement passes over the weights' bit
+ * patterns with exact integer bucket sums (the same bits on every call).
+ * Results on host; synchronises `stream` once.  Errors: MSX_ERR_ARG for
+ * n <= 0, n >= 2^36, a missing pointer, overweight outside (0, 1), or
+ * weights without a finite positive sum. */
 msx_status msx_unweight_eff(msx_ctx* ctx, const double* w, int64_t n, double overweight,
                             double* eff, double* w_max, void* stream);
 
